@@ -1,0 +1,472 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+None of these re-types an oracle formula: each compares the oracle with a
+closed form, an independent formulation, brute force, a library routine
+(libm, scipy's associated Legendre functions) or an invariant.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.special import lpmv, factorial
+
+from oracle_helpers import identity_camera, scene_from, opts, logit, random_scene, Y00
+
+DIL = float(np.float32(0.3))  # the dilation option is a binary32 input
+
+
+# ---------------------------------------------------------------- canonical exp / log
+
+def _ulps(a, b):
+    return abs(a - b) / math.ulp(b) if b != 0 else abs(a)
+
+
+def test_canonical_exp_matches_libm(orc):
+    rng = np.random.default_rng(0)
+    xs = np.concatenate([rng.uniform(-20, 20, 20000), rng.uniform(-700, 700, 2000),
+                         [0.0, 1e-300, -1e-300, 0.5 * math.log(2), -0.5 * math.log(2), 1.0, -1.0, 88.7, -103.9]])
+    worst = max(_ulps(orc.exp_d(float(x)), math.exp(float(x))) for x in xs)
+    assert worst <= 2.0, worst
+    assert orc.exp_d(800.0) == math.inf and orc.exp_d(-800.0) == 0.0
+
+
+def test_canonical_log_matches_libm(orc):
+    rng = np.random.default_rng(1)
+    xs = np.concatenate([np.exp(rng.uniform(-30, 30, 20000)), rng.uniform(1.0, 255.0, 5000),
+                         [1.0, 2.0, math.sqrt(2.0), 255.0, 1e-310, 1e300]])
+    worst = max(_ulps(orc.log_d(float(x)), math.log(float(x))) if x != 1.0 else abs(orc.log_d(1.0)) for x in xs)
+    assert worst <= 2.0, worst
+    assert orc.log_d(1.0) == 0.0
+
+
+# ---------------------------------------------------------------- spherical harmonics
+
+def _real_sh_scipy(l, m, x, y, z):
+    """Real orthonormal SH with the Condon-Shortley phase from scipy's lpmv."""
+    th = math.acos(max(-1.0, min(1.0, z)))
+    ph = math.atan2(y, x)
+    am = abs(m)
+    K = math.sqrt((2 * l + 1) / (4 * math.pi) * factorial(l - am) / factorial(l + am))
+    P = lpmv(am, l, math.cos(th))
+    if m == 0:
+        return K * P
+    if m > 0:
+        return math.sqrt(2) * K * P * math.cos(m * ph)
+    return math.sqrt(2) * K * P * math.sin(am * ph)
+
+
+def test_sh_basis_matches_associated_legendre(orc):
+    rng = np.random.default_rng(2)
+    for _ in range(200):
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        Y = orc.sh_basis(*d, mode="f64")
+        for l in range(4):
+            for m in range(-l, l + 1):
+                k = l * l + l + m
+                assert abs(Y[k] - _real_sh_scipy(l, m, *d)) < 1e-12, (l, m)
+
+
+def test_sh_basis_orthonormal_by_quadrature(orc):
+    # Gauss-Legendre in cos(theta) x uniform phi: exact for these polynomials
+    nz, nphi = 12, 24
+    zs, wz = np.polynomial.legendre.leggauss(nz)
+    G = np.zeros((16, 16))
+    for z, w in zip(zs, wz):
+        for j in range(nphi):
+            ph = 2 * math.pi * j / nphi
+            s = math.sqrt(1 - z * z)
+            Y = orc.sh_basis(s * math.cos(ph), s * math.sin(ph), z, mode="f64")
+            G += np.outer(Y, Y) * w * (2 * math.pi / nphi)
+    assert np.allclose(G, np.eye(16), atol=1e-12)
+
+
+# ---------------------------------------------------------------- EWA covariance, conic, extent
+
+def _one(orc, means, ls, q, lg, W=64, H=64, f=50.0, mode="f64", **kw):
+    sc = scene_from([means], [ls], [q], [lg], dc_rgb=(1.0, 1.0, 1.0), dtype=np.float64)
+    cam = identity_camera(W, H, f)
+    return orc.render(sc, cam, W, H, opts(**kw), mode=mode)
+
+
+def test_head_on_isotropic_closed_form(orc):
+    """Mean on the optical axis at depth z, isotropic scale s, focal f:
+    Sigma' = ((f s / z)^2 + 0.3) I, conic = Sigma'^-1 (EWA splatting)."""
+    z, s, f = 5.0, 0.05, 100.0
+    out = _one(orc, (0.0, 0.0, z), (math.log(s),) * 3, (1, 0, 0, 0), 2.0, W=128, H=128, f=f)
+    st = out["state"][0]
+    var = (f * s / z) ** 2 + DIL
+    assert st[orc.S_U] == pytest.approx(64.0, abs=1e-12) and st[orc.S_V] == pytest.approx(64.0, abs=1e-12)
+    assert st[orc.S_COVA] == pytest.approx(var, rel=1e-12)
+    assert st[orc.S_COVC] == pytest.approx(var, rel=1e-12)
+    assert abs(st[orc.S_COVB]) < 1e-15
+    assert st[orc.S_A] == pytest.approx(1 / var, rel=1e-12) and st[orc.S_C] == pytest.approx(1 / var, rel=1e-12)
+    assert st[orc.S_DEPTH] == pytest.approx(z)
+
+
+def test_off_axis_isotropic_closed_form(orc):
+    """Isotropic Gaussian off axis (no clamp): Sigma' = s^2 J J^T + 0.3 I with
+    J = [[f/z, 0, -f x/z^2], [0, f/z, -f y/z^2]]."""
+    x, y, z, s, f = 0.7, -0.4, 6.0, 0.03, 80.0
+    out = _one(orc, (x, y, z), (math.log(s),) * 3, (0.3, 0.1, -0.5, 0.8), 1.0, W=128, H=128, f=f)
+    st = out["state"][0]
+    J = np.array([[f / z, 0, -f * x / z ** 2], [0, f / z, -f * y / z ** 2]])
+    Sg = s * s * J @ J.T + DIL * np.eye(2)
+    assert st[orc.S_COVA] == pytest.approx(Sg[0, 0], rel=1e-11)
+    assert st[orc.S_COVB] == pytest.approx(Sg[0, 1], rel=1e-9, abs=1e-14)
+    assert st[orc.S_COVC] == pytest.approx(Sg[1, 1], rel=1e-11)
+    assert st[orc.S_U] == pytest.approx(f * x / z + 64.0, rel=1e-13)
+    assert st[orc.S_V] == pytest.approx(f * y / z + 64.0, rel=1e-13)
+
+
+def test_anisotropic_cov_matches_monte_carlo_projection(orc):
+    """Sample the 3D Gaussian, project every sample exactly through the
+    pinhole, and compare the empirical 2D covariance with Sigma' - 0.3 I
+    (the EWA linearisation is exact to first order in the scale)."""
+    rng = np.random.default_rng(3)
+    mean = np.array([0.3, -0.2, 5.0])
+    ls = np.log([0.02, 0.005, 0.012])
+    q = np.array([0.8, 0.2, -0.4, 0.4])
+    q /= np.linalg.norm(q)
+    f = 200.0
+    out = _one(orc, mean, ls, q, 1.0, W=256, H=256, f=f)
+    st = out["state"][0]
+    w, x, y, z = q
+    Rq = np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                   [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                   [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+    L = Rq @ np.diag(np.exp(ls))
+    pts = mean + rng.normal(size=(400000, 3)) @ L.T
+    uv = np.stack([f * pts[:, 0] / pts[:, 2], f * pts[:, 1] / pts[:, 2]], 1)
+    emp = np.cov(uv.T)
+    model = np.array([[st[orc.S_COVA] - DIL, st[orc.S_COVB]], [st[orc.S_COVB], st[orc.S_COVC] - DIL]])
+    assert np.allclose(emp, model, rtol=0.02, atol=0.02 * np.abs(model).max())
+
+
+def test_rotation_sign_and_scale_invariance(orc):
+    base = dict(means=[(0.1, 0.2, 4.0)], ls=[(-3.0, -2.5, -3.5)])
+    q = np.array([0.3, -0.6, 0.2, 0.7])
+    states = []
+    for qq in (q, -q, 3.7 * q):
+        sc = scene_from(base["means"], base["ls"], [qq], [0.5], dc_rgb=(1, 1, 1), dtype=np.float64)
+        states.append(orc.render(sc, identity_camera(64, 64, 60), 64, 64, opts())["state"][0])
+    assert np.array_equal(states[0], states[1])
+    assert np.allclose(states[0], states[2], rtol=1e-12, atol=1e-12)
+
+
+def test_conic_is_inverse_of_cov2d(orc, scenes):
+    sc = scenes.make_scene("small")
+    out = orc.render(sc, scenes.camera_for("small"), 256, 256, opts())
+    st = out["state"][out["ints"][:, 0] == 1]
+    for r in st[:500]:
+        S2 = np.array([[r[orc.S_COVA], r[orc.S_COVB]], [r[orc.S_COVB], r[orc.S_COVC]]])
+        Cn = np.array([[r[orc.S_A], r[orc.S_B]], [r[orc.S_B], r[orc.S_C]]])
+        assert np.allclose(S2 @ Cn, np.eye(2), atol=1e-10)
+
+
+def test_extent_closed_form_and_crossover(orc):
+    """k^2 = 2 ln(o / tau) below the crossover, 9 (three sigma) above it;
+    the crossover opacity e^4.5 / 255 is the paper's 0.35 (Sec. 4.1)."""
+    ostar = math.exp(4.5) / 255.0
+    golden = _golden("paper_constants.txt")
+    assert round(ostar, 2) == float(golden["extent_crossover_opacity"])
+    for o in (0.01, 0.1, 0.3, 0.35, 0.36, 0.5, 0.9):
+        st = _one(orc, (0, 0, 5), (-3,) * 3, (1, 0, 0, 0), logit(o))["state"][0]
+        o64 = st[orc.S_O]
+        assert o64 == pytest.approx(o, rel=1e-12)
+        expect = min(9.0, 2 * math.log(o / float(np.float32(1 / 255))))
+        assert st[orc.S_K2] == pytest.approx(expect, rel=1e-12)
+        assert (st[orc.S_K2] < 9.0) == (o < ostar)
+
+
+def test_bbox_is_support_function_of_ellipse(orc):
+    """hx, hy equal the maximum |x|, |y| over the boundary q = k^2."""
+    rng = np.random.default_rng(4)
+    sc = random_scene(rng, 200, dtype=np.float64)
+    out = orc.render(sc, identity_camera(128, 128, 100), 128, 128, opts())
+    t = np.linspace(0, 2 * np.pi, 20001)
+    for st, iv in zip(out["state"], out["ints"]):
+        if not iv[0]:
+            continue
+        S2 = np.array([[st[orc.S_COVA], st[orc.S_COVB]], [st[orc.S_COVB], st[orc.S_COVC]]])
+        L = np.linalg.cholesky(S2 * st[orc.S_K2])
+        pts = L @ np.stack([np.cos(t), np.sin(t)])
+        assert np.abs(pts[0]).max() == pytest.approx(st[orc.S_HX], rel=1e-6)
+        assert np.abs(pts[1]).max() == pytest.approx(st[orc.S_HY], rel=1e-6)
+
+
+# ---------------------------------------------------------------- culling (Alg. 4)
+
+def _golden(name):
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    out = {}
+    for line in open(path):
+        line = line.split("#", 1)[0].strip()
+        if line:
+            k, v = line.split("=", 1)
+            out[k.strip()] = v.strip()
+    return out
+
+
+def test_near_plane_and_opacity_cull(orc):
+    g = _golden("paper_constants.txt")
+    near = float(g["near_plane_z"])
+    tau = eval(g["opacity_threshold"], {})  # "1/255"
+    o = opts()
+    assert float(np.float32(o["alpha_min"])) == float(np.float32(tau))
+    cam = identity_camera(64, 64, 50, near=near)
+    for z, keep in ((near, False), (near * (1 + 1e-6), True)):
+        sc = scene_from([(0, 0, z)], [(-6,) * 3], [(1, 0, 0, 0)], [2.0], dc_rgb=(1, 1, 1))
+        assert bool(orc.render(sc, cam, 64, 64, o)["ints"][0, 0]) == keep
+    tau32 = float(np.float32(tau))  # the threshold option is a binary32 input
+    for op, keep in ((tau32 * (1 - 1e-9), False), (tau32 * 1.5, True)):
+        sc = scene_from([(0, 0, 3)], [(-3,) * 3], [(1, 0, 0, 0)], [logit(op)], dc_rgb=(1, 1, 1), dtype=np.float64)
+        r = orc.render(sc, cam, 64, 64, o, mode="f64")
+        assert bool(r["ints"][0, 0]) == keep
+
+
+def test_degenerate_inputs_are_culled(orc):
+    cam = identity_camera(64, 64, 50)
+    bad = [
+        dict(q=(0, 0, 0, 0)),
+        dict(m=(np.nan, 0, 3)),
+        dict(ls=(np.inf, -3, -3)),
+        dict(lg=np.nan),
+        dict(m=(0, 0, -3)),          # behind the camera
+        dict(m=(100, 0, 3)),         # far outside the image: empty pixel range
+    ]
+    for b in bad:
+        sc = scene_from([b.get("m", (0, 0, 3))], [b.get("ls", (-3, -3, -3))], [b.get("q", (1, 0, 0, 0))],
+                        [b.get("lg", 1.0)], dc_rgb=(1, 1, 1))
+        for mode in ("f64", "f32"):
+            r = orc.render(sc, cam, 64, 64, opts(), mode=mode)
+            assert r["ints"][0, 0] == 0 and r["npairs"] == 0, b
+            assert np.all(r["rgb"] == 0) and np.all(r["T"] == 1)
+
+
+# ---------------------------------------------------------------- exact tile test (Alg. 3, Eq. 7)
+
+def _hull(tx, ty, W, H):
+    return (16 * tx + 0.5, min(16 * tx + 16, W) - 0.5, 16 * ty + 0.5, min(16 * ty + 16, H) - 0.5)
+
+
+def _min_q_over_box(st, orc, box):
+    """Independent formulation: the minimum of the quadratic form over a box
+    is at the centre if inside, else on an edge at the clamped vertex of the
+    edge's 1D parabola."""
+    u, v, A, B, C = (st[i] for i in (orc.S_U, orc.S_V, orc.S_A, orc.S_B, orc.S_C))
+    X0, X1, Y0, Y1 = box
+    x0, x1, y0, y1 = X0 - u, X1 - u, Y0 - v, Y1 - v
+    if x0 <= 0 <= x1 and y0 <= 0 <= y1:
+        return 0.0
+    best = math.inf
+    for y in (y0, y1):
+        x = min(max(-B * y / A, x0), x1)
+        best = min(best, A * x * x + 2 * B * x * y + C * y * y)
+    for x in (x0, x1):
+        y = min(max(-B * x / C, y0), y1)
+        best = min(best, A * x * x + 2 * B * x * y + C * y * y)
+    return best
+
+
+def test_tile_predicate_matches_box_minimum(orc):
+    rng = np.random.default_rng(5)
+    W, H = 200, 136
+    sc = random_scene(rng, 400, ls_mu=-2.5, ls_sigma=0.8, dtype=np.float64)
+    out = orc.render(sc, identity_camera(W, H, 120), W, H, opts())
+    n = 0
+    for st, iv in zip(out["state"], out["ints"]):
+        if not iv[0]:
+            continue
+        for ty in range(iv[orc.I_TY0] - 1, iv[orc.I_TY1] + 2):
+            for tx in range(iv[orc.I_TX0] - 1, iv[orc.I_TX1] + 2):
+                if not (0 <= tx < (W + 15) // 16 and 0 <= ty < (H + 15) // 16):
+                    continue
+                m = _min_q_over_box(st, orc, _hull(tx, ty, W, H)) - st[orc.S_K2]
+                hit = orc.tile_hit(st, tx, ty, W, H)
+                if abs(m) > 1e-9 * st[orc.S_K2]:
+                    assert hit == (m <= 0), (tx, ty, m)
+                    n += 1
+    assert n > 1000
+
+
+def test_tile_predicate_textbook_circle(orc):
+    # unit-conic circle of radius 10 at (40.5, 40.5) against a 64x64 image
+    st = np.zeros(16)
+    st[orc.S_U], st[orc.S_V], st[orc.S_A], st[orc.S_B], st[orc.S_C], st[orc.S_K2] = 40.5, 40.5, 1, 0, 1, 100
+    # tile (3,3) hull starts at 48.5: corner offset (8, 8), distance 11.3 > 10 -> miss
+    assert not orc.tile_hit(st, 3, 3, 64, 64)
+    # tile (3,2): hull x in [48.5, 63.5], y in [32.5, 47.5] contains (48.5, 40.5): distance 8 -> hit
+    assert orc.tile_hit(st, 3, 2, 64, 64)
+    # tile (2,2) contains the centre
+    assert orc.tile_hit(st, 2, 2, 64, 64)
+    # tile (0,0): hull up to 15.5, distance > 25 -> miss
+    assert not orc.tile_hit(st, 0, 0, 64, 64)
+
+
+def test_pairs_superset_of_contributing_pixels(orc, scenes):
+    """Every pixel sample with q <= k^2 has its (Gaussian, tile) pair, and
+    tiles are emitted only inside the rectangle."""
+    rng = np.random.default_rng(6)
+    W, H = 96, 80
+    sc = random_scene(rng, 300, ls_mu=-2.8, dtype=np.float64)
+    out = orc.render(sc, identity_camera(W, H, 70), W, H, opts())
+    pairs = set(zip(out["tiles"].tolist(), out["vals"].tolist()))
+    tiles_x = (W + 15) // 16
+    jj, ii = np.mgrid[0:H, 0:W]
+    px, py = ii + 0.5, jj + 0.5
+    for g, (st, iv) in enumerate(zip(out["state"], out["ints"])):
+        if not iv[0]:
+            continue
+        dx, dy = px - st[orc.S_U], py - st[orc.S_V]
+        q = st[orc.S_A] * dx * dx + 2 * st[orc.S_B] * dx * dy + st[orc.S_C] * dy * dy
+        for j, i in zip(*np.nonzero(q <= st[orc.S_K2])):
+            assert ((j // 16) * tiles_x + i // 16, g) in pairs
+    for t, g in pairs:
+        iv = out["ints"][g]
+        assert iv[orc.I_TX0] <= t % tiles_x <= iv[orc.I_TX1] and iv[orc.I_TY0] <= t // tiles_x <= iv[orc.I_TY1]
+
+
+# ---------------------------------------------------------------- sort order
+
+def test_pairs_sorted_by_tile_depth_index(orc, scenes):
+    sc = scenes.make_scene("small")
+    out = orc.render(sc, scenes.camera_for("small"), 256, 256, opts(), mode="f32")
+    d = out["state"][:, orc.S_DEPTH]
+    keys = out["tiles"].astype(np.uint64) << np.uint64(32) | d[out["vals"]].view(np.uint32).astype(np.uint64)
+    order = np.lexsort((out["vals"], keys))
+    assert np.array_equal(order, np.arange(len(order)))
+    assert out["npairs"] == int(out["ints"][:, orc.I_COUNT].sum())
+    r = out["ranges"]
+    assert r[0, 0] == 0 and r[-1, 1] == out["npairs"] and np.all(r[1:, 0] == r[:-1, 1])
+    for t in range(len(r)):
+        assert np.all(out["tiles"][r[t, 0]:r[t, 1]] == t)
+
+
+# ---------------------------------------------------------------- blending
+
+def test_tiled_equals_brute_force_fp64(orc, scenes):
+    rng = np.random.default_rng(7)
+    for trial in range(3):
+        sc = random_scene(rng, 64 if trial < 2 else 400, ls_mu=-2.5, sh_degree=2, dtype=np.float64)
+        W, H = (64, 64) if trial < 2 else (72, 50)
+        cam = identity_camera(W, H, 55)
+        a = orc.render(sc, cam, W, H, opts(), brute=False)
+        b = orc.render(sc, cam, W, H, opts(), brute=True)
+        assert np.array_equal(a["rgb"], b["rgb"]) and np.array_equal(a["T"], b["T"])
+        # brute force's "last" counts positions in the global list: compare contributor sets instead
+        assert np.array_equal(a["last"] > 0, b["last"] > 0)
+
+
+def test_exact_and_bbox_binning_give_identical_images(orc, scenes):
+    """The exact test only removes pairs that contribute to no pixel (Sec. 6:
+    no accuracy loss); the image is bitwise unchanged."""
+    sc = scenes.make_scene("small")
+    cam = scenes.camera_for("small")
+    a = orc.render(sc, cam, 256, 256, opts(binning=0))
+    b = orc.render(sc, cam, 256, 256, opts(binning=1))
+    assert b["npairs"] > a["npairs"]
+    assert np.array_equal(a["rgb"], b["rgb"]) and np.array_equal(a["T"], b["T"])
+
+
+def test_transmittance_product_invariant(orc):
+    """All colours 1, background 0: pixel value = 1 - T_final exactly
+    (sum of alpha_n T_n telescopes to 1 - prod(1 - alpha_n))."""
+    rng = np.random.default_rng(8)
+    P = 300
+    means = rng.uniform(-1, 1, (P, 3)) + [0, 0, 4]
+    q = rng.normal(size=(P, 4))
+    sc = scene_from(means, rng.normal(-2.5, 0.5, (P, 3)), q, rng.normal(1, 1.5, P), dc_rgb=(1.0, 1.0, 1.0),
+                    dtype=np.float64)
+    out = orc.render(sc, identity_camera(64, 64, 60), 64, 64, opts())
+    assert np.allclose(out["state"][out["ints"][:, 0] == 1][:, orc.S_R], 1.0, atol=1e-15)
+    for c in range(3):
+        assert np.allclose(out["rgb"][c], 1.0 - out["T"], atol=1e-13)
+    assert (out["T"] < 0.5).mean() > 0.1
+
+
+def test_single_gaussian_image_closed_form(orc):
+    """Head-on isotropic Gaussian: C(r) = min(0.99, o exp(-r^2 / 2 s'^2)) c
+    inside r^2 <= k^2 s'^2, background outside."""
+    z, s, f, o = 5.0, 0.06, 100.0, 0.8
+    W = H = 64
+    sc = scene_from([(0, 0, z)], [(math.log(s),) * 3], [(1, 0, 0, 0)], [logit(o)], dc_rgb=(0.9, 0.5, 0.2),
+                    dtype=np.float64)
+    out = orc.render(sc, identity_camera(W, H, f), W, H, opts(bg=(0.1, 0.2, 0.3)))
+    var = (f * s / z) ** 2 + DIL
+    jj, ii = np.mgrid[0:H, 0:W]
+    r2 = (ii + 0.5 - 32) ** 2 + (jj + 0.5 - 32) ** 2
+    k2 = min(9.0, 2 * math.log(o * 255))
+    inside = r2 / var <= k2
+    a = np.where(inside, np.minimum(0.99, o * np.exp(-r2 / (2 * var))), 0.0)
+    for ch, (c, bgc) in enumerate(zip((0.9, 0.5, 0.2), (0.1, 0.2, 0.3))):
+        assert np.allclose(out["rgb"][ch], a * c + (1 - a) * bgc, atol=1e-12)
+
+
+def test_early_termination_bound_and_stop_rule(orc):
+    """Stopping changes a pixel by at most T_final * max colour; with
+    T_stop = 0 nothing stops."""
+    rng = np.random.default_rng(9)
+    P = 1000
+    sc = scene_from(rng.uniform(-0.5, 0.5, (P, 3)) + [0, 0, 4], rng.normal(-1.8, 0.3, (P, 3)),
+                    rng.normal(size=(P, 4)), rng.normal(3, 1, P), dc_rgb=rng.uniform(0, 1, (P, 3)),
+                    dtype=np.float64)
+    cam = identity_camera(48, 48, 50)
+    a = orc.render(sc, cam, 48, 48, opts())
+    b = orc.render(sc, cam, 48, 48, opts(T_stop=0.0))
+    assert (a["T"] < 1e-2).mean() > 0.15      # many pixels saturate
+    assert np.all(a["T"] >= 1e-4)             # never below T_stop
+    assert np.all(np.abs(a["rgb"] - b["rgb"]) <= a["T"][None] * 1.0 + 1e-12)
+
+
+def test_permutation_invariance(orc, scenes):
+    sc = scenes.make_scene("small", P=3000)
+    cam = scenes.camera_for("small")
+    perm = np.random.default_rng(10).permutation(sc.P)
+    a = orc.render(sc, cam, 256, 256, opts())
+    b = orc.render(sc.subset(perm), cam, 256, 256, opts())
+    assert np.array_equal(a["rgb"], b["rgb"])
+
+
+def test_rigid_motion_invariance(orc, scenes):
+    """Move scene and camera by the same rigid motion (SH degree 0 so colour
+    is view independent): same image up to rounding."""
+    sc = scenes.make_scene("small", P=3000).astype(np.float64)
+    cam = scenes.camera_for("small")
+    th = 0.7
+    Rm = np.array([[math.cos(th), 0, math.sin(th)], [0, 1, 0], [-math.sin(th), 0, math.cos(th)]])
+    tm = np.array([0.3, -0.2, 0.5])
+    # rotation as a quaternion (w, x, y, z) about +y
+    qr = np.array([math.cos(th / 2), 0, math.sin(th / 2), 0])
+
+    def qmul(a, b):
+        w1, x1, y1, z1 = a
+        w2, x2, y2, z2 = b
+        return np.array([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                         w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2])
+
+    from paper_2408_07967_amd.scenes import Scene, Camera
+    means2 = Rm @ sc.means + tm[:, None]
+    quats2 = qmul(qr, sc.quats)
+    sc2 = Scene(means2, sc.log_scales, quats2, sc.logits, sc.sh, 0)
+    R2 = cam.R.astype(np.float64) @ Rm.T
+    t2 = cam.t - R2 @ tm
+    cam2 = Camera(R2, t2, Rm @ cam.eye + tm, cam.fx, cam.fy, cam.cx, cam.cy, cam.near, 256, 256)
+
+    class _C:  # keep binary64 camera values (the wrapper rounds to binary32)
+        pass
+    a = orc.render(sc, cam, 256, 256, opts())
+    b = orc.render(sc2, cam2, 256, 256, opts())
+    # camera values are rounded to binary32 by the wrapper, so allow that rounding
+    diff = np.abs(a["rgb"] - b["rgb"])
+    assert np.mean(diff) < 1e-4 and np.quantile(diff, 0.999) < 2e-3
+
+
+def test_fp32_mode_close_to_fp64(orc, scenes):
+    sc = scenes.make_scene("small")
+    cam = scenes.camera_for("small")
+    a = orc.render(sc, cam, 256, 256, opts(), mode="f64")
+    b = orc.render(sc, cam, 256, 256, opts(), mode="f32")
+    d = np.abs(a["rgb"] - b["rgb"])
+    assert d.mean() < 1e-5 and (d <= 2e-3).mean() >= 0.999
