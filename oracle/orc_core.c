@@ -335,8 +335,8 @@ static int FN(orc_gauss)(const TYPE(orc_scene) *sc, int64_t g, const TYPE(orc_ca
         REAL acc = (REAL)0;
         for (int k = 0; k < nk; ++k) acc = acc + sc->sh[(int64_t)(3 * k + ch) * st + g] * Y[k];
         acc = acc + (REAL)0.5; /* offset and clamp at zero (reading) */
+        if (!R_ISFINITE(acc)) return 0; /* non-finite SH inputs are culled (reading) */
         col[ch] = acc > (REAL)0 ? acc : (REAL)0;
-        if (!R_ISFINITE(col[ch])) return 0; /* non-finite inputs are culled */
     }
     s[S_U] = u; s[S_V] = v; s[S_A] = A; s[S_B] = B; s[S_C] = C; s[S_K2] = k2;
     s[S_O] = o; s[S_DEPTH] = tz;
