@@ -1,0 +1,210 @@
+/*
+ * fgs.h - C ABI of the MI355X (gfx950) Gaussian-splatting rasterizer with
+ * exact ellipse/tile intersection (FlashGS, arXiv 2408.07967).
+ *
+ * The library renders a set of 3D Gaussians (Alg. 1 / Alg. 4 inputs:
+ * positions, scales, rotations, opacities, SH coefficients) through one
+ * pinhole camera into an RGB image, in four stages that all run as HIP
+ * kernels on the GPU:
+ *   1. per-Gaussian preprocessing with the exact ellipse/tile test
+ *      (Sec. 4.1, Alg. 3, Eq. 1-3 and Eq. 7, Alg. 4),
+ *   2. key emission after a prefix scan of per-Gaussian tile counts
+ *      (Alg. 2 offsets; Sec. 4.2 fusion of intersection and key generation),
+ *   3. radix sort of (tile | depth) keys and per-tile ranges (Sec. 2.2),
+ *   4. per-tile front-to-back alpha blending with early termination
+ *      (Sec. 2.2, Sec. 5.2).
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers marked "device" are HIP device memory owned by the caller;
+ *     "host" pointers are ordinary host memory.  The library never frees
+ *     caller memory.
+ *   - Every call returns an fgs_status and never aborts or throws across the
+ *     ABI.  Argument errors are detected on the host before any HIP call and
+ *     return FGS_ERR_INVALID_ARGUMENT; fgs_last_error() then describes them.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is stream-ordered; outputs are valid once the stream reaches the
+ *     end of the call's work.
+ *   - A context may be used by one host thread at a time.
+ */
+#ifndef FGS_H
+#define FGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FGS_OK = 0,
+    FGS_ERR_INVALID_ARGUMENT = 1,
+    FGS_ERR_OUT_OF_MEMORY = 2,
+    FGS_ERR_CAPACITY = 3,
+    FGS_ERR_DEVICE = 4,
+    FGS_ERR_NOT_SUPPORTED = 5,
+    FGS_ERR_INTERNAL = 6
+} fgs_status;
+
+typedef struct fgs_context fgs_context; /* device, scratch arena, error text */
+typedef struct fgs_frame fgs_frame;     /* saved forward state for the backward */
+
+/* Gaussian parameters, planar binary32 in device memory.  Plane c of an
+ * attribute X is X + c * plane_stride, one float per Gaussian.
+ * (Alg. 1 / Alg. 4 inputs: positions, scales s, rotations R, opacity, shs.) */
+typedef struct {
+    int64_t num_gaussians;      /* P >= 0; P == 0 renders the background   */
+    int64_t plane_stride;       /* >= P                                      */
+    int32_t sh_degree;          /* D in 0..3                                 */
+    int32_t reserved;           /* must be 0                                 */
+    const float *means;         /* device, 3 planes: world x, y, z           */
+    const float *log_scales;    /* device, 3 planes: scale = exp(value)      */
+    const float *quats;         /* device, 4 planes w, x, y, z; any non-zero
+                                   norm (normalised inside)                  */
+    const float *opacity_logits;/* device, 1 plane: opacity = sigmoid(value) */
+    const float *sh;            /* device, 3 (D+1)^2 planes; plane 3 k + ch,
+                                   k = l^2 + l + m (real SH, Condon-Shortley
+                                   phase)                                    */
+} fgs_scene;
+
+/* Gradients with respect to the raw parameters above (same planar layout);
+ * device memory owned by the caller, overwritten by fgs_render_backward. */
+typedef struct {
+    int64_t plane_stride;
+    float *means, *log_scales, *quats, *opacity_logits, *sh;
+} fgs_scene_grad;
+
+/* Pinhole camera (Alg. 1 viewmatrix / focal inputs).  x_cam = R x + t with R
+ * row-major; camera axes: x right, y down, z forward.  eye is the camera
+ * centre in world space (direction for the SH colour).  Pixel (i, j) is
+ * sampled at (i + 1/2, j + 1/2).  near_z: Gaussians need z_cam > near_z
+ * (0.2 in Alg. 4). */
+typedef struct {
+    float R[9];
+    float t[3];
+    float eye[3];
+    float fx, fy, cx, cy;
+    float near_z;
+} fgs_camera;
+
+typedef struct {
+    float alpha_min; /* tau: opacity cutoff and extent threshold, 1/255 (Sec. 4.1) */
+    float T_stop;    /* transmittance at which a pixel stops, 1e-4                 */
+    float alpha_max; /* per-Gaussian alpha clamp, 0.99                              */
+    float dilation;  /* low-pass added to the 2D covariance diagonal, 0.3 px^2      */
+    float jac_clip;  /* projection-Jacobian clamp, multiple of the half image, 1.3 */
+    float bg[3];     /* background colour, black by default                        */
+    int32_t cap_3sigma; /* 1: extent k^2 = min(9, 2 ln(o / tau)) (Eq. 1-3)          */
+    int32_t binning;    /* 0: exact ellipse/tile test (Alg. 3); 1: every tile of the
+                           tight box (test mode, same image)                        */
+} fgs_options;
+
+typedef struct {
+    int64_t visible;   /* Gaussians that survived preprocessing          */
+    int64_t pairs;     /* Gaussian-tile key/value pairs emitted          */
+    int32_t tiles_x, tiles_y;
+    int32_t sort_passes;
+    int32_t reserved;
+} fgs_stats;
+
+/* ---- context --------------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  *out receives the handle, or NULL
+ * with FGS_ERR_DEVICE when the device is missing / not gfx950. */
+fgs_status fgs_create(int device, fgs_context **out);
+
+/* Destroy a context and every frame it still owns (NULL is ignored). */
+void fgs_destroy(fgs_context *ctx);
+
+/* Static description of a status code. */
+const char *fgs_status_string(fgs_status s);
+
+/* Text of the last error on this context ("" if none); valid until the next
+ * call on the context.  With ctx == NULL: the last error of a call that was
+ * given no context. */
+const char *fgs_last_error(const fgs_context *ctx);
+
+/* Fill *opt with the defaults listed in fgs_options. */
+void fgs_default_options(fgs_options *opt);
+
+/* Host-only validation of render arguments (no HIP call).  Returns
+ * FGS_ERR_INVALID_ARGUMENT for: null pointers, P < 0, plane_stride < P,
+ * sh_degree outside 0..3, W or H outside 1..16384, non-finite camera values,
+ * fx or fy <= 0, near_z <= 0, or out-of-range options. */
+fgs_status fgs_validate(const fgs_scene *scene, const fgs_camera *cam, int32_t W, int32_t H,
+                        const fgs_options *opt);
+
+/* Pre-size the context's device scratch so that later renders up to these
+ * sizes allocate nothing (Sec. 5.3.1: allocation hoisted out of the frame
+ * loop). */
+fgs_status fgs_reserve(fgs_context *ctx, int64_t max_gaussians, int64_t max_pairs, int32_t max_w,
+                       int32_t max_h);
+
+/* Bytes of device scratch currently held by the context. */
+size_t fgs_scratch_bytes(const fgs_context *ctx);
+
+/* ---- forward ------------------------------------------------------------ */
+
+/* Render scene through cam at W x H.
+ *   out_rgb  device, [3][H][W] float (planar RGB), required.
+ *   out_T    device, [H][W] float final transmittance, or NULL.
+ *   out_last device, [H][W] uint32: 1 + position, within its tile's sorted
+ *            list, of the last Gaussian that contributed to the pixel (0 if
+ *            none), or NULL.
+ *   saved    if non-NULL, receives a frame handle that keeps the per-Gaussian
+ *            state, the sorted list, the tile ranges, T_final and last for
+ *            fgs_render_backward / fgs_frame_download; release it with
+ *            fgs_frame_release.
+ *   stats    host, or NULL: counts of the frame.
+ * The call waits once on `stream` to read the number of pairs, then enqueues
+ * the rest.  opt == NULL means defaults. */
+fgs_status fgs_render(fgs_context *ctx, const fgs_scene *scene, const fgs_camera *cam, int32_t W, int32_t H,
+                      const fgs_options *opt, float *out_rgb, float *out_T, uint32_t *out_last,
+                      fgs_frame **saved, fgs_stats *stats, void *stream);
+
+/* ---- backward ----------------------------------------------------------- */
+
+/* Gradients of a scalar loss L with respect to the raw scene parameters,
+ * given dL/dRGB for the image of `frame` (the paper claims a differentiable
+ * rasterizer; the adjoint replays the blend back to front from T_final and
+ * last, with wavefront-reduced atomics as in the related DISTWAR work).
+ *   dL_drgb  device, [3][H][W] float.
+ *   grad     device gradient planes (overwritten).
+ * scene, cam and opt must be those of the forward call. */
+fgs_status fgs_render_backward(fgs_context *ctx, const fgs_frame *frame, const fgs_scene *scene,
+                               const fgs_camera *cam, const fgs_options *opt, const float *dL_drgb,
+                               const fgs_scene_grad *grad, void *stream);
+
+/* Release a saved frame (NULL is ignored). */
+fgs_status fgs_frame_release(fgs_context *ctx, fgs_frame *frame);
+
+/* Introspection of a saved frame for tests and tools: copies one field to
+ * host memory (synchronising the frame's stream).  Fields and layouts:
+ *   FGS_FIELD_GAUSS   [P][12] float: u, v, conic A, B, C, k^2, log2(o),
+ *                     r, g, b, depth, o (valid Gaussians only; others 0)
+ *   FGS_FIELD_RECT    [P][4] int32: tx0, tx1, ty0, ty1 (valid only)
+ *   FGS_FIELD_COUNT   [P] uint32 exact tile count (0 for culled Gaussians)
+ *   FGS_FIELD_ORDER   [visible] uint32 Gaussian indices in (depth, index) order
+ *   FGS_FIELD_TILES   [pairs] uint32 tile id of each sorted pair
+ *   FGS_FIELD_VALUES  [pairs] uint32 Gaussian index of each sorted pair
+ *   FGS_FIELD_RANGES  [tiles][2] uint32 [start, end) of each tile's list
+ * `bytes` must equal the field's size (fgs_frame_field_bytes). */
+typedef enum {
+    FGS_FIELD_GAUSS = 0,
+    FGS_FIELD_RECT = 1,
+    FGS_FIELD_COUNT = 2,
+    FGS_FIELD_ORDER = 3,
+    FGS_FIELD_TILES = 4,
+    FGS_FIELD_VALUES = 5,
+    FGS_FIELD_RANGES = 6
+} fgs_field;
+
+size_t fgs_frame_field_bytes(const fgs_frame *frame, fgs_field field);
+fgs_status fgs_frame_download(fgs_context *ctx, const fgs_frame *frame, fgs_field field, void *host_dst,
+                              size_t bytes);
+fgs_status fgs_frame_stats(const fgs_frame *frame, fgs_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FGS_H */

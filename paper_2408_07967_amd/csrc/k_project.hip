@@ -1,0 +1,527 @@
+// Per-Gaussian preprocessing with the exact ellipse/tile test, and key
+// emission in depth order (FlashGS Alg. 4, Alg. 3, Eq. 1-3, Eq. 7, Sec. 4.2).
+//
+// This translation unit is compiled with -ffp-contract=off: every binary32
+// + - * / and sqrt below is one correctly rounded IEEE operation in the
+// written order, so the per-Gaussian state and the tile test give the same
+// bits as the canonical FP32 evaluation of the method; exp and ln are
+// evaluated in binary64 by a fixed operation sequence and rounded once.
+#include "fgs_internal.hpp"
+
+namespace fgs {
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kSmallCount = 4;   // rectangles of up to this many tiles: one lane
+constexpr int kSmallEmit = 4;    // Gaussians with up to this many pairs: one lane
+
+// ---- canonical binary64 exp / ln (Cody-Waite reduction + Taylor; atanh series)
+
+#define FGS_LN2_HI 0x1.62e42fee00000p-1
+#define FGS_LN2_LO 0x1.a39ef35793c76p-33
+#define FGS_INV_LN2 0x1.71547652b82fep+0
+
+__device__ __forceinline__ double pow2i(int k) {
+    return __longlong_as_double((long long)(k + 1023) << 52);
+}
+
+__device__ __forceinline__ double floor_exact(double x) {
+    double t = (double)(long long)x;
+    return (t > x) ? t - 1.0 : t;
+}
+
+__device__ double canon_exp(double x) {
+    if (x != x) return x;
+    if (x > 709.8) return __longlong_as_double(0x7ff0000000000000LL);
+    if (x < -745.2) return 0.0;
+    double k = floor_exact(x * FGS_INV_LN2 + 0.5);
+    double r = (x - k * FGS_LN2_HI) - k * FGS_LN2_LO;
+    double p = 1.0 / 6227020800.0;
+    p = p * r + 1.0 / 479001600.0;
+    p = p * r + 1.0 / 39916800.0;
+    p = p * r + 1.0 / 3628800.0;
+    p = p * r + 1.0 / 362880.0;
+    p = p * r + 1.0 / 40320.0;
+    p = p * r + 1.0 / 5040.0;
+    p = p * r + 1.0 / 720.0;
+    p = p * r + 1.0 / 120.0;
+    p = p * r + 1.0 / 24.0;
+    p = p * r + 1.0 / 6.0;
+    p = p * r + 0.5;
+    p = p * r + 1.0;
+    p = p * r + 1.0;
+    int ki = (int)k;
+    int k1 = ki / 2;
+    int k2 = ki - k1;
+    return (p * pow2i(k1)) * pow2i(k2);
+}
+
+// ln x for finite x >= 1 (the only use: ln(o / tau) with o > tau)
+__device__ double canon_log(double x) {
+    unsigned long long bits = (unsigned long long)__double_as_longlong(x);
+    int e = (int)((bits >> 52) & 0x7ff) - 1023;
+    double m = __longlong_as_double((long long)((bits & 0x000fffffffffffffULL) | 0x3ff0000000000000ULL));
+    if (m > 1.4142135623730951) {
+        m = m * 0.5;
+        e = e + 1;
+    }
+    double s = (m - 1.0) / (m + 1.0);
+    double z = s * s;
+    double p = 1.0 / 23.0;
+    p = p * z + 1.0 / 21.0;
+    p = p * z + 1.0 / 19.0;
+    p = p * z + 1.0 / 17.0;
+    p = p * z + 1.0 / 15.0;
+    p = p * z + 1.0 / 13.0;
+    p = p * z + 1.0 / 11.0;
+    p = p * z + 1.0 / 9.0;
+    p = p * z + 1.0 / 7.0;
+    p = p * z + 1.0 / 5.0;
+    p = p * z + 1.0 / 3.0;
+    double lnm = (2.0 * s) + (2.0 * s) * (z * p);
+    double de = (double)e;
+    return de * FGS_LN2_HI + (lnm + de * FGS_LN2_LO);
+}
+
+__device__ __forceinline__ float clampf_(float x, float lo, float hi) {
+    return x < lo ? lo : (x > hi ? hi : x);
+}
+
+__device__ __forceinline__ float bcast(float x, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
+}
+__device__ __forceinline__ int bcast(int x, int lane) { return __builtin_amdgcn_readlane(x, lane); }
+__device__ __forceinline__ uint32_t bcast(uint32_t x, int lane) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, lane);
+}
+
+// Exact test of the ellipse { d : A dx^2 + 2 B dx dy + C dy^2 <= k2 } around
+// (u, v) against the pixel-sample hull of tile (tx, ty) (Alg. 3; Eq. 7 with
+// the discriminant guard).  Centre inside -> hit; otherwise each edge line
+// meets the ellipse in a chord whose overlap with the edge segment is decided
+// without division or square root.
+__device__ __forceinline__ bool tile_hit(float u, float v, float A, float B, float C, float k2, int tx, int ty,
+                                         int W, int H) {
+    int xe = kTile * tx + kTile;
+    xe = xe > W ? W : xe;
+    int ye = kTile * ty + kTile;
+    ye = ye > H ? H : ye;
+    float x0 = ((float)(kTile * tx) + 0.5f) - u;
+    float x1 = ((float)xe - 0.5f) - u;
+    float y0 = ((float)(kTile * ty) + 0.5f) - v;
+    float y1 = ((float)ye - 0.5f) - v;
+    if (x0 <= 0.0f && 0.0f <= x1 && y0 <= 0.0f && 0.0f <= y1) return true;
+    const float A2 = 2.0f * A, B2 = 2.0f * B, C2 = 2.0f * C, A4 = 4.0f * A, C4 = 4.0f * C;
+    bool hit = false;
+    // edges y = y0 and y = y1 (quadratic in x: A x^2 + (2B y) x + (C y^2 - k2))
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        float ye_ = e ? y1 : y0;
+        float bq = B2 * ye_;
+        float cq = (C * ye_) * ye_ - k2;
+        float delta = bq * bq - A4 * cq;
+        float e1 = A2 * x0 + bq;
+        float e2 = A2 * x1 + bq;
+        hit |= (delta >= 0.0f) && (e1 <= 0.0f || e1 * e1 <= delta) && (e2 >= 0.0f || e2 * e2 <= delta);
+    }
+    // edges x = x0 and x = x1 (quadratic in y: C y^2 + (2B x) y + (A x^2 - k2))
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        float xe_ = e ? x1 : x0;
+        float bq = B2 * xe_;
+        float cq = (A * xe_) * xe_ - k2;
+        float delta = bq * bq - C4 * cq;
+        float e1 = C2 * y0 + bq;
+        float e2 = C2 * y1 + bq;
+        hit |= (delta >= 0.0f) && (e1 <= 0.0f || e1 * e1 <= delta) && (e2 >= 0.0f || e2 * e2 <= delta);
+    }
+    return hit;
+}
+
+// Real orthonormal SH basis with the Condon-Shortley phase, k = l^2 + l + m.
+__device__ __forceinline__ void sh_basis(float x, float y, float z, int D, float *Y) {
+    const float c0 = 0.28209479177387814f;   // 1 / (2 sqrt(pi))
+    const float c1 = 0.48860251190291992f;   // sqrt(3 / (4 pi))
+    Y[0] = c0;
+    if (D < 1) return;
+    Y[1] = -c1 * y;
+    Y[2] = c1 * z;
+    Y[3] = -c1 * x;
+    if (D < 2) return;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    const float c2a = 1.0925484305920792f;   // sqrt(15 / (4 pi))
+    const float c20 = 0.31539156525252005f;  // sqrt(5 / (16 pi))
+    const float c22 = 0.54627421529603959f;  // sqrt(15 / (16 pi))
+    Y[4] = c2a * (x * y);
+    Y[5] = -c2a * (y * z);
+    Y[6] = c20 * (3.0f * zz - 1.0f);
+    Y[7] = -c2a * (x * z);
+    Y[8] = c22 * (xx - yy);
+    if (D < 3) return;
+    const float c33 = 0.59004358992664352f;  // sqrt(35 / (32 pi))
+    const float c32 = 2.8906114426405538f;   // sqrt(105 / (4 pi))
+    const float c31 = 0.45704579946446572f;  // sqrt(21 / (32 pi))
+    const float c30 = 0.37317633259011546f;  // sqrt(7 / (16 pi))
+    const float c32b = 1.4453057213202769f;  // sqrt(105 / (16 pi))
+    Y[9] = -c33 * (y * (3.0f * xx - yy));
+    Y[10] = c32 * (x * y * z);
+    Y[11] = -c31 * (y * (5.0f * zz - 1.0f));
+    Y[12] = c30 * (z * (5.0f * zz - 3.0f));
+    Y[13] = -c31 * (x * (5.0f * zz - 1.0f));
+    Y[14] = c32b * (z * (xx - yy));
+    Y[15] = -c33 * (x * (xx - 3.0f * yy));
+}
+
+__global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevCamera cam, DevOptions op, int W, int H,
+                                                       GaussState *__restrict__ gs, uint4 *__restrict__ rect,
+                                                       uint32_t *__restrict__ count, uint2 *__restrict__ mask,
+                                                       uint32_t *__restrict__ dkey, FrameCounters *fc) {
+    __shared__ uint32_t s_hist[4 * kRadix];
+    for (int i = threadIdx.x; i < 4 * kRadix; i += kBlock) s_hist[i] = 0;
+    __syncthreads();
+
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t st = sc.stride;
+    bool valid = false;
+    float u = 0, v = 0, A = 0, B = 0, C = 0, k2 = 0, o = 0, tz = 0;
+    int tx0 = 0, tx1 = -1, ty0 = 0, ty1 = -1;
+    float col[3] = {0, 0, 0};
+
+    if (g < sc.P) {
+        const float mx = sc.means[g], my = sc.means[st + g], mz = sc.means[2 * st + g];
+        const float *R = cam.R;
+        // view transform (p_view)
+        const float tx = ((R[0] * mx + R[1] * my) + R[2] * mz) + cam.t[0];
+        const float ty = ((R[3] * mx + R[4] * my) + R[5] * mz) + cam.t[1];
+        tz = ((R[6] * mx + R[7] * my) + R[8] * mz) + cam.t[2];
+        // near plane (Alg. 4: p_view.z > 0.2); the remaining attributes are
+        // read only for Gaussians in front of the camera
+        if (tz > cam.near_z && isfinite(mx) && isfinite(my) && isfinite(mz)) {
+            const float logit = sc.logits[g];
+            o = (float)(1.0 / (1.0 + canon_exp(-(double)logit)));
+            // opacity prefilter (Alg. 4: opacity > 1/255)
+            if (o > op.alpha_min && isfinite(logit)) {
+                const float ls0 = sc.log_scales[g], ls1 = sc.log_scales[st + g], ls2 = sc.log_scales[2 * st + g];
+                const float qw = sc.quats[g], qx = sc.quats[st + g], qy = sc.quats[2 * st + g],
+                            qz = sc.quats[3 * st + g];
+                const float s0 = (float)canon_exp((double)ls0), s1 = (float)canon_exp((double)ls1),
+                            s2 = (float)canon_exp((double)ls2);
+                const float n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
+                const bool fin = isfinite(ls0) && isfinite(ls1) && isfinite(ls2) && isfinite(n2);
+                if (fin && n2 > 0.0f) {
+                    const float qn = sqrtf(n2);
+                    const float w = qw / qn, x = qx / qn, y = qy / qn, z = qz / qn;
+                    // pinhole projection (project + ndc2Pix)
+                    const float xt = tx / tz, yt = ty / tz;
+                    u = cam.fx * xt + cam.cx;
+                    v = cam.fy * yt + cam.cy;
+                    // EWA Jacobian with the view-direction clamp
+                    const float limx = op.jac_clip * ((0.5f * (float)W) / cam.fx);
+                    const float limy = op.jac_clip * ((0.5f * (float)H) / cam.fy);
+                    const float xc = clampf_(xt, -limx, limx);
+                    const float yc = clampf_(yt, -limy, limy);
+                    const float J00 = cam.fx / tz, J02 = -((cam.fx * xc) / tz);
+                    const float J11 = cam.fy / tz, J12 = -((cam.fy * yc) / tz);
+                    // 3D covariance Sigma = M M^T, M = R_q diag(s)
+                    const float r00 = 1.0f - 2.0f * (y * y + z * z);
+                    const float r01 = 2.0f * (x * y - w * z);
+                    const float r02 = 2.0f * (x * z + w * y);
+                    const float r10 = 2.0f * (x * y + w * z);
+                    const float r11 = 1.0f - 2.0f * (x * x + z * z);
+                    const float r12 = 2.0f * (y * z - w * x);
+                    const float r20 = 2.0f * (x * z - w * y);
+                    const float r21 = 2.0f * (y * z + w * x);
+                    const float r22 = 1.0f - 2.0f * (x * x + y * y);
+                    const float M00 = r00 * s0, M01 = r01 * s1, M02 = r02 * s2;
+                    const float M10 = r10 * s0, M11 = r11 * s1, M12 = r12 * s2;
+                    const float M20 = r20 * s0, M21 = r21 * s1, M22 = r22 * s2;
+                    const float S00 = (M00 * M00 + M01 * M01) + M02 * M02;
+                    const float S01 = (M00 * M10 + M01 * M11) + M02 * M12;
+                    const float S02 = (M00 * M20 + M01 * M21) + M02 * M22;
+                    const float S11 = (M10 * M10 + M11 * M11) + M12 * M12;
+                    const float S12 = (M10 * M20 + M11 * M21) + M12 * M22;
+                    const float S22 = (M20 * M20 + M21 * M21) + M22 * M22;
+                    // 2D covariance Sigma' = T Sigma T^T, T = J R_cam
+                    const float T00 = J00 * R[0] + J02 * R[6], T01 = J00 * R[1] + J02 * R[7],
+                                T02 = J00 * R[2] + J02 * R[8];
+                    const float T10 = J11 * R[3] + J12 * R[6], T11 = J11 * R[4] + J12 * R[7],
+                                T12 = J11 * R[5] + J12 * R[8];
+                    const float U00 = (T00 * S00 + T01 * S01) + T02 * S02;
+                    const float U01 = (T00 * S01 + T01 * S11) + T02 * S12;
+                    const float U02 = (T00 * S02 + T01 * S12) + T02 * S22;
+                    const float U10 = (T10 * S00 + T11 * S01) + T12 * S02;
+                    const float U11 = (T10 * S01 + T11 * S11) + T12 * S12;
+                    const float U12 = (T10 * S02 + T11 * S12) + T12 * S22;
+                    const float ca = ((U00 * T00 + U01 * T01) + U02 * T02) + op.dilation;
+                    const float cb = (U00 * T10 + U01 * T11) + U02 * T12;
+                    const float cc = ((U10 * T10 + U11 * T11) + U12 * T12) + op.dilation;
+                    const float det = ca * cc - cb * cb;
+                    if (det > 0.0f) {
+                        A = cc / det;
+                        B = (-cb) / det;
+                        C = ca / det;
+                        // opacity-aware extent (Eq. 3), capped by the 3 sigma rule (Eq. 1)
+                        double k2d = 2.0 * canon_log((double)o / (double)op.alpha_min);
+                        if (op.cap_3sigma && k2d > 9.0) k2d = 9.0;
+                        k2 = (float)k2d;
+                        // rectangle tangent to the ellipse (Sec. 4.1), in pixel samples
+                        const float hx = sqrtf(k2 * ca), hy = sqrtf(k2 * cc);
+                        const float xlo = clampf_((u - hx) - 0.5f, -1.0f, (float)W);
+                        const float xhi = clampf_((u + hx) - 0.5f, -1.0f, (float)W);
+                        const float ylo = clampf_((v - hy) - 0.5f, -1.0f, (float)H);
+                        const float yhi = clampf_((v + hy) - 0.5f, -1.0f, (float)H);
+                        int i0 = (int)ceilf(xlo), i1 = (int)floorf(xhi);
+                        int j0 = (int)ceilf(ylo), j1 = (int)floorf(yhi);
+                        i0 = i0 < 0 ? 0 : i0;
+                        j0 = j0 < 0 ? 0 : j0;
+                        i1 = i1 > W - 1 ? W - 1 : i1;
+                        j1 = j1 > H - 1 ? H - 1 : j1;
+                        if (i0 <= i1 && j0 <= j1) {
+                            tx0 = i0 / kTile;
+                            tx1 = i1 / kTile;
+                            ty0 = j0 / kTile;
+                            ty1 = j1 / kTile;
+                            // SH colour for surviving Gaussians only (Alg. 4)
+                            const float dxw = mx - cam.eye[0], dyw = my - cam.eye[1], dzw = mz - cam.eye[2];
+                            const float dn = sqrtf((dxw * dxw + dyw * dyw) + dzw * dzw);
+                            float Y[16];
+                            sh_basis(dxw / dn, dyw / dn, dzw / dn, sc.D, Y);
+                            const int nk = (sc.D + 1) * (sc.D + 1);
+                            float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+                            for (int k = 0; k < nk; ++k) {
+                                a0 = a0 + sc.sh[(int64_t)(3 * k + 0) * st + g] * Y[k];
+                                a1 = a1 + sc.sh[(int64_t)(3 * k + 1) * st + g] * Y[k];
+                                a2 = a2 + sc.sh[(int64_t)(3 * k + 2) * st + g] * Y[k];
+                            }
+                            a0 = a0 + 0.5f;
+                            a1 = a1 + 0.5f;
+                            a2 = a2 + 0.5f;
+                            // non-finite SH inputs cull the Gaussian
+                            valid = isfinite(a0) && isfinite(a1) && isfinite(a2);
+                            col[0] = a0 > 0.0f ? a0 : 0.0f;
+                            col[1] = a1 > 0.0f ? a1 : 0.0f;
+                            col[2] = a2 > 0.0f ? a2 : 0.0f;
+                        }
+                    }
+                }
+            }
+        }
+    }
+
+    // ---- exact tile count (Alg. 3 over the rectangle) -------------------------
+    const int ntx = tx1 - tx0 + 1, nty = ty1 - ty0 + 1;
+    const int nt = valid ? ntx * nty : 0;
+    uint32_t cnt = 0;
+    uint64_t hm = 0;
+    if (op.binning == 1) {
+        cnt = (uint32_t)nt;
+        hm = nt >= 64 ? ~0ull : ((1ull << nt) - 1ull);
+        if (nt > 64) hm = 0;
+    } else {
+        if (valid && nt <= kSmallCount) {
+            int bit = 0;
+            for (int ty = ty0; ty <= ty1; ++ty)
+                for (int tx = tx0; tx <= tx1; ++tx, ++bit)
+                    if (tile_hit(u, v, A, B, C, k2, tx, ty, W, H)) hm |= 1ull << bit;
+            cnt = (uint32_t)__popcll(hm);
+        }
+        // larger rectangles: the whole wavefront tests 64 tiles per step
+        // (Sec. 5.1.2 adaptive size-aware scheduling, with wave64)
+        uint64_t pending = __ballot(valid && nt > kSmallCount);
+        while (pending) {
+            const int src = __ffsll((unsigned long long)pending) - 1;
+            pending &= pending - 1;
+            const float su = bcast(u, src), sv = bcast(v, src), sA = bcast(A, src), sB = bcast(B, src),
+                        sC = bcast(C, src), sk2 = bcast(k2, src);
+            const int stx0 = bcast(tx0, src), sty0 = bcast(ty0, src), sntx = bcast(ntx, src), snt = bcast(nt, src);
+            uint32_t tot = 0;
+            uint64_t first = 0;
+            for (int c0 = 0; c0 < snt; c0 += kWave) {
+                const int idx = c0 + lane;
+                bool h = false;
+                if (idx < snt) {
+                    const int ry = idx / sntx;
+                    const int rx = idx - ry * sntx;
+                    h = tile_hit(su, sv, sA, sB, sC, sk2, stx0 + rx, sty0 + ry, W, H);
+                }
+                const uint64_t b = __ballot(h);
+                tot += (uint32_t)__popcll(b);
+                if (c0 == 0) first = b;
+            }
+            if (lane == src) {
+                cnt = tot;
+                hm = snt <= kWave ? first : 0ull;
+            }
+        }
+    }
+
+    if (g < sc.P) {
+        const uint32_t key = valid ? __float_as_uint(tz) : kInvalidKey;
+        dkey[g] = key;
+        count[g] = valid ? cnt : 0u;
+        if (valid) {
+            GaussState s;
+            s.f0 = make_float4(u, v, A, B);
+            s.f1 = make_float4(C, k2, log2f(o), col[0]);
+            s.f2 = make_float4(col[1], col[2], tz, o);
+            gs[g] = s;
+            rect[g] = make_uint4((uint32_t)tx0, (uint32_t)tx1, (uint32_t)ty0, (uint32_t)ty1);
+            mask[g] = make_uint2((uint32_t)hm, (uint32_t)(hm >> 32));
+            atomicAdd(&s_hist[0 * kRadix + (key & 0xff)], 1u);
+            atomicAdd(&s_hist[1 * kRadix + ((key >> 8) & 0xff)], 1u);
+            atomicAdd(&s_hist[2 * kRadix + ((key >> 16) & 0xff)], 1u);
+            atomicAdd(&s_hist[3 * kRadix + (key >> 24)], 1u);
+        }
+    }
+    const uint64_t vb = __ballot(valid);
+    if (lane == 0 && vb) atomicAdd(&fc->visible, (uint32_t)__popcll(vb));
+    __syncthreads();
+    for (int i = threadIdx.x; i < 4 * kRadix; i += kBlock) {
+        const uint32_t h = s_hist[i];
+        if (h) atomicAdd(&fc->hist[i / kRadix][i % kRadix], h);
+    }
+}
+
+struct PassDigits {
+    int first_pass, npasses;
+    int shift[3], bits[3];
+};
+
+// Key emission: one lane per Gaussian in (depth, index) order writes its
+// (tile, index) pairs at its scanned offset (Alg. 2 with the offsets of a
+// prefix scan; the tile test is reused from the preprocess through the hit
+// mask, or re-run for rectangles of more than 64 tiles).  Also accumulates the
+// digit histograms of the tile-sort passes.
+__global__ __launch_bounds__(kBlock) void k_emit(int W, int H, int binning, const uint32_t *__restrict__ order,
+                                                 uint32_t visible, const uint32_t *__restrict__ offsets,
+                                                 const GaussState *__restrict__ gs, const uint4 *__restrict__ rect,
+                                                 const uint32_t *__restrict__ count, const uint2 *__restrict__ mask,
+                                                 uint32_t *__restrict__ tile_keys, uint32_t *__restrict__ values,
+                                                 uint32_t cap, FrameCounters *fc, PassDigits pd) {
+    __shared__ uint32_t s_hist[3 * kRadix];
+    for (int i = threadIdx.x; i < 3 * kRadix; i += kBlock) s_hist[i] = 0;
+    __syncthreads();
+    const int tiles_x = (W + kTile - 1) / kTile;
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t r = blockIdx.x * kBlock + threadIdx.x;
+    const bool act = r < visible;
+    uint32_t g = 0, c = 0, base = 0;
+    uint4 rc = make_uint4(0, 0, 0, 0);
+    uint64_t m = 0;
+    if (act) {
+        g = order[r];
+        c = count[g];
+        base = offsets[r];
+        rc = rect[g];
+        const uint2 mm = mask[g];
+        m = (uint64_t)mm.x | ((uint64_t)mm.y << 32);
+    }
+    const int ntx = (int)rc.y - (int)rc.x + 1;
+    const int nt = act ? ntx * ((int)rc.w - (int)rc.z + 1) : 0;
+
+    auto record = [&](uint32_t tile) {
+        for (int p = 0; p < pd.npasses; ++p)
+            atomicAdd(&s_hist[p * kRadix + ((tile >> pd.shift[p]) & ((1u << pd.bits[p]) - 1u))], 1u);
+    };
+
+    const bool small = act && c > 0 && c <= kSmallEmit && nt <= kWave;
+    if (small) {
+        uint64_t mm = m;
+        uint32_t k = 0;
+        while (mm) {
+            const int b = __ffsll((unsigned long long)mm) - 1;
+            mm &= mm - 1;
+            const int ry = b / ntx, rx = b - ry * ntx;
+            const uint32_t tile = (uint32_t)(((int)rc.z + ry) * tiles_x + ((int)rc.x + rx));
+            if (base + k < cap) {  // never leave the pair buffers
+                tile_keys[base + k] = tile;
+                values[base + k] = g;
+            }
+            ++k;
+            record(tile);
+        }
+    }
+    const uint64_t lt = (1ull << lane) - 1ull;
+    uint64_t pending = __ballot(act && c > 0 && !small);
+    while (pending) {
+        const int src = __ffsll((unsigned long long)pending) - 1;
+        pending &= pending - 1;
+        const uint32_t sg = bcast(g, src), sbase = bcast(base, src);
+        const int stx0 = bcast((int)rc.x, src), sty0 = bcast((int)rc.z, src), sntx = bcast(ntx, src),
+                  snt = bcast(nt, src);
+        if (snt <= kWave) {
+            const uint64_t sm = (uint64_t)bcast((uint32_t)m, src) | ((uint64_t)bcast((uint32_t)(m >> 32), src) << 32);
+            if ((sm >> lane) & 1ull) {
+                const int ry = lane / sntx, rx = lane - ry * sntx;
+                const uint32_t tile = (uint32_t)((sty0 + ry) * tiles_x + (stx0 + rx));
+                const uint32_t at = sbase + (uint32_t)__popcll(sm & lt);
+                if (at < cap) {
+                    tile_keys[at] = tile;
+                    values[at] = sg;
+                }
+                record(tile);
+            }
+        } else {
+            const GaussState s = gs[sg];
+            uint32_t run = 0;
+            for (int c0 = 0; c0 < snt; c0 += kWave) {
+                const int idx = c0 + lane;
+                bool h = false;
+                int tile = 0;
+                if (idx < snt) {
+                    const int ry = idx / sntx, rx = idx - ry * sntx;
+                    tile = (sty0 + ry) * tiles_x + (stx0 + rx);
+                    h = binning == 1 ||
+                        tile_hit(s.f0.x, s.f0.y, s.f0.z, s.f0.w, s.f1.x, s.f1.y, stx0 + rx, sty0 + ry, W, H);
+                }
+                const uint64_t b = __ballot(h);
+                if (h) {
+                    const uint32_t at = sbase + run + (uint32_t)__popcll(b & lt);
+                    if (at < cap) {
+                        tile_keys[at] = (uint32_t)tile;
+                        values[at] = sg;
+                    }
+                    record((uint32_t)tile);
+                }
+                run += (uint32_t)__popcll(b);
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < pd.npasses * kRadix; i += kBlock) {
+        const uint32_t h = s_hist[i];
+        if (h) atomicAdd(&fc->hist[pd.first_pass + i / kRadix][i % kRadix], h);
+    }
+}
+
+}  // namespace
+
+void launch_preprocess(const DevScene &sc, const DevCamera &cam, const DevOptions &op, int W, int H,
+                       GaussState *gs, uint4 *rect, uint32_t *count, uint2 *mask, uint32_t *dkey,
+                       FrameCounters *fc, hipStream_t s) {
+    if (sc.P <= 0) return;
+    const unsigned grid = (unsigned)((sc.P + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_preprocess, dim3(grid), dim3(kBlock), 0, s, sc, cam, op, W, H, gs, rect, count, mask,
+                       dkey, fc);
+}
+
+void launch_emit(const DevScene &sc, int W, int H, int binning, const uint32_t *order, uint32_t visible,
+                 const uint32_t *offsets, const GaussState *gs, const uint4 *rect, const uint32_t *count,
+                 const uint2 *mask, uint32_t *tile_keys, uint32_t *values, uint32_t cap, FrameCounters *fc,
+                 int first_pass, int npasses, const int *shifts, const int *bits, hipStream_t s) {
+    (void)sc;
+    if (visible == 0) return;
+    PassDigits pd{};
+    pd.first_pass = first_pass;
+    pd.npasses = npasses;
+    for (int p = 0; p < npasses && p < 3; ++p) {
+        pd.shift[p] = shifts[p];
+        pd.bits[p] = bits[p];
+    }
+    const unsigned grid = (visible + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_emit, dim3(grid), dim3(kBlock), 0, s, W, H, binning, order, visible, offsets, gs, rect,
+                       count, mask, tile_keys, values, cap, fc, pd);
+}
+
+}  // namespace fgs

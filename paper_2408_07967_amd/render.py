@@ -1,0 +1,104 @@
+"""PyTorch-facing wrapper over the C ABI.  PyTorch supplies device memory and
+the current HIP stream; every stage of the rasterizer runs in libfgs.so."""
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+
+class GaussianScene:
+    """Planar float32 Gaussian parameters on a GPU (shapes [planes, P])."""
+
+    def __init__(self, means, log_scales, quats, logits, sh, sh_degree):
+        self.means, self.log_scales, self.quats, self.logits, self.sh = means, log_scales, quats, logits, sh
+        self.sh_degree = int(sh_degree)
+        P = means.shape[1]
+        for name, t, planes in (("means", means, 3), ("log_scales", log_scales, 3), ("quats", quats, 4),
+                                ("logits", logits, 1), ("sh", sh, 3 * (self.sh_degree + 1) ** 2)):
+            if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != (planes, P):
+                raise ValueError(f"{name}: expected a contiguous float32 CUDA tensor of shape ({planes}, {P}), "
+                                 f"got {tuple(t.shape)} {t.dtype} on {t.device}")
+
+    @property
+    def P(self):
+        return int(self.means.shape[1])
+
+    @staticmethod
+    def from_numpy(scene, device="cuda"):
+        def t(a):
+            return torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device)
+        return GaussianScene(t(scene.means), t(scene.log_scales), t(scene.quats), t(scene.logits), t(scene.sh),
+                             scene.sh_degree)
+
+    def tensors(self):
+        return (self.means, self.log_scales, self.quats, self.logits, self.sh)
+
+    def abi(self):
+        return B.make_scene(self.P, self.P, self.sh_degree, *(x.data_ptr() for x in self.tensors()))
+
+
+def camera_abi(cam):
+    return B.make_camera(np.asarray(cam.R, np.float32), np.asarray(cam.t, np.float32),
+                         np.asarray(cam.eye, np.float32), cam.fx, cam.fy, cam.cx, cam.cy, cam.near)
+
+
+def options_abi(opts=None):
+    if opts is None:
+        return B.default_options()
+    if isinstance(opts, B.FgsOptions):
+        return opts
+    return B.default_options(**opts)
+
+
+class Renderer:
+    """One fgs_context on the current CUDA (HIP) device."""
+
+    def __init__(self, device=None):
+        dev = torch.cuda.current_device() if device is None else int(device)
+        self.device = dev
+        self.ctx = B.Context(dev)
+
+    def reserve(self, max_gaussians, max_pairs, max_w, max_h):
+        self.ctx.check(B.lib().fgs_reserve(self.ctx.handle, int(max_gaussians), int(max_pairs), int(max_w),
+                                           int(max_h)))
+
+    def scratch_bytes(self):
+        return int(B.lib().fgs_scratch_bytes(self.ctx.handle))
+
+    def render(self, scene, cam, W, H, opts=None, out=None, want_T=False, want_last=False, save=False):
+        """Render; returns dict(rgb [3,H,W], T [H,W] or None, last [H,W] or None,
+        stats, frame handle or None)."""
+        dev = scene.means.device
+        rgb = out if out is not None else torch.empty((3, H, W), dtype=torch.float32, device=dev)
+        T = torch.empty((H, W), dtype=torch.float32, device=dev) if want_T else None
+        last = torch.empty((H, W), dtype=torch.int32, device=dev) if want_last else None
+        sc = scene.abi()
+        cm = camera_abi(cam)
+        op = options_abi(opts)
+        st = B.FgsStats()
+        fr = C.c_void_p()
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        status = B.lib().fgs_render(self.ctx.handle, C.byref(sc), C.byref(cm), int(W), int(H), C.byref(op),
+                                    rgb.data_ptr(), T.data_ptr() if T is not None else None,
+                                    last.data_ptr() if last is not None else None,
+                                    C.byref(fr) if save else None, C.byref(st), stream)
+        self.ctx.check(status)
+        return dict(rgb=rgb, T=T, last=last, frame=fr if save else None,
+                    stats=dict(visible=st.visible, pairs=st.pairs, tiles_x=st.tiles_x, tiles_y=st.tiles_y,
+                               sort_passes=st.sort_passes))
+
+    def frame_field(self, frame, field):
+        n = int(B.lib().fgs_frame_field_bytes(frame, field))
+        buf = np.zeros(max(n, 4) // 4, np.uint32)
+        self.ctx.check(B.lib().fgs_frame_download(self.ctx.handle, frame, field,
+                                                  buf.ctypes.data_as(C.c_void_p), n))
+        return buf[: n // 4]
+
+    def release(self, frame):
+        if frame:
+            self.ctx.check(B.lib().fgs_frame_release(self.ctx.handle, frame))
+
+    def close(self):
+        self.ctx.close()
