@@ -1,0 +1,166 @@
+#!/usr/bin/env python3
+"""Benchmark of the plain renderer on one MI355X.
+
+Default workload: the 10,000,000-Gaussian ground-plane scene (SH degree 3)
+rendered at 3840x2160 through the camera at 80 m altitude pitched 30 deg
+down (synthetic stand-in for the paper's large-scale aerial 4K case).
+A step is one full frame through the C ABI: preprocess with the exact
+ellipse/tile test, depth sort, count scan, key emission, tile sort, tile
+ranges and blending, with the scene already resident in HBM.
+
+Prints one JSON line with frames/s, the blend kernel's roofline figures
+(measured live with HIP events on the render stream) and the CPU oracle
+timed on the same frame.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "4K frames/s (10M Gaussians); served p50/p99 latency vs plain renderer"
+WORKLOADS = {
+    "city4k": dict(kind="city", W=3840, H=2160, name="city-10M-gaussians-3840x2160"),
+    "city8k": dict(kind="city", W=7680, H=4320, name="city-10M-gaussians-7680x4320"),
+    "medium": dict(kind="medium", W=1920, H=1080, name="medium-1M-gaussians-1920x1080"),
+    "small": dict(kind="small", W=256, H=256, name="small-10k-gaussians-256x256"),
+}
+# FP32 operations of one (pixel, Gaussian) evaluation of the blend, FMA = 2:
+# dx, dy (2); q = A dx^2 + 2B dx dy + C dy^2 (7); exponent FMA (2); exp2 (1);
+# alpha clamp (1); T' = T - alpha T (2); weight alpha T (1); 3 colour FMAs (6).
+FLOP_PER_EVAL = 22
+# 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, non-packed FP32
+PEAK_ALU_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    p = os.path.join(ROOT, "paper_2408_07967_amd", "csrc", "k_blend.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def traffic_from_profiles(workload, evals_per_launch):
+    """HBM bytes per blend launch from committed rocprofv3 counter runs, or
+    None if absent or taken on a different blend kernel source."""
+    p = os.path.join(ROOT, "profiles", f"blend_{workload}_traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    if d.get("kernel_sha") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(scene, cam, W, H, opts):
+    """The CPU oracle (binary64, OpenMP over Gaussians and tiles), untuned,
+    timed on one full frame of the same workload."""
+    from oracle import oracle as orc
+    prep = orc.Prepared(scene, cam, W, H, opts, "f64")
+    t0 = time.perf_counter()
+    state, ints, n = orc.preprocess(prep)
+    tiles, vals, rng = orc.pairs(prep, state, ints, n)
+    orc.blend_tiled(prep, state, vals, rng)
+    dt = time.perf_counter() - t0
+    return dict(value=round(1.0 / dt, 5), unit="frames/s", cores=int(orc._lib().orc_num_threads()),
+                kind="oracle", sample=f"one full {W}x{H} frame of the same scene and camera, binary64 "
+                                      f"(preprocess + pairs + sort + blend; input conversion excluded); "
+                                      f"{dt:.2f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="city4k", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-work-count", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this renderer runs on a single MI355X; "
+              "multi-GPU sharding is a design note, not a measured path", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2408_07967_amd import scenes
+    from paper_2408_07967_amd import binding as B
+    from paper_2408_07967_amd.render import GaussianScene, Renderer
+
+    wl = WORKLOADS[args.workload]
+    W, H = wl["W"], wl["H"]
+    t0 = time.perf_counter()
+    sc = scenes.make_scene(wl["kind"])
+    cam = scenes.camera_for(wl["kind"], W=W, H=H)
+    log(f"[bench] scene {wl['kind']} P={sc.P} drawn in {time.perf_counter() - t0:.1f}s")
+    torch.cuda.set_device(0)
+    gsc = GaussianScene.from_numpy(sc, "cuda:0")
+    R = Renderer(0)
+    opts = scenes.DEFAULT_OPTIONS
+    out = torch.empty((3, H, W), dtype=torch.float32, device="cuda:0")
+    stats = None
+    for _ in range(max(1, args.warmup)):
+        stats = R.render(gsc, cam, W, H, opts, out=out)["stats"]
+    torch.cuda.synchronize()
+    log(f"[bench] warmup done: visible {stats['visible']} pairs {stats['pairs']}")
+
+    evals = None
+    if not args.no_work_count:
+        R.set_instrumentation(B.INSTR_WORK)
+        R.render(gsc, cam, W, H, opts, out=out)
+        evals = int(R.instrumentation()["blend_evaluations"])
+        log(f"[bench] blend evaluations per frame: {evals}")
+
+    R.set_instrumentation(B.INSTR_STAGE_TIMES)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        R.render(gsc, cam, W, H, opts, out=out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    inst = R.instrumentation()
+    R.set_instrumentation(0)
+    dt = t1 - t0
+    fps = args.steps / dt
+    nf = max(1, inst["frames"])
+    stage_ms = {k[3:]: round(inst[k] / nf, 4) for k in inst if k.startswith("ms_")}
+    log(f"[bench] {args.steps} frames in {dt:.3f}s -> {fps:.2f} frames/s; stages {stage_ms}")
+
+    roof = None
+    if evals is not None and stage_ms["blend"] > 0:
+        achieved = evals * FLOP_PER_EVAL / (stage_ms["blend"] * 1e-3) / 1e12
+        roof = dict(bound="alu", achieved=round(achieved, 3), peak=round(PEAK_ALU_TFLOPS, 1), unit="TFLOP/s",
+                    frac=round(achieved / PEAK_ALU_TFLOPS, 4),
+                    traffic=traffic_from_profiles(args.workload, evals),
+                    kernel="k_blend", evaluations_per_launch=evals, flop_per_evaluation=FLOP_PER_EVAL,
+                    avg_launch_ms=stage_ms["blend"])
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on one frame ...")
+        cpu = cpu_baseline(sc, cam, W, H, opts)
+        log(f"[bench] cpu baseline {cpu}")
+
+    res = dict(metric=METRIC, value=round(fps, 3), unit="frames/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=round(dt / args.steps * 1e3, 4), higher_is_better=True,
+               scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
+               config=dict(workload=wl["name"], gaussians=sc.P, width=W, height=H, sh_degree=sc.sh_degree,
+                           tile=16, visible=int(stats["visible"]), pairs=int(stats["pairs"]),
+                           pairs_per_s=round(stats["pairs"] * fps, 1), stage_ms=stage_ms),
+               roofline=roof, cpu_baseline=cpu)
+    print(json.dumps(res), flush=True)
+    R.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -199,6 +199,32 @@ typedef enum {
     FGS_FIELD_RANGES = 6
 } fgs_field;
 
+/* ---- instrumentation (measurement only; off by default) ------------------ */
+
+#define FGS_INSTR_STAGE_TIMES 1 /* HIP events around every stage on the render stream */
+#define FGS_INSTR_WORK 2        /* count blend evaluations (a slower blend variant)   */
+
+typedef struct {
+    int64_t frames;            /* instrumented frames folded into the sums below     */
+    double ms_preprocess;      /* summed stage times over those frames (ms)          */
+    double ms_depth_sort;
+    double ms_scan;
+    double ms_emit;
+    double ms_tile_sort;
+    double ms_ranges;
+    double ms_blend;
+    int64_t blend_evaluations; /* with FGS_INSTR_WORK: sum over pixels of the number of
+                                  list entries the pixel examines (up to and including
+                                  the entry at which it stops, else the whole list),
+                                  summed over the instrumented frames                */
+} fgs_timings;
+
+/* Select instrumentation flags for later fgs_render calls and clear the sums. */
+fgs_status fgs_set_instrumentation(fgs_context *ctx, int flags);
+
+/* Wait for the last instrumented frame and return the sums. */
+fgs_status fgs_get_instrumentation(fgs_context *ctx, fgs_timings *out);
+
 size_t fgs_frame_field_bytes(const fgs_frame *frame, fgs_field field);
 fgs_status fgs_frame_download(fgs_context *ctx, const fgs_frame *frame, fgs_field field, void *host_dst,
                               size_t bytes);

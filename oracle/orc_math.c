@@ -29,6 +29,19 @@
  */
 #include <stdint.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Number of threads the oracle's parallel loops use (reported with timings). */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 #define ORC_LN2_HI 0x1.62e42fee00000p-1
 #define ORC_LN2_LO 0x1.a39ef35793c76p-33

@@ -48,6 +48,15 @@ class FgsStats(C.Structure):
                 ("sort_passes", C.c_int32), ("reserved", C.c_int32)]
 
 
+class FgsTimings(C.Structure):
+    _fields_ = [("frames", C.c_int64), ("ms_preprocess", C.c_double), ("ms_depth_sort", C.c_double),
+                ("ms_scan", C.c_double), ("ms_emit", C.c_double), ("ms_tile_sort", C.c_double),
+                ("ms_ranges", C.c_double), ("ms_blend", C.c_double), ("blend_evaluations", C.c_int64)]
+
+
+INSTR_STAGE_TIMES = 1
+INSTR_WORK = 2
+
 # name -> (restype, argtypes); the exported symbols of include/fgs.h
 PROTOTYPES = {
     "fgs_create": (C.c_int, [C.c_int, C.POINTER(C.c_void_p)]),
@@ -68,6 +77,8 @@ PROTOTYPES = {
     "fgs_frame_field_bytes": (C.c_size_t, [C.c_void_p, C.c_int]),
     "fgs_frame_download": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_size_t]),
     "fgs_frame_stats": (C.c_int, [C.c_void_p, C.POINTER(FgsStats)]),
+    "fgs_set_instrumentation": (C.c_int, [C.c_void_p, C.c_int]),
+    "fgs_get_instrumentation": (C.c_int, [C.c_void_p, C.POINTER(FgsTimings)]),
 }
 
 _lib = None

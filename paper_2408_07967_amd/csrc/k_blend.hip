@@ -51,11 +51,12 @@ __device__ __forceinline__ bool rect_hit(float u, float v, float A, float B, flo
     return hit;
 }
 
+template <bool kCountWork>
 __global__ __launch_bounds__(kBlock) void k_blend(const GaussState *__restrict__ gs,
                                                   const uint32_t *__restrict__ values,
                                                   const uint2 *__restrict__ ranges, int W, int H, int tiles_x,
                                                   DevOptions op, float *__restrict__ rgb, float *__restrict__ Tout,
-                                                  uint32_t *__restrict__ last_out) {
+                                                  uint32_t *__restrict__ last_out, unsigned long long *work) {
     __shared__ float4 s_f0[kBlock], s_f1[kBlock], s_f2[kBlock];
     __shared__ uint32_t s_qmask[kBlock];
 
@@ -75,6 +76,7 @@ __global__ __launch_bounds__(kBlock) void k_blend(const GaussState *__restrict__
     float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
     uint32_t last = 0;
     bool done = !in_img;
+    uint32_t examined = in_img ? (end - start) : 0u;  // entries this pixel must look at
     const float nl2e = -0.72134752044448170f;  // -log2(e) / 2
     const float amax = op.alpha_max, tstop = op.T_stop;
 
@@ -125,6 +127,7 @@ __global__ __launch_bounds__(kBlock) void k_blend(const GaussState *__restrict__
                         inq = false;
                         px = kFar;
                         done = true;
+                        if (kCountWork) examined = b0 - start + j + 1;
                     }
                     all_done = __ballot(!done) == 0;
                 }
@@ -142,6 +145,14 @@ __global__ __launch_bounds__(kBlock) void k_blend(const GaussState *__restrict__
         if (__syncthreads_count(done ? 1 : 0) == kBlock) break;
     }
 
+    if (kCountWork) {
+        // a wave that skipped a Gaussian whose ellipse misses its quadrant
+        // still counts it: the count is the method's, not this kernel's
+        unsigned long long v = examined;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) v += __shfl_xor(v, d, kWave);
+        if (lane == 0) atomicAdd(work, v);
+    }
     if (in_img) {
         const size_t hw = (size_t)W * H;
         const size_t p = (size_t)pj * W + pi;
@@ -156,10 +167,15 @@ __global__ __launch_bounds__(kBlock) void k_blend(const GaussState *__restrict__
 }  // namespace
 
 void launch_blend(const GaussState *gs, const uint32_t *values, const uint2 *ranges, int W, int H,
-                  const DevOptions &op, float *rgb, float *T, uint32_t *last, hipStream_t s) {
+                  const DevOptions &op, float *rgb, float *T, uint32_t *last, unsigned long long *work,
+                  hipStream_t s) {
     const int tiles_x = (W + kTile - 1) / kTile, tiles_y = (H + kTile - 1) / kTile;
-    hipLaunchKernelGGL(k_blend, dim3((unsigned)(tiles_x * tiles_y)), dim3(kBlock), 0, s, gs, values, ranges, W,
-                       H, tiles_x, op, rgb, T, last);
+    if (work)
+        hipLaunchKernelGGL(k_blend<true>, dim3((unsigned)(tiles_x * tiles_y)), dim3(kBlock), 0, s, gs, values,
+                           ranges, W, H, tiles_x, op, rgb, T, last, work);
+    else
+        hipLaunchKernelGGL(k_blend<false>, dim3((unsigned)(tiles_x * tiles_y)), dim3(kBlock), 0, s, gs, values,
+                           ranges, W, H, tiles_x, op, rgb, T, last, work);
 }
 
 }  // namespace fgs

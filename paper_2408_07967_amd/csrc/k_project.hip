@@ -175,13 +175,51 @@ __device__ __forceinline__ void sh_basis(float x, float y, float z, int D, float
 __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevCamera cam, DevOptions op, int W, int H,
                                                        GaussState *__restrict__ gs, uint4 *__restrict__ rect,
                                                        uint32_t *__restrict__ count, uint2 *__restrict__ mask,
-                                                       uint32_t *__restrict__ dkey, FrameCounters *fc) {
+                                                       uint32_t *__restrict__ dkey, uint2 *__restrict__ chunks,
+                                                       uint32_t chunk_cap, uint32_t *__restrict__ block_hist,
+                                                       FrameCounters *fc) {
+    // Persistent grid: each workgroup walks batches of 256 Gaussians and keeps
+    // its depth-digit histogram, visible count and pending chunk reservations
+    // in LDS, so global atomics are per workgroup, not per batch.
     __shared__ uint32_t s_hist[4 * kRadix];
+    __shared__ uint32_t s_bg[kBigList], s_boff[kBigList], s_bn[kBigList];
+    __shared__ uint32_t s_vis, s_nbig, s_nch, s_base;
     for (int i = threadIdx.x; i < 4 * kRadix; i += kBlock) s_hist[i] = 0;
+    if (threadIdx.x == 0) {
+        s_vis = 0;
+        s_nbig = 0;
+        s_nch = 0;
+    }
     __syncthreads();
 
+    // reserve chunk-list space for the pending large Gaussians and write their
+    // entries (g, first chunk); on overflow only flag it (the host resizes
+    // the list and renders the frame again)
+    auto flush_big = [&]() {
+        __syncthreads();
+        if (threadIdx.x == 0) s_base = s_nch ? atomicAdd(&fc->nchunks, s_nch) : 0u;
+        __syncthreads();
+        const uint32_t base = s_base, nb = s_nbig;
+        const bool ok = (uint64_t)base + s_nch <= chunk_cap;
+        if (!ok && threadIdx.x == 0) atomicOr(&fc->error, kErrChunkOverflow);
+        if (ok) {
+            for (uint32_t e = threadIdx.x; e < nb; e += kBlock) {
+                const uint32_t gg = s_bg[e], first = base + s_boff[e], n = s_bn[e];
+                for (uint32_t c = 0; c < n; ++c) chunks[first + c] = make_uint2(gg, first);
+                mask[gg] = make_uint2(0u, first);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            s_nbig = 0;
+            s_nch = 0;
+        }
+        __syncthreads();
+    };
+
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    for (int64_t g0 = (int64_t)blockIdx.x * kBlock; g0 < sc.P; g0 += (int64_t)gridDim.x * kBlock) {
+    const int64_t g = g0 + threadIdx.x;
     const int64_t st = sc.stride;
     bool valid = false;
     float u = 0, v = 0, A = 0, B = 0, C = 0, k2 = 0, o = 0, tz = 0;
@@ -314,10 +352,22 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevCamera ca
     const int nt = valid ? ntx * nty : 0;
     uint32_t cnt = 0;
     uint64_t hm = 0;
+    // rectangles of more than kBigTiles tiles go to the chunk list, where
+    // workgroups across the GPU test them kChunkTiles tiles at a time
+    const bool chunked = valid && nt > kBigTiles;
+    if (chunked) {
+        const uint32_t nch = (uint32_t)((nt + kChunkTiles - 1) / kChunkTiles);
+        const uint32_t slot = atomicAdd(&s_nbig, 1u);
+        s_bg[slot] = (uint32_t)g;
+        s_bn[slot] = nch;
+        s_boff[slot] = atomicAdd(&s_nch, nch);
+    }
     if (op.binning == 1) {
-        cnt = (uint32_t)nt;
-        hm = nt >= 64 ? ~0ull : ((1ull << nt) - 1ull);
-        if (nt > 64) hm = 0;
+        if (!chunked) {
+            cnt = (uint32_t)nt;
+            hm = nt >= 64 ? ~0ull : ((1ull << nt) - 1ull);
+            if (nt > 64) hm = 0;
+        }
     } else {
         if (valid && nt <= kSmallCount) {
             int bit = 0;
@@ -328,7 +378,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevCamera ca
         }
         // larger rectangles: the whole wavefront tests 64 tiles per step
         // (Sec. 5.1.2 adaptive size-aware scheduling, with wave64)
-        uint64_t pending = __ballot(valid && nt > kSmallCount);
+        uint64_t pending = __ballot(valid && nt > kSmallCount && !chunked);
         while (pending) {
             const int src = __ffsll((unsigned long long)pending) - 1;
             pending &= pending - 1;
@@ -367,7 +417,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevCamera ca
             s.f2 = make_float4(col[1], col[2], tz, o);
             gs[g] = s;
             rect[g] = make_uint4((uint32_t)tx0, (uint32_t)tx1, (uint32_t)ty0, (uint32_t)ty1);
-            mask[g] = make_uint2((uint32_t)hm, (uint32_t)(hm >> 32));
+            if (!chunked) mask[g] = make_uint2((uint32_t)hm, (uint32_t)(hm >> 32));
             atomicAdd(&s_hist[0 * kRadix + (key & 0xff)], 1u);
             atomicAdd(&s_hist[1 * kRadix + ((key >> 8) & 0xff)], 1u);
             atomicAdd(&s_hist[2 * kRadix + ((key >> 16) & 0xff)], 1u);
@@ -375,12 +425,14 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevCamera ca
         }
     }
     const uint64_t vb = __ballot(valid);
-    if (lane == 0 && vb) atomicAdd(&fc->visible, (uint32_t)__popcll(vb));
+    if (lane == 0 && vb) atomicAdd(&s_vis, (uint32_t)__popcll(vb));
     __syncthreads();
-    for (int i = threadIdx.x; i < 4 * kRadix; i += kBlock) {
-        const uint32_t h = s_hist[i];
-        if (h) atomicAdd(&fc->hist[i / kRadix][i % kRadix], h);
-    }
+    if (s_nbig > kBigList - kBlock) flush_big();
+    }  // batch loop
+    if (s_nbig) flush_big();
+    // this workgroup's histogram row; rows are summed by k_hist_reduce
+    for (int i = threadIdx.x; i < 4 * kRadix; i += kBlock) block_hist[(size_t)blockIdx.x * 4 * kRadix + i] = s_hist[i];
+    if (threadIdx.x == 0 && s_vis) atomicAdd(&fc->visible, s_vis);
 }
 
 struct PassDigits {
@@ -396,15 +448,17 @@ struct PassDigits {
 __global__ __launch_bounds__(kBlock) void k_emit(int W, int H, int binning, const uint32_t *__restrict__ order,
                                                  uint32_t visible, const uint32_t *__restrict__ offsets,
                                                  const GaussState *__restrict__ gs, const uint4 *__restrict__ rect,
-                                                 const uint32_t *__restrict__ count, const uint2 *__restrict__ mask,
+                                                 const uint32_t *__restrict__ count, uint2 *__restrict__ mask,
                                                  uint32_t *__restrict__ tile_keys, uint32_t *__restrict__ values,
-                                                 uint32_t cap, FrameCounters *fc, PassDigits pd) {
-    __shared__ uint32_t s_hist[3 * kRadix];
-    for (int i = threadIdx.x; i < 3 * kRadix; i += kBlock) s_hist[i] = 0;
+                                                 uint32_t cap, uint32_t *__restrict__ block_hist, uint32_t row0,
+                                                 PassDigits pd) {
+    __shared__ uint32_t s_hist[kTileHistBins];
+    for (int i = threadIdx.x; i < kTileHistBins; i += kBlock) s_hist[i] = 0;
     __syncthreads();
     const int tiles_x = (W + kTile - 1) / kTile;
     const int lane = threadIdx.x & (kWave - 1);
-    const uint32_t r = blockIdx.x * kBlock + threadIdx.x;
+    for (uint32_t r0 = blockIdx.x * kBlock; r0 < visible; r0 += gridDim.x * kBlock) {
+    const uint32_t r = r0 + threadIdx.x;
     const bool act = r < visible;
     uint32_t g = 0, c = 0, base = 0;
     uint4 rc = make_uint4(0, 0, 0, 0);
@@ -419,6 +473,9 @@ __global__ __launch_bounds__(kBlock) void k_emit(int W, int H, int binning, cons
     }
     const int ntx = (int)rc.y - (int)rc.x + 1;
     const int nt = act ? ntx * ((int)rc.w - (int)rc.z + 1) : 0;
+    // chunked Gaussians only publish their output base; their pairs come later
+    const bool chunked = act && nt > kBigTiles && (uint32_t)(m >> 32) != kNoChunk;
+    if (chunked) mask[g].x = base;
 
     auto record = [&](uint32_t tile) {
         for (int p = 0; p < pd.npasses; ++p)
@@ -443,7 +500,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(int W, int H, int binning, cons
         }
     }
     const uint64_t lt = (1ull << lane) - 1ull;
-    uint64_t pending = __ballot(act && c > 0 && !small);
+    uint64_t pending = __ballot(act && c > 0 && !small && !chunked);
     while (pending) {
         const int src = __ffsll((unsigned long long)pending) - 1;
         pending &= pending - 1;
@@ -488,40 +545,207 @@ __global__ __launch_bounds__(kBlock) void k_emit(int W, int H, int binning, cons
             }
         }
     }
+    }  // batch loop
     __syncthreads();
-    for (int i = threadIdx.x; i < pd.npasses * kRadix; i += kBlock) {
-        const uint32_t h = s_hist[i];
-        if (h) atomicAdd(&fc->hist[pd.first_pass + i / kRadix][i % kRadix], h);
+    for (int i = threadIdx.x; i < kTileHistBins; i += kBlock)
+        block_hist[(size_t)(row0 + blockIdx.x) * kTileHistBins + i] = s_hist[i];
+}
+
+
+// Exact tile counts of chunked Gaussians: one workgroup per chunk of
+// kChunkTiles tiles (persistent grid), per-chunk hit counts kept for the
+// emission, per-Gaussian totals by atomic add.
+__global__ __launch_bounds__(kBlock) void k_big_count(int W, int H, int binning, const GaussState *__restrict__ gs,
+                                                      const uint4 *__restrict__ rect,
+                                                      const uint2 *__restrict__ chunks, uint32_t chunk_cap,
+                                                      uint32_t *__restrict__ chunk_hits, uint32_t *count,
+                                                      const FrameCounters *fc) {
+    __shared__ uint32_t s_w[kBlock / kWave];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    if (fc->error & kErrChunkOverflow) return;  // the frame is rendered again with a larger list
+    const uint32_t n = fc->nchunks < chunk_cap ? fc->nchunks : chunk_cap;
+    for (uint32_t ch = blockIdx.x; ch < n; ch += gridDim.x) {
+        const uint2 e = chunks[ch];
+        if (e.x == kNoChunk) {
+            if (tid == 0) chunk_hits[ch] = 0;
+            continue;
+        }
+        const uint32_t g = e.x, c = ch - e.y;
+        const uint4 rc = rect[g];
+        const int ntx = (int)rc.y - (int)rc.x + 1;
+        const int nt = ntx * ((int)rc.w - (int)rc.z + 1);
+        const int idx = (int)c * kChunkTiles + tid;
+        bool h = false;
+        if (idx < nt) {
+            const int ry = idx / ntx, rx = idx - ry * ntx;
+            if (binning == 1) {
+                h = true;
+            } else {
+                const GaussState s = gs[g];
+                h = tile_hit(s.f0.x, s.f0.y, s.f0.z, s.f0.w, s.f1.x, s.f1.y, (int)rc.x + rx, (int)rc.z + ry, W, H);
+            }
+        }
+        const uint64_t b = __ballot(h);
+        if (lane == 0) s_w[wave] = (uint32_t)__popcll(b);
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t tot = 0;
+            for (int w = 0; w < kBlock / kWave; ++w) tot += s_w[w];
+            chunk_hits[ch] = tot;
+            if (tot) atomicAdd(&count[g], tot);
+        }
+        __syncthreads();
     }
+}
+
+// Pairs of the chunked Gaussians: each chunk re-runs the same exact test and
+// writes its hits after those of the Gaussian's earlier chunks.
+__global__ __launch_bounds__(kBlock) void k_big_emit(int W, int H, int binning, const GaussState *__restrict__ gs,
+                                                     const uint4 *__restrict__ rect, const uint2 *__restrict__ mask,
+                                                     const uint2 *__restrict__ chunks, uint32_t chunk_cap,
+                                                     const uint32_t *__restrict__ chunk_hits,
+                                                     uint32_t *__restrict__ tile_keys, uint32_t *__restrict__ values,
+                                                     uint32_t cap, const FrameCounters *fc,
+                                                     uint32_t *__restrict__ block_hist, uint32_t row0, PassDigits pd) {
+    __shared__ uint32_t s_hist[kTileHistBins];
+    __shared__ uint32_t s_pre[kBlock / kWave], s_cnt[kBlock / kWave];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    for (int i = tid; i < kTileHistBins; i += kBlock) s_hist[i] = 0;
+    __syncthreads();
+    const int tiles_x = (W + kTile - 1) / kTile;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const uint32_t n = fc->nchunks < chunk_cap ? fc->nchunks : chunk_cap;
+    for (uint32_t ch = blockIdx.x; ch < n; ch += gridDim.x) {
+        const uint2 e = chunks[ch];
+        if (e.x == kNoChunk || chunk_hits[ch] == 0) continue;
+        const uint32_t g = e.x, first = e.y, c = ch - first;
+        // hits of this Gaussian's earlier chunks
+        uint32_t p = 0;
+        for (uint32_t k = first + (uint32_t)tid; k < ch; k += kBlock) p += chunk_hits[k];
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) p += __shfl_xor(p, d, kWave);
+        const uint4 rc = rect[g];
+        const int ntx = (int)rc.y - (int)rc.x + 1;
+        const int nt = ntx * ((int)rc.w - (int)rc.z + 1);
+        const int idx = (int)c * kChunkTiles + tid;
+        bool h = false;
+        int tile = 0;
+        if (idx < nt) {
+            const int ry = idx / ntx, rx = idx - ry * ntx;
+            tile = ((int)rc.z + ry) * tiles_x + ((int)rc.x + rx);
+            if (binning == 1) {
+                h = true;
+            } else {
+                const GaussState s = gs[g];
+                h = tile_hit(s.f0.x, s.f0.y, s.f0.z, s.f0.w, s.f1.x, s.f1.y, (int)rc.x + rx, (int)rc.z + ry, W, H);
+            }
+        }
+        const uint64_t b = __ballot(h);
+        if (lane == 0) {
+            s_pre[wave] = p;
+            s_cnt[wave] = (uint32_t)__popcll(b);
+        }
+        __syncthreads();
+        uint32_t before = 0, prefix = 0;
+        for (int w = 0; w < kBlock / kWave; ++w) {
+            before += (w < wave) ? s_cnt[w] : 0u;
+            prefix += s_pre[w];
+        }
+        if (h) {
+            const uint32_t at = mask[g].x + prefix + before + (uint32_t)__popcll(b & lt);
+            if (at < cap) {
+                tile_keys[at] = (uint32_t)tile;
+                values[at] = g;
+            }
+            for (int q = 0; q < pd.npasses; ++q)
+                atomicAdd(&s_hist[q * kRadix + (((uint32_t)tile >> pd.shift[q]) & ((1u << pd.bits[q]) - 1u))], 1u);
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    for (int i = tid; i < kTileHistBins; i += kBlock)
+        block_hist[(size_t)(row0 + blockIdx.x) * kTileHistBins + i] = s_hist[i];
+}
+
+// Sum the per-workgroup histogram rows: out[b] = sum over rows of rows[r][b].
+// Rows are split into groups of kReduceRows so that no thread walks a long
+// chain of dependent loads; groups combine by atomic add into out (cleared
+// at the start of the frame).
+constexpr uint32_t kReduceRows = 32;
+__global__ void k_hist_reduce(const uint32_t *__restrict__ rows, uint32_t nrows, int nbins,
+                              uint32_t *__restrict__ out) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbins) return;
+    const uint32_t r0 = blockIdx.y * kReduceRows;
+    const uint32_t r1 = r0 + kReduceRows < nrows ? r0 + kReduceRows : nrows;
+    uint32_t s = 0;
+#pragma unroll 8
+    for (uint32_t r = r0; r < r1; ++r) s += rows[(size_t)r * nbins + b];
+    if (s) atomicAdd(&out[b], s);
 }
 
 }  // namespace
 
-void launch_preprocess(const DevScene &sc, const DevCamera &cam, const DevOptions &op, int W, int H,
-                       GaussState *gs, uint4 *rect, uint32_t *count, uint2 *mask, uint32_t *dkey,
-                       FrameCounters *fc, hipStream_t s) {
-    if (sc.P <= 0) return;
-    const unsigned grid = (unsigned)((sc.P + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_preprocess, dim3(grid), dim3(kBlock), 0, s, sc, cam, op, W, H, gs, rect, count, mask,
-                       dkey, fc);
+unsigned preprocess_grid(int64_t P) {
+    const int64_t b = (P + kBlock - 1) / kBlock;
+    return (unsigned)(b < kPersistentBlocks ? (b > 0 ? b : 1) : kPersistentBlocks);
 }
 
-void launch_emit(const DevScene &sc, int W, int H, int binning, const uint32_t *order, uint32_t visible,
-                 const uint32_t *offsets, const GaussState *gs, const uint4 *rect, const uint32_t *count,
-                 const uint2 *mask, uint32_t *tile_keys, uint32_t *values, uint32_t cap, FrameCounters *fc,
-                 int first_pass, int npasses, const int *shifts, const int *bits, hipStream_t s) {
-    (void)sc;
-    if (visible == 0) return;
+unsigned emit_grid(uint32_t visible) {
+    const uint32_t b = (visible + kBlock - 1) / kBlock;
+    return b < (uint32_t)kPersistentBlocks ? (b > 0 ? b : 1u) : (unsigned)kPersistentBlocks;
+}
+
+static PassDigits make_digits(int npasses, const int *shifts, const int *bits) {
     PassDigits pd{};
-    pd.first_pass = first_pass;
+    pd.first_pass = 0;
     pd.npasses = npasses;
     for (int p = 0; p < npasses && p < 3; ++p) {
         pd.shift[p] = shifts[p];
         pd.bits[p] = bits[p];
     }
-    const unsigned grid = (visible + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_emit, dim3(grid), dim3(kBlock), 0, s, W, H, binning, order, visible, offsets, gs, rect,
-                       count, mask, tile_keys, values, cap, fc, pd);
+    return pd;
+}
+
+void launch_preprocess(const DevScene &sc, const DevCamera &cam, const DevOptions &op, int W, int H,
+                       GaussState *gs, uint4 *rect, uint32_t *count, uint2 *mask, uint32_t *dkey, uint2 *chunks,
+                       uint32_t chunk_cap, uint32_t *block_hist, FrameCounters *fc, hipStream_t s) {
+    if (sc.P <= 0) return;
+    hipLaunchKernelGGL(k_preprocess, dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, cam, op, W, H, gs, rect,
+                       count, mask, dkey, chunks, chunk_cap, block_hist, fc);
+}
+
+void launch_big_count(int W, int H, int binning, const GaussState *gs, const uint4 *rect, const uint2 *chunks,
+                      uint32_t chunk_cap, uint32_t *chunk_hits, uint32_t *count, const FrameCounters *fc,
+                      hipStream_t s) {
+    if (chunk_cap == 0) return;
+    hipLaunchKernelGGL(k_big_count, dim3(kPersistentBlocks), dim3(kBlock), 0, s, W, H, binning, gs, rect, chunks,
+                       chunk_cap, chunk_hits, count, fc);
+}
+
+void launch_big_emit(int W, int H, int binning, const GaussState *gs, const uint4 *rect, const uint2 *mask,
+                     const uint2 *chunks, uint32_t chunk_cap, const uint32_t *chunk_hits, uint32_t *tile_keys,
+                     uint32_t *values, uint32_t cap, const FrameCounters *fc, uint32_t *block_hist, uint32_t row0,
+                     int npasses, const int *shifts, const int *bits, hipStream_t s) {
+    hipLaunchKernelGGL(k_big_emit, dim3(kPersistentBlocks), dim3(kBlock), 0, s, W, H, binning, gs, rect, mask, chunks,
+                       chunk_cap, chunk_hits, tile_keys, values, cap, fc, block_hist, row0,
+                       make_digits(npasses, shifts, bits));
+}
+
+void launch_emit(const DevScene &sc, int W, int H, int binning, const uint32_t *order, uint32_t visible,
+                 const uint32_t *offsets, const GaussState *gs, const uint4 *rect, const uint32_t *count,
+                 uint2 *mask, uint32_t *tile_keys, uint32_t *values, uint32_t cap, uint32_t *block_hist,
+                 int npasses, const int *shifts, const int *bits, hipStream_t s) {
+    (void)sc;
+    hipLaunchKernelGGL(k_emit, dim3(emit_grid(visible)), dim3(kBlock), 0, s, W, H, binning, order, visible, offsets,
+                       gs, rect, count, mask, tile_keys, values, cap, block_hist, 0u,
+                       make_digits(npasses, shifts, bits));
+}
+
+void launch_hist_reduce(const uint32_t *rows, uint32_t nrows, int nbins, uint32_t *out, hipStream_t s) {
+    if (nrows == 0) return;
+    hipLaunchKernelGGL(k_hist_reduce, dim3((nbins + kBlock - 1) / kBlock, (nrows + kReduceRows - 1) / kReduceRows),
+                       dim3(kBlock), 0, s, rows, nrows, nbins, out);
 }
 
 }  // namespace fgs

@@ -79,6 +79,19 @@ struct fgs_context {
     uint64_t *status = nullptr;
     size_t status_entries = 0;
     uint32_t epoch = 0;
+    // chunk list of Gaussians with large rectangles (used within one render)
+    uint2 *chunks = nullptr;
+    uint32_t *chunk_hits = nullptr;
+    size_t chunk_cap = 0;
+    uint32_t *block_hist = nullptr;  // per-workgroup histogram rows
+    // instrumentation
+    int instr = 0;
+    hipEvent_t ev[2][8] = {};
+    int ev_pending = -1;  // event set of the last instrumented frame not yet folded in
+    int ev_next = 0;
+    hipStream_t ev_stream = nullptr;
+    fgs_timings acc{};
+    unsigned long long *work_dev = nullptr;
 };
 
 namespace {
@@ -108,6 +121,24 @@ uint32_t next_epoch(fgs_context *ctx) {
     ctx->epoch = (ctx->epoch + 1) & 0x3fffffffu;
     if (ctx->epoch == 0) ctx->epoch = 1;
     return ctx->epoch;
+}
+
+// Add the stage times of a completed instrumented frame to the sums.
+void fold_events(fgs_context *ctx) {
+    if (ctx->ev_pending < 0) return;
+    hipEvent_t *e = ctx->ev[ctx->ev_pending];
+    float ms[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int i = 0; i < 7; ++i)
+        if (hipEventElapsedTime(&ms[i], e[i], e[i + 1]) != hipSuccess) ms[i] = 0.0f;
+    ctx->acc.frames += 1;
+    ctx->acc.ms_preprocess += ms[0];
+    ctx->acc.ms_depth_sort += ms[1];
+    ctx->acc.ms_scan += ms[2];
+    ctx->acc.ms_emit += ms[3];
+    ctx->acc.ms_tile_sort += ms[4];
+    ctx->acc.ms_ranges += ms[5];
+    ctx->acc.ms_blend += ms[6];
+    ctx->ev_pending = -1;
 }
 
 template <class T>
@@ -176,6 +207,19 @@ fgs_status ensure_status(fgs_context *ctx, size_t entries) {
     HIP_TRY(ctx, hipMalloc((void **)&ctx->status, cap * sizeof(uint64_t)));
     HIP_TRY(ctx, hipMemset(ctx->status, 0, cap * sizeof(uint64_t)));
     ctx->status_entries = cap;
+    return FGS_OK;
+}
+
+fgs_status ensure_chunks(fgs_context *ctx, size_t need) {
+    need = std::max<size_t>(need, 65536);
+    if (need <= ctx->chunk_cap && ctx->chunks) return FGS_OK;
+    HIP_TRY(ctx, grow(ctx->chunks, 0, need));
+    HIP_TRY(ctx, grow(ctx->chunk_hits, 0, need));
+    ctx->chunk_cap = need;
+    if (!ctx->block_hist) {
+        const size_t rows = 2 * (size_t)kPersistentBlocks + 1;
+        HIP_TRY(ctx, grow(ctx->block_hist, 0, rows * (size_t)kDepthHistBins));
+    }
     return FGS_OK;
 }
 
@@ -350,6 +394,13 @@ void fgs_destroy(fgs_context *ctx) {
     }
     for (FrameBuffers &b : ctx->pool) free_frame_buffers(b);
     free_frame_buffers(ctx->fb);
+    for (auto &set : ctx->ev)
+        for (hipEvent_t &e : set)
+            if (e) (void)hipEventDestroy(e);
+    if (ctx->work_dev) (void)hipFree(ctx->work_dev);
+    if (ctx->chunks) (void)hipFree(ctx->chunks);
+    if (ctx->block_hist) (void)hipFree(ctx->block_hist);
+    if (ctx->chunk_hits) (void)hipFree(ctx->chunk_hits);
     if (ctx->fc_dev) (void)hipFree(ctx->fc_dev);
     if (ctx->fc_host) (void)hipHostFree(ctx->fc_host);
     if (ctx->status) (void)hipFree(ctx->status);
@@ -406,6 +457,7 @@ fgs_status fgs_render(fgs_context *ctx, const fgs_scene *scene, const fgs_camera
     if ((st = ensure_tiles(ctx, fb, ntiles)) != FGS_OK) return st;
     if ((st = ensure_status(ctx, (((size_t)P + kSortTile - 1) / kSortTile + 1) * kRadix)) != FGS_OK) return st;
     if (saved && (st = ensure_pixels(ctx, fb, npix)) != FGS_OK) return st;
+    if ((st = ensure_chunks(ctx, (size_t)P / 8)) != FGS_OK) return st;
 
     DevScene dsc{};
     dsc.means = scene->means;
@@ -419,13 +471,26 @@ fgs_status fgs_render(fgs_context *ctx, const fgs_scene *scene, const fgs_camera
     const DevCamera dcam = to_dev(*cam);
     const DevOptions dop = to_dev(opt);
     FrameCounters *fc = ctx->fc_dev;
+    const bool timed = (ctx->instr & FGS_INSTR_STAGE_TIMES) != 0;
+    const int es = ctx->ev_next;
+    auto mark = [&](int i) {
+        if (timed) (void)hipEventRecord(ctx->ev[es][i], s);
+    };
 
+    uint32_t V = 0, N = 0;
+    for (int attempt = 0;; ++attempt) {
+    const uint32_t chunk_cap = (uint32_t)std::min<size_t>(ctx->chunk_cap, 0xffffffffu);
     // ---- stage 1: preprocess + exact tile count ---------------------------
     launch_fill_u32(reinterpret_cast<uint32_t *>(fc), 0u, sizeof(FrameCounters) / 4, s);
-    launch_preprocess(dsc, dcam, dop, W, H, fb.gs, fb.rect, fb.count, fb.mask, fb.dkey, fc, s);
+    mark(0);
+    launch_preprocess(dsc, dcam, dop, W, H, fb.gs, fb.rect, fb.count, fb.mask, fb.dkey, ctx->chunks, chunk_cap,
+                      ctx->block_hist, fc, s);
+    launch_big_count(W, H, opt.binning, fb.gs, fb.rect, ctx->chunks, chunk_cap, ctx->chunk_hits, fb.count, fc, s);
+    if (P > 0) launch_hist_reduce(ctx->block_hist, preprocess_grid(P), kDepthHistBins, &fc->hist[0][0], s);
     // ---- depth order of the visible Gaussians: 4 LSD passes over the depth
     // digits, hoisted before key duplication (the low half of the (tile |
     // depth) key is the same for every pair of a Gaussian) --------------------
+    mark(1);
     const uint32_t P32 = (uint32_t)P;
     launch_onesweep(fb.dkey, nullptr, fb.dk_b, fb.dv_b, P32, nullptr, 0, 8, 0, true, true, fc, ctx->status,
                     next_epoch(ctx), s);
@@ -435,22 +500,41 @@ fgs_status fgs_render(fgs_context *ctx, const fgs_scene *scene, const fgs_camera
                     next_epoch(ctx), s);
     launch_onesweep(fb.dk_b, fb.dv_b, fb.dkey, fb.dv_a, P32, &fc->visible, 24, 8, 3, false, false, fc, ctx->status,
                     next_epoch(ctx), s);
+    mark(2);
     // ---- stage 2a: scan of the tile counts in depth order -------------------
     launch_count_scan(fb.dv_a, fb.count, P32, fb.offsets, fc, ctx->status, next_epoch(ctx), s);
+    mark(3);
     HIP_TRY(ctx, hipGetLastError());
     HIP_TRY(ctx, hipMemcpyAsync(ctx->fc_host, fc, sizeof(uint32_t) * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
-    if (ctx->fc_host->error) return fail(ctx, FGS_ERR_INTERNAL, "a bounded device wait gave up (sort/scan)");
-    const uint32_t V = ctx->fc_host->visible;
-    const uint32_t N = ctx->fc_host->pairs;
+    fold_events(ctx);  // the previous instrumented frame is complete after the wait
+    if (ctx->fc_host->error & kErrLookback) return fail(ctx, FGS_ERR_INTERNAL, "a bounded device wait gave up");
+    if (ctx->fc_host->error & kErrChunkOverflow) {
+        // the large-Gaussian chunk list was too small: size it exactly and
+        // render the frame again
+        if (attempt > 0) return fail(ctx, FGS_ERR_INTERNAL, "chunk list overflow after resizing");
+        if ((st = ensure_chunks(ctx, (size_t)ctx->fc_host->nchunks + (size_t)ctx->fc_host->nchunks / 8)) != FGS_OK)
+            return st;
+        continue;
+    }
+    V = ctx->fc_host->visible;
+    N = ctx->fc_host->pairs;
+    break;
+    }  // attempts
+    const uint32_t chunk_cap = (uint32_t)std::min<size_t>(ctx->chunk_cap, 0xffffffffu);
 
     // ---- stage 2b: key emission -------------------------------------------
     if ((st = ensure_pairs(ctx, fb, N)) != FGS_OK) return st;
     if ((st = ensure_status(ctx, (((size_t)N + kSortTile - 1) / kSortTile + 1) * kRadix)) != FGS_OK) return st;
     int shifts[3] = {0, 0, 0}, widths[3] = {0, 0, 0};
     const int npass = plan_tile_passes(ceil_log2(ntiles), shifts, widths);
+    const uint32_t pair_cap = (uint32_t)std::min<size_t>(fb.capN, 0xffffffffu);
     launch_emit(dsc, W, H, opt.binning, fb.dv_a, V, fb.offsets, fb.gs, fb.rect, fb.count, fb.mask, fb.tk_a, fb.tv_a,
-                (uint32_t)std::min<size_t>(fb.capN, 0xffffffffu), fc, 4, npass, shifts, widths, s);
+                pair_cap, ctx->block_hist, npass, shifts, widths, s);
+    launch_big_emit(W, H, opt.binning, fb.gs, fb.rect, fb.mask, ctx->chunks, chunk_cap, ctx->chunk_hits, fb.tk_a,
+                    fb.tv_a, pair_cap, fc, ctx->block_hist, emit_grid(V), npass, shifts, widths, s);
+    launch_hist_reduce(ctx->block_hist, emit_grid(V) + kPersistentBlocks, kTileHistBins, &fc->hist[4][0], s);
+    mark(4);
     // ---- stage 3: stable LSD sort of the pairs by tile id -------------------
     uint32_t *ki = fb.tk_a, *vi = fb.tv_a, *ko = fb.tk_b, *vo = fb.tv_b;
     for (int p = 0; p < npass; ++p) {
@@ -459,12 +543,21 @@ fgs_status fgs_render(fgs_context *ctx, const fgs_scene *scene, const fgs_camera
         std::swap(ki, ko);
         std::swap(vi, vo);
     }
+    mark(5);
     launch_tile_ranges(ki, N, fb.ranges, ntiles, s);
+    mark(6);
     // ---- stage 4: blend -----------------------------------------------------
     float *Tdst = saved ? fb.T : out_T;
     uint32_t *Ldst = saved ? fb.last : out_last;
-    launch_blend(fb.gs, vi, fb.ranges, W, H, dop, out_rgb, Tdst, Ldst, s);
+    launch_blend(fb.gs, vi, fb.ranges, W, H, dop, out_rgb, Tdst, Ldst,
+                 (ctx->instr & FGS_INSTR_WORK) ? ctx->work_dev : nullptr, s);
+    mark(7);
     HIP_TRY(ctx, hipGetLastError());
+    if (timed) {
+        ctx->ev_pending = es;
+        ctx->ev_next = es ^ 1;
+        ctx->ev_stream = s;
+    }
     if (saved) {
         if (out_T) HIP_TRY(ctx, hipMemcpyAsync(out_T, fb.T, npix * sizeof(float), hipMemcpyDeviceToDevice, s));
         if (out_last)
@@ -563,6 +656,42 @@ fgs_status fgs_frame_download(fgs_context *ctx, const fgs_frame *f, fgs_field fi
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     HIP_TRY(ctx, hipStreamSynchronize(f->stream));
     HIP_TRY(ctx, hipMemcpy(host_dst, src, bytes, hipMemcpyDeviceToHost));
+    return FGS_OK;
+}
+
+fgs_status fgs_set_instrumentation(fgs_context *ctx, int flags) {
+    if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARGUMENT, "context is NULL");
+    if (flags & ~(FGS_INSTR_STAGE_TIMES | FGS_INSTR_WORK))
+        return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "unknown instrumentation flags %d", flags);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    if (flags & FGS_INSTR_STAGE_TIMES)
+        for (auto &set : ctx->ev)
+            for (hipEvent_t &e : set)
+                if (!e) HIP_TRY(ctx, hipEventCreate(&e));
+    if ((flags & FGS_INSTR_WORK) && !ctx->work_dev)
+        HIP_TRY(ctx, hipMalloc((void **)&ctx->work_dev, sizeof(unsigned long long)));
+    if (ctx->work_dev) HIP_TRY(ctx, hipMemset(ctx->work_dev, 0, sizeof(unsigned long long)));
+    ctx->instr = flags;
+    ctx->ev_pending = -1;
+    ctx->acc = fgs_timings{};
+    return FGS_OK;
+}
+
+fgs_status fgs_get_instrumentation(fgs_context *ctx, fgs_timings *out) {
+    if (!ctx || !out) return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "NULL argument");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    if (ctx->ev_pending >= 0) {
+        HIP_TRY(ctx, hipEventSynchronize(ctx->ev[ctx->ev_pending][7]));
+        fold_events(ctx);
+    }
+    if (ctx->work_dev) {
+        HIP_TRY(ctx, hipDeviceSynchronize());
+        unsigned long long w = 0;
+        HIP_TRY(ctx, hipMemcpy(&w, ctx->work_dev, sizeof w, hipMemcpyDeviceToHost));
+        ctx->acc.blend_evaluations = (int64_t)w;
+    }
+    *out = ctx->acc;
     return FGS_OK;
 }
 

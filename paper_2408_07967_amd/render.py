@@ -89,6 +89,14 @@ class Renderer:
                     stats=dict(visible=st.visible, pairs=st.pairs, tiles_x=st.tiles_x, tiles_y=st.tiles_y,
                                sort_passes=st.sort_passes))
 
+    def set_instrumentation(self, flags):
+        self.ctx.check(B.lib().fgs_set_instrumentation(self.ctx.handle, int(flags)))
+
+    def instrumentation(self):
+        t = B.FgsTimings()
+        self.ctx.check(B.lib().fgs_get_instrumentation(self.ctx.handle, C.byref(t)))
+        return {k: getattr(t, k) for k, _ in B.FgsTimings._fields_}
+
     def frame_field(self, frame, field):
         n = int(B.lib().fgs_frame_field_bytes(frame, field))
         buf = np.zeros(max(n, 4) // 4, np.uint32)

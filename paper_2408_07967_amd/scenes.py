@@ -27,8 +27,10 @@ aerial 4K case):
   serve   - 6,000,000 Gaussians with the city distributions; request poses on
             a 200 m orbit at 50-150 m altitude.
 """
-from dataclasses import dataclass, field
+from concurrent.futures import ThreadPoolExecutor
+from dataclasses import dataclass
 import math
+import os
 
 import numpy as np
 
@@ -75,61 +77,73 @@ class Camera:
     H: int = 0
 
 
-def _normal(rng, mu, sigma, n):
-    return (rng.standard_normal(n, dtype=np.float32) * np.float32(sigma) + np.float32(mu)).astype(np.float32)
+def _plane_rngs(seed, n):
+    """Independent PCG64 streams, one per plane (SeedSequence.spawn), so that
+    planes can be drawn in parallel threads with a fixed result."""
+    return [np.random.Generator(np.random.PCG64(c)) for c in np.random.SeedSequence(seed).spawn(n)]
 
 
-def _unit_quats(rng, n):
-    q = np.empty((4, n), np.float32)
-    for c in range(4):
-        q[c] = rng.standard_normal(n, dtype=np.float32)
-    nrm = np.sqrt((q.astype(np.float64) ** 2).sum(0))
-    nrm[nrm == 0] = 1.0
-    return (q / nrm).astype(np.float32)
+def _draw(jobs, P):
+    """jobs: list of (rng, kind, a, b); kind in normal/uniform/exponential.
+    Returns a [len(jobs), P] float32 array."""
+    out = np.empty((len(jobs), P), np.float32)
 
+    def one(i):
+        rng, kind, a, b = jobs[i]
+        if kind == "normal":
+            x = rng.standard_normal(P, dtype=np.float32)
+            x *= np.float32(b)
+            x += np.float32(a)
+        elif kind == "uniform":
+            x = rng.random(P, dtype=np.float32)
+            x *= np.float32(b - a)
+            x += np.float32(a)
+        else:  # exponential with mean a
+            x = rng.standard_exponential(P, dtype=np.float32)
+            x *= np.float32(a)
+        out[i] = x
 
-def _sh(rng, degree, n, dc_sigma=0.5, rest_sigma=0.1):
-    nk = (degree + 1) ** 2
-    sh = np.empty((3 * nk, n), np.float32)
-    for p in range(3 * nk):
-        sh[p] = _normal(rng, 0.0, dc_sigma if p < 3 else rest_sigma, n)
-    return sh
+    workers = min(16, os.cpu_count() or 1, len(jobs))
+    if P * len(jobs) < 2_000_000 or workers <= 1:
+        for i in range(len(jobs)):
+            one(i)
+    else:
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            list(ex.map(one, range(len(jobs))))
+    return out
 
 
 def make_scene(kind, seed=None, P=None):
-    """Draw a scene.  Draw order: means, log-scales, quaternions, logits,
-    SH DC, SH rest; every draw float32 from numpy's PCG64 default_rng."""
+    """Draw a scene.  Each plane has its own PCG64 stream spawned from the
+    seed, in the order: means (3), log-scales (3), quaternion components (4,
+    N(0, 1) then normalised), opacity logits (1), SH DC (3), SH rest."""
     if kind == "small":
-        seed = 1 if seed is None else seed
-        P = 10_000 if P is None else P
-        rng = np.random.default_rng(seed)
-        means = np.stack([rng.uniform(-1, 1, P).astype(np.float32) for _ in range(3)])
-        ls = np.stack([_normal(rng, -3.5, 0.5, P) for _ in range(3)])
-        degree = 0
+        seed, P, degree = (1 if seed is None else seed), (10_000 if P is None else P), 0
+        mean_jobs = [("uniform", -1.0, 1.0)] * 3
+        ls_mu, ls_sigma = -3.5, 0.5
     elif kind == "medium":
-        seed = 2 if seed is None else seed
-        P = 1_000_000 if P is None else P
-        rng = np.random.default_rng(seed)
-        means = np.stack([rng.uniform(-5, 5, P).astype(np.float32) for _ in range(3)])
-        ls = np.stack([_normal(rng, -3.5, 0.5, P) for _ in range(3)])
-        degree = 3
+        seed, P, degree = (2 if seed is None else seed), (1_000_000 if P is None else P), 3
+        mean_jobs = [("uniform", -5.0, 5.0)] * 3
+        ls_mu, ls_sigma = -3.5, 0.5
     elif kind in ("city", "serve"):
         seed = (3 if kind == "city" else 5) if seed is None else seed
         P = (10_000_000 if kind == "city" else 6_000_000) if P is None else P
-        rng = np.random.default_rng(seed)
-        x = rng.uniform(-500, 500, P).astype(np.float32)
-        y = (rng.standard_exponential(P, dtype=np.float32) * np.float32(15.0)).astype(np.float32)
-        z = rng.uniform(-500, 500, P).astype(np.float32)
-        means = np.stack([x, y, z])
-        ls = np.stack([_normal(rng, -1.0, 1.2, P) for _ in range(3)])
         degree = 3
+        mean_jobs = [("uniform", -500.0, 500.0), ("exponential", 15.0, 0.0), ("uniform", -500.0, 500.0)]
+        ls_mu, ls_sigma = -1.0, 1.2
     else:
         raise ValueError(f"unknown scene kind {kind!r}")
-    quats = _unit_quats(rng, P)
-    logits = _normal(rng, 0.0, 1.5, P)[None, :]
-    sh = _sh(rng, degree, P)
-    return Scene(np.ascontiguousarray(means), np.ascontiguousarray(ls), quats,
-                 np.ascontiguousarray(logits), sh, degree)
+    nk = (degree + 1) ** 2
+    specs = (mean_jobs + [("normal", ls_mu, ls_sigma)] * 3 + [("normal", 0.0, 1.0)] * 4 +
+             [("normal", 0.0, 1.5)] + [("normal", 0.0, 0.5)] * 3 + [("normal", 0.0, 0.1)] * (3 * nk - 3))
+    rngs = _plane_rngs(seed, len(specs))
+    planes = _draw([(r, *sp) for r, sp in zip(rngs, specs)], P)
+    means, ls, q, logits, sh = planes[0:3], planes[3:6], planes[6:10], planes[10:11], planes[11:]
+    nrm = np.sqrt((q.astype(np.float64) ** 2).sum(0))
+    nrm[nrm == 0] = 1.0
+    quats = (q / nrm).astype(np.float32)
+    return Scene(np.ascontiguousarray(means), np.ascontiguousarray(ls), quats, np.ascontiguousarray(logits),
+                 np.ascontiguousarray(sh), degree)
 
 
 def look_at(eye, target, W, H, fov_deg, up=(0.0, 1.0, 0.0), near=0.2):
@@ -176,8 +190,7 @@ def serve_pose(rng):
 
 def perturb_means(scene, seed=4, sigma=0.01):
     """Target scene for the differentiation workload: means + N(0, sigma)."""
-    rng = np.random.default_rng(seed)
-    m = scene.means + np.stack([_normal(rng, 0.0, sigma, scene.P) for _ in range(3)])
+    m = scene.means + _draw([(r, "normal", 0.0, sigma) for r in _plane_rngs(seed, 3)], scene.P)
     return Scene(m.astype(np.float32), scene.log_scales, scene.quats, scene.logits, scene.sh, scene.sh_degree)
 
 

@@ -123,3 +123,32 @@ def test_deterministic_repeat(orc, R, scenes):
     b = gpu_frame(R, gsc, cam, 1920, 1080, opts())
     for k in ("rgb", "T", "last", "order", "tiles", "values", "ranges"):
         assert np.array_equal(a[k], b[k]), k
+
+
+def test_large_rectangles_chunked(orc, R):
+    """Gaussians whose rectangles span hundreds of tiles (chunked tile test
+    and emission across workgroups)."""
+    rng = np.random.default_rng(31)
+    P = 400
+    means = np.c_[rng.uniform(-2, 2, P), rng.uniform(-1.2, 1.2, P), rng.uniform(3, 12, P)]
+    ls = rng.normal(-1.2, 0.6, (P, 3))
+    sc = scene_from(means, ls, rng.normal(size=(P, 4)), rng.normal(-1, 1.5, P), sh=rng.normal(0, 0.3, (12, P)),
+                    sh_degree=1)
+    cam = identity_camera(1024, 768, 700.0)
+    g, o32, _ = _full_check(orc, R, sc, cam, 1024, 768, opts(), "chunked")
+    nt = (o32["ints"][:, orc.I_TX1] - o32["ints"][:, orc.I_TX0] + 1) * (o32["ints"][:, orc.I_TY1] - o32["ints"][:, orc.I_TY0] + 1)
+    assert (nt[o32["ints"][:, 0] == 1] > 256).sum() > 20
+
+
+def test_chunk_list_overflow_falls_back(orc, R):
+    """More chunk entries than the list holds (600 screen-filling Gaussians at
+    4K need about 76,000): the overflow Gaussians are counted in-wave and the
+    result is unchanged."""
+    rng = np.random.default_rng(32)
+    P = 600
+    means = np.c_[rng.uniform(-0.3, 0.3, P), rng.uniform(-0.2, 0.2, P), rng.uniform(5, 9, P)]
+    sc = scene_from(means, np.full((P, 3), 1.2), rng.normal(size=(P, 4)), rng.normal(0, 1, P),
+                    dc_rgb=rng.uniform(0, 1, (P, 3)))
+    cam = identity_camera(3840, 2160, 1500.0)
+    g, o32, _ = _full_check(orc, R, sc, cam, 3840, 2160, opts(), "overflow")
+    assert o32["npairs"] > 65536 * 256
