@@ -14,7 +14,6 @@ constexpr int kSortTile = kBlock * kSortItems;  // keys per sort workgroup
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr uint32_t kInvalidKey = 0xffffffffu;
-constexpr int kMaxPasses = 8;      // 4 depth passes + up to 3 tile passes (+1 spare)
 
 // Camera and options passed by value: they land in the kernel-argument
 // segment and are read through scalar registers (the paper's constant-memory
@@ -42,20 +41,13 @@ struct alignas(16) GaussState {
     float4 f0, f1, f2;
 };
 
-// Frame-scoped device counters and histograms, cleared at the start of a frame.
+// Frame-scoped device counters, cleared at the start of a frame.
 struct FrameCounters {
-    uint32_t visible;                    // Gaussians that passed preprocessing
-    uint32_t pairs;                      // total pairs (written by the scan)
-    uint32_t error;                      // non-zero: a bounded wait gave up
-    uint32_t nchunks;                    // entries appended to the large-Gaussian chunk list
-    uint32_t block_ctr[kMaxPasses + 2];  // dynamic workgroup ids per pass / scan
-    uint32_t hist[kMaxPasses][kRadix];   // digit histograms per pass
-    unsigned long long work;             // blend evaluations (instrumented runs)
+    uint32_t visible;  // Gaussians that passed preprocessing
+    uint32_t pairs;    // total pairs (written by the count scan)
+    uint32_t error;    // error bits (kErrChunkOverflow)
+    uint32_t nchunks;  // entries requested in the large-Gaussian chunk list
 };
-
-// Lookback status word: high 32 bits = (epoch << 2) | flag, low 32 = value.
-constexpr uint32_t kFlagAggregate = 1u;
-constexpr uint32_t kFlagInclusive = 2u;
 
 // ---- launchers (implemented in the .hip files) ----------------------------
 
@@ -68,62 +60,60 @@ constexpr int kChunkTiles = kBlock;
 constexpr uint32_t kNoChunk = 0xffffffffu;
 constexpr int kPersistentBlocks = 2048;
 constexpr int kBigList = 512;                    // pending chunk reservations per workgroup
-constexpr int kTileHistBins = 3 * kRadix;        // histogram row of the (up to 3) tile passes
-constexpr int kDepthHistBins = 4 * kRadix;       // histogram row of the 4 depth passes
 // FrameCounters::error bits
-constexpr uint32_t kErrLookback = 1u;            // a bounded look-back wait gave up
 constexpr uint32_t kErrChunkOverflow = 2u;       // chunk list too small: render again
 
-// Per-workgroup histogram rows: preprocess writes grid rows of kDepthHistBins,
-// emission writes rows of kTileHistBins; k_hist_reduce sums them into
-// FrameCounters::hist.
-void launch_hist_reduce(const uint32_t *rows, uint32_t nrows, int nbins, uint32_t *out, hipStream_t s);
+// Radix sort / scan passes use a fixed grid of kSortBlocks workgroups,
+// grouped by kSortGroup for the offset computation.
+constexpr int kSortBlocks = 1024;
+constexpr int kSortGroup = 32;
+
 unsigned preprocess_grid(int64_t P);
 unsigned emit_grid(uint32_t visible);
 
 // Preprocess: per-Gaussian state, tile rectangle, exact tile count, hit mask,
-// depth key (kInvalidKey for culled Gaussians), depth-digit histograms and
-// the visible count.  Large rectangles append chunk entries (g, first chunk)
-// to `chunks` (capacity chunk_cap; on overflow the Gaussian is counted in
-// its own wavefront instead) and get count 0, mask = (0, first chunk).
+// depth key (kInvalidKey for culled Gaussians) and the visible count.  Large
+// rectangles append chunk entries (g, first chunk) to `chunks` (capacity
+// chunk_cap; on overflow the error bit kErrChunkOverflow is set and the host
+// renders the frame again with a larger list) and get count 0,
+// mask = (0, first chunk).
 void launch_preprocess(const DevScene &sc, const DevCamera &cam, const DevOptions &op, int W, int H,
                        GaussState *gs, uint4 *rect, uint32_t *count, uint2 *mask, uint32_t *dkey, uint2 *chunks,
-                       uint32_t chunk_cap, uint32_t *block_hist, FrameCounters *fc, hipStream_t s);
+                       uint32_t chunk_cap, FrameCounters *fc, hipStream_t s);
 
-// Exact tile counts of the chunked Gaussians: per-chunk hits and atomic
-// per-Gaussian sums.
+// Exact tile counts of the chunked Gaussians: per-chunk hit masks and counts,
+// atomic per-Gaussian sums.
 void launch_big_count(int W, int H, int binning, const GaussState *gs, const uint4 *rect, const uint2 *chunks,
-                      uint32_t chunk_cap, uint32_t *chunk_hits, uint32_t *count, const FrameCounters *fc,
-                      hipStream_t s);
+                      uint32_t chunk_cap, uint32_t *chunk_hits, uint32_t *chunk_mask, uint32_t *count,
+                      const FrameCounters *fc, hipStream_t s);
 
 // Emit (tile, gaussian) pairs for Gaussians in depth order.  Chunked
 // Gaussians only record their output base in mask[g].x.
-void launch_emit(const DevScene &sc, int W, int H, int binning, const uint32_t *order, uint32_t visible,
-                 const uint32_t *offsets, const GaussState *gs, const uint4 *rect, const uint32_t *count,
-                 uint2 *mask, uint32_t *tile_keys, uint32_t *values, uint32_t cap, uint32_t *block_hist,
-                 int npasses, const int *shifts, const int *bits, hipStream_t s);
+void launch_emit(int W, int H, const uint32_t *order, uint32_t visible, const uint32_t *offsets,
+                 const uint4 *rect, const uint32_t *count, uint2 *mask, uint32_t *tile_keys, uint32_t *values,
+                 uint32_t cap, hipStream_t s);
 
-// Emit the pairs of the chunked Gaussians (after launch_emit); histogram rows
-// go after the emit kernel's rows (row0 = emit_grid(visible)).
-void launch_big_emit(int W, int H, int binning, const GaussState *gs, const uint4 *rect, const uint2 *mask,
-                     const uint2 *chunks, uint32_t chunk_cap, const uint32_t *chunk_hits, uint32_t *tile_keys,
-                     uint32_t *values, uint32_t cap, const FrameCounters *fc, uint32_t *block_hist, uint32_t row0,
-                     int npasses, const int *shifts, const int *bits, hipStream_t s);
+// Emit the pairs of the chunked Gaussians (after launch_emit).
+void launch_big_emit(int W, const uint4 *rect, const uint2 *mask, const uint2 *chunks, uint32_t chunk_cap,
+                     const uint32_t *chunk_hits, const uint32_t *chunk_mask, uint32_t *tile_keys, uint32_t *values,
+                     uint32_t cap, const FrameCounters *fc, hipStream_t s);
 
-// One onesweep pass: stable scatter of (key, value) by digit
-// (key >> shift) & ((1 << bits) - 1).
-//   n_host  upper bound on the number of keys (sizes the grid)
-//   n_dev   if non-null, the actual count is read here on the device
-//   vals_in null: values are the input positions (identity)
+// One stable LSD radix pass of (key, value) pairs by the digit
+// (key >> shift) & ((1 << bits) - 1), bits <= 8.
+//   n_host  upper bound on the number of keys; n_dev: if non-null, the
+//           actual count is read there on the device
+//   vals_in null: values are the input positions
 //   filter  drop keys equal to kInvalidKey
-void launch_onesweep(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_out, uint32_t *vals_out,
-                     uint32_t n_host, const uint32_t *n_dev, int shift, int bits, int pass, bool filter,
-                     bool write_keys, FrameCounters *fc, uint64_t *status, uint32_t epoch, hipStream_t s);
+//   hist    scratch [kSortBlocks][kRadix]; gsum scratch [kSortBlocks/kSortGroup][kRadix]
+void launch_radix_pass(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_out, uint32_t *vals_out,
+                       uint32_t n_host, const uint32_t *n_dev, int shift, int bits, bool filter, bool write_keys,
+                       uint32_t *hist, uint32_t *gsum, hipStream_t s);
 
-// Gather counts in depth order and exclusive-scan them into offsets;
-// writes the total into fc->pairs.
-void launch_count_scan(const uint32_t *order, const uint32_t *count, uint32_t n_host, uint32_t *offsets,
-                       FrameCounters *fc, uint64_t *status, uint32_t epoch, hipStream_t s);
+// offsets[r] = sum of count[order[r']] for r' < r over the n visible
+// Gaussians (n_dev, bounded by n_host); offsets[n] and *pairs get the total.
+// cs: scratch [n_host]; sums: scratch [kSortBlocks].
+void launch_count_scan(const uint32_t *order, const uint32_t *count, uint32_t n_host, const uint32_t *n_dev,
+                       uint32_t *cs, uint32_t *sums, uint32_t *offsets, uint32_t *pairs, hipStream_t s);
 
 void launch_tile_ranges(const uint32_t *tile_keys, uint32_t n, uint2 *ranges, uint32_t ntiles, hipStream_t s);
 

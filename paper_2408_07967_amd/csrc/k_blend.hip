@@ -51,16 +51,19 @@ __device__ __forceinline__ bool rect_hit(float u, float v, float A, float B, flo
     return hit;
 }
 
-template <bool kCountWork>
+template <bool kCountWork, bool kLast>
 __global__ __launch_bounds__(kBlock) void k_blend(const GaussState *__restrict__ gs,
                                                   const uint32_t *__restrict__ values,
                                                   const uint2 *__restrict__ ranges, int W, int H, int tiles_x,
                                                   DevOptions op, float *__restrict__ rgb, float *__restrict__ Tout,
                                                   uint32_t *__restrict__ last_out, unsigned long long *work) {
-    __shared__ float4 s_f0[kBlock], s_f1[kBlock], s_f2[kBlock];
-    __shared__ uint32_t s_qmask[kBlock];
+    __shared__ float4 s_f0[kBlock], s_f1[kBlock];
+    __shared__ float2 s_f2[kBlock];
+    // s_rel[q][w]: bit i set iff entry 64 w + i of the batch meets quadrant q
+    __shared__ uint32_t s_rel[4][kBlock / kWave][2];
 
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);  // wave-uniform
     const int tile = blockIdx.x;
     const int tx = tile % tiles_x, ty = tile / tiles_x;
     const int qx = wave & 1, qy = wave >> 1;
@@ -70,21 +73,24 @@ __global__ __launch_bounds__(kBlock) void k_blend(const GaussState *__restrict__
     float px = in_img ? (float)pi + 0.5f : kFar;
     const float py = (float)pj + 0.5f;
 
-    // quadrant hulls of this tile (pixel samples, clipped to the image) for the staging test
     const uint2 rg = ranges[tile];
     const uint32_t start = rg.x, end = rg.y;
     float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
     uint32_t last = 0;
     bool done = !in_img;
+    bool wave_done = __ballot(!done) == 0;
     uint32_t examined = in_img ? (end - start) : 0u;  // entries this pixel must look at
-    const float nl2e = -0.72134752044448170f;  // -log2(e) / 2
-    const float amax = op.alpha_max, tstop = op.T_stop;
+    const float nl2e = -0.72134752044448170f;          // -log2(e) / 2
+    // loop-invariant clamp as the result of an arithmetic op (a canonical
+    // value, so the minimum needs no per-iteration canonicalisation)
+    const float amax = op.alpha_max + 0.0f;
+    const float tstop = op.T_stop;
 
     for (uint32_t b0 = start; b0 < end; b0 += kBlock) {
         const uint32_t nb = (end - b0) < (uint32_t)kBlock ? (end - b0) : (uint32_t)kBlock;
+        uint32_t qm = 0;
         if ((uint32_t)tid < nb) {
             const GaussState s = gs[values[b0 + tid]];
-            uint32_t qm = 0;
             const float k2i = s.f1.y * 1.00002f + 1e-5f;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -97,47 +103,57 @@ __global__ __launch_bounds__(kBlock) void k_blend(const GaussState *__restrict__
                              (float)Y0i + 0.5f, (float)Y1i - 0.5f))
                     qm |= 1u << q;
             }
-            // store 2B in place of B for the pixel loop
+            // 2B in place of B for the pixel loop
             s_f0[tid] = make_float4(s.f0.x, s.f0.y, s.f0.z, 2.0f * s.f0.w);
             s_f1[tid] = s.f1;
-            s_f2[tid] = s.f2;
-            s_qmask[tid] = qm;
+            s_f2[tid] = make_float2(s.f2.x, s.f2.y);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint64_t bq = __ballot((qm >> q) & 1u);
+            if (lane == 0) {
+                s_rel[q][wave][0] = (uint32_t)bq;
+                s_rel[q][wave][1] = (uint32_t)(bq >> 32);
+            }
         }
         __syncthreads();
-        if (__ballot(!done) != 0) {
-            for (uint32_t j = 0; j < nb; ++j) {
-                const uint32_t qm = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_qmask[j]);
-                if (!((qm >> wave) & 1u)) continue;
-                const float4 f0 = s_f0[j], f1 = s_f1[j];
-                const float2 f2 = make_float2(s_f2[j].x, s_f2[j].y);
-                const float dx = px - f0.x, dy = py - f0.y;
-                const float t = fmaf(f0.z, dx, f0.w * dy);
-                const float q = fmaf(f1.x * dy, dy, dx * t);
-                bool inq = q <= f1.y;
-                float a = fminf(amax, __builtin_amdgcn_exp2f(fmaf(q, nl2e, f1.z)));
-                a = inq ? a : 0.0f;
-                float Tn = fmaf(-a, T, T);
-                const bool stop = Tn < tstop;
-                bool all_done = false;
-                if (__ballot(stop) != 0) {
-                    // rare path: lanes that saturate stop before this Gaussian
-                    if (stop) {
-                        a = 0.0f;
-                        Tn = T;
-                        inq = false;
-                        px = kFar;
-                        done = true;
-                        if (kCountWork) examined = b0 - start + j + 1;
+        if (!wave_done) {
+            for (int wd = 0; wd < kBlock / kWave && !wave_done; ++wd) {
+                uint64_t m = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)s_rel[wave][wd][0]) |
+                             ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)s_rel[wave][wd][1]) << 32);
+                while (m) {
+                    const int j = wd * kWave + __builtin_ctzll(m);
+                    m &= m - 1;
+                    const float4 f0 = s_f0[j], f1 = s_f1[j];
+                    const float2 f2 = s_f2[j];
+                    const float dx = px - f0.x, dy = py - f0.y;
+                    const float t = fmaf(f0.z, dx, f0.w * dy);
+                    const float q = fmaf(f1.x * dy, dy, dx * t);
+                    bool inq = q <= f1.y;
+                    const float e = __builtin_amdgcn_exp2f(fmaf(q, nl2e, f1.z));
+                    float a = inq ? fminf(e, amax) : 0.0f;
+                    float Tn = fmaf(-a, T, T);
+                    const bool stop = Tn < tstop;
+                    if (__ballot(stop) != 0) {
+                        // rare path: lanes that saturate stop before this Gaussian
+                        if (stop) {
+                            a = 0.0f;
+                            Tn = T;
+                            inq = false;
+                            px = kFar;
+                            done = true;
+                            if (kCountWork) examined = b0 - start + (uint32_t)j + 1u;
+                        }
+                        wave_done = __ballot(!done) == 0;
                     }
-                    all_done = __ballot(!done) == 0;
+                    const float wgt = a * T;
+                    c0 = fmaf(wgt, f1.w, c0);
+                    c1 = fmaf(wgt, f2.x, c1);
+                    c2 = fmaf(wgt, f2.y, c2);
+                    T = Tn;
+                    if (kLast) last = inq ? (b0 - start + (uint32_t)j + 1u) : last;
+                    if (wave_done) break;
                 }
-                const float wgt = a * T;
-                c0 = fmaf(wgt, f1.w, c0);
-                c1 = fmaf(wgt, f2.x, c1);
-                c2 = fmaf(wgt, f2.y, c2);
-                T = Tn;
-                last = inq ? (b0 - start + j + 1) : last;
-                if (all_done) break;
             }
         }
         // all 256 pixels finished: stop walking the list (also the barrier
@@ -160,7 +176,7 @@ __global__ __launch_bounds__(kBlock) void k_blend(const GaussState *__restrict__
         rgb[hw + p] = c1 + T * op.bg[1];
         rgb[2 * hw + p] = c2 + T * op.bg[2];
         if (Tout) Tout[p] = T;
-        if (last_out) last_out[p] = last;
+        if (kLast && last_out) last_out[p] = last;
     }
 }
 
@@ -170,12 +186,16 @@ void launch_blend(const GaussState *gs, const uint32_t *values, const uint2 *ran
                   const DevOptions &op, float *rgb, float *T, uint32_t *last, unsigned long long *work,
                   hipStream_t s) {
     const int tiles_x = (W + kTile - 1) / kTile, tiles_y = (H + kTile - 1) / kTile;
+    const dim3 grid((unsigned)(tiles_x * tiles_y)), block(kBlock);
     if (work)
-        hipLaunchKernelGGL(k_blend<true>, dim3((unsigned)(tiles_x * tiles_y)), dim3(kBlock), 0, s, gs, values,
-                           ranges, W, H, tiles_x, op, rgb, T, last, work);
+        hipLaunchKernelGGL((k_blend<true, true>), grid, block, 0, s, gs, values, ranges, W, H, tiles_x, op, rgb, T,
+                           last, work);
+    else if (last)
+        hipLaunchKernelGGL((k_blend<false, true>), grid, block, 0, s, gs, values, ranges, W, H, tiles_x, op, rgb, T,
+                           last, work);
     else
-        hipLaunchKernelGGL(k_blend<false>, dim3((unsigned)(tiles_x * tiles_y)), dim3(kBlock), 0, s, gs, values,
-                           ranges, W, H, tiles_x, op, rgb, T, last, work);
+        hipLaunchKernelGGL((k_blend<false, false>), grid, block, 0, s, gs, values, ranges, W, H, tiles_x, op, rgb,
+                           T, last, work);
 }
 
 }  // namespace fgs

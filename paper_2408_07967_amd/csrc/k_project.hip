@@ -138,6 +138,32 @@ __device__ __forceinline__ bool tile_hit(float u, float v, float A, float B, flo
     return hit;
 }
 
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, int lane) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)x, d, kWave);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+// Largest lane L with s[L] <= item, for s non-decreasing over 64 lanes with
+// s[0] = 0: the owner of flattened item `item` (lanes with no items are
+// skipped because the next lane has the same start).
+__device__ __forceinline__ int owner_lane(const uint32_t *s, uint32_t item) {
+    int lo = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1)
+        if (s[lo + step] <= item) lo += step;
+    return lo;
+}
+
+// k / n for 0 <= k < 64 and 1 <= n <= 64: (k + 1/2) / n is at least 1/128
+// away from an integer, far more than the reciprocal's error.
+__device__ __forceinline__ int small_div(uint32_t k, int n) {
+    return (int)(((float)k + 0.5f) * __builtin_amdgcn_rcpf((float)n));
+}
+
 // Real orthonormal SH basis with the Condon-Shortley phase, k = l^2 + l + m.
 __device__ __forceinline__ void sh_basis(float x, float y, float z, int D, float *Y) {
     const float c0 = 0.28209479177387814f;   // 1 / (2 sqrt(pi))
@@ -176,15 +202,13 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevCamera ca
                                                        GaussState *__restrict__ gs, uint4 *__restrict__ rect,
                                                        uint32_t *__restrict__ count, uint2 *__restrict__ mask,
                                                        uint32_t *__restrict__ dkey, uint2 *__restrict__ chunks,
-                                                       uint32_t chunk_cap, uint32_t *__restrict__ block_hist,
-                                                       FrameCounters *fc) {
+                                                       uint32_t chunk_cap, FrameCounters *fc) {
     // Persistent grid: each workgroup walks batches of 256 Gaussians and keeps
     // its depth-digit histogram, visible count and pending chunk reservations
     // in LDS, so global atomics are per workgroup, not per batch.
-    __shared__ uint32_t s_hist[4 * kRadix];
     __shared__ uint32_t s_bg[kBigList], s_boff[kBigList], s_bn[kBigList];
+    __shared__ uint32_t s_excl[kBlock / kWave][kWave], s_mlo[kBlock / kWave][kWave], s_mhi[kBlock / kWave][kWave];
     __shared__ uint32_t s_vis, s_nbig, s_nch, s_base;
-    for (int i = threadIdx.x; i < 4 * kRadix; i += kBlock) s_hist[i] = 0;
     if (threadIdx.x == 0) {
         s_vis = 0;
         s_nbig = 0;
@@ -362,48 +386,39 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevCamera ca
         s_bn[slot] = nch;
         s_boff[slot] = atomicAdd(&s_nch, nch);
     }
+    const bool small = valid && !chunked;  // rectangle of at most kBigTiles tiles
     if (op.binning == 1) {
-        if (!chunked) {
+        if (small) {
             cnt = (uint32_t)nt;
             hm = nt >= 64 ? ~0ull : ((1ull << nt) - 1ull);
-            if (nt > 64) hm = 0;
         }
     } else {
-        if (valid && nt <= kSmallCount) {
-            int bit = 0;
-            for (int ty = ty0; ty <= ty1; ++ty)
-                for (int tx = tx0; tx <= tx1; ++tx, ++bit)
-                    if (tile_hit(u, v, A, B, C, k2, tx, ty, W, H)) hm |= 1ull << bit;
-            cnt = (uint32_t)__popcll(hm);
-        }
-        // larger rectangles: the whole wavefront tests 64 tiles per step
-        // (Sec. 5.1.2 adaptive size-aware scheduling, with wave64)
-        uint64_t pending = __ballot(valid && nt > kSmallCount && !chunked);
-        while (pending) {
-            const int src = __ffsll((unsigned long long)pending) - 1;
-            pending &= pending - 1;
-            const float su = bcast(u, src), sv = bcast(v, src), sA = bcast(A, src), sB = bcast(B, src),
-                        sC = bcast(C, src), sk2 = bcast(k2, src);
-            const int stx0 = bcast(tx0, src), sty0 = bcast(ty0, src), sntx = bcast(ntx, src), snt = bcast(nt, src);
-            uint32_t tot = 0;
-            uint64_t first = 0;
-            for (int c0 = 0; c0 < snt; c0 += kWave) {
-                const int idx = c0 + lane;
-                bool h = false;
-                if (idx < snt) {
-                    const int ry = idx / sntx;
-                    const int rx = idx - ry * sntx;
-                    h = tile_hit(su, sv, sA, sB, sC, sk2, stx0 + rx, sty0 + ry, W, H);
-                }
-                const uint64_t b = __ballot(h);
-                tot += (uint32_t)__popcll(b);
-                if (c0 == 0) first = b;
-            }
-            if (lane == src) {
-                cnt = tot;
-                hm = snt <= kWave ? first : 0ull;
+        // The wavefront flattens its (Gaussian, rectangle tile) items so that
+        // every lane tests one tile per step whatever the mix of rectangle
+        // sizes (Sec. 5.1.2 size-aware scheduling, balanced across wave64).
+        const int wave = threadIdx.x / kWave;
+        uint32_t *sx = s_excl[wave];
+        const uint32_t items = small ? (uint32_t)nt : 0u;
+        const uint32_t incl = wave_incl_scan(items, lane);
+        const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+        sx[lane] = incl - items;
+        s_mlo[wave][lane] = 0u;
+        s_mhi[wave][lane] = 0u;
+        for (uint32_t b0 = 0; b0 < total; b0 += kWave) {
+            const uint32_t item = b0 + (uint32_t)lane;
+            const int L = owner_lane(sx, item < total ? item : total - 1u);
+            const uint32_t k = item - sx[L];
+            const float su = __shfl(u, L, kWave), sv = __shfl(v, L, kWave), sA = __shfl(A, L, kWave),
+                        sB = __shfl(B, L, kWave), sC = __shfl(C, L, kWave), sk2 = __shfl(k2, L, kWave);
+            const int stx0 = __shfl(tx0, L, kWave), sty0 = __shfl(ty0, L, kWave), sntx = __shfl(ntx, L, kWave);
+            if (item < total) {
+                const int ry = small_div(k, sntx), rx = (int)k - ry * sntx;
+                if (tile_hit(su, sv, sA, sB, sC, sk2, stx0 + rx, sty0 + ry, W, H))
+                    atomicOr(k < 32u ? &s_mlo[wave][L] : &s_mhi[wave][L], 1u << (k & 31u));
             }
         }
+        hm = (uint64_t)s_mlo[wave][lane] | ((uint64_t)s_mhi[wave][lane] << 32);
+        cnt = (uint32_t)__popcll(hm);
     }
 
     if (g < sc.P) {
@@ -418,10 +433,6 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevCamera ca
             gs[g] = s;
             rect[g] = make_uint4((uint32_t)tx0, (uint32_t)tx1, (uint32_t)ty0, (uint32_t)ty1);
             if (!chunked) mask[g] = make_uint2((uint32_t)hm, (uint32_t)(hm >> 32));
-            atomicAdd(&s_hist[0 * kRadix + (key & 0xff)], 1u);
-            atomicAdd(&s_hist[1 * kRadix + ((key >> 8) & 0xff)], 1u);
-            atomicAdd(&s_hist[2 * kRadix + ((key >> 16) & 0xff)], 1u);
-            atomicAdd(&s_hist[3 * kRadix + (key >> 24)], 1u);
         }
     }
     const uint64_t vb = __ballot(valid);
@@ -430,31 +441,20 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevCamera ca
     if (s_nbig > kBigList - kBlock) flush_big();
     }  // batch loop
     if (s_nbig) flush_big();
-    // this workgroup's histogram row; rows are summed by k_hist_reduce
-    for (int i = threadIdx.x; i < 4 * kRadix; i += kBlock) block_hist[(size_t)blockIdx.x * 4 * kRadix + i] = s_hist[i];
     if (threadIdx.x == 0 && s_vis) atomicAdd(&fc->visible, s_vis);
 }
-
-struct PassDigits {
-    int first_pass, npasses;
-    int shift[3], bits[3];
-};
 
 // Key emission: one lane per Gaussian in (depth, index) order writes its
 // (tile, index) pairs at its scanned offset (Alg. 2 with the offsets of a
 // prefix scan; the tile test is reused from the preprocess through the hit
-// mask, or re-run for rectangles of more than 64 tiles).  Also accumulates the
-// digit histograms of the tile-sort passes.
-__global__ __launch_bounds__(kBlock) void k_emit(int W, int H, int binning, const uint32_t *__restrict__ order,
+// mask).  Chunked Gaussians only record their output base here.
+__global__ __launch_bounds__(kBlock) void k_emit(int W, int H, const uint32_t *__restrict__ order,
                                                  uint32_t visible, const uint32_t *__restrict__ offsets,
-                                                 const GaussState *__restrict__ gs, const uint4 *__restrict__ rect,
+                                                 const uint4 *__restrict__ rect,
                                                  const uint32_t *__restrict__ count, uint2 *__restrict__ mask,
                                                  uint32_t *__restrict__ tile_keys, uint32_t *__restrict__ values,
-                                                 uint32_t cap, uint32_t *__restrict__ block_hist, uint32_t row0,
-                                                 PassDigits pd) {
-    __shared__ uint32_t s_hist[kTileHistBins];
-    for (int i = threadIdx.x; i < kTileHistBins; i += kBlock) s_hist[i] = 0;
-    __syncthreads();
+                                                 uint32_t cap) {
+    __shared__ uint32_t s_excl[kBlock / kWave][kWave];
     const int tiles_x = (W + kTile - 1) / kTile;
     const int lane = threadIdx.x & (kWave - 1);
     for (uint32_t r0 = blockIdx.x * kBlock; r0 < visible; r0 += gridDim.x * kBlock) {
@@ -477,78 +477,35 @@ __global__ __launch_bounds__(kBlock) void k_emit(int W, int H, int binning, cons
     const bool chunked = act && nt > kBigTiles && (uint32_t)(m >> 32) != kNoChunk;
     if (chunked) mask[g].x = base;
 
-    auto record = [&](uint32_t tile) {
-        for (int p = 0; p < pd.npasses; ++p)
-            atomicAdd(&s_hist[p * kRadix + ((tile >> pd.shift[p]) & ((1u << pd.bits[p]) - 1u))], 1u);
-    };
 
-    const bool small = act && c > 0 && c <= kSmallEmit && nt <= kWave;
-    if (small) {
-        uint64_t mm = m;
-        uint32_t k = 0;
-        while (mm) {
-            const int b = __ffsll((unsigned long long)mm) - 1;
-            mm &= mm - 1;
-            const int ry = b / ntx, rx = b - ry * ntx;
-            const uint32_t tile = (uint32_t)(((int)rc.z + ry) * tiles_x + ((int)rc.x + rx));
-            if (base + k < cap) {  // never leave the pair buffers
-                tile_keys[base + k] = tile;
-                values[base + k] = g;
-            }
-            ++k;
-            record(tile);
-        }
-    }
-    const uint64_t lt = (1ull << lane) - 1ull;
-    uint64_t pending = __ballot(act && c > 0 && !small && !chunked);
-    while (pending) {
-        const int src = __ffsll((unsigned long long)pending) - 1;
-        pending &= pending - 1;
-        const uint32_t sg = bcast(g, src), sbase = bcast(base, src);
-        const int stx0 = bcast((int)rc.x, src), sty0 = bcast((int)rc.z, src), sntx = bcast(ntx, src),
-                  snt = bcast(nt, src);
-        if (snt <= kWave) {
-            const uint64_t sm = (uint64_t)bcast((uint32_t)m, src) | ((uint64_t)bcast((uint32_t)(m >> 32), src) << 32);
-            if ((sm >> lane) & 1ull) {
-                const int ry = lane / sntx, rx = lane - ry * sntx;
-                const uint32_t tile = (uint32_t)((sty0 + ry) * tiles_x + (stx0 + rx));
-                const uint32_t at = sbase + (uint32_t)__popcll(sm & lt);
-                if (at < cap) {
-                    tile_keys[at] = tile;
-                    values[at] = sg;
-                }
-                record(tile);
-            }
-        } else {
-            const GaussState s = gs[sg];
-            uint32_t run = 0;
-            for (int c0 = 0; c0 < snt; c0 += kWave) {
-                const int idx = c0 + lane;
-                bool h = false;
-                int tile = 0;
-                if (idx < snt) {
-                    const int ry = idx / sntx, rx = idx - ry * sntx;
-                    tile = (sty0 + ry) * tiles_x + (stx0 + rx);
-                    h = binning == 1 ||
-                        tile_hit(s.f0.x, s.f0.y, s.f0.z, s.f0.w, s.f1.x, s.f1.y, stx0 + rx, sty0 + ry, W, H);
-                }
-                const uint64_t b = __ballot(h);
-                if (h) {
-                    const uint32_t at = sbase + run + (uint32_t)__popcll(b & lt);
-                    if (at < cap) {
-                        tile_keys[at] = (uint32_t)tile;
-                        values[at] = sg;
-                    }
-                    record((uint32_t)tile);
-                }
-                run += (uint32_t)__popcll(b);
+    // flattened (Gaussian, rectangle tile) items: every lane handles one tile
+    // of some Gaussian per step and writes it if the hit mask of the
+    // preprocess has its bit, at the Gaussian's offset plus the hits before it
+    const uint32_t items = (act && !chunked && c > 0) ? (uint32_t)nt : 0u;
+    const uint32_t incl = wave_incl_scan(items, lane);
+    const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+    uint32_t *sx = s_excl[threadIdx.x / kWave];
+    sx[lane] = incl - items;
+    for (uint32_t b0 = 0; b0 < total; b0 += kWave) {
+        const uint32_t item = b0 + (uint32_t)lane;
+        const int L = owner_lane(sx, item < total ? item : total - 1u);
+        const uint32_t k = item - sx[L];
+        const uint64_t mL = (uint64_t)(uint32_t)__shfl((int)(uint32_t)m, L, kWave) |
+                            ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(m >> 32), L, kWave) << 32);
+        const uint32_t gL = (uint32_t)__shfl((int)g, L, kWave), baseL = (uint32_t)__shfl((int)base, L, kWave);
+        const int tx0L = __shfl((int)rc.x, L, kWave), ty0L = __shfl((int)rc.z, L, kWave),
+                  ntxL = __shfl(ntx, L, kWave);
+        if (item < total && ((mL >> k) & 1ull)) {
+            const int ry = small_div(k, ntxL), rx = (int)k - ry * ntxL;
+            const uint32_t tile = (uint32_t)((ty0L + ry) * tiles_x + (tx0L + rx));
+            const uint32_t at = baseL + (uint32_t)__popcll(mL & ((1ull << k) - 1ull));
+            if (at < cap) {  // never leave the pair buffers
+                tile_keys[at] = tile;
+                values[at] = gL;
             }
         }
     }
     }  // batch loop
-    __syncthreads();
-    for (int i = threadIdx.x; i < kTileHistBins; i += kBlock)
-        block_hist[(size_t)(row0 + blockIdx.x) * kTileHistBins + i] = s_hist[i];
 }
 
 
@@ -558,7 +515,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(int W, int H, int binning, cons
 __global__ __launch_bounds__(kBlock) void k_big_count(int W, int H, int binning, const GaussState *__restrict__ gs,
                                                       const uint4 *__restrict__ rect,
                                                       const uint2 *__restrict__ chunks, uint32_t chunk_cap,
-                                                      uint32_t *__restrict__ chunk_hits, uint32_t *count,
+                                                      uint32_t *__restrict__ chunk_hits,
+                                                      uint32_t *__restrict__ chunk_mask, uint32_t *count,
                                                       const FrameCounters *fc) {
     __shared__ uint32_t s_w[kBlock / kWave];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
@@ -586,7 +544,11 @@ __global__ __launch_bounds__(kBlock) void k_big_count(int W, int H, int binning,
             }
         }
         const uint64_t b = __ballot(h);
-        if (lane == 0) s_w[wave] = (uint32_t)__popcll(b);
+        if (lane == 0) {
+            s_w[wave] = (uint32_t)__popcll(b);
+            chunk_mask[(size_t)ch * (kChunkTiles / 32) + 2 * wave] = (uint32_t)b;
+            chunk_mask[(size_t)ch * (kChunkTiles / 32) + 2 * wave + 1] = (uint32_t)(b >> 32);
+        }
         __syncthreads();
         if (tid == 0) {
             uint32_t tot = 0;
@@ -598,20 +560,16 @@ __global__ __launch_bounds__(kBlock) void k_big_count(int W, int H, int binning,
     }
 }
 
-// Pairs of the chunked Gaussians: each chunk re-runs the same exact test and
-// writes its hits after those of the Gaussian's earlier chunks.
-__global__ __launch_bounds__(kBlock) void k_big_emit(int W, int H, int binning, const GaussState *__restrict__ gs,
-                                                     const uint4 *__restrict__ rect, const uint2 *__restrict__ mask,
-                                                     const uint2 *__restrict__ chunks, uint32_t chunk_cap,
-                                                     const uint32_t *__restrict__ chunk_hits,
+// Pairs of the chunked Gaussians: each chunk writes the hits recorded by
+// k_big_count after those of the Gaussian's earlier chunks.
+__global__ __launch_bounds__(kBlock) void k_big_emit(int W, const uint4 *__restrict__ rect,
+                                                     const uint2 *__restrict__ mask, const uint2 *__restrict__ chunks,
+                                                     uint32_t chunk_cap, const uint32_t *__restrict__ chunk_hits,
+                                                     const uint32_t *__restrict__ chunk_mask,
                                                      uint32_t *__restrict__ tile_keys, uint32_t *__restrict__ values,
-                                                     uint32_t cap, const FrameCounters *fc,
-                                                     uint32_t *__restrict__ block_hist, uint32_t row0, PassDigits pd) {
-    __shared__ uint32_t s_hist[kTileHistBins];
+                                                     uint32_t cap, const FrameCounters *fc) {
     __shared__ uint32_t s_pre[kBlock / kWave], s_cnt[kBlock / kWave];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    for (int i = tid; i < kTileHistBins; i += kBlock) s_hist[i] = 0;
-    __syncthreads();
     const int tiles_x = (W + kTile - 1) / kTile;
     const uint64_t lt = (1ull << lane) - 1ull;
     const uint32_t n = fc->nchunks < chunk_cap ? fc->nchunks : chunk_cap;
@@ -624,22 +582,7 @@ __global__ __launch_bounds__(kBlock) void k_big_emit(int W, int H, int binning, 
         for (uint32_t k = first + (uint32_t)tid; k < ch; k += kBlock) p += chunk_hits[k];
 #pragma unroll
         for (int d = 1; d < kWave; d <<= 1) p += __shfl_xor(p, d, kWave);
-        const uint4 rc = rect[g];
-        const int ntx = (int)rc.y - (int)rc.x + 1;
-        const int nt = ntx * ((int)rc.w - (int)rc.z + 1);
-        const int idx = (int)c * kChunkTiles + tid;
-        bool h = false;
-        int tile = 0;
-        if (idx < nt) {
-            const int ry = idx / ntx, rx = idx - ry * ntx;
-            tile = ((int)rc.z + ry) * tiles_x + ((int)rc.x + rx);
-            if (binning == 1) {
-                h = true;
-            } else {
-                const GaussState s = gs[g];
-                h = tile_hit(s.f0.x, s.f0.y, s.f0.z, s.f0.w, s.f1.x, s.f1.y, (int)rc.x + rx, (int)rc.z + ry, W, H);
-            }
-        }
+        const bool h = (chunk_mask[(size_t)ch * (kChunkTiles / 32) + tid / 32] >> (tid & 31)) & 1u;
         const uint64_t b = __ballot(h);
         if (lane == 0) {
             s_pre[wave] = p;
@@ -652,100 +595,78 @@ __global__ __launch_bounds__(kBlock) void k_big_emit(int W, int H, int binning, 
             prefix += s_pre[w];
         }
         if (h) {
+            const uint4 rc = rect[g];
+            const int ntx = (int)rc.y - (int)rc.x + 1;
+            const int idx = (int)c * kChunkTiles + tid;
+            const int ry = idx / ntx, rx = idx - ry * ntx;
+            const uint32_t tile = (uint32_t)(((int)rc.z + ry) * tiles_x + ((int)rc.x + rx));
             const uint32_t at = mask[g].x + prefix + before + (uint32_t)__popcll(b & lt);
             if (at < cap) {
-                tile_keys[at] = (uint32_t)tile;
+                tile_keys[at] = tile;
                 values[at] = g;
             }
-            for (int q = 0; q < pd.npasses; ++q)
-                atomicAdd(&s_hist[q * kRadix + (((uint32_t)tile >> pd.shift[q]) & ((1u << pd.bits[q]) - 1u))], 1u);
         }
         __syncthreads();
     }
-    __syncthreads();
-    for (int i = tid; i < kTileHistBins; i += kBlock)
-        block_hist[(size_t)(row0 + blockIdx.x) * kTileHistBins + i] = s_hist[i];
-}
-
-// Sum the per-workgroup histogram rows: out[b] = sum over rows of rows[r][b].
-// Rows are split into groups of kReduceRows so that no thread walks a long
-// chain of dependent loads; groups combine by atomic add into out (cleared
-// at the start of the frame).
-constexpr uint32_t kReduceRows = 32;
-__global__ void k_hist_reduce(const uint32_t *__restrict__ rows, uint32_t nrows, int nbins,
-                              uint32_t *__restrict__ out) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nbins) return;
-    const uint32_t r0 = blockIdx.y * kReduceRows;
-    const uint32_t r1 = r0 + kReduceRows < nrows ? r0 + kReduceRows : nrows;
-    uint32_t s = 0;
-#pragma unroll 8
-    for (uint32_t r = r0; r < r1; ++r) s += rows[(size_t)r * nbins + b];
-    if (s) atomicAdd(&out[b], s);
 }
 
 }  // namespace
 
+// Workgroups that fit on the device at once for a kernel (its register and
+// LDS use decide the occupancy): a persistent grid of exactly that size
+// keeps every CU busy without a tail of late workgroups.
+template <class K>
+static unsigned resident_blocks(K kernel) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu <= 0 ||
+        cus <= 0)
+        return kPersistentBlocks;
+    const unsigned n = (unsigned)(per_cu * cus);
+    return n < (unsigned)kPersistentBlocks ? n : (unsigned)kPersistentBlocks;
+}
+
 unsigned preprocess_grid(int64_t P) {
+    static const unsigned cap = resident_blocks(k_preprocess);
     const int64_t b = (P + kBlock - 1) / kBlock;
-    return (unsigned)(b < kPersistentBlocks ? (b > 0 ? b : 1) : kPersistentBlocks);
+    return (unsigned)(b < (int64_t)cap ? (b > 0 ? b : 1) : cap);
 }
 
 unsigned emit_grid(uint32_t visible) {
+    static const unsigned cap = resident_blocks(k_emit);
     const uint32_t b = (visible + kBlock - 1) / kBlock;
-    return b < (uint32_t)kPersistentBlocks ? (b > 0 ? b : 1u) : (unsigned)kPersistentBlocks;
-}
-
-static PassDigits make_digits(int npasses, const int *shifts, const int *bits) {
-    PassDigits pd{};
-    pd.first_pass = 0;
-    pd.npasses = npasses;
-    for (int p = 0; p < npasses && p < 3; ++p) {
-        pd.shift[p] = shifts[p];
-        pd.bits[p] = bits[p];
-    }
-    return pd;
+    return b < cap ? (b > 0 ? b : 1u) : cap;
 }
 
 void launch_preprocess(const DevScene &sc, const DevCamera &cam, const DevOptions &op, int W, int H,
                        GaussState *gs, uint4 *rect, uint32_t *count, uint2 *mask, uint32_t *dkey, uint2 *chunks,
-                       uint32_t chunk_cap, uint32_t *block_hist, FrameCounters *fc, hipStream_t s) {
+                       uint32_t chunk_cap, FrameCounters *fc, hipStream_t s) {
     if (sc.P <= 0) return;
     hipLaunchKernelGGL(k_preprocess, dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, cam, op, W, H, gs, rect,
-                       count, mask, dkey, chunks, chunk_cap, block_hist, fc);
+                       count, mask, dkey, chunks, chunk_cap, fc);
 }
 
 void launch_big_count(int W, int H, int binning, const GaussState *gs, const uint4 *rect, const uint2 *chunks,
-                      uint32_t chunk_cap, uint32_t *chunk_hits, uint32_t *count, const FrameCounters *fc,
-                      hipStream_t s) {
+                      uint32_t chunk_cap, uint32_t *chunk_hits, uint32_t *chunk_mask, uint32_t *count,
+                      const FrameCounters *fc, hipStream_t s) {
     if (chunk_cap == 0) return;
     hipLaunchKernelGGL(k_big_count, dim3(kPersistentBlocks), dim3(kBlock), 0, s, W, H, binning, gs, rect, chunks,
-                       chunk_cap, chunk_hits, count, fc);
+                       chunk_cap, chunk_hits, chunk_mask, count, fc);
 }
 
-void launch_big_emit(int W, int H, int binning, const GaussState *gs, const uint4 *rect, const uint2 *mask,
-                     const uint2 *chunks, uint32_t chunk_cap, const uint32_t *chunk_hits, uint32_t *tile_keys,
-                     uint32_t *values, uint32_t cap, const FrameCounters *fc, uint32_t *block_hist, uint32_t row0,
-                     int npasses, const int *shifts, const int *bits, hipStream_t s) {
-    hipLaunchKernelGGL(k_big_emit, dim3(kPersistentBlocks), dim3(kBlock), 0, s, W, H, binning, gs, rect, mask, chunks,
-                       chunk_cap, chunk_hits, tile_keys, values, cap, fc, block_hist, row0,
-                       make_digits(npasses, shifts, bits));
+void launch_big_emit(int W, const uint4 *rect, const uint2 *mask, const uint2 *chunks, uint32_t chunk_cap,
+                     const uint32_t *chunk_hits, const uint32_t *chunk_mask, uint32_t *tile_keys, uint32_t *values,
+                     uint32_t cap, const FrameCounters *fc, hipStream_t s) {
+    hipLaunchKernelGGL(k_big_emit, dim3(kPersistentBlocks), dim3(kBlock), 0, s, W, rect, mask, chunks, chunk_cap,
+                       chunk_hits, chunk_mask, tile_keys, values, cap, fc);
 }
 
-void launch_emit(const DevScene &sc, int W, int H, int binning, const uint32_t *order, uint32_t visible,
-                 const uint32_t *offsets, const GaussState *gs, const uint4 *rect, const uint32_t *count,
-                 uint2 *mask, uint32_t *tile_keys, uint32_t *values, uint32_t cap, uint32_t *block_hist,
-                 int npasses, const int *shifts, const int *bits, hipStream_t s) {
-    (void)sc;
-    hipLaunchKernelGGL(k_emit, dim3(emit_grid(visible)), dim3(kBlock), 0, s, W, H, binning, order, visible, offsets,
-                       gs, rect, count, mask, tile_keys, values, cap, block_hist, 0u,
-                       make_digits(npasses, shifts, bits));
-}
-
-void launch_hist_reduce(const uint32_t *rows, uint32_t nrows, int nbins, uint32_t *out, hipStream_t s) {
-    if (nrows == 0) return;
-    hipLaunchKernelGGL(k_hist_reduce, dim3((nbins + kBlock - 1) / kBlock, (nrows + kReduceRows - 1) / kReduceRows),
-                       dim3(kBlock), 0, s, rows, nrows, nbins, out);
+void launch_emit(int W, int H, const uint32_t *order, uint32_t visible, const uint32_t *offsets,
+                 const uint4 *rect, const uint32_t *count, uint2 *mask, uint32_t *tile_keys, uint32_t *values,
+                 uint32_t cap, hipStream_t s) {
+    hipLaunchKernelGGL(k_emit, dim3(emit_grid(visible)), dim3(kBlock), 0, s, W, H, order, visible, offsets, rect,
+                       count, mask, tile_keys, values, cap);
 }
 
 }  // namespace fgs

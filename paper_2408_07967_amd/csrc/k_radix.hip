@@ -1,0 +1,332 @@
+// Stable LSD radix sort pass and exclusive scan without any wait between
+// workgroups (the sort stage of Sec. 2.2; the scan of Alg. 2's offsets).
+//
+// A pass over n keys uses a fixed grid of kSortBlocks workgroups; workgroup b
+// owns a contiguous range of 4096-key tiles (the range is derived on the
+// device from n, so n may be a device-side count):
+//   upsweep    - digit histogram of each workgroup's range   -> hist[b][d]
+//   group sums - sum of the histograms of every kGroup
+//                consecutive workgroups                      -> gsum[w][d]
+//   downsweep  - each workgroup derives the global offset of its first key
+//                of every digit (digit totals, earlier groups, earlier
+//                workgroups of its own group), then walks its tiles in order:
+//                stable ballot ranking per wave64, LDS staging in digit
+//                order, coalesced scatter, running per-digit offsets.
+// Keys are read twice (upsweep and downsweep); in exchange no workgroup ever
+// waits for another one, which on gfx950 is cheaper than a decoupled
+// look-back across eight XCDs.
+#include "fgs_internal.hpp"
+
+namespace fgs {
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kWaves = kBlock / kWave;
+
+__device__ __forceinline__ uint32_t count_of(uint32_t n_host, const uint32_t *n_dev) {
+    if (!n_dev) return n_host;
+    const uint32_t nd = *n_dev;
+    return nd < n_host ? nd : n_host;
+}
+
+// key range [lo, hi) of workgroup b: whole 4096-key tiles split evenly
+__device__ __forceinline__ void block_range(uint32_t n, uint32_t b, uint32_t nb, uint32_t *lo, uint32_t *hi) {
+    const uint32_t tiles = (n + kSortTile - 1) / kSortTile;
+    const uint32_t t0 = (uint32_t)(((uint64_t)tiles * b) / nb);
+    const uint32_t t1 = (uint32_t)(((uint64_t)tiles * (b + 1)) / nb);
+    *lo = t0 * (uint32_t)kSortTile;
+    const uint32_t h = t1 * (uint32_t)kSortTile;
+    *hi = h < n ? h : n;
+    if (*lo > *hi) *lo = *hi;
+}
+
+// Exclusive scan of one value per thread over a 256-thread workgroup.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s_tmp, uint32_t *total) {
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)x, d, kWave);
+        if (lane >= d) x += y;
+    }
+    if (lane == kWave - 1) s_tmp[wave] = x;
+    __syncthreads();
+    uint32_t wpre = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        const uint32_t t = s_tmp[w];
+        wpre += (w < wave) ? t : 0u;
+        tot += t;
+    }
+    __syncthreads();
+    *total = tot;
+    return wpre + x - v;
+}
+
+template <bool kFilter>
+__global__ __launch_bounds__(kBlock) void k_radix_upsweep(const uint32_t *__restrict__ keys, uint32_t n_host,
+                                                          const uint32_t *n_dev, int shift, int bits,
+                                                          uint32_t *__restrict__ hist) {
+    __shared__ uint32_t s_h[kWaves][kRadix];
+    const int tid = threadIdx.x, wave = tid / kWave;
+    for (int i = tid; i < kWaves * kRadix; i += kBlock) (&s_h[0][0])[i] = 0;
+    __syncthreads();
+    const uint32_t n = count_of(n_host, n_dev);
+    uint32_t lo, hi;
+    block_range(n, blockIdx.x, gridDim.x, &lo, &hi);
+    const uint32_t dmask = (1u << bits) - 1u;
+    // kSortItems independent loads in flight per thread before any use
+    for (uint32_t c0 = lo; c0 < hi; c0 += kSortTile) {
+        uint32_t k[kSortItems];
+#pragma unroll
+        for (int i = 0; i < kSortItems; ++i) {
+            const uint32_t idx = c0 + (uint32_t)(i * kBlock + tid);
+            k[i] = idx < hi ? keys[idx] : kInvalidKey;
+        }
+#pragma unroll
+        for (int i = 0; i < kSortItems; ++i) {
+            const uint32_t idx = c0 + (uint32_t)(i * kBlock + tid);
+            if (idx < hi && (!kFilter || k[i] != kInvalidKey)) atomicAdd(&s_h[wave][(k[i] >> shift) & dmask], 1u);
+        }
+    }
+    __syncthreads();
+    hist[(size_t)blockIdx.x * kRadix + tid] = s_h[0][tid] + s_h[1][tid] + s_h[2][tid] + s_h[3][tid];
+}
+
+// gsum[w][d] = sum of hist[b][d] over the kSortGroup workgroups of group w
+__global__ __launch_bounds__(kBlock) void k_radix_groups(const uint32_t *__restrict__ hist, uint32_t nb,
+                                                         uint32_t *__restrict__ gsum) {
+    const uint32_t b0 = blockIdx.x * kSortGroup;
+    uint32_t s = 0;
+#pragma unroll 8
+    for (int r = 0; r < kSortGroup; ++r)
+        if (b0 + r < nb) s += hist[(size_t)(b0 + r) * kRadix + threadIdx.x];
+    gsum[(size_t)blockIdx.x * kRadix + threadIdx.x] = s;
+}
+
+template <bool kIdentityVals, bool kFilter, bool kWriteKeys>
+__global__ __launch_bounds__(kBlock) void k_radix_downsweep(const uint32_t *__restrict__ keys_in,
+                                                            const uint32_t *__restrict__ vals_in,
+                                                            uint32_t *__restrict__ keys_out,
+                                                            uint32_t *__restrict__ vals_out, uint32_t n_host,
+                                                            const uint32_t *n_dev, int shift, int bits,
+                                                            const uint32_t *__restrict__ hist,
+                                                            const uint32_t *__restrict__ gsum) {
+    __shared__ uint32_t s_keys[kSortTile];
+    __shared__ uint32_t s_vals[kSortTile];
+    __shared__ uint32_t s_wave[kWaves][kRadix];
+    __shared__ uint32_t s_off[kRadix];
+    __shared__ uint32_t s_excl[kRadix];
+    __shared__ uint32_t s_tmp[kWaves];
+    __shared__ uint32_t s_nv;
+
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const uint32_t n = count_of(n_host, n_dev);
+    const uint32_t b = blockIdx.x, nb = gridDim.x;
+    uint32_t lo, hi;
+    block_range(n, b, nb, &lo, &hi);
+
+    // global offset of this workgroup's first key of digit tid
+    {
+        const uint32_t ngroups = (nb + kSortGroup - 1) / kSortGroup;
+        const uint32_t mygroup = b / kSortGroup;
+        uint32_t total = 0, before = 0;
+        for (uint32_t w = 0; w < ngroups; ++w) {
+            const uint32_t g = gsum[(size_t)w * kRadix + tid];
+            total += g;
+            before += (w < mygroup) ? g : 0u;
+        }
+        for (uint32_t r = mygroup * kSortGroup; r < b; ++r) before += hist[(size_t)r * kRadix + tid];
+        uint32_t all = 0;
+        const uint32_t dbase = block_exclusive_scan(total, s_tmp, &all);
+        s_off[tid] = dbase + before;
+    }
+    if (lo >= hi) return;  // uniform: no tile for this workgroup
+
+    const uint32_t dmask = (1u << bits) - 1u;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    for (uint32_t t0 = lo; t0 < hi; t0 += kSortTile) {
+        for (int i = tid; i < kWaves * kRadix; i += kBlock) (&s_wave[0][0])[i] = 0;
+        __syncthreads();
+        const uint32_t base = t0 + (uint32_t)wave * (kSortItems * kWave);
+        uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+        // all loads of the tile first, so that they are in flight together
+#pragma unroll
+        for (int i = 0; i < kSortItems; ++i) {
+            const uint32_t idx = base + (uint32_t)(i * kWave + lane);
+            const bool in = idx < hi;
+            key[i] = in ? keys_in[idx] : kInvalidKey;
+            val[i] = kIdentityVals ? idx : (in ? vals_in[idx] : 0u);
+        }
+#pragma unroll
+        for (int i = 0; i < kSortItems; ++i) {
+            const uint32_t idx = base + (uint32_t)(i * kWave + lane);
+            const bool in = idx < hi;
+            const uint32_t k = key[i];
+            const bool ok = in && (!kFilter || k != kInvalidKey);
+            const uint32_t d = (k >> shift) & dmask;
+            // lanes of this step with the same digit (stable rank = lower lanes)
+            uint64_t peers = __ballot(ok);
+            for (int bb = 0; bb < bits; ++bb) {
+                const bool bit = (d >> bb) & 1u;
+                const uint64_t m = __ballot(bit);
+                peers &= bit ? m : ~m;
+            }
+            const uint32_t before = (uint32_t)__popcll(peers & lt);
+            const uint32_t cnt = (uint32_t)__popcll(peers);
+            uint32_t prev = 0;
+            if (ok) prev = s_wave[wave][d];
+            if (ok && before == 0) s_wave[wave][d] = prev + cnt;
+            rank[i] = ok ? prev + before : 0xffffffffu;
+        }
+        __syncthreads();
+        // thread tid owns digit tid: per-wave counts -> exclusive over waves
+        const uint32_t c0 = s_wave[0][tid], c1 = s_wave[1][tid], c2 = s_wave[2][tid], c3 = s_wave[3][tid];
+        s_wave[0][tid] = 0;
+        s_wave[1][tid] = c0;
+        s_wave[2][tid] = c0 + c1;
+        s_wave[3][tid] = c0 + c1 + c2;
+        const uint32_t dsum = c0 + c1 + c2 + c3;
+        uint32_t nvalid = 0;
+        s_excl[tid] = block_exclusive_scan(dsum, s_tmp, &nvalid);
+        if (tid == 0) s_nv = nvalid;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kSortItems; ++i) {
+            if (rank[i] != 0xffffffffu) {
+                const uint32_t d = (key[i] >> shift) & dmask;
+                const uint32_t lp = s_excl[d] + s_wave[wave][d] + rank[i];
+                s_keys[lp] = key[i];
+                s_vals[lp] = val[i];
+            }
+        }
+        __syncthreads();
+        const uint32_t nv = s_nv;
+        for (uint32_t j = tid; j < nv; j += kBlock) {
+            const uint32_t k = s_keys[j];
+            const uint32_t d = (k >> shift) & dmask;
+            const uint32_t gpos = s_off[d] + (j - s_excl[d]);
+            if (gpos < n) {  // never leave the output (n bounds the scattered count)
+                if (kWriteKeys) keys_out[gpos] = k;
+                vals_out[gpos] = s_vals[j];
+            }
+        }
+        __syncthreads();
+        s_off[tid] += dsum;
+    }
+}
+
+// ---- exclusive scan of per-Gaussian tile counts in depth order -------------
+
+// cs[r] = count[order[r]]; sums[b] = sum over the workgroup's range
+__global__ __launch_bounds__(kBlock) void k_scan_upsweep(const uint32_t *__restrict__ order,
+                                                         const uint32_t *__restrict__ count, uint32_t n_host,
+                                                         const uint32_t *n_dev, uint32_t *__restrict__ cs,
+                                                         uint32_t *__restrict__ sums) {
+    __shared__ uint32_t s_tmp[kWaves];
+    const uint32_t n = count_of(n_host, n_dev);
+    uint32_t lo, hi;
+    block_range(n, blockIdx.x, gridDim.x, &lo, &hi);
+    uint32_t s = 0;
+    for (uint32_t c0 = lo; c0 < hi; c0 += 8 * kBlock) {
+        uint32_t g[8], c[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t i = c0 + (uint32_t)(k * kBlock) + threadIdx.x;
+            g[k] = i < hi ? order[i] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t i = c0 + (uint32_t)(k * kBlock) + threadIdx.x;
+            c[k] = i < hi ? count[g[k]] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t i = c0 + (uint32_t)(k * kBlock) + threadIdx.x;
+            if (i < hi) cs[i] = c[k];
+            s += c[k];
+        }
+    }
+    uint32_t tot = 0;
+    (void)block_exclusive_scan(s, s_tmp, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// one workgroup: exclusive scan of the kSortBlocks workgroup sums; total -> *pairs
+__global__ __launch_bounds__(kBlock) void k_scan_sums(uint32_t *__restrict__ sums, uint32_t nb, uint32_t *pairs) {
+    __shared__ uint32_t s_tmp[kWaves];
+    constexpr int kPer = kSortBlocks / kBlock;
+    uint32_t v[kPer], s = 0;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        const uint32_t idx = threadIdx.x * kPer + i;
+        v[i] = idx < nb ? sums[idx] : 0u;
+        s += v[i];
+    }
+    uint32_t tot = 0;
+    uint32_t run = block_exclusive_scan(s, s_tmp, &tot);
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        const uint32_t idx = threadIdx.x * kPer + i;
+        if (idx < nb) sums[idx] = run;
+        run += v[i];
+    }
+    if (threadIdx.x == 0) *pairs = tot;
+}
+
+// offsets[r] = exclusive prefix of cs; offsets[n] = total
+__global__ __launch_bounds__(kBlock) void k_scan_downsweep(const uint32_t *__restrict__ cs, uint32_t n_host,
+                                                           const uint32_t *n_dev, const uint32_t *__restrict__ sums,
+                                                           uint32_t *__restrict__ offsets) {
+    __shared__ uint32_t s_tmp[kWaves];
+    const uint32_t n = count_of(n_host, n_dev);
+    uint32_t lo, hi;
+    block_range(n, blockIdx.x, gridDim.x, &lo, &hi);
+    uint32_t run = sums[blockIdx.x];
+    for (uint32_t c0 = lo; c0 < hi; c0 += kBlock) {
+        const uint32_t i = c0 + threadIdx.x;
+        const uint32_t c = i < hi ? cs[i] : 0u;
+        uint32_t tot = 0;
+        const uint32_t ex = block_exclusive_scan(c, s_tmp, &tot);
+        if (i < hi) offsets[i] = run + ex;
+        run += tot;
+    }
+    if (hi == n && lo < hi && threadIdx.x == 0) offsets[n] = run;
+}
+
+}  // namespace
+
+void launch_radix_pass(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_out, uint32_t *vals_out,
+                       uint32_t n_host, const uint32_t *n_dev, int shift, int bits, bool filter, bool write_keys,
+                       uint32_t *hist, uint32_t *gsum, hipStream_t s) {
+    if (n_host == 0) return;
+    const unsigned nb = kSortBlocks;
+    const unsigned ng = (nb + kSortGroup - 1) / kSortGroup;
+    if (filter)
+        hipLaunchKernelGGL(k_radix_upsweep<true>, dim3(nb), dim3(kBlock), 0, s, keys_in, n_host, n_dev, shift, bits,
+                           hist);
+    else
+        hipLaunchKernelGGL(k_radix_upsweep<false>, dim3(nb), dim3(kBlock), 0, s, keys_in, n_host, n_dev, shift,
+                           bits, hist);
+    hipLaunchKernelGGL(k_radix_groups, dim3(ng), dim3(kBlock), 0, s, hist, nb, gsum);
+    const bool ident = vals_in == nullptr;
+#define FGS_DS(I, F, K)                                                                                         \
+    hipLaunchKernelGGL((k_radix_downsweep<I, F, K>), dim3(nb), dim3(kBlock), 0, s, keys_in, vals_in, keys_out, \
+                       vals_out, n_host, n_dev, shift, bits, hist, gsum)
+    if (ident && filter && write_keys) FGS_DS(true, true, true);
+    else if (!ident && !filter && write_keys) FGS_DS(false, false, true);
+    else if (!ident && !filter && !write_keys) FGS_DS(false, false, false);
+    else if (ident && !filter && write_keys) FGS_DS(true, false, true);
+    else FGS_DS(false, true, true);
+#undef FGS_DS
+}
+
+void launch_count_scan(const uint32_t *order, const uint32_t *count, uint32_t n_host, const uint32_t *n_dev,
+                       uint32_t *cs, uint32_t *sums, uint32_t *offsets, uint32_t *pairs, hipStream_t s) {
+    if (n_host == 0) return;
+    hipLaunchKernelGGL(k_scan_upsweep, dim3(kSortBlocks), dim3(kBlock), 0, s, order, count, n_host, n_dev, cs, sums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, s, sums, (uint32_t)kSortBlocks, pairs);
+    hipLaunchKernelGGL(k_scan_downsweep, dim3(kSortBlocks), dim3(kBlock), 0, s, cs, n_host, n_dev, sums, offsets);
+}
+
+}  // namespace fgs

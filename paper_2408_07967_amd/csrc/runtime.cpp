@@ -76,14 +76,13 @@ struct fgs_context {
     std::vector<fgs_frame *> frames;
     FrameCounters *fc_dev = nullptr;
     FrameCounters *fc_host = nullptr;
-    uint64_t *status = nullptr;
-    size_t status_entries = 0;
-    uint32_t epoch = 0;
+    // radix-sort and scan scratch (fixed size)
+    uint32_t *rhist = nullptr, *gsum = nullptr, *sums = nullptr;
     // chunk list of Gaussians with large rectangles (used within one render)
     uint2 *chunks = nullptr;
     uint32_t *chunk_hits = nullptr;
     size_t chunk_cap = 0;
-    uint32_t *block_hist = nullptr;  // per-workgroup histogram rows
+    uint32_t *chunk_mask = nullptr;  // 256-bit hit mask per chunk
     // instrumentation
     int instr = 0;
     hipEvent_t ev[2][8] = {};
@@ -116,12 +115,6 @@ fgs_status fail(fgs_context *ctx, fgs_status s, const char *fmt, ...) {
             return fail(ctx, e_ == hipErrorOutOfMemory ? FGS_ERR_OUT_OF_MEMORY : FGS_ERR_DEVICE, "%s: %s", \
                         #expr, hipGetErrorString(e_));                                                       \
     } while (0)
-
-uint32_t next_epoch(fgs_context *ctx) {
-    ctx->epoch = (ctx->epoch + 1) & 0x3fffffffu;
-    if (ctx->epoch == 0) ctx->epoch = 1;
-    return ctx->epoch;
-}
 
 // Add the stage times of a completed instrumented frame to the sums.
 void fold_events(fgs_context *ctx) {
@@ -196,17 +189,11 @@ fgs_status ensure_pixels(fgs_context *ctx, FrameBuffers &b, size_t pix) {
     return FGS_OK;
 }
 
-fgs_status ensure_status(fgs_context *ctx, size_t entries) {
-    if (entries <= ctx->status_entries && ctx->status) return FGS_OK;
-    size_t cap = entries + entries / 4 + 4096;
-    if (ctx->status) {
-        HIP_TRY(ctx, hipDeviceSynchronize());
-        (void)hipFree(ctx->status);
-    }
-    ctx->status = nullptr;
-    HIP_TRY(ctx, hipMalloc((void **)&ctx->status, cap * sizeof(uint64_t)));
-    HIP_TRY(ctx, hipMemset(ctx->status, 0, cap * sizeof(uint64_t)));
-    ctx->status_entries = cap;
+fgs_status ensure_sort_scratch(fgs_context *ctx) {
+    if (ctx->rhist) return FGS_OK;
+    HIP_TRY(ctx, grow(ctx->rhist, 0, (size_t)kSortBlocks * kRadix));
+    HIP_TRY(ctx, grow(ctx->gsum, 0, (size_t)(kSortBlocks / kSortGroup) * kRadix));
+    HIP_TRY(ctx, grow(ctx->sums, 0, (size_t)kSortBlocks));
     return FGS_OK;
 }
 
@@ -215,11 +202,8 @@ fgs_status ensure_chunks(fgs_context *ctx, size_t need) {
     if (need <= ctx->chunk_cap && ctx->chunks) return FGS_OK;
     HIP_TRY(ctx, grow(ctx->chunks, 0, need));
     HIP_TRY(ctx, grow(ctx->chunk_hits, 0, need));
+    HIP_TRY(ctx, grow(ctx->chunk_mask, 0, need * (kChunkTiles / 32)));
     ctx->chunk_cap = need;
-    if (!ctx->block_hist) {
-        const size_t rows = 2 * (size_t)kPersistentBlocks + 1;
-        HIP_TRY(ctx, grow(ctx->block_hist, 0, rows * (size_t)kDepthHistBins));
-    }
     return FGS_OK;
 }
 
@@ -399,11 +383,13 @@ void fgs_destroy(fgs_context *ctx) {
             if (e) (void)hipEventDestroy(e);
     if (ctx->work_dev) (void)hipFree(ctx->work_dev);
     if (ctx->chunks) (void)hipFree(ctx->chunks);
-    if (ctx->block_hist) (void)hipFree(ctx->block_hist);
+    if (ctx->chunk_mask) (void)hipFree(ctx->chunk_mask);
+    if (ctx->rhist) (void)hipFree(ctx->rhist);
+    if (ctx->gsum) (void)hipFree(ctx->gsum);
+    if (ctx->sums) (void)hipFree(ctx->sums);
     if (ctx->chunk_hits) (void)hipFree(ctx->chunk_hits);
     if (ctx->fc_dev) (void)hipFree(ctx->fc_dev);
     if (ctx->fc_host) (void)hipHostFree(ctx->fc_host);
-    if (ctx->status) (void)hipFree(ctx->status);
     delete ctx;
 }
 
@@ -419,13 +405,15 @@ fgs_status fgs_reserve(fgs_context *ctx, int64_t max_gaussians, int64_t max_pair
     if ((s = ensure_pairs(ctx, ctx->fb, (size_t)max_pairs)) != FGS_OK) return s;
     const size_t tiles = (size_t)((max_w + kTile - 1) / kTile) * ((max_h + kTile - 1) / kTile);
     if ((s = ensure_tiles(ctx, ctx->fb, tiles)) != FGS_OK) return s;
-    const size_t blocks = ((size_t)std::max<int64_t>(max_gaussians, max_pairs) + kSortTile - 1) / kSortTile + 1;
-    return ensure_status(ctx, blocks * kRadix);
+    if ((s = ensure_chunks(ctx, (size_t)max_gaussians / 8)) != FGS_OK) return s;
+    return ensure_sort_scratch(ctx);
 }
 
 size_t fgs_scratch_bytes(const fgs_context *ctx) {
     if (!ctx) return 0;
-    size_t b = ctx->fb.bytes() + ctx->status_entries * sizeof(uint64_t) + sizeof(FrameCounters);
+    size_t b = ctx->fb.bytes() + sizeof(FrameCounters) + ctx->chunk_cap * (sizeof(uint2) + 9 * sizeof(uint32_t)) +
+               ((size_t)kSortBlocks * kRadix + (size_t)(kSortBlocks / kSortGroup) * kRadix + kSortBlocks) *
+                   sizeof(uint32_t);
     for (const FrameBuffers &p : ctx->pool) b += p.bytes();
     for (const fgs_frame *f : ctx->frames) b += f->fb.bytes();
     return b;
@@ -455,7 +443,7 @@ fgs_status fgs_render(fgs_context *ctx, const fgs_scene *scene, const fgs_camera
     const size_t npix = (size_t)W * H;
     if ((st = ensure_gauss(ctx, fb, (size_t)P)) != FGS_OK) return st;
     if ((st = ensure_tiles(ctx, fb, ntiles)) != FGS_OK) return st;
-    if ((st = ensure_status(ctx, (((size_t)P + kSortTile - 1) / kSortTile + 1) * kRadix)) != FGS_OK) return st;
+    if ((st = ensure_sort_scratch(ctx)) != FGS_OK) return st;
     if (saved && (st = ensure_pixels(ctx, fb, npix)) != FGS_OK) return st;
     if ((st = ensure_chunks(ctx, (size_t)P / 8)) != FGS_OK) return st;
 
@@ -483,32 +471,28 @@ fgs_status fgs_render(fgs_context *ctx, const fgs_scene *scene, const fgs_camera
     // ---- stage 1: preprocess + exact tile count ---------------------------
     launch_fill_u32(reinterpret_cast<uint32_t *>(fc), 0u, sizeof(FrameCounters) / 4, s);
     mark(0);
-    launch_preprocess(dsc, dcam, dop, W, H, fb.gs, fb.rect, fb.count, fb.mask, fb.dkey, ctx->chunks, chunk_cap,
-                      ctx->block_hist, fc, s);
-    launch_big_count(W, H, opt.binning, fb.gs, fb.rect, ctx->chunks, chunk_cap, ctx->chunk_hits, fb.count, fc, s);
-    if (P > 0) launch_hist_reduce(ctx->block_hist, preprocess_grid(P), kDepthHistBins, &fc->hist[0][0], s);
+    launch_preprocess(dsc, dcam, dop, W, H, fb.gs, fb.rect, fb.count, fb.mask, fb.dkey, ctx->chunks, chunk_cap, fc,
+                      s);
+    launch_big_count(W, H, opt.binning, fb.gs, fb.rect, ctx->chunks, chunk_cap, ctx->chunk_hits, ctx->chunk_mask,
+                     fb.count, fc, s);
     // ---- depth order of the visible Gaussians: 4 LSD passes over the depth
     // digits, hoisted before key duplication (the low half of the (tile |
     // depth) key is the same for every pair of a Gaussian) --------------------
     mark(1);
     const uint32_t P32 = (uint32_t)P;
-    launch_onesweep(fb.dkey, nullptr, fb.dk_b, fb.dv_b, P32, nullptr, 0, 8, 0, true, true, fc, ctx->status,
-                    next_epoch(ctx), s);
-    launch_onesweep(fb.dk_b, fb.dv_b, fb.dkey, fb.dv_a, P32, &fc->visible, 8, 8, 1, false, true, fc, ctx->status,
-                    next_epoch(ctx), s);
-    launch_onesweep(fb.dkey, fb.dv_a, fb.dk_b, fb.dv_b, P32, &fc->visible, 16, 8, 2, false, true, fc, ctx->status,
-                    next_epoch(ctx), s);
-    launch_onesweep(fb.dk_b, fb.dv_b, fb.dkey, fb.dv_a, P32, &fc->visible, 24, 8, 3, false, false, fc, ctx->status,
-                    next_epoch(ctx), s);
+    uint32_t *rh = ctx->rhist, *gs_ = ctx->gsum;
+    launch_radix_pass(fb.dkey, nullptr, fb.dk_b, fb.dv_b, P32, nullptr, 0, 8, true, true, rh, gs_, s);
+    launch_radix_pass(fb.dk_b, fb.dv_b, fb.dkey, fb.dv_a, P32, &fc->visible, 8, 8, false, true, rh, gs_, s);
+    launch_radix_pass(fb.dkey, fb.dv_a, fb.dk_b, fb.dv_b, P32, &fc->visible, 16, 8, false, true, rh, gs_, s);
+    launch_radix_pass(fb.dk_b, fb.dv_b, fb.dkey, fb.dv_a, P32, &fc->visible, 24, 8, false, false, rh, gs_, s);
     mark(2);
     // ---- stage 2a: scan of the tile counts in depth order -------------------
-    launch_count_scan(fb.dv_a, fb.count, P32, fb.offsets, fc, ctx->status, next_epoch(ctx), s);
+    launch_count_scan(fb.dv_a, fb.count, P32, &fc->visible, fb.dk_b, ctx->sums, fb.offsets, &fc->pairs, s);
     mark(3);
     HIP_TRY(ctx, hipGetLastError());
     HIP_TRY(ctx, hipMemcpyAsync(ctx->fc_host, fc, sizeof(uint32_t) * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     fold_events(ctx);  // the previous instrumented frame is complete after the wait
-    if (ctx->fc_host->error & kErrLookback) return fail(ctx, FGS_ERR_INTERNAL, "a bounded device wait gave up");
     if (ctx->fc_host->error & kErrChunkOverflow) {
         // the large-Gaussian chunk list was too small: size it exactly and
         // render the frame again
@@ -525,21 +509,17 @@ fgs_status fgs_render(fgs_context *ctx, const fgs_scene *scene, const fgs_camera
 
     // ---- stage 2b: key emission -------------------------------------------
     if ((st = ensure_pairs(ctx, fb, N)) != FGS_OK) return st;
-    if ((st = ensure_status(ctx, (((size_t)N + kSortTile - 1) / kSortTile + 1) * kRadix)) != FGS_OK) return st;
     int shifts[3] = {0, 0, 0}, widths[3] = {0, 0, 0};
     const int npass = plan_tile_passes(ceil_log2(ntiles), shifts, widths);
     const uint32_t pair_cap = (uint32_t)std::min<size_t>(fb.capN, 0xffffffffu);
-    launch_emit(dsc, W, H, opt.binning, fb.dv_a, V, fb.offsets, fb.gs, fb.rect, fb.count, fb.mask, fb.tk_a, fb.tv_a,
-                pair_cap, ctx->block_hist, npass, shifts, widths, s);
-    launch_big_emit(W, H, opt.binning, fb.gs, fb.rect, fb.mask, ctx->chunks, chunk_cap, ctx->chunk_hits, fb.tk_a,
-                    fb.tv_a, pair_cap, fc, ctx->block_hist, emit_grid(V), npass, shifts, widths, s);
-    launch_hist_reduce(ctx->block_hist, emit_grid(V) + kPersistentBlocks, kTileHistBins, &fc->hist[4][0], s);
+    launch_emit(W, H, fb.dv_a, V, fb.offsets, fb.rect, fb.count, fb.mask, fb.tk_a, fb.tv_a, pair_cap, s);
+    launch_big_emit(W, fb.rect, fb.mask, ctx->chunks, chunk_cap, ctx->chunk_hits, ctx->chunk_mask, fb.tk_a, fb.tv_a,
+                    pair_cap, fc, s);
     mark(4);
     // ---- stage 3: stable LSD sort of the pairs by tile id -------------------
     uint32_t *ki = fb.tk_a, *vi = fb.tv_a, *ko = fb.tk_b, *vo = fb.tv_b;
     for (int p = 0; p < npass; ++p) {
-        launch_onesweep(ki, vi, ko, vo, N, nullptr, shifts[p], widths[p], 4 + p, false, true, fc, ctx->status,
-                        next_epoch(ctx), s);
+        launch_radix_pass(ki, vi, ko, vo, N, nullptr, shifts[p], widths[p], false, true, ctx->rhist, ctx->gsum, s);
         std::swap(ki, ko);
         std::swap(vi, vo);
     }
