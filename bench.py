@@ -85,6 +85,9 @@ def main():
     ap.add_argument("--workload", default="city4k", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-work-count", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed region, run one device copy of 256 MiB (read 256 MiB, write 256 MiB) "
+                         "whose FETCH_SIZE / WRITE_SIZE counters scale the blend kernel's counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this renderer runs on a single MI355X; "
@@ -135,6 +138,13 @@ def main():
     nf = max(1, inst["frames"])
     stage_ms = {k[3:]: round(inst[k] / nf, 4) for k in inst if k.startswith("ms_")}
     log(f"[bench] {args.steps} frames in {dt:.3f}s -> {fps:.2f} frames/s; stages {stage_ms}")
+
+    if args.copy_calibration:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     roof = None
     if evals is not None and stage_ms["blend"] > 0:
