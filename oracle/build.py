@@ -1,6 +1,7 @@
 """Build the CPU oracle library (test infrastructure only).
 
-Compiles orc_core.c twice (binary64 and binary32 modes) plus orc_math.c with
+Compiles orc_core.c twice (binary64 and binary32 modes) plus orc_grad.c (the
+binary64 adjoint) and orc_math.c with
 gcc into oracle/liboracle.so.  -ffp-contract=off keeps every written
 operation a separately rounded IEEE-754 operation; no fast-math.
 """
@@ -20,6 +21,7 @@ def build(verbose=False):
         objs = []
         for src, defs, name in (("orc_core.c", ["-DORC_FP64"], "core64.o"),
                                 ("orc_core.c", ["-DORC_FP32"], "core32.o"),
+                                ("orc_grad.c", [], "grad64.o"),
                                 ("orc_math.c", [], "math.o")):
             out = os.path.join(td, name)
             cmd = ["gcc", *CFLAGS, *defs, "-c", os.path.join(HERE, src), "-o", out]

@@ -210,3 +210,30 @@ def log_d(x):
     f.restype = C.c_double
     f.argtypes = [C.c_double]
     return f(x)
+
+
+def backward(out, dL_drgb):
+    """Binary64 adjoint of a binary64 render (`out` from render(..., mode="f64")).
+
+    dL_drgb: [3, H, W].  Returns gradients shaped like the scene's arrays
+    (means [3, P], log_scales [3, P], quats [4, P], logits [1, P],
+    sh [3 (D+1)^2, P]) and the per-Gaussian state gradient [P, 9]
+    (u, v, A, B, C, o, r, g, b)."""
+    prep = out["prep"]
+    assert prep.mode == "f64", "the adjoint is defined on the binary64 render"
+    P = prep.P
+    nsh = prep.arrays[4].shape[0]
+    g = dict(means=np.zeros((3, P)), log_scales=np.zeros((3, P)), quats=np.zeros((4, P)),
+             logits=np.zeros((1, P)), sh=np.zeros((nsh, P)), state=np.zeros((P, 9)))
+    dL = np.ascontiguousarray(dL_drgb, np.float64)
+    assert dL.shape == (3, prep.H, prep.W)
+    vals = np.ascontiguousarray(out["vals"], np.uint32)
+    if vals.size == 0:
+        vals = np.zeros(1, np.uint32)
+    f = _lib().orc_backward_f64
+    f.restype = None
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)
+    f(C.byref(prep.sc), C.byref(prep.cam), prep.W, prep.H, C.byref(prep.opts), ptr(out["state"]), ptr(out["ints"]),
+      ptr(vals), ptr(np.ascontiguousarray(out["ranges"])), ptr(dL), ptr(g["means"]), ptr(g["log_scales"]),
+      ptr(g["quats"]), ptr(g["logits"]), ptr(g["sh"]), ptr(g["state"]))
+    return g
