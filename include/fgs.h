@@ -164,13 +164,25 @@ fgs_status fgs_render(fgs_context *ctx, const fgs_scene *scene, const fgs_camera
 
 /* ---- backward ----------------------------------------------------------- */
 
-/* Gradients of a scalar loss L with respect to the raw scene parameters,
- * given dL/dRGB for the image of `frame` (the paper claims a differentiable
- * rasterizer; the adjoint replays the blend back to front from T_final and
- * last, with wavefront-reduced atomics as in the related DISTWAR work).
- *   dL_drgb  device, [3][H][W] float.
- *   grad     device gradient planes (overwritten).
- * scene, cam and opt must be those of the forward call. */
+/* Gradients of a scalar loss L with respect to the raw scene parameters
+ * (the paper calls its rasterizer differentiable and leaves the adjoint out;
+ * this one replays each pixel's blend back to front from its saved final
+ * transmittance and last contributor, with wavefront-reduced atomics as in
+ * the DISTWAR work the paper cites).
+ *   frame    a frame saved by fgs_render of this context (not released).
+ *   scene    the forward call's scene, same pointers and unchanged values.
+ *   cam, opt NULL, or identical to the forward call's (else INVALID_ARGUMENT).
+ *   dL_drgb  device, [3][H][W] float, H and W of the frame.
+ *   grad     device gradient planes, planar like the scene with
+ *            grad->plane_stride >= P; every plane of Gaussians 0..P-1 is
+ *            overwritten (zero for culled Gaussians).  The derivative through
+ *            a clamped alpha, a colour channel clamped at 0 or a clamped
+ *            Jacobian view direction is zero.  Camera gradients are not
+ *            computed.
+ * Enqueued on `stream`, which first waits for the forward's work if it ran
+ * on another stream.  Floating-point atomics make the summation order, and so
+ * the last bits of the gradients, vary from run to run.  The context's
+ * accumulation buffer (9 floats per Gaussian) grows on first use. */
 fgs_status fgs_render_backward(fgs_context *ctx, const fgs_frame *frame, const fgs_scene *scene,
                                const fgs_camera *cam, const fgs_options *opt, const float *dL_drgb,
                                const fgs_scene_grad *grad, void *stream);

@@ -123,4 +123,18 @@ void launch_blend(const GaussState *gs, const uint32_t *values, const uint2 *ran
                   const DevOptions &op, float *rgb, float *T, uint32_t *last, unsigned long long *work,
                   hipStream_t s);
 
+// Adjoint of the blend: accumulates per-Gaussian sums (9 planes of stride
+// acc_stride, cleared by the caller) from dL/dRGB, replaying each pixel's
+// tile list back to front from its final transmittance and last contributor.
+void launch_blend_backward(const GaussState *gs, const uint32_t *values, const uint2 *ranges, const float *Tfin,
+                           const uint32_t *last, const float *dL, int W, int H, const DevOptions &op, float *acc,
+                           int64_t acc_stride, hipStream_t s);
+
+// Adjoint of the preprocessing: raw-parameter gradients (planar, stride
+// grad_stride, overwritten) from the blend adjoint's sums.
+void launch_preprocess_backward(const DevScene &sc, const DevCamera &cam, const DevOptions &op, int W, int H,
+                                const GaussState *gs, const float *acc, int64_t acc_stride, float *g_means,
+                                float *g_log_scales, float *g_quats, float *g_logits, float *g_sh,
+                                int64_t grad_stride, hipStream_t s);
+
 }  // namespace fgs

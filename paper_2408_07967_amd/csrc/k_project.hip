@@ -7,6 +7,7 @@
 // bits as the canonical FP32 evaluation of the method; exp and ln are
 // evaluated in binary64 by a fixed operation sequence and rounded once.
 #include "fgs_internal.hpp"
+#include "sh_basis.hpp"
 
 namespace fgs {
 namespace {
@@ -162,40 +163,6 @@ __device__ __forceinline__ int owner_lane(const uint32_t *s, uint32_t item) {
 // away from an integer, far more than the reciprocal's error.
 __device__ __forceinline__ int small_div(uint32_t k, int n) {
     return (int)(((float)k + 0.5f) * __builtin_amdgcn_rcpf((float)n));
-}
-
-// Real orthonormal SH basis with the Condon-Shortley phase, k = l^2 + l + m.
-__device__ __forceinline__ void sh_basis(float x, float y, float z, int D, float *Y) {
-    const float c0 = 0.28209479177387814f;   // 1 / (2 sqrt(pi))
-    const float c1 = 0.48860251190291992f;   // sqrt(3 / (4 pi))
-    Y[0] = c0;
-    if (D < 1) return;
-    Y[1] = -c1 * y;
-    Y[2] = c1 * z;
-    Y[3] = -c1 * x;
-    if (D < 2) return;
-    const float xx = x * x, yy = y * y, zz = z * z;
-    const float c2a = 1.0925484305920792f;   // sqrt(15 / (4 pi))
-    const float c20 = 0.31539156525252005f;  // sqrt(5 / (16 pi))
-    const float c22 = 0.54627421529603959f;  // sqrt(15 / (16 pi))
-    Y[4] = c2a * (x * y);
-    Y[5] = -c2a * (y * z);
-    Y[6] = c20 * (3.0f * zz - 1.0f);
-    Y[7] = -c2a * (x * z);
-    Y[8] = c22 * (xx - yy);
-    if (D < 3) return;
-    const float c33 = 0.59004358992664352f;  // sqrt(35 / (32 pi))
-    const float c32 = 2.8906114426405538f;   // sqrt(105 / (4 pi))
-    const float c31 = 0.45704579946446572f;  // sqrt(21 / (32 pi))
-    const float c30 = 0.37317633259011546f;  // sqrt(7 / (16 pi))
-    const float c32b = 1.4453057213202769f;  // sqrt(105 / (16 pi))
-    Y[9] = -c33 * (y * (3.0f * xx - yy));
-    Y[10] = c32 * (x * y * z);
-    Y[11] = -c31 * (y * (5.0f * zz - 1.0f));
-    Y[12] = c30 * (z * (5.0f * zz - 3.0f));
-    Y[13] = -c31 * (x * (5.0f * zz - 1.0f));
-    Y[14] = c32b * (z * (xx - yy));
-    Y[15] = -c33 * (x * (xx - 3.0f * yy));
 }
 
 __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevCamera cam, DevOptions op, int W, int H,

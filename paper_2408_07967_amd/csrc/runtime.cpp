@@ -65,6 +65,9 @@ struct fgs_frame {
     uint32_t visible = 0, pairs = 0;
     bool tiles_in_a = true;
     hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;  // recorded on `stream` after the forward's last kernel
+    fgs_camera cam{};
+    fgs_options opt{};
     fgs_stats stats{};
 };
 
@@ -91,6 +94,9 @@ struct fgs_context {
     hipStream_t ev_stream = nullptr;
     fgs_timings acc{};
     unsigned long long *work_dev = nullptr;
+    // backward: per-Gaussian sums of the blend adjoint, 9 planes of gacc_stride
+    float *gacc = nullptr;
+    size_t gacc_stride = 0;
 };
 
 namespace {
@@ -374,8 +380,10 @@ void fgs_destroy(fgs_context *ctx) {
     (void)hipDeviceSynchronize();
     for (fgs_frame *f : ctx->frames) {
         free_frame_buffers(f->fb);
+        if (f->done) (void)hipEventDestroy(f->done);
         delete f;
     }
+    if (ctx->gacc) (void)hipFree(ctx->gacc);
     for (FrameBuffers &b : ctx->pool) free_frame_buffers(b);
     free_frame_buffers(ctx->fb);
     for (auto &set : ctx->ev)
@@ -414,6 +422,7 @@ size_t fgs_scratch_bytes(const fgs_context *ctx) {
     size_t b = ctx->fb.bytes() + sizeof(FrameCounters) + ctx->chunk_cap * (sizeof(uint2) + 9 * sizeof(uint32_t)) +
                ((size_t)kSortBlocks * kRadix + (size_t)(kSortBlocks / kSortGroup) * kRadix + kSortBlocks) *
                    sizeof(uint32_t);
+    b += 9 * ctx->gacc_stride * sizeof(float);
     for (const FrameBuffers &p : ctx->pool) b += p.bytes();
     for (const fgs_frame *f : ctx->frames) b += f->fb.bytes();
     return b;
@@ -563,6 +572,14 @@ fgs_status fgs_render(fgs_context *ctx, const fgs_scene *scene, const fgs_camera
         f->tiles_in_a = (ki == fb.tk_a);
         f->stream = s;
         f->stats = stt;
+        f->cam = *cam;
+        f->opt = opt;
+        if (hipEventCreateWithFlags(&f->done, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(f->done, s) != hipSuccess) {
+            if (f->done) (void)hipEventDestroy(f->done);
+            delete f;
+            return fail(ctx, FGS_ERR_DEVICE, "cannot record the saved frame's completion event");
+        }
         ctx->frames.push_back(f);
         // the context continues with pooled or fresh buffers
         if (!ctx->pool.empty()) {
@@ -584,6 +601,11 @@ fgs_status fgs_frame_release(fgs_context *ctx, fgs_frame *frame) {
             ctx->frames.erase(ctx->frames.begin() + (long)i);
             (void)hipSetDevice(ctx->device);
             (void)hipStreamSynchronize(frame->stream);
+            if (frame->done) {
+                // a backward may have used the frame on another stream
+                (void)hipEventSynchronize(frame->done);
+                (void)hipEventDestroy(frame->done);
+            }
             if (ctx->pool.size() < 4)
                 ctx->pool.push_back(frame->fb);
             else
@@ -677,15 +699,64 @@ fgs_status fgs_get_instrumentation(fgs_context *ctx, fgs_timings *out) {
 
 fgs_status fgs_render_backward(fgs_context *ctx, const fgs_frame *frame, const fgs_scene *scene,
                                const fgs_camera *cam, const fgs_options *opt, const float *dL_drgb,
-                               const fgs_scene_grad *grad, void *stream) {
-    (void)frame;
-    (void)scene;
-    (void)cam;
-    (void)opt;
-    (void)dL_drgb;
-    (void)grad;
-    (void)stream;
-    return fail(ctx, FGS_ERR_NOT_SUPPORTED, "backward not built yet");
+                               const fgs_scene_grad *grad, void *stream_v) {
+    if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARGUMENT, "context is NULL");
+    if (!frame) return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "frame is NULL");
+    bool owned = false;
+    for (const fgs_frame *f : ctx->frames) owned |= (f == frame);
+    if (!owned) return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "frame does not belong to this context");
+    fgs_status st = validate(ctx, scene, cam ? cam : &frame->cam, frame->W, frame->H, opt ? opt : &frame->opt);
+    if (st != FGS_OK) return st;
+    if (scene->num_gaussians != frame->P)
+        return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "scene has %lld Gaussians, the frame was rendered with %lld",
+                    (long long)scene->num_gaussians, (long long)frame->P);
+    if (cam && memcmp(cam, &frame->cam, sizeof(fgs_camera)) != 0)
+        return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "camera differs from the forward call's");
+    if (opt && memcmp(opt, &frame->opt, sizeof(fgs_options)) != 0)
+        return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "options differ from the forward call's");
+    if (!dL_drgb) return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "dL_drgb is NULL");
+    if (!grad) return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "grad is NULL");
+    const int64_t P = frame->P;
+    if (grad->plane_stride < P)
+        return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "grad.plane_stride %lld < num_gaussians %lld",
+                    (long long)grad->plane_stride, (long long)P);
+    if (P > 0 && (!grad->means || !grad->log_scales || !grad->quats || !grad->opacity_logits || !grad->sh))
+        return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "a gradient pointer is NULL");
+    ctx->err.clear();
+    hipStream_t s = (hipStream_t)stream_v;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    if (s != frame->stream) HIP_TRY(ctx, hipStreamWaitEvent(s, frame->done, 0));
+    if (P == 0) return FGS_OK;
+
+    const size_t stride = (size_t)P;
+    if (ctx->gacc_stride < stride || !ctx->gacc) {
+        const size_t cap = stride + stride / 8 + 1024;
+        HIP_TRY(ctx, grow(ctx->gacc, 0, 9 * cap));
+        ctx->gacc_stride = cap;
+    }
+    const int64_t as = (int64_t)ctx->gacc_stride;
+    // cleared with a fill kernel (no memset node if the caller captures a graph)
+    launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->gacc), 0u, 9 * (size_t)as, s);
+
+    const fgs_options &op = frame->opt;
+    const DevOptions dop = to_dev(op);
+    const DevCamera dcam = to_dev(frame->cam);
+    const FrameBuffers &fb = frame->fb;
+    launch_blend_backward(fb.gs, frame->tiles_in_a ? fb.tv_a : fb.tv_b, fb.ranges, fb.T, fb.last, dL_drgb,
+                          frame->W, frame->H, dop, ctx->gacc, as, s);
+    DevScene dsc{};
+    dsc.means = scene->means;
+    dsc.log_scales = scene->log_scales;
+    dsc.quats = scene->quats;
+    dsc.logits = scene->opacity_logits;
+    dsc.sh = scene->sh;
+    dsc.P = P;
+    dsc.stride = scene->plane_stride;
+    dsc.D = scene->sh_degree;
+    launch_preprocess_backward(dsc, dcam, dop, frame->W, frame->H, fb.gs, ctx->gacc, as, grad->means,
+                               grad->log_scales, grad->quats, grad->opacity_logits, grad->sh, grad->plane_stride, s);
+    HIP_TRY(ctx, hipGetLastError());
+    return FGS_OK;
 }
 
 }  // extern "C"

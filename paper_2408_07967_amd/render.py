@@ -1,6 +1,7 @@
 """PyTorch-facing wrapper over the C ABI.  PyTorch supplies device memory and
 the current HIP stream; every stage of the rasterizer runs in libfgs.so."""
 import ctypes as C
+import weakref
 
 import numpy as np
 import torch
@@ -89,6 +90,24 @@ class Renderer:
                     stats=dict(visible=st.visible, pairs=st.pairs, tiles_x=st.tiles_x, tiles_y=st.tiles_y,
                                sort_passes=st.sort_passes))
 
+    def backward(self, frame, scene, cam, W, H, opts, dL_drgb):
+        """Gradients of L with respect to the raw parameters of `scene`, given
+        dL/dRGB [3, H, W] for a frame saved by render(..., save=True).
+        Returns a tuple of tensors shaped like scene.tensors()."""
+        dev = scene.means.device
+        dL = dL_drgb.to(device=dev, dtype=torch.float32).contiguous()
+        if tuple(dL.shape) != (3, H, W):
+            raise ValueError(f"dL_drgb must have shape (3, {H}, {W}), got {tuple(dL.shape)}")
+        grads = tuple(torch.empty_like(t) for t in scene.tensors())
+        g = B.FgsSceneGrad(scene.P, *(t.data_ptr() for t in grads))
+        sc = scene.abi()
+        cm = camera_abi(cam)
+        op = options_abi(opts)
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        self.ctx.check(B.lib().fgs_render_backward(self.ctx.handle, frame, C.byref(sc), C.byref(cm), C.byref(op),
+                                                   dL.data_ptr(), C.byref(g), stream))
+        return grads
+
     def set_instrumentation(self, flags):
         self.ctx.check(B.lib().fgs_set_instrumentation(self.ctx.handle, int(flags)))
 
@@ -105,8 +124,48 @@ class Renderer:
         return buf[: n // 4]
 
     def release(self, frame):
-        if frame:
+        # a closed context has already freed its frames
+        if frame and self.ctx.handle:
             self.ctx.check(B.lib().fgs_frame_release(self.ctx.handle, frame))
 
     def close(self):
         self.ctx.close()
+
+
+class _FrameHolder:
+    """Keeps a saved frame alive for the autograd graph; releases it when the
+    graph is freed."""
+
+    def __init__(self, renderer, frame):
+        self.frame = frame
+        self._fin = weakref.finalize(self, renderer.release, frame)
+
+
+class RenderFunction(torch.autograd.Function):
+    """Differentiable render: rgb = render(means, log_scales, quats, logits, sh).
+
+    The forward saves its frame (per-Gaussian state, sorted lists, final
+    transmittance and last contributor per pixel); the backward runs the
+    hand-written adjoint kernels of libfgs.so."""
+
+    @staticmethod
+    def forward(ctx, renderer, cam, W, H, opts, sh_degree, means, log_scales, quats, logits, sh):
+        scene = GaussianScene(means.detach().contiguous(), log_scales.detach().contiguous(),
+                              quats.detach().contiguous(), logits.detach().contiguous(), sh.detach().contiguous(),
+                              sh_degree)
+        out = renderer.render(scene, cam, W, H, opts, save=True)
+        ctx.renderer, ctx.cam, ctx.W, ctx.H, ctx.opts = renderer, cam, W, H, opts
+        ctx.scene = scene
+        ctx.holder = _FrameHolder(renderer, out["frame"])
+        ctx.stats = out["stats"]
+        return out["rgb"]
+
+    @staticmethod
+    def backward(ctx, grad_rgb):
+        grads = ctx.renderer.backward(ctx.holder.frame, ctx.scene, ctx.cam, ctx.W, ctx.H, ctx.opts, grad_rgb)
+        return (None, None, None, None, None, None) + tuple(grads)
+
+
+def render_differentiable(renderer, cam, W, H, opts, sh_degree, means, log_scales, quats, logits, sh):
+    """rgb [3, H, W] with gradients for the five planar parameter tensors."""
+    return RenderFunction.apply(renderer, cam, W, H, opts, sh_degree, means, log_scales, quats, logits, sh)
