@@ -242,6 +242,99 @@ fgs_status fgs_frame_download(fgs_context *ctx, const fgs_frame *frame, fgs_fiel
                               size_t bytes);
 fgs_status fgs_frame_stats(const fgs_frame *frame, fgs_stats *stats);
 
+/* ---- render server: continuous batching over a resident scene ---------- */
+/* The paper renders one frame at a time from statically allocated buffers
+ * (Sec. 5.3.1).  The server keeps one scene resident and serves camera
+ * requests of mixed resolutions concurrently.  A request takes a slot (its
+ * own stream and per-Gaussian buffers) and runs the first half of the frame
+ * (preprocess, exact tile counts, depth order, count scan), which yields its
+ * exact pair count N.  It is then admitted when its pair and sort buffers
+ * (16 bytes per pair) fit in the free part of a device byte budget: FIFO, a
+ * request that does not fit may be overtaken by at most max_bypass later
+ * ones.  The second half (emission, tile sort, ranges, blend) then runs as
+ * a hipGraph captured once per (slot, resolution) and replayed.  Requests
+ * in different slots overlap on the device.  One worker thread owned by the
+ * server issues all of its GPU work.  Images are bit-identical to fgs_render
+ * of the same request alone. */
+typedef struct fgs_server fgs_server;
+
+typedef struct {
+    int64_t budget_bytes;   /* pair and sort buffers of admitted requests (>= 1 MiB) */
+    int32_t max_inflight;   /* slots, 1..32                                          */
+    int32_t max_width;      /* largest request, 1..16384                             */
+    int32_t max_height;
+    int32_t max_bypass;     /* >= 0                                                  */
+    int32_t use_graphs;     /* 1: replay a captured graph per (slot, W, H); 0: launch */
+    int32_t reserved;       /* must be 0                                             */
+} fgs_server_config;
+
+typedef struct {
+    uint64_t id;
+    int32_t status;         /* FGS_OK; FGS_ERR_CAPACITY if the request can never fit
+                               the budget; FGS_ERR_DEVICE on a device error        */
+    int32_t width, height;
+    int32_t slot;
+    const float *rgb;       /* device [3][H][W]; valid until fgs_server_release(id) */
+    int64_t arrival_ns;     /* fgs_clock_ns() clock, as submitted                   */
+    int64_t start_ns;       /* first half enqueued                                  */
+    int64_t admit_ns;       /* second half enqueued                                 */
+    int64_t done_ns;        /* completion observed by the worker                    */
+    int64_t visible, pairs;
+} fgs_server_result;
+
+typedef struct {
+    int64_t submitted, completed, rejected;
+    int64_t graphs_captured, graph_launches;
+    int64_t region_allocs, region_evictions, bypasses;
+    int64_t peak_bytes_in_use;  /* of the budget                                       */
+    int64_t budget_bytes;
+    int64_t slot_bytes;         /* per-slot buffers outside the budget (all slots)     */
+} fgs_server_stats;
+
+/* Monotonic clock (ns) of the server's timestamps. */
+int64_t fgs_clock_ns(void);
+
+/* scene: device planes that stay valid and unchanged while the server lives.
+ * opt: NULL means defaults; fixed for all requests. */
+fgs_status fgs_server_create(int device, const fgs_scene *scene, const fgs_options *opt,
+                             const fgs_server_config *cfg, fgs_server **out);
+/* Stops the worker after the work in flight; frees everything. */
+void fgs_server_destroy(fgs_server *srv);
+const char *fgs_server_last_error(const fgs_server *srv);
+/* Queue a request (thread-safe).  W, H within the configured maximum.
+ * out_rgb: NULL (the image stays in the slot until fgs_server_release), or
+ * caller-owned device memory of 3 W H floats that receives a copy of the
+ * image before the request is reported complete. */
+fgs_status fgs_server_submit(fgs_server *srv, uint64_t id, const fgs_camera *cam, int32_t W, int32_t H,
+                             int64_t arrival_ns, float *out_rgb);
+/* Move up to max completed requests into out, waiting up to wait_ns for the
+ * first; returns their number (>= 0) or a negative fgs_status. */
+int32_t fgs_server_poll(fgs_server *srv, fgs_server_result *out, int32_t max, int64_t wait_ns);
+/* The image of a completed request may be overwritten; its slot is reused. */
+fgs_status fgs_server_release(fgs_server *srv, uint64_t id);
+fgs_status fgs_server_get_stats(fgs_server *srv, fgs_server_stats *out);
+
+/* One request of a recorded trace: arrival relative to the replay's start. */
+typedef struct {
+    uint64_t id;
+    fgs_camera cam;
+    int32_t width, height;
+    int64_t arrival_offset_ns;
+} fgs_trace_request;
+
+/* Replay a trace through the server: submit each request at its arrival
+ * time, release every image as soon as it completes.  results[i] belongs to
+ * trace[i]. */
+fgs_status fgs_server_replay(fgs_server *srv, const fgs_trace_request *trace, int64_t n,
+                             fgs_server_result *results);
+
+/* The same trace through the plain renderer: one request at a time in
+ * arrival order, fgs_render into rgb_scratch (device, >= 3 W H floats of the
+ * largest request), waiting for each frame before the next. */
+fgs_status fgs_replay_plain(fgs_context *ctx, const fgs_scene *scene, const fgs_options *opt,
+                            const fgs_trace_request *trace, int64_t n, float *rgb_scratch,
+                            fgs_server_result *results, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -57,6 +57,30 @@ class FgsTimings(C.Structure):
 INSTR_STAGE_TIMES = 1
 INSTR_WORK = 2
 
+
+class FgsServerConfig(C.Structure):
+    _fields_ = [("budget_bytes", C.c_int64), ("max_inflight", C.c_int32), ("max_width", C.c_int32),
+                ("max_height", C.c_int32), ("max_bypass", C.c_int32), ("use_graphs", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class FgsServerResult(C.Structure):
+    _fields_ = [("id", C.c_uint64), ("status", C.c_int32), ("width", C.c_int32), ("height", C.c_int32),
+                ("slot", C.c_int32), ("rgb", C.c_void_p), ("arrival_ns", C.c_int64), ("start_ns", C.c_int64),
+                ("admit_ns", C.c_int64), ("done_ns", C.c_int64), ("visible", C.c_int64), ("pairs", C.c_int64)]
+
+
+class FgsServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("rejected", C.c_int64),
+                ("graphs_captured", C.c_int64), ("graph_launches", C.c_int64), ("region_allocs", C.c_int64),
+                ("region_evictions", C.c_int64), ("bypasses", C.c_int64), ("peak_bytes_in_use", C.c_int64),
+                ("budget_bytes", C.c_int64), ("slot_bytes", C.c_int64)]
+
+
+class FgsTraceRequest(C.Structure):
+    _fields_ = [("id", C.c_uint64), ("cam", FgsCamera), ("width", C.c_int32), ("height", C.c_int32),
+                ("arrival_offset_ns", C.c_int64)]
+
 # name -> (restype, argtypes); the exported symbols of include/fgs.h
 PROTOTYPES = {
     "fgs_create": (C.c_int, [C.c_int, C.POINTER(C.c_void_p)]),
@@ -79,6 +103,21 @@ PROTOTYPES = {
     "fgs_frame_stats": (C.c_int, [C.c_void_p, C.POINTER(FgsStats)]),
     "fgs_set_instrumentation": (C.c_int, [C.c_void_p, C.c_int]),
     "fgs_get_instrumentation": (C.c_int, [C.c_void_p, C.POINTER(FgsTimings)]),
+    "fgs_clock_ns": (C.c_int64, []),
+    "fgs_server_create": (C.c_int, [C.c_int, C.POINTER(FgsScene), C.POINTER(FgsOptions),
+                                    C.POINTER(FgsServerConfig), C.POINTER(C.c_void_p)]),
+    "fgs_server_destroy": (None, [C.c_void_p]),
+    "fgs_server_last_error": (C.c_char_p, [C.c_void_p]),
+    "fgs_server_submit": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(FgsCamera), C.c_int32, C.c_int32,
+                                    C.c_int64, C.c_void_p]),
+    "fgs_server_poll": (C.c_int32, [C.c_void_p, C.POINTER(FgsServerResult), C.c_int32, C.c_int64]),
+    "fgs_server_release": (C.c_int, [C.c_void_p, C.c_uint64]),
+    "fgs_server_get_stats": (C.c_int, [C.c_void_p, C.POINTER(FgsServerStats)]),
+    "fgs_server_replay": (C.c_int, [C.c_void_p, C.POINTER(FgsTraceRequest), C.c_int64,
+                                    C.POINTER(FgsServerResult)]),
+    "fgs_replay_plain": (C.c_int, [C.c_void_p, C.POINTER(FgsScene), C.POINTER(FgsOptions),
+                                   C.POINTER(FgsTraceRequest), C.c_int64, C.c_void_p, C.POINTER(FgsServerResult),
+                                   C.c_void_p]),
 }
 
 _lib = None

@@ -89,9 +89,10 @@ void launch_big_count(int W, int H, int binning, const GaussState *gs, const uin
 
 // Emit (tile, gaussian) pairs for Gaussians in depth order.  Chunked
 // Gaussians only record their output base in mask[g].x.
-void launch_emit(int W, int H, const uint32_t *order, uint32_t visible, const uint32_t *offsets,
-                 const uint4 *rect, const uint32_t *count, uint2 *mask, uint32_t *tile_keys, uint32_t *values,
-                 uint32_t cap, hipStream_t s);
+// visible: the count, or a bound on it when visible_dev (device) holds it.
+void launch_emit(int W, int H, const uint32_t *order, uint32_t visible, const uint32_t *visible_dev,
+                 const uint32_t *offsets, const uint4 *rect, const uint32_t *count, uint2 *mask, uint32_t *tile_keys,
+                 uint32_t *values, uint32_t cap, hipStream_t s);
 
 // Emit the pairs of the chunked Gaussians (after launch_emit).
 void launch_big_emit(int W, const uint4 *rect, const uint2 *mask, const uint2 *chunks, uint32_t chunk_cap,
@@ -115,7 +116,9 @@ void launch_radix_pass(const uint32_t *keys_in, const uint32_t *vals_in, uint32_
 void launch_count_scan(const uint32_t *order, const uint32_t *count, uint32_t n_host, const uint32_t *n_dev,
                        uint32_t *cs, uint32_t *sums, uint32_t *offsets, uint32_t *pairs, hipStream_t s);
 
-void launch_tile_ranges(const uint32_t *tile_keys, uint32_t n, uint2 *ranges, uint32_t ntiles, hipStream_t s);
+// n: the key count, or a bound on it when n_dev (device) holds it.
+void launch_tile_ranges(const uint32_t *tile_keys, uint32_t n, const uint32_t *n_dev, uint2 *ranges,
+                        uint32_t ntiles, hipStream_t s);
 
 // work: if non-null, the blend adds the number of list entries every pixel
 // examines (a separate, slower kernel instantiation)

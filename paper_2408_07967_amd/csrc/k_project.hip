@@ -416,12 +416,16 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevCamera ca
 // prefix scan; the tile test is reused from the preprocess through the hit
 // mask).  Chunked Gaussians only record their output base here.
 __global__ __launch_bounds__(kBlock) void k_emit(int W, int H, const uint32_t *__restrict__ order,
-                                                 uint32_t visible, const uint32_t *__restrict__ offsets,
+                                                 uint32_t visible, const uint32_t *__restrict__ visible_dev,
+                                                 const uint32_t *__restrict__ offsets,
                                                  const uint4 *__restrict__ rect,
                                                  const uint32_t *__restrict__ count, uint2 *__restrict__ mask,
                                                  uint32_t *__restrict__ tile_keys, uint32_t *__restrict__ values,
                                                  uint32_t cap) {
     __shared__ uint32_t s_excl[kBlock / kWave][kWave];
+    // the visible count comes from the device when the launch is sized by a
+    // bound (graph-captured frames); it never exceeds the bound
+    if (visible_dev) visible = min(visible, *visible_dev);
     const int tiles_x = (W + kTile - 1) / kTile;
     const int lane = threadIdx.x & (kWave - 1);
     for (uint32_t r0 = blockIdx.x * kBlock; r0 < visible; r0 += gridDim.x * kBlock) {
@@ -629,11 +633,12 @@ void launch_big_emit(int W, const uint4 *rect, const uint2 *mask, const uint2 *c
                        chunk_hits, chunk_mask, tile_keys, values, cap, fc);
 }
 
-void launch_emit(int W, int H, const uint32_t *order, uint32_t visible, const uint32_t *offsets,
-                 const uint4 *rect, const uint32_t *count, uint2 *mask, uint32_t *tile_keys, uint32_t *values,
-                 uint32_t cap, hipStream_t s) {
-    hipLaunchKernelGGL(k_emit, dim3(emit_grid(visible)), dim3(kBlock), 0, s, W, H, order, visible, offsets, rect,
-                       count, mask, tile_keys, values, cap);
+void launch_emit(int W, int H, const uint32_t *order, uint32_t visible, const uint32_t *visible_dev,
+                 const uint32_t *offsets, const uint4 *rect, const uint32_t *count, uint2 *mask, uint32_t *tile_keys,
+                 uint32_t *values, uint32_t cap, hipStream_t s) {
+    if (visible == 0) return;
+    hipLaunchKernelGGL(k_emit, dim3(emit_grid(visible)), dim3(kBlock), 0, s, W, H, order, visible, visible_dev,
+                       offsets, rect, count, mask, tile_keys, values, cap);
 }
 
 }  // namespace fgs

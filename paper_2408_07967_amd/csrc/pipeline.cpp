@@ -1,0 +1,280 @@
+// Host-side frame pipeline: buffer management, argument checks and the
+// kernel sequence of one frame (preprocess -> depth order -> count scan ->
+// emission -> tile sort -> ranges -> blend).
+#include "pipeline.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace fgs {
+
+namespace {
+
+template <class T>
+hipError_t grow(T *&p, size_t n_need) {
+    if (p) {
+        // the old buffer may still be read by queued work
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return e;
+        (void)hipFree(p);
+    }
+    p = nullptr;
+    return hipMalloc((void **)&p, (n_need ? n_need : 1) * sizeof(T));
+}
+
+#define FGS_GROW(p, n)                       \
+    do {                                     \
+        hipError_t e_ = grow((p), (n));      \
+        if (e_ != hipSuccess) return e_;     \
+    } while (0)
+
+void free_p(void *&p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+bool finite_all(const float *p, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+int ceil_log2(uint64_t x) {
+    int b = 0;
+    while ((1ull << b) < x) ++b;
+    return b;
+}
+
+// Split `bits` tile-id bits into passes of at most kRadixBits each.
+int plan_tile_passes(int bits, int *shift, int *width) {
+    if (bits <= 0) return 0;
+    const int np = (bits + kRadixBits - 1) / kRadixBits;
+    int s = 0;
+    for (int p = 0; p < np; ++p) {
+        const int w = (bits - s + (np - p) - 1) / (np - p);
+        shift[p] = s;
+        width[p] = w;
+        s += w;
+    }
+    return np;
+}
+
+}  // namespace
+
+hipError_t ensure_gauss(FrameBuffers &b, size_t P) {
+    if (P <= b.capP && b.gs) return hipSuccess;
+    const size_t cap = P + P / 8 + 1024;
+    FGS_GROW(b.gs, cap);
+    FGS_GROW(b.rect, cap);
+    FGS_GROW(b.count, cap);
+    FGS_GROW(b.mask, cap);
+    FGS_GROW(b.dkey, cap);
+    FGS_GROW(b.dk_b, cap);
+    FGS_GROW(b.dv_a, cap);
+    FGS_GROW(b.dv_b, cap);
+    FGS_GROW(b.offsets, cap + 1);
+    b.capP = cap;
+    return hipSuccess;
+}
+
+hipError_t ensure_pairs(FrameBuffers &b, size_t N) {
+    if (N <= b.capN && b.tk_a) return hipSuccess;
+    const size_t cap = N + N / 4 + 4096;
+    FGS_GROW(b.tk_a, cap);
+    FGS_GROW(b.tk_b, cap);
+    FGS_GROW(b.tv_a, cap);
+    FGS_GROW(b.tv_b, cap);
+    b.capN = cap;
+    b.pairs_owned = true;
+    return hipSuccess;
+}
+
+hipError_t ensure_tiles(FrameBuffers &b, size_t tiles) {
+    if (tiles <= b.capTiles && b.ranges) return hipSuccess;
+    FGS_GROW(b.ranges, tiles);
+    b.capTiles = tiles;
+    return hipSuccess;
+}
+
+hipError_t ensure_pixels(FrameBuffers &b, size_t pix) {
+    if (pix <= b.capPix && b.T) return hipSuccess;
+    FGS_GROW(b.T, pix);
+    FGS_GROW(b.last, pix);
+    b.capPix = pix;
+    return hipSuccess;
+}
+
+hipError_t ensure_sort_scratch(SortScratch &s) {
+    if (s.rhist) return hipSuccess;
+    FGS_GROW(s.rhist, (size_t)kSortBlocks * kRadix);
+    FGS_GROW(s.gsum, (size_t)(kSortBlocks / kSortGroup) * kRadix);
+    FGS_GROW(s.sums, (size_t)kSortBlocks);
+    return hipSuccess;
+}
+
+hipError_t ensure_chunks(ChunkList &c, size_t need) {
+    need = std::max<size_t>(need, 65536);
+    if (need <= c.cap && c.chunks) return hipSuccess;
+    FGS_GROW(c.chunks, need);
+    FGS_GROW(c.hits, need);
+    FGS_GROW(c.mask, need * (kChunkTiles / 32));
+    c.cap = need;
+    return hipSuccess;
+}
+
+void free_frame_buffers(FrameBuffers &b) {
+    void **ps[] = {(void **)&b.gs, (void **)&b.rect, (void **)&b.count, (void **)&b.mask, (void **)&b.dkey,
+                   (void **)&b.dk_b, (void **)&b.dv_a, (void **)&b.dv_b, (void **)&b.offsets, (void **)&b.ranges,
+                   (void **)&b.T, (void **)&b.last};
+    for (void **p : ps) free_p(*p);
+    if (b.pairs_owned) {
+        void **pp[] = {(void **)&b.tk_a, (void **)&b.tk_b, (void **)&b.tv_a, (void **)&b.tv_b};
+        for (void **p : pp) free_p(*p);
+    }
+    b = FrameBuffers{};
+}
+
+void free_sort_scratch(SortScratch &s) {
+    free_p(*(void **)&s.rhist);
+    free_p(*(void **)&s.gsum);
+    free_p(*(void **)&s.sums);
+}
+
+void free_chunks(ChunkList &c) {
+    free_p(*(void **)&c.chunks);
+    free_p(*(void **)&c.hits);
+    free_p(*(void **)&c.mask);
+    c.cap = 0;
+}
+
+fgs_status check_args(const fgs_scene *sc, const fgs_camera *cam, int32_t W, int32_t H, const fgs_options *opt,
+                      std::string &err) {
+    auto bad = [&](const char *m) {
+        err = m;
+        return FGS_ERR_INVALID_ARGUMENT;
+    };
+    if (!sc) return bad("scene is NULL");
+    if (!cam) return bad("camera is NULL");
+    if (sc->num_gaussians < 0 || sc->num_gaussians > 0x7fffffffLL) return bad("num_gaussians out of range [0, 2^31)");
+    if (sc->plane_stride < sc->num_gaussians) return bad("plane_stride < num_gaussians");
+    if (sc->sh_degree < 0 || sc->sh_degree > 3) return bad("sh_degree outside 0..3");
+    if (sc->reserved != 0) return bad("scene.reserved must be 0");
+    if (sc->num_gaussians > 0 && (!sc->means || !sc->log_scales || !sc->quats || !sc->opacity_logits || !sc->sh))
+        return bad("a scene attribute pointer is NULL");
+    if (W < 1 || W > 16384 || H < 1 || H > 16384) return bad("image size outside 1..16384");
+    if (!finite_all(cam->R, 9) || !finite_all(cam->t, 3) || !finite_all(cam->eye, 3) || !std::isfinite(cam->fx) ||
+        !std::isfinite(cam->fy) || !std::isfinite(cam->cx) || !std::isfinite(cam->cy) || !std::isfinite(cam->near_z))
+        return bad("camera has a non-finite value");
+    if (!(cam->fx > 0.0f) || !(cam->fy > 0.0f)) return bad("focal length <= 0");
+    if (!(cam->near_z > 0.0f)) return bad("near_z <= 0");
+    if (opt) {
+        if (!(opt->alpha_min > 0.0f && opt->alpha_min < 1.0f)) return bad("alpha_min outside (0, 1)");
+        if (!(opt->T_stop >= 0.0f && opt->T_stop < 1.0f)) return bad("T_stop outside [0, 1)");
+        if (!(opt->alpha_max > 0.0f && opt->alpha_max < 1.0f)) return bad("alpha_max outside (0, 1)");
+        if (!(opt->dilation >= 0.0f) || !std::isfinite(opt->dilation)) return bad("dilation must be finite and >= 0");
+        if (!(opt->jac_clip > 0.0f) || !std::isfinite(opt->jac_clip)) return bad("jac_clip must be finite and > 0");
+        if (!finite_all(opt->bg, 3)) return bad("background is not finite");
+        if (opt->binning < 0 || opt->binning > 1) return bad("binning not in {0, 1}");
+    }
+    return FGS_OK;
+}
+
+DevOptions to_dev(const fgs_options &o) {
+    DevOptions d{};
+    d.alpha_min = o.alpha_min;
+    d.T_stop = o.T_stop;
+    d.alpha_max = o.alpha_max;
+    d.dilation = o.dilation;
+    d.jac_clip = o.jac_clip;
+    for (int i = 0; i < 3; ++i) d.bg[i] = o.bg[i];
+    d.cap_3sigma = o.cap_3sigma;
+    d.binning = o.binning;
+    return d;
+}
+
+DevCamera to_dev(const fgs_camera &c) {
+    DevCamera d{};
+    memcpy(d.R, c.R, sizeof d.R);
+    memcpy(d.t, c.t, sizeof d.t);
+    memcpy(d.eye, c.eye, sizeof d.eye);
+    d.fx = c.fx;
+    d.fy = c.fy;
+    d.cx = c.cx;
+    d.cy = c.cy;
+    d.near_z = c.near_z;
+    return d;
+}
+
+DevScene to_dev(const fgs_scene &s) {
+    DevScene d{};
+    d.means = s.means;
+    d.log_scales = s.log_scales;
+    d.quats = s.quats;
+    d.logits = s.opacity_logits;
+    d.sh = s.sh;
+    d.P = s.num_gaussians;
+    d.stride = s.plane_stride;
+    d.D = s.sh_degree;
+    return d;
+}
+
+void enqueue_front(const DevScene &sc, const DevCamera &cam, const DevOptions &op, int W, int H, FrameBuffers &fb,
+                   ChunkList &ch, SortScratch &ss, FrameCounters *fc, FrameCounters *host_fc, hipStream_t s,
+                   const StageMarks &mk) {
+    const uint32_t chunk_cap = (uint32_t)std::min<size_t>(ch.cap, 0xffffffffu);
+    // ---- stage 1: preprocess + exact tile count -------------------------------
+    launch_fill_u32(reinterpret_cast<uint32_t *>(fc), 0u, sizeof(FrameCounters) / 4, s);
+    mk.mark(0, s);
+    launch_preprocess(sc, cam, op, W, H, fb.gs, fb.rect, fb.count, fb.mask, fb.dkey, ch.chunks, chunk_cap, fc, s);
+    launch_big_count(W, H, op.binning, fb.gs, fb.rect, ch.chunks, chunk_cap, ch.hits, ch.mask, fb.count, fc, s);
+    // ---- depth order of the visible Gaussians: 4 LSD passes over the depth
+    // digits, hoisted before key duplication (the low half of the (tile |
+    // depth) key is the same for every pair of a Gaussian) --------------------
+    mk.mark(1, s);
+    const uint32_t P32 = (uint32_t)sc.P;
+    launch_radix_pass(fb.dkey, nullptr, fb.dk_b, fb.dv_b, P32, nullptr, 0, 8, true, true, ss.rhist, ss.gsum, s);
+    launch_radix_pass(fb.dk_b, fb.dv_b, fb.dkey, fb.dv_a, P32, &fc->visible, 8, 8, false, true, ss.rhist, ss.gsum, s);
+    launch_radix_pass(fb.dkey, fb.dv_a, fb.dk_b, fb.dv_b, P32, &fc->visible, 16, 8, false, true, ss.rhist, ss.gsum,
+                      s);
+    launch_radix_pass(fb.dk_b, fb.dv_b, fb.dkey, fb.dv_a, P32, &fc->visible, 24, 8, false, false, ss.rhist, ss.gsum,
+                      s);
+    mk.mark(2, s);
+    // ---- stage 2a: scan of the tile counts in depth order -------------------------
+    launch_count_scan(fb.dv_a, fb.count, P32, &fc->visible, fb.dk_b, ss.sums, fb.offsets, &fc->pairs, s);
+    mk.mark(3, s);
+    (void)hipMemcpyAsync(host_fc, fc, sizeof(FrameCounters), hipMemcpyDeviceToHost, s);
+}
+
+bool enqueue_back(int W, int H, const DevOptions &op, uint32_t P, FrameBuffers &fb, ChunkList &ch, SortScratch &ss,
+                  FrameCounters *fc, float *rgb, float *T, uint32_t *last, unsigned long long *work, hipStream_t s,
+                  const StageMarks &mk) {
+    const int tiles_x = (W + kTile - 1) / kTile, tiles_y = (H + kTile - 1) / kTile;
+    const uint32_t ntiles = (uint32_t)tiles_x * (uint32_t)tiles_y;
+    const uint32_t chunk_cap = (uint32_t)std::min<size_t>(ch.cap, 0xffffffffu);
+    const uint32_t pair_cap = (uint32_t)std::min<size_t>(fb.capN, 0xffffffffu);
+    // ---- stage 2b: key emission -------------------------------------------------
+    launch_emit(W, H, fb.dv_a, P, &fc->visible, fb.offsets, fb.rect, fb.count, fb.mask, fb.tk_a, fb.tv_a, pair_cap,
+                s);
+    launch_big_emit(W, fb.rect, fb.mask, ch.chunks, chunk_cap, ch.hits, ch.mask, fb.tk_a, fb.tv_a, pair_cap, fc, s);
+    mk.mark(4, s);
+    // ---- stage 3: stable LSD sort of the pairs by tile id ---------------------------
+    int shifts[4] = {0, 0, 0, 0}, widths[4] = {0, 0, 0, 0};
+    const int npass = plan_tile_passes(ceil_log2(ntiles), shifts, widths);
+    uint32_t *ki = fb.tk_a, *vi = fb.tv_a, *ko = fb.tk_b, *vo = fb.tv_b;
+    for (int p = 0; p < npass; ++p) {
+        launch_radix_pass(ki, vi, ko, vo, pair_cap, &fc->pairs, shifts[p], widths[p], false, true, ss.rhist, ss.gsum,
+                          s);
+        std::swap(ki, ko);
+        std::swap(vi, vo);
+    }
+    mk.mark(5, s);
+    launch_tile_ranges(ki, pair_cap, &fc->pairs, fb.ranges, ntiles, s);
+    mk.mark(6, s);
+    // ---- stage 4: blend -------------------------------------------------------------
+    launch_blend(fb.gs, vi, fb.ranges, W, H, op, rgb, T, last, work, s);
+    mk.mark(7, s);
+    return ki == fb.tk_a;
+}
+
+}  // namespace fgs

@@ -1,0 +1,105 @@
+// Host-side frame pipeline shared by the plain renderer (runtime.cpp) and the
+// render server (server.cpp): device buffers of one frame, argument checks,
+// and the two halves of a frame's kernel sequence.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <string>
+
+#include "fgs.h"
+#include "fgs_internal.hpp"
+
+namespace fgs {
+
+// One frame's device buffers, sized for a capacity and reused across frames
+// (Sec. 5.3.1: no per-frame allocation once warmed up).
+struct FrameBuffers {
+    size_t capP = 0, capN = 0, capTiles = 0, capPix = 0;
+    // per Gaussian
+    GaussState *gs = nullptr;
+    uint4 *rect = nullptr;
+    uint32_t *count = nullptr;
+    uint2 *mask = nullptr;
+    uint32_t *dkey = nullptr, *dk_b = nullptr, *dv_a = nullptr, *dv_b = nullptr;
+    uint32_t *offsets = nullptr;
+    // per pair (ping-pong for the LSD passes)
+    uint32_t *tk_a = nullptr, *tk_b = nullptr, *tv_a = nullptr, *tv_b = nullptr;
+    bool pairs_owned = true;  // false: the pair arrays live in a caller's arena
+    // per tile / pixel
+    uint2 *ranges = nullptr;
+    float *T = nullptr;
+    uint32_t *last = nullptr;
+
+    size_t gauss_bytes() const {
+        return capP * (sizeof(GaussState) + sizeof(uint4) + sizeof(uint32_t) + sizeof(uint2) + 4 * sizeof(uint32_t)) +
+               (capP + 1) * sizeof(uint32_t);
+    }
+    size_t bytes() const {
+        return gauss_bytes() + (pairs_owned ? capN * 4 * sizeof(uint32_t) : 0) + capTiles * sizeof(uint2) +
+               capPix * (sizeof(float) + sizeof(uint32_t));
+    }
+};
+
+// Radix-sort and scan scratch of one in-flight frame.
+struct SortScratch {
+    uint32_t *rhist = nullptr, *gsum = nullptr, *sums = nullptr;
+    static size_t bytes() {
+        return ((size_t)kSortBlocks * kRadix + (size_t)(kSortBlocks / kSortGroup) * kRadix + kSortBlocks) *
+               sizeof(uint32_t);
+    }
+};
+
+// List of Gaussians whose rectangles exceed kBigTiles tiles.
+struct ChunkList {
+    uint2 *chunks = nullptr;
+    uint32_t *hits = nullptr;
+    uint32_t *mask = nullptr;  // 256-bit hit mask per chunk
+    size_t cap = 0;
+    size_t bytes() const { return cap * (sizeof(uint2) + 9 * sizeof(uint32_t)); }
+};
+
+hipError_t ensure_gauss(FrameBuffers &b, size_t P);
+hipError_t ensure_pairs(FrameBuffers &b, size_t N);
+hipError_t ensure_tiles(FrameBuffers &b, size_t tiles);
+hipError_t ensure_pixels(FrameBuffers &b, size_t pix);
+hipError_t ensure_sort_scratch(SortScratch &s);
+hipError_t ensure_chunks(ChunkList &c, size_t need);
+void free_frame_buffers(FrameBuffers &b);
+void free_sort_scratch(SortScratch &s);
+void free_chunks(ChunkList &c);
+
+// Argument checks shared by every entry point; writes a message to err.
+fgs_status check_args(const fgs_scene *sc, const fgs_camera *cam, int32_t W, int32_t H, const fgs_options *opt,
+                      std::string &err);
+
+DevOptions to_dev(const fgs_options &o);
+DevCamera to_dev(const fgs_camera &c);
+DevScene to_dev(const fgs_scene &s);
+
+// Optional per-stage HIP events (index 0..7 around the stages).
+struct StageMarks {
+    hipEvent_t *ev = nullptr;
+    void mark(int i, hipStream_t s) const {
+        if (ev) (void)hipEventRecord(ev[i], s);
+    }
+};
+
+// Stages 1 and 2a: preprocess with the exact tile count, depth order of the
+// visible Gaussians, scan of the tile counts in depth order.  Ends with an
+// asynchronous copy of the frame counters to host_fc (pinned).
+void enqueue_front(const DevScene &sc, const DevCamera &cam, const DevOptions &op, int W, int H, FrameBuffers &fb,
+                   ChunkList &ch, SortScratch &ss, FrameCounters *fc, FrameCounters *host_fc, hipStream_t s,
+                   const StageMarks &mk);
+
+// Stages 2b to 4: key emission, stable tile sort, tile ranges and blending.
+// Every count is read on the device from fc, and every grid is sized by a
+// capacity, so the sequence holds no host dependency and can be captured in
+// a graph.  P bounds the visible count; fb.capN bounds the pair count.
+// Returns true if the sorted tile ids end in tk_a (else tk_b).
+bool enqueue_back(int W, int H, const DevOptions &op, uint32_t P, FrameBuffers &fb, ChunkList &ch, SortScratch &ss,
+                  FrameCounters *fc, float *rgb, float *T, uint32_t *last, unsigned long long *work, hipStream_t s,
+                  const StageMarks &mk);
+
+}  // namespace fgs

@@ -1,0 +1,710 @@
+// Render server: continuous batching of camera requests over one resident
+// scene (declared in include/fgs.h).
+//
+// Request life cycle, driven by one worker thread that issues all GPU work:
+//   QUEUED  -> FRONT  a free slot runs the first half of the frame on its
+//                     own stream (preprocess, exact tile counts, depth order,
+//                     count scan) and copies the frame counters to the host
+//   FRONT   -> WAIT   the counters arrived: N pairs are known
+//   WAIT    -> BACK   admitted: 16 N bytes (+ headroom) of the byte budget
+//                     back the slot's pair and sort buffers; the second half
+//                     (emission, tile sort, ranges, blend) is a graph captured
+//                     once per (slot, W, H) while the slot's buffers stay put
+//   BACK    -> DONE   the image is complete; the client polls the result
+//   DONE    -> IDLE   the client released the image
+// Admission is FIFO over the waiting requests in arrival order; a request
+// that does not fit may be overtaken by at most max_bypass later ones.
+// Slots keep their pair region between requests (so their graphs stay
+// valid); regions of slots that are not blending are evicted when a waiting
+// request needs the space.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "fgs.h"
+#include "fgs_internal.hpp"
+#include "pipeline.hpp"
+
+using namespace fgs;
+
+namespace {
+
+int64_t now_ns() {
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// First-fit allocator over one device allocation (offsets only).
+class Arena {
+  public:
+    void init(size_t bytes) {
+        size_ = bytes;
+        free_.clear();
+        free_[0] = bytes;
+        used_ = 0;
+    }
+    bool alloc(size_t bytes, size_t *off) {
+        bytes = align_up(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes;
+                const size_t at = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                used_ += bytes;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = align_up(bytes);
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto next = std::next(it);
+        if (next != free_.end() && it->first + it->second == next->first) {
+            it->second += next->second;
+            free_.erase(next);
+        }
+        if (it != free_.begin()) {
+            auto prev = std::prev(it);
+            if (prev->first + prev->second == it->first) {
+                prev->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t largest_free() const {
+        size_t m = 0;
+        for (auto &f : free_) m = std::max(m, f.second);
+        return m;
+    }
+    size_t used() const { return used_; }
+    size_t size() const { return size_; }
+
+  private:
+    std::map<size_t, size_t> free_;
+    size_t size_ = 0, used_ = 0;
+};
+
+struct Request {
+    uint64_t id = 0;
+    fgs_camera cam{};
+    int W = 0, H = 0;
+    int64_t arrival_ns = 0;
+    uint64_t seq = 0;  // submission order
+    float *out = nullptr;  // optional caller copy of the image
+};
+
+enum class SlotState { IDLE, FRONT, WAIT, BACK, DONE };
+
+struct GraphEntry {
+    int W, H;
+    hipGraphExec_t exec;
+};
+
+struct Slot {
+    int idx = 0;
+    SlotState state = SlotState::IDLE;
+    hipStream_t stream = nullptr;
+    hipEvent_t evA = nullptr, evB = nullptr;
+    FrameBuffers fb;
+    ChunkList ch;
+    SortScratch ss;
+    FrameCounters *fc_dev = nullptr, *fc_host = nullptr;
+    float *img = nullptr;
+    // pair region in the arena
+    bool has_region = false;
+    size_t reg_off = 0, reg_bytes = 0;
+    std::vector<GraphEntry> graphs;
+    // current request
+    Request req;
+    int attempts = 0;
+    int bypassed = 0;
+    int64_t start_ns = 0, admit_ns = 0, done_ns = 0;
+    uint32_t V = 0, N = 0;
+};
+
+}  // namespace
+
+struct fgs_server {
+    int device = 0;
+    fgs_scene scene{};
+    DevScene dsc{};
+    fgs_options opt{};
+    DevOptions dop{};
+    fgs_server_config cfg{};
+    std::string err;  // guarded by mu
+    uint8_t *arena_base = nullptr;
+    Arena arena;
+    std::vector<Slot> slots;
+    // shared with client threads
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request> incoming;
+    std::deque<fgs_server_result> done;
+    std::vector<uint64_t> releases;
+    bool stop = false;
+    uint64_t next_seq = 0;
+    fgs_server_stats st{};   // guarded by mu
+    fgs_server_stats wst{};  // the worker's own counters, published into st under mu
+    std::thread worker;
+    bool worker_failed = false;
+};
+
+namespace {
+
+void set_error(fgs_server *srv, const char *msg) {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->err = msg;
+}
+
+void drop_graphs(Slot &s) {
+    for (GraphEntry &g : s.graphs) (void)hipGraphExecDestroy(g.exec);
+    s.graphs.clear();
+}
+
+void drop_region(fgs_server *srv, Slot &s) {
+    if (!s.has_region) return;
+    drop_graphs(s);
+    srv->arena.release(s.reg_off, s.reg_bytes);
+    s.has_region = false;
+    s.reg_bytes = 0;
+    s.fb.tk_a = s.fb.tk_b = s.fb.tv_a = s.fb.tv_b = nullptr;
+    s.fb.capN = 0;
+    srv->wst.region_evictions += 1;
+}
+
+void point_pairs(fgs_server *srv, Slot &s) {
+    const size_t cap = (s.reg_bytes / 16) / 64 * 64;
+    uint32_t *base = reinterpret_cast<uint32_t *>(srv->arena_base + s.reg_off);
+    s.fb.tk_a = base;
+    s.fb.tk_b = base + cap;
+    s.fb.tv_a = base + 2 * cap;
+    s.fb.tv_b = base + 3 * cap;
+    s.fb.capN = cap;
+    s.fb.pairs_owned = false;
+}
+
+size_t bytes_for_pairs(uint32_t N) { return align_up(16 * ((size_t)N + (size_t)N / 8 + 4096)); }
+
+// Try to give slot s a region for its N pairs; evicts cached regions of
+// slots that are not blending.  Returns false if the budget cannot hold it now.
+bool ensure_region(fgs_server *srv, Slot &s) {
+    if (s.has_region && s.reg_bytes / 16 >= (size_t)s.N + 64) return true;
+    const size_t need = bytes_for_pairs(s.N);
+    drop_region(srv, s);
+    size_t off = 0;
+    bool ok = srv->arena.alloc(need, &off);
+    for (size_t i = 0; !ok && i < srv->slots.size(); ++i) {
+        Slot &o = srv->slots[i];
+        if (&o == &s || !o.has_region || o.state == SlotState::BACK) continue;
+        drop_region(srv, o);
+        ok = srv->arena.alloc(need, &off);
+    }
+    if (!ok) return false;
+    s.has_region = true;
+    s.reg_off = off;
+    s.reg_bytes = need;
+    point_pairs(srv, s);
+    srv->wst.region_allocs += 1;
+    srv->wst.peak_bytes_in_use = std::max<int64_t>(srv->wst.peak_bytes_in_use, (int64_t)srv->arena.used());
+    return true;
+}
+
+void start_front(fgs_server *srv, Slot &s) {
+    const DevCamera dcam = to_dev(s.req.cam);
+    enqueue_front(srv->dsc, dcam, srv->dop, s.req.W, s.req.H, s.fb, s.ch, s.ss, s.fc_dev, s.fc_host, s.stream,
+                  StageMarks{});
+    (void)hipEventRecord(s.evA, s.stream);
+    s.state = SlotState::FRONT;
+}
+
+hipError_t start_back(fgs_server *srv, Slot &s) {
+    const int W = s.req.W, H = s.req.H;
+    const uint32_t P = (uint32_t)srv->scene.num_gaussians;
+    if (srv->cfg.use_graphs) {
+        hipGraphExec_t exec = nullptr;
+        for (GraphEntry &g : s.graphs)
+            if (g.W == W && g.H == H) exec = g.exec;
+        if (!exec) {
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamBeginCapture(s.stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return e;
+            enqueue_back(W, H, srv->dop, P, s.fb, s.ch, s.ss, s.fc_dev, s.img, nullptr, nullptr, nullptr, s.stream,
+                         StageMarks{});
+            e = hipStreamEndCapture(s.stream, &graph);
+            if (e != hipSuccess) return e;
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) return e;
+            s.graphs.push_back(GraphEntry{W, H, exec});
+            srv->wst.graphs_captured += 1;
+        }
+        hipError_t e = hipGraphLaunch(exec, s.stream);
+        if (e != hipSuccess) return e;
+        srv->wst.graph_launches += 1;
+    } else {
+        enqueue_back(W, H, srv->dop, P, s.fb, s.ch, s.ss, s.fc_dev, s.img, nullptr, nullptr, nullptr, s.stream,
+                     StageMarks{});
+    }
+    if (s.req.out) {
+        const hipError_t c = hipMemcpyAsync(s.req.out, s.img, 3 * (size_t)W * H * sizeof(float),
+                                            hipMemcpyDeviceToDevice, s.stream);
+        if (c != hipSuccess) return c;
+    }
+    hipError_t e = hipEventRecord(s.evB, s.stream);
+    if (e != hipSuccess) return e;
+    s.state = SlotState::BACK;
+    return hipSuccess;
+}
+
+fgs_server_result make_result(const Slot &s, int32_t status) {
+    fgs_server_result r{};
+    r.id = s.req.id;
+    r.status = status;
+    r.width = s.req.W;
+    r.height = s.req.H;
+    r.slot = s.idx;
+    r.rgb = status == FGS_OK ? s.img : nullptr;
+    r.arrival_ns = s.req.arrival_ns;
+    r.start_ns = s.start_ns;
+    r.admit_ns = s.admit_ns;
+    r.done_ns = s.done_ns;
+    r.visible = s.V;
+    r.pairs = s.N;
+    return r;
+}
+
+void finish(fgs_server *srv, Slot &s, int32_t status) {
+    s.done_ns = now_ns();
+    const fgs_server_result r = make_result(s, status);
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->done.push_back(r);
+        if (status == FGS_OK)
+            srv->st.completed += 1;
+        else
+            srv->st.rejected += 1;
+    }
+    srv->cv_done.notify_all();
+    // a failed request holds no image: its slot is free again at once
+    s.state = status == FGS_OK ? SlotState::DONE : SlotState::IDLE;
+}
+
+void worker_main(fgs_server *srv) {
+    if (hipSetDevice(srv->device) != hipSuccess) {
+        srv->worker_failed = true;
+        return;
+    }
+    std::deque<Request> pending;
+    const int max_bypass = srv->cfg.max_bypass;
+    for (;;) {
+        bool progress = false;
+        bool in_flight = false;
+        {
+            std::unique_lock<std::mutex> lk(srv->mu);
+            for (uint64_t id : srv->releases)
+                for (Slot &s : srv->slots)
+                    if (s.state == SlotState::DONE && s.req.id == id) s.state = SlotState::IDLE;
+            srv->releases.clear();
+            while (!srv->incoming.empty()) {
+                pending.push_back(srv->incoming.front());
+                srv->incoming.pop_front();
+            }
+            if (srv->stop) {
+                // shutting down: queued requests are dropped, finished images
+                // are no longer held for the client
+                pending.clear();
+                for (Slot &s : srv->slots)
+                    if (s.state == SlotState::DONE) s.state = SlotState::IDLE;
+            }
+            for (const Slot &s : srv->slots)
+                in_flight |= (s.state == SlotState::FRONT || s.state == SlotState::WAIT || s.state == SlotState::BACK);
+            if (srv->stop && pending.empty() && !in_flight) return;
+            if (!in_flight && pending.empty()) {
+                srv->cv_work.wait_for(lk, std::chrono::milliseconds(2));
+                continue;
+            }
+        }
+        // 1. start the first half of queued requests on free slots (FIFO)
+        for (Slot &s : srv->slots) {
+            if (pending.empty()) break;
+            if (s.state != SlotState::IDLE) continue;
+            s.req = pending.front();
+            pending.pop_front();
+            s.attempts = 0;
+            s.bypassed = 0;
+            s.start_ns = now_ns();
+            start_front(srv, s);
+            progress = true;
+        }
+        // 2. first halves that finished: their pair counts are known
+        for (Slot &s : srv->slots) {
+            if (s.state != SlotState::FRONT) continue;
+            const hipError_t q = hipEventQuery(s.evA);
+            if (q == hipErrorNotReady) continue;
+            progress = true;
+            if (q != hipSuccess) {
+                set_error(srv, hipGetErrorString(q));
+                finish(srv, s, FGS_ERR_DEVICE);
+                continue;
+            }
+            if ((s.fc_host->error & kErrChunkOverflow) && s.attempts == 0) {
+                // large-Gaussian chunk list too small: grow it (its graphs
+                // reference it) and run the first half again
+                s.attempts += 1;
+                drop_graphs(s);
+                if (ensure_chunks(s.ch, (size_t)s.fc_host->nchunks + (size_t)s.fc_host->nchunks / 8) != hipSuccess) {
+                    finish(srv, s, FGS_ERR_OUT_OF_MEMORY);
+                    continue;
+                }
+                start_front(srv, s);
+                continue;
+            }
+            if (s.fc_host->error & kErrChunkOverflow) {
+                finish(srv, s, FGS_ERR_INTERNAL);
+                continue;
+            }
+            s.V = s.fc_host->visible;
+            s.N = s.fc_host->pairs;
+            if (bytes_for_pairs(s.N) > srv->arena.size()) {
+                finish(srv, s, FGS_ERR_CAPACITY);  // can never fit the budget
+                continue;
+            }
+            s.state = SlotState::WAIT;
+        }
+        // 3. admission: FIFO over waiting requests, bounded bypass
+        {
+            std::vector<Slot *> waiting;
+            for (Slot &s : srv->slots)
+                if (s.state == SlotState::WAIT) waiting.push_back(&s);
+            std::sort(waiting.begin(), waiting.end(), [](Slot *a, Slot *b) { return a->req.seq < b->req.seq; });
+            Slot *blocked = nullptr;  // oldest request that did not fit
+            for (Slot *s : waiting) {
+                if (blocked && blocked->bypassed >= max_bypass) break;
+                if (!ensure_region(srv, *s)) {
+                    if (!blocked) blocked = s;
+                    continue;
+                }
+                if (blocked) {
+                    blocked->bypassed += 1;
+                    srv->wst.bypasses += 1;
+                }
+                s->admit_ns = now_ns();
+                const hipError_t e = start_back(srv, *s);
+                progress = true;
+                if (e != hipSuccess) {
+                    set_error(srv, hipGetErrorString(e));
+                    finish(srv, *s, FGS_ERR_DEVICE);
+                }
+            }
+        }
+        // 4. completed images
+        for (Slot &s : srv->slots) {
+            if (s.state != SlotState::BACK) continue;
+            const hipError_t q = hipEventQuery(s.evB);
+            if (q == hipErrorNotReady) continue;
+            progress = true;
+            if (q != hipSuccess) set_error(srv, hipGetErrorString(q));
+            finish(srv, s, q == hipSuccess ? FGS_OK : FGS_ERR_DEVICE);
+        }
+        if (progress) {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            srv->st.graphs_captured = srv->wst.graphs_captured;
+            srv->st.graph_launches = srv->wst.graph_launches;
+            srv->st.region_allocs = srv->wst.region_allocs;
+            srv->st.region_evictions = srv->wst.region_evictions;
+            srv->st.bypasses = srv->wst.bypasses;
+            srv->st.peak_bytes_in_use = srv->wst.peak_bytes_in_use;
+        } else if (in_flight) {
+            std::this_thread::yield();  // completions are polled: stay on the core
+        } else {
+            // queued work waits for a slot to be released
+            std::unique_lock<std::mutex> lk(srv->mu);
+            srv->cv_work.wait_for(lk, std::chrono::milliseconds(1));
+        }
+    }
+}
+
+fgs_status server_fail(fgs_server *srv, fgs_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (srv) set_error(srv, buf);
+    return s;
+}
+
+thread_local std::string g_server_error_copy;
+
+void free_server(fgs_server *srv) {
+    (void)hipSetDevice(srv->device);
+    (void)hipDeviceSynchronize();
+    for (Slot &s : srv->slots) {
+        drop_graphs(s);
+        s.fb.tk_a = s.fb.tk_b = s.fb.tv_a = s.fb.tv_b = nullptr;  // arena-owned
+        free_frame_buffers(s.fb);
+        free_chunks(s.ch);
+        free_sort_scratch(s.ss);
+        if (s.fc_dev) (void)hipFree(s.fc_dev);
+        if (s.fc_host) (void)hipHostFree(s.fc_host);
+        if (s.img) (void)hipFree(s.img);
+        if (s.evA) (void)hipEventDestroy(s.evA);
+        if (s.evB) (void)hipEventDestroy(s.evB);
+        if (s.stream) (void)hipStreamDestroy(s.stream);
+    }
+    if (srv->arena_base) (void)hipFree(srv->arena_base);
+    delete srv;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t fgs_clock_ns(void) { return now_ns(); }
+
+fgs_status fgs_server_create(int device, const fgs_scene *scene, const fgs_options *opt,
+                             const fgs_server_config *cfg, fgs_server **out) {
+    if (!out) return FGS_ERR_INVALID_ARGUMENT;
+    *out = nullptr;
+    if (!cfg) return FGS_ERR_INVALID_ARGUMENT;
+    if (cfg->budget_bytes < (1 << 20) || cfg->max_inflight < 1 || cfg->max_inflight > 32 || cfg->max_width < 1 ||
+        cfg->max_width > 16384 || cfg->max_height < 1 || cfg->max_height > 16384 || cfg->max_bypass < 0 ||
+        cfg->reserved != 0)
+        return FGS_ERR_INVALID_ARGUMENT;
+    fgs_camera probe{};
+    for (int i = 0; i < 3; ++i) probe.R[4 * i] = 1.0f;
+    probe.fx = probe.fy = 1.0f;
+    probe.near_z = 0.2f;
+    std::string m;
+    if (check_args(scene, &probe, cfg->max_width, cfg->max_height, opt, m) != FGS_OK) return FGS_ERR_INVALID_ARGUMENT;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return FGS_ERR_DEVICE;
+    if (hipSetDevice(device) != hipSuccess) return FGS_ERR_DEVICE;
+
+    fgs_server *srv = new fgs_server();
+    srv->device = device;
+    srv->scene = *scene;
+    srv->dsc = to_dev(*scene);
+    if (opt)
+        srv->opt = *opt;
+    else
+        fgs_default_options(&srv->opt);
+    srv->dop = to_dev(srv->opt);
+    srv->cfg = *cfg;
+    srv->st.budget_bytes = cfg->budget_bytes;
+    // occupancy queries happen outside any graph capture
+    (void)preprocess_grid(1);
+    (void)emit_grid(1);
+
+    const size_t P = (size_t)scene->num_gaussians;
+    const size_t tiles =
+        (size_t)((cfg->max_width + kTile - 1) / kTile) * (size_t)((cfg->max_height + kTile - 1) / kTile);
+    const size_t pix = (size_t)cfg->max_width * cfg->max_height;
+    hipError_t e = hipMalloc((void **)&srv->arena_base, (size_t)cfg->budget_bytes);
+    srv->arena.init((size_t)cfg->budget_bytes / kAlign * kAlign);
+    srv->slots.resize((size_t)cfg->max_inflight);
+    size_t slot_bytes = 0;
+    for (int i = 0; i < cfg->max_inflight && e == hipSuccess; ++i) {
+        Slot &s = srv->slots[(size_t)i];
+        s.idx = i;
+        // default priority (no priority streams)
+        if ((e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking)) != hipSuccess) break;
+        if ((e = hipEventCreateWithFlags(&s.evA, hipEventDisableTiming)) != hipSuccess) break;
+        if ((e = hipEventCreateWithFlags(&s.evB, hipEventDisableTiming)) != hipSuccess) break;
+        if ((e = ensure_gauss(s.fb, P)) != hipSuccess) break;
+        if ((e = ensure_tiles(s.fb, tiles)) != hipSuccess) break;
+        if ((e = ensure_chunks(s.ch, P / 8)) != hipSuccess) break;
+        if ((e = ensure_sort_scratch(s.ss)) != hipSuccess) break;
+        if ((e = hipMalloc((void **)&s.fc_dev, sizeof(FrameCounters))) != hipSuccess) break;
+        if ((e = hipHostMalloc((void **)&s.fc_host, sizeof(FrameCounters), hipHostMallocDefault)) != hipSuccess) break;
+        if ((e = hipMalloc((void **)&s.img, 3 * pix * sizeof(float))) != hipSuccess) break;
+        s.fb.pairs_owned = false;
+        slot_bytes += s.fb.bytes() + s.ch.bytes() + SortScratch::bytes() + 3 * pix * sizeof(float);
+    }
+    if (e != hipSuccess) {
+        free_server(srv);
+        return e == hipErrorOutOfMemory ? FGS_ERR_OUT_OF_MEMORY : FGS_ERR_DEVICE;
+    }
+    srv->st.slot_bytes = (int64_t)slot_bytes;
+    srv->worker = std::thread(worker_main, srv);
+    *out = srv;
+    return FGS_OK;
+}
+
+void fgs_server_destroy(fgs_server *srv) {
+    if (!srv) return;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+        // images still held by the client are released at shutdown
+        for (Slot &s : srv->slots)
+            if (s.state == SlotState::DONE) srv->releases.push_back(s.req.id);
+    }
+    srv->cv_work.notify_all();
+    if (srv->worker.joinable()) srv->worker.join();
+    free_server(srv);
+}
+
+const char *fgs_server_last_error(const fgs_server *srv) {
+    if (!srv) return "server is NULL";
+    fgs_server *m = const_cast<fgs_server *>(srv);
+    std::lock_guard<std::mutex> lk(m->mu);
+    g_server_error_copy = m->err;  // stable for the calling thread
+    return g_server_error_copy.c_str();
+}
+
+fgs_status fgs_server_submit(fgs_server *srv, uint64_t id, const fgs_camera *cam, int32_t W, int32_t H,
+                             int64_t arrival_ns, float *out_rgb) {
+    if (!srv) return FGS_ERR_INVALID_ARGUMENT;
+    std::string m;
+    if (check_args(&srv->scene, cam, W, H, &srv->opt, m) != FGS_OK)
+        return server_fail(srv, FGS_ERR_INVALID_ARGUMENT, "%s", m.c_str());
+    if (W > srv->cfg.max_width || H > srv->cfg.max_height)
+        return server_fail(srv, FGS_ERR_INVALID_ARGUMENT, "request %dx%d exceeds the server's %dx%d", W, H,
+                           srv->cfg.max_width, srv->cfg.max_height);
+    if (srv->worker_failed) return server_fail(srv, FGS_ERR_DEVICE, "worker thread could not start");
+    Request r;
+    r.id = id;
+    r.cam = *cam;
+    r.W = W;
+    r.H = H;
+    r.arrival_ns = arrival_ns;
+    r.out = out_rgb;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if (srv->stop) {
+            srv->err = "server is stopping";
+            return FGS_ERR_INVALID_ARGUMENT;
+        }
+        r.seq = srv->next_seq++;
+        srv->incoming.push_back(r);
+        srv->st.submitted += 1;
+    }
+    srv->cv_work.notify_one();
+    return FGS_OK;
+}
+
+int32_t fgs_server_poll(fgs_server *srv, fgs_server_result *out, int32_t max, int64_t wait_ns) {
+    if (!srv || (!out && max > 0) || max < 0) return -(int32_t)FGS_ERR_INVALID_ARGUMENT;
+    std::unique_lock<std::mutex> lk(srv->mu);
+    if (srv->done.empty() && wait_ns > 0)
+        srv->cv_done.wait_for(lk, std::chrono::nanoseconds(wait_ns), [&] { return !srv->done.empty(); });
+    int32_t k = 0;
+    while (k < max && !srv->done.empty()) {
+        out[k++] = srv->done.front();
+        srv->done.pop_front();
+    }
+    return k;
+}
+
+fgs_status fgs_server_release(fgs_server *srv, uint64_t id) {
+    if (!srv) return FGS_ERR_INVALID_ARGUMENT;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->releases.push_back(id);
+    }
+    srv->cv_work.notify_one();
+    return FGS_OK;
+}
+
+fgs_status fgs_server_get_stats(fgs_server *srv, fgs_server_stats *out) {
+    if (!srv || !out) return FGS_ERR_INVALID_ARGUMENT;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    *out = srv->st;
+    return FGS_OK;
+}
+
+fgs_status fgs_server_replay(fgs_server *srv, const fgs_trace_request *trace, int64_t n,
+                             fgs_server_result *results) {
+    if (!srv || (n > 0 && (!trace || !results)) || n < 0) return FGS_ERR_INVALID_ARGUMENT;
+    std::map<uint64_t, int64_t> index;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!index.emplace(trace[i].id, i).second)
+            return server_fail(srv, FGS_ERR_INVALID_ARGUMENT, "duplicate request id in the trace");
+        if (i > 0 && trace[i].arrival_offset_ns < trace[i - 1].arrival_offset_ns)
+            return server_fail(srv, FGS_ERR_INVALID_ARGUMENT, "trace arrivals are not in order");
+    }
+    const int64_t t0 = now_ns() + 1000000;  // 1 ms to set up
+    int64_t next = 0, got = 0;
+    std::vector<fgs_server_result> buf(64);
+    while (got < n) {
+        const int64_t t = now_ns();
+        while (next < n && t0 + trace[next].arrival_offset_ns <= t) {
+            const fgs_trace_request &q = trace[next];
+            const fgs_status s =
+                fgs_server_submit(srv, q.id, &q.cam, q.width, q.height, t0 + q.arrival_offset_ns, nullptr);
+            if (s != FGS_OK) return s;
+            ++next;
+        }
+        int64_t wait = 0;
+        if (next < n) wait = std::max<int64_t>(0, t0 + trace[next].arrival_offset_ns - now_ns());
+        else wait = 5000000;
+        wait = std::min<int64_t>(wait, 200000);  // stay responsive to arrivals
+        const int32_t k = fgs_server_poll(srv, buf.data(), (int32_t)buf.size(), wait);
+        if (k < 0) return (fgs_status)(-k);
+        for (int32_t j = 0; j < k; ++j) {
+            auto it = index.find(buf[(size_t)j].id);
+            if (it == index.end()) continue;  // not from this trace
+            results[it->second] = buf[(size_t)j];
+            results[it->second].rgb = nullptr;  // released at once
+            if (buf[(size_t)j].status == FGS_OK) (void)fgs_server_release(srv, buf[(size_t)j].id);
+            ++got;
+        }
+    }
+    return FGS_OK;
+}
+
+fgs_status fgs_replay_plain(fgs_context *ctx, const fgs_scene *scene, const fgs_options *opt,
+                            const fgs_trace_request *trace, int64_t n, float *rgb_scratch,
+                            fgs_server_result *results, void *stream) {
+    if (!ctx || (n > 0 && (!trace || !results || !rgb_scratch)) || n < 0) return FGS_ERR_INVALID_ARGUMENT;
+    for (int64_t i = 1; i < n; ++i)
+        if (trace[i].arrival_offset_ns < trace[i - 1].arrival_offset_ns) return FGS_ERR_INVALID_ARGUMENT;
+    const int64_t t0 = now_ns() + 1000000;
+    for (int64_t i = 0; i < n; ++i) {
+        const fgs_trace_request &q = trace[i];
+        const int64_t arrive = t0 + q.arrival_offset_ns;
+        while (now_ns() < arrive) std::this_thread::yield();
+        fgs_server_result &r = results[i];
+        r = fgs_server_result{};
+        r.id = q.id;
+        r.width = q.width;
+        r.height = q.height;
+        r.slot = 0;
+        r.arrival_ns = arrive;
+        r.start_ns = now_ns();
+        fgs_stats stt{};
+        fgs_status s = fgs_render(ctx, scene, &q.cam, q.width, q.height, opt, rgb_scratch, nullptr, nullptr, nullptr,
+                                  &stt, stream);
+        r.admit_ns = now_ns();  // the render call returns once the second half is enqueued
+        if (s == FGS_OK && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) s = FGS_ERR_DEVICE;
+        r.done_ns = now_ns();
+        r.status = s;
+        r.visible = stt.visible;
+        r.pairs = stt.pairs;
+        if (s != FGS_OK) return s;
+    }
+    return FGS_OK;
+}
+
+}  // extern "C"

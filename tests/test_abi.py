@@ -93,6 +93,19 @@ def test_null_arguments_rejected_without_device():
     g = B.FgsSceneGrad(0, None, None, None, None, None)
     st = B.lib().fgs_render_backward(None, None, C.byref(sc), C.byref(cam), C.byref(op), None, C.byref(g), None)
     assert st == B.FGS_ERR_INVALID_ARGUMENT
+    cfg = B.FgsServerConfig(1 << 30, 4, 64, 64, 2, 1, 0)
+    h = C.c_void_p()
+    assert B.lib().fgs_server_create(0, C.byref(sc), C.byref(op), None, C.byref(h)) == B.FGS_ERR_INVALID_ARGUMENT
+    bad = B.FgsServerConfig(1 << 30, 0, 64, 64, 2, 1, 0)  # no slots
+    assert B.lib().fgs_server_create(0, C.byref(sc), C.byref(op), C.byref(bad), C.byref(h)) == \
+        B.FGS_ERR_INVALID_ARGUMENT
+    assert B.lib().fgs_server_create(0, None, C.byref(op), C.byref(cfg), C.byref(h)) == B.FGS_ERR_INVALID_ARGUMENT
+    assert not h.value
+    assert B.lib().fgs_server_submit(None, 1, C.byref(cam), 8, 8, 0, None) == B.FGS_ERR_INVALID_ARGUMENT
+    assert B.lib().fgs_server_poll(None, None, 0, 0) < 0
+    assert B.lib().fgs_server_release(None, 1) == B.FGS_ERR_INVALID_ARGUMENT
+    B.lib().fgs_server_destroy(None)
+    assert B.lib().fgs_clock_ns() > 0
     assert B.lib().fgs_frame_release(None, None) == B.FGS_OK
     assert B.lib().fgs_frame_field_bytes(None, 0) == 0
     assert B.lib().fgs_scratch_bytes(None) == 0

@@ -1,0 +1,151 @@
+"""GPU tests of the render server: every served image equals the same
+request rendered alone by the plain renderer (bit for bit: the kernels are
+deterministic and the graphs replay the same kernel sequence), under a byte
+budget small enough that requests wait for admission and regions are
+evicted; graph replays stay correct across repeated use of a slot; requests
+that can never fit the budget are rejected; trace replay through the server
+and the plain renderer completes every request."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2408_07967_amd import scenes
+    from paper_2408_07967_amd.render import GaussianScene, Renderer
+    sc = scenes.make_scene("serve", P=400_000)
+    gsc = GaussianScene.from_numpy(sc)
+    R = Renderer()
+    yield scenes, gsc, R
+    R.close()
+
+
+def _alone(R, gsc, cam, W, H, opts):
+    out = R.render(gsc, cam, W, H, opts)
+    return out["rgb"].clone(), out["stats"]["pairs"]
+
+
+def _serve_all(srv, reqs, gsc):
+    import torch
+    outs = {}
+    for rid, cam, W, H in reqs:
+        outs[rid] = torch.empty(3 * W * H, dtype=torch.float32, device="cuda")
+        srv.submit(rid, cam, W, H, out=outs[rid])
+    got = {}
+    while len(got) < len(reqs):
+        for r in srv.poll(wait_s=0.5):
+            got[r["id"]] = r
+            srv.release(r["id"])
+    torch.cuda.synchronize()
+    return got, outs
+
+
+def test_served_images_equal_alone_under_a_tight_budget(setup):
+    import torch
+    from paper_2408_07967_amd.serve import RenderServer
+    scenes, gsc, R = setup
+    rng = np.random.default_rng(11)
+    reqs = []
+    for i in range(14):
+        cam = scenes.serve_pose(rng)
+        reqs.append((i, cam, cam.W, cam.H))
+    print(f"[serve] {len(reqs)} requests, sizes {[r[2] for r in reqs]}", flush=True)
+    alone = {rid: _alone(R, gsc, cam, W, H, None) for rid, cam, W, H in reqs}
+    torch.cuda.synchronize()
+    biggest = max(p for _, p in alone.values())
+    # room for about two of the largest requests at once
+    budget = int(2.2 * 16 * (biggest * 9 // 8 + 4096))
+    srv = RenderServer(gsc, budget_bytes=budget, max_inflight=5, max_bypass=2)
+    try:
+        got, outs = _serve_all(srv, reqs, gsc)
+        st = srv.stats()
+    finally:
+        srv.close()
+    print(f"[serve] stats {st}", flush=True)
+    for rid, cam, W, H in reqs:
+        r = got[rid]
+        assert r["status"] == 0, r
+        assert r["pairs"] == alone[rid][1]
+        assert r["arrival_ns"] <= r["start_ns"] <= r["admit_ns"] <= r["done_ns"]
+        img = outs[rid].view(3, H, W)
+        assert torch.equal(img, alone[rid][0]), f"request {rid} ({W}x{H}) differs from the image rendered alone"
+    assert st["completed"] == len(reqs)
+    assert st["peak_bytes_in_use"] <= budget
+    assert st["graphs_captured"] >= 1 and st["graph_launches"] == len(reqs)
+
+
+def test_graph_replays_on_one_slot_match_eager(setup):
+    """One slot, the same resolutions again and again: each replay of a
+    captured graph is checked against the eager renderer, with eager work in
+    between."""
+    import torch
+    from paper_2408_07967_amd.serve import RenderServer
+    scenes, gsc, R = setup
+    rng = np.random.default_rng(12)
+    cams = [scenes.serve_pose(rng) for _ in range(3)]
+    srv = RenderServer(gsc, budget_bytes=2 << 30, max_inflight=1)
+    try:
+        rid = 0
+        for rep in range(3):
+            for cam in cams:
+                ref, _ = _alone(R, gsc, cam, cam.W, cam.H, None)
+                got, outs = _serve_all(srv, [(rid, cam, cam.W, cam.H)], gsc)
+                assert got[rid]["status"] == 0
+                assert torch.equal(outs[rid].view(3, cam.H, cam.W), ref), (rep, rid)
+                rid += 1
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert st["graph_launches"] == 9
+    assert st["graphs_captured"] <= 9
+
+
+def test_direct_launch_mode_and_capacity_rejection(setup):
+    import torch
+    from paper_2408_07967_amd import binding as B
+    from paper_2408_07967_amd.serve import RenderServer
+    scenes, gsc, R = setup
+    rng = np.random.default_rng(13)
+    cam = scenes.serve_pose(rng)
+    ref, pairs = _alone(R, gsc, cam, cam.W, cam.H, None)
+    assert pairs * 16 > (1 << 20)
+    srv = RenderServer(gsc, budget_bytes=1 << 20, max_inflight=2, use_graphs=False)
+    try:
+        got, _ = _serve_all(srv, [(0, cam, cam.W, cam.H)], gsc)
+        assert got[0]["status"] == B.FGS_ERR_CAPACITY
+        assert srv.stats()["rejected"] == 1
+    finally:
+        srv.close()
+    srv = RenderServer(gsc, budget_bytes=2 << 30, max_inflight=2, use_graphs=False)
+    try:
+        got, outs = _serve_all(srv, [(1, cam, cam.W, cam.H)], gsc)
+        assert got[1]["status"] == 0
+        assert torch.equal(outs[1].view(3, cam.H, cam.W), ref)
+        assert srv.stats()["graph_launches"] == 0
+    finally:
+        srv.close()
+
+
+def test_trace_replay_server_and_plain(setup):
+    from paper_2408_07967_amd.serve import RenderServer, make_trace, replay_plain, latency_summary
+    scenes, gsc, R = setup
+    trace = make_trace(rate_hz=150.0, seconds=0.5, seed=9)
+    print(f"[serve] trace of {len(trace)} requests", flush=True)
+    srv = RenderServer(gsc, budget_bytes=4 << 30, max_inflight=4)
+    try:
+        res = srv.replay(trace)
+    finally:
+        srv.close()
+    plain = replay_plain(R, gsc, None, trace)
+    for a, b, q in zip(res, plain, trace):
+        assert a["id"] == q["id"] and b["id"] == q["id"]
+        assert a["status"] == 0 and b["status"] == 0
+        assert a["pairs"] == b["pairs"]
+        assert a["done_ns"] >= a["arrival_ns"] and b["done_ns"] >= b["arrival_ns"]
+    print("[serve] server", latency_summary(res), flush=True)
+    print("[serve] plain ", latency_summary(plain), flush=True)
