@@ -77,6 +77,56 @@ def cpu_baseline(scene, cam, W, H, opts):
                                       f"{dt:.2f} s")
 
 
+SERVE_BUDGET = 3 << 30   # pair and sort buffers of admitted requests
+SERVE_SLOTS = 6
+
+
+def serving_leg(args):
+    """Serving workload: resident 6M-Gaussian scene of the large-scene
+    distributions, Poisson camera requests on the 200 m orbit with mixed
+    resolutions, replayed natively through the render server (continuous
+    batching, byte-budget admission, graph replay) and through the plain
+    one-request-at-a-time renderer on the same GPU."""
+    import torch
+    from paper_2408_07967_amd import scenes
+    from paper_2408_07967_amd.render import GaussianScene, Renderer
+    from paper_2408_07967_amd.serve import RenderServer, make_trace, replay_plain, latency_summary
+    t0 = time.perf_counter()
+    sc = scenes.make_scene("serve")
+    gsc = GaussianScene.from_numpy(sc, "cuda:0")
+    del sc
+    trace = make_trace(args.serve_rate, args.serve_seconds, seed=5)
+    warm = make_trace(400.0, 0.25, seed=6)
+    log(f"[bench] serving: P={gsc.P}, {len(trace)} requests over {args.serve_seconds:.0f} s at "
+        f"{args.serve_rate:.0f}/s (setup {time.perf_counter() - t0:.1f}s)")
+    R = Renderer(0)
+    replay_plain(R, gsc, None, warm)
+    plain = replay_plain(R, gsc, None, trace)
+    ps = latency_summary(plain)
+    log(f"[bench] plain renderer: {ps}")
+    R.close()
+    torch.cuda.synchronize()
+    srv = RenderServer(gsc, budget_bytes=SERVE_BUDGET, max_inflight=SERVE_SLOTS, max_bypass=4)
+    try:
+        srv.replay(warm)
+        res = srv.replay(trace)
+        st = srv.stats()
+    finally:
+        srv.close()
+    ss = latency_summary(res)
+    log(f"[bench] server: {ss} stats {st}")
+    rnd = lambda d: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
+    return dict(workload=f"serve-6M-gaussians-poisson{args.serve_rate:.0f}-{args.serve_seconds:.0f}s-"
+                         f"720p-1080p-1440p-2160p",
+                requests=len(trace), server=rnd(ss), plain=rnd(ps),
+                p50_ratio_plain_over_server=round(ps["p50_ms"] / ss["p50_ms"], 3),
+                p99_ratio_plain_over_server=round(ps["p99_ms"] / ss["p99_ms"], 3),
+                budget_bytes=SERVE_BUDGET, slots=SERVE_SLOTS,
+                peak_bytes_in_use=st["peak_bytes_in_use"], graphs_captured=st["graphs_captured"],
+                graph_launches=st["graph_launches"], bypasses=st["bypasses"],
+                region_evictions=st["region_evictions"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +135,10 @@ def main():
     ap.add_argument("--workload", default="city4k", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-work-count", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="length of the Poisson request trace (the full serving workload is 60 s)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, run one device copy of 256 MiB (read 256 MiB, write 256 MiB) "
                          "whose FETCH_SIZE / WRITE_SIZE counters scale the blend kernel's counters")
@@ -161,15 +215,20 @@ def main():
         cpu = cpu_baseline(sc, cam, W, H, opts)
         log(f"[bench] cpu baseline {cpu}")
 
+    R.close()
+    del gsc, out
+    serving = None
+    if not args.no_serve:
+        serving = serving_leg(args)
+
     res = dict(metric=METRIC, value=round(fps, 3), unit="frames/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(dt / args.steps * 1e3, 4), higher_is_better=True,
                scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
                config=dict(workload=wl["name"], gaussians=sc.P, width=W, height=H, sh_degree=sc.sh_degree,
                            tile=16, visible=int(stats["visible"]), pairs=int(stats["pairs"]),
                            pairs_per_s=round(stats["pairs"] * fps, 1), stage_ms=stage_ms),
-               roofline=roof, cpu_baseline=cpu)
+               roofline=roof, cpu_baseline=cpu, serving=serving)
     print(json.dumps(res), flush=True)
-    R.close()
 
 
 if __name__ == "__main__":
