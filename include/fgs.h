@@ -96,7 +96,10 @@ typedef struct {
     float bg[3];     /* background colour, black by default                        */
     int32_t cap_3sigma; /* 1: extent k^2 = min(9, 2 ln(o / tau)) (Eq. 1-3)          */
     int32_t binning;    /* 0: exact ellipse/tile test (Alg. 3); 1: every tile of the
-                           tight box (test mode, same image)                        */
+                           tight box; 2: every tile of the square box of the 3 sigma
+                           circle, radius ceil(3 sqrt(lambda_max)) (the 3DGS binning
+                           of Alg. 1 / Alg. 2).  1 and 2 are comparison modes: more
+                           pairs, the same image                                     */
 } fgs_options;
 
 typedef struct {
@@ -104,7 +107,8 @@ typedef struct {
     int64_t pairs;     /* Gaussian-tile key/value pairs emitted          */
     int32_t tiles_x, tiles_y;
     int32_t sort_passes;
-    int32_t reserved;
+    int32_t big_chunks; /* 256-tile chunks of the rectangles of more than 64
+                           tiles, tested by workgroups across the GPU        */
 } fgs_stats;
 
 /* ---- context --------------------------------------------------------- */
@@ -161,6 +165,31 @@ size_t fgs_scratch_bytes(const fgs_context *ctx);
 fgs_status fgs_render(fgs_context *ctx, const fgs_scene *scene, const fgs_camera *cam, int32_t W, int32_t H,
                       const fgs_options *opt, float *out_rgb, float *out_T, uint32_t *out_last,
                       fgs_frame **saved, fgs_stats *stats, void *stream);
+
+/* ---- prepared (resident) scenes ------------------------------------------ */
+
+/* The paper moves preprocessing shared by the viewpoints of one scene to an
+ * initial stage (Sec. 5.3.1).  fgs_prepare_scene computes, once, the
+ * view-independent part of every Gaussian: opacity (0 for a Gaussian that can
+ * never be visible), 3D covariance, extent k^2 and log2 opacity, and the SH
+ * coefficients Gaussian-major, so a frame reads 16 bytes for every Gaussian,
+ * 32 more for those in front of the camera and one contiguous run of SH for
+ * the visible ones.  Device memory owned by the context: 48 B + 4 ceil4(3 (D+1)^2)
+ * B per Gaussian (240 B at degree 3).  It depends on the scene's values
+ * (copy of the fgs_scene struct kept; the planes must stay valid and
+ * unchanged for backward passes) and on opt->alpha_min and opt->cap_3sigma.
+ * Frames rendered from it are bit-identical to fgs_render of the scene.
+ * Enqueued on `stream`. */
+typedef struct fgs_prepared fgs_prepared;
+fgs_status fgs_prepare_scene(fgs_context *ctx, const fgs_scene *scene, const fgs_options *opt, fgs_prepared **out,
+                             void *stream);
+/* Waits for the device, then frees the precompute (NULL is ignored). */
+fgs_status fgs_prepared_release(fgs_context *ctx, fgs_prepared *prepared);
+/* fgs_render from a prepared scene.  opt: NULL means defaults; its
+ * alpha_min and cap_3sigma must equal those of the preparation. */
+fgs_status fgs_render_prepared(fgs_context *ctx, const fgs_prepared *prepared, const fgs_camera *cam, int32_t W,
+                               int32_t H, const fgs_options *opt, float *out_rgb, float *out_T, uint32_t *out_last,
+                               fgs_frame **saved, fgs_stats *stats, void *stream);
 
 /* ---- backward ----------------------------------------------------------- */
 
@@ -254,8 +283,9 @@ fgs_status fgs_frame_stats(const fgs_frame *frame, fgs_stats *stats);
  * ones.  The second half (emission, tile sort, ranges, blend) then runs as
  * a hipGraph captured once per (slot, resolution) and replayed.  Requests
  * in different slots overlap on the device.  One worker thread owned by the
- * server issues all of its GPU work.  Images are bit-identical to fgs_render
- * of the same request alone. */
+ * server issues all of its GPU work.  The server keeps the scene's
+ * view-independent precompute (see fgs_prepare_scene).  Images are
+ * bit-identical to fgs_render of the same request alone. */
 typedef struct fgs_server fgs_server;
 
 typedef struct {
@@ -288,7 +318,8 @@ typedef struct {
     int64_t region_allocs, region_evictions, bypasses;
     int64_t peak_bytes_in_use;  /* of the budget                                       */
     int64_t budget_bytes;
-    int64_t slot_bytes;         /* per-slot buffers outside the budget (all slots)     */
+    int64_t slot_bytes;         /* buffers outside the budget: all slots and the
+                                   scene's view-independent precompute             */
 } fgs_server_stats;
 
 /* Monotonic clock (ns) of the server's timestamps. */

@@ -274,8 +274,22 @@ static int FN(orc_gauss)(const TYPE(orc_scene) *sc, int64_t g, const TYPE(orc_ca
     REAL k2 = R_EXTENT(o, op->alpha_min, op->cap_3sigma);
     /* rectangle tightly tangent to the ellipse (Sec. 4.1): half-extents
      * k sqrt(Sigma'_xx), k sqrt(Sigma'_yy), taken over pixel samples */
-    REAL hx = R_SQRT(k2 * ca);
-    REAL hy = R_SQRT(k2 * cc);
+    REAL hx, hy;
+    if (op->binning == 2) {
+        /* comparison mode: the square box of the circle of radius
+         * ceil(3 sqrt(lambda_max)) of Sigma' (Alg. 1, Eq. 1), every tile of it
+         * (Alg. 2); the per-pixel rule, and so the image, is unchanged
+         * (reading: the box is taken over pixel samples like the tight one) */
+        REAL mid = (REAL)0.5 * (ca + cc);
+        REAL disc = mid * mid - det;
+        if (disc < (REAL)0) disc = (REAL)0;
+        REAL lam = mid + R_SQRT(disc);
+        hx = R_CEIL((REAL)3 * R_SQRT(lam));
+        hy = hx;
+    } else {
+        hx = R_SQRT(k2 * ca);
+        hy = R_SQRT(k2 * cc);
+    }
     REAL xlo = FN(orc_clamp)((u - hx) - (REAL)0.5, (REAL)-1, (REAL)W);
     REAL xhi = FN(orc_clamp)((u + hx) - (REAL)0.5, (REAL)-1, (REAL)W);
     REAL ylo = FN(orc_clamp)((v - hy) - (REAL)0.5, (REAL)-1, (REAL)H);
@@ -313,7 +327,7 @@ static int FN(orc_gauss)(const TYPE(orc_scene) *sc, int64_t g, const TYPE(orc_ca
     int cnt = 0;
     for (int ty_ = iv[I_TY0]; ty_ <= iv[I_TY1]; ++ty_)
         for (int tx_ = iv[I_TX0]; tx_ <= iv[I_TX1]; ++tx_)
-            cnt += (op->binning == 1) ? 1 : FN(orc_tile_hit)(s, tx_, ty_, W, H);
+            cnt += (op->binning != 0) ? 1 : FN(orc_tile_hit)(s, tx_, ty_, W, H);
     iv[I_COUNT] = cnt;
     return 1;
 }
@@ -363,7 +377,7 @@ void FN(orc_pairs)(const TYPE(orc_scene) *sc, int W, int H, const TYPE(orc_optio
         if (!iv[I_VALID]) continue;
         for (int ty = iv[I_TY0]; ty <= iv[I_TY1]; ++ty)
             for (int tx = iv[I_TX0]; tx <= iv[I_TX1]; ++tx)
-                if (op->binning == 1 || FN(orc_tile_hit)(state + g * S_N, tx, ty, W, H))
+                if (op->binning != 0 || FN(orc_tile_hit)(state + g * S_N, tx, ty, W, H))
                     cnt[(int64_t)ty * tiles_x + tx + 1]++;
     }
     for (int64_t t = 0; t < ntiles; ++t) cnt[t + 1] += cnt[t];
@@ -375,7 +389,7 @@ void FN(orc_pairs)(const TYPE(orc_scene) *sc, int W, int H, const TYPE(orc_optio
         if (!iv[I_VALID]) continue;
         for (int ty = iv[I_TY0]; ty <= iv[I_TY1]; ++ty)
             for (int tx = iv[I_TX0]; tx <= iv[I_TX1]; ++tx)
-                if (op->binning == 1 || FN(orc_tile_hit)(state + g * S_N, tx, ty, W, H)) {
+                if (op->binning != 0 || FN(orc_tile_hit)(state + g * S_N, tx, ty, W, H)) {
                     int64_t t = (int64_t)ty * tiles_x + tx;
                     int64_t at = cur[t]++;
                     if (at < npairs) {

@@ -34,7 +34,7 @@ typedef struct {
     REAL jac_clip;  /* 1.3, reading */
     REAL bg[3];
     int32_t cap_3sigma; /* 1: k^2 = min(9, 2 ln(o/tau)) (Sec. 4.1) */
-    int32_t binning;    /* 0 exact (Alg. 3), 1 tight box only */
+    int32_t binning;    /* 0 exact (Alg. 3), 1 tight box only, 2 3 sigma square box (Alg. 1) */
 } TYPE(orc_options);
 
 /* ---- per-Gaussian state ------------------------------------------------ */

@@ -45,7 +45,7 @@ class FgsOptions(C.Structure):
 
 class FgsStats(C.Structure):
     _fields_ = [("visible", C.c_int64), ("pairs", C.c_int64), ("tiles_x", C.c_int32), ("tiles_y", C.c_int32),
-                ("sort_passes", C.c_int32), ("reserved", C.c_int32)]
+                ("sort_passes", C.c_int32), ("big_chunks", C.c_int32)]
 
 
 class FgsTimings(C.Structure):
@@ -103,6 +103,12 @@ PROTOTYPES = {
     "fgs_frame_stats": (C.c_int, [C.c_void_p, C.POINTER(FgsStats)]),
     "fgs_set_instrumentation": (C.c_int, [C.c_void_p, C.c_int]),
     "fgs_get_instrumentation": (C.c_int, [C.c_void_p, C.POINTER(FgsTimings)]),
+    "fgs_prepare_scene": (C.c_int, [C.c_void_p, C.POINTER(FgsScene), C.POINTER(FgsOptions),
+                                    C.POINTER(C.c_void_p), C.c_void_p]),
+    "fgs_prepared_release": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "fgs_render_prepared": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(FgsCamera), C.c_int32, C.c_int32,
+                                      C.POINTER(FgsOptions), C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.POINTER(C.c_void_p), C.POINTER(FgsStats), C.c_void_p]),
     "fgs_clock_ns": (C.c_int64, []),
     "fgs_server_create": (C.c_int, [C.c_int, C.POINTER(FgsScene), C.POINTER(FgsOptions),
                                     C.POINTER(FgsServerConfig), C.POINTER(C.c_void_p)]),

@@ -1,13 +1,15 @@
 // Per-pixel evaluation shared by the blend and its adjoint.  Both must take
-// the same contribution and clamp decisions bit for bit, so the quadratic
-// form and the alpha are written once, with explicit multiply-adds.
+// the same contribution and clamp decisions bit for bit, so the staged
+// coefficients and the exponent are written once, with explicit multiply-adds.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
+#include "fgs_internal.hpp"
+
 namespace fgs {
 
-constexpr float kNegHalfLog2e = -0.72134752044448170f;  // -log2(e) / 2
+constexpr float kHalfLog2e = 0.72134752044448170f;  // log2(e) / 2
 
 // Conservative ellipse / rectangle test used only to skip work: the
 // rectangle [X0, X1] x [Y0, Y1] in pixel-sample coordinates (Alg. 3 with the
@@ -39,16 +41,37 @@ __device__ __forceinline__ bool rect_hit(float u, float v, float A, float B, flo
     return hit;
 }
 
-// q = A dx^2 + 2B dx dy + C dy^2 with twoB = 2B, as C dy^2 + dx (A dx + 2B dy).
-__device__ __forceinline__ float conic_q(float A, float twoB, float C, float dx, float dy) {
-    const float t = fmaf(A, dx, twoB * dy);
-    return fmaf(C * dy, dy, dx * t);
+// Staged form of a Gaussian for the pixel loop.  With c = log2(e) / 2 the
+// base-2 exponent of o exp(-q/2) is (Sec. 5.3.2, exponent in log form)
+//     E = log2 o - c q = log2 o + A' dx^2 + B2' dx dy + C' dy^2,
+// A' = -c A, B2' = -2 c B, C' = -c C, and the pixel lies in the opacity-aware
+// extent (q <= k^2) iff E >= thr = log2 o - c k^2.
+//   f0 = (u, v, A', B2')   f1 = (C', thr, log2 o, r)   f2 = (g, b)
+__device__ __forceinline__ void stage_gauss(const GaussState &s, float4 &f0, float4 &f1, float2 &f2) {
+    const float log2o = s.f1.z;
+    f0 = make_float4(s.f0.x, s.f0.y, -kHalfLog2e * s.f0.z, -2.0f * kHalfLog2e * s.f0.w);
+    f1 = make_float4(-kHalfLog2e * s.f1.x, fmaf(-kHalfLog2e, s.f1.y, log2o), log2o, s.f1.w);
+    f2 = make_float2(s.f2.x, s.f2.y);
 }
 
-// o exp(-q/2) = 2^(log2 o - q log2(e) / 2) (Sec. 5.3.2: exponent in log form),
-// before the alpha_max clamp.
-__device__ __forceinline__ float gauss_alpha(float q, float log2o) {
-    return __builtin_amdgcn_exp2f(fmaf(q, kNegHalfLog2e, log2o));
+// Row terms shared by the pixels of one row (same dy).
+struct RowTerms {
+    float b2dy;  // B2' dy
+    float base;  // C' dy^2 + log2 o
+};
+
+__device__ __forceinline__ RowTerms row_terms(const float4 &f0, const float4 &f1, float py) {
+    const float dy = py - f0.y;
+    RowTerms r;
+    r.b2dy = f0.w * dy;
+    r.base = fmaf(f1.x * dy, dy, f1.z);
+    return r;
+}
+
+// E at pixel-sample x for the row terms r: dx (A' dx + B2' dy) + C' dy^2 + log2 o.
+__device__ __forceinline__ float exponent_at(const float4 &f0, const RowTerms &r, float px) {
+    const float dx = px - f0.x;
+    return fmaf(dx, fmaf(f0.z, dx, r.b2dy), r.base);
 }
 
 }  // namespace fgs

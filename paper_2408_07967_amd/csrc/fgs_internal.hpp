@@ -35,6 +35,14 @@ struct DevScene {
     int D;
 };
 
+// View-independent precompute of a resident scene (see launch_prepare).
+struct DevPrepared {
+    const float4 *pos_o;  // (x, y, z, opacity); opacity 0: never visible
+    const float4 *cov;    // 2 per Gaussian: (S00, S01, S02, S11), (S12, S22, k^2, log2 o)
+    const float *sh;      // Gaussian-major SH, sh_stride floats per Gaussian
+    int sh_stride;
+};
+
 // Per-Gaussian state for the blend, 48 bytes = 3 x float4.
 //   f0 = (u, v, A, B)   f1 = (C, k2, log2 o, r)   f2 = (g, b, depth, o)
 struct alignas(16) GaussState {
@@ -77,9 +85,15 @@ unsigned emit_grid(uint32_t visible);
 // chunk_cap; on overflow the error bit kErrChunkOverflow is set and the host
 // renders the frame again with a larger list) and get count 0,
 // mask = (0, first chunk).
-void launch_preprocess(const DevScene &sc, const DevCamera &cam, const DevOptions &op, int W, int H,
-                       GaussState *gs, uint4 *rect, uint32_t *count, uint2 *mask, uint32_t *dkey, uint2 *chunks,
-                       uint32_t chunk_cap, FrameCounters *fc, hipStream_t s);
+// pp: NULL (raw parameters) or the scene's precompute.
+void launch_preprocess(const DevScene &sc, const DevPrepared *pp, const DevCamera &cam, const DevOptions &op,
+                       int W, int H, GaussState *gs, uint4 *rect, uint32_t *count, uint2 *mask, uint32_t *dkey,
+                       uint2 *chunks, uint32_t chunk_cap, FrameCounters *fc, hipStream_t s);
+
+// View-independent precompute (opacity, 3D covariance, k^2, log2 opacity,
+// Gaussian-major SH) for options op (alpha_min and cap_3sigma).
+void launch_prepare(const DevScene &sc, const DevOptions &op, float4 *pos_o, float4 *cov, float *sh, int sh_stride,
+                    hipStream_t s);
 
 // Exact tile counts of the chunked Gaussians: per-chunk hit masks and counts,
 // atomic per-Gaussian sums.

@@ -6,8 +6,9 @@
 // cites among related work).
 //
 // k_blend_bwd: one 256-thread workgroup per tile and one wavefront per 8 x 8
-// quadrant, as in the forward blend.  Each pixel walks its tile list back to
-// front from its last contributor:
+// quadrant, with the forward's staged coefficients and exponent (so both take
+// the same contribution and clamp decisions).  Each pixel walks its tile list
+// back to front from its last contributor:
 //     T_n = T_{n+1} / (1 - a_n)
 //     dL/dc_n     = g . a_n T_n                        (g = dL/dRGB of the pixel)
 //     dL/da_n     = T_n g . (c_n - R_n),   R_{n-1} = c_n a_n + (1 - a_n) R_n,  R_last = bg
@@ -129,9 +130,12 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const GaussState *__restri
                              (float)Y0i + 0.5f, (float)Y1i - 0.5f))
                     qm |= 1u << q;
             }
-            s_f0[tid] = make_float4(s.f0.x, s.f0.y, s.f0.z, 2.0f * s.f0.w);
-            s_f1[tid] = s.f1;
-            s_f2[tid] = make_float2(s.f2.x, s.f2.y);
+            float4 f0, f1;
+            float2 f2;
+            stage_gauss(s, f0, f1, f2);
+            s_f0[tid] = f0;
+            s_f1[tid] = f1;
+            s_f2[tid] = f2;
             s_id[tid] = g;
         }
 #pragma unroll
@@ -155,11 +159,12 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(const GaussState *__restri
                     if (pos >= wave_L) continue;
                     const float4 f0 = s_f0[j], f1 = s_f1[j];
                     const float2 f2 = s_f2[j];
-                    const float dx = px - f0.x, dy = py - f0.y;
-                    const float q = conic_q(f0.z, f0.w, f1.x, dx, dy);
-                    const bool c = pos < L && q <= f1.y;
+                    // the forward's exponent and contribution test, bit for bit
+                    const float E = exponent_at(f0, row_terms(f0, f1, py), px);
+                    const bool c = pos < L && E >= f1.y;
                     if (__ballot(c) == 0) continue;
-                    const float e = gauss_alpha(q, f1.z);
+                    const float dx = px - f0.x, dy = py - f0.y;
+                    const float e = __builtin_amdgcn_exp2f(E);
                     const float a = c ? fminf(e, amax) : 0.0f;
                     T = T * __builtin_amdgcn_rcpf(1.0f - a);  // a = 0: T unchanged
                     const float wc = a * T;

@@ -1,124 +1,148 @@
 // Per-tile front-to-back alpha blending with early termination (Sec. 2.2
 // rendering stage; Sec. 5.2 early stop on saturated transmittance, opacity
-// checks moved out of the per-pixel loop, base-2 exponent in log form).
+// checks moved out of the per-pixel loop; Sec. 5.3.2 exponent in log form).
 //
-// One 256-thread workgroup per 16 x 16 tile; each wavefront owns an 8 x 8
-// quadrant, one pixel per lane.  The tile's sorted list is walked in batches
-// of 256 Gaussians: every thread stages one Gaussian's 48-byte state in LDS
-// and tests the ellipse against the four quadrant hulls (the same exact
-// test as the tile binning, with a slightly inflated extent so it never
-// drops a contributor), so a wavefront skips Gaussians that miss its quadrant
-// with one scalar branch.  Per pixel and Gaussian:
-//   q = A dx^2 + 2B dx dy + C dy^2; contributes iff q <= k^2;
-//   alpha = min(alpha_max, 2^(log2 o - q log2(e) / 2));
+// One 128-thread workgroup per 16 x 16 tile: each wavefront owns a 16 x 8
+// half, each lane two horizontally adjacent pixels, so the row terms of the
+// quadratic form, the LDS reads and the loop control are shared by two
+// pixels.  The tile's sorted list is walked in batches of 256 Gaussians:
+// every thread stages two Gaussians (the coefficients of the exponent,
+// opacity threshold and colour) in LDS and tests each ellipse against the two
+// halves (the exact tile test with a slightly inflated extent, so it never
+// drops a contributor); a wavefront walks only the set bits of its half's
+// masks, in scalar code.  Per pixel and Gaussian:
+//   E = log2 o - q log2(e) / 2; contributes iff E >= log2 o - k^2 log2(e) / 2;
+//   alpha = min(alpha_max, 2^E);
 //   T' = T (1 - alpha); if T' < T_stop the pixel stops before blending it;
 //   C += colour alpha T; T = T'.
-// A stopped lane moves its sample point to +1e30 so that q overflows and the
-// Gaussian never contributes again: the hot loop carries no done-flag.
+// A stopped pixel moves its sample point to +1e30 so that E becomes -inf and
+// the Gaussian never contributes again: the hot loop carries no done-flag.
 #include "fgs_internal.hpp"
+#include "blend_common.hpp"
 
 namespace fgs {
 namespace {
 
 constexpr int kWave = 64;
+constexpr int kThreads = 128;        // two wavefronts per tile
+constexpr int kBatch = 256;          // Gaussians staged per batch
+constexpr int kWords = kBatch / kWave;
 constexpr float kFar = 1e30f;
 
-// Conservative ellipse / rectangle test used only to skip work: the
-// rectangle [X0, X1] x [Y0, Y1] in pixel-sample coordinates.
-__device__ __forceinline__ bool rect_hit(float u, float v, float A, float B, float C, float k2, float X0, float X1,
-                                         float Y0, float Y1) {
-    const float x0 = X0 - u, x1 = X1 - u, y0 = Y0 - v, y1 = Y1 - v;
-    if (x0 <= 0.0f && 0.0f <= x1 && y0 <= 0.0f && 0.0f <= y1) return true;
-    bool hit = false;
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-        const float ye_ = e ? y1 : y0;
-        const float bq = 2.0f * B * ye_;
-        const float cq = C * ye_ * ye_ - k2;
-        const float delta = bq * bq - 4.0f * A * cq;
-        const float e1 = 2.0f * A * x0 + bq, e2 = 2.0f * A * x1 + bq;
-        hit |= (delta >= 0.0f) && (e1 <= 0.0f || e1 * e1 <= delta) && (e2 >= 0.0f || e2 * e2 <= delta);
-    }
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-        const float xe_ = e ? x1 : x0;
-        const float bq = 2.0f * B * xe_;
-        const float cq = A * xe_ * xe_ - k2;
-        const float delta = bq * bq - 4.0f * C * cq;
-        const float e1 = 2.0f * C * y0 + bq, e2 = 2.0f * C * y1 + bq;
-        hit |= (delta >= 0.0f) && (e1 <= 0.0f || e1 * e1 <= delta) && (e2 >= 0.0f || e2 * e2 <= delta);
-    }
-    return hit;
+struct Pixel {
+    float x;        // sample x, or kFar once stopped
+    float T, c0, c1, c2;
+    uint32_t last;
+    uint32_t examined;
+    bool done;
+};
+
+// Alpha and transmittance of one pixel for one Gaussian, before the
+// termination check.
+struct Step {
+    float a, Tn;
+    bool in, stop;
+};
+
+__device__ __forceinline__ Step step(const Pixel &p, float e, float thr, float amax, float tstop) {
+    Step st;
+    st.in = e >= thr;
+    st.a = st.in ? fminf(__builtin_amdgcn_exp2f(e), amax) : 0.0f;
+    st.Tn = fmaf(-st.a, p.T, p.T);
+    st.stop = st.Tn < tstop;
+    return st;
+}
+
+// The pixel saturates: it stops before this Gaussian (rare path).
+template <bool kCountWork>
+__device__ __forceinline__ void stop_before(Pixel &p, Step &st, uint32_t pos) {
+    st.a = 0.0f;
+    st.Tn = p.T;
+    st.in = false;
+    p.x = kFar;
+    p.done = true;
+    if (kCountWork) p.examined = pos + 1u;
+}
+
+template <bool kLast>
+__device__ __forceinline__ void apply(Pixel &p, const Step &st, const float4 &f1, const float2 &f2, uint32_t pos) {
+    const float w = st.a * p.T;
+    p.c0 = fmaf(w, f1.w, p.c0);
+    p.c1 = fmaf(w, f2.x, p.c1);
+    p.c2 = fmaf(w, f2.y, p.c2);
+    p.T = st.Tn;
+    if (kLast) p.last = st.in ? pos + 1u : p.last;
 }
 
 template <bool kCountWork, bool kLast>
-__global__ __launch_bounds__(kBlock) void k_blend(const GaussState *__restrict__ gs,
-                                                  const uint32_t *__restrict__ values,
-                                                  const uint2 *__restrict__ ranges, int W, int H, int tiles_x,
-                                                  DevOptions op, float *__restrict__ rgb, float *__restrict__ Tout,
-                                                  uint32_t *__restrict__ last_out, unsigned long long *work) {
-    __shared__ float4 s_f0[kBlock], s_f1[kBlock];
-    __shared__ float2 s_f2[kBlock];
-    // s_rel[q][w]: bit i set iff entry 64 w + i of the batch meets quadrant q
-    __shared__ uint32_t s_rel[4][kBlock / kWave][2];
+__global__ __launch_bounds__(kThreads) void k_blend(const GaussState *__restrict__ gs,
+                                                    const uint32_t *__restrict__ values,
+                                                    const uint2 *__restrict__ ranges, int W, int H, int tiles_x,
+                                                    DevOptions op, float *__restrict__ rgb, float *__restrict__ Tout,
+                                                    uint32_t *__restrict__ last_out, unsigned long long *work) {
+    __shared__ float4 s_f0[kBatch], s_f1[kBatch];
+    __shared__ float2 s_f2[kBatch];
+    // s_rel[h][w]: bit i set iff entry 64 w + i of the batch meets half h
+    __shared__ uint32_t s_rel[2][kWords][2];
 
     const int tid = threadIdx.x, lane = tid & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);  // wave-uniform
     const int tile = blockIdx.x;
     const int tx = tile % tiles_x, ty = tile / tiles_x;
-    const int qx = wave & 1, qy = wave >> 1;
-    const int pi = tx * kTile + qx * 8 + (lane & 7);
-    const int pj = ty * kTile + qy * 8 + (lane >> 3);
-    const bool in_img = pi < W && pj < H;
-    float px = in_img ? (float)pi + 0.5f : kFar;
+    const int pi0 = tx * kTile + 2 * (lane & 7);
+    const int pj = ty * kTile + wave * 8 + (lane >> 3);
+    const bool in0 = pi0 < W && pj < H, in1 = pi0 + 1 < W && pj < H;
     const float py = (float)pj + 0.5f;
 
     const uint2 rg = ranges[tile];
     const uint32_t start = rg.x, end = rg.y;
-    float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
-    uint32_t last = 0;
-    bool done = !in_img;
-    bool wave_done = __ballot(!done) == 0;
-    uint32_t examined = in_img ? (end - start) : 0u;  // entries this pixel must look at
-    const float nl2e = -0.72134752044448170f;          // -log2(e) / 2
+    Pixel p0{in0 ? (float)pi0 + 0.5f : kFar, 1.0f, 0.0f, 0.0f, 0.0f, 0u, in0 ? end - start : 0u, !in0};
+    Pixel p1{in1 ? (float)pi0 + 1.5f : kFar, 1.0f, 0.0f, 0.0f, 0.0f, 0u, in1 ? end - start : 0u, !in1};
+    bool wave_done = __ballot(!(p0.done && p1.done)) == 0;
     // loop-invariant clamp as the result of an arithmetic op (a canonical
     // value, so the minimum needs no per-iteration canonicalisation)
     const float amax = op.alpha_max + 0.0f;
     const float tstop = op.T_stop;
 
-    for (uint32_t b0 = start; b0 < end; b0 += kBlock) {
-        const uint32_t nb = (end - b0) < (uint32_t)kBlock ? (end - b0) : (uint32_t)kBlock;
-        uint32_t qm = 0;
-        if ((uint32_t)tid < nb) {
-            const GaussState s = gs[values[b0 + tid]];
-            const float k2i = s.f1.y * 1.00002f + 1e-5f;
+    for (uint32_t b0 = start; b0 < end; b0 += kBatch) {
+        const uint32_t nb = (end - b0) < (uint32_t)kBatch ? (end - b0) : (uint32_t)kBatch;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int X0i = tx * kTile + (q & 1) * 8, Y0i = ty * kTile + (q >> 1) * 8;
-                int X1i = X0i + 8, Y1i = Y0i + 8;
-                X1i = X1i > W ? W : X1i;
-                Y1i = Y1i > H ? H : Y1i;
-                if (X0i < X1i && Y0i < Y1i &&
-                    rect_hit(s.f0.x, s.f0.y, s.f0.z, s.f0.w, s.f1.x, k2i, (float)X0i + 0.5f, (float)X1i - 0.5f,
-                             (float)Y0i + 0.5f, (float)Y1i - 0.5f))
-                    qm |= 1u << q;
+        for (int r = 0; r < kBatch / kThreads; ++r) {
+            const uint32_t i = (uint32_t)(r * kThreads + tid);
+            uint32_t hm = 0;
+            if (i < nb) {
+                const GaussState s = gs[values[b0 + i]];
+                const float k2i = s.f1.y * 1.00002f + 1e-5f;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int X0i = tx * kTile, Y0i = ty * kTile + h * 8;
+                    int X1i = X0i + kTile, Y1i = Y0i + 8;
+                    X1i = X1i > W ? W : X1i;
+                    Y1i = Y1i > H ? H : Y1i;
+                    if (Y0i < Y1i && rect_hit(s.f0.x, s.f0.y, s.f0.z, s.f0.w, s.f1.x, k2i, (float)X0i + 0.5f,
+                                              (float)X1i - 0.5f, (float)Y0i + 0.5f, (float)Y1i - 0.5f))
+                        hm |= 1u << h;
+                }
+                float4 f0, f1;
+                float2 f2;
+                stage_gauss(s, f0, f1, f2);
+                s_f0[i] = f0;
+                s_f1[i] = f1;
+                s_f2[i] = f2;
             }
-            // 2B in place of B for the pixel loop
-            s_f0[tid] = make_float4(s.f0.x, s.f0.y, s.f0.z, 2.0f * s.f0.w);
-            s_f1[tid] = s.f1;
-            s_f2[tid] = make_float2(s.f2.x, s.f2.y);
-        }
+            // entry i = 128 r + 64 wave + lane: word 2 r + wave, bit lane
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint64_t bq = __ballot((qm >> q) & 1u);
-            if (lane == 0) {
-                s_rel[q][wave][0] = (uint32_t)bq;
-                s_rel[q][wave][1] = (uint32_t)(bq >> 32);
+            for (int h = 0; h < 2; ++h) {
+                const uint64_t bq = __ballot((hm >> h) & 1u);
+                if (lane == 0) {
+                    s_rel[h][2 * r + wave][0] = (uint32_t)bq;
+                    s_rel[h][2 * r + wave][1] = (uint32_t)(bq >> 32);
+                }
             }
         }
         __syncthreads();
         if (!wave_done) {
-            for (int wd = 0; wd < kBlock / kWave && !wave_done; ++wd) {
+            for (int wd = 0; wd < kWords && !wave_done; ++wd) {
                 uint64_t m = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)s_rel[wave][wd][0]) |
                              ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)s_rel[wave][wd][1]) << 32);
                 while (m) {
@@ -126,57 +150,51 @@ __global__ __launch_bounds__(kBlock) void k_blend(const GaussState *__restrict__
                     m &= m - 1;
                     const float4 f0 = s_f0[j], f1 = s_f1[j];
                     const float2 f2 = s_f2[j];
-                    const float dx = px - f0.x, dy = py - f0.y;
-                    const float t = fmaf(f0.z, dx, f0.w * dy);
-                    const float q = fmaf(f1.x * dy, dy, dx * t);
-                    bool inq = q <= f1.y;
-                    const float e = __builtin_amdgcn_exp2f(fmaf(q, nl2e, f1.z));
-                    float a = inq ? fminf(e, amax) : 0.0f;
-                    float Tn = fmaf(-a, T, T);
-                    const bool stop = Tn < tstop;
-                    if (__ballot(stop) != 0) {
-                        // rare path: lanes that saturate stop before this Gaussian
-                        if (stop) {
-                            a = 0.0f;
-                            Tn = T;
-                            inq = false;
-                            px = kFar;
-                            done = true;
-                            if (kCountWork) examined = b0 - start + (uint32_t)j + 1u;
-                        }
-                        wave_done = __ballot(!done) == 0;
+                    const RowTerms rt = row_terms(f0, f1, py);
+                    const float e0 = exponent_at(f0, rt, p0.x);
+                    const float e1 = exponent_at(f0, rt, p1.x);
+                    const uint32_t pos = b0 - start + (uint32_t)j;
+                    Step s0 = step(p0, e0, f1.y, amax, tstop);
+                    Step s1 = step(p1, e1, f1.y, amax, tstop);
+                    if (__ballot(s0.stop || s1.stop) != 0) {
+                        if (s0.stop) stop_before<kCountWork>(p0, s0, pos);
+                        if (s1.stop) stop_before<kCountWork>(p1, s1, pos);
+                        wave_done = __ballot(!(p0.done && p1.done)) == 0;
                     }
-                    const float wgt = a * T;
-                    c0 = fmaf(wgt, f1.w, c0);
-                    c1 = fmaf(wgt, f2.x, c1);
-                    c2 = fmaf(wgt, f2.y, c2);
-                    T = Tn;
-                    if (kLast) last = inq ? (b0 - start + (uint32_t)j + 1u) : last;
+                    apply<kLast>(p0, s0, f1, f2, pos);
+                    apply<kLast>(p1, s1, f1, f2, pos);
                     if (wave_done) break;
                 }
             }
         }
         // all 256 pixels finished: stop walking the list (also the barrier
         // that protects the staging buffers)
-        if (__syncthreads_count(done ? 1 : 0) == kBlock) break;
+        if (__syncthreads_count((p0.done && p1.done) ? 1 : 0) == kThreads) break;
     }
 
     if (kCountWork) {
-        // a wave that skipped a Gaussian whose ellipse misses its quadrant
-        // still counts it: the count is the method's, not this kernel's
-        unsigned long long v = examined;
+        // a wave that skipped a Gaussian whose ellipse misses its half still
+        // counts it: the count is the method's, not this kernel's
+        unsigned long long v = (unsigned long long)p0.examined + p1.examined;
 #pragma unroll
         for (int d = 1; d < kWave; d <<= 1) v += __shfl_xor(v, d, kWave);
         if (lane == 0) atomicAdd(work, v);
     }
-    if (in_img) {
-        const size_t hw = (size_t)W * H;
-        const size_t p = (size_t)pj * W + pi;
-        rgb[p] = c0 + T * op.bg[0];
-        rgb[hw + p] = c1 + T * op.bg[1];
-        rgb[2 * hw + p] = c2 + T * op.bg[2];
-        if (Tout) Tout[p] = T;
-        if (kLast && last_out) last_out[p] = last;
+    const size_t hw = (size_t)W * H;
+    const size_t q = (size_t)pj * W + pi0;
+    if (in0) {
+        rgb[q] = p0.c0 + p0.T * op.bg[0];
+        rgb[hw + q] = p0.c1 + p0.T * op.bg[1];
+        rgb[2 * hw + q] = p0.c2 + p0.T * op.bg[2];
+        if (Tout) Tout[q] = p0.T;
+        if (kLast && last_out) last_out[q] = p0.last;
+    }
+    if (in1) {
+        rgb[q + 1] = p1.c0 + p1.T * op.bg[0];
+        rgb[hw + q + 1] = p1.c1 + p1.T * op.bg[1];
+        rgb[2 * hw + q + 1] = p1.c2 + p1.T * op.bg[2];
+        if (Tout) Tout[q + 1] = p1.T;
+        if (kLast && last_out) last_out[q + 1] = p1.last;
     }
 }
 
@@ -186,7 +204,7 @@ void launch_blend(const GaussState *gs, const uint32_t *values, const uint2 *ran
                   const DevOptions &op, float *rgb, float *T, uint32_t *last, unsigned long long *work,
                   hipStream_t s) {
     const int tiles_x = (W + kTile - 1) / kTile, tiles_y = (H + kTile - 1) / kTile;
-    const dim3 grid((unsigned)(tiles_x * tiles_y)), block(kBlock);
+    const dim3 grid((unsigned)(tiles_x * tiles_y)), block(kThreads);
     if (work)
         hipLaunchKernelGGL((k_blend<true, true>), grid, block, 0, s, gs, values, ranges, W, H, tiles_x, op, rgb, T,
                            last, work);

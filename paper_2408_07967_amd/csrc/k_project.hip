@@ -165,11 +165,88 @@ __device__ __forceinline__ int small_div(uint32_t k, int n) {
     return (int)(((float)k + 0.5f) * __builtin_amdgcn_rcpf((float)n));
 }
 
-__global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevCamera cam, DevOptions op, int W, int H,
-                                                       GaussState *__restrict__ gs, uint4 *__restrict__ rect,
-                                                       uint32_t *__restrict__ count, uint2 *__restrict__ mask,
-                                                       uint32_t *__restrict__ dkey, uint2 *__restrict__ chunks,
-                                                       uint32_t chunk_cap, FrameCounters *fc) {
+// 3D covariance Sigma = M M^T with M = R(q / |q|) diag(exp(log-scale))
+// (computeCov3D), upper triangle S00, S01, S02, S11, S12, S22.  False for a
+// non-finite scale or a quaternion of zero or non-finite norm.
+__device__ __forceinline__ bool cov3d(float ls0, float ls1, float ls2, const float *q4, float *S) {
+    const float qw = q4[0], qx = q4[1], qy = q4[2], qz = q4[3];
+    const float s0 = (float)canon_exp((double)ls0), s1 = (float)canon_exp((double)ls1),
+                s2 = (float)canon_exp((double)ls2);
+    const float n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
+    const bool fin = isfinite(ls0) && isfinite(ls1) && isfinite(ls2) && isfinite(n2);
+    if (!(fin && n2 > 0.0f)) return false;
+    const float qn = sqrtf(n2);
+    const float w = qw / qn, x = qx / qn, y = qy / qn, z = qz / qn;
+    const float r00 = 1.0f - 2.0f * (y * y + z * z);
+    const float r01 = 2.0f * (x * y - w * z);
+    const float r02 = 2.0f * (x * z + w * y);
+    const float r10 = 2.0f * (x * y + w * z);
+    const float r11 = 1.0f - 2.0f * (x * x + z * z);
+    const float r12 = 2.0f * (y * z - w * x);
+    const float r20 = 2.0f * (x * z - w * y);
+    const float r21 = 2.0f * (y * z + w * x);
+    const float r22 = 1.0f - 2.0f * (x * x + y * y);
+    const float M00 = r00 * s0, M01 = r01 * s1, M02 = r02 * s2;
+    const float M10 = r10 * s0, M11 = r11 * s1, M12 = r12 * s2;
+    const float M20 = r20 * s0, M21 = r21 * s1, M22 = r22 * s2;
+    S[0] = (M00 * M00 + M01 * M01) + M02 * M02;
+    S[1] = (M00 * M10 + M01 * M11) + M02 * M12;
+    S[2] = (M00 * M20 + M01 * M21) + M02 * M22;
+    S[3] = (M10 * M10 + M11 * M11) + M12 * M12;
+    S[4] = (M10 * M20 + M11 * M21) + M12 * M22;
+    S[5] = (M20 * M20 + M21 * M21) + M22 * M22;
+    return true;
+}
+
+// Opacity-aware extent (Eq. 3), capped by the 3 sigma rule (Eq. 1).
+__device__ __forceinline__ float extent_k2(float o, const DevOptions &op) {
+    double k2d = 2.0 * canon_log((double)o / (double)op.alpha_min);
+    if (op.cap_3sigma && k2d > 9.0) k2d = 9.0;
+    return (float)k2d;
+}
+
+// View-independent precompute of a resident scene (Sec. 5.3.1: preprocessing
+// shared by the viewpoints of one scene): per Gaussian (x, y, z, opacity) with
+// opacity 0 for a Gaussian that can never be visible, the 3D covariance with
+// k^2 and log2(opacity), and the SH coefficients Gaussian-major.  The same
+// operations as the per-frame path, so frames render bit for bit the same.
+__global__ __launch_bounds__(kBlock) void k_prepare(DevScene sc, DevOptions op, float4 *__restrict__ pos_o,
+                                                    float4 *__restrict__ cov, float *__restrict__ sh_out,
+                                                    int sh_stride) {
+    const int64_t st = sc.stride;
+    const int ncoef = 3 * (sc.D + 1) * (sc.D + 1);
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < sc.P;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const float mx = sc.means[g], my = sc.means[st + g], mz = sc.means[2 * st + g];
+        const float logit = sc.logits[g];
+        const float o = (float)(1.0 / (1.0 + canon_exp(-(double)logit)));
+        float S[6] = {0, 0, 0, 0, 0, 0};
+        float k2 = 0.0f, l2o = 0.0f;
+        bool ok = isfinite(logit) && o > op.alpha_min;
+        if (ok) {
+            const float q4[4] = {sc.quats[g], sc.quats[st + g], sc.quats[2 * st + g], sc.quats[3 * st + g]};
+            ok = cov3d(sc.log_scales[g], sc.log_scales[st + g], sc.log_scales[2 * st + g], q4, S);
+        }
+        if (ok) {
+            k2 = extent_k2(o, op);
+            l2o = log2f(o);
+        }
+        pos_o[g] = make_float4(mx, my, mz, ok ? o : 0.0f);
+        cov[2 * g] = make_float4(S[0], S[1], S[2], S[3]);
+        cov[2 * g + 1] = make_float4(S[4], S[5], k2, l2o);
+        float *dst = sh_out + g * sh_stride;
+        for (int j = 0; j < ncoef; ++j) dst[j] = sc.sh[(int64_t)j * st + g];
+        for (int j = ncoef; j < sh_stride; ++j) dst[j] = 0.0f;
+    }
+}
+
+template <bool kPrep>
+__global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevPrepared pp, DevCamera cam, DevOptions op,
+                                                       int W, int H, GaussState *__restrict__ gs,
+                                                       uint4 *__restrict__ rect, uint32_t *__restrict__ count,
+                                                       uint2 *__restrict__ mask, uint32_t *__restrict__ dkey,
+                                                       uint2 *__restrict__ chunks, uint32_t chunk_cap,
+                                                       FrameCounters *fc) {
     // Persistent grid: each workgroup walks batches of 256 Gaussians and keeps
     // its depth-digit histogram, visible count and pending chunk reservations
     // in LDS, so global atomics are per workgroup, not per batch.
@@ -213,12 +290,23 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevCamera ca
     const int64_t g = g0 + threadIdx.x;
     const int64_t st = sc.stride;
     bool valid = false;
-    float u = 0, v = 0, A = 0, B = 0, C = 0, k2 = 0, o = 0, tz = 0;
+    float u = 0, v = 0, A = 0, B = 0, C = 0, k2 = 0, o = 0, tz = 0, l2o = 0;
     int tx0 = 0, tx1 = -1, ty0 = 0, ty1 = -1;
     float col[3] = {0, 0, 0};
 
     if (g < sc.P) {
-        const float mx = sc.means[g], my = sc.means[st + g], mz = sc.means[2 * st + g];
+        float mx, my, mz, po = 0.0f;
+        if constexpr (kPrep) {
+            const float4 p4 = pp.pos_o[g];
+            mx = p4.x;
+            my = p4.y;
+            mz = p4.z;
+            po = p4.w;
+        } else {
+            mx = sc.means[g];
+            my = sc.means[st + g];
+            mz = sc.means[2 * st + g];
+        }
         const float *R = cam.R;
         // view transform (p_view)
         const float tx = ((R[0] * mx + R[1] * my) + R[2] * mz) + cam.t[0];
@@ -227,20 +315,38 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevCamera ca
         // near plane (Alg. 4: p_view.z > 0.2); the remaining attributes are
         // read only for Gaussians in front of the camera
         if (tz > cam.near_z && isfinite(mx) && isfinite(my) && isfinite(mz)) {
-            const float logit = sc.logits[g];
-            o = (float)(1.0 / (1.0 + canon_exp(-(double)logit)));
-            // opacity prefilter (Alg. 4: opacity > 1/255)
-            if (o > op.alpha_min && isfinite(logit)) {
-                const float ls0 = sc.log_scales[g], ls1 = sc.log_scales[st + g], ls2 = sc.log_scales[2 * st + g];
-                const float qw = sc.quats[g], qx = sc.quats[st + g], qy = sc.quats[2 * st + g],
-                            qz = sc.quats[3 * st + g];
-                const float s0 = (float)canon_exp((double)ls0), s1 = (float)canon_exp((double)ls1),
-                            s2 = (float)canon_exp((double)ls2);
-                const float n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
-                const bool fin = isfinite(ls0) && isfinite(ls1) && isfinite(ls2) && isfinite(n2);
-                if (fin && n2 > 0.0f) {
-                    const float qn = sqrtf(n2);
-                    const float w = qw / qn, x = qx / qn, y = qy / qn, z = qz / qn;
+            bool ok = false;
+            float S[6] = {0, 0, 0, 0, 0, 0};
+            float log2o = 0.0f;
+            if constexpr (kPrep) {
+                // view-independent part precomputed once (Sec. 5.3.1); an
+                // invalid Gaussian has opacity 0
+                o = po;
+                ok = o > op.alpha_min;
+                if (ok) {
+                    const float4 c0 = pp.cov[2 * g], c1 = pp.cov[2 * g + 1];
+                    S[0] = c0.x; S[1] = c0.y; S[2] = c0.z; S[3] = c0.w; S[4] = c1.x; S[5] = c1.y;
+                    k2 = c1.z;
+                    log2o = c1.w;
+                }
+            } else {
+                const float logit = sc.logits[g];
+                o = (float)(1.0 / (1.0 + canon_exp(-(double)logit)));
+                // opacity prefilter (Alg. 4: opacity > 1/255)
+                if (o > op.alpha_min && isfinite(logit)) {
+                    const float ls0 = sc.log_scales[g], ls1 = sc.log_scales[st + g],
+                                ls2 = sc.log_scales[2 * st + g];
+                    const float q4[4] = {sc.quats[g], sc.quats[st + g], sc.quats[2 * st + g], sc.quats[3 * st + g]};
+                    ok = cov3d(ls0, ls1, ls2, q4, S);
+                    if (ok) {
+                        k2 = extent_k2(o, op);
+                        log2o = log2f(o);
+                    }
+                }
+            }
+            if (ok) {
+                const float S00 = S[0], S01 = S[1], S02 = S[2], S11 = S[3], S12 = S[4], S22 = S[5];
+                {
                     // pinhole projection (project + ndc2Pix)
                     const float xt = tx / tz, yt = ty / tz;
                     u = cam.fx * xt + cam.cx;
@@ -252,25 +358,6 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevCamera ca
                     const float yc = clampf_(yt, -limy, limy);
                     const float J00 = cam.fx / tz, J02 = -((cam.fx * xc) / tz);
                     const float J11 = cam.fy / tz, J12 = -((cam.fy * yc) / tz);
-                    // 3D covariance Sigma = M M^T, M = R_q diag(s)
-                    const float r00 = 1.0f - 2.0f * (y * y + z * z);
-                    const float r01 = 2.0f * (x * y - w * z);
-                    const float r02 = 2.0f * (x * z + w * y);
-                    const float r10 = 2.0f * (x * y + w * z);
-                    const float r11 = 1.0f - 2.0f * (x * x + z * z);
-                    const float r12 = 2.0f * (y * z - w * x);
-                    const float r20 = 2.0f * (x * z - w * y);
-                    const float r21 = 2.0f * (y * z + w * x);
-                    const float r22 = 1.0f - 2.0f * (x * x + y * y);
-                    const float M00 = r00 * s0, M01 = r01 * s1, M02 = r02 * s2;
-                    const float M10 = r10 * s0, M11 = r11 * s1, M12 = r12 * s2;
-                    const float M20 = r20 * s0, M21 = r21 * s1, M22 = r22 * s2;
-                    const float S00 = (M00 * M00 + M01 * M01) + M02 * M02;
-                    const float S01 = (M00 * M10 + M01 * M11) + M02 * M12;
-                    const float S02 = (M00 * M20 + M01 * M21) + M02 * M22;
-                    const float S11 = (M10 * M10 + M11 * M11) + M12 * M12;
-                    const float S12 = (M10 * M20 + M11 * M21) + M12 * M22;
-                    const float S22 = (M20 * M20 + M21 * M21) + M22 * M22;
                     // 2D covariance Sigma' = T Sigma T^T, T = J R_cam
                     const float T00 = J00 * R[0] + J02 * R[6], T01 = J00 * R[1] + J02 * R[7],
                                 T02 = J00 * R[2] + J02 * R[8];
@@ -290,12 +377,21 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevCamera ca
                         A = cc / det;
                         B = (-cb) / det;
                         C = ca / det;
-                        // opacity-aware extent (Eq. 3), capped by the 3 sigma rule (Eq. 1)
-                        double k2d = 2.0 * canon_log((double)o / (double)op.alpha_min);
-                        if (op.cap_3sigma && k2d > 9.0) k2d = 9.0;
-                        k2 = (float)k2d;
-                        // rectangle tangent to the ellipse (Sec. 4.1), in pixel samples
-                        const float hx = sqrtf(k2 * ca), hy = sqrtf(k2 * cc);
+                        // rectangle tangent to the ellipse (Sec. 4.1), in pixel samples;
+                        // binning 2: the square of the 3 sigma circle of 3DGS
+                        // (Alg. 1: radius ceil(3 sqrt(lambda_max)) of Sigma')
+                        float hx, hy;
+                        if (op.binning == 2) {
+                            const float mid = 0.5f * (ca + cc);
+                            float disc = mid * mid - det;
+                            disc = disc > 0.0f ? disc : 0.0f;
+                            const float lam = mid + sqrtf(disc);
+                            hx = ceilf(3.0f * sqrtf(lam));
+                            hy = hx;
+                        } else {
+                            hx = sqrtf(k2 * ca);
+                            hy = sqrtf(k2 * cc);
+                        }
                         const float xlo = clampf_((u - hx) - 0.5f, -1.0f, (float)W);
                         const float xhi = clampf_((u + hx) - 0.5f, -1.0f, (float)W);
                         const float ylo = clampf_((v - hy) - 0.5f, -1.0f, (float)H);
@@ -318,10 +414,20 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevCamera ca
                             sh_basis(dxw / dn, dyw / dn, dzw / dn, sc.D, Y);
                             const int nk = (sc.D + 1) * (sc.D + 1);
                             float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
-                            for (int k = 0; k < nk; ++k) {
-                                a0 = a0 + sc.sh[(int64_t)(3 * k + 0) * st + g] * Y[k];
-                                a1 = a1 + sc.sh[(int64_t)(3 * k + 1) * st + g] * Y[k];
-                                a2 = a2 + sc.sh[(int64_t)(3 * k + 2) * st + g] * Y[k];
+                            if constexpr (kPrep) {
+                                // Gaussian-major coefficients: one contiguous read
+                                const float *shg = pp.sh + (int64_t)g * pp.sh_stride;
+                                for (int k = 0; k < nk; ++k) {
+                                    a0 = a0 + shg[3 * k + 0] * Y[k];
+                                    a1 = a1 + shg[3 * k + 1] * Y[k];
+                                    a2 = a2 + shg[3 * k + 2] * Y[k];
+                                }
+                            } else {
+                                for (int k = 0; k < nk; ++k) {
+                                    a0 = a0 + sc.sh[(int64_t)(3 * k + 0) * st + g] * Y[k];
+                                    a1 = a1 + sc.sh[(int64_t)(3 * k + 1) * st + g] * Y[k];
+                                    a2 = a2 + sc.sh[(int64_t)(3 * k + 2) * st + g] * Y[k];
+                                }
                             }
                             a0 = a0 + 0.5f;
                             a1 = a1 + 0.5f;
@@ -331,6 +437,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevCamera ca
                             col[0] = a0 > 0.0f ? a0 : 0.0f;
                             col[1] = a1 > 0.0f ? a1 : 0.0f;
                             col[2] = a2 > 0.0f ? a2 : 0.0f;
+                            l2o = log2o;
                         }
                     }
                 }
@@ -354,7 +461,8 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevCamera ca
         s_boff[slot] = atomicAdd(&s_nch, nch);
     }
     const bool small = valid && !chunked;  // rectangle of at most kBigTiles tiles
-    if (op.binning == 1) {
+    if (op.binning != 0) {
+        // every tile of the rectangle (test and comparison modes)
         if (small) {
             cnt = (uint32_t)nt;
             hm = nt >= 64 ? ~0ull : ((1ull << nt) - 1ull);
@@ -395,7 +503,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevCamera ca
         if (valid) {
             GaussState s;
             s.f0 = make_float4(u, v, A, B);
-            s.f1 = make_float4(C, k2, log2f(o), col[0]);
+            s.f1 = make_float4(C, k2, l2o, col[0]);
             s.f2 = make_float4(col[1], col[2], tz, o);
             gs[g] = s;
             rect[g] = make_uint4((uint32_t)tx0, (uint32_t)tx1, (uint32_t)ty0, (uint32_t)ty1);
@@ -483,101 +591,116 @@ __global__ __launch_bounds__(kBlock) void k_emit(int W, int H, const uint32_t *_
 // Exact tile counts of chunked Gaussians: one workgroup per chunk of
 // kChunkTiles tiles (persistent grid), per-chunk hit counts kept for the
 // emission, per-Gaussian totals by atomic add.
+// Exact tile tests of the chunked Gaussians: one wavefront per chunk of
+// kChunkTiles rectangle tiles (4 per lane, independent), so that every
+// workgroup keeps four chunks in flight without barriers; the next chunk's
+// descriptor is loaded before the current chunk is tested.
 __global__ __launch_bounds__(kBlock) void k_big_count(int W, int H, int binning, const GaussState *__restrict__ gs,
                                                       const uint4 *__restrict__ rect,
                                                       const uint2 *__restrict__ chunks, uint32_t chunk_cap,
                                                       uint32_t *__restrict__ chunk_hits,
                                                       uint32_t *__restrict__ chunk_mask, uint32_t *count,
                                                       const FrameCounters *fc) {
-    __shared__ uint32_t s_w[kBlock / kWave];
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    constexpr int kPer = kChunkTiles / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
     if (fc->error & kErrChunkOverflow) return;  // the frame is rendered again with a larger list
     const uint32_t n = fc->nchunks < chunk_cap ? fc->nchunks : chunk_cap;
-    for (uint32_t ch = blockIdx.x; ch < n; ch += gridDim.x) {
-        const uint2 e = chunks[ch];
+    const uint32_t nwaves = gridDim.x * (kBlock / kWave);
+    uint32_t ch = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    uint2 e = ch < n ? chunks[ch] : make_uint2(kNoChunk, 0u);
+    for (; ch < n; ch += nwaves) {
+        const uint32_t nxt = ch + nwaves;
+        const uint2 e_next = nxt < n ? chunks[nxt] : make_uint2(kNoChunk, 0u);
         if (e.x == kNoChunk) {
-            if (tid == 0) chunk_hits[ch] = 0;
+            if (lane == 0) chunk_hits[ch] = 0;
+            e = e_next;
             continue;
         }
         const uint32_t g = e.x, c = ch - e.y;
         const uint4 rc = rect[g];
         const int ntx = (int)rc.y - (int)rc.x + 1;
         const int nt = ntx * ((int)rc.w - (int)rc.z + 1);
-        const int idx = (int)c * kChunkTiles + tid;
-        bool h = false;
-        if (idx < nt) {
-            const int ry = idx / ntx, rx = idx - ry * ntx;
-            if (binning == 1) {
-                h = true;
-            } else {
-                const GaussState s = gs[g];
-                h = tile_hit(s.f0.x, s.f0.y, s.f0.z, s.f0.w, s.f1.x, s.f1.y, (int)rc.x + rx, (int)rc.z + ry, W, H);
+        GaussState s{};
+        if (binning == 0) s = gs[g];
+        uint32_t tot = 0;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int idx = (int)c * kChunkTiles + j * kWave + lane;
+            bool h = false;
+            if (idx < nt) {
+                const int ry = idx / ntx, rx = idx - ry * ntx;
+                h = binning != 0 ||
+                    tile_hit(s.f0.x, s.f0.y, s.f0.z, s.f0.w, s.f1.x, s.f1.y, (int)rc.x + rx, (int)rc.z + ry, W, H);
+            }
+            const uint64_t b = __ballot(h);
+            tot += (uint32_t)__popcll(b);
+            if (lane == 0) {
+                chunk_mask[(size_t)ch * (kChunkTiles / 32) + 2 * j] = (uint32_t)b;
+                chunk_mask[(size_t)ch * (kChunkTiles / 32) + 2 * j + 1] = (uint32_t)(b >> 32);
             }
         }
-        const uint64_t b = __ballot(h);
         if (lane == 0) {
-            s_w[wave] = (uint32_t)__popcll(b);
-            chunk_mask[(size_t)ch * (kChunkTiles / 32) + 2 * wave] = (uint32_t)b;
-            chunk_mask[(size_t)ch * (kChunkTiles / 32) + 2 * wave + 1] = (uint32_t)(b >> 32);
-        }
-        __syncthreads();
-        if (tid == 0) {
-            uint32_t tot = 0;
-            for (int w = 0; w < kBlock / kWave; ++w) tot += s_w[w];
             chunk_hits[ch] = tot;
             if (tot) atomicAdd(&count[g], tot);
         }
-        __syncthreads();
+        e = e_next;
     }
 }
 
-// Pairs of the chunked Gaussians: each chunk writes the hits recorded by
-// k_big_count after those of the Gaussian's earlier chunks.
+// Pairs of the chunked Gaussians: each chunk (one wavefront) writes the hits
+// recorded by k_big_count after those of the Gaussian's earlier chunks.
 __global__ __launch_bounds__(kBlock) void k_big_emit(int W, const uint4 *__restrict__ rect,
                                                      const uint2 *__restrict__ mask, const uint2 *__restrict__ chunks,
                                                      uint32_t chunk_cap, const uint32_t *__restrict__ chunk_hits,
                                                      const uint32_t *__restrict__ chunk_mask,
                                                      uint32_t *__restrict__ tile_keys, uint32_t *__restrict__ values,
                                                      uint32_t cap, const FrameCounters *fc) {
-    __shared__ uint32_t s_pre[kBlock / kWave], s_cnt[kBlock / kWave];
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    constexpr int kPer = kChunkTiles / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
     const int tiles_x = (W + kTile - 1) / kTile;
     const uint64_t lt = (1ull << lane) - 1ull;
     const uint32_t n = fc->nchunks < chunk_cap ? fc->nchunks : chunk_cap;
-    for (uint32_t ch = blockIdx.x; ch < n; ch += gridDim.x) {
-        const uint2 e = chunks[ch];
-        if (e.x == kNoChunk || chunk_hits[ch] == 0) continue;
+    const uint32_t nwaves = gridDim.x * (kBlock / kWave);
+    uint32_t ch = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    uint2 e = ch < n ? chunks[ch] : make_uint2(kNoChunk, 0u);
+    for (; ch < n; ch += nwaves) {
+        const uint32_t nxt = ch + nwaves;
+        const uint2 e_next = nxt < n ? chunks[nxt] : make_uint2(kNoChunk, 0u);
+        const uint32_t hits = e.x == kNoChunk ? 0u : chunk_hits[ch];
+        if (hits == 0) {
+            e = e_next;
+            continue;
+        }
         const uint32_t g = e.x, first = e.y, c = ch - first;
+        const uint4 rc = rect[g];
+        const uint32_t base = mask[g].x;
+        uint64_t b[kPer];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j)
+            b[j] = (uint64_t)chunk_mask[(size_t)ch * (kChunkTiles / 32) + 2 * j] |
+                   ((uint64_t)chunk_mask[(size_t)ch * (kChunkTiles / 32) + 2 * j + 1] << 32);
         // hits of this Gaussian's earlier chunks
         uint32_t p = 0;
-        for (uint32_t k = first + (uint32_t)tid; k < ch; k += kBlock) p += chunk_hits[k];
+        for (uint32_t k = first + (uint32_t)lane; k < ch; k += kWave) p += chunk_hits[k];
 #pragma unroll
         for (int d = 1; d < kWave; d <<= 1) p += __shfl_xor(p, d, kWave);
-        const bool h = (chunk_mask[(size_t)ch * (kChunkTiles / 32) + tid / 32] >> (tid & 31)) & 1u;
-        const uint64_t b = __ballot(h);
-        if (lane == 0) {
-            s_pre[wave] = p;
-            s_cnt[wave] = (uint32_t)__popcll(b);
-        }
-        __syncthreads();
-        uint32_t before = 0, prefix = 0;
-        for (int w = 0; w < kBlock / kWave; ++w) {
-            before += (w < wave) ? s_cnt[w] : 0u;
-            prefix += s_pre[w];
-        }
-        if (h) {
-            const uint4 rc = rect[g];
-            const int ntx = (int)rc.y - (int)rc.x + 1;
-            const int idx = (int)c * kChunkTiles + tid;
-            const int ry = idx / ntx, rx = idx - ry * ntx;
-            const uint32_t tile = (uint32_t)(((int)rc.z + ry) * tiles_x + ((int)rc.x + rx));
-            const uint32_t at = mask[g].x + prefix + before + (uint32_t)__popcll(b & lt);
-            if (at < cap) {
-                tile_keys[at] = tile;
-                values[at] = g;
+        const int ntx = (int)rc.y - (int)rc.x + 1;
+        uint32_t before = base + p;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            if ((b[j] >> lane) & 1ull) {
+                const int idx = (int)c * kChunkTiles + j * kWave + lane;
+                const int ry = idx / ntx, rx = idx - ry * ntx;
+                const uint32_t tile = (uint32_t)(((int)rc.z + ry) * tiles_x + ((int)rc.x + rx));
+                const uint32_t at = before + (uint32_t)__popcll(b[j] & lt);
+                if (at < cap) {  // never leave the pair buffers
+                    tile_keys[at] = tile;
+                    values[at] = g;
+                }
             }
+            before += (uint32_t)__popcll(b[j]);
         }
-        __syncthreads();
+        e = e_next;
     }
 }
 
@@ -599,7 +722,7 @@ static unsigned resident_blocks(K kernel) {
 }
 
 unsigned preprocess_grid(int64_t P) {
-    static const unsigned cap = resident_blocks(k_preprocess);
+    static const unsigned cap = resident_blocks(k_preprocess<false>);
     const int64_t b = (P + kBlock - 1) / kBlock;
     return (unsigned)(b < (int64_t)cap ? (b > 0 ? b : 1) : cap);
 }
@@ -610,12 +733,24 @@ unsigned emit_grid(uint32_t visible) {
     return b < cap ? (b > 0 ? b : 1u) : cap;
 }
 
-void launch_preprocess(const DevScene &sc, const DevCamera &cam, const DevOptions &op, int W, int H,
-                       GaussState *gs, uint4 *rect, uint32_t *count, uint2 *mask, uint32_t *dkey, uint2 *chunks,
-                       uint32_t chunk_cap, FrameCounters *fc, hipStream_t s) {
+void launch_preprocess(const DevScene &sc, const DevPrepared *pp, const DevCamera &cam, const DevOptions &op,
+                       int W, int H, GaussState *gs, uint4 *rect, uint32_t *count, uint2 *mask, uint32_t *dkey,
+                       uint2 *chunks, uint32_t chunk_cap, FrameCounters *fc, hipStream_t s) {
     if (sc.P <= 0) return;
-    hipLaunchKernelGGL(k_preprocess, dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, cam, op, W, H, gs, rect,
-                       count, mask, dkey, chunks, chunk_cap, fc);
+    if (pp)
+        hipLaunchKernelGGL(k_preprocess<true>, dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, *pp, cam, op, W,
+                           H, gs, rect, count, mask, dkey, chunks, chunk_cap, fc);
+    else
+        hipLaunchKernelGGL(k_preprocess<false>, dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, DevPrepared{},
+                           cam, op, W, H, gs, rect, count, mask, dkey, chunks, chunk_cap, fc);
+}
+
+void launch_prepare(const DevScene &sc, const DevOptions &op, float4 *pos_o, float4 *cov, float *sh, int sh_stride,
+                    hipStream_t s) {
+    if (sc.P <= 0) return;
+    const int64_t blocks = (sc.P + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_prepare, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(kBlock), 0, s, sc, op,
+                       pos_o, cov, sh, sh_stride);
 }
 
 void launch_big_count(int W, int H, int binning, const GaussState *gs, const uint4 *rect, const uint2 *chunks,

@@ -126,17 +126,28 @@ __global__ __launch_bounds__(kBlock) void k_radix_downsweep(const uint32_t *__re
     uint32_t lo, hi;
     block_range(n, b, nb, &lo, &hi);
 
-    // global offset of this workgroup's first key of digit tid
+    // global offset of this workgroup's first key of digit tid: every group
+    // sum and every earlier histogram row of the group is loaded at once (a
+    // fixed, unrolled trip count keeps all the loads in flight together)
     {
-        const uint32_t ngroups = (nb + kSortGroup - 1) / kSortGroup;
+        constexpr uint32_t kGroups = (kSortBlocks + kSortGroup - 1) / kSortGroup;
         const uint32_t mygroup = b / kSortGroup;
-        uint32_t total = 0, before = 0;
-        for (uint32_t w = 0; w < ngroups; ++w) {
-            const uint32_t g = gsum[(size_t)w * kRadix + tid];
-            total += g;
-            before += (w < mygroup) ? g : 0u;
+        uint32_t gv[kGroups], hv[kSortGroup];
+#pragma unroll
+        for (uint32_t w = 0; w < kGroups; ++w) gv[w] = gsum[(size_t)w * kRadix + tid];
+#pragma unroll
+        for (uint32_t r = 0; r < (uint32_t)kSortGroup; ++r) {
+            const uint32_t row = mygroup * kSortGroup + r;
+            hv[r] = row < b ? hist[(size_t)row * kRadix + tid] : 0u;
         }
-        for (uint32_t r = mygroup * kSortGroup; r < b; ++r) before += hist[(size_t)r * kRadix + tid];
+        uint32_t total = 0, before = 0;
+#pragma unroll
+        for (uint32_t w = 0; w < kGroups; ++w) {
+            total += gv[w];
+            before += (w < mygroup) ? gv[w] : 0u;
+        }
+#pragma unroll
+        for (uint32_t r = 0; r < (uint32_t)kSortGroup; ++r) before += hv[r];
         uint32_t all = 0;
         const uint32_t dbase = block_exclusive_scan(total, s_tmp, &all);
         s_off[tid] = dbase + before;

@@ -175,7 +175,7 @@ fgs_status check_args(const fgs_scene *sc, const fgs_camera *cam, int32_t W, int
         if (!(opt->dilation >= 0.0f) || !std::isfinite(opt->dilation)) return bad("dilation must be finite and >= 0");
         if (!(opt->jac_clip > 0.0f) || !std::isfinite(opt->jac_clip)) return bad("jac_clip must be finite and > 0");
         if (!finite_all(opt->bg, 3)) return bad("background is not finite");
-        if (opt->binning < 0 || opt->binning > 1) return bad("binning not in {0, 1}");
+        if (opt->binning < 0 || opt->binning > 2) return bad("binning not in {0, 1, 2}");
     }
     return FGS_OK;
 }
@@ -219,14 +219,37 @@ DevScene to_dev(const fgs_scene &s) {
     return d;
 }
 
-void enqueue_front(const DevScene &sc, const DevCamera &cam, const DevOptions &op, int W, int H, FrameBuffers &fb,
-                   ChunkList &ch, SortScratch &ss, FrameCounters *fc, FrameCounters *host_fc, hipStream_t s,
-                   const StageMarks &mk) {
+hipError_t build_prepared(const fgs_scene &sc, const fgs_options &op, PreparedBuffers &pb, hipStream_t s) {
+    free_prepared(pb);
+    const int64_t P = sc.num_gaussians;
+    const int ncoef = 3 * (sc.sh_degree + 1) * (sc.sh_degree + 1);
+    pb.P = P;
+    pb.sh_stride = (ncoef + 3) / 4 * 4;
+    const size_t n = (size_t)(P > 0 ? P : 1);
+    hipError_t e;
+    if ((e = hipMalloc((void **)&pb.pos_o, n * sizeof(float4))) != hipSuccess) return e;
+    if ((e = hipMalloc((void **)&pb.cov, 2 * n * sizeof(float4))) != hipSuccess) return e;
+    if ((e = hipMalloc((void **)&pb.sh, n * (size_t)pb.sh_stride * sizeof(float))) != hipSuccess) return e;
+    launch_prepare(to_dev(sc), to_dev(op), pb.pos_o, pb.cov, pb.sh, pb.sh_stride, s);
+    return hipGetLastError();
+}
+
+void free_prepared(PreparedBuffers &pb) {
+    free_p(*(void **)&pb.pos_o);
+    free_p(*(void **)&pb.cov);
+    free_p(*(void **)&pb.sh);
+    pb = PreparedBuffers{};
+}
+
+void enqueue_front(const DevScene &sc, const DevPrepared *pp, const DevCamera &cam, const DevOptions &op, int W,
+                   int H, FrameBuffers &fb, ChunkList &ch, SortScratch &ss, FrameCounters *fc,
+                   FrameCounters *host_fc, hipStream_t s, const StageMarks &mk) {
     const uint32_t chunk_cap = (uint32_t)std::min<size_t>(ch.cap, 0xffffffffu);
     // ---- stage 1: preprocess + exact tile count -------------------------------
     launch_fill_u32(reinterpret_cast<uint32_t *>(fc), 0u, sizeof(FrameCounters) / 4, s);
     mk.mark(0, s);
-    launch_preprocess(sc, cam, op, W, H, fb.gs, fb.rect, fb.count, fb.mask, fb.dkey, ch.chunks, chunk_cap, fc, s);
+    launch_preprocess(sc, pp, cam, op, W, H, fb.gs, fb.rect, fb.count, fb.mask, fb.dkey, ch.chunks, chunk_cap, fc,
+                      s);
     launch_big_count(W, H, op.binning, fb.gs, fb.rect, ch.chunks, chunk_cap, ch.hits, ch.mask, fb.count, fc, s);
     // ---- depth order of the visible Gaussians: 4 LSD passes over the depth
     // digits, hoisted before key duplication (the low half of the (tile |

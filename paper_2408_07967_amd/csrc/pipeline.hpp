@@ -89,9 +89,25 @@ struct StageMarks {
 // Stages 1 and 2a: preprocess with the exact tile count, depth order of the
 // visible Gaussians, scan of the tile counts in depth order.  Ends with an
 // asynchronous copy of the frame counters to host_fc (pinned).
-void enqueue_front(const DevScene &sc, const DevCamera &cam, const DevOptions &op, int W, int H, FrameBuffers &fb,
-                   ChunkList &ch, SortScratch &ss, FrameCounters *fc, FrameCounters *host_fc, hipStream_t s,
-                   const StageMarks &mk);
+// pp: NULL (raw parameters) or the scene's view-independent precompute.
+void enqueue_front(const DevScene &sc, const DevPrepared *pp, const DevCamera &cam, const DevOptions &op, int W,
+                   int H, FrameBuffers &fb, ChunkList &ch, SortScratch &ss, FrameCounters *fc,
+                   FrameCounters *host_fc, hipStream_t s, const StageMarks &mk);
+
+// Device buffers of a scene's view-independent precompute.
+struct PreparedBuffers {
+    float4 *pos_o = nullptr;
+    float4 *cov = nullptr;
+    float *sh = nullptr;
+    int sh_stride = 0;
+    int64_t P = 0;
+    size_t bytes() const { return (size_t)P * (3 * sizeof(float4) + (size_t)sh_stride * sizeof(float)); }
+    DevPrepared dev() const { return DevPrepared{pos_o, cov, sh, sh_stride}; }
+};
+
+// Allocate and fill the precompute of sc for options op on stream s.
+hipError_t build_prepared(const fgs_scene &sc, const fgs_options &op, PreparedBuffers &pb, hipStream_t s);
+void free_prepared(PreparedBuffers &pb);
 
 // Stages 2b to 4: key emission, stable tile sort, tile ranges and blending.
 // Every count is read on the device from fc, and every grid is sized by a

@@ -33,6 +33,12 @@ struct fgs_frame {
     fgs_stats stats{};
 };
 
+struct fgs_prepared {
+    fgs_scene scene{};
+    fgs_options opt{};
+    PreparedBuffers pb;
+};
+
 struct fgs_context {
     int device = 0;
     std::string err;
@@ -53,6 +59,7 @@ struct fgs_context {
     // backward: per-Gaussian sums of the blend adjoint, 9 planes of gacc_stride
     float *gacc = nullptr;
     size_t gacc_stride = 0;
+    std::vector<fgs_prepared *> prepared;
 };
 
 namespace {
@@ -184,6 +191,10 @@ void fgs_destroy(fgs_context *ctx) {
         delete f;
     }
     if (ctx->gacc) (void)hipFree(ctx->gacc);
+    for (fgs_prepared *p : ctx->prepared) {
+        free_prepared(p->pb);
+        delete p;
+    }
     for (FrameBuffers &b : ctx->pool) free_frame_buffers(b);
     free_frame_buffers(ctx->fb);
     for (auto &set : ctx->ev)
@@ -217,14 +228,19 @@ size_t fgs_scratch_bytes(const fgs_context *ctx) {
     if (!ctx) return 0;
     size_t b = ctx->fb.bytes() + sizeof(FrameCounters) + ctx->ch.bytes() + (ctx->ss.rhist ? SortScratch::bytes() : 0);
     b += 9 * ctx->gacc_stride * sizeof(float);
+    for (const fgs_prepared *p : ctx->prepared) b += p->pb.bytes();
     for (const FrameBuffers &p : ctx->pool) b += p.bytes();
     for (const fgs_frame *f : ctx->frames) b += f->fb.bytes();
     return b;
 }
 
-fgs_status fgs_render(fgs_context *ctx, const fgs_scene *scene, const fgs_camera *cam, int32_t W, int32_t H,
-                      const fgs_options *opt_in, float *out_rgb, float *out_T, uint32_t *out_last, fgs_frame **saved,
-                      fgs_stats *stats, void *stream_v) {
+}  // extern "C"
+
+namespace {
+
+fgs_status render_impl(fgs_context *ctx, const fgs_scene *scene, const fgs_prepared *prep, const fgs_camera *cam,
+                       int32_t W, int32_t H, const fgs_options *opt_in, float *out_rgb, float *out_T,
+                       uint32_t *out_last, fgs_frame **saved, fgs_stats *stats, void *stream_v) {
     if (saved) *saved = nullptr;
     if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARGUMENT, "context is NULL");
     fgs_status st = validate(ctx, scene, cam, W, H, opt_in);
@@ -235,6 +251,8 @@ fgs_status fgs_render(fgs_context *ctx, const fgs_scene *scene, const fgs_camera
         opt = *opt_in;
     else
         fgs_default_options(&opt);
+    if (prep && (opt.alpha_min != prep->opt.alpha_min || opt.cap_3sigma != prep->opt.cap_3sigma))
+        return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "alpha_min / cap_3sigma differ from the scene's preparation");
     ctx->err.clear();
     hipStream_t s = (hipStream_t)stream_v;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
@@ -258,9 +276,11 @@ fgs_status fgs_render(fgs_context *ctx, const fgs_scene *scene, const fgs_camera
     StageMarks mk;
     if (timed) mk.ev = ctx->ev[es];
 
-    uint32_t V = 0, N = 0;
+    uint32_t V = 0, N = 0, big = 0;
     for (int attempt = 0;; ++attempt) {
-        enqueue_front(dsc, dcam, dop, W, H, fb, ctx->ch, ctx->ss, ctx->fc_dev, ctx->fc_host, s, mk);
+        const DevPrepared pdev = prep ? prep->pb.dev() : DevPrepared{};
+        enqueue_front(dsc, prep ? &pdev : nullptr, dcam, dop, W, H, fb, ctx->ch, ctx->ss, ctx->fc_dev, ctx->fc_host,
+                      s, mk);
         HIP_TRY(ctx, hipGetLastError());
         HIP_TRY(ctx, hipStreamSynchronize(s));
         fold_events(ctx);  // the previous instrumented frame is complete after the wait
@@ -273,6 +293,7 @@ fgs_status fgs_render(fgs_context *ctx, const fgs_scene *scene, const fgs_camera
         }
         V = ctx->fc_host->visible;
         N = ctx->fc_host->pairs;
+        big = ctx->fc_host->nchunks;
         break;
     }
     HIP_TRY(ctx, ensure_pairs(fb, N));
@@ -296,6 +317,7 @@ fgs_status fgs_render(fgs_context *ctx, const fgs_scene *scene, const fgs_camera
     stt.pairs = N;
     stt.tiles_x = tiles_x;
     stt.tiles_y = tiles_y;
+    stt.big_chunks = (int32_t)big;
     {
         int b = 0;
         while ((1ull << b) < (uint64_t)ntiles) ++b;
@@ -333,6 +355,74 @@ fgs_status fgs_render(fgs_context *ctx, const fgs_scene *scene, const fgs_camera
         *saved = f;
     }
     return FGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fgs_status fgs_render(fgs_context *ctx, const fgs_scene *scene, const fgs_camera *cam, int32_t W, int32_t H,
+                      const fgs_options *opt, float *out_rgb, float *out_T, uint32_t *out_last, fgs_frame **saved,
+                      fgs_stats *stats, void *stream) {
+    return render_impl(ctx, scene, nullptr, cam, W, H, opt, out_rgb, out_T, out_last, saved, stats, stream);
+}
+
+fgs_status fgs_prepare_scene(fgs_context *ctx, const fgs_scene *scene, const fgs_options *opt_in,
+                             fgs_prepared **out, void *stream) {
+    if (out) *out = nullptr;
+    if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARGUMENT, "context is NULL");
+    if (!out) return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "out is NULL");
+    fgs_camera probe{};
+    for (int i = 0; i < 3; ++i) probe.R[4 * i] = 1.0f;
+    probe.fx = probe.fy = 1.0f;
+    probe.near_z = 0.2f;
+    fgs_status st = validate(ctx, scene, &probe, 1, 1, opt_in);
+    if (st != FGS_OK) return st;
+    fgs_options opt;
+    if (opt_in)
+        opt = *opt_in;
+    else
+        fgs_default_options(&opt);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    fgs_prepared *p = new fgs_prepared();
+    p->scene = *scene;
+    p->opt = opt;
+    const hipError_t e = build_prepared(*scene, opt, p->pb, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        free_prepared(p->pb);
+        delete p;
+        return hip_fail(ctx, e, "building the scene's precompute");
+    }
+    ctx->prepared.push_back(p);
+    *out = p;
+    return FGS_OK;
+}
+
+fgs_status fgs_prepared_release(fgs_context *ctx, fgs_prepared *p) {
+    if (!p) return FGS_OK;
+    if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARGUMENT, "context is NULL");
+    for (size_t i = 0; i < ctx->prepared.size(); ++i) {
+        if (ctx->prepared[i] == p) {
+            ctx->prepared.erase(ctx->prepared.begin() + (long)i);
+            (void)hipSetDevice(ctx->device);
+            (void)hipDeviceSynchronize();  // frames may still read it
+            free_prepared(p->pb);
+            delete p;
+            return FGS_OK;
+        }
+    }
+    return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "prepared scene does not belong to this context");
+}
+
+fgs_status fgs_render_prepared(fgs_context *ctx, const fgs_prepared *p, const fgs_camera *cam, int32_t W, int32_t H,
+                               const fgs_options *opt, float *out_rgb, float *out_T, uint32_t *out_last,
+                               fgs_frame **saved, fgs_stats *stats, void *stream) {
+    if (saved) *saved = nullptr;
+    if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARGUMENT, "context is NULL");
+    bool owned = false;
+    for (const fgs_prepared *q : ctx->prepared) owned |= (q == p);
+    if (!p || !owned) return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "prepared scene is NULL or not of this context");
+    return render_impl(ctx, &p->scene, p, cam, W, H, opt, out_rgb, out_T, out_last, saved, stats, stream);
 }
 
 fgs_status fgs_frame_release(fgs_context *ctx, fgs_frame *frame) {

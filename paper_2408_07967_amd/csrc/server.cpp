@@ -154,6 +154,8 @@ struct fgs_server {
     std::string err;  // guarded by mu
     uint8_t *arena_base = nullptr;
     Arena arena;
+    PreparedBuffers prep;  // view-independent precompute of the resident scene
+    DevPrepared pdev{};
     std::vector<Slot> slots;
     // shared with client threads
     std::mutex mu;
@@ -231,8 +233,8 @@ bool ensure_region(fgs_server *srv, Slot &s) {
 
 void start_front(fgs_server *srv, Slot &s) {
     const DevCamera dcam = to_dev(s.req.cam);
-    enqueue_front(srv->dsc, dcam, srv->dop, s.req.W, s.req.H, s.fb, s.ch, s.ss, s.fc_dev, s.fc_host, s.stream,
-                  StageMarks{});
+    enqueue_front(srv->dsc, &srv->pdev, dcam, srv->dop, s.req.W, s.req.H, s.fb, s.ch, s.ss, s.fc_dev, s.fc_host,
+                  s.stream, StageMarks{});
     (void)hipEventRecord(s.evA, s.stream);
     s.state = SlotState::FRONT;
 }
@@ -473,6 +475,7 @@ void free_server(fgs_server *srv) {
         if (s.stream) (void)hipStreamDestroy(s.stream);
     }
     if (srv->arena_base) (void)hipFree(srv->arena_base);
+    free_prepared(srv->prep);
     delete srv;
 }
 
@@ -521,6 +524,9 @@ fgs_status fgs_server_create(int device, const fgs_scene *scene, const fgs_optio
         (size_t)((cfg->max_width + kTile - 1) / kTile) * (size_t)((cfg->max_height + kTile - 1) / kTile);
     const size_t pix = (size_t)cfg->max_width * cfg->max_height;
     hipError_t e = hipMalloc((void **)&srv->arena_base, (size_t)cfg->budget_bytes);
+    if (e == hipSuccess) e = build_prepared(*scene, srv->opt, srv->prep, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    srv->pdev = srv->prep.dev();
     srv->arena.init((size_t)cfg->budget_bytes / kAlign * kAlign);
     srv->slots.resize((size_t)cfg->max_inflight);
     size_t slot_bytes = 0;
@@ -545,7 +551,7 @@ fgs_status fgs_server_create(int device, const fgs_scene *scene, const fgs_optio
         free_server(srv);
         return e == hipErrorOutOfMemory ? FGS_ERR_OUT_OF_MEMORY : FGS_ERR_DEVICE;
     }
-    srv->st.slot_bytes = (int64_t)slot_bytes;
+    srv->st.slot_bytes = (int64_t)(slot_bytes + srv->prep.bytes());
     srv->worker = std::thread(worker_main, srv);
     *out = srv;
     return FGS_OK;

@@ -68,9 +68,25 @@ class Renderer:
     def scratch_bytes(self):
         return int(B.lib().fgs_scratch_bytes(self.ctx.handle))
 
-    def render(self, scene, cam, W, H, opts=None, out=None, want_T=False, want_last=False, save=False):
+    def prepare(self, scene, opts=None):
+        """View-independent precompute of a resident scene (renders from it are
+        bit-identical to renders of the scene).  Returns a handle for
+        render(..., prepared=handle); free it with release_prepared."""
+        h = C.c_void_p()
+        sc = scene.abi()
+        op = options_abi(opts)
+        stream = torch.cuda.current_stream(scene.means.device).cuda_stream
+        self.ctx.check(B.lib().fgs_prepare_scene(self.ctx.handle, C.byref(sc), C.byref(op), C.byref(h), stream))
+        return h
+
+    def release_prepared(self, handle):
+        if handle and self.ctx.handle:
+            self.ctx.check(B.lib().fgs_prepared_release(self.ctx.handle, handle))
+
+    def render(self, scene, cam, W, H, opts=None, out=None, want_T=False, want_last=False, save=False,
+               prepared=None):
         """Render; returns dict(rgb [3,H,W], T [H,W] or None, last [H,W] or None,
-        stats, frame handle or None)."""
+        stats, frame handle or None).  prepared: a handle from prepare(scene)."""
         dev = scene.means.device
         rgb = out if out is not None else torch.empty((3, H, W), dtype=torch.float32, device=dev)
         T = torch.empty((H, W), dtype=torch.float32, device=dev) if want_T else None
@@ -81,14 +97,18 @@ class Renderer:
         st = B.FgsStats()
         fr = C.c_void_p()
         stream = torch.cuda.current_stream(dev).cuda_stream
-        status = B.lib().fgs_render(self.ctx.handle, C.byref(sc), C.byref(cm), int(W), int(H), C.byref(op),
-                                    rgb.data_ptr(), T.data_ptr() if T is not None else None,
-                                    last.data_ptr() if last is not None else None,
-                                    C.byref(fr) if save else None, C.byref(st), stream)
+        outs = (rgb.data_ptr(), T.data_ptr() if T is not None else None,
+                last.data_ptr() if last is not None else None, C.byref(fr) if save else None, C.byref(st), stream)
+        if prepared is not None:
+            status = B.lib().fgs_render_prepared(self.ctx.handle, prepared, C.byref(cm), int(W), int(H),
+                                                 C.byref(op), *outs)
+        else:
+            status = B.lib().fgs_render(self.ctx.handle, C.byref(sc), C.byref(cm), int(W), int(H), C.byref(op),
+                                        *outs)
         self.ctx.check(status)
         return dict(rgb=rgb, T=T, last=last, frame=fr if save else None,
                     stats=dict(visible=st.visible, pairs=st.pairs, tiles_x=st.tiles_x, tiles_y=st.tiles_y,
-                               sort_passes=st.sort_passes))
+                               sort_passes=st.sort_passes, big_chunks=st.big_chunks))
 
     def backward(self, frame, scene, cam, W, H, opts, dL_drgb):
         """Gradients of L with respect to the raw parameters of `scene`, given

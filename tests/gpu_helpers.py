@@ -11,10 +11,11 @@ IMG_FRAC = 0.999
 IMG_MEAN = 1e-5
 
 
-def gpu_frame(R, gscene, cam, W, H, opts):
-    """Render on the GPU and download the saved frame's fields."""
+def gpu_frame(R, gscene, cam, W, H, opts, prepared=None):
+    """Render on the GPU (from the raw parameters, or from a prepared scene)
+    and download the saved frame's fields."""
     import torch
-    out = R.render(gscene, cam, W, H, opts, want_T=True, want_last=True, save=True)
+    out = R.render(gscene, cam, W, H, opts, want_T=True, want_last=True, save=True, prepared=prepared)
     torch.cuda.synchronize()
     fr = out["frame"]
     P = gscene.P

@@ -115,6 +115,65 @@ def test_bbox_binning_same_image_more_pairs(orc, R, scenes):
     assert mx < 1e-5, mx
 
 
+@pytest.mark.parametrize("kind,P,W,H", [("small", None, 256, 256), ("medium", 150_000, 960, 540)])
+def test_3sigma_square_binning_parity(orc, R, scenes, kind, P, W, H):
+    """binning = 2: state, pairs and order bit-exact against the FP32 oracle
+    in the same mode; the image equals the exact-binning image."""
+    sc = scenes.make_scene(kind, P=P)
+    cam = scenes.camera_for(kind, W=W, H=H)
+    g, _, _ = _full_check(orc, R, sc, cam, W, H, opts(binning=2), f"{kind}-binning2")
+    a = gpu_frame(R, _gs(sc), cam, W, H, opts(binning=0))
+    assert g["stats"]["pairs"] > a["stats"]["pairs"]
+    mx, frac, mean = image_error(a["rgb"], g["rgb"])
+    assert mx < 1e-5, mx
+
+
+@pytest.mark.parametrize("case", ["small", "random_sh3", "degenerate", "medium_binning2", "uncapped"])
+def test_prepared_scene_is_bit_identical(orc, R, scenes, case):
+    """A frame from the view-independent precompute equals the frame from the
+    raw parameters bit for bit (state, pairs, order, image, T, last)."""
+    o = opts()
+    if case == "small":
+        sc, cam, W, H = scenes.make_scene("small"), scenes.camera_for("small"), 256, 256
+    elif case == "random_sh3":
+        sc = random_scene(np.random.default_rng(31), 4000, ls_mu=-2.4, sh_degree=3)
+        W, H = 301, 177
+        cam = identity_camera(W, H, 0.9 * W)
+    elif case == "degenerate":
+        rng = np.random.default_rng(32)
+        sc = random_scene(rng, 600, ls_mu=-2.0, sh_degree=2)
+        sc.means[0, 5] = np.nan
+        sc.log_scales[1, 6] = np.inf
+        sc.quats[:, 7] = 0.0
+        sc.logits[0, 8] = -9.0      # below the opacity threshold
+        sc.sh[4, 9] = np.nan
+        sc.means[2, 10] = -1.0      # behind the camera
+        W, H = 96, 80
+        cam = identity_camera(W, H, 70.0)
+    elif case == "medium_binning2":
+        sc = scenes.make_scene("medium", P=120_000)
+        W, H = 960, 540
+        cam = scenes.camera_for("medium", 3, W=W, H=H)
+        o = opts(binning=2)
+    else:
+        sc, cam, W, H = scenes.make_scene("small"), scenes.camera_for("small"), 256, 256
+        o = opts(cap_3sigma=0, alpha_min=0.01)
+    gsc = _gs(sc)
+    h = R.prepare(gsc, o)
+    try:
+        a = gpu_frame(R, gsc, cam, W, H, o)
+        b = gpu_frame(R, gsc, cam, W, H, o, prepared=h)
+    finally:
+        R.release_prepared(h)
+    assert a["stats"] == b["stats"]
+    for k in ("rgb", "T", "last", "gauss", "rect", "count", "order", "tiles", "values", "ranges"):
+        if k in ("gauss", "rect"):
+            vis = a["order"].astype(np.int64)  # culled Gaussians have no state
+            assert np.array_equal(a[k][vis].view(np.uint32), b[k][vis].view(np.uint32)), k
+        else:
+            assert np.array_equal(np.asarray(a[k]).view(np.uint32), np.asarray(b[k]).view(np.uint32)), k
+
+
 def test_deterministic_repeat(orc, R, scenes):
     sc = scenes.make_scene("medium", P=100_000)
     cam = scenes.camera_for("medium", 2)

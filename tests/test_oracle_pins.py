@@ -370,6 +370,38 @@ def test_exact_and_bbox_binning_give_identical_images(orc, scenes):
     assert np.array_equal(a["rgb"], b["rgb"]) and np.array_equal(a["T"], b["T"])
 
 
+def test_3sigma_square_binning_mode(orc, scenes):
+    """binning = 2 (3DGS binning, Alg. 1 / Alg. 2): the box is the square of
+    the circle of radius ceil(3 sqrt(lambda_max)) of Sigma', every tile of it.
+    Head-on isotropic Gaussian: lambda_max = (f s / z)^2 + dilation in closed
+    form.  The image equals exact binning; pair counts order as
+    exact <= tight box <= 3 sigma square."""
+    f, z, s_ = 120.0, 5.0, 0.04
+    sc = scene_from([[0.013, -0.021, z]], [[np.log(s_)] * 3], [[1, 0, 0, 0]], [logit(0.8)], dc_rgb=[0.5, 0.5, 0.5],
+                    dtype=np.float64)
+    W = H = 128
+    o = opts(binning=2)
+    out = orc.render(sc, identity_camera(W, H, f), W, H, o)
+    st, iv = out["state"][0], out["ints"][0]
+    lam = (f * s_ / z) ** 2 + float(np.float32(0.3))
+    r = np.ceil(3.0 * np.sqrt(lam))
+    assert st[orc.S_HX] == r and st[orc.S_HY] == r
+    u = f * 0.013 / z + W / 2
+    assert iv[orc.I_I0] == int(np.ceil(u - r - 0.5)) and iv[orc.I_I1] == int(np.floor(u + r - 0.5))
+    assert iv[orc.I_COUNT] == (iv[orc.I_TX1] - iv[orc.I_TX0] + 1) * (iv[orc.I_TY1] - iv[orc.I_TY0] + 1)
+    sc = scenes.make_scene("small")
+    cam = scenes.camera_for("small")
+    a = orc.render(sc, cam, 256, 256, opts(binning=0))
+    b = orc.render(sc, cam, 256, 256, opts(binning=1))
+    c = orc.render(sc, cam, 256, 256, opts(binning=2))
+    assert a["npairs"] < b["npairs"] < c["npairs"]
+    assert np.array_equal(a["rgb"], c["rgb"]) and np.array_equal(a["T"], c["T"])
+    # the square contains the tight box of every Gaussian visible in both
+    both = (a["ints"][:, 0] == 1) & (c["ints"][:, 0] == 1)
+    assert np.all(c["state"][both, orc.S_HX] >= a["state"][both, orc.S_HX])
+    assert np.all(c["state"][both, orc.S_HY] >= a["state"][both, orc.S_HY])
+
+
 def test_transmittance_product_invariant(orc):
     """All colours 1, background 0: pixel value = 1 - T_final exactly
     (sum of alpha_n T_n telescopes to 1 - prod(1 - alpha_n))."""
