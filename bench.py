@@ -130,6 +130,45 @@ def serving_leg(args):
                 region_evictions=st["region_evictions"])
 
 
+def differentiation_leg(steps):
+    """Forward + backward on the differentiation workload: 1M Gaussians of the
+    1080p orbit scene at 1920x1080, L1 loss against the image of the same scene
+    with means perturbed by N(0, 0.01).  Times the forward (saved frame) and
+    the backward (blend adjoint + preprocess adjoint) with HIP-synchronised
+    wall clocks."""
+    import torch
+    from paper_2408_07967_amd import scenes
+    from paper_2408_07967_amd.render import GaussianScene, Renderer
+    sc = scenes.make_scene("medium")
+    gsc = GaussianScene.from_numpy(sc, "cuda:0")
+    tgt_sc = GaussianScene.from_numpy(scenes.perturb_means(sc), "cuda:0")
+    del sc
+    cam = scenes.camera_for("medium", W=1920, H=1080)
+    R = Renderer(0)
+    target = R.render(tgt_sc, cam, 1920, 1080)["rgb"].clone()
+    del tgt_sc
+    fwd = bwd = 0.0
+    for it in range(steps + 2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = R.render(gsc, cam, 1920, 1080, save=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dL = torch.sign(out["rgb"] - target) / out["rgb"].numel()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        R.backward(out["frame"], gsc, cam, 1920, 1080, None, dL)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        R.release(out["frame"])
+        if it >= 2:
+            fwd += t1 - t0
+            bwd += t3 - t2
+    R.close()
+    return dict(workload="medium-1M-gaussians-1920x1080-l1", forward_ms=round(fwd / steps * 1e3, 3),
+                backward_ms=round(bwd / steps * 1e3, 3), pairs=int(out["stats"]["pairs"]))
+
+
 def compare_binning(steps):
     """Pair redundancy of the binning modes (the paper's pair-count and
     stage-breakdown comparison, on the synthetic workloads): exact ellipse/tile
@@ -190,6 +229,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-work-count", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-backward", action="store_true", help="skip the forward + backward timing")
     ap.add_argument("--compare-binning", action="store_true",
                     help="also report pairs and stage times of the three binning modes")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
@@ -294,6 +334,9 @@ def main():
     if not args.no_serve:
         serving = serving_leg(args)
     binning_modes = compare_binning(max(5, args.steps // 5)) if args.compare_binning else None
+    differentiation = None if args.no_backward else differentiation_leg(10)
+    if differentiation:
+        log(f"[bench] forward + backward: {differentiation}")
 
     res = dict(metric=METRIC, value=round(fps, 3), unit="frames/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(dt / args.steps * 1e3, 4), higher_is_better=True,
@@ -304,7 +347,7 @@ def main():
                            visible=int(stats["visible"]), pairs=int(stats["pairs"]),
                            big_rect_chunks=int(stats["big_chunks"]),
                            pairs_per_s=round(stats["pairs"] * fps, 1), stage_ms=stage_ms),
-               roofline=roof, cpu_baseline=cpu, serving=serving)
+               roofline=roof, cpu_baseline=cpu, serving=serving, differentiation=differentiation)
     if binning_modes is not None:
         res["binning_modes"] = binning_modes
     print(json.dumps(res), flush=True)

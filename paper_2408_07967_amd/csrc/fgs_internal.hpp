@@ -79,15 +79,16 @@ constexpr int kSortGroup = 32;
 unsigned preprocess_grid(int64_t P);
 unsigned emit_grid(uint32_t visible);
 
-// Preprocess: per-Gaussian state, tile rectangle, exact tile count, hit mask,
-// depth key (kInvalidKey for culled Gaussians) and the visible count.  Large
-// rectangles append chunk entries (g, first chunk) to `chunks` (capacity
-// chunk_cap; on overflow the error bit kErrChunkOverflow is set and the host
-// renders the frame again with a larger list) and get count 0,
-// mask = (0, first chunk).
+// Preprocess: per-Gaussian state, tile rectangle, exact tile count, emission
+// record, depth key (kInvalidKey for culled Gaussians) and the visible count.
+// The emission record is (tx0 | tx1 << 16, ty0 | ty1 << 16, hit mask low,
+// hit mask high).  Large rectangles append chunk entries (g, first chunk) to
+// `chunks` (capacity chunk_cap; on overflow the error bit kErrChunkOverflow
+// is set and the host renders the frame again with a larger list) and get
+// count 0 and record (rectangle, 0, first chunk).
 // pp: NULL (raw parameters) or the scene's precompute.
 void launch_preprocess(const DevScene &sc, const DevPrepared *pp, const DevCamera &cam, const DevOptions &op,
-                       int W, int H, GaussState *gs, uint4 *rect, uint32_t *count, uint2 *mask, uint32_t *dkey,
+                       int W, int H, GaussState *gs, uint4 *rect, uint32_t *count, uint4 *erec, uint32_t *dkey,
                        uint2 *chunks, uint32_t chunk_cap, FrameCounters *fc, hipStream_t s);
 
 // View-independent precompute (opacity, 3D covariance, k^2, log2 opacity,
@@ -102,14 +103,14 @@ void launch_big_count(int W, int H, int binning, const GaussState *gs, const uin
                       const FrameCounters *fc, hipStream_t s);
 
 // Emit (tile, gaussian) pairs for Gaussians in depth order.  Chunked
-// Gaussians only record their output base in mask[g].x.
+// Gaussians only record their output base in erec[g].z.
 // visible: the count, or a bound on it when visible_dev (device) holds it.
 void launch_emit(int W, int H, const uint32_t *order, uint32_t visible, const uint32_t *visible_dev,
-                 const uint32_t *offsets, const uint4 *rect, const uint32_t *count, uint2 *mask, uint32_t *tile_keys,
-                 uint32_t *values, uint32_t cap, hipStream_t s);
+                 const uint32_t *offsets, uint4 *erec, uint32_t *tile_keys, uint32_t *values, uint32_t cap,
+                 hipStream_t s);
 
 // Emit the pairs of the chunked Gaussians (after launch_emit).
-void launch_big_emit(int W, const uint4 *rect, const uint2 *mask, const uint2 *chunks, uint32_t chunk_cap,
+void launch_big_emit(int W, const uint4 *rect, const uint4 *erec, const uint2 *chunks, uint32_t chunk_cap,
                      const uint32_t *chunk_hits, const uint32_t *chunk_mask, uint32_t *tile_keys, uint32_t *values,
                      uint32_t cap, const FrameCounters *fc, hipStream_t s);
 

@@ -244,13 +244,13 @@ template <bool kPrep>
 __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevPrepared pp, DevCamera cam, DevOptions op,
                                                        int W, int H, GaussState *__restrict__ gs,
                                                        uint4 *__restrict__ rect, uint32_t *__restrict__ count,
-                                                       uint2 *__restrict__ mask, uint32_t *__restrict__ dkey,
+                                                       uint4 *__restrict__ erec, uint32_t *__restrict__ dkey,
                                                        uint2 *__restrict__ chunks, uint32_t chunk_cap,
                                                        FrameCounters *fc) {
     // Persistent grid: each workgroup walks batches of 256 Gaussians and keeps
     // its depth-digit histogram, visible count and pending chunk reservations
     // in LDS, so global atomics are per workgroup, not per batch.
-    __shared__ uint32_t s_bg[kBigList], s_boff[kBigList], s_bn[kBigList];
+    __shared__ uint32_t s_bg[kBigList], s_boff[kBigList], s_bn[kBigList], s_bx[kBigList], s_by[kBigList];
     __shared__ uint32_t s_excl[kBlock / kWave][kWave], s_mlo[kBlock / kWave][kWave], s_mhi[kBlock / kWave][kWave];
     __shared__ uint32_t s_vis, s_nbig, s_nch, s_base;
     if (threadIdx.x == 0) {
@@ -274,7 +274,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevPrepared 
             for (uint32_t e = threadIdx.x; e < nb; e += kBlock) {
                 const uint32_t gg = s_bg[e], first = base + s_boff[e], n = s_bn[e];
                 for (uint32_t c = 0; c < n; ++c) chunks[first + c] = make_uint2(gg, first);
-                mask[gg] = make_uint2(0u, first);
+                erec[gg] = make_uint4(s_bx[e], s_by[e], 0u, first);
             }
         }
         __syncthreads();
@@ -458,6 +458,8 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevPrepared 
         const uint32_t slot = atomicAdd(&s_nbig, 1u);
         s_bg[slot] = (uint32_t)g;
         s_bn[slot] = nch;
+        s_bx[slot] = (uint32_t)tx0 | ((uint32_t)tx1 << 16);
+        s_by[slot] = (uint32_t)ty0 | ((uint32_t)ty1 << 16);
         s_boff[slot] = atomicAdd(&s_nch, nch);
     }
     const bool small = valid && !chunked;  // rectangle of at most kBigTiles tiles
@@ -507,7 +509,11 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevPrepared 
             s.f2 = make_float4(col[1], col[2], tz, o);
             gs[g] = s;
             rect[g] = make_uint4((uint32_t)tx0, (uint32_t)tx1, (uint32_t)ty0, (uint32_t)ty1);
-            if (!chunked) mask[g] = make_uint2((uint32_t)hm, (uint32_t)(hm >> 32));
+            // emission record: rectangle (4 x 16 bits) and hit mask in one
+            // 16-byte gather
+            if (!chunked)
+                erec[g] = make_uint4((uint32_t)tx0 | ((uint32_t)tx1 << 16), (uint32_t)ty0 | ((uint32_t)ty1 << 16),
+                                     (uint32_t)hm, (uint32_t)(hm >> 32));
         }
     }
     const uint64_t vb = __ballot(valid);
@@ -525,9 +531,7 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevPrepared 
 // mask).  Chunked Gaussians only record their output base here.
 __global__ __launch_bounds__(kBlock) void k_emit(int W, int H, const uint32_t *__restrict__ order,
                                                  uint32_t visible, const uint32_t *__restrict__ visible_dev,
-                                                 const uint32_t *__restrict__ offsets,
-                                                 const uint4 *__restrict__ rect,
-                                                 const uint32_t *__restrict__ count, uint2 *__restrict__ mask,
+                                                 const uint32_t *__restrict__ offsets, uint4 *__restrict__ erec,
                                                  uint32_t *__restrict__ tile_keys, uint32_t *__restrict__ values,
                                                  uint32_t cap) {
     __shared__ uint32_t s_excl[kBlock / kWave][kWave];
@@ -539,28 +543,27 @@ __global__ __launch_bounds__(kBlock) void k_emit(int W, int H, const uint32_t *_
     for (uint32_t r0 = blockIdx.x * kBlock; r0 < visible; r0 += gridDim.x * kBlock) {
     const uint32_t r = r0 + threadIdx.x;
     const bool act = r < visible;
-    uint32_t g = 0, c = 0, base = 0;
+    uint32_t g = 0, base = 0;
     uint4 rc = make_uint4(0, 0, 0, 0);
     uint64_t m = 0;
     if (act) {
         g = order[r];
-        c = count[g];
         base = offsets[r];
-        rc = rect[g];
-        const uint2 mm = mask[g];
-        m = (uint64_t)mm.x | ((uint64_t)mm.y << 32);
+        const uint4 er = erec[g];
+        rc = make_uint4(er.x & 0xffffu, er.x >> 16, er.y & 0xffffu, er.y >> 16);
+        m = (uint64_t)er.z | ((uint64_t)er.w << 32);
     }
     const int ntx = (int)rc.y - (int)rc.x + 1;
     const int nt = act ? ntx * ((int)rc.w - (int)rc.z + 1) : 0;
     // chunked Gaussians only publish their output base; their pairs come later
     const bool chunked = act && nt > kBigTiles && (uint32_t)(m >> 32) != kNoChunk;
-    if (chunked) mask[g].x = base;
+    if (chunked) erec[g].z = base;
 
 
     // flattened (Gaussian, rectangle tile) items: every lane handles one tile
     // of some Gaussian per step and writes it if the hit mask of the
     // preprocess has its bit, at the Gaussian's offset plus the hits before it
-    const uint32_t items = (act && !chunked && c > 0) ? (uint32_t)nt : 0u;
+    const uint32_t items = (act && !chunked && m != 0) ? (uint32_t)nt : 0u;
     const uint32_t incl = wave_incl_scan(items, lane);
     const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
     uint32_t *sx = s_excl[threadIdx.x / kWave];
@@ -650,7 +653,7 @@ __global__ __launch_bounds__(kBlock) void k_big_count(int W, int H, int binning,
 // Pairs of the chunked Gaussians: each chunk (one wavefront) writes the hits
 // recorded by k_big_count after those of the Gaussian's earlier chunks.
 __global__ __launch_bounds__(kBlock) void k_big_emit(int W, const uint4 *__restrict__ rect,
-                                                     const uint2 *__restrict__ mask, const uint2 *__restrict__ chunks,
+                                                     const uint4 *__restrict__ erec, const uint2 *__restrict__ chunks,
                                                      uint32_t chunk_cap, const uint32_t *__restrict__ chunk_hits,
                                                      const uint32_t *__restrict__ chunk_mask,
                                                      uint32_t *__restrict__ tile_keys, uint32_t *__restrict__ values,
@@ -673,7 +676,7 @@ __global__ __launch_bounds__(kBlock) void k_big_emit(int W, const uint4 *__restr
         }
         const uint32_t g = e.x, first = e.y, c = ch - first;
         const uint4 rc = rect[g];
-        const uint32_t base = mask[g].x;
+        const uint32_t base = erec[g].z;
         uint64_t b[kPer];
 #pragma unroll
         for (int j = 0; j < kPer; ++j)
@@ -734,15 +737,15 @@ unsigned emit_grid(uint32_t visible) {
 }
 
 void launch_preprocess(const DevScene &sc, const DevPrepared *pp, const DevCamera &cam, const DevOptions &op,
-                       int W, int H, GaussState *gs, uint4 *rect, uint32_t *count, uint2 *mask, uint32_t *dkey,
+                       int W, int H, GaussState *gs, uint4 *rect, uint32_t *count, uint4 *erec, uint32_t *dkey,
                        uint2 *chunks, uint32_t chunk_cap, FrameCounters *fc, hipStream_t s) {
     if (sc.P <= 0) return;
     if (pp)
         hipLaunchKernelGGL(k_preprocess<true>, dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, *pp, cam, op, W,
-                           H, gs, rect, count, mask, dkey, chunks, chunk_cap, fc);
+                           H, gs, rect, count, erec, dkey, chunks, chunk_cap, fc);
     else
         hipLaunchKernelGGL(k_preprocess<false>, dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, DevPrepared{},
-                           cam, op, W, H, gs, rect, count, mask, dkey, chunks, chunk_cap, fc);
+                           cam, op, W, H, gs, rect, count, erec, dkey, chunks, chunk_cap, fc);
 }
 
 void launch_prepare(const DevScene &sc, const DevOptions &op, float4 *pos_o, float4 *cov, float *sh, int sh_stride,
@@ -761,19 +764,19 @@ void launch_big_count(int W, int H, int binning, const GaussState *gs, const uin
                        chunk_cap, chunk_hits, chunk_mask, count, fc);
 }
 
-void launch_big_emit(int W, const uint4 *rect, const uint2 *mask, const uint2 *chunks, uint32_t chunk_cap,
+void launch_big_emit(int W, const uint4 *rect, const uint4 *erec, const uint2 *chunks, uint32_t chunk_cap,
                      const uint32_t *chunk_hits, const uint32_t *chunk_mask, uint32_t *tile_keys, uint32_t *values,
                      uint32_t cap, const FrameCounters *fc, hipStream_t s) {
-    hipLaunchKernelGGL(k_big_emit, dim3(kPersistentBlocks), dim3(kBlock), 0, s, W, rect, mask, chunks, chunk_cap,
+    hipLaunchKernelGGL(k_big_emit, dim3(kPersistentBlocks), dim3(kBlock), 0, s, W, rect, erec, chunks, chunk_cap,
                        chunk_hits, chunk_mask, tile_keys, values, cap, fc);
 }
 
 void launch_emit(int W, int H, const uint32_t *order, uint32_t visible, const uint32_t *visible_dev,
-                 const uint32_t *offsets, const uint4 *rect, const uint32_t *count, uint2 *mask, uint32_t *tile_keys,
-                 uint32_t *values, uint32_t cap, hipStream_t s) {
+                 const uint32_t *offsets, uint4 *erec, uint32_t *tile_keys, uint32_t *values, uint32_t cap,
+                 hipStream_t s) {
     if (visible == 0) return;
     hipLaunchKernelGGL(k_emit, dim3(emit_grid(visible)), dim3(kBlock), 0, s, W, H, order, visible, visible_dev,
-                       offsets, rect, count, mask, tile_keys, values, cap);
+                       offsets, erec, tile_keys, values, cap);
 }
 
 }  // namespace fgs

@@ -68,7 +68,7 @@ hipError_t ensure_gauss(FrameBuffers &b, size_t P) {
     FGS_GROW(b.gs, cap);
     FGS_GROW(b.rect, cap);
     FGS_GROW(b.count, cap);
-    FGS_GROW(b.mask, cap);
+    FGS_GROW(b.erec, cap);
     FGS_GROW(b.dkey, cap);
     FGS_GROW(b.dk_b, cap);
     FGS_GROW(b.dv_a, cap);
@@ -124,7 +124,7 @@ hipError_t ensure_chunks(ChunkList &c, size_t need) {
 }
 
 void free_frame_buffers(FrameBuffers &b) {
-    void **ps[] = {(void **)&b.gs, (void **)&b.rect, (void **)&b.count, (void **)&b.mask, (void **)&b.dkey,
+    void **ps[] = {(void **)&b.gs, (void **)&b.rect, (void **)&b.count, (void **)&b.erec, (void **)&b.dkey,
                    (void **)&b.dk_b, (void **)&b.dv_a, (void **)&b.dv_b, (void **)&b.offsets, (void **)&b.ranges,
                    (void **)&b.T, (void **)&b.last};
     for (void **p : ps) free_p(*p);
@@ -248,7 +248,7 @@ void enqueue_front(const DevScene &sc, const DevPrepared *pp, const DevCamera &c
     // ---- stage 1: preprocess + exact tile count -------------------------------
     launch_fill_u32(reinterpret_cast<uint32_t *>(fc), 0u, sizeof(FrameCounters) / 4, s);
     mk.mark(0, s);
-    launch_preprocess(sc, pp, cam, op, W, H, fb.gs, fb.rect, fb.count, fb.mask, fb.dkey, ch.chunks, chunk_cap, fc,
+    launch_preprocess(sc, pp, cam, op, W, H, fb.gs, fb.rect, fb.count, fb.erec, fb.dkey, ch.chunks, chunk_cap, fc,
                       s);
     launch_big_count(W, H, op.binning, fb.gs, fb.rect, ch.chunks, chunk_cap, ch.hits, ch.mask, fb.count, fc, s);
     // ---- depth order of the visible Gaussians: 4 LSD passes over the depth
@@ -277,9 +277,8 @@ bool enqueue_back(int W, int H, const DevOptions &op, uint32_t P, FrameBuffers &
     const uint32_t chunk_cap = (uint32_t)std::min<size_t>(ch.cap, 0xffffffffu);
     const uint32_t pair_cap = (uint32_t)std::min<size_t>(fb.capN, 0xffffffffu);
     // ---- stage 2b: key emission -------------------------------------------------
-    launch_emit(W, H, fb.dv_a, P, &fc->visible, fb.offsets, fb.rect, fb.count, fb.mask, fb.tk_a, fb.tv_a, pair_cap,
-                s);
-    launch_big_emit(W, fb.rect, fb.mask, ch.chunks, chunk_cap, ch.hits, ch.mask, fb.tk_a, fb.tv_a, pair_cap, fc, s);
+    launch_emit(W, H, fb.dv_a, P, &fc->visible, fb.offsets, fb.erec, fb.tk_a, fb.tv_a, pair_cap, s);
+    launch_big_emit(W, fb.rect, fb.erec, ch.chunks, chunk_cap, ch.hits, ch.mask, fb.tk_a, fb.tv_a, pair_cap, fc, s);
     mk.mark(4, s);
     // ---- stage 3: stable LSD sort of the pairs by tile id ---------------------------
     int shifts[4] = {0, 0, 0, 0}, widths[4] = {0, 0, 0, 0};

@@ -21,7 +21,7 @@ struct FrameBuffers {
     GaussState *gs = nullptr;
     uint4 *rect = nullptr;
     uint32_t *count = nullptr;
-    uint2 *mask = nullptr;
+    uint4 *erec = nullptr;  // emission record: rectangle (16-bit) and hit mask
     uint32_t *dkey = nullptr, *dk_b = nullptr, *dv_a = nullptr, *dv_b = nullptr;
     uint32_t *offsets = nullptr;
     // per pair (ping-pong for the LSD passes)
@@ -33,7 +33,7 @@ struct FrameBuffers {
     uint32_t *last = nullptr;
 
     size_t gauss_bytes() const {
-        return capP * (sizeof(GaussState) + sizeof(uint4) + sizeof(uint32_t) + sizeof(uint2) + 4 * sizeof(uint32_t)) +
+        return capP * (sizeof(GaussState) + sizeof(uint4) + sizeof(uint32_t) + sizeof(uint4) + 4 * sizeof(uint32_t)) +
                (capP + 1) * sizeof(uint32_t);
     }
     size_t bytes() const {

@@ -34,6 +34,7 @@
 
 #include "fgs.h"
 #include "fgs_internal.hpp"
+#include "arena.hpp"
 #include "pipeline.hpp"
 
 using namespace fgs;
@@ -46,63 +47,7 @@ int64_t now_ns() {
         .count();
 }
 
-constexpr size_t kAlign = 256;
-
-size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-// First-fit allocator over one device allocation (offsets only).
-class Arena {
-  public:
-    void init(size_t bytes) {
-        size_ = bytes;
-        free_.clear();
-        free_[0] = bytes;
-        used_ = 0;
-    }
-    bool alloc(size_t bytes, size_t *off) {
-        bytes = align_up(bytes);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                *off = it->first;
-                const size_t rest = it->second - bytes;
-                const size_t at = it->first + bytes;
-                free_.erase(it);
-                if (rest) free_[at] = rest;
-                used_ += bytes;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes) {
-        bytes = align_up(bytes);
-        used_ -= bytes;
-        auto it = free_.emplace(off, bytes).first;
-        auto next = std::next(it);
-        if (next != free_.end() && it->first + it->second == next->first) {
-            it->second += next->second;
-            free_.erase(next);
-        }
-        if (it != free_.begin()) {
-            auto prev = std::prev(it);
-            if (prev->first + prev->second == it->first) {
-                prev->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-    size_t largest_free() const {
-        size_t m = 0;
-        for (auto &f : free_) m = std::max(m, f.second);
-        return m;
-    }
-    size_t used() const { return used_; }
-    size_t size() const { return size_; }
-
-  private:
-    std::map<size_t, size_t> free_;
-    size_t size_ = 0, used_ = 0;
-};
+size_t align_up(size_t x) { return arena_align(x); }
 
 struct Request {
     uint64_t id = 0;
@@ -399,17 +344,8 @@ void worker_main(fgs_server *srv) {
             for (Slot &s : srv->slots)
                 if (s.state == SlotState::WAIT) waiting.push_back(&s);
             std::sort(waiting.begin(), waiting.end(), [](Slot *a, Slot *b) { return a->req.seq < b->req.seq; });
-            Slot *blocked = nullptr;  // oldest request that did not fit
-            for (Slot *s : waiting) {
-                if (blocked && blocked->bypassed >= max_bypass) break;
-                if (!ensure_region(srv, *s)) {
-                    if (!blocked) blocked = s;
-                    continue;
-                }
-                if (blocked) {
-                    blocked->bypassed += 1;
-                    srv->wst.bypasses += 1;
-                }
+            auto try_admit = [&](Slot *s) {
+                if (!ensure_region(srv, *s)) return false;
                 s->admit_ns = now_ns();
                 const hipError_t e = start_back(srv, *s);
                 progress = true;
@@ -417,7 +353,10 @@ void worker_main(fgs_server *srv) {
                     set_error(srv, hipGetErrorString(e));
                     finish(srv, *s, FGS_ERR_DEVICE);
                 }
-            }
+                return true;
+            };
+            auto bypassed = [](Slot *s) -> int & { return s->bypassed; };
+            (void)admit_fifo_bounded_bypass(waiting, max_bypass, try_admit, bypassed, &srv->wst.bypasses);
         }
         // 4. completed images
         for (Slot &s : srv->slots) {
@@ -527,7 +466,7 @@ fgs_status fgs_server_create(int device, const fgs_scene *scene, const fgs_optio
     if (e == hipSuccess) e = build_prepared(*scene, srv->opt, srv->prep, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     srv->pdev = srv->prep.dev();
-    srv->arena.init((size_t)cfg->budget_bytes / kAlign * kAlign);
+    srv->arena.init((size_t)cfg->budget_bytes);
     srv->slots.resize((size_t)cfg->max_inflight);
     size_t slot_bytes = 0;
     for (int i = 0; i < cfg->max_inflight && e == hipSuccess; ++i) {
