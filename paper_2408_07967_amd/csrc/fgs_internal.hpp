@@ -40,6 +40,7 @@ struct DevPrepared {
     const float4 *pos_o;  // (x, y, z, opacity); opacity 0: never visible
     const float4 *cov;    // 2 per Gaussian: (S00, S01, S02, S11), (S12, S22, k^2, log2 o)
     const float *sh;      // Gaussian-major SH, sh_stride floats per Gaussian
+    const float2 *bnd;    // (trace of the 3D covariance, k^2): bounds the screen extent
     int sh_stride;
 };
 
@@ -86,15 +87,22 @@ unsigned emit_grid(uint32_t visible);
 // `chunks` (capacity chunk_cap; on overflow the error bit kErrChunkOverflow
 // is set and the host renders the frame again with a larger list) and get
 // count 0 and record (rectangle, 0, first chunk).
-// pp: NULL (raw parameters) or the scene's precompute.
+// pp: NULL (raw parameters) or the scene's precompute.  With a precompute a
+// cull pass of kCullBlocks workgroups first writes dkey = kInvalidKey and
+// count = 0 for every Gaussian and lists, for each workgroup's contiguous
+// range, the Gaussians that may be visible (in index order, at the start of
+// the range in cand, capacity sc.P; their number in seg_count[workgroup]),
+// and the preprocess runs over those lists only.
+constexpr int kCullBlocks = 2048;
 void launch_preprocess(const DevScene &sc, const DevPrepared *pp, const DevCamera &cam, const DevOptions &op,
                        int W, int H, GaussState *gs, uint4 *rect, uint32_t *count, uint4 *erec, uint32_t *dkey,
-                       uint2 *chunks, uint32_t chunk_cap, FrameCounters *fc, hipStream_t s);
+                       uint32_t *cand, uint32_t *seg_count, uint2 *chunks, uint32_t chunk_cap, FrameCounters *fc,
+                       hipStream_t s);
 
 // View-independent precompute (opacity, 3D covariance, k^2, log2 opacity,
 // Gaussian-major SH) for options op (alpha_min and cap_3sigma).
-void launch_prepare(const DevScene &sc, const DevOptions &op, float4 *pos_o, float4 *cov, float *sh, int sh_stride,
-                    hipStream_t s);
+void launch_prepare(const DevScene &sc, const DevOptions &op, float4 *pos_o, float4 *cov, float *sh, float2 *bnd,
+                    int sh_stride, hipStream_t s);
 
 // Exact tile counts of the chunked Gaussians: per-chunk hit masks and counts,
 // atomic per-Gaussian sums.

@@ -212,7 +212,7 @@ __device__ __forceinline__ float extent_k2(float o, const DevOptions &op) {
 // operations as the per-frame path, so frames render bit for bit the same.
 __global__ __launch_bounds__(kBlock) void k_prepare(DevScene sc, DevOptions op, float4 *__restrict__ pos_o,
                                                     float4 *__restrict__ cov, float *__restrict__ sh_out,
-                                                    int sh_stride) {
+                                                    float2 *__restrict__ bnd, int sh_stride) {
     const int64_t st = sc.stride;
     const int ncoef = 3 * (sc.D + 1) * (sc.D + 1);
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < sc.P;
@@ -234,10 +234,98 @@ __global__ __launch_bounds__(kBlock) void k_prepare(DevScene sc, DevOptions op, 
         pos_o[g] = make_float4(mx, my, mz, ok ? o : 0.0f);
         cov[2 * g] = make_float4(S[0], S[1], S[2], S[3]);
         cov[2 * g + 1] = make_float4(S[4], S[5], k2, l2o);
+        // trace(Sigma) >= its largest eigenvalue: bounds the screen extent
+        bnd[g] = make_float2(S[0] + S[3] + S[5], k2);
         float *dst = sh_out + g * sh_stride;
         for (int j = 0; j < ncoef; ++j) dst[j] = sc.sh[(int64_t)j * st + g];
         for (int j = ncoef; j < sh_stride; ++j) dst[j] = 0.0f;
     }
+}
+
+// Gaussians [lo, hi) of cull workgroup b of kCullBlocks: whole 256-Gaussian
+// batches split evenly.
+__device__ __forceinline__ void cull_range(int64_t P, uint32_t b, int64_t *lo, int64_t *hi) {
+    const int64_t batches = (P + kBlock - 1) / kBlock;
+    *lo = batches * b / kCullBlocks * kBlock;
+    const int64_t h = batches * (b + 1) / kCullBlocks * kBlock;
+    *hi = h < P ? h : P;
+    if (*lo > *hi) *lo = *hi;
+}
+
+// Cull of a prepared scene: reads 24 bytes per Gaussian and keeps those in
+// front of the near plane, above the opacity threshold and whose extent may
+// reach a pixel sample.  The extent test is conservative: Sigma'_xx =
+// t0^T Sigma t0 <= |t0|^2 trace(Sigma) for the row t0 of T = J R_cam, so
+// sqrt(k^2 (|t0|^2 trace + dilation)) (or the 3 sigma radius plus one for the
+// square box) bounds the half-width of the box, and a 0.1 % + 3 px margin
+// covers rounding.  Everything it drops the exact path would cull too.  Each
+// workgroup owns a contiguous range of Gaussians and lists its candidates in
+// index order at the start of that range (no global atomics); every
+// Gaussian's depth key starts invalid and its tile count zero.
+__global__ __launch_bounds__(kBlock) void k_cull(DevScene sc, DevPrepared pp, DevCamera cam, DevOptions op, int W,
+                                                 int H, uint32_t *__restrict__ dkey, uint32_t *__restrict__ count,
+                                                 uint32_t *__restrict__ cand, uint32_t *__restrict__ seg_count) {
+    __shared__ uint32_t s_w[kBlock / kWave];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    int64_t lo, hi;
+    cull_range(sc.P, blockIdx.x, &lo, &hi);
+    uint32_t n = 0;  // candidates of this workgroup so far (uniform)
+    for (int64_t g0 = lo; g0 < hi; g0 += kBlock) {
+        const int64_t g = g0 + threadIdx.x;
+        bool keep = false;
+        if (g < hi) {
+            dkey[g] = kInvalidKey;
+            count[g] = 0u;
+            const float4 p4 = pp.pos_o[g];
+            const float *R = cam.R;
+            const float tx = ((R[0] * p4.x + R[1] * p4.y) + R[2] * p4.z) + cam.t[0];
+            const float ty = ((R[3] * p4.x + R[4] * p4.y) + R[5] * p4.z) + cam.t[1];
+            const float tz = ((R[6] * p4.x + R[7] * p4.y) + R[8] * p4.z) + cam.t[2];
+            keep = tz > cam.near_z && p4.w > op.alpha_min && isfinite(p4.x) && isfinite(p4.y) && isfinite(p4.z);
+            if (keep) {
+                const float2 b = pp.bnd[g];
+                const float iz = 1.0f / tz;
+                const float xt = tx * iz, yt = ty * iz;
+                const float limx = op.jac_clip * (0.5f * (float)W / cam.fx);
+                const float limy = op.jac_clip * (0.5f * (float)H / cam.fy);
+                const float xc = fminf(fmaxf(xt, -limx), limx), yc = fminf(fmaxf(yt, -limy), limy);
+                const float J00 = cam.fx * iz, J02 = -cam.fx * xc * iz, J11 = cam.fy * iz, J12 = -cam.fy * yc * iz;
+                float n0 = 0.0f, n1 = 0.0f;
+                for (int j = 0; j < 3; ++j) {
+                    const float t0 = J00 * R[j] + J02 * R[6 + j], t1 = J11 * R[3 + j] + J12 * R[6 + j];
+                    n0 += t0 * t0;
+                    n1 += t1 * t1;
+                }
+                float hx, hy;
+                if (op.binning == 2) {
+                    // square of radius ceil(3 sqrt(lambda_max(Sigma'))), lambda_max <= trace
+                    hx = sqrtf(9.0f * ((n0 + n1) * b.x + op.dilation)) * 1.001f + 3.0f;
+                    hy = hx;
+                } else {
+                    hx = sqrtf(b.y * (n0 * b.x + op.dilation)) * 1.001f + 3.0f;
+                    hy = sqrtf(b.y * (n1 * b.x + op.dilation)) * 1.001f + 3.0f;
+                }
+                const float u = cam.fx * xt + cam.cx, v = cam.fy * yt + cam.cy;
+                // drop only what is certainly off the image (a NaN keeps it)
+                const bool out = (u + hx < 0.0f) || (u - hx > (float)W) || (v + hy < 0.0f) || (v - hy > (float)H);
+                keep = !out;
+            }
+        }
+        // ordered compaction into this workgroup's own segment
+        const uint64_t bal = __ballot(keep);
+        if (lane == 0) s_w[wave] = (uint32_t)__popcll(bal);
+        __syncthreads();
+        uint32_t before = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / kWave; ++w) {
+            before += w < wave ? s_w[w] : 0u;
+            tot += s_w[w];
+        }
+        if (keep) cand[lo + n + before + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull))] = (uint32_t)g;
+        n += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) seg_count[blockIdx.x] = n;
 }
 
 template <bool kPrep>
@@ -245,8 +333,9 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevPrepared 
                                                        int W, int H, GaussState *__restrict__ gs,
                                                        uint4 *__restrict__ rect, uint32_t *__restrict__ count,
                                                        uint4 *__restrict__ erec, uint32_t *__restrict__ dkey,
-                                                       uint2 *__restrict__ chunks, uint32_t chunk_cap,
-                                                       FrameCounters *fc) {
+                                                       const uint32_t *__restrict__ cand,
+                                                       const uint32_t *__restrict__ seg_count, uint2 *__restrict__ chunks,
+                                                       uint32_t chunk_cap, FrameCounters *fc) {
     // Persistent grid: each workgroup walks batches of 256 Gaussians and keeps
     // its depth-digit histogram, visible count and pending chunk reservations
     // in LDS, so global atomics are per workgroup, not per batch.
@@ -286,8 +375,30 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevPrepared 
     };
 
     const int lane = threadIdx.x & (kWave - 1);
-    for (int64_t g0 = (int64_t)blockIdx.x * kBlock; g0 < sc.P; g0 += (int64_t)gridDim.x * kBlock) {
-    const int64_t g = g0 + threadIdx.x;
+    // a prepared scene walks the cull's candidate segments, raw parameters
+    // walk every Gaussian; g = sc.P marks an idle lane
+    int64_t batch = blockIdx.x;   // raw: batch of 256 Gaussians
+    uint32_t seg = blockIdx.x;    // prepared: candidate segment and offset in it
+    uint32_t off = 0;
+    for (;;) {
+    int64_t g = sc.P;
+    if constexpr (kPrep) {
+        while (seg < (uint32_t)kCullBlocks && off >= seg_count[seg]) {
+            seg += gridDim.x;
+            off = 0;
+        }
+        if (seg >= (uint32_t)kCullBlocks) break;
+        int64_t lo, hi;
+        cull_range(sc.P, seg, &lo, &hi);
+        const uint32_t ii = off + threadIdx.x;
+        if (ii < seg_count[seg]) g = (int64_t)cand[lo + ii];
+        off += kBlock;
+    } else {
+        if (batch * kBlock >= sc.P) break;
+        const int64_t ii = batch * kBlock + threadIdx.x;
+        if (ii < sc.P) g = ii;
+        batch += gridDim.x;
+    }
     const int64_t st = sc.stride;
     bool valid = false;
     float u = 0, v = 0, A = 0, B = 0, C = 0, k2 = 0, o = 0, tz = 0, l2o = 0;
@@ -414,19 +525,31 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevPrepared 
                             sh_basis(dxw / dn, dyw / dn, dzw / dn, sc.D, Y);
                             const int nk = (sc.D + 1) * (sc.D + 1);
                             float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+                            // every coefficient load is issued before the first
+                            // use (one memory round trip, not one per coefficient)
+                            const int ncoef = 3 * nk;
+                            float shv[48];
                             if constexpr (kPrep) {
                                 // Gaussian-major coefficients: one contiguous read
-                                const float *shg = pp.sh + (int64_t)g * pp.sh_stride;
-                                for (int k = 0; k < nk; ++k) {
-                                    a0 = a0 + shg[3 * k + 0] * Y[k];
-                                    a1 = a1 + shg[3 * k + 1] * Y[k];
-                                    a2 = a2 + shg[3 * k + 2] * Y[k];
+                                const float4 *shg = reinterpret_cast<const float4 *>(pp.sh + (int64_t)g * pp.sh_stride);
+#pragma unroll
+                                for (int j = 0; j < 12; ++j) {
+                                    const float4 q4 = 4 * j < ncoef ? shg[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+                                    shv[4 * j] = q4.x;
+                                    shv[4 * j + 1] = q4.y;
+                                    shv[4 * j + 2] = q4.z;
+                                    shv[4 * j + 3] = q4.w;
                                 }
                             } else {
-                                for (int k = 0; k < nk; ++k) {
-                                    a0 = a0 + sc.sh[(int64_t)(3 * k + 0) * st + g] * Y[k];
-                                    a1 = a1 + sc.sh[(int64_t)(3 * k + 1) * st + g] * Y[k];
-                                    a2 = a2 + sc.sh[(int64_t)(3 * k + 2) * st + g] * Y[k];
+#pragma unroll
+                                for (int j = 0; j < 48; ++j) shv[j] = j < ncoef ? sc.sh[(int64_t)j * st + g] : 0.0f;
+                            }
+#pragma unroll
+                            for (int k = 0; k < 16; ++k) {
+                                if (k < nk) {
+                                    a0 = a0 + shv[3 * k + 0] * Y[k];
+                                    a1 = a1 + shv[3 * k + 1] * Y[k];
+                                    a2 = a2 + shv[3 * k + 2] * Y[k];
                                 }
                             }
                             a0 = a0 + 0.5f;
@@ -738,22 +861,26 @@ unsigned emit_grid(uint32_t visible) {
 
 void launch_preprocess(const DevScene &sc, const DevPrepared *pp, const DevCamera &cam, const DevOptions &op,
                        int W, int H, GaussState *gs, uint4 *rect, uint32_t *count, uint4 *erec, uint32_t *dkey,
-                       uint2 *chunks, uint32_t chunk_cap, FrameCounters *fc, hipStream_t s) {
+                       uint32_t *cand, uint32_t *seg_count, uint2 *chunks, uint32_t chunk_cap, FrameCounters *fc,
+                       hipStream_t s) {
     if (sc.P <= 0) return;
-    if (pp)
+    if (pp) {
+        hipLaunchKernelGGL(k_cull, dim3(kCullBlocks), dim3(kBlock), 0, s, sc, *pp, cam, op, W, H, dkey, count, cand,
+                           seg_count);
         hipLaunchKernelGGL(k_preprocess<true>, dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, *pp, cam, op, W,
-                           H, gs, rect, count, erec, dkey, chunks, chunk_cap, fc);
-    else
+                           H, gs, rect, count, erec, dkey, cand, seg_count, chunks, chunk_cap, fc);
+    } else {
         hipLaunchKernelGGL(k_preprocess<false>, dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, DevPrepared{},
-                           cam, op, W, H, gs, rect, count, erec, dkey, chunks, chunk_cap, fc);
+                           cam, op, W, H, gs, rect, count, erec, dkey, cand, seg_count, chunks, chunk_cap, fc);
+    }
 }
 
-void launch_prepare(const DevScene &sc, const DevOptions &op, float4 *pos_o, float4 *cov, float *sh, int sh_stride,
-                    hipStream_t s) {
+void launch_prepare(const DevScene &sc, const DevOptions &op, float4 *pos_o, float4 *cov, float *sh, float2 *bnd,
+                    int sh_stride, hipStream_t s) {
     if (sc.P <= 0) return;
     const int64_t blocks = (sc.P + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_prepare, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(kBlock), 0, s, sc, op,
-                       pos_o, cov, sh, sh_stride);
+                       pos_o, cov, sh, bnd, sh_stride);
 }
 
 void launch_big_count(int W, int H, int binning, const GaussState *gs, const uint4 *rect, const uint2 *chunks,

@@ -74,6 +74,7 @@ hipError_t ensure_gauss(FrameBuffers &b, size_t P) {
     FGS_GROW(b.dv_a, cap);
     FGS_GROW(b.dv_b, cap);
     FGS_GROW(b.offsets, cap + 1);
+    FGS_GROW(b.seg_count, kCullBlocks);
     b.capP = cap;
     return hipSuccess;
 }
@@ -125,7 +126,8 @@ hipError_t ensure_chunks(ChunkList &c, size_t need) {
 
 void free_frame_buffers(FrameBuffers &b) {
     void **ps[] = {(void **)&b.gs, (void **)&b.rect, (void **)&b.count, (void **)&b.erec, (void **)&b.dkey,
-                   (void **)&b.dk_b, (void **)&b.dv_a, (void **)&b.dv_b, (void **)&b.offsets, (void **)&b.ranges,
+                   (void **)&b.dk_b, (void **)&b.dv_a, (void **)&b.dv_b, (void **)&b.offsets, (void **)&b.seg_count,
+                   (void **)&b.ranges,
                    (void **)&b.T, (void **)&b.last};
     for (void **p : ps) free_p(*p);
     if (b.pairs_owned) {
@@ -230,7 +232,8 @@ hipError_t build_prepared(const fgs_scene &sc, const fgs_options &op, PreparedBu
     if ((e = hipMalloc((void **)&pb.pos_o, n * sizeof(float4))) != hipSuccess) return e;
     if ((e = hipMalloc((void **)&pb.cov, 2 * n * sizeof(float4))) != hipSuccess) return e;
     if ((e = hipMalloc((void **)&pb.sh, n * (size_t)pb.sh_stride * sizeof(float))) != hipSuccess) return e;
-    launch_prepare(to_dev(sc), to_dev(op), pb.pos_o, pb.cov, pb.sh, pb.sh_stride, s);
+    if ((e = hipMalloc((void **)&pb.bnd, n * sizeof(float2))) != hipSuccess) return e;
+    launch_prepare(to_dev(sc), to_dev(op), pb.pos_o, pb.cov, pb.sh, pb.bnd, pb.sh_stride, s);
     return hipGetLastError();
 }
 
@@ -238,6 +241,7 @@ void free_prepared(PreparedBuffers &pb) {
     free_p(*(void **)&pb.pos_o);
     free_p(*(void **)&pb.cov);
     free_p(*(void **)&pb.sh);
+    free_p(*(void **)&pb.bnd);
     pb = PreparedBuffers{};
 }
 
@@ -248,8 +252,9 @@ void enqueue_front(const DevScene &sc, const DevPrepared *pp, const DevCamera &c
     // ---- stage 1: preprocess + exact tile count -------------------------------
     launch_fill_u32(reinterpret_cast<uint32_t *>(fc), 0u, sizeof(FrameCounters) / 4, s);
     mk.mark(0, s);
-    launch_preprocess(sc, pp, cam, op, W, H, fb.gs, fb.rect, fb.count, fb.erec, fb.dkey, ch.chunks, chunk_cap, fc,
-                      s);
+    // the candidate list of a prepared scene lives in dv_b until the depth sort
+    launch_preprocess(sc, pp, cam, op, W, H, fb.gs, fb.rect, fb.count, fb.erec, fb.dkey, fb.dv_b, fb.seg_count,
+                      ch.chunks, chunk_cap, fc, s);
     launch_big_count(W, H, op.binning, fb.gs, fb.rect, ch.chunks, chunk_cap, ch.hits, ch.mask, fb.count, fc, s);
     // ---- depth order of the visible Gaussians: 4 LSD passes over the depth
     // digits, hoisted before key duplication (the low half of the (tile |

@@ -24,6 +24,7 @@ struct FrameBuffers {
     uint4 *erec = nullptr;  // emission record: rectangle (16-bit) and hit mask
     uint32_t *dkey = nullptr, *dk_b = nullptr, *dv_a = nullptr, *dv_b = nullptr;
     uint32_t *offsets = nullptr;
+    uint32_t *seg_count = nullptr;  // kCullBlocks candidate counts of a prepared scene's cull
     // per pair (ping-pong for the LSD passes)
     uint32_t *tk_a = nullptr, *tk_b = nullptr, *tv_a = nullptr, *tv_b = nullptr;
     bool pairs_owned = true;  // false: the pair arrays live in a caller's arena
@@ -34,7 +35,7 @@ struct FrameBuffers {
 
     size_t gauss_bytes() const {
         return capP * (sizeof(GaussState) + sizeof(uint4) + sizeof(uint32_t) + sizeof(uint4) + 4 * sizeof(uint32_t)) +
-               (capP + 1) * sizeof(uint32_t);
+               (capP + 1) * sizeof(uint32_t) + kCullBlocks * sizeof(uint32_t);
     }
     size_t bytes() const {
         return gauss_bytes() + (pairs_owned ? capN * 4 * sizeof(uint32_t) : 0) + capTiles * sizeof(uint2) +
@@ -99,10 +100,13 @@ struct PreparedBuffers {
     float4 *pos_o = nullptr;
     float4 *cov = nullptr;
     float *sh = nullptr;
+    float2 *bnd = nullptr;
     int sh_stride = 0;
     int64_t P = 0;
-    size_t bytes() const { return (size_t)P * (3 * sizeof(float4) + (size_t)sh_stride * sizeof(float)); }
-    DevPrepared dev() const { return DevPrepared{pos_o, cov, sh, sh_stride}; }
+    size_t bytes() const {
+        return (size_t)P * (3 * sizeof(float4) + sizeof(float2) + (size_t)sh_stride * sizeof(float));
+    }
+    DevPrepared dev() const { return DevPrepared{pos_o, cov, sh, bnd, sh_stride}; }
 };
 
 // Allocate and fill the precompute of sc for options op on stream s.

@@ -128,7 +128,8 @@ def test_3sigma_square_binning_parity(orc, R, scenes, kind, P, W, H):
     assert mx < 1e-5, mx
 
 
-@pytest.mark.parametrize("case", ["small", "random_sh3", "degenerate", "medium_binning2", "uncapped"])
+@pytest.mark.parametrize("case", ["small", "random_sh3", "degenerate", "medium_binning2", "uncapped",
+                                  "offscreen_big", "offscreen_big_binning2"])
 def test_prepared_scene_is_bit_identical(orc, R, scenes, case):
     """A frame from the view-independent precompute equals the frame from the
     raw parameters bit for bit (state, pairs, order, image, T, last)."""
@@ -155,6 +156,14 @@ def test_prepared_scene_is_bit_identical(orc, R, scenes, case):
         W, H = 960, 540
         cam = scenes.camera_for("medium", 3, W=W, H=H)
         o = opts(binning=2)
+    elif case.startswith("offscreen_big"):
+        # wide, elongated Gaussians centred off the image whose footprints
+        # reach into it: the cull of a prepared scene must keep them
+        rng = np.random.default_rng(33)
+        sc = random_scene(rng, 3000, box=3.0, ls_mu=-1.2, ls_sigma=0.8, sh_degree=1)
+        W, H = 200, 120
+        cam = identity_camera(W, H, 60.0)
+        o = opts(binning=2) if case.endswith("binning2") else opts()
     else:
         sc, cam, W, H = scenes.make_scene("small"), scenes.camera_for("small"), 256, 256
         o = opts(cap_3sigma=0, alpha_min=0.01)
