@@ -45,8 +45,12 @@ def log(*a):
 
 
 def kernel_source_hash():
-    p = os.path.join(ROOT, "paper_2408_07967_amd", "csrc", "k_blend.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    """Hash of the blend kernel's sources (the kernel file and its shared
+    per-pixel arithmetic)."""
+    h = hashlib.sha256()
+    for f in ("k_blend.hip", "blend_common.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2408_07967_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def traffic_from_profiles(workload, evals_per_launch):
@@ -118,12 +122,27 @@ def serving_leg(args):
         srv.close()
     ss = latency_summary(res)
     log(f"[bench] server: {ss} stats {st}")
+    # a high-load point of the same workload, where the plain renderer queues
+    hi_rate = 2.5 * args.serve_rate
+    hi_trace = make_trace(hi_rate, min(args.serve_seconds, 8.0), seed=7)
+    R = Renderer(0)
+    hp = latency_summary(replay_plain(R, gsc, None, hi_trace))
+    R.close()
+    srv = RenderServer(gsc, budget_bytes=SERVE_BUDGET, max_inflight=SERVE_SLOTS, max_bypass=4)
+    try:
+        srv.replay(warm)
+        hs = latency_summary(srv.replay(hi_trace))
+    finally:
+        srv.close()
+    log(f"[bench] at {hi_rate:.0f}/s: plain {hp} server {hs}")
     rnd = lambda d: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
     return dict(workload=f"serve-6M-gaussians-poisson{args.serve_rate:.0f}-{args.serve_seconds:.0f}s-"
                          f"720p-1080p-1440p-2160p",
                 requests=len(trace), server=rnd(ss), plain=rnd(ps),
                 p50_ratio_plain_over_server=round(ps["p50_ms"] / ss["p50_ms"], 3),
                 p99_ratio_plain_over_server=round(ps["p99_ms"] / ss["p99_ms"], 3),
+                high_load=dict(rate_per_s=hi_rate, requests=len(hi_trace), server=rnd(hs), plain=rnd(hp),
+                               p99_ratio_plain_over_server=round(hp["p99_ms"] / hs["p99_ms"], 3)),
                 budget_bytes=SERVE_BUDGET, slots=SERVE_SLOTS,
                 peak_bytes_in_use=st["peak_bytes_in_use"], graphs_captured=st["graphs_captured"],
                 graph_launches=st["graph_launches"], bypasses=st["bypasses"],

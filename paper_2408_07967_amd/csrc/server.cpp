@@ -263,6 +263,8 @@ void worker_main(fgs_server *srv) {
     }
     std::deque<Request> pending;
     const int max_bypass = srv->cfg.max_bypass;
+    constexpr int64_t kSpinIdleNs = 50'000'000;  // 50 ms
+    int64_t idle_since = now_ns();
     for (;;) {
         bool progress = false;
         bool in_flight = false;
@@ -287,9 +289,17 @@ void worker_main(fgs_server *srv) {
                 in_flight |= (s.state == SlotState::FRONT || s.state == SlotState::WAIT || s.state == SlotState::BACK);
             if (srv->stop && pending.empty() && !in_flight) return;
             if (!in_flight && pending.empty()) {
-                srv->cv_work.wait_for(lk, std::chrono::milliseconds(2));
+                // idle: keep polling (yielding the core) for a while so a new
+                // request starts without a sleep/wake-up delay, then sleep
+                if (now_ns() - idle_since > kSpinIdleNs) {
+                    srv->cv_work.wait_for(lk, std::chrono::milliseconds(2));
+                } else {
+                    lk.unlock();
+                    std::this_thread::yield();
+                }
                 continue;
             }
+            idle_since = now_ns();
         }
         // 1. start the first half of queued requests on free slots (FIFO)
         for (Slot &s : srv->slots) {
