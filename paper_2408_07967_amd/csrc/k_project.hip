@@ -101,42 +101,77 @@ __device__ __forceinline__ uint32_t bcast(uint32_t x, int lane) {
 // the discriminant guard).  Centre inside -> hit; otherwise each edge line
 // meets the ellipse in a chord whose overlap with the edge segment is decided
 // without division or square root.
-__device__ __forceinline__ bool tile_hit(float u, float v, float A, float B, float C, float k2, int tx, int ty,
-                                         int W, int H) {
+//
+// The test splits into terms of the tile's column alone and of its row alone,
+// so that the tiles of one rectangle can share them; tile_hit is the two
+// halves combined, with the same binary32 operations in the same order.
+//
+// Column terms (hull x-range [x0, x1] relative to u):
+//   a = (2A x0, 2A x1, bq(x0), delta(x0)), b = (bq(x1), delta(x1), flag, 0)
+// with bq(x) = 2B x and delta(x) = bq^2 - 4C (A x^2 - k2) for the vertical
+// edge at x (quadratic in y), and flag = 1 if x0 <= 0 <= x1.
+__device__ __forceinline__ void tile_col_terms(float u, float A, float B, float C, float k2, int tx, int W,
+                                               float4 &a, float4 &b) {
     int xe = kTile * tx + kTile;
     xe = xe > W ? W : xe;
+    const float x0 = ((float)(kTile * tx) + 0.5f) - u;
+    const float x1 = ((float)xe - 0.5f) - u;
+    const float A2 = 2.0f * A, B2 = 2.0f * B, C4 = 4.0f * C;
+    const float bq0 = B2 * x0, bq1 = B2 * x1;
+    const float cq0 = (A * x0) * x0 - k2, cq1 = (A * x1) * x1 - k2;
+    a = make_float4(A2 * x0, A2 * x1, bq0, bq0 * bq0 - C4 * cq0);
+    b = make_float4(bq1, bq1 * bq1 - C4 * cq1, (x0 <= 0.0f && 0.0f <= x1) ? 1.0f : 0.0f, 0.0f);
+}
+
+// Row terms (hull y-range [y0, y1] relative to v):
+//   a = (bq(y0), delta(y0), bq(y1), delta(y1)), b = (2C y0, 2C y1, flag, 0)
+// with bq(y) = 2B y and delta(y) = bq^2 - 4A (C y^2 - k2) for the horizontal
+// edge at y (quadratic in x), and flag = 1 if y0 <= 0 <= y1.
+__device__ __forceinline__ void tile_row_terms(float v, float A, float B, float C, float k2, int ty, int H,
+                                               float4 &a, float4 &b) {
     int ye = kTile * ty + kTile;
     ye = ye > H ? H : ye;
-    float x0 = ((float)(kTile * tx) + 0.5f) - u;
-    float x1 = ((float)xe - 0.5f) - u;
-    float y0 = ((float)(kTile * ty) + 0.5f) - v;
-    float y1 = ((float)ye - 0.5f) - v;
-    if (x0 <= 0.0f && 0.0f <= x1 && y0 <= 0.0f && 0.0f <= y1) return true;
-    const float A2 = 2.0f * A, B2 = 2.0f * B, C2 = 2.0f * C, A4 = 4.0f * A, C4 = 4.0f * C;
-    bool hit = false;
-    // edges y = y0 and y = y1 (quadratic in x: A x^2 + (2B y) x + (C y^2 - k2))
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-        float ye_ = e ? y1 : y0;
-        float bq = B2 * ye_;
-        float cq = (C * ye_) * ye_ - k2;
-        float delta = bq * bq - A4 * cq;
-        float e1 = A2 * x0 + bq;
-        float e2 = A2 * x1 + bq;
-        hit |= (delta >= 0.0f) && (e1 <= 0.0f || e1 * e1 <= delta) && (e2 >= 0.0f || e2 * e2 <= delta);
-    }
-    // edges x = x0 and x = x1 (quadratic in y: C y^2 + (2B x) y + (A x^2 - k2))
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-        float xe_ = e ? x1 : x0;
-        float bq = B2 * xe_;
-        float cq = (A * xe_) * xe_ - k2;
-        float delta = bq * bq - C4 * cq;
-        float e1 = C2 * y0 + bq;
-        float e2 = C2 * y1 + bq;
-        hit |= (delta >= 0.0f) && (e1 <= 0.0f || e1 * e1 <= delta) && (e2 >= 0.0f || e2 * e2 <= delta);
-    }
-    return hit;
+    const float y0 = ((float)(kTile * ty) + 0.5f) - v;
+    const float y1 = ((float)ye - 0.5f) - v;
+    const float B2 = 2.0f * B, C2 = 2.0f * C, A4 = 4.0f * A;
+    const float bq0 = B2 * y0, bq1 = B2 * y1;
+    const float cq0 = (C * y0) * y0 - k2, cq1 = (C * y1) * y1 - k2;
+    a = make_float4(bq0, bq0 * bq0 - A4 * cq0, bq1, bq1 * bq1 - A4 * cq1);
+    b = make_float4(C2 * y0, C2 * y1, (y0 <= 0.0f && 0.0f <= y1) ? 1.0f : 0.0f, 0.0f);
+}
+
+// One edge: the chord [r-, r+] of the quadratic with discriminant d overlaps
+// the edge segment, given e1 = 2a s0 + bq and e2 = 2a s1 + bq at its ends.
+// (Bitwise, not short-circuit, so that the test compiles to straight-line
+// code.)
+__device__ __forceinline__ bool edge_hit(float e1, float e2, float d) {
+    return (d >= 0.0f) & ((e1 <= 0.0f) | (e1 * e1 <= d)) & ((e2 >= 0.0f) | (e2 * e2 <= d));
+}
+
+__device__ __forceinline__ bool tile_hit_terms(const float4 ca, const float4 cb, const float4 ra, const float4 rb) {
+    const bool inside = (cb.z != 0.0f) & (rb.z != 0.0f);  // centre inside the hull
+    // horizontal edges y = y0, y1, then vertical edges x = x0, x1
+    return inside | edge_hit(ca.x + ra.x, ca.y + ra.x, ra.y) | edge_hit(ca.x + ra.z, ca.y + ra.z, ra.w) |
+           edge_hit(rb.x + ca.z, rb.y + ca.z, ca.w) | edge_hit(rb.x + cb.x, rb.y + cb.x, cb.y);
+}
+
+__device__ __forceinline__ bool tile_hit(float u, float v, float A, float B, float C, float k2, int tx, int ty,
+                                         int W, int H) {
+    float4 ca, cb, ra, rb;
+    tile_col_terms(u, A, B, C, k2, tx, W, ca, cb);
+    tile_row_terms(v, A, B, C, k2, ty, H, ra, rb);
+    return tile_hit_terms(ca, cb, ra, rb);
+}
+
+// Row and column of row-major position idx in rows of ntx (idx < 2^24,
+// rcpn = reciprocal of ntx): the rounded quotient estimate is off by at most
+// one and is corrected, so this equals integer division.
+__device__ __forceinline__ void row_col(int idx, int ntx, float rcpn, int &ry, int &rx) {
+    ry = (int)((float)idx * rcpn);
+    rx = idx - ry * ntx;
+    const int below = rx < 0, above = rx >= ntx;
+    ry += above - below;
+    rx += (below - above) * ntx;
 }
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, int lane) {
@@ -375,24 +410,56 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevPrepared 
     };
 
     const int lane = threadIdx.x & (kWave - 1);
-    // a prepared scene walks the cull's candidate segments, raw parameters
-    // walk every Gaussian; g = sc.P marks an idle lane
-    int64_t batch = blockIdx.x;   // raw: batch of 256 Gaussians
-    uint32_t seg = blockIdx.x;    // prepared: candidate segment and offset in it
-    uint32_t off = 0;
+    // A prepared scene walks the cull's candidates as one list: the exclusive
+    // prefix of the segment counts maps a list position to its segment, and
+    // workgroups take 256-position batches in turn, so every workgroup gets
+    // the same share whatever the segment sizes.  Raw parameters walk every
+    // Gaussian.  g = sc.P marks an idle lane.
+    static_assert((kCullBlocks & (kCullBlocks - 1)) == 0 && kCullBlocks % kBlock == 0, "segment prefix layout");
+    __shared__ uint32_t s_pref[kPrep ? kCullBlocks : 1];
+    __shared__ uint32_t s_wtot[kBlock / kWave];
+    uint32_t ncand = 0;
+    if constexpr (kPrep) {
+        constexpr int kPer = kCullBlocks / kBlock;
+        uint32_t c[kPer], sum = 0;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            c[j] = seg_count[threadIdx.x * kPer + j];
+            sum += c[j];
+        }
+        const int wave = threadIdx.x / kWave;
+        const uint32_t incl = wave_incl_scan(sum, lane);
+        if (lane == kWave - 1) s_wtot[wave] = incl;
+        __syncthreads();
+        uint32_t run = incl - sum;
+        for (int w = 0; w < kBlock / kWave; ++w) {
+            if (w < wave) run += s_wtot[w];
+            ncand += s_wtot[w];
+        }
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            s_pref[threadIdx.x * kPer + j] = run;
+            run += c[j];
+        }
+        __syncthreads();
+    }
+    int64_t batch = blockIdx.x;  // batch of 256 list positions (prepared) or Gaussians (raw)
     for (;;) {
     int64_t g = sc.P;
     if constexpr (kPrep) {
-        while (seg < (uint32_t)kCullBlocks && off >= seg_count[seg]) {
-            seg += gridDim.x;
-            off = 0;
+        if ((uint64_t)batch * kBlock >= ncand) break;
+        const uint32_t ii = (uint32_t)batch * kBlock + threadIdx.x;
+        if (ii < ncand) {
+            // last segment whose prefix is <= ii: it holds position ii
+            uint32_t sg = 0;
+#pragma unroll
+            for (uint32_t step = kCullBlocks / 2; step > 0; step >>= 1)
+                if (s_pref[sg + step] <= ii) sg += step;
+            int64_t lo, hi;
+            cull_range(sc.P, sg, &lo, &hi);
+            g = (int64_t)cand[lo + (ii - s_pref[sg])];
         }
-        if (seg >= (uint32_t)kCullBlocks) break;
-        int64_t lo, hi;
-        cull_range(sc.P, seg, &lo, &hi);
-        const uint32_t ii = off + threadIdx.x;
-        if (ii < seg_count[seg]) g = (int64_t)cand[lo + ii];
-        off += kBlock;
+        batch += gridDim.x;
     } else {
         if (batch * kBlock >= sc.P) break;
         const int64_t ii = batch * kBlock + threadIdx.x;
@@ -714,9 +781,6 @@ __global__ __launch_bounds__(kBlock) void k_emit(int W, int H, const uint32_t *_
 }
 
 
-// Exact tile counts of chunked Gaussians: one workgroup per chunk of
-// kChunkTiles tiles (persistent grid), per-chunk hit counts kept for the
-// emission, per-Gaussian totals by atomic add.
 // Exact tile tests of the chunked Gaussians: one wavefront per chunk of
 // kChunkTiles rectangle tiles (4 per lane, independent), so that every
 // workgroup keeps four chunks in flight without barriers; the next chunk's
@@ -748,13 +812,15 @@ __global__ __launch_bounds__(kBlock) void k_big_count(int W, int H, int binning,
         const int nt = ntx * ((int)rc.w - (int)rc.z + 1);
         GaussState s{};
         if (binning == 0) s = gs[g];
+        const float rcpn = __builtin_amdgcn_rcpf((float)ntx);
         uint32_t tot = 0;
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
             const int idx = (int)c * kChunkTiles + j * kWave + lane;
             bool h = false;
             if (idx < nt) {
-                const int ry = idx / ntx, rx = idx - ry * ntx;
+                int ry, rx;
+                row_col(idx, ntx, rcpn, ry, rx);
                 h = binning != 0 ||
                     tile_hit(s.f0.x, s.f0.y, s.f0.z, s.f0.w, s.f1.x, s.f1.y, (int)rc.x + rx, (int)rc.z + ry, W, H);
             }
@@ -811,12 +877,14 @@ __global__ __launch_bounds__(kBlock) void k_big_emit(int W, const uint4 *__restr
 #pragma unroll
         for (int d = 1; d < kWave; d <<= 1) p += __shfl_xor(p, d, kWave);
         const int ntx = (int)rc.y - (int)rc.x + 1;
+        const float rcpn = __builtin_amdgcn_rcpf((float)ntx);
         uint32_t before = base + p;
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
             if ((b[j] >> lane) & 1ull) {
                 const int idx = (int)c * kChunkTiles + j * kWave + lane;
-                const int ry = idx / ntx, rx = idx - ry * ntx;
+                int ry, rx;
+                row_col(idx, ntx, rcpn, ry, rx);
                 const uint32_t tile = (uint32_t)(((int)rc.z + ry) * tiles_x + ((int)rc.x + rx));
                 const uint32_t at = before + (uint32_t)__popcll(b[j] & lt);
                 if (at < cap) {  // never leave the pair buffers
