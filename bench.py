@@ -307,19 +307,27 @@ def main():
         R.set_instrumentation(B.INSTR_WORK)
         R.render(gsc, cam, W, H, opts, out=out, prepared=prep)
         evals = int(R.instrumentation()["blend_evaluations"])
+        R.set_instrumentation(0)
         log(f"[bench] blend evaluations per frame: {evals}")
 
-    R.set_instrumentation(B.INSTR_STAGE_TIMES)
+    # the timed frames run without instrumentation
+    R.set_instrumentation(0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         R.render(gsc, cam, W, H, opts, out=out, prepared=prep)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    inst = R.instrumentation()
-    R.set_instrumentation(0)
     dt = t1 - t0
     fps = args.steps / dt
+    # stage times (HIP events recorded on the render stream between stages,
+    # which adds a marker per stage) over a second run of the same frames
+    R.set_instrumentation(B.INSTR_STAGE_TIMES)
+    for _ in range(args.steps):
+        R.render(gsc, cam, W, H, opts, out=out, prepared=prep)
+    torch.cuda.synchronize()
+    inst = R.instrumentation()
+    R.set_instrumentation(0)
     nf = max(1, inst["frames"])
     stage_ms = {k[3:]: round(inst[k] / nf, 4) for k in inst if k.startswith("ms_")}
     log(f"[bench] {args.steps} frames in {dt:.3f}s -> {fps:.2f} frames/s; stages {stage_ms}")

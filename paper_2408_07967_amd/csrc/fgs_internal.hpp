@@ -76,6 +76,7 @@ constexpr uint32_t kErrChunkOverflow = 2u;       // chunk list too small: render
 // grouped by kSortGroup for the offset computation.
 constexpr int kSortBlocks = 1024;
 constexpr int kSortGroup = 32;
+constexpr int kSortGroups = (kSortBlocks + kSortGroup - 1) / kSortGroup;
 
 unsigned preprocess_grid(int64_t P);
 unsigned emit_grid(uint32_t visible);
@@ -128,7 +129,7 @@ void launch_big_emit(int W, const uint4 *rect, const uint4 *erec, const uint2 *c
 //           actual count is read there on the device
 //   vals_in null: values are the input positions
 //   filter  drop keys equal to kInvalidKey
-//   hist    scratch [kSortBlocks][kRadix]; gsum scratch [kSortBlocks/kSortGroup][kRadix]
+//   hist    scratch [kSortBlocks][kRadix]; gsum scratch [kSortGroups][kRadix]
 void launch_radix_pass(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_out, uint32_t *vals_out,
                        uint32_t n_host, const uint32_t *n_dev, int shift, int bits, bool filter, bool write_keys,
                        uint32_t *hist, uint32_t *gsum, hipStream_t s);

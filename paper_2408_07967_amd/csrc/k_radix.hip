@@ -5,7 +5,7 @@
 // owns a contiguous range of 4096-key tiles (the range is derived on the
 // device from n, so n may be a device-side count):
 //   upsweep    - digit histogram of each workgroup's range   -> hist[b][d]
-//   group sums - sum of the histograms of every kGroup
+//   group sums - sum of the histograms of every kSortGroup
 //                consecutive workgroups                      -> gsum[w][d]
 //   downsweep  - each workgroup derives the global offset of its first key
 //                of every digit (digit totals, earlier groups, earlier
@@ -14,7 +14,9 @@
 //                order, coalesced scatter, running per-digit offsets.
 // Keys are read twice (upsweep and downsweep); in exchange no workgroup ever
 // waits for another one, which on gfx950 is cheaper than a decoupled
-// look-back across eight XCDs.
+// look-back across eight XCDs.  (Handing the histograms over inside the
+// upsweep, by a release fence and an arrival counter, was measured slower:
+// a device-scope release on gfx950 writes back the XCD's L2.)
 #include "fgs_internal.hpp"
 
 namespace fgs {
@@ -104,8 +106,10 @@ __global__ __launch_bounds__(kBlock) void k_radix_groups(const uint32_t *__restr
     gsum[(size_t)blockIdx.x * kRadix + threadIdx.x] = s;
 }
 
+// (LDS holds four workgroups per CU, so registers are capped at what four
+// waves per SIMD allow.)
 template <bool kIdentityVals, bool kFilter, bool kWriteKeys>
-__global__ __launch_bounds__(kBlock) void k_radix_downsweep(const uint32_t *__restrict__ keys_in,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_radix_downsweep(const uint32_t *__restrict__ keys_in,
                                                             const uint32_t *__restrict__ vals_in,
                                                             uint32_t *__restrict__ keys_out,
                                                             uint32_t *__restrict__ vals_out, uint32_t n_host,
@@ -130,7 +134,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_downsweep(const uint32_t *__re
     // sum and every earlier histogram row of the group is loaded at once (a
     // fixed, unrolled trip count keeps all the loads in flight together)
     {
-        constexpr uint32_t kGroups = (kSortBlocks + kSortGroup - 1) / kSortGroup;
+        constexpr uint32_t kGroups = kSortGroups;
         const uint32_t mygroup = b / kSortGroup;
         uint32_t gv[kGroups], hv[kSortGroup];
 #pragma unroll
@@ -156,12 +160,12 @@ __global__ __launch_bounds__(kBlock) void k_radix_downsweep(const uint32_t *__re
 
     const uint32_t dmask = (1u << bits) - 1u;
     const uint64_t lt = (1ull << lane) - 1ull;
-    for (uint32_t t0 = lo; t0 < hi; t0 += kSortTile) {
-        for (int i = tid; i < kWaves * kRadix; i += kBlock) (&s_wave[0][0])[i] = 0;
-        __syncthreads();
-        const uint32_t base = t0 + (uint32_t)wave * (kSortItems * kWave);
-        uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
-        // all loads of the tile first, so that they are in flight together
+    // A tile's loads are all issued before any use, and the next tile's are
+    // issued as soon as the current one sits in LDS, so that they are in
+    // flight while the current tile is written out.
+    uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+    auto load_tile = [&](uint32_t t) {
+        const uint32_t base = t + (uint32_t)wave * (kSortItems * kWave);
 #pragma unroll
         for (int i = 0; i < kSortItems; ++i) {
             const uint32_t idx = base + (uint32_t)(i * kWave + lane);
@@ -169,6 +173,12 @@ __global__ __launch_bounds__(kBlock) void k_radix_downsweep(const uint32_t *__re
             key[i] = in ? keys_in[idx] : kInvalidKey;
             val[i] = kIdentityVals ? idx : (in ? vals_in[idx] : 0u);
         }
+    };
+    load_tile(lo);
+    for (uint32_t t0 = lo; t0 < hi; t0 += kSortTile) {
+        for (int i = tid; i < kWaves * kRadix; i += kBlock) (&s_wave[0][0])[i] = 0;
+        __syncthreads();
+        const uint32_t base = t0 + (uint32_t)wave * (kSortItems * kWave);
 #pragma unroll
         for (int i = 0; i < kSortItems; ++i) {
             const uint32_t idx = base + (uint32_t)(i * kWave + lane);
@@ -211,6 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_downsweep(const uint32_t *__re
                 s_vals[lp] = val[i];
             }
         }
+        if (t0 + kSortTile < hi) load_tile(t0 + kSortTile);
         __syncthreads();
         const uint32_t nv = s_nv;
         for (uint32_t j = tid; j < nv; j += kBlock) {
@@ -263,37 +274,34 @@ __global__ __launch_bounds__(kBlock) void k_scan_upsweep(const uint32_t *__restr
     if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
-// one workgroup: exclusive scan of the kSortBlocks workgroup sums; total -> *pairs
-__global__ __launch_bounds__(kBlock) void k_scan_sums(uint32_t *__restrict__ sums, uint32_t nb, uint32_t *pairs) {
-    __shared__ uint32_t s_tmp[kWaves];
-    constexpr int kPer = kSortBlocks / kBlock;
-    uint32_t v[kPer], s = 0;
-#pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-        const uint32_t idx = threadIdx.x * kPer + i;
-        v[i] = idx < nb ? sums[idx] : 0u;
-        s += v[i];
-    }
-    uint32_t tot = 0;
-    uint32_t run = block_exclusive_scan(s, s_tmp, &tot);
-#pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-        const uint32_t idx = threadIdx.x * kPer + i;
-        if (idx < nb) sums[idx] = run;
-        run += v[i];
-    }
-    if (threadIdx.x == 0) *pairs = tot;
-}
-
-// offsets[r] = exclusive prefix of cs; offsets[n] = total
+// offsets[r] = exclusive prefix of cs; offsets[n] and *pairs = total.  Each
+// workgroup sums the kSortBlocks workgroup sums itself (4 KB from L2) for its
+// base and the total.
 __global__ __launch_bounds__(kBlock) void k_scan_downsweep(const uint32_t *__restrict__ cs, uint32_t n_host,
                                                            const uint32_t *n_dev, const uint32_t *__restrict__ sums,
-                                                           uint32_t *__restrict__ offsets) {
+                                                           uint32_t *__restrict__ offsets, uint32_t *pairs) {
     __shared__ uint32_t s_tmp[kWaves];
     const uint32_t n = count_of(n_host, n_dev);
     uint32_t lo, hi;
     block_range(n, blockIdx.x, gridDim.x, &lo, &hi);
-    uint32_t run = sums[blockIdx.x];
+    uint32_t run = 0;
+    {
+        constexpr int kPer = kSortBlocks / kBlock;
+        static_assert(kSortBlocks % kBlock == 0, "whole rows of workgroup sums per thread");
+        uint32_t pre = 0, all = 0;
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const uint32_t j = (uint32_t)(i * kBlock) + threadIdx.x;
+            const uint32_t v = j < gridDim.x ? sums[j] : 0u;
+            pre += j < blockIdx.x ? v : 0u;
+            all += v;
+        }
+        uint32_t tot_pre = 0, tot_all = 0;
+        (void)block_exclusive_scan(pre, s_tmp, &tot_pre);
+        (void)block_exclusive_scan(all, s_tmp, &tot_all);
+        run = tot_pre;
+        if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *pairs = tot_all;
+    }
     for (uint32_t c0 = lo; c0 < hi; c0 += kBlock) {
         const uint32_t i = c0 + threadIdx.x;
         const uint32_t c = i < hi ? cs[i] : 0u;
@@ -312,14 +320,13 @@ void launch_radix_pass(const uint32_t *keys_in, const uint32_t *vals_in, uint32_
                        uint32_t *hist, uint32_t *gsum, hipStream_t s) {
     if (n_host == 0) return;
     const unsigned nb = kSortBlocks;
-    const unsigned ng = (nb + kSortGroup - 1) / kSortGroup;
     if (filter)
         hipLaunchKernelGGL(k_radix_upsweep<true>, dim3(nb), dim3(kBlock), 0, s, keys_in, n_host, n_dev, shift, bits,
                            hist);
     else
         hipLaunchKernelGGL(k_radix_upsweep<false>, dim3(nb), dim3(kBlock), 0, s, keys_in, n_host, n_dev, shift,
                            bits, hist);
-    hipLaunchKernelGGL(k_radix_groups, dim3(ng), dim3(kBlock), 0, s, hist, nb, gsum);
+    hipLaunchKernelGGL(k_radix_groups, dim3(kSortGroups), dim3(kBlock), 0, s, hist, nb, gsum);
     const bool ident = vals_in == nullptr;
 #define FGS_DS(I, F, K)                                                                                         \
     hipLaunchKernelGGL((k_radix_downsweep<I, F, K>), dim3(nb), dim3(kBlock), 0, s, keys_in, vals_in, keys_out, \
@@ -336,8 +343,8 @@ void launch_count_scan(const uint32_t *order, const uint32_t *count, uint32_t n_
                        uint32_t *cs, uint32_t *sums, uint32_t *offsets, uint32_t *pairs, hipStream_t s) {
     if (n_host == 0) return;
     hipLaunchKernelGGL(k_scan_upsweep, dim3(kSortBlocks), dim3(kBlock), 0, s, order, count, n_host, n_dev, cs, sums);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, s, sums, (uint32_t)kSortBlocks, pairs);
-    hipLaunchKernelGGL(k_scan_downsweep, dim3(kSortBlocks), dim3(kBlock), 0, s, cs, n_host, n_dev, sums, offsets);
+    hipLaunchKernelGGL(k_scan_downsweep, dim3(kSortBlocks), dim3(kBlock), 0, s, cs, n_host, n_dev, sums, offsets,
+                       pairs);
 }
 
 }  // namespace fgs

@@ -109,7 +109,7 @@ hipError_t ensure_pixels(FrameBuffers &b, size_t pix) {
 hipError_t ensure_sort_scratch(SortScratch &s) {
     if (s.rhist) return hipSuccess;
     FGS_GROW(s.rhist, (size_t)kSortBlocks * kRadix);
-    FGS_GROW(s.gsum, (size_t)(kSortBlocks / kSortGroup) * kRadix);
+    FGS_GROW(s.gsum, (size_t)kSortGroups * kRadix);
     FGS_GROW(s.sums, (size_t)kSortBlocks);
     return hipSuccess;
 }

@@ -47,8 +47,7 @@ struct FrameBuffers {
 struct SortScratch {
     uint32_t *rhist = nullptr, *gsum = nullptr, *sums = nullptr;
     static size_t bytes() {
-        return ((size_t)kSortBlocks * kRadix + (size_t)(kSortBlocks / kSortGroup) * kRadix + kSortBlocks) *
-               sizeof(uint32_t);
+        return ((size_t)kSortBlocks * kRadix + (size_t)kSortGroups * kRadix + kSortBlocks) * sizeof(uint32_t);
     }
 };
 

@@ -47,6 +47,7 @@ struct fgs_context {
     std::vector<fgs_frame *> frames;
     FrameCounters *fc_dev = nullptr;
     FrameCounters *fc_host = nullptr;
+    hipEvent_t front_done = nullptr;  // the front half's counters are on the host
     SortScratch ss;
     ChunkList ch;
     // instrumentation
@@ -177,6 +178,10 @@ fgs_status fgs_create(int device, fgs_context **out) {
         fgs_destroy(ctx);
         return fail(nullptr, FGS_ERR_OUT_OF_MEMORY, "cannot allocate frame counters");
     }
+    if (hipEventCreateWithFlags(&ctx->front_done, hipEventDisableTiming) != hipSuccess) {
+        fgs_destroy(ctx);
+        return fail(nullptr, FGS_ERR_DEVICE, "cannot create an event");
+    }
     *out = ctx;
     return FGS_OK;
 }
@@ -205,6 +210,7 @@ void fgs_destroy(fgs_context *ctx) {
     free_sort_scratch(ctx->ss);
     if (ctx->fc_dev) (void)hipFree(ctx->fc_dev);
     if (ctx->fc_host) (void)hipHostFree(ctx->fc_host);
+    if (ctx->front_done) (void)hipEventDestroy(ctx->front_done);
     delete ctx;
 }
 
@@ -282,7 +288,14 @@ fgs_status render_impl(fgs_context *ctx, const fgs_scene *scene, const fgs_prepa
         enqueue_front(dsc, prep ? &pdev : nullptr, dcam, dop, W, H, fb, ctx->ch, ctx->ss, ctx->fc_dev, ctx->fc_host,
                       s, mk);
         HIP_TRY(ctx, hipGetLastError());
-        HIP_TRY(ctx, hipStreamSynchronize(s));
+        // The back half is sized by the pair count: wait for the counters by
+        // polling (the front half takes about a millisecond at 4K, where a
+        // blocking wait's wake-up would add a large share of that).
+        HIP_TRY(ctx, hipEventRecord(ctx->front_done, s));
+        hipError_t q;
+        while ((q = hipEventQuery(ctx->front_done)) == hipErrorNotReady) {
+        }
+        HIP_TRY(ctx, q);
         fold_events(ctx);  // the previous instrumented frame is complete after the wait
         if (ctx->fc_host->error & kErrChunkOverflow) {
             // the large-Gaussian chunk list was too small: size it exactly and
