@@ -245,9 +245,23 @@ void free_prepared(PreparedBuffers &pb) {
     pb = PreparedBuffers{};
 }
 
+hipError_t SideStream::create() {
+    hipError_t e = hipStreamCreateWithFlags(&side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+    return e;
+}
+
+void SideStream::destroy() {
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+    if (side) (void)hipStreamDestroy(side);
+    *this = SideStream{};
+}
+
 void enqueue_front(const DevScene &sc, const DevPrepared *pp, const DevCamera &cam, const DevOptions &op, int W,
                    int H, FrameBuffers &fb, ChunkList &ch, SortScratch &ss, FrameCounters *fc,
-                   FrameCounters *host_fc, hipStream_t s, const StageMarks &mk) {
+                   FrameCounters *host_fc, hipStream_t s, const SideStream &side, const StageMarks &mk) {
     const uint32_t chunk_cap = (uint32_t)std::min<size_t>(ch.cap, 0xffffffffu);
     // ---- stage 1: preprocess + exact tile count -------------------------------
     launch_fill_u32(reinterpret_cast<uint32_t *>(fc), 0u, sizeof(FrameCounters) / 4, s);
@@ -255,7 +269,15 @@ void enqueue_front(const DevScene &sc, const DevPrepared *pp, const DevCamera &c
     // the candidate list of a prepared scene lives in dv_b until the depth sort
     launch_preprocess(sc, pp, cam, op, W, H, fb.gs, fb.rect, fb.count, fb.erec, fb.dkey, fb.dv_b, fb.seg_count,
                       ch.chunks, chunk_cap, fc, s);
-    launch_big_count(W, H, op.binning, fb.gs, fb.rect, ch.chunks, chunk_cap, ch.hits, ch.mask, fb.count, fc, s);
+    // the large rectangles' exact tests touch neither the depth keys nor the
+    // sort scratch: they run beside the depth sort
+    hipStream_t sb = s;
+    if (side.side && hipEventRecord(side.fork, s) == hipSuccess &&
+        hipStreamWaitEvent(side.side, side.fork, 0) == hipSuccess)
+        sb = side.side;
+    launch_big_count(W, H, op.binning, fb.gs, fb.rect, ch.chunks, chunk_cap, ch.hits, ch.mask, fb.count, fc, sb);
+    const bool joined = sb == s || hipEventRecord(side.join, sb) == hipSuccess;
+    if (!joined) (void)hipStreamSynchronize(sb);  // cannot order the streams by an event: wait here instead
     // ---- depth order of the visible Gaussians: 4 LSD passes over the depth
     // digits, hoisted before key duplication (the low half of the (tile |
     // depth) key is the same for every pair of a Gaussian) --------------------
@@ -267,6 +289,8 @@ void enqueue_front(const DevScene &sc, const DevPrepared *pp, const DevCamera &c
                       s);
     launch_radix_pass(fb.dk_b, fb.dv_b, fb.dkey, fb.dv_a, P32, &fc->visible, 24, 8, false, false, ss.rhist, ss.gsum,
                       s);
+    // the scan reads the counts of the large rectangles
+    if (sb != s && joined && hipStreamWaitEvent(s, side.join, 0) != hipSuccess) (void)hipStreamSynchronize(sb);
     mk.mark(2, s);
     // ---- stage 2a: scan of the tile counts in depth order -------------------------
     launch_count_scan(fb.dv_a, fb.count, P32, &fc->visible, fb.dk_b, ss.sums, fb.offsets, &fc->pairs, s);

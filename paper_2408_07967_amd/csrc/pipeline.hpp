@@ -86,13 +86,26 @@ struct StageMarks {
     }
 };
 
+// A second stream and two events that let independent work of one frame run
+// beside the main stream (fork: side waits for main; join: main waits for
+// side).  All three are owned by the caller; side == nullptr runs everything
+// on the main stream.
+struct SideStream {
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    hipError_t create();  // non-blocking stream, default priority
+    void destroy();
+};
+
 // Stages 1 and 2a: preprocess with the exact tile count, depth order of the
-// visible Gaussians, scan of the tile counts in depth order.  Ends with an
-// asynchronous copy of the frame counters to host_fc (pinned).
+// visible Gaussians, scan of the tile counts in depth order.  The exact tests
+// of the large rectangles run on the side stream while the depth order is
+// sorted on s; the scan waits for both.  Ends with an asynchronous copy of
+// the frame counters to host_fc (pinned).
 // pp: NULL (raw parameters) or the scene's view-independent precompute.
 void enqueue_front(const DevScene &sc, const DevPrepared *pp, const DevCamera &cam, const DevOptions &op, int W,
                    int H, FrameBuffers &fb, ChunkList &ch, SortScratch &ss, FrameCounters *fc,
-                   FrameCounters *host_fc, hipStream_t s, const StageMarks &mk);
+                   FrameCounters *host_fc, hipStream_t s, const SideStream &side, const StageMarks &mk);
 
 // Device buffers of a scene's view-independent precompute.
 struct PreparedBuffers {

@@ -48,6 +48,7 @@ struct fgs_context {
     FrameCounters *fc_dev = nullptr;
     FrameCounters *fc_host = nullptr;
     hipEvent_t front_done = nullptr;  // the front half's counters are on the host
+    SideStream side;                  // independent work of a frame runs beside the frame's stream
     SortScratch ss;
     ChunkList ch;
     // instrumentation
@@ -178,7 +179,8 @@ fgs_status fgs_create(int device, fgs_context **out) {
         fgs_destroy(ctx);
         return fail(nullptr, FGS_ERR_OUT_OF_MEMORY, "cannot allocate frame counters");
     }
-    if (hipEventCreateWithFlags(&ctx->front_done, hipEventDisableTiming) != hipSuccess) {
+    if (hipEventCreateWithFlags(&ctx->front_done, hipEventDisableTiming) != hipSuccess ||
+        ctx->side.create() != hipSuccess) {
         fgs_destroy(ctx);
         return fail(nullptr, FGS_ERR_DEVICE, "cannot create an event");
     }
@@ -211,6 +213,7 @@ void fgs_destroy(fgs_context *ctx) {
     if (ctx->fc_dev) (void)hipFree(ctx->fc_dev);
     if (ctx->fc_host) (void)hipHostFree(ctx->fc_host);
     if (ctx->front_done) (void)hipEventDestroy(ctx->front_done);
+    ctx->side.destroy();
     delete ctx;
 }
 
@@ -286,7 +289,7 @@ fgs_status render_impl(fgs_context *ctx, const fgs_scene *scene, const fgs_prepa
     for (int attempt = 0;; ++attempt) {
         const DevPrepared pdev = prep ? prep->pb.dev() : DevPrepared{};
         enqueue_front(dsc, prep ? &pdev : nullptr, dcam, dop, W, H, fb, ctx->ch, ctx->ss, ctx->fc_dev, ctx->fc_host,
-                      s, mk);
+                      s, ctx->side, mk);
         HIP_TRY(ctx, hipGetLastError());
         // The back half is sized by the pair count: wait for the counters by
         // polling (the front half takes about a millisecond at 4K, where a

@@ -70,6 +70,7 @@ struct Slot {
     SlotState state = SlotState::IDLE;
     hipStream_t stream = nullptr;
     hipEvent_t evA = nullptr, evB = nullptr;
+    SideStream side;
     FrameBuffers fb;
     ChunkList ch;
     SortScratch ss;
@@ -179,7 +180,7 @@ bool ensure_region(fgs_server *srv, Slot &s) {
 void start_front(fgs_server *srv, Slot &s) {
     const DevCamera dcam = to_dev(s.req.cam);
     enqueue_front(srv->dsc, &srv->pdev, dcam, srv->dop, s.req.W, s.req.H, s.fb, s.ch, s.ss, s.fc_dev, s.fc_host,
-                  s.stream, StageMarks{});
+                  s.stream, s.side, StageMarks{});
     (void)hipEventRecord(s.evA, s.stream);
     s.state = SlotState::FRONT;
 }
@@ -422,6 +423,7 @@ void free_server(fgs_server *srv) {
         if (s.evA) (void)hipEventDestroy(s.evA);
         if (s.evB) (void)hipEventDestroy(s.evB);
         if (s.stream) (void)hipStreamDestroy(s.stream);
+        s.side.destroy();
     }
     if (srv->arena_base) (void)hipFree(srv->arena_base);
     free_prepared(srv->prep);
@@ -486,6 +488,7 @@ fgs_status fgs_server_create(int device, const fgs_scene *scene, const fgs_optio
         if ((e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking)) != hipSuccess) break;
         if ((e = hipEventCreateWithFlags(&s.evA, hipEventDisableTiming)) != hipSuccess) break;
         if ((e = hipEventCreateWithFlags(&s.evB, hipEventDisableTiming)) != hipSuccess) break;
+        if ((e = s.side.create()) != hipSuccess) break;
         if ((e = ensure_gauss(s.fb, P)) != hipSuccess) break;
         if ((e = ensure_tiles(s.fb, tiles)) != hipSuccess) break;
         if ((e = ensure_chunks(s.ch, P / 8)) != hipSuccess) break;
