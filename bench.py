@@ -68,20 +68,48 @@ def traffic_from_profiles(workload, evals_per_launch):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(scene, cam, W, H, opts):
-    """The CPU oracle (binary64, OpenMP over Gaussians and tiles), untuned,
-    timed on one full frame of the same workload."""
+def oracle_frame(scene, cam, W, H, opts, mode="f64"):
+    """One oracle frame (binary64, or its binary32 mode): (seconds, pairs,
+    image [3, H, W])."""
     from oracle import oracle as orc
-    prep = orc.Prepared(scene, cam, W, H, opts, "f64")
+    prep = orc.Prepared(scene, cam, W, H, opts, mode)
     t0 = time.perf_counter()
     state, ints, n = orc.preprocess(prep)
     tiles, vals, rng = orc.pairs(prep, state, ints, n)
-    orc.blend_tiled(prep, state, vals, rng)
-    dt = time.perf_counter() - t0
-    return dict(value=round(1.0 / dt, 5), unit="frames/s", cores=int(orc._lib().orc_num_threads()),
-                kind="oracle", sample=f"one full {W}x{H} frame of the same scene and camera, binary64 "
-                                      f"(preprocess + pairs + sort + blend; input conversion excluded); "
-                                      f"{dt:.2f} s")
+    rgb, _, _ = orc.blend_tiled(prep, state, vals, rng)
+    return time.perf_counter() - t0, int(n), rgb
+
+
+def cpu_baseline(scene, cam, W, H, opts):
+    """The CPU oracle (binary64, OpenMP over Gaussians and tiles), untuned,
+    timed on one full frame of the same workload; also returns its image."""
+    from oracle import oracle as orc
+    from paper_2408_07967_amd import scenes
+    dt, npairs, rgb = oracle_frame(scene, cam, W, H, opts)
+    res = dict(value=round(1.0 / dt, 5), unit="frames/s", cores=int(orc._lib().orc_num_threads()),
+               kind="oracle", sample=f"one full {W}x{H} frame of the same scene and camera, binary64 "
+                                     f"(preprocess + pairs + sort + blend; input conversion excluded); "
+                                     f"{dt:.2f} s", pairs_per_s=round(npairs / dt, 1))
+    # the smaller synthetic workloads, one frame each
+    other = {}
+    for kind, name in (("small", "small-10k-gaussians-256x256"), ("medium", "medium-1M-gaussians-1920x1080")):
+        sc2 = scenes.make_scene(kind)
+        cam2 = scenes.camera_for(kind, 0)
+        dt2, n2, _ = oracle_frame(sc2, cam2, cam2.W, cam2.H, opts)
+        other[name] = dict(frames_per_s=round(1.0 / dt2, 3), pairs_per_s=round(n2 / dt2, 1), seconds=round(dt2, 3))
+    res["other_workloads"] = other
+    return res, rgb
+
+
+def image_parity(gpu_rgb, ref_rgb, tol=2e-3):
+    """Per-pixel comparison of the rendered image with the binary64 oracle's:
+    a pixel is within tolerance when all three channels are."""
+    import numpy as np
+    d = np.abs(gpu_rgb.astype(np.float64) - ref_rgb.astype(np.float64))
+    px = d.max(axis=0)
+    return dict(reference="oracle binary64, same scene and camera", tolerance=tol,
+                frac_pixels_within=round(float((px <= tol).mean()), 6), max_abs=float(px.max()),
+                mean_abs=float(d.mean()), bar="frac_pixels_within >= 0.999 and mean_abs <= 1e-5")
 
 
 SERVE_BUDGET = 3 << 30   # pair and sort buffers of admitted requests
@@ -331,6 +359,17 @@ def main():
     nf = max(1, inst["frames"])
     stage_ms = {k[3:]: round(inst[k] / nf, 4) for k in inst if k.startswith("ms_")}
     log(f"[bench] {args.steps} frames in {dt:.3f}s -> {fps:.2f} frames/s; stages {stage_ms}")
+    # single-frame latency: each frame waited for on its own
+    lat = []
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        R.render(gsc, cam, W, H, opts, out=out, prepared=prep)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t0) * 1e3)
+    lat = np.sort(np.asarray(lat))
+    frame_ms = dict(p10=round(float(np.percentile(lat, 10)), 4), p50=round(float(np.percentile(lat, 50)), 4),
+                    p90=round(float(np.percentile(lat, 90)), 4))
+    log(f"[bench] single-frame latency ms {frame_ms}")
 
     if args.copy_calibration:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
@@ -349,10 +388,19 @@ def main():
                     avg_launch_ms=stage_ms["blend"])
 
     cpu = None
+    parity = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on one frame ...")
-        cpu = cpu_baseline(sc, cam, W, H, opts)
+        cpu, ref_rgb = cpu_baseline(sc, cam, W, H, opts)
         log(f"[bench] cpu baseline {cpu}")
+        parity = image_parity(out.cpu().numpy(), ref_rgb)
+        # the same comparison for the oracle's own binary32 mode: what binary32
+        # arithmetic reaches on this frame
+        _, _, f32_rgb = oracle_frame(sc, cam, W, H, opts, "f32")
+        parity["oracle_binary32_vs_binary64"] = {k: v for k, v in image_parity(f32_rgb, ref_rgb).items()
+                                                 if k in ("frac_pixels_within", "max_abs", "mean_abs")}
+        del ref_rgb, f32_rgb
+        log(f"[bench] image parity {parity}")
 
     R.release_prepared(prep)
     R.close()
@@ -373,8 +421,9 @@ def main():
                            raw_params_frames_per_s=round(raw_fps, 3), prepare_ms=round(prep_ms, 2),
                            visible=int(stats["visible"]), pairs=int(stats["pairs"]),
                            big_rect_chunks=int(stats["big_chunks"]),
-                           pairs_per_s=round(stats["pairs"] * fps, 1), stage_ms=stage_ms),
-               roofline=roof, cpu_baseline=cpu, serving=serving, differentiation=differentiation)
+                           pairs_per_s=round(stats["pairs"] * fps, 1), stage_ms=stage_ms,
+                           single_frame_ms=frame_ms),
+               roofline=roof, cpu_baseline=cpu, parity=parity, serving=serving, differentiation=differentiation)
     if binning_modes is not None:
         res["binning_modes"] = binning_modes
     print(json.dumps(res), flush=True)

@@ -271,9 +271,23 @@ __global__ __launch_bounds__(kBlock) void k_prepare(DevScene sc, DevOptions op, 
         cov[2 * g + 1] = make_float4(S[4], S[5], k2, l2o);
         // trace(Sigma) >= its largest eigenvalue: bounds the screen extent
         bnd[g] = make_float2(S[0] + S[3] + S[5], k2);
-        float *dst = sh_out + g * sh_stride;
-        for (int j = 0; j < ncoef; ++j) dst[j] = sc.sh[(int64_t)j * st + g];
-        for (int j = ncoef; j < sh_stride; ++j) dst[j] = 0.0f;
+    }
+    // SH: planar in, Gaussian-major out, transposed through LDS so that both
+    // the reads (one plane, consecutive Gaussians) and the writes (the
+    // workgroup's records, one contiguous range) are coalesced
+    __shared__ float s_t[kBlock * (48 + 1)];
+    for (int64_t g0 = (int64_t)blockIdx.x * kBlock; g0 < sc.P; g0 += (int64_t)gridDim.x * kBlock) {
+        const int64_t g = g0 + threadIdx.x;
+        const int n = sc.P - g0 < kBlock ? (int)(sc.P - g0) : kBlock;
+        __syncthreads();
+        for (int j = 0; j < sh_stride; ++j)
+            s_t[threadIdx.x * (48 + 1) + j] = (j < ncoef && g < sc.P) ? sc.sh[(int64_t)j * st + g] : 0.0f;
+        __syncthreads();
+        float *dst = sh_out + g0 * sh_stride;
+        for (int e = threadIdx.x; e < n * sh_stride; e += kBlock) {
+            const int r = e / sh_stride, j = e - r * sh_stride;
+            dst[e] = s_t[r * (48 + 1) + j];
+        }
     }
 }
 
