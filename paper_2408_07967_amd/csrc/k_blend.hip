@@ -80,8 +80,8 @@ __global__ __launch_bounds__(kThreads) void k_blend(const GaussState *__restrict
                                                     const uint2 *__restrict__ ranges, int W, int H, int tiles_x,
                                                     DevOptions op, float *__restrict__ rgb, float *__restrict__ Tout,
                                                     uint32_t *__restrict__ last_out, unsigned long long *work) {
-    __shared__ float4 s_f0[kBatch], s_f1[kBatch];
-    __shared__ float2 s_f2[kBatch];
+    // one float4 stride for all three arrays: a single LDS address per Gaussian
+    __shared__ float4 s_f0[kBatch], s_f1[kBatch], s_f2[kBatch];
     // s_rel[h][w]: bit i set iff entry 64 w + i of the batch meets half h
     __shared__ uint32_t s_rel[2][kWords][2];
 
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(kThreads) void k_blend(const GaussState *__restrict
                 stage_gauss(s, f0, f1, f2);
                 s_f0[i] = f0;
                 s_f1[i] = f1;
-                s_f2[i] = f2;
+                s_f2[i] = make_float4(f2.x, f2.y, 0.0f, 0.0f);
             }
             // entry i = 128 r + 64 wave + lane: word 2 r + wave, bit lane
 #pragma unroll
@@ -145,11 +145,11 @@ __global__ __launch_bounds__(kThreads) void k_blend(const GaussState *__restrict
             for (int wd = 0; wd < kWords && !wave_done; ++wd) {
                 uint64_t m = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)s_rel[wave][wd][0]) |
                              ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)s_rel[wave][wd][1]) << 32);
-                while (m) {
-                    const int j = wd * kWave + __builtin_ctzll(m);
-                    m &= m - 1;
+                // one staged Gaussian for both pixels of the lane; true once
+                // every pixel of the wavefront has stopped
+                auto blend_one = [&](int j) {
                     const float4 f0 = s_f0[j], f1 = s_f1[j];
-                    const float2 f2 = s_f2[j];
+                    const float2 f2 = *reinterpret_cast<const float2 *>(&s_f2[j]);
                     const RowTerms rt = row_terms(f0, f1, py);
                     const float e0 = exponent_at(f0, rt, p0.x);
                     const float e1 = exponent_at(f0, rt, p1.x);
@@ -163,7 +163,17 @@ __global__ __launch_bounds__(kThreads) void k_blend(const GaussState *__restrict
                     }
                     apply<kLast>(p0, s0, f1, f2, pos);
                     apply<kLast>(p1, s1, f1, f2, pos);
-                    if (wave_done) break;
+                    return wave_done;
+                };
+                // two Gaussians per trip (the loop-carried state alternates
+                // between register sets instead of being copied back)
+                while (m) {
+                    const int ja = wd * kWave + __builtin_ctzll(m);
+                    m &= m - 1;
+                    if (blend_one(ja) || !m) break;
+                    const int jb = wd * kWave + __builtin_ctzll(m);
+                    m &= m - 1;
+                    if (blend_one(jb)) break;
                 }
             }
         }
