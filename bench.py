@@ -113,7 +113,8 @@ def image_parity(gpu_rgb, ref_rgb, tol=2e-3):
 
 
 SERVE_BUDGET = 3 << 30   # pair and sort buffers of admitted requests
-SERVE_SLOTS = 6
+SERVE_SLOTS = 4
+SERVE_SHARE = 2          # a request runs beside others only while two or more wait
 
 
 def serving_leg(args):
@@ -141,7 +142,11 @@ def serving_leg(args):
     log(f"[bench] plain renderer: {ps}")
     R.close()
     torch.cuda.synchronize()
-    srv = RenderServer(gsc, budget_bytes=SERVE_BUDGET, max_inflight=SERVE_SLOTS, max_bypass=4)
+    def server():
+        return RenderServer(gsc, budget_bytes=SERVE_BUDGET, max_inflight=SERVE_SLOTS, max_bypass=4,
+                            share_queue=SERVE_SHARE)
+
+    srv = server()
     try:
         srv.replay(warm)
         res = srv.replay(trace)
@@ -150,28 +155,33 @@ def serving_leg(args):
         srv.close()
     ss = latency_summary(res)
     log(f"[bench] server: {ss} stats {st}")
-    # a high-load point of the same workload, where the plain renderer queues
-    hi_rate = 2.5 * args.serve_rate
-    hi_trace = make_trace(hi_rate, min(args.serve_seconds, 8.0), seed=7)
-    R = Renderer(0)
-    hp = latency_summary(replay_plain(R, gsc, None, hi_trace))
-    R.close()
-    srv = RenderServer(gsc, budget_bytes=SERVE_BUDGET, max_inflight=SERVE_SLOTS, max_bypass=4)
-    try:
-        srv.replay(warm)
-        hs = latency_summary(srv.replay(hi_trace))
-    finally:
-        srv.close()
-    log(f"[bench] at {hi_rate:.0f}/s: plain {hp} server {hs}")
     rnd = lambda d: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
+    # load sweep on shorter traces of the same workload: at 4x the plain
+    # renderer can no longer keep up and its queue grows for the whole trace
+    sweep = []
+    for mult, secs in ((2.5, 8.0), (4.0, 4.0)):
+        rate = mult * args.serve_rate
+        tr = make_trace(rate, min(args.serve_seconds, secs), seed=7)
+        R = Renderer(0)
+        hp = latency_summary(replay_plain(R, gsc, None, tr))
+        R.close()
+        srv = server()
+        try:
+            srv.replay(warm)
+            hs = latency_summary(srv.replay(tr))
+        finally:
+            srv.close()
+        log(f"[bench] at {rate:.0f}/s: plain {hp} server {hs}")
+        sweep.append(dict(rate_per_s=rate, requests=len(tr), server=rnd(hs), plain=rnd(hp),
+                          p50_ratio_plain_over_server=round(hp["p50_ms"] / hs["p50_ms"], 3),
+                          p99_ratio_plain_over_server=round(hp["p99_ms"] / hs["p99_ms"], 3)))
     return dict(workload=f"serve-6M-gaussians-poisson{args.serve_rate:.0f}-{args.serve_seconds:.0f}s-"
                          f"720p-1080p-1440p-2160p",
                 requests=len(trace), server=rnd(ss), plain=rnd(ps),
                 p50_ratio_plain_over_server=round(ps["p50_ms"] / ss["p50_ms"], 3),
                 p99_ratio_plain_over_server=round(ps["p99_ms"] / ss["p99_ms"], 3),
-                high_load=dict(rate_per_s=hi_rate, requests=len(hi_trace), server=rnd(hs), plain=rnd(hp),
-                               p99_ratio_plain_over_server=round(hp["p99_ms"] / hs["p99_ms"], 3)),
-                budget_bytes=SERVE_BUDGET, slots=SERVE_SLOTS,
+                load_sweep=sweep,
+                budget_bytes=SERVE_BUDGET, slots=SERVE_SLOTS, share_queue=SERVE_SHARE,
                 peak_bytes_in_use=st["peak_bytes_in_use"], graphs_captured=st["graphs_captured"],
                 graph_launches=st["graph_launches"], bypasses=st["bypasses"],
                 region_evictions=st["region_evictions"])

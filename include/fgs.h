@@ -296,7 +296,10 @@ typedef struct {
     int32_t max_height;
     int32_t max_bypass;     /* >= 0                                                  */
     int32_t use_graphs;     /* 1: replay a captured graph per (slot, W, H); 0: launch */
-    int32_t reserved;       /* must be 0                                             */
+    int32_t share_queue;    /* >= 0.  0: waiting requests start on every free slot;
+                               k >= 1: a request starts beside others still in flight
+                               only while at least k requests are waiting, so at light
+                               load requests run one at a time on the whole GPU      */
 } fgs_server_config;
 
 typedef struct {

@@ -61,7 +61,7 @@ INSTR_WORK = 2
 class FgsServerConfig(C.Structure):
     _fields_ = [("budget_bytes", C.c_int64), ("max_inflight", C.c_int32), ("max_width", C.c_int32),
                 ("max_height", C.c_int32), ("max_bypass", C.c_int32), ("use_graphs", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("share_queue", C.c_int32)]
 
 
 class FgsServerResult(C.Structure):

@@ -302,10 +302,18 @@ void worker_main(fgs_server *srv) {
             }
             idle_since = now_ns();
         }
-        // 1. start the first half of queued requests on free slots (FIFO)
+        // 1. start the first half of queued requests on free slots (FIFO); with
+        // share_queue = k, beside requests already in flight only while k or
+        // more are waiting (a lone request gets the whole GPU)
+        int active = 0;
+        for (const Slot &s : srv->slots)
+            active += (s.state == SlotState::FRONT || s.state == SlotState::WAIT || s.state == SlotState::BACK);
         for (Slot &s : srv->slots) {
             if (pending.empty()) break;
             if (s.state != SlotState::IDLE) continue;
+            const int k = srv->cfg.share_queue;
+            if (active > 0 && k > 0 && (int64_t)pending.size() < (int64_t)k) break;
+            ++active;
             s.req = pending.front();
             pending.pop_front();
             s.attempts = 0;
@@ -443,7 +451,7 @@ fgs_status fgs_server_create(int device, const fgs_scene *scene, const fgs_optio
     if (!cfg) return FGS_ERR_INVALID_ARGUMENT;
     if (cfg->budget_bytes < (1 << 20) || cfg->max_inflight < 1 || cfg->max_inflight > 32 || cfg->max_width < 1 ||
         cfg->max_width > 16384 || cfg->max_height < 1 || cfg->max_height > 16384 || cfg->max_bypass < 0 ||
-        cfg->reserved != 0)
+        cfg->share_queue < 0)
         return FGS_ERR_INVALID_ARGUMENT;
     fgs_camera probe{};
     for (int i = 0; i < 3; ++i) probe.R[4 * i] = 1.0f;
@@ -614,11 +622,16 @@ fgs_status fgs_server_replay(fgs_server *srv, const fgs_trace_request *trace, in
             if (s != FGS_OK) return s;
             ++next;
         }
+        // sleep until shortly before the next arrival (a timed wait wakes up
+        // late by tens of microseconds), then poll without waiting so that
+        // the request is submitted at its arrival time
+        constexpr int64_t kSlack = 150000;
         int64_t wait = 0;
-        if (next < n) wait = std::max<int64_t>(0, t0 + trace[next].arrival_offset_ns - now_ns());
+        if (next < n) wait = std::max<int64_t>(0, t0 + trace[next].arrival_offset_ns - now_ns() - kSlack);
         else wait = 5000000;
         wait = std::min<int64_t>(wait, 200000);  // stay responsive to arrivals
         const int32_t k = fgs_server_poll(srv, buf.data(), (int32_t)buf.size(), wait);
+        if (k == 0 && wait == 0) std::this_thread::yield();
         if (k < 0) return (fgs_status)(-k);
         for (int32_t j = 0; j < k; ++j) {
             auto it = index.find(buf[(size_t)j].id);
@@ -638,6 +651,13 @@ fgs_status fgs_replay_plain(fgs_context *ctx, const fgs_scene *scene, const fgs_
     if (!ctx || (n > 0 && (!trace || !results || !rgb_scratch)) || n < 0) return FGS_ERR_INVALID_ARGUMENT;
     for (int64_t i = 1; i < n; ++i)
         if (trace[i].arrival_offset_ns < trace[i - 1].arrival_offset_ns) return FGS_ERR_INVALID_ARGUMENT;
+    // completion is observed by polling an event, as the server's worker does
+    hipEvent_t done = nullptr;
+    if (hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) return FGS_ERR_DEVICE;
+    struct EventGuard {
+        hipEvent_t e;
+        ~EventGuard() { (void)hipEventDestroy(e); }
+    } guard{done};
     const int64_t t0 = now_ns() + 1000000;
     for (int64_t i = 0; i < n; ++i) {
         const fgs_trace_request &q = trace[i];
@@ -655,7 +675,13 @@ fgs_status fgs_replay_plain(fgs_context *ctx, const fgs_scene *scene, const fgs_
         fgs_status s = fgs_render(ctx, scene, &q.cam, q.width, q.height, opt, rgb_scratch, nullptr, nullptr, nullptr,
                                   &stt, stream);
         r.admit_ns = now_ns();  // the render call returns once the second half is enqueued
-        if (s == FGS_OK && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) s = FGS_ERR_DEVICE;
+        if (s == FGS_OK) {
+            hipError_t q2 = hipEventRecord(done, (hipStream_t)stream);
+            if (q2 == hipSuccess)
+                while ((q2 = hipEventQuery(done)) == hipErrorNotReady) {
+                }
+            if (q2 != hipSuccess) s = FGS_ERR_DEVICE;
+        }
         r.done_ns = now_ns();
         r.status = s;
         r.visible = stt.visible;

@@ -99,6 +99,9 @@ def test_null_arguments_rejected_without_device():
     bad = B.FgsServerConfig(1 << 30, 0, 64, 64, 2, 1, 0)  # no slots
     assert B.lib().fgs_server_create(0, C.byref(sc), C.byref(op), C.byref(bad), C.byref(h)) == \
         B.FGS_ERR_INVALID_ARGUMENT
+    bad = B.FgsServerConfig(1 << 30, 4, 64, 64, 2, 1, -1)  # negative sharing threshold
+    assert B.lib().fgs_server_create(0, C.byref(sc), C.byref(op), C.byref(bad), C.byref(h)) == \
+        B.FGS_ERR_INVALID_ARGUMENT
     assert B.lib().fgs_server_create(0, None, C.byref(op), C.byref(cfg), C.byref(h)) == B.FGS_ERR_INVALID_ARGUMENT
     assert not h.value
     assert B.lib().fgs_server_submit(None, 1, C.byref(cam), 8, 8, 0, None) == B.FGS_ERR_INVALID_ARGUMENT

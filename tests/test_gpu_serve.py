@@ -45,7 +45,11 @@ def _serve_all(srv, reqs, gsc):
     return got, outs
 
 
-def test_served_images_equal_alone_under_a_tight_budget(setup):
+@pytest.mark.parametrize("share_queue", [0, 2])
+def test_served_images_equal_alone_under_a_tight_budget(setup, share_queue):
+    """All requests queued at once: with share_queue = 2 the server starts a
+    request beside others only while two or more wait, so the queue drains
+    through both the shared and the one-at-a-time regime."""
     import torch
     from paper_2408_07967_amd.serve import RenderServer
     scenes, gsc, R = setup
@@ -60,7 +64,7 @@ def test_served_images_equal_alone_under_a_tight_budget(setup):
     biggest = max(p for _, p in alone.values())
     # room for about two of the largest requests at once
     budget = int(2.2 * 16 * (biggest * 9 // 8 + 4096))
-    srv = RenderServer(gsc, budget_bytes=budget, max_inflight=5, max_bypass=2)
+    srv = RenderServer(gsc, budget_bytes=budget, max_inflight=5, max_bypass=2, share_queue=share_queue)
     try:
         got, outs = _serve_all(srv, reqs, gsc)
         st = srv.stats()
