@@ -167,6 +167,18 @@ fgs_status fgs_render(fgs_context *ctx, const fgs_scene *scene, const fgs_camera
                       const fgs_options *opt, float *out_rgb, float *out_T, uint32_t *out_last,
                       fgs_frame **saved, fgs_stats *stats, void *stream);
 
+/* Plan one frame without rendering it: the first half of fgs_render runs
+ * (preprocess with the exact tile count, depth order, scan of the counts;
+ * Alg. 4 and Alg. 2 up to the pair count) and the call waits for it.
+ *   pairs_out  host, or NULL: number of Gaussian-tile pairs of the frame
+ *   bytes_out  host, or NULL: device bytes the context needs to render it
+ *              (per-Gaussian, pair, tile, sort and chunk buffers; without the
+ *              output image and without a saved frame's per-pixel buffers)
+ * At least one of the two must be non-NULL.  The context keeps the
+ * per-Gaussian buffers it grew; pair buffers are not allocated. */
+fgs_status fgs_plan(fgs_context *ctx, const fgs_scene *scene, const fgs_camera *cam, int32_t W, int32_t H,
+                    const fgs_options *opt, int64_t *pairs_out, size_t *bytes_out, void *stream);
+
 /* ---- prepared (resident) scenes ------------------------------------------ */
 
 /* The paper moves preprocessing shared by the viewpoints of one scene to an

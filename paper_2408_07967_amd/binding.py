@@ -103,6 +103,8 @@ PROTOTYPES = {
     "fgs_frame_stats": (C.c_int, [C.c_void_p, C.POINTER(FgsStats)]),
     "fgs_set_instrumentation": (C.c_int, [C.c_void_p, C.c_int]),
     "fgs_get_instrumentation": (C.c_int, [C.c_void_p, C.POINTER(FgsTimings)]),
+    "fgs_plan": (C.c_int, [C.c_void_p, C.POINTER(FgsScene), C.POINTER(FgsCamera), C.c_int32, C.c_int32,
+                           C.POINTER(FgsOptions), C.POINTER(C.c_int64), C.POINTER(C.c_size_t), C.c_void_p]),
     "fgs_prepare_scene": (C.c_int, [C.c_void_p, C.POINTER(FgsScene), C.POINTER(FgsOptions),
                                     C.POINTER(C.c_void_p), C.c_void_p]),
     "fgs_prepared_release": (C.c_int, [C.c_void_p, C.c_void_p]),

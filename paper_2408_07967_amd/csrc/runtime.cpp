@@ -247,14 +247,22 @@ size_t fgs_scratch_bytes(const fgs_context *ctx) {
 
 namespace {
 
+// Planning only (fgs_plan): the front half runs, the pair count and the bytes
+// a render needs are reported, nothing is blended.
+struct PlanOut {
+    int64_t *pairs;
+    size_t *bytes;
+};
+
 fgs_status render_impl(fgs_context *ctx, const fgs_scene *scene, const fgs_prepared *prep, const fgs_camera *cam,
                        int32_t W, int32_t H, const fgs_options *opt_in, float *out_rgb, float *out_T,
-                       uint32_t *out_last, fgs_frame **saved, fgs_stats *stats, void *stream_v) {
+                       uint32_t *out_last, fgs_frame **saved, fgs_stats *stats, void *stream_v,
+                       const PlanOut *plan = nullptr) {
     if (saved) *saved = nullptr;
     if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARGUMENT, "context is NULL");
     fgs_status st = validate(ctx, scene, cam, W, H, opt_in);
     if (st != FGS_OK) return st;
-    if (!out_rgb) return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "out_rgb is NULL");
+    if (!out_rgb && !plan) return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "out_rgb is NULL");
     fgs_options opt;
     if (opt_in)
         opt = *opt_in;
@@ -311,6 +319,27 @@ fgs_status render_impl(fgs_context *ctx, const fgs_scene *scene, const fgs_prepa
         N = ctx->fc_host->pairs;
         big = ctx->fc_host->nchunks;
         break;
+    }
+    if (plan) {
+        FrameBuffers need;
+        need.capP = (size_t)P;
+        need.capN = N;
+        need.capTiles = ntiles;
+        ChunkList chunks_need;
+        chunks_need.cap = std::max<size_t>((size_t)big + big / 8, 65536);
+        if (plan->pairs) *plan->pairs = (int64_t)N;
+        if (plan->bytes)
+            *plan->bytes = need.bytes() + SortScratch::bytes() + chunks_need.bytes() + sizeof(FrameCounters);
+        if (stats) {
+            fgs_stats stt{};
+            stt.visible = V;
+            stt.pairs = N;
+            stt.tiles_x = tiles_x;
+            stt.tiles_y = tiles_y;
+            stt.big_chunks = (int32_t)big;
+            *stats = stt;
+        }
+        return FGS_OK;
     }
     HIP_TRY(ctx, ensure_pairs(fb, N));
     float *Tdst = saved ? fb.T : out_T;
@@ -381,6 +410,17 @@ fgs_status fgs_render(fgs_context *ctx, const fgs_scene *scene, const fgs_camera
                       const fgs_options *opt, float *out_rgb, float *out_T, uint32_t *out_last, fgs_frame **saved,
                       fgs_stats *stats, void *stream) {
     return render_impl(ctx, scene, nullptr, cam, W, H, opt, out_rgb, out_T, out_last, saved, stats, stream);
+}
+
+fgs_status fgs_plan(fgs_context *ctx, const fgs_scene *scene, const fgs_camera *cam, int32_t W, int32_t H,
+                    const fgs_options *opt, int64_t *pairs_out, size_t *bytes_out, void *stream) {
+    if (pairs_out) *pairs_out = 0;
+    if (bytes_out) *bytes_out = 0;
+    if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARGUMENT, "context is NULL");
+    if (!pairs_out && !bytes_out) return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "pairs_out and bytes_out are NULL");
+    const PlanOut plan{pairs_out, bytes_out};
+    return render_impl(ctx, scene, nullptr, cam, W, H, opt, nullptr, nullptr, nullptr, nullptr, nullptr, stream,
+                       &plan);
 }
 
 fgs_status fgs_prepare_scene(fgs_context *ctx, const fgs_scene *scene, const fgs_options *opt_in,

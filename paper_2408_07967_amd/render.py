@@ -110,6 +110,19 @@ class Renderer:
                     stats=dict(visible=st.visible, pairs=st.pairs, tiles_x=st.tiles_x, tiles_y=st.tiles_y,
                                sort_passes=st.sort_passes, big_chunks=st.big_chunks))
 
+    def plan(self, scene, cam, W, H, opts=None):
+        """Pair count and device bytes of one frame, without rendering it:
+        returns dict(pairs, bytes)."""
+        sc = scene.abi()
+        cm = camera_abi(cam)
+        op = options_abi(opts)
+        n = C.c_int64()
+        b = C.c_size_t()
+        stream = torch.cuda.current_stream(scene.means.device).cuda_stream
+        self.ctx.check(B.lib().fgs_plan(self.ctx.handle, C.byref(sc), C.byref(cm), int(W), int(H), C.byref(op),
+                                        C.byref(n), C.byref(b), stream))
+        return dict(pairs=int(n.value), bytes=int(b.value))
+
     def backward(self, frame, scene, cam, W, H, opts, dL_drgb):
         """Gradients of L with respect to the raw parameters of `scene`, given
         dL/dRGB [3, H, W] for a frame saved by render(..., save=True).

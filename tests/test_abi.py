@@ -90,6 +90,10 @@ def test_null_arguments_rejected_without_device():
     # render with a NULL context is rejected on the host
     st = B.lib().fgs_render(None, C.byref(sc), C.byref(cam), 8, 8, C.byref(op), 1, None, None, None, None, None)
     assert st == B.FGS_ERR_INVALID_ARGUMENT
+    n = C.c_int64(5)
+    assert B.lib().fgs_plan(None, C.byref(sc), C.byref(cam), 8, 8, C.byref(op), C.byref(n), None, None) == \
+        B.FGS_ERR_INVALID_ARGUMENT
+    assert n.value == 0
     g = B.FgsSceneGrad(0, None, None, None, None, None)
     st = B.lib().fgs_render_backward(None, None, C.byref(sc), C.byref(cam), C.byref(op), None, C.byref(g), None)
     assert st == B.FGS_ERR_INVALID_ARGUMENT

@@ -193,6 +193,23 @@ def test_deterministic_repeat(orc, R, scenes):
         assert np.array_equal(a[k], b[k]), k
 
 
+def test_plan_reports_the_pairs_of_the_render(orc, R, scenes):
+    """fgs_plan runs only the first half: its pair count equals the FP32
+    oracle's and the render's, and a render within its byte figure does not
+    grow the context's scratch beyond it."""
+    sc = scenes.make_scene("medium", P=200_000)
+    cam = scenes.camera_for("medium", 1, W=1280, H=720)
+    gsc = _gs(sc)
+    o = opts()
+    print("[parity] plan: medium P=200000 1280x720", flush=True)
+    pl = R.plan(gsc, cam, 1280, 720, o)
+    o32 = orc.render(sc, cam, 1280, 720, o, mode="f32")
+    assert pl["pairs"] == o32["npairs"]
+    out = R.render(gsc, cam, 1280, 720, o)
+    assert out["stats"]["pairs"] == pl["pairs"]
+    assert pl["bytes"] > 16 * pl["pairs"]
+
+
 def test_large_rectangles_chunked(orc, R):
     """Gaussians whose rectangles span hundreds of tiles (chunked tile test
     and emission across workgroups)."""
