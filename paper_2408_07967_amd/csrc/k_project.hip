@@ -378,49 +378,48 @@ __global__ __launch_bounds__(kBlock) void k_cull(DevScene sc, DevPrepared pp, De
 }
 
 template <bool kPrep>
-__global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevPrepared pp, DevCamera cam, DevOptions op,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_preprocess(DevScene sc, DevPrepared pp, DevCamera cam, DevOptions op,
                                                        int W, int H, GaussState *__restrict__ gs,
                                                        uint4 *__restrict__ rect, uint32_t *__restrict__ count,
                                                        uint4 *__restrict__ erec, uint32_t *__restrict__ dkey,
                                                        const uint32_t *__restrict__ cand,
                                                        const uint32_t *__restrict__ seg_count, uint2 *__restrict__ chunks,
                                                        uint32_t chunk_cap, FrameCounters *fc) {
-    // Persistent grid: each workgroup walks batches of 256 Gaussians and keeps
-    // its depth-digit histogram, visible count and pending chunk reservations
-    // in LDS, so global atomics are per workgroup, not per batch.
-    __shared__ uint32_t s_bg[kBigList], s_boff[kBigList], s_bn[kBigList], s_bx[kBigList], s_by[kBigList];
+    // Persistent grid: each workgroup walks batches of 256 Gaussians.  Every
+    // wavefront keeps its own visible count and pending chunk reservations
+    // (LDS), so the batch loop has no workgroup barrier and global atomics
+    // are per wavefront flush, not per batch.
+    constexpr int kWaveBig = kBigList / (kBlock / kWave);  // pending large Gaussians per wavefront
+    __shared__ uint32_t s_bg[kBlock / kWave][kWaveBig], s_boff[kBlock / kWave][kWaveBig],
+        s_bn[kBlock / kWave][kWaveBig], s_bx[kBlock / kWave][kWaveBig], s_by[kBlock / kWave][kWaveBig];
     __shared__ uint32_t s_excl[kBlock / kWave][kWave], s_mlo[kBlock / kWave][kWave], s_mhi[kBlock / kWave][kWave];
-    __shared__ uint32_t s_vis, s_nbig, s_nch, s_base;
-    if (threadIdx.x == 0) {
-        s_vis = 0;
-        s_nbig = 0;
-        s_nch = 0;
-    }
-    __syncthreads();
+    const int wv = threadIdx.x / kWave;  // this lane's wavefront
+    uint32_t w_nbig = 0, w_nch = 0;      // wave-uniform: pending entries and their chunks
+    uint32_t w_vis = 0;                  // wave-uniform: visible Gaussians so far
 
-    // reserve chunk-list space for the pending large Gaussians and write their
-    // entries (g, first chunk); on overflow only flag it (the host resizes
-    // the list and renders the frame again)
-    auto flush_big = [&]() {
-        __syncthreads();
-        if (threadIdx.x == 0) s_base = s_nch ? atomicAdd(&fc->nchunks, s_nch) : 0u;
-        __syncthreads();
-        const uint32_t base = s_base, nb = s_nbig;
-        const bool ok = (uint64_t)base + s_nch <= chunk_cap;
-        if (!ok && threadIdx.x == 0) atomicOr(&fc->error, kErrChunkOverflow);
+    // reserve chunk-list space for the wavefront's pending large Gaussians
+    // and write their entries (g, first chunk); on overflow only flag it
+    // (the host resizes the list and renders the frame again)
+    auto flush_big = [&](int ln) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        uint32_t base = 0;
+        if (ln == 0) base = atomicAdd(&fc->nchunks, w_nch);
+        base = (uint32_t)__shfl((int)base, 0, kWave);
+        const bool ok = (uint64_t)base + w_nch <= chunk_cap;
+        if (!ok && ln == 0) atomicOr(&fc->error, kErrChunkOverflow);
         if (ok) {
-            for (uint32_t e = threadIdx.x; e < nb; e += kBlock) {
-                const uint32_t gg = s_bg[e], first = base + s_boff[e], n = s_bn[e];
+            for (uint32_t e = (uint32_t)ln; e < w_nbig; e += kWave) {
+                const uint32_t gg = s_bg[wv][e], first = base + s_boff[wv][e], n = s_bn[wv][e];
                 for (uint32_t c = 0; c < n; ++c) chunks[first + c] = make_uint2(gg, first);
-                erec[gg] = make_uint4(s_bx[e], s_by[e], 0u, first);
+                erec[gg] = make_uint4(s_bx[wv][e], s_by[wv][e], 0u, first);
             }
         }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            s_nbig = 0;
-            s_nch = 0;
-        }
-        __syncthreads();
+        // every lane has read the list before it is refilled
+        __builtin_amdgcn_wave_barrier();
+        w_nbig = 0;
+        w_nch = 0;
     };
 
     const int lane = threadIdx.x & (kWave - 1);
@@ -657,14 +656,22 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevPrepared 
     // rectangles of more than kBigTiles tiles go to the chunk list, where
     // workgroups across the GPU test them kChunkTiles tiles at a time
     const bool chunked = valid && nt > kBigTiles;
-    if (chunked) {
-        const uint32_t nch = (uint32_t)((nt + kChunkTiles - 1) / kChunkTiles);
-        const uint32_t slot = atomicAdd(&s_nbig, 1u);
-        s_bg[slot] = (uint32_t)g;
-        s_bn[slot] = nch;
-        s_bx[slot] = (uint32_t)tx0 | ((uint32_t)tx1 << 16);
-        s_by[slot] = (uint32_t)ty0 | ((uint32_t)ty1 << 16);
-        s_boff[slot] = atomicAdd(&s_nch, nch);
+    {
+        const uint64_t cm = __ballot(chunked);
+        if (cm) {  // uniform
+            const uint32_t nch = chunked ? (uint32_t)((nt + kChunkTiles - 1) / kChunkTiles) : 0u;
+            const uint32_t incl = wave_incl_scan(nch, lane);
+            if (chunked) {
+                const uint32_t slot = w_nbig + (uint32_t)__popcll(cm & ((1ull << lane) - 1ull));
+                s_bg[wv][slot] = (uint32_t)g;
+                s_bn[wv][slot] = nch;
+                s_bx[wv][slot] = (uint32_t)tx0 | ((uint32_t)tx1 << 16);
+                s_by[wv][slot] = (uint32_t)ty0 | ((uint32_t)ty1 << 16);
+                s_boff[wv][slot] = w_nch + incl - nch;
+            }
+            w_nbig += (uint32_t)__popcll(cm);
+            w_nch += (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+        }
     }
     const bool small = valid && !chunked;  // rectangle of at most kBigTiles tiles
     if (op.binning != 0) {
@@ -720,13 +727,11 @@ __global__ __launch_bounds__(kBlock) void k_preprocess(DevScene sc, DevPrepared 
                                      (uint32_t)hm, (uint32_t)(hm >> 32));
         }
     }
-    const uint64_t vb = __ballot(valid);
-    if (lane == 0 && vb) atomicAdd(&s_vis, (uint32_t)__popcll(vb));
-    __syncthreads();
-    if (s_nbig > kBigList - kBlock) flush_big();
+    w_vis += (uint32_t)__popcll(__ballot(valid));
+    if (w_nbig > (uint32_t)(kWaveBig - kWave)) flush_big(lane);  // room for the next batch
     }  // batch loop
-    if (s_nbig) flush_big();
-    if (threadIdx.x == 0 && s_vis) atomicAdd(&fc->visible, s_vis);
+    if (w_nbig) flush_big(lane);
+    if (lane == 0 && w_vis) atomicAdd(&fc->visible, w_vis);
 }
 
 // Key emission: one lane per Gaussian in (depth, index) order writes its
