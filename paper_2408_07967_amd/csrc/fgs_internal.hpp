@@ -56,6 +56,7 @@ struct FrameCounters {
     uint32_t pairs;    // total pairs (written by the count scan)
     uint32_t error;    // error bits (kErrChunkOverflow)
     uint32_t nchunks;  // entries requested in the large-Gaussian chunk list
+    uint32_t ncand;    // candidates of a prepared scene's cull (dense depth keys)
 };
 
 // ---- launchers (implemented in the .hip files) ----------------------------
@@ -89,16 +90,18 @@ unsigned emit_grid(uint32_t visible);
 // is set and the host renders the frame again with a larger list) and get
 // count 0 and record (rectangle, 0, first chunk).
 // pp: NULL (raw parameters) or the scene's precompute.  With a precompute a
-// cull pass of kCullBlocks workgroups first writes dkey = kInvalidKey and
-// count = 0 for every Gaussian and lists, for each workgroup's contiguous
-// range, the Gaussians that may be visible (in index order, at the start of
-// the range in cand, capacity sc.P; their number in seg_count[workgroup]),
-// and the preprocess runs over those lists only.
+// cull pass of kCullBlocks workgroups first writes count = 0 for every
+// Gaussian and lists, for each workgroup's contiguous range, the Gaussians
+// that may be visible (in index order, at the start of the range in cand,
+// capacity sc.P; their number in seg_count[workgroup]), and the preprocess
+// runs over those lists only, taken as one list of fc->ncand positions: the
+// depth key of position i goes to dkey[i] and its Gaussian to gmap[i]
+// (without a precompute dkey is indexed by Gaussian and gmap is unused).
 constexpr int kCullBlocks = 2048;
 void launch_preprocess(const DevScene &sc, const DevPrepared *pp, const DevCamera &cam, const DevOptions &op,
                        int W, int H, GaussState *gs, uint4 *rect, uint32_t *count, uint4 *erec, uint32_t *dkey,
-                       uint32_t *cand, uint32_t *seg_count, uint2 *chunks, uint32_t chunk_cap, FrameCounters *fc,
-                       hipStream_t s);
+                       uint32_t *cand, uint32_t *seg_count, uint32_t *gmap, uint2 *chunks, uint32_t chunk_cap,
+                       FrameCounters *fc, hipStream_t s);
 
 // View-independent precompute (opacity, 3D covariance, k^2, log2 opacity,
 // Gaussian-major SH) for options op (alpha_min and cap_3sigma).

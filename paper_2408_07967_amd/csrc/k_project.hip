@@ -310,7 +310,7 @@ __device__ __forceinline__ void cull_range(int64_t P, uint32_t b, int64_t *lo, i
 // covers rounding.  Everything it drops the exact path would cull too.  Each
 // workgroup owns a contiguous range of Gaussians and lists its candidates in
 // index order at the start of that range (no global atomics); every
-// Gaussian's depth key starts invalid and its tile count zero.
+// Gaussian's tile count starts at zero.
 __global__ __launch_bounds__(kBlock) void k_cull(DevScene sc, DevPrepared pp, DevCamera cam, DevOptions op, int W,
                                                  int H, uint32_t *__restrict__ dkey, uint32_t *__restrict__ count,
                                                  uint32_t *__restrict__ cand, uint32_t *__restrict__ seg_count) {
@@ -323,7 +323,6 @@ __global__ __launch_bounds__(kBlock) void k_cull(DevScene sc, DevPrepared pp, De
         const int64_t g = g0 + threadIdx.x;
         bool keep = false;
         if (g < hi) {
-            dkey[g] = kInvalidKey;
             count[g] = 0u;
             const float4 p4 = pp.pos_o[g];
             const float *R = cam.R;
@@ -383,7 +382,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                                                        uint4 *__restrict__ rect, uint32_t *__restrict__ count,
                                                        uint4 *__restrict__ erec, uint32_t *__restrict__ dkey,
                                                        const uint32_t *__restrict__ cand,
-                                                       const uint32_t *__restrict__ seg_count, uint2 *__restrict__ chunks,
+                                                       const uint32_t *__restrict__ seg_count,
+                                                       uint32_t *__restrict__ gmap, uint2 *__restrict__ chunks,
                                                        uint32_t chunk_cap, FrameCounters *fc) {
     // Persistent grid: each workgroup walks batches of 256 Gaussians.  Every
     // wavefront keeps its own visible count and pending chunk reservations
@@ -456,12 +456,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         }
         __syncthreads();
     }
+    if constexpr (kPrep) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) fc->ncand = ncand;
+    }
     int64_t batch = blockIdx.x;  // batch of 256 list positions (prepared) or Gaussians (raw)
     for (;;) {
     int64_t g = sc.P;
+    uint32_t ii = 0;  // prepared: position in the candidate list
     if constexpr (kPrep) {
         if ((uint64_t)batch * kBlock >= ncand) break;
-        const uint32_t ii = (uint32_t)batch * kBlock + threadIdx.x;
+        ii = (uint32_t)batch * kBlock + threadIdx.x;
         if (ii < ncand) {
             // last segment whose prefix is <= ii: it holds position ii
             uint32_t sg = 0;
@@ -711,7 +715,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 
     if (g < sc.P) {
         const uint32_t key = valid ? __float_as_uint(tz) : kInvalidKey;
-        dkey[g] = key;
+        if constexpr (kPrep) {
+            // depth keys of a prepared scene's candidates are dense, at their
+            // list positions, with the Gaussian beside them (gmap)
+            dkey[ii] = key;
+            gmap[ii] = (uint32_t)g;
+        } else {
+            dkey[g] = key;
+        }
         count[g] = valid ? cnt : 0u;
         if (valid) {
             GaussState s;
@@ -948,17 +959,17 @@ unsigned emit_grid(uint32_t visible) {
 
 void launch_preprocess(const DevScene &sc, const DevPrepared *pp, const DevCamera &cam, const DevOptions &op,
                        int W, int H, GaussState *gs, uint4 *rect, uint32_t *count, uint4 *erec, uint32_t *dkey,
-                       uint32_t *cand, uint32_t *seg_count, uint2 *chunks, uint32_t chunk_cap, FrameCounters *fc,
-                       hipStream_t s) {
+                       uint32_t *cand, uint32_t *seg_count, uint32_t *gmap, uint2 *chunks, uint32_t chunk_cap,
+                       FrameCounters *fc, hipStream_t s) {
     if (sc.P <= 0) return;
     if (pp) {
         hipLaunchKernelGGL(k_cull, dim3(kCullBlocks), dim3(kBlock), 0, s, sc, *pp, cam, op, W, H, dkey, count, cand,
                            seg_count);
         hipLaunchKernelGGL(k_preprocess<true>, dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, *pp, cam, op, W,
-                           H, gs, rect, count, erec, dkey, cand, seg_count, chunks, chunk_cap, fc);
+                           H, gs, rect, count, erec, dkey, cand, seg_count, gmap, chunks, chunk_cap, fc);
     } else {
         hipLaunchKernelGGL(k_preprocess<false>, dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, DevPrepared{},
-                           cam, op, W, H, gs, rect, count, erec, dkey, cand, seg_count, chunks, chunk_cap, fc);
+                           cam, op, W, H, gs, rect, count, erec, dkey, cand, seg_count, gmap, chunks, chunk_cap, fc);
     }
 }
 

@@ -267,8 +267,10 @@ void enqueue_front(const DevScene &sc, const DevPrepared *pp, const DevCamera &c
     launch_fill_u32(reinterpret_cast<uint32_t *>(fc), 0u, sizeof(FrameCounters) / 4, s);
     mk.mark(0, s);
     // the candidate list of a prepared scene lives in dv_b until the depth sort
+    // (a prepared scene's depth keys are dense over the candidates, with the
+    // Gaussian index of each in fb.offsets, free until the count scan)
     launch_preprocess(sc, pp, cam, op, W, H, fb.gs, fb.rect, fb.count, fb.erec, fb.dkey, fb.dv_b, fb.seg_count,
-                      ch.chunks, chunk_cap, fc, s);
+                      fb.offsets, ch.chunks, chunk_cap, fc, s);
     // the large rectangles' exact tests touch neither the depth keys nor the
     // sort scratch: they run beside the depth sort
     hipStream_t sb = s;
@@ -283,7 +285,11 @@ void enqueue_front(const DevScene &sc, const DevPrepared *pp, const DevCamera &c
     // depth) key is the same for every pair of a Gaussian) --------------------
     mk.mark(1, s);
     const uint32_t P32 = (uint32_t)sc.P;
-    launch_radix_pass(fb.dkey, nullptr, fb.dk_b, fb.dv_b, P32, nullptr, 0, 8, true, true, ss.rhist, ss.gsum, s);
+    if (pp)
+        launch_radix_pass(fb.dkey, fb.offsets, fb.dk_b, fb.dv_b, P32, &fc->ncand, 0, 8, true, true, ss.rhist,
+                          ss.gsum, s);
+    else
+        launch_radix_pass(fb.dkey, nullptr, fb.dk_b, fb.dv_b, P32, nullptr, 0, 8, true, true, ss.rhist, ss.gsum, s);
     launch_radix_pass(fb.dk_b, fb.dv_b, fb.dkey, fb.dv_a, P32, &fc->visible, 8, 8, false, true, ss.rhist, ss.gsum, s);
     launch_radix_pass(fb.dkey, fb.dv_a, fb.dk_b, fb.dv_b, P32, &fc->visible, 16, 8, false, true, ss.rhist, ss.gsum,
                       s);
