@@ -239,9 +239,10 @@ fgs_status fgs_frame_release(fgs_context *ctx, fgs_frame *frame);
  *   FGS_FIELD_RECT    [P][4] int32: tx0, tx1, ty0, ty1 (valid only)
  *   FGS_FIELD_COUNT   [P] uint32 exact tile count (0 for culled Gaussians)
  *   FGS_FIELD_ORDER   [visible] uint32 Gaussian indices in (depth, index) order
- *   FGS_FIELD_TILES   [pairs] uint32 tile id of each sorted pair
+ *   FGS_FIELD_TILES   [pairs] uint32 tile id of each sorted pair (the sort keeps only
+ *                     the ranges; the ids are expanded from them on the host)
  *   FGS_FIELD_VALUES  [pairs] uint32 Gaussian index of each sorted pair
- *   FGS_FIELD_RANGES  [tiles][2] uint32 [start, end) of each tile's list
+ *   FGS_FIELD_RANGES  [tiles][2] uint32 [start, end) of each tile's list ((0, 0) if empty)
  * `bytes` must equal the field's size (fgs_frame_field_bytes). */
 typedef enum {
     FGS_FIELD_GAUSS = 0,

@@ -133,9 +133,18 @@ void launch_big_emit(int W, const uint4 *rect, const uint4 *erec, const uint2 *c
 //   vals_in null: values are the input positions
 //   filter  drop keys equal to kInvalidKey
 //   hist    scratch [kSortBlocks][kRadix]; gsum scratch [kSortGroups][kRadix]
+//   run_ends if non-null (the last pass of a sort by the whole key, keys <
+//           nruns): run_ends[k] = [start, end) of key k's run in the output,
+//           by atomic min / max on entries set by launch_init_ranges; a key
+//           with no element keeps start > end
 void launch_radix_pass(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_out, uint32_t *vals_out,
                        uint32_t n_host, const uint32_t *n_dev, int shift, int bits, bool filter, bool write_keys,
-                       uint32_t *hist, uint32_t *gsum, hipStream_t s);
+                       uint32_t *hist, uint32_t *gsum, hipStream_t s, uint2 *run_ends = nullptr,
+                       uint32_t nruns = 0);
+
+// ranges[t] = (0xffffffff, 0) for t < ntiles: an empty range that atomic
+// min / max narrow to the tile's run.
+void launch_init_ranges(uint2 *ranges, uint32_t ntiles, hipStream_t s);
 
 // offsets[r] = sum of count[order[r']] for r' < r over the n visible
 // Gaussians (n_dev, bounded by n_host); offsets[n] and *pairs get the total.

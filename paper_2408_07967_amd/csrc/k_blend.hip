@@ -95,7 +95,7 @@ __global__ __launch_bounds__(kThreads) void k_blend(const GaussState *__restrict
     const float py = (float)pj + 0.5f;
 
     const uint2 rg = ranges[tile];
-    const uint32_t start = rg.x, end = rg.y;
+    const uint32_t start = rg.x, end = rg.y > rg.x ? rg.y : rg.x;  // an empty tile may hold start > end
     Pixel p0{in0 ? (float)pi0 + 0.5f : kFar, 1.0f, 0.0f, 0.0f, 0.0f, 0u, in0 ? end - start : 0u, !in0};
     Pixel p1{in1 ? (float)pi0 + 1.5f : kFar, 1.0f, 0.0f, 0.0f, 0.0f, 0u, in1 ? end - start : 0u, !in1};
     bool wave_done = __ballot(!(p0.done && p1.done)) == 0;

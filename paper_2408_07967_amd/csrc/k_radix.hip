@@ -115,7 +115,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                                                             uint32_t *__restrict__ vals_out, uint32_t n_host,
                                                             const uint32_t *n_dev, int shift, int bits,
                                                             const uint32_t *__restrict__ hist,
-                                                            const uint32_t *__restrict__ gsum) {
+                                                            const uint32_t *__restrict__ gsum,
+                                                            uint32_t *__restrict__ run_end, uint32_t nruns) {
     __shared__ uint32_t s_keys[kSortTile];
     __shared__ uint32_t s_vals[kSortTile];
     __shared__ uint32_t s_wave[kWaves][kRadix];
@@ -231,6 +232,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             if (gpos < n) {  // never leave the output (n bounds the scattered count)
                 if (kWriteKeys) keys_out[gpos] = k;
                 vals_out[gpos] = s_vals[j];
+                // last pass of a sort by the whole key: the keys of one
+                // digit run of this tile are in key order, so the first and
+                // last element of each key's stretch may start and end its run
+                if (run_end && k < nruns) {
+                    if (j == 0 || s_keys[j - 1] != k) atomicMin(&run_end[2 * (size_t)k], gpos);
+                    if (j + 1 == nv || s_keys[j + 1] != k) atomicMax(&run_end[2 * (size_t)k + 1], gpos + 1);
+                }
             }
         }
         __syncthreads();
@@ -317,7 +325,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_downsweep(const uint32_t *__res
 
 void launch_radix_pass(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_out, uint32_t *vals_out,
                        uint32_t n_host, const uint32_t *n_dev, int shift, int bits, bool filter, bool write_keys,
-                       uint32_t *hist, uint32_t *gsum, hipStream_t s) {
+                       uint32_t *hist, uint32_t *gsum, hipStream_t s, uint2 *run_ends, uint32_t nruns) {
     if (n_host == 0) return;
     const unsigned nb = kSortBlocks;
     if (filter)
@@ -330,7 +338,7 @@ void launch_radix_pass(const uint32_t *keys_in, const uint32_t *vals_in, uint32_
     const bool ident = vals_in == nullptr;
 #define FGS_DS(I, F, K)                                                                                         \
     hipLaunchKernelGGL((k_radix_downsweep<I, F, K>), dim3(nb), dim3(kBlock), 0, s, keys_in, vals_in, keys_out, \
-                       vals_out, n_host, n_dev, shift, bits, hist, gsum)
+                       vals_out, n_host, n_dev, shift, bits, hist, gsum, reinterpret_cast<uint32_t *>(run_ends), nruns)
     if (ident && filter && write_keys) FGS_DS(true, true, true);
     else if (!ident && !filter && write_keys) FGS_DS(false, false, true);
     else if (!ident && !filter && !write_keys) FGS_DS(false, false, false);

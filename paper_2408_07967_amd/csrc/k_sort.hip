@@ -43,7 +43,19 @@ __global__ void k_tile_ranges(const uint32_t *__restrict__ keys, uint32_t n, con
     }
 }
 
+__global__ void k_init_ranges(uint2 *__restrict__ ranges, uint32_t ntiles) {
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += gridDim.x * blockDim.x)
+        ranges[t] = make_uint2(0xffffffffu, 0u);
+}
+
 }  // namespace
+
+void launch_init_ranges(uint2 *ranges, uint32_t ntiles, hipStream_t s) {
+    if (ntiles == 0) return;
+    uint32_t blocks = (ntiles + kBlock - 1) / kBlock;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_init_ranges, dim3(blocks), dim3(kBlock), 0, s, ranges, ntiles);
+}
 
 void launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t s) {
     if (n == 0) return;

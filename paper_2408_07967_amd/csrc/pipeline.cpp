@@ -319,14 +319,19 @@ bool enqueue_back(int W, int H, const DevOptions &op, uint32_t P, FrameBuffers &
     int shifts[4] = {0, 0, 0, 0}, widths[4] = {0, 0, 0, 0};
     const int npass = plan_tile_passes(ceil_log2(ntiles), shifts, widths);
     uint32_t *ki = fb.tk_a, *vi = fb.tv_a, *ko = fb.tk_b, *vo = fb.tv_b;
+    // The last pass records where each tile's run starts and ends instead of
+    // writing the sorted tile ids (an empty tile keeps start > end).  A
+    // one-tile image has no pass: its range comes from the emitted ids.
+    if (npass > 0) launch_init_ranges(fb.ranges, ntiles, s);
     for (int p = 0; p < npass; ++p) {
-        launch_radix_pass(ki, vi, ko, vo, pair_cap, &fc->pairs, shifts[p], widths[p], false, true, ss.rhist, ss.gsum,
-                          s);
+        const bool last_pass = p + 1 == npass;
+        launch_radix_pass(ki, vi, ko, vo, pair_cap, &fc->pairs, shifts[p], widths[p], false, !last_pass, ss.rhist,
+                          ss.gsum, s, last_pass ? fb.ranges : nullptr, ntiles);
         std::swap(ki, ko);
         std::swap(vi, vo);
     }
     mk.mark(5, s);
-    launch_tile_ranges(ki, pair_cap, &fc->pairs, fb.ranges, ntiles, s);
+    if (npass == 0) launch_tile_ranges(ki, pair_cap, &fc->pairs, fb.ranges, ntiles, s);
     mk.mark(6, s);
     // ---- stage 4: blend -------------------------------------------------------------
     launch_blend(fb.gs, vi, fb.ranges, W, H, op, rgb, T, last, work, s);

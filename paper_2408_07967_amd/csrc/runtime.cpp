@@ -538,14 +538,32 @@ fgs_status fgs_frame_download(fgs_context *ctx, const fgs_frame *f, fgs_field fi
     case FGS_FIELD_RECT: src = b.rect; break;
     case FGS_FIELD_COUNT: src = b.count; break;
     case FGS_FIELD_ORDER: src = b.dv_a; break;
-    case FGS_FIELD_TILES: src = f->tiles_in_a ? b.tk_a : b.tk_b; break;
+    case FGS_FIELD_TILES: break;  // expanded from the ranges below
     case FGS_FIELD_VALUES: src = f->tiles_in_a ? b.tv_a : b.tv_b; break;
     case FGS_FIELD_RANGES: src = b.ranges; break;
     default: return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "unknown field %d", (int)field);
     }
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     HIP_TRY(ctx, hipStreamSynchronize(f->stream));
+    if (field == FGS_FIELD_TILES) {
+        // the sort's last pass records the tile ranges, not the sorted tile
+        // ids: the id of pair i is the tile whose range holds i
+        const size_t tiles = (size_t)f->stats.tiles_x * f->stats.tiles_y;
+        std::vector<uint2> rg(tiles);
+        HIP_TRY(ctx, hipMemcpy(rg.data(), b.ranges, tiles * sizeof(uint2), hipMemcpyDeviceToHost));
+        uint32_t *dst = static_cast<uint32_t *>(host_dst);
+        for (size_t i = 0; i < f->pairs; ++i) dst[i] = 0xffffffffu;
+        for (size_t t = 0; t < tiles; ++t)
+            for (uint32_t i = rg[t].x; i < rg[t].y && i < f->pairs; ++i) dst[i] = (uint32_t)t;
+        return FGS_OK;
+    }
     HIP_TRY(ctx, hipMemcpy(host_dst, src, bytes, hipMemcpyDeviceToHost));
+    if (field == FGS_FIELD_RANGES) {
+        // an empty tile may hold start > end on the device; report (0, 0)
+        uint2 *r = static_cast<uint2 *>(host_dst);
+        for (size_t t = 0; t < bytes / sizeof(uint2); ++t)
+            if (r[t].x >= r[t].y) r[t] = make_uint2(0u, 0u);
+    }
     return FGS_OK;
 }
 
