@@ -160,9 +160,11 @@ size_t fgs_scratch_bytes(const fgs_context *ctx);
  *            fgs_render_backward / fgs_frame_download; release it with
  *            fgs_frame_release.
  *   stats    host, or NULL: counts of the frame.
- * The call waits once on `stream` to read the number of pairs (busy-polling
- * an event, so the calling thread spins for the front half of the frame),
- * then enqueues the rest.  opt == NULL means defaults. */
+ * The call enqueues the whole frame, then waits once on `stream` for the
+ * number of pairs (busy-polling an event, so the calling thread spins for the
+ * first half of the frame); if the context's pair buffers were too small for
+ * it, they grow and the second half is enqueued again.  It returns with the
+ * second half still in flight.  opt == NULL means defaults. */
 fgs_status fgs_render(fgs_context *ctx, const fgs_scene *scene, const fgs_camera *cam, int32_t W, int32_t H,
                       const fgs_options *opt, float *out_rgb, float *out_T, uint32_t *out_last,
                       fgs_frame **saved, fgs_stats *stats, void *stream);

@@ -293,16 +293,32 @@ fgs_status render_impl(fgs_context *ctx, const fgs_scene *scene, const fgs_prepa
     StageMarks mk;
     if (timed) mk.ev = ctx->ev[es];
 
+    float *Tdst = saved ? fb.T : out_T;
+    uint32_t *Ldst = saved ? fb.last : out_last;
+    unsigned long long *work = (ctx->instr & FGS_INSTR_WORK) ? ctx->work_dev : nullptr;
     uint32_t V = 0, N = 0, big = 0;
+    bool tiles_in_a = true;
+    size_t spec_cap = 0;  // pair capacity of a second half already enqueued (0: none)
     for (int attempt = 0;; ++attempt) {
         const DevPrepared pdev = prep ? prep->pb.dev() : DevPrepared{};
         enqueue_front(dsc, prep ? &pdev : nullptr, dcam, dop, W, H, fb, ctx->ch, ctx->ss, ctx->fc_dev, ctx->fc_host,
                       s, ctx->side, mk);
         HIP_TRY(ctx, hipGetLastError());
-        // The back half is sized by the pair count: wait for the counters by
-        // polling (the front half takes about a millisecond at 4K, where a
-        // blocking wait's wake-up would add a large share of that).
         HIP_TRY(ctx, hipEventRecord(ctx->front_done, s));
+        // The second half reads every count on the device and never writes
+        // beyond the pair buffers, so it is enqueued at once with the buffers
+        // at hand; the GPU goes on while the host reads the pair count.  If
+        // the frame has more pairs than they hold, it runs again below.
+        spec_cap = 0;
+        if (!plan && !work && fb.capN > 0) {
+            tiles_in_a = enqueue_back(W, H, dop, (uint32_t)P, fb, ctx->ch, ctx->ss, ctx->fc_dev, out_rgb, Tdst, Ldst,
+                                      nullptr, s, mk);
+            HIP_TRY(ctx, hipGetLastError());
+            spec_cap = fb.capN;
+        }
+        // wait for the counters by polling (the first half takes about a
+        // millisecond at 4K, where a blocking wait's wake-up would add a
+        // large share of that)
         hipError_t q;
         while ((q = hipEventQuery(ctx->front_done)) == hipErrorNotReady) {
         }
@@ -310,8 +326,10 @@ fgs_status render_impl(fgs_context *ctx, const fgs_scene *scene, const fgs_prepa
         fold_events(ctx);  // the previous instrumented frame is complete after the wait
         if (ctx->fc_host->error & kErrChunkOverflow) {
             // the large-Gaussian chunk list was too small: size it exactly and
-            // render the frame again
+            // render the frame again (a second half already enqueued skipped
+            // the large rectangles; it is redone)
             if (attempt > 0) return fail(ctx, FGS_ERR_INTERNAL, "chunk list overflow after resizing");
+            if (spec_cap) HIP_TRY(ctx, hipStreamSynchronize(s));  // the list is in use
             HIP_TRY(ctx, ensure_chunks(ctx->ch, (size_t)ctx->fc_host->nchunks + (size_t)ctx->fc_host->nchunks / 8));
             continue;
         }
@@ -341,11 +359,14 @@ fgs_status render_impl(fgs_context *ctx, const fgs_scene *scene, const fgs_prepa
         }
         return FGS_OK;
     }
-    HIP_TRY(ctx, ensure_pairs(fb, N));
-    float *Tdst = saved ? fb.T : out_T;
-    uint32_t *Ldst = saved ? fb.last : out_last;
-    const bool tiles_in_a = enqueue_back(W, H, dop, (uint32_t)P, fb, ctx->ch, ctx->ss, ctx->fc_dev, out_rgb, Tdst,
-                                         Ldst, (ctx->instr & FGS_INSTR_WORK) ? ctx->work_dev : nullptr, s, mk);
+    if (spec_cap == 0 || N > spec_cap) {
+        // no second half yet, or it ran out of pair buffer: grow the buffers
+        // (after it has finished with them) and enqueue it again
+        if (spec_cap) HIP_TRY(ctx, hipStreamSynchronize(s));
+        HIP_TRY(ctx, ensure_pairs(fb, N));
+        tiles_in_a = enqueue_back(W, H, dop, (uint32_t)P, fb, ctx->ch, ctx->ss, ctx->fc_dev, out_rgb, Tdst, Ldst,
+                                  work, s, mk);
+    }
     HIP_TRY(ctx, hipGetLastError());
     if (timed) {
         ctx->ev_pending = es;
