@@ -117,14 +117,15 @@ void launch_big_count(int W, int H, int binning, const GaussState *gs, const uin
 // Emit (tile, gaussian) pairs for Gaussians in depth order.  Chunked
 // Gaussians only record their output base in erec[g].z.
 // visible: the count, or a bound on it when visible_dev (device) holds it.
+// tile_keys: uint32 or, with key_bytes == 2, uint16 tile ids
 void launch_emit(int W, int H, const uint32_t *order, uint32_t visible, const uint32_t *visible_dev,
-                 const uint32_t *offsets, uint4 *erec, uint32_t *tile_keys, uint32_t *values, uint32_t cap,
+                 const uint32_t *offsets, uint4 *erec, void *tile_keys, int key_bytes, uint32_t *values, uint32_t cap,
                  hipStream_t s);
 
 // Emit the pairs of the chunked Gaussians (after launch_emit).
 void launch_big_emit(int W, const uint4 *rect, const uint4 *erec, const uint2 *chunks, uint32_t chunk_cap,
-                     const uint32_t *chunk_hits, const uint32_t *chunk_mask, uint32_t *tile_keys, uint32_t *values,
-                     uint32_t cap, const FrameCounters *fc, hipStream_t s);
+                     const uint32_t *chunk_hits, const uint32_t *chunk_mask, void *tile_keys, int key_bytes,
+                     uint32_t *values, uint32_t cap, const FrameCounters *fc, hipStream_t s);
 
 // One stable LSD radix pass of (key, value) pairs by the digit
 // (key >> shift) & ((1 << bits) - 1), bits <= 8.
@@ -137,10 +138,12 @@ void launch_big_emit(int W, const uint4 *rect, const uint4 *erec, const uint2 *c
 //           nruns): run_ends[k] = [start, end) of key k's run in the output,
 //           by atomic min / max on entries set by launch_init_ranges; a key
 //           with no element keeps start > end
-void launch_radix_pass(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_out, uint32_t *vals_out,
+//   key_bytes 4 (uint32 keys) or 2 (uint16 keys: unfiltered passes with
+//           explicit values only)
+void launch_radix_pass(const void *keys_in, const uint32_t *vals_in, void *keys_out, uint32_t *vals_out,
                        uint32_t n_host, const uint32_t *n_dev, int shift, int bits, bool filter, bool write_keys,
                        uint32_t *hist, uint32_t *gsum, hipStream_t s, uint2 *run_ends = nullptr,
-                       uint32_t nruns = 0);
+                       uint32_t nruns = 0, int key_bytes = 4);
 
 // ranges[t] = (0xffffffff, 0) for t < ntiles: an empty range that atomic
 // min / max narrow to the tile's run.
@@ -152,9 +155,8 @@ void launch_init_ranges(uint2 *ranges, uint32_t ntiles, hipStream_t s);
 void launch_count_scan(const uint32_t *order, const uint32_t *count, uint32_t n_host, const uint32_t *n_dev,
                        uint32_t *cs, uint32_t *sums, uint32_t *offsets, uint32_t *pairs, hipStream_t s);
 
-// n: the key count, or a bound on it when n_dev (device) holds it.
-void launch_tile_ranges(const uint32_t *tile_keys, uint32_t n, const uint32_t *n_dev, uint2 *ranges,
-                        uint32_t ntiles, hipStream_t s);
+// A one-tile image: ranges[0] = [0, min(*n_dev, n)).
+void launch_single_range(uint2 *ranges, uint32_t n, const uint32_t *n_dev, hipStream_t s);
 
 // work: if non-null, the blend adds the number of list entries every pixel
 // examines (a separate, slower kernel instantiation)

@@ -749,10 +749,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 // (tile, index) pairs at its scanned offset (Alg. 2 with the offsets of a
 // prefix scan; the tile test is reused from the preprocess through the hit
 // mask).  Chunked Gaussians only record their output base here.
+template <class KeyT>
 __global__ __launch_bounds__(kBlock) void k_emit(int W, int H, const uint32_t *__restrict__ order,
                                                  uint32_t visible, const uint32_t *__restrict__ visible_dev,
                                                  const uint32_t *__restrict__ offsets, uint4 *__restrict__ erec,
-                                                 uint32_t *__restrict__ tile_keys, uint32_t *__restrict__ values,
+                                                 KeyT *__restrict__ tile_keys, uint32_t *__restrict__ values,
                                                  uint32_t cap) {
     __shared__ uint32_t s_excl[kBlock / kWave][kWave];
     // the visible count comes from the device when the launch is sized by a
@@ -802,7 +803,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(int W, int H, const uint32_t *_
             const uint32_t tile = (uint32_t)((ty0L + ry) * tiles_x + (tx0L + rx));
             const uint32_t at = baseL + (uint32_t)__popcll(mL & ((1ull << k) - 1ull));
             if (at < cap) {  // never leave the pair buffers
-                tile_keys[at] = tile;
+                tile_keys[at] = (KeyT)tile;
                 values[at] = gL;
             }
         }
@@ -871,11 +872,12 @@ __global__ __launch_bounds__(kBlock) void k_big_count(int W, int H, int binning,
 
 // Pairs of the chunked Gaussians: each chunk (one wavefront) writes the hits
 // recorded by k_big_count after those of the Gaussian's earlier chunks.
+template <class KeyT>
 __global__ __launch_bounds__(kBlock) void k_big_emit(int W, const uint4 *__restrict__ rect,
                                                      const uint4 *__restrict__ erec, const uint2 *__restrict__ chunks,
                                                      uint32_t chunk_cap, const uint32_t *__restrict__ chunk_hits,
                                                      const uint32_t *__restrict__ chunk_mask,
-                                                     uint32_t *__restrict__ tile_keys, uint32_t *__restrict__ values,
+                                                     KeyT *__restrict__ tile_keys, uint32_t *__restrict__ values,
                                                      uint32_t cap, const FrameCounters *fc) {
     constexpr int kPer = kChunkTiles / kWave;
     const int lane = threadIdx.x & (kWave - 1);
@@ -918,7 +920,7 @@ __global__ __launch_bounds__(kBlock) void k_big_emit(int W, const uint4 *__restr
                 const uint32_t tile = (uint32_t)(((int)rc.z + ry) * tiles_x + ((int)rc.x + rx));
                 const uint32_t at = before + (uint32_t)__popcll(b[j] & lt);
                 if (at < cap) {  // never leave the pair buffers
-                    tile_keys[at] = tile;
+                    tile_keys[at] = (KeyT)tile;
                     values[at] = g;
                 }
             }
@@ -952,7 +954,7 @@ unsigned preprocess_grid(int64_t P) {
 }
 
 unsigned emit_grid(uint32_t visible) {
-    static const unsigned cap = resident_blocks(k_emit);
+    static const unsigned cap = resident_blocks(k_emit<uint32_t>);
     const uint32_t b = (visible + kBlock - 1) / kBlock;
     return b < cap ? (b > 0 ? b : 1u) : cap;
 }
@@ -990,18 +992,26 @@ void launch_big_count(int W, int H, int binning, const GaussState *gs, const uin
 }
 
 void launch_big_emit(int W, const uint4 *rect, const uint4 *erec, const uint2 *chunks, uint32_t chunk_cap,
-                     const uint32_t *chunk_hits, const uint32_t *chunk_mask, uint32_t *tile_keys, uint32_t *values,
-                     uint32_t cap, const FrameCounters *fc, hipStream_t s) {
-    hipLaunchKernelGGL(k_big_emit, dim3(kPersistentBlocks), dim3(kBlock), 0, s, W, rect, erec, chunks, chunk_cap,
-                       chunk_hits, chunk_mask, tile_keys, values, cap, fc);
+                     const uint32_t *chunk_hits, const uint32_t *chunk_mask, void *tile_keys, int key_bytes,
+                     uint32_t *values, uint32_t cap, const FrameCounters *fc, hipStream_t s) {
+    if (key_bytes == 2)
+        hipLaunchKernelGGL(k_big_emit<uint16_t>, dim3(kPersistentBlocks), dim3(kBlock), 0, s, W, rect, erec, chunks,
+                           chunk_cap, chunk_hits, chunk_mask, static_cast<uint16_t *>(tile_keys), values, cap, fc);
+    else
+        hipLaunchKernelGGL(k_big_emit<uint32_t>, dim3(kPersistentBlocks), dim3(kBlock), 0, s, W, rect, erec, chunks,
+                           chunk_cap, chunk_hits, chunk_mask, static_cast<uint32_t *>(tile_keys), values, cap, fc);
 }
 
 void launch_emit(int W, int H, const uint32_t *order, uint32_t visible, const uint32_t *visible_dev,
-                 const uint32_t *offsets, uint4 *erec, uint32_t *tile_keys, uint32_t *values, uint32_t cap,
+                 const uint32_t *offsets, uint4 *erec, void *tile_keys, int key_bytes, uint32_t *values, uint32_t cap,
                  hipStream_t s) {
     if (visible == 0) return;
-    hipLaunchKernelGGL(k_emit, dim3(emit_grid(visible)), dim3(kBlock), 0, s, W, H, order, visible, visible_dev,
-                       offsets, erec, tile_keys, values, cap);
+    if (key_bytes == 2)
+        hipLaunchKernelGGL(k_emit<uint16_t>, dim3(emit_grid(visible)), dim3(kBlock), 0, s, W, H, order, visible,
+                           visible_dev, offsets, erec, static_cast<uint16_t *>(tile_keys), values, cap);
+    else
+        hipLaunchKernelGGL(k_emit<uint32_t>, dim3(emit_grid(visible)), dim3(kBlock), 0, s, W, H, order, visible,
+                           visible_dev, offsets, erec, static_cast<uint32_t *>(tile_keys), values, cap);
 }
 
 }  // namespace fgs

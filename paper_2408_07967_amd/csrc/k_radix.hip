@@ -65,8 +65,8 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s
     return wpre + x - v;
 }
 
-template <bool kFilter>
-__global__ __launch_bounds__(kBlock) void k_radix_upsweep(const uint32_t *__restrict__ keys, uint32_t n_host,
+template <bool kFilter, class KeyT>
+__global__ __launch_bounds__(kBlock) void k_radix_upsweep(const KeyT *__restrict__ keys, uint32_t n_host,
                                                           const uint32_t *n_dev, int shift, int bits,
                                                           uint32_t *__restrict__ hist) {
     __shared__ uint32_t s_h[kWaves][kRadix];
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_upsweep(const uint32_t *__rest
 #pragma unroll
         for (int i = 0; i < kSortItems; ++i) {
             const uint32_t idx = c0 + (uint32_t)(i * kBlock + tid);
-            k[i] = idx < hi ? keys[idx] : kInvalidKey;
+            k[i] = idx < hi ? (uint32_t)keys[idx] : kInvalidKey;
         }
 #pragma unroll
         for (int i = 0; i < kSortItems; ++i) {
@@ -108,10 +108,10 @@ __global__ __launch_bounds__(kBlock) void k_radix_groups(const uint32_t *__restr
 
 // (LDS holds four workgroups per CU, so registers are capped at what four
 // waves per SIMD allow.)
-template <bool kIdentityVals, bool kFilter, bool kWriteKeys>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_radix_downsweep(const uint32_t *__restrict__ keys_in,
+template <bool kIdentityVals, bool kFilter, bool kWriteKeys, class KeyT>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_radix_downsweep(const KeyT *__restrict__ keys_in,
                                                             const uint32_t *__restrict__ vals_in,
-                                                            uint32_t *__restrict__ keys_out,
+                                                            KeyT *__restrict__ keys_out,
                                                             uint32_t *__restrict__ vals_out, uint32_t n_host,
                                                             const uint32_t *n_dev, int shift, int bits,
                                                             const uint32_t *__restrict__ hist,
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         for (int i = 0; i < kSortItems; ++i) {
             const uint32_t idx = base + (uint32_t)(i * kWave + lane);
             const bool in = idx < hi;
-            key[i] = in ? keys_in[idx] : kInvalidKey;
+            key[i] = in ? (uint32_t)keys_in[idx] : kInvalidKey;
             val[i] = kIdentityVals ? idx : (in ? vals_in[idx] : 0u);
         }
     };
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             const uint32_t d = (k >> shift) & dmask;
             const uint32_t gpos = s_off[d] + (j - s_excl[d]);
             if (gpos < n) {  // never leave the output (n bounds the scattered count)
-                if (kWriteKeys) keys_out[gpos] = k;
+                if (kWriteKeys) keys_out[gpos] = (KeyT)k;
                 vals_out[gpos] = s_vals[j];
                 // last pass of a sort by the whole key: the keys of one
                 // digit run of this tile are in key order, so the first and
@@ -323,27 +323,38 @@ __global__ __launch_bounds__(kBlock) void k_scan_downsweep(const uint32_t *__res
 
 }  // namespace
 
-void launch_radix_pass(const uint32_t *keys_in, const uint32_t *vals_in, uint32_t *keys_out, uint32_t *vals_out,
+void launch_radix_pass(const void *keys_in, const uint32_t *vals_in, void *keys_out, uint32_t *vals_out,
                        uint32_t n_host, const uint32_t *n_dev, int shift, int bits, bool filter, bool write_keys,
-                       uint32_t *hist, uint32_t *gsum, hipStream_t s, uint2 *run_ends, uint32_t nruns) {
+                       uint32_t *hist, uint32_t *gsum, hipStream_t s, uint2 *run_ends, uint32_t nruns, int key_bytes) {
     if (n_host == 0) return;
     const unsigned nb = kSortBlocks;
-    if (filter)
-        hipLaunchKernelGGL(k_radix_upsweep<true>, dim3(nb), dim3(kBlock), 0, s, keys_in, n_host, n_dev, shift, bits,
-                           hist);
+    const bool k16 = key_bytes == 2;
+    const uint32_t *k32i = static_cast<const uint32_t *>(keys_in);
+    const uint16_t *k16i = static_cast<const uint16_t *>(keys_in);
+    if (k16)
+        hipLaunchKernelGGL((k_radix_upsweep<false, uint16_t>), dim3(nb), dim3(kBlock), 0, s, k16i, n_host, n_dev,
+                           shift, bits, hist);
+    else if (filter)
+        hipLaunchKernelGGL((k_radix_upsweep<true, uint32_t>), dim3(nb), dim3(kBlock), 0, s, k32i, n_host, n_dev,
+                           shift, bits, hist);
     else
-        hipLaunchKernelGGL(k_radix_upsweep<false>, dim3(nb), dim3(kBlock), 0, s, keys_in, n_host, n_dev, shift,
-                           bits, hist);
+        hipLaunchKernelGGL((k_radix_upsweep<false, uint32_t>), dim3(nb), dim3(kBlock), 0, s, k32i, n_host, n_dev,
+                           shift, bits, hist);
     hipLaunchKernelGGL(k_radix_groups, dim3(kSortGroups), dim3(kBlock), 0, s, hist, nb, gsum);
     const bool ident = vals_in == nullptr;
-#define FGS_DS(I, F, K)                                                                                         \
-    hipLaunchKernelGGL((k_radix_downsweep<I, F, K>), dim3(nb), dim3(kBlock), 0, s, keys_in, vals_in, keys_out, \
-                       vals_out, n_host, n_dev, shift, bits, hist, gsum, reinterpret_cast<uint32_t *>(run_ends), nruns)
-    if (ident && filter && write_keys) FGS_DS(true, true, true);
-    else if (!ident && !filter && write_keys) FGS_DS(false, false, true);
-    else if (!ident && !filter && !write_keys) FGS_DS(false, false, false);
-    else if (ident && !filter && write_keys) FGS_DS(true, false, true);
-    else FGS_DS(false, true, true);
+    uint32_t *ends = reinterpret_cast<uint32_t *>(run_ends);
+#define FGS_DS(I, F, K, T)                                                                                          \
+    hipLaunchKernelGGL((k_radix_downsweep<I, F, K, T>), dim3(nb), dim3(kBlock), 0, s, static_cast<const T *>(keys_in), \
+                       vals_in, static_cast<T *>(keys_out), vals_out, n_host, n_dev, shift, bits, hist, gsum, ends,   \
+                       nruns)
+    // 16-bit keys: the tile passes (never filtered, explicit values)
+    if (k16 && write_keys) FGS_DS(false, false, true, uint16_t);
+    else if (k16) FGS_DS(false, false, false, uint16_t);
+    else if (ident && filter && write_keys) FGS_DS(true, true, true, uint32_t);
+    else if (!ident && !filter && write_keys) FGS_DS(false, false, true, uint32_t);
+    else if (!ident && !filter && !write_keys) FGS_DS(false, false, false, uint32_t);
+    else if (ident && !filter && write_keys) FGS_DS(true, false, true, uint32_t);
+    else FGS_DS(false, true, true, uint32_t);
 #undef FGS_DS
 }
 

@@ -312,8 +312,11 @@ bool enqueue_back(int W, int H, const DevOptions &op, uint32_t P, FrameBuffers &
     const uint32_t chunk_cap = (uint32_t)std::min<size_t>(ch.cap, 0xffffffffu);
     const uint32_t pair_cap = (uint32_t)std::min<size_t>(fb.capN, 0xffffffffu);
     // ---- stage 2b: key emission -------------------------------------------------
-    launch_emit(W, H, fb.dv_a, P, &fc->visible, fb.offsets, fb.erec, fb.tk_a, fb.tv_a, pair_cap, s);
-    launch_big_emit(W, fb.rect, fb.erec, ch.chunks, chunk_cap, ch.hits, ch.mask, fb.tk_a, fb.tv_a, pair_cap, fc, s);
+    // tile ids travel as uint16 through emission and sort when they fit
+    const int kb = ntiles <= 65536u ? 2 : 4;
+    launch_emit(W, H, fb.dv_a, P, &fc->visible, fb.offsets, fb.erec, fb.tk_a, kb, fb.tv_a, pair_cap, s);
+    launch_big_emit(W, fb.rect, fb.erec, ch.chunks, chunk_cap, ch.hits, ch.mask, fb.tk_a, kb, fb.tv_a, pair_cap, fc,
+                    s);
     mk.mark(4, s);
     // ---- stage 3: stable LSD sort of the pairs by tile id ---------------------------
     int shifts[4] = {0, 0, 0, 0}, widths[4] = {0, 0, 0, 0};
@@ -321,17 +324,17 @@ bool enqueue_back(int W, int H, const DevOptions &op, uint32_t P, FrameBuffers &
     uint32_t *ki = fb.tk_a, *vi = fb.tv_a, *ko = fb.tk_b, *vo = fb.tv_b;
     // The last pass records where each tile's run starts and ends instead of
     // writing the sorted tile ids (an empty tile keeps start > end).  A
-    // one-tile image has no pass: its range comes from the emitted ids.
+    // one-tile image has no pass: its single range holds every pair.
     if (npass > 0) launch_init_ranges(fb.ranges, ntiles, s);
     for (int p = 0; p < npass; ++p) {
         const bool last_pass = p + 1 == npass;
         launch_radix_pass(ki, vi, ko, vo, pair_cap, &fc->pairs, shifts[p], widths[p], false, !last_pass, ss.rhist,
-                          ss.gsum, s, last_pass ? fb.ranges : nullptr, ntiles);
+                          ss.gsum, s, last_pass ? fb.ranges : nullptr, ntiles, kb);
         std::swap(ki, ko);
         std::swap(vi, vo);
     }
     mk.mark(5, s);
-    if (npass == 0) launch_tile_ranges(ki, pair_cap, &fc->pairs, fb.ranges, ntiles, s);
+    if (npass == 0) launch_single_range(fb.ranges, pair_cap, &fc->pairs, s);
     mk.mark(6, s);
     // ---- stage 4: blend -------------------------------------------------------------
     launch_blend(fb.gs, vi, fb.ranges, W, H, op, rgb, T, last, work, s);
