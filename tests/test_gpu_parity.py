@@ -103,6 +103,23 @@ def test_one_pixel_and_one_tile_images(orc, R, scenes):
         _full_check(orc, R, sc, cam, W, H, opts(), f"{W}x{H}")
 
 
+def test_wide_image_with_32bit_tile_ids(orc, R):
+    """More than 65536 tiles (16384 x 1040 = 66560): tile ids are sorted as
+    uint32 in three passes instead of uint16."""
+    from oracle_helpers import scene_from
+    rng = np.random.default_rng(23)
+    P = 4000
+    means = np.stack([rng.uniform(-30, 30, P), rng.uniform(-2.5, 2.5, P), rng.uniform(5, 7, P)], 1)
+    q = rng.normal(size=(P, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    sc = scene_from(means, rng.normal(-1.5, 0.5, (P, 3)), q, rng.normal(0, 1.5, P), sh_degree=1,
+                    sh=rng.normal(0, 0.3, (12, P)))
+    W, H = 16384, 1040
+    g, o32, _ = _full_check(orc, R, sc, identity_camera(W, H, 1000.0), W, H, opts(), f"{W}x{H}")
+    assert g["stats"]["sort_passes"] == 4 + 3
+    assert g["stats"]["pairs"] > 100_000
+
+
 def test_bbox_binning_same_image_more_pairs(orc, R, scenes):
     sc = scenes.make_scene("small")
     cam = scenes.camera_for("small")
