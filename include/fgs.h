@@ -213,7 +213,8 @@ fgs_status fgs_render_prepared(fgs_context *ctx, const fgs_prepared *prepared, c
  * this one replays each pixel's blend back to front from its saved final
  * transmittance and last contributor, with wavefront-reduced atomics as in
  * the DISTWAR work the paper cites).
- *   frame    a frame saved by fgs_render of this context (not released).
+ *   frame    a frame saved by fgs_render of this context (not released);
+ *            a frame of fgs_render_prepared gives FGS_ERR_NOT_SUPPORTED.
  *   scene    the forward call's scene, same pointers and unchanged values.
  *   cam, opt NULL, or identical to the forward call's (else INVALID_ARGUMENT).
  *   dL_drgb  device, [3][H][W] float, H and W of the frame.
@@ -237,7 +238,8 @@ fgs_status fgs_frame_release(fgs_context *ctx, fgs_frame *frame);
 /* Introspection of a saved frame for tests and tools: copies one field to
  * host memory (synchronising the frame's stream).  Fields and layouts:
  *   FGS_FIELD_GAUSS   [P][12] float: u, v, conic A, B, C, k^2, log2(o),
- *                     r, g, b, depth, o (valid Gaussians only; others 0)
+ *                     r, g, b, depth, o (valid Gaussians only; others are 0
+ *                     for a prepared scene's frame and unspecified otherwise)
  *   FGS_FIELD_RECT    [P][4] int32: tx0, tx1, ty0, ty1 (valid only)
  *   FGS_FIELD_COUNT   [P] uint32 exact tile count (0 for culled Gaussians)
  *   FGS_FIELD_ORDER   [visible] uint32 Gaussian indices in (depth, index) order

@@ -90,13 +90,14 @@ unsigned emit_grid(uint32_t visible);
 // is set and the host renders the frame again with a larger list) and get
 // count 0 and record (rectangle, 0, first chunk).
 // pp: NULL (raw parameters) or the scene's precompute.  With a precompute a
-// cull pass of kCullBlocks workgroups first writes count = 0 for every
-// Gaussian and lists, for each workgroup's contiguous range, the Gaussians
-// that may be visible (in index order, at the start of the range in cand,
-// capacity sc.P; their number in seg_count[workgroup]), and the preprocess
-// runs over those lists only, taken as one list of fc->ncand positions: the
-// depth key of position i goes to dkey[i] and its Gaussian to gmap[i]
-// (without a precompute dkey is indexed by Gaussian and gmap is unused).
+// cull pass of kCullBlocks workgroups first lists, for each workgroup's
+// contiguous range, the Gaussians that may be visible (in index order, at the
+// start of the range in cand, capacity sc.P; their number in
+// seg_count[workgroup]), and the preprocess runs over those lists only, taken
+// as one list of fc->ncand positions: every per-Gaussian output (gs, rect,
+// count, erec, dkey, chunk entries) of position i goes to index i, and the
+// Gaussian of position i to gmap[i].  Without a precompute the outputs are
+// indexed by Gaussian and gmap is unused.
 constexpr int kCullBlocks = 2048;
 void launch_preprocess(const DevScene &sc, const DevPrepared *pp, const DevCamera &cam, const DevOptions &op,
                        int W, int H, GaussState *gs, uint4 *rect, uint32_t *count, uint4 *erec, uint32_t *dkey,

@@ -309,8 +309,7 @@ __device__ __forceinline__ void cull_range(int64_t P, uint32_t b, int64_t *lo, i
 // square box) bounds the half-width of the box, and a 0.1 % + 3 px margin
 // covers rounding.  Everything it drops the exact path would cull too.  Each
 // workgroup owns a contiguous range of Gaussians and lists its candidates in
-// index order at the start of that range (no global atomics); every
-// Gaussian's tile count starts at zero.
+// index order at the start of that range (no global atomics).
 __global__ __launch_bounds__(kBlock) void k_cull(DevScene sc, DevPrepared pp, DevCamera cam, DevOptions op, int W,
                                                  int H, uint32_t *__restrict__ dkey, uint32_t *__restrict__ count,
                                                  uint32_t *__restrict__ cand, uint32_t *__restrict__ seg_count) {
@@ -323,7 +322,6 @@ __global__ __launch_bounds__(kBlock) void k_cull(DevScene sc, DevPrepared pp, De
         const int64_t g = g0 + threadIdx.x;
         bool keep = false;
         if (g < hi) {
-            count[g] = 0u;
             const float4 p4 = pp.pos_o[g];
             const float *R = cam.R;
             const float tx = ((R[0] * p4.x + R[1] * p4.y) + R[2] * p4.z) + cam.t[0];
@@ -459,6 +457,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     if constexpr (kPrep) {
         if (blockIdx.x == 0 && threadIdx.x == 0) fc->ncand = ncand;
     }
+    // outputs of a prepared scene go to the candidate's list position (dense,
+    // contiguous per wavefront), of raw parameters to the Gaussian's index
     int64_t batch = blockIdx.x;  // batch of 256 list positions (prepared) or Gaussians (raw)
     for (;;) {
     int64_t g = sc.P;
@@ -667,7 +667,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             const uint32_t incl = wave_incl_scan(nch, lane);
             if (chunked) {
                 const uint32_t slot = w_nbig + (uint32_t)__popcll(cm & ((1ull << lane) - 1ull));
-                s_bg[wv][slot] = (uint32_t)g;
+                s_bg[wv][slot] = kPrep ? ii : (uint32_t)g;
                 s_bn[wv][slot] = nch;
                 s_bx[wv][slot] = (uint32_t)tx0 | ((uint32_t)tx1 << 16);
                 s_by[wv][slot] = (uint32_t)ty0 | ((uint32_t)ty1 << 16);
@@ -715,27 +715,27 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 
     if (g < sc.P) {
         const uint32_t key = valid ? __float_as_uint(tz) : kInvalidKey;
-        if constexpr (kPrep) {
-            // depth keys of a prepared scene's candidates are dense, at their
-            // list positions, with the Gaussian beside them (gmap)
-            dkey[ii] = key;
-            gmap[ii] = (uint32_t)g;
-        } else {
-            dkey[g] = key;
-        }
-        count[g] = valid ? cnt : 0u;
+        const int64_t oi = kPrep ? (int64_t)ii : g;  // output slot
+        if constexpr (kPrep) gmap[ii] = (uint32_t)g;
+        dkey[oi] = key;
+        count[oi] = valid ? cnt : 0u;
         if (valid) {
             GaussState s;
             s.f0 = make_float4(u, v, A, B);
             s.f1 = make_float4(C, k2, l2o, col[0]);
             s.f2 = make_float4(col[1], col[2], tz, o);
-            gs[g] = s;
-            rect[g] = make_uint4((uint32_t)tx0, (uint32_t)tx1, (uint32_t)ty0, (uint32_t)ty1);
+            gs[oi] = s;
+            rect[oi] = make_uint4((uint32_t)tx0, (uint32_t)tx1, (uint32_t)ty0, (uint32_t)ty1);
             // emission record: rectangle (4 x 16 bits) and hit mask in one
             // 16-byte gather
             if (!chunked)
-                erec[g] = make_uint4((uint32_t)tx0 | ((uint32_t)tx1 << 16), (uint32_t)ty0 | ((uint32_t)ty1 << 16),
-                                     (uint32_t)hm, (uint32_t)(hm >> 32));
+                erec[oi] = make_uint4((uint32_t)tx0 | ((uint32_t)tx1 << 16), (uint32_t)ty0 | ((uint32_t)ty1 << 16),
+                                      (uint32_t)hm, (uint32_t)(hm >> 32));
+        } else if (kPrep) {
+            // a list slot is reused every frame: clear a culled candidate's
+            // state and rectangle
+            gs[oi] = GaussState{};
+            rect[oi] = make_uint4(0u, 0u, 0u, 0u);
         }
     }
     w_vis += (uint32_t)__popcll(__ballot(valid));

@@ -75,6 +75,7 @@ hipError_t ensure_gauss(FrameBuffers &b, size_t P) {
     FGS_GROW(b.dv_b, cap);
     FGS_GROW(b.offsets, cap + 1);
     FGS_GROW(b.seg_count, kCullBlocks);
+    FGS_GROW(b.gmap, cap);
     b.capP = cap;
     return hipSuccess;
 }
@@ -126,7 +127,7 @@ hipError_t ensure_chunks(ChunkList &c, size_t need) {
 
 void free_frame_buffers(FrameBuffers &b) {
     void **ps[] = {(void **)&b.gs, (void **)&b.rect, (void **)&b.count, (void **)&b.erec, (void **)&b.dkey,
-                   (void **)&b.dk_b, (void **)&b.dv_a, (void **)&b.dv_b, (void **)&b.offsets, (void **)&b.seg_count,
+                   (void **)&b.dk_b, (void **)&b.dv_a, (void **)&b.dv_b, (void **)&b.offsets, (void **)&b.seg_count, (void **)&b.gmap,
                    (void **)&b.ranges,
                    (void **)&b.T, (void **)&b.last};
     for (void **p : ps) free_p(*p);
@@ -267,10 +268,10 @@ void enqueue_front(const DevScene &sc, const DevPrepared *pp, const DevCamera &c
     launch_fill_u32(reinterpret_cast<uint32_t *>(fc), 0u, sizeof(FrameCounters) / 4, s);
     mk.mark(0, s);
     // the candidate list of a prepared scene lives in dv_b until the depth sort
-    // (a prepared scene's depth keys are dense over the candidates, with the
-    // Gaussian index of each in fb.offsets, free until the count scan)
+    // (a prepared scene's outputs are dense over the candidate list, with the
+    // Gaussian of each list position in fb.gmap)
     launch_preprocess(sc, pp, cam, op, W, H, fb.gs, fb.rect, fb.count, fb.erec, fb.dkey, fb.dv_b, fb.seg_count,
-                      fb.offsets, ch.chunks, chunk_cap, fc, s);
+                      fb.gmap, ch.chunks, chunk_cap, fc, s);
     // the large rectangles' exact tests touch neither the depth keys nor the
     // sort scratch: they run beside the depth sort
     hipStream_t sb = s;
@@ -285,11 +286,10 @@ void enqueue_front(const DevScene &sc, const DevPrepared *pp, const DevCamera &c
     // depth) key is the same for every pair of a Gaussian) --------------------
     mk.mark(1, s);
     const uint32_t P32 = (uint32_t)sc.P;
-    if (pp)
-        launch_radix_pass(fb.dkey, fb.offsets, fb.dk_b, fb.dv_b, P32, &fc->ncand, 0, 8, true, true, ss.rhist,
-                          ss.gsum, s);
-    else
-        launch_radix_pass(fb.dkey, nullptr, fb.dk_b, fb.dv_b, P32, nullptr, 0, 8, true, true, ss.rhist, ss.gsum, s);
+    // (values: the output slots, i.e. list positions of a prepared scene's
+    // candidates or Gaussian indices)
+    launch_radix_pass(fb.dkey, nullptr, fb.dk_b, fb.dv_b, P32, pp ? &fc->ncand : nullptr, 0, 8, true, true, ss.rhist,
+                      ss.gsum, s);
     launch_radix_pass(fb.dk_b, fb.dv_b, fb.dkey, fb.dv_a, P32, &fc->visible, 8, 8, false, true, ss.rhist, ss.gsum, s);
     launch_radix_pass(fb.dkey, fb.dv_a, fb.dk_b, fb.dv_b, P32, &fc->visible, 16, 8, false, true, ss.rhist, ss.gsum,
                       s);

@@ -25,6 +25,7 @@ struct FrameBuffers {
     uint32_t *dkey = nullptr, *dk_b = nullptr, *dv_a = nullptr, *dv_b = nullptr;
     uint32_t *offsets = nullptr;
     uint32_t *seg_count = nullptr;  // kCullBlocks candidate counts of a prepared scene's cull
+    uint32_t *gmap = nullptr;       // prepared scene: Gaussian of each candidate list position
     // per pair (ping-pong for the LSD passes)
     uint32_t *tk_a = nullptr, *tk_b = nullptr, *tv_a = nullptr, *tv_b = nullptr;
     bool pairs_owned = true;  // false: the pair arrays live in a caller's arena
@@ -34,7 +35,7 @@ struct FrameBuffers {
     uint32_t *last = nullptr;
 
     size_t gauss_bytes() const {
-        return capP * (sizeof(GaussState) + sizeof(uint4) + sizeof(uint32_t) + sizeof(uint4) + 4 * sizeof(uint32_t)) +
+        return capP * (sizeof(GaussState) + sizeof(uint4) + sizeof(uint32_t) + sizeof(uint4) + 5 * sizeof(uint32_t)) +
                (capP + 1) * sizeof(uint32_t) + kCullBlocks * sizeof(uint32_t);
     }
     size_t bytes() const {

@@ -31,6 +31,10 @@ struct fgs_frame {
     fgs_camera cam{};
     fgs_options opt{};
     fgs_stats stats{};
+    // rendered from a prepared scene: per-Gaussian buffers are indexed by
+    // candidate list position (ncand of them; fb.gmap gives the Gaussian)
+    bool dense = false;
+    uint32_t ncand = 0;
 };
 
 struct fgs_prepared {
@@ -296,7 +300,7 @@ fgs_status render_impl(fgs_context *ctx, const fgs_scene *scene, const fgs_prepa
     float *Tdst = saved ? fb.T : out_T;
     uint32_t *Ldst = saved ? fb.last : out_last;
     unsigned long long *work = (ctx->instr & FGS_INSTR_WORK) ? ctx->work_dev : nullptr;
-    uint32_t V = 0, N = 0, big = 0;
+    uint32_t V = 0, N = 0, big = 0, ncand = 0;
     bool tiles_in_a = true;
     size_t spec_cap = 0;  // pair capacity of a second half already enqueued (0: none)
     for (int attempt = 0;; ++attempt) {
@@ -336,6 +340,7 @@ fgs_status render_impl(fgs_context *ctx, const fgs_scene *scene, const fgs_prepa
         V = ctx->fc_host->visible;
         N = ctx->fc_host->pairs;
         big = ctx->fc_host->nchunks;
+        ncand = prep ? ctx->fc_host->ncand : 0;
         break;
     }
     if (plan) {
@@ -399,6 +404,8 @@ fgs_status render_impl(fgs_context *ctx, const fgs_scene *scene, const fgs_prepa
         f->P = P;
         f->visible = V;
         f->pairs = N;
+        f->dense = prep != nullptr;
+        f->ncand = ncand;
         f->tiles_in_a = tiles_in_a;
         f->stream = s;
         f->stats = stt;
@@ -578,6 +585,28 @@ fgs_status fgs_frame_download(fgs_context *ctx, const fgs_frame *f, fgs_field fi
             for (uint32_t i = rg[t].x; i < rg[t].y && i < f->pairs; ++i) dst[i] = (uint32_t)t;
         return FGS_OK;
     }
+    if (f->dense && (field == FGS_FIELD_GAUSS || field == FGS_FIELD_RECT || field == FGS_FIELD_COUNT ||
+                     field == FGS_FIELD_ORDER || field == FGS_FIELD_VALUES)) {
+        // a prepared scene's frame holds per-Gaussian data by candidate list
+        // position: map positions to Gaussian indices
+        std::vector<uint32_t> gm(f->ncand);
+        if (f->ncand) HIP_TRY(ctx, hipMemcpy(gm.data(), b.gmap, f->ncand * sizeof(uint32_t), hipMemcpyDeviceToHost));
+        if (field == FGS_FIELD_ORDER || field == FGS_FIELD_VALUES) {
+            HIP_TRY(ctx, hipMemcpy(host_dst, src, bytes, hipMemcpyDeviceToHost));
+            uint32_t *d = static_cast<uint32_t *>(host_dst);
+            for (size_t i = 0; i < bytes / sizeof(uint32_t); ++i) d[i] = d[i] < f->ncand ? gm[d[i]] : 0xffffffffu;
+            return FGS_OK;
+        }
+        const size_t esz = field == FGS_FIELD_GAUSS ? sizeof(GaussState)
+                                                    : (field == FGS_FIELD_RECT ? sizeof(uint4) : sizeof(uint32_t));
+        std::vector<uint8_t> tmp((size_t)f->ncand * esz);
+        if (f->ncand) HIP_TRY(ctx, hipMemcpy(tmp.data(), src, tmp.size(), hipMemcpyDeviceToHost));
+        uint8_t *d = static_cast<uint8_t *>(host_dst);
+        memset(d, 0, bytes);
+        for (size_t c = 0; c < f->ncand; ++c)
+            if ((size_t)gm[c] * esz + esz <= bytes) memcpy(d + (size_t)gm[c] * esz, tmp.data() + c * esz, esz);
+        return FGS_OK;
+    }
     HIP_TRY(ctx, hipMemcpy(host_dst, src, bytes, hipMemcpyDeviceToHost));
     if (field == FGS_FIELD_RANGES) {
         // an empty tile may hold start > end on the device; report (0, 0)
@@ -641,6 +670,9 @@ fgs_status fgs_render_backward(fgs_context *ctx, const fgs_frame *frame, const f
         return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "camera differs from the forward call's");
     if (opt && memcmp(opt, &frame->opt, sizeof(fgs_options)) != 0)
         return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "options differ from the forward call's");
+    if (frame->dense)
+        return fail(ctx, FGS_ERR_NOT_SUPPORTED,
+                    "the frame was rendered from a prepared scene; render from the parameters for gradients");
     if (!dL_drgb) return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "dL_drgb is NULL");
     if (!grad) return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "grad is NULL");
     const int64_t P = frame->P;
