@@ -200,6 +200,24 @@ def test_prepared_scene_is_bit_identical(orc, R, scenes, case):
             assert np.array_equal(np.asarray(a[k]).view(np.uint32), np.asarray(b[k]).view(np.uint32)), k
 
 
+def test_backward_of_prepared_frame_not_supported(R, scenes):
+    """A prepared scene's frame holds its state by candidate position: the
+    adjoint is for frames rendered from the parameters, and says so."""
+    import torch
+    from paper_2408_07967_amd import binding as B
+    sc = scenes.make_scene("small")
+    cam = scenes.camera_for("small")
+    gsc = _gs(sc)
+    h = R.prepare(gsc, opts())
+    try:
+        out = R.render(gsc, cam, 256, 256, opts(), save=True, prepared=h)
+        with pytest.raises(B.FgsError, match="not supported"):
+            R.backward(out["frame"], gsc, cam, 256, 256, opts(), torch.ones((3, 256, 256), device="cuda"))
+        R.release(out["frame"])
+    finally:
+        R.release_prepared(h)
+
+
 def test_deterministic_repeat(orc, R, scenes):
     sc = scenes.make_scene("medium", P=100_000)
     cam = scenes.camera_for("medium", 2)
