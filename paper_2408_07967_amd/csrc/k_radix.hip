@@ -95,15 +95,24 @@ __global__ __launch_bounds__(kBlock) void k_radix_upsweep(const KeyT *__restrict
     hist[(size_t)blockIdx.x * kRadix + tid] = s_h[0][tid] + s_h[1][tid] + s_h[2][tid] + s_h[3][tid];
 }
 
-// gsum[w][d] = sum of hist[b][d] over the kSortGroup workgroups of group w
-__global__ __launch_bounds__(kBlock) void k_radix_groups(const uint32_t *__restrict__ hist, uint32_t nb,
-                                                         uint32_t *__restrict__ gsum) {
-    const uint32_t b0 = blockIdx.x * kSortGroup;
+// gsum[w][d] = sum of hist[b][d] over the kSortGroup workgroups of group w.
+// One wavefront per (group, 64 digits): every row of the group is loaded at
+// once, so the kernel costs one memory round trip.
+static_assert(kSortBlocks % kSortGroup == 0, "whole groups of histogram rows");
+static_assert(kRadix % kWave == 0, "digits split by wavefront");
+constexpr int kGroupsGrid = kSortGroups * (kRadix / kWave);
+
+__global__ __launch_bounds__(kWave) void k_radix_groups(const uint32_t *__restrict__ hist,
+                                                        uint32_t *__restrict__ gsum) {
+    const uint32_t w = blockIdx.x / (kRadix / kWave);
+    const uint32_t d = (blockIdx.x % (kRadix / kWave)) * kWave + threadIdx.x;
+    uint32_t v[kSortGroup];
+#pragma unroll
+    for (int r = 0; r < kSortGroup; ++r) v[r] = hist[(size_t)(w * kSortGroup + r) * kRadix + d];
     uint32_t s = 0;
-#pragma unroll 8
-    for (int r = 0; r < kSortGroup; ++r)
-        if (b0 + r < nb) s += hist[(size_t)(b0 + r) * kRadix + threadIdx.x];
-    gsum[(size_t)blockIdx.x * kRadix + threadIdx.x] = s;
+#pragma unroll
+    for (int r = 0; r < kSortGroup; ++r) s += v[r];
+    gsum[(size_t)w * kRadix + d] = s;
 }
 
 // (LDS holds four workgroups per CU, so registers are capped at what four
@@ -340,7 +349,7 @@ void launch_radix_pass(const void *keys_in, const uint32_t *vals_in, void *keys_
     else
         hipLaunchKernelGGL((k_radix_upsweep<false, uint32_t>), dim3(nb), dim3(kBlock), 0, s, k32i, n_host, n_dev,
                            shift, bits, hist);
-    hipLaunchKernelGGL(k_radix_groups, dim3(kSortGroups), dim3(kBlock), 0, s, hist, nb, gsum);
+    hipLaunchKernelGGL(k_radix_groups, dim3(kGroupsGrid), dim3(kWave), 0, s, hist, gsum);
     const bool ident = vals_in == nullptr;
     uint32_t *ends = reinterpret_cast<uint32_t *>(run_ends);
 #define FGS_DS(I, F, K, T)                                                                                          \
