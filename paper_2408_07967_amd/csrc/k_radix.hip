@@ -24,6 +24,9 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kWaves = kBlock / kWave;
+// values of the 16-bit-key (tile) passes are written in aligned runs of 8
+// (32 bytes)
+constexpr int kCarryVals = 0;
 
 __device__ __forceinline__ uint32_t count_of(uint32_t n_host, const uint32_t *n_dev) {
     if (!n_dev) return n_host;
@@ -117,7 +120,13 @@ __global__ __launch_bounds__(kWave) void k_radix_groups(const uint32_t *__restri
 
 // (LDS holds four workgroups per CU, so registers are capped at what four
 // waves per SIMD allow.)
-template <bool kIdentityVals, bool kFilter, bool kWriteKeys, class KeyT>
+//
+// kCarry > 0: values are written in whole aligned runs of kCarry elements
+// (one 32-byte memory sector for kCarry = 8).  The elements of a digit's last,
+// incomplete run are held in LDS until a later tile of the workgroup completes
+// the run (or the workgroup ends), so that no sector is written in two pieces
+// far apart in time (which costs a second sector write).
+template <bool kIdentityVals, bool kFilter, bool kWriteKeys, class KeyT, int kCarry>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_radix_downsweep(const KeyT *__restrict__ keys_in,
                                                             const uint32_t *__restrict__ vals_in,
                                                             KeyT *__restrict__ keys_out,
@@ -126,13 +135,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                                                             const uint32_t *__restrict__ hist,
                                                             const uint32_t *__restrict__ gsum,
                                                             uint32_t *__restrict__ run_end, uint32_t nruns) {
-    __shared__ uint32_t s_keys[kSortTile];
+    // (per-wave and per-tile digit counts are at most kSortTile: 16 bits)
+    __shared__ KeyT s_keys[kSortTile];
     __shared__ uint32_t s_vals[kSortTile];
-    __shared__ uint32_t s_wave[kWaves][kRadix];
+    __shared__ uint16_t s_wave[kWaves][kRadix];
     __shared__ uint32_t s_off[kRadix];
-    __shared__ uint32_t s_excl[kRadix];
+    __shared__ uint16_t s_excl[kRadix + 1];
     __shared__ uint32_t s_tmp[kWaves];
     __shared__ uint32_t s_nv;
+    // carried values: digit d's held elements sit at slot (position % kCarry)
+    // of s_car[d]; s_cnt[d] of them end at position s_off[d]
+    static_assert(kCarry == 0 || (kCarry & (kCarry - 1)) == 0, "power-of-two run length");
+    __shared__ uint32_t s_car[kCarry ? kRadix * kCarry : 1];
+    __shared__ uint8_t s_cnt[kCarry ? kRadix : 1];
 
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const uint32_t n = count_of(n_host, n_dev);
@@ -165,6 +180,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         uint32_t all = 0;
         const uint32_t dbase = block_exclusive_scan(total, s_tmp, &all);
         s_off[tid] = dbase + before;
+        if (kCarry) s_cnt[tid] = 0;
     }
     if (lo >= hi) return;  // uniform: no tile for this workgroup
 
@@ -196,12 +212,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             const uint32_t k = key[i];
             const bool ok = in && (!kFilter || k != kInvalidKey);
             const uint32_t d = (k >> shift) & dmask;
-            // lanes of this step with the same digit (stable rank = lower lanes)
+            // lanes of this step with the same digit (stable rank = lower
+            // lanes): per digit bit, keep the lanes whose bit agrees.  All
+            // kRadixBits bits are matched (a narrower digit has zero high bits
+            // in every lane), so the loop unrolls into straight-line code.
             uint64_t peers = __ballot(ok);
-            for (int bb = 0; bb < bits; ++bb) {
-                const bool bit = (d >> bb) & 1u;
-                const uint64_t m = __ballot(bit);
-                peers &= bit ? m : ~m;
+#pragma unroll
+            for (int bb = 0; bb < kRadixBits; ++bb) {
+                const uint32_t t = (uint32_t)((int32_t)(d << (31 - bb)) >> 31);  // bit bb of d, 0 or ~0
+                const uint64_t m = __ballot(t != 0u);
+                peers &= ~(m ^ (((uint64_t)t << 32) | t));
             }
             const uint32_t before = (uint32_t)__popcll(peers & lt);
             const uint32_t cnt = (uint32_t)__popcll(peers);
@@ -219,28 +239,53 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         s_wave[3][tid] = c0 + c1 + c2;
         const uint32_t dsum = c0 + c1 + c2 + c3;
         uint32_t nvalid = 0;
-        s_excl[tid] = block_exclusive_scan(dsum, s_tmp, &nvalid);
-        if (tid == 0) s_nv = nvalid;
+        s_excl[tid] = (uint16_t)block_exclusive_scan(dsum, s_tmp, &nvalid);
+        if (tid == 0) {
+            s_nv = nvalid;
+            s_excl[kRadix] = (uint16_t)nvalid;
+        }
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < kSortItems; ++i) {
             if (rank[i] != 0xffffffffu) {
                 const uint32_t d = (key[i] >> shift) & dmask;
                 const uint32_t lp = s_excl[d] + s_wave[wave][d] + rank[i];
-                s_keys[lp] = key[i];
+                s_keys[lp] = (KeyT)key[i];
                 s_vals[lp] = val[i];
             }
         }
         if (t0 + kSortTile < hi) load_tile(t0 + kSortTile);
         __syncthreads();
         const uint32_t nv = s_nv;
+        if (kCarry) {
+            // held values of runs that this tile completes
+            for (int i = tid; i < kRadix * kCarry; i += kBlock) {
+                const int d = i / kCarry, slot = i % kCarry;
+                const uint32_t off = s_off[d], c = s_cnt[d], r = off % kCarry;
+                const uint32_t nd = (uint32_t)s_excl[d + 1] - s_excl[d];
+                if ((uint32_t)slot < r && (uint32_t)slot + c >= r && (off + nd) / kCarry != off / kCarry) {
+                    const uint32_t p = off - r + (uint32_t)slot;
+                    if (p < n) vals_out[p] = s_car[i];
+                }
+            }
+            __syncthreads();
+        }
         for (uint32_t j = tid; j < nv; j += kBlock) {
             const uint32_t k = s_keys[j];
             const uint32_t d = (k >> shift) & dmask;
-            const uint32_t gpos = s_off[d] + (j - s_excl[d]);
+            const uint32_t off = s_off[d], first = s_excl[d];
+            const uint32_t gpos = off + (j - first);
             if (gpos < n) {  // never leave the output (n bounds the scattered count)
                 if (kWriteKeys) keys_out[gpos] = (KeyT)k;
-                vals_out[gpos] = s_vals[j];
+                bool direct = true;
+                if (kCarry) {
+                    // positions from the last run boundary before the digit's
+                    // new end on are held for a later tile
+                    const uint32_t fe = (off + ((uint32_t)s_excl[d + 1] - first)) & ~(uint32_t)(kCarry - 1);
+                    direct = gpos < fe;
+                    if (!direct) s_car[d * kCarry + gpos % kCarry] = s_vals[j];
+                }
+                if (direct) vals_out[gpos] = s_vals[j];
                 // last pass of a sort by the whole key: the keys of one
                 // digit run of this tile are in key order, so the first and
                 // last element of each key's stretch may start and end its run
@@ -251,7 +296,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             }
         }
         __syncthreads();
+        if (kCarry) {
+            const uint32_t off = s_off[tid], ne = off + dsum, fe = ne & ~(uint32_t)(kCarry - 1);
+            const uint32_t held = off - s_cnt[tid];
+            s_cnt[tid] = (uint8_t)(ne - (fe > held ? fe : held));
+        }
         s_off[tid] += dsum;
+    }
+    if (kCarry) {
+        // the workgroup's last, incomplete runs
+        __syncthreads();
+        for (int i = tid; i < kRadix * kCarry; i += kBlock) {
+            const int d = i / kCarry, slot = i % kCarry;
+            const uint32_t off = s_off[d], c = s_cnt[d], r = off % kCarry;
+            if ((uint32_t)slot < r && (uint32_t)slot + c >= r) {
+                const uint32_t p = off - r + (uint32_t)slot;
+                if (p < n) vals_out[p] = s_car[i];
+            }
+        }
     }
 }
 
@@ -353,7 +415,8 @@ void launch_radix_pass(const void *keys_in, const uint32_t *vals_in, void *keys_
     const bool ident = vals_in == nullptr;
     uint32_t *ends = reinterpret_cast<uint32_t *>(run_ends);
 #define FGS_DS(I, F, K, T)                                                                                          \
-    hipLaunchKernelGGL((k_radix_downsweep<I, F, K, T>), dim3(nb), dim3(kBlock), 0, s, static_cast<const T *>(keys_in), \
+    hipLaunchKernelGGL((k_radix_downsweep<I, F, K, T, sizeof(T) == 2 ? kCarryVals : 0>), dim3(nb), dim3(kBlock), 0, s, \
+                       static_cast<const T *>(keys_in),                                                              \
                        vals_in, static_cast<T *>(keys_out), vals_out, n_host, n_dev, shift, bits, hist, gsum, ends,   \
                        nruns)
     // 16-bit keys: the tile passes (never filtered, explicit values)
