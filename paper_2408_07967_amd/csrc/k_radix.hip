@@ -141,6 +141,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     __shared__ uint16_t s_wave[kWaves][kRadix];
     __shared__ uint32_t s_off[kRadix];
     __shared__ uint16_t s_excl[kRadix + 1];
+    __shared__ uint32_t s_gbase[kRadix];  // output position of tile element j of digit d: s_gbase[d] + j
     __shared__ uint32_t s_tmp[kWaves];
     __shared__ uint32_t s_nv;
     // carried values: digit d's held elements sit at slot (position % kCarry)
@@ -185,7 +186,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     if (lo >= hi) return;  // uniform: no tile for this workgroup
 
     const uint32_t dmask = (1u << bits) - 1u;
-    const uint64_t lt = (1ull << lane) - 1ull;
     // A tile's loads are all issued before any use, and the next tile's are
     // issued as soon as the current one sits in LDS, so that they are in
     // flight while the current tile is written out.
@@ -213,18 +213,25 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             const bool ok = in && (!kFilter || k != kInvalidKey);
             const uint32_t d = (k >> shift) & dmask;
             // lanes of this step with the same digit (stable rank = lower
-            // lanes): per digit bit, keep the lanes whose bit agrees.  All
-            // kRadixBits bits are matched (a narrower digit has zero high bits
-            // in every lane), so the loop unrolls into straight-line code.
-            uint64_t peers = __ballot(ok);
+            // lanes): a lane differs from this one where some digit bit
+            // disagrees, i.e. where ballot(bit) xor (own bit, widened) is
+            // set.  All kRadixBits bits are matched (a narrower digit has zero
+            // high bits in every lane).  Per bit: one bitfield extract, one
+            // compare and one three-input logic op per half mask
+            // (bitop3 table 0xf6 = src0 | (src1 ^ src2)).
+            uint32_t diff_lo = 0, diff_hi = 0;
 #pragma unroll
             for (int bb = 0; bb < kRadixBits; ++bb) {
-                const uint32_t t = (uint32_t)((int32_t)(d << (31 - bb)) >> 31);  // bit bb of d, 0 or ~0
+                const uint32_t t = (uint32_t)__builtin_amdgcn_sbfe((int)d, bb, 1);  // 0 or ~0
                 const uint64_t m = __ballot(t != 0u);
-                peers &= ~(m ^ (((uint64_t)t << 32) | t));
+                diff_lo = __builtin_amdgcn_bitop3_b32(diff_lo, (uint32_t)m, t, 0xf6);
+                diff_hi = __builtin_amdgcn_bitop3_b32(diff_hi, (uint32_t)(m >> 32), t, 0xf6);
             }
-            const uint32_t before = (uint32_t)__popcll(peers & lt);
-            const uint32_t cnt = (uint32_t)__popcll(peers);
+            const uint64_t okm = __ballot(ok);
+            const uint32_t peers_lo = (uint32_t)okm & ~diff_lo, peers_hi = (uint32_t)(okm >> 32) & ~diff_hi;
+            // set bits of peers below this lane
+            const uint32_t before = __builtin_amdgcn_mbcnt_hi(peers_hi, __builtin_amdgcn_mbcnt_lo(peers_lo, 0u));
+            const uint32_t cnt = (uint32_t)__popc(peers_lo) + (uint32_t)__popc(peers_hi);
             uint32_t prev = 0;
             if (ok) prev = s_wave[wave][d];
             if (ok && before == 0) s_wave[wave][d] = prev + cnt;
@@ -239,7 +246,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         s_wave[3][tid] = c0 + c1 + c2;
         const uint32_t dsum = c0 + c1 + c2 + c3;
         uint32_t nvalid = 0;
-        s_excl[tid] = (uint16_t)block_exclusive_scan(dsum, s_tmp, &nvalid);
+        const uint32_t excl = block_exclusive_scan(dsum, s_tmp, &nvalid);
+        s_excl[tid] = (uint16_t)excl;
+        s_gbase[tid] = s_off[tid] - excl;
         if (tid == 0) {
             s_nv = nvalid;
             s_excl[kRadix] = (uint16_t)nvalid;
@@ -273,15 +282,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         for (uint32_t j = tid; j < nv; j += kBlock) {
             const uint32_t k = s_keys[j];
             const uint32_t d = (k >> shift) & dmask;
-            const uint32_t off = s_off[d], first = s_excl[d];
-            const uint32_t gpos = off + (j - first);
+            const uint32_t gpos = s_gbase[d] + j;
             if (gpos < n) {  // never leave the output (n bounds the scattered count)
                 if (kWriteKeys) keys_out[gpos] = (KeyT)k;
                 bool direct = true;
                 if (kCarry) {
                     // positions from the last run boundary before the digit's
                     // new end on are held for a later tile
-                    const uint32_t fe = (off + ((uint32_t)s_excl[d + 1] - first)) & ~(uint32_t)(kCarry - 1);
+                    const uint32_t fe = (s_off[d] + ((uint32_t)s_excl[d + 1] - s_excl[d])) & ~(uint32_t)(kCarry - 1);
                     direct = gpos < fe;
                     if (!direct) s_car[d * kCarry + gpos % kCarry] = s_vals[j];
                 }
