@@ -24,9 +24,6 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kWaves = kBlock / kWave;
-// values of the 16-bit-key (tile) passes are written in aligned runs of 8
-// (32 bytes)
-constexpr int kCarryVals = 0;
 
 __device__ __forceinline__ uint32_t count_of(uint32_t n_host, const uint32_t *n_dev) {
     if (!n_dev) return n_host;
@@ -120,13 +117,7 @@ __global__ __launch_bounds__(kWave) void k_radix_groups(const uint32_t *__restri
 
 // (LDS holds four workgroups per CU, so registers are capped at what four
 // waves per SIMD allow.)
-//
-// kCarry > 0: values are written in whole aligned runs of kCarry elements
-// (one 32-byte memory sector for kCarry = 8).  The elements of a digit's last,
-// incomplete run are held in LDS until a later tile of the workgroup completes
-// the run (or the workgroup ends), so that no sector is written in two pieces
-// far apart in time (which costs a second sector write).
-template <bool kIdentityVals, bool kFilter, bool kWriteKeys, class KeyT, int kCarry>
+template <bool kIdentityVals, bool kFilter, bool kWriteKeys, class KeyT>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_radix_downsweep(const KeyT *__restrict__ keys_in,
                                                             const uint32_t *__restrict__ vals_in,
                                                             KeyT *__restrict__ keys_out,
@@ -144,11 +135,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     __shared__ uint32_t s_gbase[kRadix];  // output position of tile element j of digit d: s_gbase[d] + j
     __shared__ uint32_t s_tmp[kWaves];
     __shared__ uint32_t s_nv;
-    // carried values: digit d's held elements sit at slot (position % kCarry)
-    // of s_car[d]; s_cnt[d] of them end at position s_off[d]
-    static_assert(kCarry == 0 || (kCarry & (kCarry - 1)) == 0, "power-of-two run length");
-    __shared__ uint32_t s_car[kCarry ? kRadix * kCarry : 1];
-    __shared__ uint8_t s_cnt[kCarry ? kRadix : 1];
 
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const uint32_t n = count_of(n_host, n_dev);
@@ -181,7 +167,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         uint32_t all = 0;
         const uint32_t dbase = block_exclusive_scan(total, s_tmp, &all);
         s_off[tid] = dbase + before;
-        if (kCarry) s_cnt[tid] = 0;
     }
     if (lo >= hi) return;  // uniform: no tile for this workgroup
 
@@ -266,34 +251,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         if (t0 + kSortTile < hi) load_tile(t0 + kSortTile);
         __syncthreads();
         const uint32_t nv = s_nv;
-        if (kCarry) {
-            // held values of runs that this tile completes
-            for (int i = tid; i < kRadix * kCarry; i += kBlock) {
-                const int d = i / kCarry, slot = i % kCarry;
-                const uint32_t off = s_off[d], c = s_cnt[d], r = off % kCarry;
-                const uint32_t nd = (uint32_t)s_excl[d + 1] - s_excl[d];
-                if ((uint32_t)slot < r && (uint32_t)slot + c >= r && (off + nd) / kCarry != off / kCarry) {
-                    const uint32_t p = off - r + (uint32_t)slot;
-                    if (p < n) vals_out[p] = s_car[i];
-                }
-            }
-            __syncthreads();
-        }
         for (uint32_t j = tid; j < nv; j += kBlock) {
             const uint32_t k = s_keys[j];
             const uint32_t d = (k >> shift) & dmask;
             const uint32_t gpos = s_gbase[d] + j;
             if (gpos < n) {  // never leave the output (n bounds the scattered count)
                 if (kWriteKeys) keys_out[gpos] = (KeyT)k;
-                bool direct = true;
-                if (kCarry) {
-                    // positions from the last run boundary before the digit's
-                    // new end on are held for a later tile
-                    const uint32_t fe = (s_off[d] + ((uint32_t)s_excl[d + 1] - s_excl[d])) & ~(uint32_t)(kCarry - 1);
-                    direct = gpos < fe;
-                    if (!direct) s_car[d * kCarry + gpos % kCarry] = s_vals[j];
-                }
-                if (direct) vals_out[gpos] = s_vals[j];
+                vals_out[gpos] = s_vals[j];
                 // last pass of a sort by the whole key: the keys of one
                 // digit run of this tile are in key order, so the first and
                 // last element of each key's stretch may start and end its run
@@ -304,24 +268,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             }
         }
         __syncthreads();
-        if (kCarry) {
-            const uint32_t off = s_off[tid], ne = off + dsum, fe = ne & ~(uint32_t)(kCarry - 1);
-            const uint32_t held = off - s_cnt[tid];
-            s_cnt[tid] = (uint8_t)(ne - (fe > held ? fe : held));
-        }
         s_off[tid] += dsum;
-    }
-    if (kCarry) {
-        // the workgroup's last, incomplete runs
-        __syncthreads();
-        for (int i = tid; i < kRadix * kCarry; i += kBlock) {
-            const int d = i / kCarry, slot = i % kCarry;
-            const uint32_t off = s_off[d], c = s_cnt[d], r = off % kCarry;
-            if ((uint32_t)slot < r && (uint32_t)slot + c >= r) {
-                const uint32_t p = off - r + (uint32_t)slot;
-                if (p < n) vals_out[p] = s_car[i];
-            }
-        }
     }
 }
 
@@ -423,8 +370,7 @@ void launch_radix_pass(const void *keys_in, const uint32_t *vals_in, void *keys_
     const bool ident = vals_in == nullptr;
     uint32_t *ends = reinterpret_cast<uint32_t *>(run_ends);
 #define FGS_DS(I, F, K, T)                                                                                          \
-    hipLaunchKernelGGL((k_radix_downsweep<I, F, K, T, sizeof(T) == 2 ? kCarryVals : 0>), dim3(nb), dim3(kBlock), 0, s, \
-                       static_cast<const T *>(keys_in),                                                              \
+    hipLaunchKernelGGL((k_radix_downsweep<I, F, K, T>), dim3(nb), dim3(kBlock), 0, s, static_cast<const T *>(keys_in), \
                        vals_in, static_cast<T *>(keys_out), vals_out, n_host, n_dev, shift, bits, hist, gsum, ends,   \
                        nruns)
     // 16-bit keys: the tile passes (never filtered, explicit values)
