@@ -431,6 +431,7 @@ def main():
                            raw_params_frames_per_s=round(raw_fps, 3), prepare_ms=round(prep_ms, 2),
                            visible=int(stats["visible"]), pairs=int(stats["pairs"]),
                            big_rect_chunks=int(stats["big_chunks"]),
+                           candidates=int(stats["candidates"]),
                            pairs_per_s=round(stats["pairs"] * fps, 1), stage_ms=stage_ms,
                            single_frame_ms=frame_ms),
                roofline=roof, cpu_baseline=cpu, parity=parity, serving=serving, differentiation=differentiation)

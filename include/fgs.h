@@ -109,6 +109,8 @@ typedef struct {
     int32_t sort_passes;
     int32_t big_chunks; /* 256-tile chunks of the rectangles of more than 64
                            tiles, tested by workgroups across the GPU        */
+    int64_t candidates; /* Gaussians preprocessed: the cull's candidates of a
+                           prepared scene, every Gaussian otherwise          */
 } fgs_stats;
 
 /* ---- context --------------------------------------------------------- */

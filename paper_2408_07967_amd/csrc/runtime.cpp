@@ -360,6 +360,7 @@ fgs_status render_impl(fgs_context *ctx, const fgs_scene *scene, const fgs_prepa
             stt.tiles_x = tiles_x;
             stt.tiles_y = tiles_y;
             stt.big_chunks = (int32_t)big;
+            stt.candidates = prep ? (int64_t)ncand : (int64_t)P;
             *stats = stt;
         }
         return FGS_OK;
@@ -389,6 +390,7 @@ fgs_status render_impl(fgs_context *ctx, const fgs_scene *scene, const fgs_prepa
     stt.tiles_x = tiles_x;
     stt.tiles_y = tiles_y;
     stt.big_chunks = (int32_t)big;
+    stt.candidates = prep ? (int64_t)ncand : (int64_t)P;
     {
         int b = 0;
         while ((1ull << b) < (uint64_t)ntiles) ++b;

@@ -108,7 +108,8 @@ class Renderer:
         self.ctx.check(status)
         return dict(rgb=rgb, T=T, last=last, frame=fr if save else None,
                     stats=dict(visible=st.visible, pairs=st.pairs, tiles_x=st.tiles_x, tiles_y=st.tiles_y,
-                               sort_passes=st.sort_passes, big_chunks=st.big_chunks))
+                               sort_passes=st.sort_passes, big_chunks=st.big_chunks,
+                               candidates=st.candidates))
 
     def plan(self, scene, cam, W, H, opts=None):
         """Pair count and device bytes of one frame, without rendering it:

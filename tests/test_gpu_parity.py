@@ -191,6 +191,10 @@ def test_prepared_scene_is_bit_identical(orc, R, scenes, case):
         b = gpu_frame(R, gsc, cam, W, H, o, prepared=h)
     finally:
         R.release_prepared(h)
+    # the prepared scene preprocesses only the cull's candidates: never fewer
+    # than the visible Gaussians, never more than the scene holds
+    ca, cb = a["stats"].pop("candidates"), b["stats"].pop("candidates")
+    assert ca == sc.P and a["stats"]["visible"] <= cb <= sc.P
     assert a["stats"] == b["stats"]
     for k in ("rgb", "T", "last", "gauss", "rect", "count", "order", "tiles", "values", "ranges"):
         if k in ("gauss", "rect"):
