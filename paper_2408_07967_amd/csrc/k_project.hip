@@ -872,6 +872,11 @@ __global__ __launch_bounds__(kBlock) void k_big_count(int W, int H, int binning,
 
 // Pairs of the chunked Gaussians: each chunk (one wavefront) writes the hits
 // recorded by k_big_count after those of the Gaussian's earlier chunks.
+// A wavefront walks its chunks one ahead: while it writes a chunk's pairs, the
+// next chunk's data is already in flight in a single vector load (one dword
+// per lane: the hit mask, the chunk's hit count, the rectangle, the output
+// base and the hit counts of up to 50 earlier chunks of the Gaussian), and
+// the chunk entry after that in a scalar load.
 template <class KeyT>
 __global__ __launch_bounds__(kBlock) void k_big_emit(int W, const uint4 *__restrict__ rect,
                                                      const uint4 *__restrict__ erec, const uint2 *__restrict__ chunks,
@@ -880,41 +885,54 @@ __global__ __launch_bounds__(kBlock) void k_big_emit(int W, const uint4 *__restr
                                                      KeyT *__restrict__ tile_keys, uint32_t *__restrict__ values,
                                                      uint32_t cap, const FrameCounters *fc) {
     constexpr int kPer = kChunkTiles / kWave;
+    constexpr int kMaskWords = kChunkTiles / 32;
+    // lanes of the look-ahead load
+    constexpr int kLaneHits = kMaskWords, kLaneRect = kLaneHits + 1, kLaneBase = kLaneRect + 4,
+                  kLanePre = kLaneBase + 1;
     const int lane = threadIdx.x & (kWave - 1);
     const int tiles_x = (W + kTile - 1) / kTile;
     const uint64_t lt = (1ull << lane) - 1ull;
     const uint32_t n = fc->nchunks < chunk_cap ? fc->nchunks : chunk_cap;
     const uint32_t nwaves = gridDim.x * (kBlock / kWave);
-    uint32_t ch = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-    uint2 e = ch < n ? chunks[ch] : make_uint2(kNoChunk, 0u);
-    for (; ch < n; ch += nwaves) {
-        const uint32_t nxt = ch + nwaves;
-        const uint2 e_next = nxt < n ? chunks[nxt] : make_uint2(kNoChunk, 0u);
-        const uint32_t hits = e.x == kNoChunk ? 0u : chunk_hits[ch];
-        if (hits == 0) {
-            e = e_next;
-            continue;
-        }
-        const uint32_t g = e.x, first = e.y, c = ch - first;
-        const uint4 rc = rect[g];
-        const uint32_t base = erec[g].z;
+    auto entry = [&](uint32_t c) { return c < n ? chunks[c] : make_uint2(kNoChunk, 0u); };
+    auto load_data = [&](uint32_t c, uint2 ec) -> uint32_t {
+        if (ec.x == kNoChunk) return 0u;  // uniform
+        const uint32_t g = ec.x, first = ec.y;
+        const uint32_t k = first + (uint32_t)(lane - kLanePre);  // an earlier chunk (lanes from kLanePre on)
+        const uint32_t *src = chunk_hits + k;
+        const bool use = lane < kLanePre || k < c;
+        src = lane == kLaneBase ? reinterpret_cast<const uint32_t *>(erec + g) + 2 : src;
+        src = lane < kLaneBase ? reinterpret_cast<const uint32_t *>(rect + g) + (lane - kLaneRect) : src;
+        src = lane == kLaneHits ? chunk_hits + c : src;
+        src = lane < kMaskWords ? chunk_mask + (size_t)c * kMaskWords + lane : src;
+        return use ? *src : 0u;
+    };
+    auto emit = [&](uint32_t c, uint2 ec, uint32_t v) {
+        if (ec.x == kNoChunk) return;
+        const uint32_t hits = bcast(v, kLaneHits);
+        if (hits == 0) return;
+        const uint32_t g = ec.x, first = ec.y;
+        const uint4 rc = make_uint4(bcast(v, kLaneRect), bcast(v, kLaneRect + 1), bcast(v, kLaneRect + 2),
+                                    bcast(v, kLaneRect + 3));
+        const uint32_t base = bcast(v, kLaneBase);
+        // hits of this Gaussian's earlier chunks (past the first 50: loaded here)
+        uint32_t p = lane >= kLanePre ? v : 0u;
+        for (uint32_t k = first + (uint32_t)(kWave - kLanePre) + (uint32_t)lane; k < c; k += kWave)
+            p += chunk_hits[k];
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) p += __shfl_xor(p, d, kWave);
         uint64_t b[kPer];
 #pragma unroll
         for (int j = 0; j < kPer; ++j)
-            b[j] = (uint64_t)chunk_mask[(size_t)ch * (kChunkTiles / 32) + 2 * j] |
-                   ((uint64_t)chunk_mask[(size_t)ch * (kChunkTiles / 32) + 2 * j + 1] << 32);
-        // hits of this Gaussian's earlier chunks
-        uint32_t p = 0;
-        for (uint32_t k = first + (uint32_t)lane; k < ch; k += kWave) p += chunk_hits[k];
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) p += __shfl_xor(p, d, kWave);
+            b[j] = (uint64_t)bcast(v, 2 * j) | ((uint64_t)bcast(v, 2 * j + 1) << 32);
         const int ntx = (int)rc.y - (int)rc.x + 1;
         const float rcpn = __builtin_amdgcn_rcpf((float)ntx);
+        const uint32_t cc = c - first;
         uint32_t before = base + p;
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
             if ((b[j] >> lane) & 1ull) {
-                const int idx = (int)c * kChunkTiles + j * kWave + lane;
+                const int idx = (int)cc * kChunkTiles + j * kWave + lane;
                 int ry, rx;
                 row_col(idx, ntx, rcpn, ry, rx);
                 const uint32_t tile = (uint32_t)(((int)rc.z + ry) * tiles_x + ((int)rc.x + rx));
@@ -926,7 +944,18 @@ __global__ __launch_bounds__(kBlock) void k_big_emit(int W, const uint4 *__restr
             }
             before += (uint32_t)__popcll(b[j]);
         }
-        e = e_next;
+    };
+    uint32_t ch = (uint32_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave));
+    uint2 e0 = entry(ch), e1 = entry(ch + nwaves);
+    uint32_t d0 = load_data(ch, e0);
+    for (; ch < n; ch += nwaves) {
+        const uint32_t c1 = ch + nwaves;
+        const uint32_t d1 = load_data(c1, e1);
+        const uint2 e2 = entry(c1 + nwaves);
+        emit(ch, e0, d0);
+        e0 = e1;
+        e1 = e2;
+        d0 = d1;
     }
 }
 
