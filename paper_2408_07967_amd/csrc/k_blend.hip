@@ -47,7 +47,9 @@ struct Step {
 __device__ __forceinline__ Step step(const Pixel &p, float e, float thr, float amax, float tstop) {
     Step st;
     st.in = e >= thr;
-    st.a = st.in ? fminf(__builtin_amdgcn_exp2f(e), amax) : 0.0f;
+    // min(2^E, amax) as a clamp to [0, amax] (2^E >= 0): one v_med3_f32, with
+    // no per-iteration canonicalisation of amax that a minimum would bring
+    st.a = st.in ? __builtin_amdgcn_fmed3f(__builtin_amdgcn_exp2f(e), 0.0f, amax) : 0.0f;
     st.Tn = fmaf(-st.a, p.T, p.T);
     st.stop = st.Tn < tstop;
     return st;
