@@ -336,12 +336,47 @@ __global__ __launch_bounds__(kBlock) void k_scan_downsweep(const uint32_t *__res
         run = tot_pre;
         if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *pairs = tot_all;
     }
-    for (uint32_t c0 = lo; c0 < hi; c0 += kBlock) {
-        const uint32_t i = c0 + threadIdx.x;
-        const uint32_t c = i < hi ? cs[i] : 0u;
+    // one 4096-entry tile per step: every thread scans its own 16
+    // consecutive entries (four 16-byte loads and stores where the tile is
+    // whole), then the threads' totals are scanned across the workgroup
+    constexpr int kRun = kSortTile / kBlock;
+    static_assert(kRun % 4 == 0, "whole 16-byte groups per thread");
+    for (uint32_t c0 = lo; c0 < hi; c0 += kSortTile) {
+        const uint32_t b = c0 + threadIdx.x * (uint32_t)kRun;
+        uint32_t v[kRun];
+        const bool whole = b + kRun <= hi;
+        if (whole) {
+#pragma unroll
+            for (int q = 0; q < kRun / 4; ++q) {
+                const uint4 x = *reinterpret_cast<const uint4 *>(cs + b + 4 * q);
+                v[4 * q] = x.x;
+                v[4 * q + 1] = x.y;
+                v[4 * q + 2] = x.z;
+                v[4 * q + 3] = x.w;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kRun; ++k) v[k] = b + k < hi ? cs[b + k] : 0u;
+        }
+        uint32_t own = 0;
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) {
+            const uint32_t x = v[k];
+            v[k] = own;  // exclusive within the thread's run
+            own += x;
+        }
         uint32_t tot = 0;
-        const uint32_t ex = block_exclusive_scan(c, s_tmp, &tot);
-        if (i < hi) offsets[i] = run + ex;
+        const uint32_t ex = run + block_exclusive_scan(own, s_tmp, &tot);
+        if (whole) {
+#pragma unroll
+            for (int q = 0; q < kRun / 4; ++q)
+                *reinterpret_cast<uint4 *>(offsets + b + 4 * q) =
+                    make_uint4(ex + v[4 * q], ex + v[4 * q + 1], ex + v[4 * q + 2], ex + v[4 * q + 3]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < kRun; ++k)
+                if (b + k < hi) offsets[b + k] = ex + v[k];
+        }
         run += tot;
     }
     if (hi == n && lo < hi && threadIdx.x == 0) offsets[n] = run;
