@@ -77,18 +77,32 @@ __global__ __launch_bounds__(kBlock) void k_radix_upsweep(const KeyT *__restrict
     uint32_t lo, hi;
     block_range(n, blockIdx.x, gridDim.x, &lo, &hi);
     const uint32_t dmask = (1u << bits) - 1u;
-    // kSortItems independent loads in flight per thread before any use
+    // Each thread counts kSortItems consecutive keys of a tile (the histogram
+    // ignores their order), read with 16-byte loads where the tile is whole:
+    // all loads in flight before any use.
+    constexpr int kPerVec = 16 / (int)sizeof(KeyT);
+    static_assert(kSortItems % kPerVec == 0, "whole 16-byte groups per thread");
     for (uint32_t c0 = lo; c0 < hi; c0 += kSortTile) {
+        const uint32_t b = c0 + (uint32_t)tid * kSortItems;
         uint32_t k[kSortItems];
+        if (b + kSortItems <= hi) {
+            uint4 q[kSortItems / kPerVec];
 #pragma unroll
-        for (int i = 0; i < kSortItems; ++i) {
-            const uint32_t idx = c0 + (uint32_t)(i * kBlock + tid);
-            k[i] = idx < hi ? (uint32_t)keys[idx] : kInvalidKey;
+            for (int j = 0; j < kSortItems / kPerVec; ++j) q[j] = reinterpret_cast<const uint4 *>(keys + b)[j];
+#pragma unroll
+            for (int j = 0; j < kSortItems / kPerVec; ++j) {
+                const uint32_t w[4] = {q[j].x, q[j].y, q[j].z, q[j].w};
+#pragma unroll
+                for (int e = 0; e < kPerVec; ++e)
+                    k[j * kPerVec + e] = sizeof(KeyT) == 2 ? (w[e / 2] >> (16 * (e % 2))) & 0xffffu : w[e];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < kSortItems; ++i) k[i] = b + i < hi ? (uint32_t)keys[b + i] : kInvalidKey;
         }
 #pragma unroll
         for (int i = 0; i < kSortItems; ++i) {
-            const uint32_t idx = c0 + (uint32_t)(i * kBlock + tid);
-            if (idx < hi && (!kFilter || k[i] != kInvalidKey)) atomicAdd(&s_h[wave][(k[i] >> shift) & dmask], 1u);
+            if (b + i < hi && (!kFilter || k[i] != kInvalidKey)) atomicAdd(&s_h[wave][(k[i] >> shift) & dmask], 1u);
         }
     }
     __syncthreads();
