@@ -1,5 +1,6 @@
-// Tile-range extraction from the sorted tile ids (each tile's workload is its
-// run of the sorted list, Sec. 2.2) and a fill kernel used to clear counters.
+// Tile ranges (each tile's workload is its run of the sorted list, Sec. 2.2):
+// their initial empty state, which the last tile-sort pass narrows, the range
+// of a one-tile image, and a fill kernel used to clear counters.
 #include "fgs_internal.hpp"
 
 namespace fgs {
@@ -10,10 +11,7 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t value, size_t n) {
         p[i] = value;
 }
 
-// ranges[t] = [first, last + 1) of tile t in the sorted keys (empty: [0, 0)).
-// n_dev, if given, holds the actual key count (at most n).  Each thread
-// takes four consecutive keys with one 16-byte load (keys is 16-byte
-// aligned) and compares them with their neighbours.
+// The one range of a one-tile image: every pair (*n_dev of them, at most n).
 __global__ void k_single_range(uint2 *__restrict__ ranges, uint32_t n, const uint32_t *__restrict__ n_dev) {
     if (threadIdx.x == 0) ranges[0] = make_uint2(0u, min(n, *n_dev));
 }
