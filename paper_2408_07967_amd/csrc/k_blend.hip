@@ -25,7 +25,7 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kThreads = 128;        // two wavefronts per tile
-constexpr int kBatch = 256;          // Gaussians staged per batch
+constexpr int kBatch = 128;          // Gaussians staged per batch
 constexpr int kWords = kBatch / kWave;
 constexpr float kFar = 1e30f;
 
