@@ -5,8 +5,9 @@
 // One 128-thread workgroup per 16 x 16 tile: each wavefront owns a 16 x 8
 // half, each lane two horizontally adjacent pixels, so the row terms of the
 // quadratic form, the LDS reads and the loop control are shared by two
-// pixels.  The tile's sorted list is walked in batches of 256 Gaussians:
-// every thread stages two Gaussians (the coefficients of the exponent,
+// pixels.  The tile's sorted list is walked in batches of 128 Gaussians
+// (6.4 KB of LDS per workgroup: eight wavefronts per SIMD fit):
+// every thread stages one Gaussian (the coefficients of the exponent,
 // opacity threshold and colour) in LDS and tests each ellipse against the two
 // halves (the exact tile test with a slightly inflated extent, so it never
 // drops a contributor); a wavefront walks only the set bits of its half's
