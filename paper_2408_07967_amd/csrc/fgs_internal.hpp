@@ -99,8 +99,13 @@ unsigned emit_grid(uint32_t visible);
 // Gaussian of position i to gmap[i].  Without a precompute the outputs are
 // indexed by Gaussian and gmap is unused.
 constexpr int kCullBlocks = 2048;
+// count8: the count again in one byte (kCount8Big for a chunked rectangle,
+// whose count k_big_count adds to count later): the scan gathers this
+// 1-byte array, which the L2 caches hold whole.
+constexpr uint8_t kCount8Big = 255;
 void launch_preprocess(const DevScene &sc, const DevPrepared *pp, const DevCamera &cam, const DevOptions &op,
-                       int W, int H, GaussState *gs, uint4 *rect, uint32_t *count, uint4 *erec, uint32_t *dkey,
+                       int W, int H, GaussState *gs, uint4 *rect, uint32_t *count, uint8_t *count8, uint4 *erec,
+                       uint32_t *dkey,
                        uint32_t *cand, uint32_t *seg_count, uint32_t *gmap, uint2 *chunks, uint32_t chunk_cap,
                        FrameCounters *fc, hipStream_t s);
 
@@ -152,9 +157,11 @@ void launch_init_ranges(uint2 *ranges, uint32_t ntiles, hipStream_t s);
 
 // offsets[r] = sum of count[order[r']] for r' < r over the n visible
 // Gaussians (n_dev, bounded by n_host); offsets[n] and *pairs get the total.
-// cs: scratch [n_host]; sums: scratch [kSortBlocks].
-void launch_count_scan(const uint32_t *order, const uint32_t *count, uint32_t n_host, const uint32_t *n_dev,
-                       uint32_t *cs, uint32_t *sums, uint32_t *offsets, uint32_t *pairs, hipStream_t s);
+// The count is read from count8, and from count where count8 holds
+// kCount8Big.  cs: scratch [n_host]; sums: scratch [kSortBlocks].
+void launch_count_scan(const uint32_t *order, const uint8_t *count8, const uint32_t *count, uint32_t n_host,
+                       const uint32_t *n_dev, uint32_t *cs, uint32_t *sums, uint32_t *offsets, uint32_t *pairs,
+                       hipStream_t s);
 
 // A one-tile image: ranges[0] = [0, min(*n_dev, n)).
 void launch_single_range(uint2 *ranges, uint32_t n, const uint32_t *n_dev, hipStream_t s);

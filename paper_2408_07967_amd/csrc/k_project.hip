@@ -378,7 +378,8 @@ template <bool kPrep>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_preprocess(DevScene sc, DevPrepared pp, DevCamera cam, DevOptions op,
                                                        int W, int H, GaussState *__restrict__ gs,
                                                        uint4 *__restrict__ rect, uint32_t *__restrict__ count,
-                                                       uint4 *__restrict__ erec, uint32_t *__restrict__ dkey,
+                                                       uint8_t *__restrict__ count8, uint4 *__restrict__ erec,
+                                                       uint32_t *__restrict__ dkey,
                                                        const uint32_t *__restrict__ cand,
                                                        const uint32_t *__restrict__ seg_count,
                                                        uint32_t *__restrict__ gmap, uint2 *__restrict__ chunks,
@@ -719,6 +720,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         if constexpr (kPrep) gmap[ii] = (uint32_t)g;
         dkey[oi] = key;
         count[oi] = valid ? cnt : 0u;
+        count8[oi] = chunked ? kCount8Big : (uint8_t)(valid ? cnt : 0u);  // cnt <= kBigTiles < kCount8Big
         if (valid) {
             GaussState s;
             s.f0 = make_float4(u, v, A, B);
@@ -989,7 +991,8 @@ unsigned emit_grid(uint32_t visible) {
 }
 
 void launch_preprocess(const DevScene &sc, const DevPrepared *pp, const DevCamera &cam, const DevOptions &op,
-                       int W, int H, GaussState *gs, uint4 *rect, uint32_t *count, uint4 *erec, uint32_t *dkey,
+                       int W, int H, GaussState *gs, uint4 *rect, uint32_t *count, uint8_t *count8, uint4 *erec,
+                       uint32_t *dkey,
                        uint32_t *cand, uint32_t *seg_count, uint32_t *gmap, uint2 *chunks, uint32_t chunk_cap,
                        FrameCounters *fc, hipStream_t s) {
     if (sc.P <= 0) return;
@@ -997,10 +1000,10 @@ void launch_preprocess(const DevScene &sc, const DevPrepared *pp, const DevCamer
         hipLaunchKernelGGL(k_cull, dim3(kCullBlocks), dim3(kBlock), 0, s, sc, *pp, cam, op, W, H, dkey, count, cand,
                            seg_count);
         hipLaunchKernelGGL(k_preprocess<true>, dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, *pp, cam, op, W,
-                           H, gs, rect, count, erec, dkey, cand, seg_count, gmap, chunks, chunk_cap, fc);
+                           H, gs, rect, count, count8, erec, dkey, cand, seg_count, gmap, chunks, chunk_cap, fc);
     } else {
         hipLaunchKernelGGL(k_preprocess<false>, dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, DevPrepared{},
-                           cam, op, W, H, gs, rect, count, erec, dkey, cand, seg_count, gmap, chunks, chunk_cap, fc);
+                           cam, op, W, H, gs, rect, count, count8, erec, dkey, cand, seg_count, gmap, chunks, chunk_cap, fc);
     }
 }
 

@@ -288,8 +288,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 
 // ---- exclusive scan of per-Gaussian tile counts in depth order -------------
 
-// cs[r] = count[order[r]]; sums[b] = sum over the workgroup's range
+// cs[r] = count of order[r] (from the one-byte copy, or count[] for a
+// chunked rectangle); sums[b] = sum over the workgroup's range
 __global__ __launch_bounds__(kBlock) void k_scan_upsweep(const uint32_t *__restrict__ order,
+                                                         const uint8_t *__restrict__ count8,
                                                          const uint32_t *__restrict__ count, uint32_t n_host,
                                                          const uint32_t *n_dev, uint32_t *__restrict__ cs,
                                                          uint32_t *__restrict__ sums) {
@@ -308,8 +310,11 @@ __global__ __launch_bounds__(kBlock) void k_scan_upsweep(const uint32_t *__restr
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const uint32_t i = c0 + (uint32_t)(k * kBlock) + threadIdx.x;
-            c[k] = i < hi ? count[g[k]] : 0u;
+            c[k] = i < hi ? count8[g[k]] : 0u;
         }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (c[k] == kCount8Big) c[k] = count[g[k]];  // a chunked rectangle (rare)
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const uint32_t i = c0 + (uint32_t)(k * kBlock) + threadIdx.x;
@@ -433,10 +438,12 @@ void launch_radix_pass(const void *keys_in, const uint32_t *vals_in, void *keys_
 #undef FGS_DS
 }
 
-void launch_count_scan(const uint32_t *order, const uint32_t *count, uint32_t n_host, const uint32_t *n_dev,
-                       uint32_t *cs, uint32_t *sums, uint32_t *offsets, uint32_t *pairs, hipStream_t s) {
+void launch_count_scan(const uint32_t *order, const uint8_t *count8, const uint32_t *count, uint32_t n_host,
+                       const uint32_t *n_dev, uint32_t *cs, uint32_t *sums, uint32_t *offsets, uint32_t *pairs,
+                       hipStream_t s) {
     if (n_host == 0) return;
-    hipLaunchKernelGGL(k_scan_upsweep, dim3(kSortBlocks), dim3(kBlock), 0, s, order, count, n_host, n_dev, cs, sums);
+    hipLaunchKernelGGL(k_scan_upsweep, dim3(kSortBlocks), dim3(kBlock), 0, s, order, count8, count, n_host, n_dev, cs,
+                       sums);
     hipLaunchKernelGGL(k_scan_downsweep, dim3(kSortBlocks), dim3(kBlock), 0, s, cs, n_host, n_dev, sums, offsets,
                        pairs);
 }

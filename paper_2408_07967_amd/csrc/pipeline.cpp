@@ -68,6 +68,7 @@ hipError_t ensure_gauss(FrameBuffers &b, size_t P) {
     FGS_GROW(b.gs, cap);
     FGS_GROW(b.rect, cap);
     FGS_GROW(b.count, cap);
+    FGS_GROW(b.count8, cap);
     FGS_GROW(b.erec, cap);
     FGS_GROW(b.dkey, cap);
     FGS_GROW(b.dk_b, cap);
@@ -126,7 +127,7 @@ hipError_t ensure_chunks(ChunkList &c, size_t need) {
 }
 
 void free_frame_buffers(FrameBuffers &b) {
-    void **ps[] = {(void **)&b.gs, (void **)&b.rect, (void **)&b.count, (void **)&b.erec, (void **)&b.dkey,
+    void **ps[] = {(void **)&b.gs, (void **)&b.rect, (void **)&b.count, (void **)&b.count8, (void **)&b.erec, (void **)&b.dkey,
                    (void **)&b.dk_b, (void **)&b.dv_a, (void **)&b.dv_b, (void **)&b.offsets, (void **)&b.seg_count, (void **)&b.gmap,
                    (void **)&b.ranges,
                    (void **)&b.T, (void **)&b.last};
@@ -270,7 +271,7 @@ void enqueue_front(const DevScene &sc, const DevPrepared *pp, const DevCamera &c
     // the candidate list of a prepared scene lives in dv_b until the depth sort
     // (a prepared scene's outputs are dense over the candidate list, with the
     // Gaussian of each list position in fb.gmap)
-    launch_preprocess(sc, pp, cam, op, W, H, fb.gs, fb.rect, fb.count, fb.erec, fb.dkey, fb.dv_b, fb.seg_count,
+    launch_preprocess(sc, pp, cam, op, W, H, fb.gs, fb.rect, fb.count, fb.count8, fb.erec, fb.dkey, fb.dv_b, fb.seg_count,
                       fb.gmap, ch.chunks, chunk_cap, fc, s);
     // the large rectangles' exact tests touch neither the depth keys nor the
     // sort scratch: they run beside the depth sort
@@ -299,7 +300,7 @@ void enqueue_front(const DevScene &sc, const DevPrepared *pp, const DevCamera &c
     if (sb != s && joined && hipStreamWaitEvent(s, side.join, 0) != hipSuccess) (void)hipStreamSynchronize(sb);
     mk.mark(2, s);
     // ---- stage 2a: scan of the tile counts in depth order -------------------------
-    launch_count_scan(fb.dv_a, fb.count, P32, &fc->visible, fb.dk_b, ss.sums, fb.offsets, &fc->pairs, s);
+    launch_count_scan(fb.dv_a, fb.count8, fb.count, P32, &fc->visible, fb.dk_b, ss.sums, fb.offsets, &fc->pairs, s);
     mk.mark(3, s);
     (void)hipMemcpyAsync(host_fc, fc, sizeof(FrameCounters), hipMemcpyDeviceToHost, s);
 }

@@ -21,6 +21,7 @@ struct FrameBuffers {
     GaussState *gs = nullptr;
     uint4 *rect = nullptr;
     uint32_t *count = nullptr;
+    uint8_t *count8 = nullptr;  // tile count of a small rectangle, kCount8Big for a chunked one (the scan's gather)
     uint4 *erec = nullptr;  // emission record: rectangle (16-bit) and hit mask
     uint32_t *dkey = nullptr, *dk_b = nullptr, *dv_a = nullptr, *dv_b = nullptr;
     uint32_t *offsets = nullptr;
@@ -35,7 +36,8 @@ struct FrameBuffers {
     uint32_t *last = nullptr;
 
     size_t gauss_bytes() const {
-        return capP * (sizeof(GaussState) + sizeof(uint4) + sizeof(uint32_t) + sizeof(uint4) + 5 * sizeof(uint32_t)) +
+        return capP * (sizeof(GaussState) + sizeof(uint4) + sizeof(uint32_t) + sizeof(uint4) + 5 * sizeof(uint32_t) +
+                       sizeof(uint8_t)) +
                (capP + 1) * sizeof(uint32_t) + kCullBlocks * sizeof(uint32_t);
     }
     size_t bytes() const {
