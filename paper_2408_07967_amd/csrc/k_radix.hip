@@ -31,13 +31,15 @@ __device__ __forceinline__ uint32_t count_of(uint32_t n_host, const uint32_t *n_
     return nd < n_host ? nd : n_host;
 }
 
-// key range [lo, hi) of workgroup b: whole 4096-key tiles split evenly
-__device__ __forceinline__ void block_range(uint32_t n, uint32_t b, uint32_t nb, uint32_t *lo, uint32_t *hi) {
-    const uint32_t tiles = (n + kSortTile - 1) / kSortTile;
+// key range [lo, hi) of workgroup b: whole tiles of `granule` keys (4096 for
+// the sort passes) split evenly
+__device__ __forceinline__ void block_range(uint32_t n, uint32_t b, uint32_t nb, uint32_t *lo, uint32_t *hi,
+                                            uint32_t granule = kSortTile) {
+    const uint32_t tiles = (n + granule - 1) / granule;
     const uint32_t t0 = (uint32_t)(((uint64_t)tiles * b) / nb);
     const uint32_t t1 = (uint32_t)(((uint64_t)tiles * (b + 1)) / nb);
-    *lo = t0 * (uint32_t)kSortTile;
-    const uint32_t h = t1 * (uint32_t)kSortTile;
+    *lo = t0 * granule;
+    const uint32_t h = t1 * granule;
     *hi = h < n ? h : n;
     if (*lo > *hi) *lo = *hi;
 }
@@ -288,6 +290,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 
 // ---- exclusive scan of per-Gaussian tile counts in depth order -------------
 
+// Workgroup ranges of the scan are whole 1024-entry tiles: the few million
+// visible Gaussians keep every one of the kSortBlocks workgroups busy.
+constexpr uint32_t kScanGranule = 1024;
+
 // cs[r] = count of order[r] (from the one-byte copy, or count[] for a
 // chunked rectangle); sums[b] = sum over the workgroup's range
 __global__ __launch_bounds__(kBlock) void k_scan_upsweep(const uint32_t *__restrict__ order,
@@ -298,7 +304,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_upsweep(const uint32_t *__restr
     __shared__ uint32_t s_tmp[kWaves];
     const uint32_t n = count_of(n_host, n_dev);
     uint32_t lo, hi;
-    block_range(n, blockIdx.x, gridDim.x, &lo, &hi);
+    block_range(n, blockIdx.x, gridDim.x, &lo, &hi, kScanGranule);
     uint32_t s = 0;
     for (uint32_t c0 = lo; c0 < hi; c0 += 8 * kBlock) {
         uint32_t g[8], c[8];
@@ -336,7 +342,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_downsweep(const uint32_t *__res
     __shared__ uint32_t s_tmp[kWaves];
     const uint32_t n = count_of(n_host, n_dev);
     uint32_t lo, hi;
-    block_range(n, blockIdx.x, gridDim.x, &lo, &hi);
+    block_range(n, blockIdx.x, gridDim.x, &lo, &hi, kScanGranule);
     uint32_t run = 0;
     {
         constexpr int kPer = kSortBlocks / kBlock;
