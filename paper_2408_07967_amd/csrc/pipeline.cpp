@@ -263,7 +263,8 @@ void SideStream::destroy() {
 
 void enqueue_front(const DevScene &sc, const DevPrepared *pp, const DevCamera &cam, const DevOptions &op, int W,
                    int H, FrameBuffers &fb, ChunkList &ch, SortScratch &ss, FrameCounters *fc,
-                   FrameCounters *host_fc, hipStream_t s, const SideStream &side, const StageMarks &mk) {
+                   FrameCounters *host_fc, hipStream_t s, const SideStream &side, const StageMarks &mk,
+                   hipEvent_t counters_ready) {
     const uint32_t chunk_cap = (uint32_t)std::min<size_t>(ch.cap, 0xffffffffu);
     // ---- stage 1: preprocess + exact tile count -------------------------------
     launch_fill_u32(reinterpret_cast<uint32_t *>(fc), 0u, sizeof(FrameCounters) / 4, s);
@@ -302,7 +303,14 @@ void enqueue_front(const DevScene &sc, const DevPrepared *pp, const DevCamera &c
     // ---- stage 2a: scan of the tile counts in depth order -------------------------
     launch_count_scan(fb.dv_a, fb.count8, fb.count, P32, &fc->visible, fb.dk_b, ss.sums, fb.offsets, &fc->pairs, s);
     mk.mark(3, s);
-    (void)hipMemcpyAsync(host_fc, fc, sizeof(FrameCounters), hipMemcpyDeviceToHost, s);
+    // the second half reads the counters on the device; only the host waits
+    // for their copy, which therefore runs beside it when it can
+    hipStream_t sc2 = s;
+    if (counters_ready && side.side && hipEventRecord(side.fork, s) == hipSuccess &&
+        hipStreamWaitEvent(side.side, side.fork, 0) == hipSuccess)
+        sc2 = side.side;
+    (void)hipMemcpyAsync(host_fc, fc, sizeof(FrameCounters), hipMemcpyDeviceToHost, sc2);
+    if (counters_ready) (void)hipEventRecord(counters_ready, sc2);
 }
 
 bool enqueue_back(int W, int H, const DevOptions &op, uint32_t P, FrameBuffers &fb, ChunkList &ch, SortScratch &ss,

@@ -104,11 +104,14 @@ struct SideStream {
 // visible Gaussians, scan of the tile counts in depth order.  The exact tests
 // of the large rectangles run on the side stream while the depth order is
 // sorted on s; the scan waits for both.  Ends with an asynchronous copy of
-// the frame counters to host_fc (pinned).
+// the frame counters to host_fc (pinned): on s when counters_ready is NULL;
+// otherwise on the side stream, followed there by counters_ready, so that s
+// goes straight on to the second half.
 // pp: NULL (raw parameters) or the scene's view-independent precompute.
 void enqueue_front(const DevScene &sc, const DevPrepared *pp, const DevCamera &cam, const DevOptions &op, int W,
                    int H, FrameBuffers &fb, ChunkList &ch, SortScratch &ss, FrameCounters *fc,
-                   FrameCounters *host_fc, hipStream_t s, const SideStream &side, const StageMarks &mk);
+                   FrameCounters *host_fc, hipStream_t s, const SideStream &side, const StageMarks &mk,
+                   hipEvent_t counters_ready = nullptr);
 
 // Device buffers of a scene's view-independent precompute.
 struct PreparedBuffers {

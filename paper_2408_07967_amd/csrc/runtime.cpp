@@ -306,9 +306,8 @@ fgs_status render_impl(fgs_context *ctx, const fgs_scene *scene, const fgs_prepa
     for (int attempt = 0;; ++attempt) {
         const DevPrepared pdev = prep ? prep->pb.dev() : DevPrepared{};
         enqueue_front(dsc, prep ? &pdev : nullptr, dcam, dop, W, H, fb, ctx->ch, ctx->ss, ctx->fc_dev, ctx->fc_host,
-                      s, ctx->side, mk);
+                      s, ctx->side, mk, ctx->front_done);
         HIP_TRY(ctx, hipGetLastError());
-        HIP_TRY(ctx, hipEventRecord(ctx->front_done, s));
         // The second half reads every count on the device and never writes
         // beyond the pair buffers, so it is enqueued at once with the buffers
         // at hand; the GPU goes on while the host reads the pair count.  If
