@@ -90,7 +90,7 @@ unsigned emit_grid(uint32_t visible);
 // is set and the host renders the frame again with a larger list) and get
 // count 0 and record (rectangle, 0, first chunk).
 // pp: NULL (raw parameters) or the scene's precompute.  With a precompute a
-// cull pass of kCullBlocks workgroups first lists, for each workgroup's
+// cull pass of kCullBlocks workgroups (which also clears *fc) first lists, for each workgroup's
 // contiguous range, the Gaussians that may be visible (in index order, at the
 // start of the range in cand, capacity sc.P; their number in
 // seg_count[workgroup]), and the preprocess runs over those lists only, taken
@@ -124,9 +124,11 @@ void launch_big_count(int W, int H, int binning, const GaussState *gs, const uin
 // Gaussians only record their output base in erec[g].z.
 // visible: the count, or a bound on it when visible_dev (device) holds it.
 // tile_keys: uint32 or, with key_bytes == 2, uint16 tile ids
+// ranges: if non-null, ranges[t] = (0xffffffff, 0) for t < ntiles first
+// (the empty ranges that the last tile-sort pass narrows)
 void launch_emit(int W, int H, const uint32_t *order, uint32_t visible, const uint32_t *visible_dev,
                  const uint32_t *offsets, uint4 *erec, void *tile_keys, int key_bytes, uint32_t *values, uint32_t cap,
-                 hipStream_t s);
+                 uint2 *ranges, uint32_t ntiles, hipStream_t s);
 
 // Emit the pairs of the chunked Gaussians (after launch_emit).
 void launch_big_emit(int W, const uint4 *rect, const uint4 *erec, const uint2 *chunks, uint32_t chunk_cap,
@@ -142,7 +144,7 @@ void launch_big_emit(int W, const uint4 *rect, const uint4 *erec, const uint2 *c
 //   hist    scratch [kSortBlocks][kRadix]; gsum scratch [kSortGroups][kRadix]
 //   run_ends if non-null (the last pass of a sort by the whole key, keys <
 //           nruns): run_ends[k] = [start, end) of key k's run in the output,
-//           by atomic min / max on entries set by launch_init_ranges; a key
+//           by atomic min / max on entries that launch_emit set empty; a key
 //           with no element keeps start > end
 //   key_bytes 4 (uint32 keys) or 2 (uint16 keys: unfiltered passes with
 //           explicit values only)
@@ -150,10 +152,6 @@ void launch_radix_pass(const void *keys_in, const uint32_t *vals_in, void *keys_
                        uint32_t n_host, const uint32_t *n_dev, int shift, int bits, bool filter, bool write_keys,
                        uint32_t *hist, uint32_t *gsum, hipStream_t s, uint2 *run_ends = nullptr,
                        uint32_t nruns = 0, int key_bytes = 4);
-
-// ranges[t] = (0xffffffff, 0) for t < ntiles: an empty range that atomic
-// min / max narrow to the tile's run.
-void launch_init_ranges(uint2 *ranges, uint32_t ntiles, hipStream_t s);
 
 // offsets[r] = sum of count[order[r']] for r' < r over the n visible
 // Gaussians (n_dev, bounded by n_host); offsets[n] and *pairs get the total.

@@ -6,6 +6,8 @@
 // written order, so the per-Gaussian state and the tile test give the same
 // bits as the canonical FP32 evaluation of the method; exp and ln are
 // evaluated in binary64 by a fixed operation sequence and rounded once.
+#include <algorithm>
+
 #include "fgs_internal.hpp"
 #include "sh_basis.hpp"
 
@@ -311,9 +313,13 @@ __device__ __forceinline__ void cull_range(int64_t P, uint32_t b, int64_t *lo, i
 // workgroup owns a contiguous range of Gaussians and lists its candidates in
 // index order at the start of that range (no global atomics).
 __global__ __launch_bounds__(kBlock) void k_cull(DevScene sc, DevPrepared pp, DevCamera cam, DevOptions op, int W,
-                                                 int H, uint32_t *__restrict__ dkey, uint32_t *__restrict__ count,
-                                                 uint32_t *__restrict__ cand, uint32_t *__restrict__ seg_count) {
+                                                 int H, uint32_t *__restrict__ cand, uint32_t *__restrict__ seg_count,
+                                                 FrameCounters *fc) {
     __shared__ uint32_t s_w[kBlock / kWave];
+    // the frame's counters start at zero (the preprocess, next on the
+    // stream, is their first user)
+    static_assert(sizeof(FrameCounters) / 4 <= kBlock, "counters cleared by one workgroup");
+    if (blockIdx.x == 0 && threadIdx.x < sizeof(FrameCounters) / 4) reinterpret_cast<uint32_t *>(fc)[threadIdx.x] = 0;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     int64_t lo, hi;
     cull_range(sc.P, blockIdx.x, &lo, &hi);
@@ -756,8 +762,13 @@ __global__ __launch_bounds__(kBlock) void k_emit(int W, int H, const uint32_t *_
                                                  uint32_t visible, const uint32_t *__restrict__ visible_dev,
                                                  const uint32_t *__restrict__ offsets, uint4 *__restrict__ erec,
                                                  KeyT *__restrict__ tile_keys, uint32_t *__restrict__ values,
-                                                 uint32_t cap) {
+                                                 uint32_t cap, uint2 *__restrict__ ranges, uint32_t ntiles) {
     __shared__ uint32_t s_excl[kBlock / kWave][kWave];
+    // every tile's range starts empty, (0xffffffff, 0), for the last sort
+    // pass to narrow (ranges NULL: no pass records them)
+    if (ranges)
+        for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < ntiles; t += gridDim.x * kBlock)
+            ranges[t] = make_uint2(0xffffffffu, 0u);
     // the visible count comes from the device when the launch is sized by a
     // bound (graph-captured frames); it never exceeds the bound
     if (visible_dev) visible = min(visible, *visible_dev);
@@ -997,8 +1008,8 @@ void launch_preprocess(const DevScene &sc, const DevPrepared *pp, const DevCamer
                        FrameCounters *fc, hipStream_t s) {
     if (sc.P <= 0) return;
     if (pp) {
-        hipLaunchKernelGGL(k_cull, dim3(kCullBlocks), dim3(kBlock), 0, s, sc, *pp, cam, op, W, H, dkey, count, cand,
-                           seg_count);
+        hipLaunchKernelGGL(k_cull, dim3(kCullBlocks), dim3(kBlock), 0, s, sc, *pp, cam, op, W, H, cand, seg_count,
+                           fc);
         hipLaunchKernelGGL(k_preprocess<true>, dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, *pp, cam, op, W,
                            H, gs, rect, count, count8, erec, dkey, cand, seg_count, gmap, chunks, chunk_cap, fc);
     } else {
@@ -1036,14 +1047,16 @@ void launch_big_emit(int W, const uint4 *rect, const uint4 *erec, const uint2 *c
 
 void launch_emit(int W, int H, const uint32_t *order, uint32_t visible, const uint32_t *visible_dev,
                  const uint32_t *offsets, uint4 *erec, void *tile_keys, int key_bytes, uint32_t *values, uint32_t cap,
-                 hipStream_t s) {
-    if (visible == 0) return;
+                 uint2 *ranges, uint32_t ntiles, hipStream_t s) {
+    if (visible == 0 && (!ranges || ntiles == 0)) return;
+    unsigned grid = emit_grid(visible);
+    if (ranges) grid = std::max(grid, std::min<unsigned>((ntiles + kBlock - 1) / kBlock, kPersistentBlocks));
     if (key_bytes == 2)
-        hipLaunchKernelGGL(k_emit<uint16_t>, dim3(emit_grid(visible)), dim3(kBlock), 0, s, W, H, order, visible,
-                           visible_dev, offsets, erec, static_cast<uint16_t *>(tile_keys), values, cap);
+        hipLaunchKernelGGL(k_emit<uint16_t>, dim3(grid), dim3(kBlock), 0, s, W, H, order, visible, visible_dev,
+                           offsets, erec, static_cast<uint16_t *>(tile_keys), values, cap, ranges, ntiles);
     else
-        hipLaunchKernelGGL(k_emit<uint32_t>, dim3(emit_grid(visible)), dim3(kBlock), 0, s, W, H, order, visible,
-                           visible_dev, offsets, erec, static_cast<uint32_t *>(tile_keys), values, cap);
+        hipLaunchKernelGGL(k_emit<uint32_t>, dim3(grid), dim3(kBlock), 0, s, W, H, order, visible, visible_dev,
+                           offsets, erec, static_cast<uint32_t *>(tile_keys), values, cap, ranges, ntiles);
 }
 
 }  // namespace fgs

@@ -1,6 +1,5 @@
-// Tile ranges (each tile's workload is its run of the sorted list, Sec. 2.2):
-// their initial empty state, which the last tile-sort pass narrows, the range
-// of a one-tile image, and a fill kernel used to clear counters.
+// The tile range of a one-tile image (each tile's workload is its run of the
+// sorted list, Sec. 2.2) and a fill kernel used to clear counters.
 #include "fgs_internal.hpp"
 
 namespace fgs {
@@ -16,19 +15,7 @@ __global__ void k_single_range(uint2 *__restrict__ ranges, uint32_t n, const uin
     if (threadIdx.x == 0) ranges[0] = make_uint2(0u, min(n, *n_dev));
 }
 
-__global__ void k_init_ranges(uint2 *__restrict__ ranges, uint32_t ntiles) {
-    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < ntiles; t += gridDim.x * blockDim.x)
-        ranges[t] = make_uint2(0xffffffffu, 0u);
-}
-
 }  // namespace
-
-void launch_init_ranges(uint2 *ranges, uint32_t ntiles, hipStream_t s) {
-    if (ntiles == 0) return;
-    uint32_t blocks = (ntiles + kBlock - 1) / kBlock;
-    if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_init_ranges, dim3(blocks), dim3(kBlock), 0, s, ranges, ntiles);
-}
 
 void launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t s) {
     if (n == 0) return;

@@ -267,7 +267,8 @@ void enqueue_front(const DevScene &sc, const DevPrepared *pp, const DevCamera &c
                    hipEvent_t counters_ready) {
     const uint32_t chunk_cap = (uint32_t)std::min<size_t>(ch.cap, 0xffffffffu);
     // ---- stage 1: preprocess + exact tile count -------------------------------
-    launch_fill_u32(reinterpret_cast<uint32_t *>(fc), 0u, sizeof(FrameCounters) / 4, s);
+    // (a prepared scene's cull clears the counters itself)
+    if (!pp || sc.P <= 0) launch_fill_u32(reinterpret_cast<uint32_t *>(fc), 0u, sizeof(FrameCounters) / 4, s);
     mk.mark(0, s);
     // the candidate list of a prepared scene lives in dv_b until the depth sort
     // (a prepared scene's outputs are dense over the candidate list, with the
@@ -323,18 +324,20 @@ bool enqueue_back(int W, int H, const DevOptions &op, uint32_t P, FrameBuffers &
     // ---- stage 2b: key emission -------------------------------------------------
     // tile ids travel as uint16 through emission and sort when they fit
     const int kb = ntiles <= 65536u ? 2 : 4;
-    launch_emit(W, H, fb.dv_a, P, &fc->visible, fb.offsets, fb.erec, fb.tk_a, kb, fb.tv_a, pair_cap, s);
+    int shifts[4] = {0, 0, 0, 0}, widths[4] = {0, 0, 0, 0};
+    const int npass = plan_tile_passes(ceil_log2(ntiles), shifts, widths);
+    // the emission also sets every tile's range empty when a sort pass
+    // records the ranges (a one-tile image has no pass: its single range
+    // holds every pair)
+    launch_emit(W, H, fb.dv_a, P, &fc->visible, fb.offsets, fb.erec, fb.tk_a, kb, fb.tv_a, pair_cap,
+                npass > 0 ? fb.ranges : nullptr, ntiles, s);
     launch_big_emit(W, fb.rect, fb.erec, ch.chunks, chunk_cap, ch.hits, ch.mask, fb.tk_a, kb, fb.tv_a, pair_cap, fc,
                     s);
     mk.mark(4, s);
     // ---- stage 3: stable LSD sort of the pairs by tile id ---------------------------
-    int shifts[4] = {0, 0, 0, 0}, widths[4] = {0, 0, 0, 0};
-    const int npass = plan_tile_passes(ceil_log2(ntiles), shifts, widths);
     uint32_t *ki = fb.tk_a, *vi = fb.tv_a, *ko = fb.tk_b, *vo = fb.tv_b;
     // The last pass records where each tile's run starts and ends instead of
-    // writing the sorted tile ids (an empty tile keeps start > end).  A
-    // one-tile image has no pass: its single range holds every pair.
-    if (npass > 0) launch_init_ranges(fb.ranges, ntiles, s);
+    // writing the sorted tile ids (an empty tile keeps start > end).
     for (int p = 0; p < npass; ++p) {
         const bool last_pass = p + 1 == npass;
         launch_radix_pass(ki, vi, ko, vo, pair_cap, &fc->pairs, shifts[p], widths[p], false, !last_pass, ss.rhist,
