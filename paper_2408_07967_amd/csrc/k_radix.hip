@@ -223,7 +223,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             uint32_t diff_lo = 0, diff_hi = 0;
 #pragma unroll
             for (int bb = 0; bb < kRadixBits; ++bb) {
-                const uint32_t t = (uint32_t)__builtin_amdgcn_sbfe((int)d, bb, 1);  // 0 or ~0
+                // bit bb of d widened to 0 or ~0 by one signed bitfield extract
+                // (written out: the compiler otherwise splits it into two shifts)
+                uint32_t t;
+                asm("v_bfe_i32 %0, %1, %2, 1" : "=v"(t) : "v"(d), "i"(bb));
                 const uint64_t m = __ballot(t != 0u);
                 diff_lo = __builtin_amdgcn_bitop3_b32(diff_lo, (uint32_t)m, t, 0xf6);
                 diff_hi = __builtin_amdgcn_bitop3_b32(diff_hi, (uint32_t)(m >> 32), t, 0xf6);
