@@ -78,6 +78,11 @@ constexpr uint32_t kErrChunkOverflow = 2u;       // chunk list too small: render
 constexpr int kSortBlocks = 1024;
 constexpr int kSortGroup = 32;
 constexpr int kSortGroups = (kSortBlocks + kSortGroup - 1) / kSortGroup;
+// Group sums of one pass: kSortGroups x kRadix counters.  Every pass of a
+// frame has its own (4 depth passes, up to 4 tile passes), cleared by the
+// kernel that runs before the pass.
+constexpr int kGsumWords = kSortGroups * kRadix;
+constexpr int kGsumSlots = 8;
 
 unsigned preprocess_grid(int64_t P);
 unsigned emit_grid(uint32_t visible);
@@ -103,11 +108,12 @@ constexpr int kCullBlocks = 2048;
 // whose count k_big_count adds to count later): the scan gathers this
 // 1-byte array, which the L2 caches hold whole.
 constexpr uint8_t kCount8Big = 255;
+// gsum_clear: kGsumWords counters cleared (the first depth pass's group sums).
 void launch_preprocess(const DevScene &sc, const DevPrepared *pp, const DevCamera &cam, const DevOptions &op,
                        int W, int H, GaussState *gs, uint4 *rect, uint32_t *count, uint8_t *count8, uint4 *erec,
                        uint32_t *dkey,
                        uint32_t *cand, uint32_t *seg_count, uint32_t *gmap, uint2 *chunks, uint32_t chunk_cap,
-                       FrameCounters *fc, hipStream_t s);
+                       FrameCounters *fc, uint32_t *gsum_clear, hipStream_t s);
 
 // View-independent precompute (opacity, 3D covariance, k^2, log2 opacity,
 // Gaussian-major SH) for options op (alpha_min and cap_3sigma).
@@ -125,10 +131,11 @@ void launch_big_count(int W, int H, int binning, const GaussState *gs, const uin
 // visible: the count, or a bound on it when visible_dev (device) holds it.
 // tile_keys: uint32 or, with key_bytes == 2, uint16 tile ids
 // ranges: if non-null, ranges[t] = (0xffffffff, 0) for t < ntiles first
-// (the empty ranges that the last tile-sort pass narrows)
+// (the empty ranges that the last tile-sort pass narrows); gsum_clear, if
+// non-null: kGsumWords counters cleared (the first tile pass's group sums)
 void launch_emit(int W, int H, const uint32_t *order, uint32_t visible, const uint32_t *visible_dev,
                  const uint32_t *offsets, uint4 *erec, void *tile_keys, int key_bytes, uint32_t *values, uint32_t cap,
-                 uint2 *ranges, uint32_t ntiles, hipStream_t s);
+                 uint2 *ranges, uint32_t ntiles, uint32_t *gsum_clear, hipStream_t s);
 
 // Emit the pairs of the chunked Gaussians (after launch_emit).
 void launch_big_emit(int W, const uint4 *rect, const uint4 *erec, const uint2 *chunks, uint32_t chunk_cap,
@@ -141,7 +148,11 @@ void launch_big_emit(int W, const uint4 *rect, const uint4 *erec, const uint2 *c
 //           actual count is read there on the device
 //   vals_in null: values are the input positions
 //   filter  drop keys equal to kInvalidKey
-//   hist    scratch [kSortBlocks][kRadix]; gsum scratch [kSortGroups][kRadix]
+//   hist    scratch [kSortBlocks][kRadix]
+//   gsum    [kSortGroups][kRadix], zero on entry: the upsweep adds each
+//           workgroup's histogram into its group's row (so no separate group
+//           kernel runs); gsum_next, if non-null, is cleared by the downsweep
+//           for the next pass
 //   run_ends if non-null (the last pass of a sort by the whole key, keys <
 //           nruns): run_ends[k] = [start, end) of key k's run in the output,
 //           by atomic min / max on entries that launch_emit set empty; a key
@@ -150,8 +161,8 @@ void launch_big_emit(int W, const uint4 *rect, const uint4 *erec, const uint2 *c
 //           explicit values only)
 void launch_radix_pass(const void *keys_in, const uint32_t *vals_in, void *keys_out, uint32_t *vals_out,
                        uint32_t n_host, const uint32_t *n_dev, int shift, int bits, bool filter, bool write_keys,
-                       uint32_t *hist, uint32_t *gsum, hipStream_t s, uint2 *run_ends = nullptr,
-                       uint32_t nruns = 0, int key_bytes = 4);
+                       uint32_t *hist, uint32_t *gsum, uint32_t *gsum_next, hipStream_t s,
+                       uint2 *run_ends = nullptr, uint32_t nruns = 0, int key_bytes = 4);
 
 // offsets[r] = sum of count[order[r']] for r' < r over the n visible
 // Gaussians (n_dev, bounded by n_host); offsets[n] and *pairs get the total.

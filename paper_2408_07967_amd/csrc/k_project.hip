@@ -389,7 +389,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                                                        const uint32_t *__restrict__ cand,
                                                        const uint32_t *__restrict__ seg_count,
                                                        uint32_t *__restrict__ gmap, uint2 *__restrict__ chunks,
-                                                       uint32_t chunk_cap, FrameCounters *fc) {
+                                                       uint32_t chunk_cap, FrameCounters *fc,
+                                                       uint32_t *__restrict__ gsum_clear) {
+    // the first depth pass's group sums start at zero
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < (uint32_t)kGsumWords; i += gridDim.x * kBlock)
+        gsum_clear[i] = 0;
     // Persistent grid: each workgroup walks batches of 256 Gaussians.  Every
     // wavefront keeps its own visible count and pending chunk reservations
     // (LDS), so the batch loop has no workgroup barrier and global atomics
@@ -762,13 +766,18 @@ __global__ __launch_bounds__(kBlock) void k_emit(int W, int H, const uint32_t *_
                                                  uint32_t visible, const uint32_t *__restrict__ visible_dev,
                                                  const uint32_t *__restrict__ offsets, uint4 *__restrict__ erec,
                                                  KeyT *__restrict__ tile_keys, uint32_t *__restrict__ values,
-                                                 uint32_t cap, uint2 *__restrict__ ranges, uint32_t ntiles) {
+                                                 uint32_t cap, uint2 *__restrict__ ranges, uint32_t ntiles,
+                                                 uint32_t *__restrict__ gsum_clear) {
     __shared__ uint32_t s_excl[kBlock / kWave][kWave];
     // every tile's range starts empty, (0xffffffff, 0), for the last sort
     // pass to narrow (ranges NULL: no pass records them)
     if (ranges)
         for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < ntiles; t += gridDim.x * kBlock)
             ranges[t] = make_uint2(0xffffffffu, 0u);
+    // and the first tile pass's group sums start at zero
+    if (gsum_clear)
+        for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < (uint32_t)kGsumWords; i += gridDim.x * kBlock)
+            gsum_clear[i] = 0;
     // the visible count comes from the device when the launch is sized by a
     // bound (graph-captured frames); it never exceeds the bound
     if (visible_dev) visible = min(visible, *visible_dev);
@@ -1005,16 +1014,16 @@ void launch_preprocess(const DevScene &sc, const DevPrepared *pp, const DevCamer
                        int W, int H, GaussState *gs, uint4 *rect, uint32_t *count, uint8_t *count8, uint4 *erec,
                        uint32_t *dkey,
                        uint32_t *cand, uint32_t *seg_count, uint32_t *gmap, uint2 *chunks, uint32_t chunk_cap,
-                       FrameCounters *fc, hipStream_t s) {
+                       FrameCounters *fc, uint32_t *gsum_clear, hipStream_t s) {
     if (sc.P <= 0) return;
     if (pp) {
         hipLaunchKernelGGL(k_cull, dim3(kCullBlocks), dim3(kBlock), 0, s, sc, *pp, cam, op, W, H, cand, seg_count,
                            fc);
         hipLaunchKernelGGL(k_preprocess<true>, dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, *pp, cam, op, W,
-                           H, gs, rect, count, count8, erec, dkey, cand, seg_count, gmap, chunks, chunk_cap, fc);
+                           H, gs, rect, count, count8, erec, dkey, cand, seg_count, gmap, chunks, chunk_cap, fc, gsum_clear);
     } else {
         hipLaunchKernelGGL(k_preprocess<false>, dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, DevPrepared{},
-                           cam, op, W, H, gs, rect, count, count8, erec, dkey, cand, seg_count, gmap, chunks, chunk_cap, fc);
+                           cam, op, W, H, gs, rect, count, count8, erec, dkey, cand, seg_count, gmap, chunks, chunk_cap, fc, gsum_clear);
     }
 }
 
@@ -1047,16 +1056,16 @@ void launch_big_emit(int W, const uint4 *rect, const uint4 *erec, const uint2 *c
 
 void launch_emit(int W, int H, const uint32_t *order, uint32_t visible, const uint32_t *visible_dev,
                  const uint32_t *offsets, uint4 *erec, void *tile_keys, int key_bytes, uint32_t *values, uint32_t cap,
-                 uint2 *ranges, uint32_t ntiles, hipStream_t s) {
-    if (visible == 0 && (!ranges || ntiles == 0)) return;
+                 uint2 *ranges, uint32_t ntiles, uint32_t *gsum_clear, hipStream_t s) {
+    if (visible == 0 && (!ranges || ntiles == 0) && !gsum_clear) return;
     unsigned grid = emit_grid(visible);
     if (ranges) grid = std::max(grid, std::min<unsigned>((ntiles + kBlock - 1) / kBlock, kPersistentBlocks));
     if (key_bytes == 2)
         hipLaunchKernelGGL(k_emit<uint16_t>, dim3(grid), dim3(kBlock), 0, s, W, H, order, visible, visible_dev,
-                           offsets, erec, static_cast<uint16_t *>(tile_keys), values, cap, ranges, ntiles);
+                           offsets, erec, static_cast<uint16_t *>(tile_keys), values, cap, ranges, ntiles, gsum_clear);
     else
         hipLaunchKernelGGL(k_emit<uint32_t>, dim3(grid), dim3(kBlock), 0, s, W, H, order, visible, visible_dev,
-                           offsets, erec, static_cast<uint32_t *>(tile_keys), values, cap, ranges, ntiles);
+                           offsets, erec, static_cast<uint32_t *>(tile_keys), values, cap, ranges, ntiles, gsum_clear);
 }
 
 }  // namespace fgs

@@ -4,9 +4,9 @@
 // A pass over n keys uses a fixed grid of kSortBlocks workgroups; workgroup b
 // owns a contiguous range of 4096-key tiles (the range is derived on the
 // device from n, so n may be a device-side count):
-//   upsweep    - digit histogram of each workgroup's range   -> hist[b][d]
-//   group sums - sum of the histograms of every kSortGroup
-//                consecutive workgroups                      -> gsum[w][d]
+//   upsweep    - digit histogram of each workgroup's range   -> hist[b][d],
+//                and added (device-scope atomics) into the row
+//                of its group of kSortGroup workgroups       -> gsum[w][d]
 //   downsweep  - each workgroup derives the global offset of its first key
 //                of every digit (digit totals, earlier groups, earlier
 //                workgroups of its own group), then walks its tiles in order:
@@ -70,7 +70,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s
 template <bool kFilter, class KeyT>
 __global__ __launch_bounds__(kBlock) void k_radix_upsweep(const KeyT *__restrict__ keys, uint32_t n_host,
                                                           const uint32_t *n_dev, int shift, int bits,
-                                                          uint32_t *__restrict__ hist) {
+                                                          uint32_t *__restrict__ hist, uint32_t *gsum) {
     __shared__ uint32_t s_h[kWaves][kRadix];
     const int tid = threadIdx.x, wave = tid / kWave;
     for (int i = tid; i < kWaves * kRadix; i += kBlock) (&s_h[0][0])[i] = 0;
@@ -108,28 +108,12 @@ __global__ __launch_bounds__(kBlock) void k_radix_upsweep(const KeyT *__restrict
         }
     }
     __syncthreads();
-    hist[(size_t)blockIdx.x * kRadix + tid] = s_h[0][tid] + s_h[1][tid] + s_h[2][tid] + s_h[3][tid];
+    const uint32_t h = s_h[0][tid] + s_h[1][tid] + s_h[2][tid] + s_h[3][tid];
+    hist[(size_t)blockIdx.x * kRadix + tid] = h;
+    if (h) atomicAdd(&gsum[(size_t)(blockIdx.x / kSortGroup) * kRadix + tid], h);
 }
 
-// gsum[w][d] = sum of hist[b][d] over the kSortGroup workgroups of group w.
-// One wavefront per (group, 64 digits): every row of the group is loaded at
-// once, so the kernel costs one memory round trip.
-static_assert(kSortBlocks % kSortGroup == 0, "whole groups of histogram rows");
-static_assert(kRadix % kWave == 0, "digits split by wavefront");
-constexpr int kGroupsGrid = kSortGroups * (kRadix / kWave);
-
-__global__ __launch_bounds__(kWave) void k_radix_groups(const uint32_t *__restrict__ hist,
-                                                        uint32_t *__restrict__ gsum) {
-    const uint32_t w = blockIdx.x / (kRadix / kWave);
-    const uint32_t d = (blockIdx.x % (kRadix / kWave)) * kWave + threadIdx.x;
-    uint32_t v[kSortGroup];
-#pragma unroll
-    for (int r = 0; r < kSortGroup; ++r) v[r] = hist[(size_t)(w * kSortGroup + r) * kRadix + d];
-    uint32_t s = 0;
-#pragma unroll
-    for (int r = 0; r < kSortGroup; ++r) s += v[r];
-    gsum[(size_t)w * kRadix + d] = s;
-}
+static_assert(kSortBlocks % kSortGroup == 0, "whole groups of workgroups");
 
 // (LDS holds four workgroups per CU, so registers are capped at what four
 // waves per SIMD allow.)
@@ -141,6 +125,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                                                             const uint32_t *n_dev, int shift, int bits,
                                                             const uint32_t *__restrict__ hist,
                                                             const uint32_t *__restrict__ gsum,
+                                                            uint32_t *__restrict__ gsum_next,
                                                             uint32_t *__restrict__ run_end, uint32_t nruns) {
     // (per-wave and per-tile digit counts are at most kSortTile: 16 bits)
     __shared__ KeyT s_keys[kSortTile];
@@ -153,6 +138,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     __shared__ uint32_t s_nv;
 
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    // the next pass's group sums start at zero
+    if (gsum_next)
+        for (uint32_t i = blockIdx.x * kBlock + tid; i < (uint32_t)kGsumWords; i += gridDim.x * kBlock) gsum_next[i] = 0;
     const uint32_t n = count_of(n_host, n_dev);
     const uint32_t b = blockIdx.x, nb = gridDim.x;
     uint32_t lo, hi;
@@ -414,7 +402,8 @@ __global__ __launch_bounds__(kBlock) void k_scan_downsweep(const uint32_t *__res
 
 void launch_radix_pass(const void *keys_in, const uint32_t *vals_in, void *keys_out, uint32_t *vals_out,
                        uint32_t n_host, const uint32_t *n_dev, int shift, int bits, bool filter, bool write_keys,
-                       uint32_t *hist, uint32_t *gsum, hipStream_t s, uint2 *run_ends, uint32_t nruns, int key_bytes) {
+                       uint32_t *hist, uint32_t *gsum, uint32_t *gsum_next, hipStream_t s, uint2 *run_ends,
+                       uint32_t nruns, int key_bytes) {
     if (n_host == 0) return;
     const unsigned nb = kSortBlocks;
     const bool k16 = key_bytes == 2;
@@ -422,20 +411,19 @@ void launch_radix_pass(const void *keys_in, const uint32_t *vals_in, void *keys_
     const uint16_t *k16i = static_cast<const uint16_t *>(keys_in);
     if (k16)
         hipLaunchKernelGGL((k_radix_upsweep<false, uint16_t>), dim3(nb), dim3(kBlock), 0, s, k16i, n_host, n_dev,
-                           shift, bits, hist);
+                           shift, bits, hist, gsum);
     else if (filter)
         hipLaunchKernelGGL((k_radix_upsweep<true, uint32_t>), dim3(nb), dim3(kBlock), 0, s, k32i, n_host, n_dev,
-                           shift, bits, hist);
+                           shift, bits, hist, gsum);
     else
         hipLaunchKernelGGL((k_radix_upsweep<false, uint32_t>), dim3(nb), dim3(kBlock), 0, s, k32i, n_host, n_dev,
-                           shift, bits, hist);
-    hipLaunchKernelGGL(k_radix_groups, dim3(kGroupsGrid), dim3(kWave), 0, s, hist, gsum);
+                           shift, bits, hist, gsum);
     const bool ident = vals_in == nullptr;
     uint32_t *ends = reinterpret_cast<uint32_t *>(run_ends);
 #define FGS_DS(I, F, K, T)                                                                                          \
     hipLaunchKernelGGL((k_radix_downsweep<I, F, K, T>), dim3(nb), dim3(kBlock), 0, s, static_cast<const T *>(keys_in), \
-                       vals_in, static_cast<T *>(keys_out), vals_out, n_host, n_dev, shift, bits, hist, gsum, ends,   \
-                       nruns)
+                       vals_in, static_cast<T *>(keys_out), vals_out, n_host, n_dev, shift, bits, hist, gsum,         \
+                       gsum_next, ends, nruns)
     // 16-bit keys: the tile passes (never filtered, explicit values)
     if (k16 && write_keys) FGS_DS(false, false, true, uint16_t);
     else if (k16) FGS_DS(false, false, false, uint16_t);

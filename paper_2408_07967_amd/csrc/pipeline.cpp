@@ -111,7 +111,7 @@ hipError_t ensure_pixels(FrameBuffers &b, size_t pix) {
 hipError_t ensure_sort_scratch(SortScratch &s) {
     if (s.rhist) return hipSuccess;
     FGS_GROW(s.rhist, (size_t)kSortBlocks * kRadix);
-    FGS_GROW(s.gsum, (size_t)kSortGroups * kRadix);
+    FGS_GROW(s.gsum, (size_t)kGsumSlots * kGsumWords);
     FGS_GROW(s.sums, (size_t)kSortBlocks);
     return hipSuccess;
 }
@@ -273,8 +273,11 @@ void enqueue_front(const DevScene &sc, const DevPrepared *pp, const DevCamera &c
     // the candidate list of a prepared scene lives in dv_b until the depth sort
     // (a prepared scene's outputs are dense over the candidate list, with the
     // Gaussian of each list position in fb.gmap)
+    // group-sum slots: depth passes 0-3, tile passes 4-7; each slot is cleared
+    // by the kernel before its pass (the preprocess, the emission, or the
+    // previous pass's downsweep)
     launch_preprocess(sc, pp, cam, op, W, H, fb.gs, fb.rect, fb.count, fb.count8, fb.erec, fb.dkey, fb.dv_b, fb.seg_count,
-                      fb.gmap, ch.chunks, chunk_cap, fc, s);
+                      fb.gmap, ch.chunks, chunk_cap, fc, ss.slot(0), s);
     // the large rectangles' exact tests touch neither the depth keys nor the
     // sort scratch: they run beside the depth sort
     hipStream_t sb = s;
@@ -292,12 +295,13 @@ void enqueue_front(const DevScene &sc, const DevPrepared *pp, const DevCamera &c
     // (values: the output slots, i.e. list positions of a prepared scene's
     // candidates or Gaussian indices)
     launch_radix_pass(fb.dkey, nullptr, fb.dk_b, fb.dv_b, P32, pp ? &fc->ncand : nullptr, 0, 8, true, true, ss.rhist,
-                      ss.gsum, s);
-    launch_radix_pass(fb.dk_b, fb.dv_b, fb.dkey, fb.dv_a, P32, &fc->visible, 8, 8, false, true, ss.rhist, ss.gsum, s);
-    launch_radix_pass(fb.dkey, fb.dv_a, fb.dk_b, fb.dv_b, P32, &fc->visible, 16, 8, false, true, ss.rhist, ss.gsum,
-                      s);
-    launch_radix_pass(fb.dk_b, fb.dv_b, fb.dkey, fb.dv_a, P32, &fc->visible, 24, 8, false, false, ss.rhist, ss.gsum,
-                      s);
+                      ss.slot(0), ss.slot(1), s);
+    launch_radix_pass(fb.dk_b, fb.dv_b, fb.dkey, fb.dv_a, P32, &fc->visible, 8, 8, false, true, ss.rhist, ss.slot(1),
+                      ss.slot(2), s);
+    launch_radix_pass(fb.dkey, fb.dv_a, fb.dk_b, fb.dv_b, P32, &fc->visible, 16, 8, false, true, ss.rhist, ss.slot(2),
+                      ss.slot(3), s);
+    launch_radix_pass(fb.dk_b, fb.dv_b, fb.dkey, fb.dv_a, P32, &fc->visible, 24, 8, false, false, ss.rhist,
+                      ss.slot(3), nullptr, s);
     // the scan reads the counts of the large rectangles
     if (sb != s && joined && hipStreamWaitEvent(s, side.join, 0) != hipSuccess) (void)hipStreamSynchronize(sb);
     mk.mark(2, s);
@@ -329,8 +333,9 @@ bool enqueue_back(int W, int H, const DevOptions &op, uint32_t P, FrameBuffers &
     // the emission also sets every tile's range empty when a sort pass
     // records the ranges (a one-tile image has no pass: its single range
     // holds every pair)
+    static_assert(kGsumSlots >= 4 + 4, "four depth and up to four tile passes");
     launch_emit(W, H, fb.dv_a, P, &fc->visible, fb.offsets, fb.erec, fb.tk_a, kb, fb.tv_a, pair_cap,
-                npass > 0 ? fb.ranges : nullptr, ntiles, s);
+                npass > 0 ? fb.ranges : nullptr, ntiles, npass > 0 ? ss.slot(4) : nullptr, s);
     launch_big_emit(W, fb.rect, fb.erec, ch.chunks, chunk_cap, ch.hits, ch.mask, fb.tk_a, kb, fb.tv_a, pair_cap, fc,
                     s);
     mk.mark(4, s);
@@ -341,7 +346,8 @@ bool enqueue_back(int W, int H, const DevOptions &op, uint32_t P, FrameBuffers &
     for (int p = 0; p < npass; ++p) {
         const bool last_pass = p + 1 == npass;
         launch_radix_pass(ki, vi, ko, vo, pair_cap, &fc->pairs, shifts[p], widths[p], false, !last_pass, ss.rhist,
-                          ss.gsum, s, last_pass ? fb.ranges : nullptr, ntiles, kb);
+                          ss.slot(4 + p), last_pass ? nullptr : ss.slot(5 + p), s, last_pass ? fb.ranges : nullptr,
+                          ntiles, kb);
         std::swap(ki, ko);
         std::swap(vi, vo);
     }

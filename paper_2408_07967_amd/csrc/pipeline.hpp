@@ -48,9 +48,10 @@ struct FrameBuffers {
 
 // Radix-sort and scan scratch of one in-flight frame.
 struct SortScratch {
-    uint32_t *rhist = nullptr, *gsum = nullptr, *sums = nullptr;
+    uint32_t *rhist = nullptr, *gsum = nullptr, *sums = nullptr;  // gsum: kGsumSlots slots of kGsumWords
+    uint32_t *slot(int i) const { return gsum + (size_t)i * kGsumWords; }
     static size_t bytes() {
-        return ((size_t)kSortBlocks * kRadix + (size_t)kSortGroups * kRadix + kSortBlocks) * sizeof(uint32_t);
+        return ((size_t)kSortBlocks * kRadix + (size_t)kGsumSlots * kGsumWords + kSortBlocks) * sizeof(uint32_t);
     }
 };
 
