@@ -232,6 +232,33 @@ def test_deterministic_repeat(orc, R, scenes):
         assert np.array_equal(a[k], b[k]), k
 
 
+def test_pair_buffers_grow_inside_a_frame(orc, scenes):
+    """A fresh context renders a small frame, then one with far more pairs
+    than its buffers hold: the second half, enqueued with the small buffers,
+    runs again after they grow (every sort pass's group sums cleared again).
+    The grown frame and a repeat of it are bit-exact against the oracle."""
+    import torch
+    from paper_2408_07967_amd.render import Renderer
+    Rf = Renderer()
+    try:
+        small = scenes.make_scene("small")
+        gpu_frame(Rf, _gs(small), scenes.camera_for("small"), 64, 64, opts())
+        sc = scenes.make_scene("medium", P=200_000)
+        cam = scenes.camera_for("medium", 3, W=1280, H=720)
+        print("[parity] regrow: small 64x64, then medium P=200000 1280x720 twice", flush=True)
+        gsc = _gs(sc)
+        g1 = gpu_frame(Rf, gsc, cam, 1280, 720, opts())
+        o32 = orc.render(sc, cam, 1280, 720, opts(), mode="f32")
+        check_gauss_state(orc, g1, o32)
+        check_pairs(g1, o32)
+        g2 = gpu_frame(Rf, gsc, cam, 1280, 720, opts())
+        for k in ("rgb", "T", "last", "order", "tiles", "values", "ranges"):
+            assert np.array_equal(g1[k], g2[k]), k
+        torch.cuda.synchronize()
+    finally:
+        Rf.close()
+
+
 def test_plan_reports_the_pairs_of_the_render(orc, R, scenes):
     """fgs_plan runs only the first half: its pair count equals the FP32
     oracle's and the render's, and a render within its byte figure does not
