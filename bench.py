@@ -292,6 +292,8 @@ def main():
     ap.add_argument("--no-work-count", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-backward", action="store_true", help="skip the forward + backward timing")
+    ap.add_argument("--blend-variant", type=int, default=0, choices=(0, 1),
+                    help="0: LDS-batched blend (default); 1: prefetch-pipeline blend (same image)")
     ap.add_argument("--compare-binning", action="store_true",
                     help="also report pairs and stage times of the three binning modes")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
@@ -321,6 +323,7 @@ def main():
     torch.cuda.set_device(0)
     gsc = GaussianScene.from_numpy(sc, "cuda:0")
     R = Renderer(0)
+    R.set_blend_variant(args.blend_variant)
     opts = scenes.DEFAULT_OPTIONS
     out = torch.empty((3, H, W), dtype=torch.float32, device="cuda:0")
     stats = None
@@ -433,6 +436,7 @@ def main():
                scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
                config=dict(workload=wl["name"], gaussians=sc.P, width=W, height=H, sh_degree=sc.sh_degree,
                            tile=16, scene_format="prepared (view-independent precompute, done once per scene)",
+                           blend_variant="prefetch pipeline" if args.blend_variant else "LDS batches",
                            raw_params_frames_per_s=round(raw_fps, 3), prepare_ms=round(prep_ms, 2),
                            visible=int(stats["visible"]), pairs=int(stats["pairs"]),
                            big_rect_chunks=int(stats["big_chunks"]),

@@ -283,6 +283,21 @@ typedef struct {
 /* Select instrumentation flags for later fgs_render calls and clear the sums. */
 fgs_status fgs_set_instrumentation(fgs_context *ctx, int flags);
 
+/* ---- blend variants (Sec. 5.3.2) --------------------------------------------
+ * Two kernels render the same image, bit for bit:
+ *   FGS_BLEND_LDS_BATCHES (default): the workgroup of a tile stages batches of
+ *       its sorted list in LDS and each wavefront skips the entries whose
+ *       ellipse misses its half of the tile;
+ *   FGS_BLEND_PREFETCH: each wavefront walks the list on its own with a
+ *       software prefetch pipeline (the state of entry i + 1 and the index of
+ *       entry i + 2 in flight while entry i is blended), no LDS, no skipping.
+ * Applies to later fgs_render / fgs_render_prepared calls of ctx (the
+ * evaluation count of FGS_INSTR_WORK always uses the default).  Returns
+ * FGS_ERR_INVALID_ARGUMENT for another value. */
+#define FGS_BLEND_LDS_BATCHES 0
+#define FGS_BLEND_PREFETCH 1
+fgs_status fgs_set_blend_variant(fgs_context *ctx, int32_t variant);
+
 /* Wait for the last instrumented frame and return the sums. */
 fgs_status fgs_get_instrumentation(fgs_context *ctx, fgs_timings *out);
 

@@ -57,6 +57,8 @@ class FgsTimings(C.Structure):
 
 INSTR_STAGE_TIMES = 1
 INSTR_WORK = 2
+BLEND_LDS_BATCHES = 0
+BLEND_PREFETCH = 1
 
 
 class FgsServerConfig(C.Structure):
@@ -103,6 +105,7 @@ PROTOTYPES = {
     "fgs_frame_download": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_size_t]),
     "fgs_frame_stats": (C.c_int, [C.c_void_p, C.POINTER(FgsStats)]),
     "fgs_set_instrumentation": (C.c_int, [C.c_void_p, C.c_int]),
+    "fgs_set_blend_variant": (C.c_int, [C.c_void_p, C.c_int32]),
     "fgs_get_instrumentation": (C.c_int, [C.c_void_p, C.POINTER(FgsTimings)]),
     "fgs_plan": (C.c_int, [C.c_void_p, C.POINTER(FgsScene), C.POINTER(FgsCamera), C.c_int32, C.c_int32,
                            C.POINTER(FgsOptions), C.POINTER(C.c_int64), C.POINTER(C.c_size_t), C.c_void_p]),

@@ -177,9 +177,12 @@ void launch_single_range(uint2 *ranges, uint32_t n, const uint32_t *n_dev, hipSt
 
 // work: if non-null, the blend adds the number of list entries every pixel
 // examines (a separate, slower kernel instantiation)
+// variant: 0 the LDS-batched blend; 1 the prefetch-pipeline blend (same
+// image bit for bit; not with work).  nvalues, ngs: entries held by the
+// values and gs buffers (the bounds of the variant's buffer loads).
 void launch_blend(const GaussState *gs, const uint32_t *values, const uint2 *ranges, int W, int H,
                   const DevOptions &op, float *rgb, float *T, uint32_t *last, unsigned long long *work,
-                  hipStream_t s);
+                  int variant, uint32_t nvalues, uint32_t ngs, hipStream_t s);
 
 // Adjoint of the blend: accumulates per-Gaussian sums (9 planes of stride
 // acc_stride, cleared by the caller) from dL/dRGB, replaying each pixel's

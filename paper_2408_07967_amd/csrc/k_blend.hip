@@ -211,13 +211,133 @@ __global__ __launch_bounds__(kThreads) void k_blend(const GaussState *__restrict
     }
 }
 
+// Variant of the blend (selected per context): each wavefront walks its
+// tile's whole list on its own with a software prefetch pipeline, the form
+// of the paper's render loop (Sec. 5.3.2): while entry i is blended, the
+// state of entry i + 1 and the index of entry i + 2 are in flight (vector
+// buffer loads, which complete in order, so the wait for entry i's state
+// leaves the later loads outstanding).  Nothing is staged in LDS and no half
+// mask is kept: every entry is evaluated for the wavefront's 128 pixels; an
+// entry whose ellipse misses a pixel gives it alpha 0, which leaves colour,
+// transmittance and last contributor exactly as they were, so the image is
+// bit for bit the one of k_blend.
+template <bool kLast>
+__global__ __launch_bounds__(kThreads) void k_blend_prefetch(const GaussState *__restrict__ gs,
+                                                             const uint32_t *__restrict__ values,
+                                                             const uint2 *__restrict__ ranges, int W, int H,
+                                                             int tiles_x, uint32_t nvalues, uint32_t ngs,
+                                                             DevOptions op, float *__restrict__ rgb,
+                                                             float *__restrict__ Tout, uint32_t *__restrict__ last_out) {
+    const int tid = threadIdx.x, lane = tid & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);  // wave-uniform
+    const int tile = blockIdx.x;
+    const int tx = tile % tiles_x, ty = tile / tiles_x;
+    const int pi0 = tx * kTile + 2 * (lane & 7);
+    const int pj = ty * kTile + wave * 8 + (lane >> 3);
+    const bool in0 = pi0 < W && pj < H, in1 = pi0 + 1 < W && pj < H;
+    const float py = (float)pj + 0.5f;
+
+    const uint2 rg = ranges[tile];
+    const uint32_t start = rg.x, end = rg.y > rg.x ? rg.y : rg.x;  // an empty tile may hold start > end
+    Pixel p0{in0 ? (float)pi0 + 0.5f : kFar, 1.0f, 0.0f, 0.0f, 0.0f, 0u, 0u, !in0};
+    Pixel p1{in1 ? (float)pi0 + 1.5f : kFar, 1.0f, 0.0f, 0.0f, 0.0f, 0u, 0u, !in1};
+    bool wave_done = __ballot(!(p0.done && p1.done)) == 0;
+    const float amax = op.alpha_max + 0.0f;
+    const float tstop = op.T_stop;
+
+    if (!wave_done && start < end) {
+        // bounds-checked buffer loads with a wave-uniform offset
+        const __amdgpu_buffer_rsrc_t vrs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t *>(values), (short)0, (int)(nvalues * 4u), 0x00020000);
+        const __amdgpu_buffer_rsrc_t grs = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<GaussState *>(gs), (short)0, (int)(ngs * (uint32_t)sizeof(GaussState)), 0x00020000);
+        auto index = [&](uint32_t i) -> uint32_t {  // entry i's Gaussian (past the list: entry start's)
+            return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(vrs, (i < end ? i : start) * 4u, 0, 0);
+        };
+        auto state = [&](uint32_t g) -> GaussState {
+            GaussState st;
+            const uint32_t o = g * (uint32_t)sizeof(GaussState);
+            const auto v0 = __builtin_amdgcn_raw_buffer_load_b128(grs, o, 0, 0);
+            const auto v1 = __builtin_amdgcn_raw_buffer_load_b128(grs, o + 16u, 0, 0);
+            const auto v2 = __builtin_amdgcn_raw_buffer_load_b128(grs, o + 32u, 0, 0);
+            st.f0 = make_float4(__uint_as_float(v0[0]), __uint_as_float(v0[1]), __uint_as_float(v0[2]),
+                                __uint_as_float(v0[3]));
+            st.f1 = make_float4(__uint_as_float(v1[0]), __uint_as_float(v1[1]), __uint_as_float(v1[2]),
+                                __uint_as_float(v1[3]));
+            st.f2 = make_float4(__uint_as_float(v2[0]), __uint_as_float(v2[1]), __uint_as_float(v2[2]),
+                                __uint_as_float(v2[3]));
+            return st;
+        };
+        // one entry for both pixels of the lane; true once every pixel of the
+        // wavefront has stopped
+        auto blend_one = [&](const GaussState &gsx, uint32_t pos) {
+            float4 f0, f1;
+            float2 f2;
+            stage_gauss(gsx, f0, f1, f2);
+            const RowTerms rt = row_terms(f0, f1, py);
+            const float e0 = exponent_at(f0, rt, p0.x);
+            const float e1 = exponent_at(f0, rt, p1.x);
+            Step s0 = step(p0, e0, f1.y, amax, tstop);
+            Step s1 = step(p1, e1, f1.y, amax, tstop);
+            if (__ballot(s0.stop || s1.stop) != 0) {
+                if (s0.stop) stop_before<false>(p0, s0, pos);
+                if (s1.stop) stop_before<false>(p1, s1, pos);
+                wave_done = __ballot(!(p0.done && p1.done)) == 0;
+            }
+            apply<kLast>(p0, s0, f1, f2, pos);
+            apply<kLast>(p1, s1, f1, f2, pos);
+            return wave_done;
+        };
+        // two entries per trip, so that the prefetched values alternate
+        // between two register sets instead of being copied
+        uint32_t i = start;
+        uint32_t inext = index(i + 1);
+        GaussState sa = state(index(i)), sb;
+        for (;;) {
+            sb = state(inext);                // entry i + 1
+            const uint32_t inn = index(i + 2);
+            if (blend_one(sa, i - start) || ++i >= end) break;
+            sa = state(inn);                  // entry i + 1
+            const uint32_t in3 = index(i + 2);
+            if (blend_one(sb, i - start) || ++i >= end) break;
+            inext = in3;
+        }
+    }
+
+    const size_t hw = (size_t)W * H;
+    const size_t q = (size_t)pj * W + pi0;
+    if (in0) {
+        rgb[q] = p0.c0 + p0.T * op.bg[0];
+        rgb[hw + q] = p0.c1 + p0.T * op.bg[1];
+        rgb[2 * hw + q] = p0.c2 + p0.T * op.bg[2];
+        if (Tout) Tout[q] = p0.T;
+        if (kLast && last_out) last_out[q] = p0.last;
+    }
+    if (in1) {
+        rgb[q + 1] = p1.c0 + p1.T * op.bg[0];
+        rgb[hw + q + 1] = p1.c1 + p1.T * op.bg[1];
+        rgb[2 * hw + q + 1] = p1.c2 + p1.T * op.bg[2];
+        if (Tout) Tout[q + 1] = p1.T;
+        if (kLast && last_out) last_out[q + 1] = p1.last;
+    }
+}
+
 }  // namespace
 
 void launch_blend(const GaussState *gs, const uint32_t *values, const uint2 *ranges, int W, int H,
                   const DevOptions &op, float *rgb, float *T, uint32_t *last, unsigned long long *work,
-                  hipStream_t s) {
+                  int variant, uint32_t nvalues, uint32_t ngs, hipStream_t s) {
     const int tiles_x = (W + kTile - 1) / kTile, tiles_y = (H + kTile - 1) / kTile;
     const dim3 grid((unsigned)(tiles_x * tiles_y)), block(kThreads);
+    if (variant == 1 && !work && nvalues > 0 && ngs > 0) {
+        if (last)
+            hipLaunchKernelGGL((k_blend_prefetch<true>), grid, block, 0, s, gs, values, ranges, W, H, tiles_x, nvalues,
+                               ngs, op, rgb, T, last);
+        else
+            hipLaunchKernelGGL((k_blend_prefetch<false>), grid, block, 0, s, gs, values, ranges, W, H, tiles_x,
+                               nvalues, ngs, op, rgb, T, last);
+        return;
+    }
     if (work)
         hipLaunchKernelGGL((k_blend<true, true>), grid, block, 0, s, gs, values, ranges, W, H, tiles_x, op, rgb, T,
                            last, work);

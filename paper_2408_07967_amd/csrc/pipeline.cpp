@@ -320,7 +320,7 @@ void enqueue_front(const DevScene &sc, const DevPrepared *pp, const DevCamera &c
 
 bool enqueue_back(int W, int H, const DevOptions &op, uint32_t P, FrameBuffers &fb, ChunkList &ch, SortScratch &ss,
                   FrameCounters *fc, float *rgb, float *T, uint32_t *last, unsigned long long *work, hipStream_t s,
-                  const StageMarks &mk) {
+                  const StageMarks &mk, int blend_variant) {
     const int tiles_x = (W + kTile - 1) / kTile, tiles_y = (H + kTile - 1) / kTile;
     const uint32_t ntiles = (uint32_t)tiles_x * (uint32_t)tiles_y;
     const uint32_t chunk_cap = (uint32_t)std::min<size_t>(ch.cap, 0xffffffffu);
@@ -355,7 +355,10 @@ bool enqueue_back(int W, int H, const DevOptions &op, uint32_t P, FrameBuffers &
     if (npass == 0) launch_single_range(fb.ranges, pair_cap, &fc->pairs, s);
     mk.mark(6, s);
     // ---- stage 4: blend -------------------------------------------------------------
-    launch_blend(fb.gs, vi, fb.ranges, W, H, op, rgb, T, last, work, s);
+    // (the variant's buffer loads take 32-bit byte offsets)
+    const bool fits = fb.capN <= 0x7fffffffu / 4u && fb.capP <= 0x7fffffffu / sizeof(GaussState);
+    launch_blend(fb.gs, vi, fb.ranges, W, H, op, rgb, T, last, work, fits ? blend_variant : 0, (uint32_t)fb.capN,
+                 (uint32_t)fb.capP, s);
     mk.mark(7, s);
     return ki == fb.tk_a;
 }

@@ -137,8 +137,9 @@ void free_prepared(PreparedBuffers &pb);
 // capacity, so the sequence holds no host dependency and can be captured in
 // a graph.  P bounds the visible count; fb.capN bounds the pair count.
 // Returns true if the sorted tile ids end in tk_a (else tk_b).
+// blend_variant: see launch_blend.
 bool enqueue_back(int W, int H, const DevOptions &op, uint32_t P, FrameBuffers &fb, ChunkList &ch, SortScratch &ss,
                   FrameCounters *fc, float *rgb, float *T, uint32_t *last, unsigned long long *work, hipStream_t s,
-                  const StageMarks &mk);
+                  const StageMarks &mk, int blend_variant = 0);
 
 }  // namespace fgs

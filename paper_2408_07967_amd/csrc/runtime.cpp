@@ -57,6 +57,7 @@ struct fgs_context {
     ChunkList ch;
     // instrumentation
     int instr = 0;
+    int blend_variant = 0;  // FGS_BLEND_*
     hipEvent_t ev[2][8] = {};
     int ev_pending = -1;  // event set of the last instrumented frame not yet folded in
     int ev_next = 0;
@@ -315,7 +316,7 @@ fgs_status render_impl(fgs_context *ctx, const fgs_scene *scene, const fgs_prepa
         spec_cap = 0;
         if (!plan && !work && fb.capN > 0) {
             tiles_in_a = enqueue_back(W, H, dop, (uint32_t)P, fb, ctx->ch, ctx->ss, ctx->fc_dev, out_rgb, Tdst, Ldst,
-                                      nullptr, s, mk);
+                                      nullptr, s, mk, ctx->blend_variant);
             HIP_TRY(ctx, hipGetLastError());
             spec_cap = fb.capN;
         }
@@ -370,7 +371,7 @@ fgs_status render_impl(fgs_context *ctx, const fgs_scene *scene, const fgs_prepa
         if (spec_cap) HIP_TRY(ctx, hipStreamSynchronize(s));
         HIP_TRY(ctx, ensure_pairs(fb, N));
         tiles_in_a = enqueue_back(W, H, dop, (uint32_t)P, fb, ctx->ch, ctx->ss, ctx->fc_dev, out_rgb, Tdst, Ldst,
-                                  work, s, mk);
+                                  work, s, mk, ctx->blend_variant);
     }
     HIP_TRY(ctx, hipGetLastError());
     if (timed) {
@@ -634,6 +635,14 @@ fgs_status fgs_set_instrumentation(fgs_context *ctx, int flags) {
     ctx->instr = flags;
     ctx->ev_pending = -1;
     ctx->acc = fgs_timings{};
+    return FGS_OK;
+}
+
+fgs_status fgs_set_blend_variant(fgs_context *ctx, int32_t variant) {
+    if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARGUMENT, "context is NULL");
+    if (variant != FGS_BLEND_LDS_BATCHES && variant != FGS_BLEND_PREFETCH)
+        return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "unknown blend variant %d", variant);
+    ctx->blend_variant = variant;
     return FGS_OK;
 }
 

@@ -145,6 +145,11 @@ class Renderer:
     def set_instrumentation(self, flags):
         self.ctx.check(B.lib().fgs_set_instrumentation(self.ctx.handle, int(flags)))
 
+    def set_blend_variant(self, variant):
+        """B.BLEND_LDS_BATCHES (default) or B.BLEND_PREFETCH: two blend kernels
+        that render the same image bit for bit."""
+        self.ctx.check(B.lib().fgs_set_blend_variant(self.ctx.handle, int(variant)))
+
     def instrumentation(self):
         t = B.FgsTimings()
         self.ctx.check(B.lib().fgs_get_instrumentation(self.ctx.handle, C.byref(t)))

@@ -116,6 +116,7 @@ def test_null_arguments_rejected_without_device():
     assert B.lib().fgs_frame_release(None, None) == B.FGS_OK
     assert B.lib().fgs_frame_field_bytes(None, 0) == 0
     assert B.lib().fgs_scratch_bytes(None) == 0
+    assert B.lib().fgs_set_blend_variant(None, B.BLEND_PREFETCH) == B.FGS_ERR_INVALID_ARGUMENT
 
 
 def test_status_strings():

@@ -222,6 +222,37 @@ def test_backward_of_prepared_frame_not_supported(R, scenes):
         R.release_prepared(h)
 
 
+@pytest.mark.parametrize("case", ["small", "random14", "city1M-540p"])
+def test_prefetch_blend_variant_is_bit_identical(orc, R, scenes, case):
+    """The prefetch-pipeline blend (no LDS staging, no half masks) renders the
+    image, T_final and last contributor of the default blend bit for bit, and
+    both meet the oracle's bar."""
+    from paper_2408_07967_amd import binding as B
+    if case == "small":
+        sc, cam, W, H = scenes.make_scene("small"), scenes.camera_for("small"), 256, 256
+    elif case == "random14":
+        rng = np.random.default_rng(14)
+        sc = random_scene(rng, 20000, ls_mu=-3.2, sh_degree=3)
+        W, H = 517, 301
+        cam = identity_camera(W, H, 0.9 * max(W, H))
+    else:
+        sc = scenes.make_scene("city", P=1_000_000)
+        W, H = 960, 540
+        cam = scenes.camera_for("city", W=W, H=H)
+    print(f"[parity] blend variants: {case} P={sc.P} {W}x{H}", flush=True)
+    gsc = _gs(sc)
+    a = gpu_frame(R, gsc, cam, W, H, opts())
+    R.set_blend_variant(B.BLEND_PREFETCH)
+    try:
+        b = gpu_frame(R, gsc, cam, W, H, opts())
+    finally:
+        R.set_blend_variant(B.BLEND_LDS_BATCHES)
+    for k in ("rgb", "T", "last", "tiles", "values", "ranges"):
+        assert np.array_equal(np.asarray(a[k]).view(np.uint32), np.asarray(b[k]).view(np.uint32)), k
+    if case != "city1M-540p":
+        check_image(b, orc.render(sc, cam, W, H, opts(), mode="f64"), case)
+
+
 def test_deterministic_repeat(orc, R, scenes):
     sc = scenes.make_scene("medium", P=100_000)
     cam = scenes.camera_for("medium", 2)
