@@ -1,6 +1,7 @@
 """GPU parity at the full size of the timed workload: the 10M-Gaussian city
 scene at 3840x2160, rendered from the prepared scene with the default options,
-exactly as the benchmark renders it.  The oracle finishes this frame in a few
+exactly as the benchmark renders it (and from the raw parameters, which must
+give the same frame bit for bit).  The oracle finishes this frame in a few
 seconds, so every output is compared, not a sample: per-Gaussian state, depth
 order, all sorted pairs and tile ranges bit-exact against the FP32 oracle;
 image, final transmittance and last contributor against the FP64 oracle.
@@ -42,6 +43,7 @@ def test_city_10M_4k_prepared_full_size(orc, scenes):
     h = R.prepare(gsc, o)
     try:
         g = gpu_frame(R, gsc, cam, W, H, o, prepared=h)
+        graw = gpu_frame(R, gsc, cam, W, H, o)  # the raw-parameter path, same frame
     finally:
         R.release_prepared(h)
         del gsc
@@ -51,9 +53,12 @@ def test_city_10M_4k_prepared_full_size(orc, scenes):
 
     o32 = orc.render(sc, cam, W, H, o, mode="f32")
     _log(f"oracle binary32 frame done ({time.perf_counter() - t0:.1f}s)")
-    check_gauss_state(orc, g, o32)
-    check_pairs(g, o32)
-    _log("state, depth order, pairs and ranges bit-exact")
+    for tag, gx in (("prepared", g), ("raw parameters", graw)):
+        check_gauss_state(orc, gx, o32)
+        check_pairs(gx, o32)
+        _log(f"{tag}: state, depth order, pairs and ranges bit-exact")
+    for k in ("rgb", "T", "last"):
+        assert np.array_equal(np.asarray(g[k]).view(np.uint32), np.asarray(graw[k]).view(np.uint32)), k
 
     o64 = orc.render(sc, cam, W, H, o, mode="f64")
     _log(f"oracle binary64 frame done ({time.perf_counter() - t0:.1f}s)")
