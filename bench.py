@@ -231,6 +231,46 @@ def differentiation_leg(steps):
                 backward_ms=round(bwd / steps * 1e3, 3), pairs=int(out["stats"]["pairs"]))
 
 
+def batch_leg(R, gsc, prep, W, H, opts, ncams, steps):
+    """Multi-camera batches of the resident scene: ncams viewpoints of a
+    camera rig (the workload camera with its eye moved sideways in 2 m steps,
+    same orientation) rendered by one batch call, against the same cameras
+    rendered one call each.  Both sides have every input resident in HBM;
+    frames/s counts camera images."""
+    import math
+    import numpy as np
+    import torch
+    from paper_2408_07967_amd import scenes
+    base = scenes.camera_for("city", W=W, H=H)
+    cams = []
+    for i in range(ncams):
+        dx = 2.0 * (i - (ncams - 1) / 2.0)
+        eye = np.asarray(base.eye, np.float64) + np.array([dx, 0.0, 0.0])
+        fwd = np.array([0.0, math.sin(math.radians(-30.0)), math.cos(math.radians(-30.0))])
+        cams.append(scenes.look_at(eye, eye + fwd, W, H, 70.0))
+    outs = [torch.empty((3, H, W), dtype=torch.float32, device="cuda:0") for _ in cams]
+    for _ in range(2):
+        got = R.render_batch(prep, gsc, cams, W, H, opts)
+        for c, o in zip(cams, outs):
+            R.render(gsc, c, W, H, opts, out=o, prepared=prep)
+    torch.cuda.synchronize()
+    same = all(torch.equal(g["rgb"].view(torch.int32), o.view(torch.int32)) for g, o in zip(got, outs))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for c, o in zip(cams, outs):
+            R.render(gsc, c, W, H, opts, out=o, prepared=prep)
+    torch.cuda.synchronize()
+    single = steps * ncams / (time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        got = R.render_batch(prep, gsc, cams, W, H, opts)
+    torch.cuda.synchronize()
+    batched = steps * ncams / (time.perf_counter() - t0)
+    return dict(cameras=ncams, rig="eye moved sideways in 2 m steps", batched_frames_per_s=round(batched, 2),
+                one_call_per_camera_frames_per_s=round(single, 2), speedup=round(batched / single, 4),
+                union_candidates=int(got[0]["stats"]["candidates"]), bit_identical=bool(same))
+
+
 def compare_binning(steps):
     """Pair redundancy of the binning modes (the paper's pair-count and
     stage-breakdown comparison, on the synthetic workloads): exact ellipse/tile
@@ -299,6 +339,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="length of the Poisson request trace (the full serving workload is 60 s)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--batch-cameras", type=int, default=4,
+                    help="cameras of the multi-camera batch leg (0 skips it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, run one device copy of 256 MiB (read 256 MiB, write 256 MiB) "
                          "whose FETCH_SIZE / WRITE_SIZE counters scale the blend kernel's counters")
@@ -420,6 +462,10 @@ def main():
         del ref_rgb, f32_rgb
         log(f"[bench] image parity {parity}")
 
+    batch = None
+    if args.batch_cameras > 0:
+        batch = batch_leg(R, gsc, prep, W, H, opts, args.batch_cameras, max(3, args.steps // 10))
+        log(f"[bench] multi-camera batch: {batch}")
     R.release_prepared(prep)
     R.close()
     del gsc, out
@@ -443,7 +489,8 @@ def main():
                            candidates=int(stats["candidates"]),
                            pairs_per_s=round(stats["pairs"] * fps, 1), stage_ms=stage_ms,
                            single_frame_ms=frame_ms),
-               roofline=roof, cpu_baseline=cpu, parity=parity, serving=serving, differentiation=differentiation)
+               roofline=roof, cpu_baseline=cpu, parity=parity, serving=serving, differentiation=differentiation,
+               multi_camera=batch)
     if binning_modes is not None:
         res["binning_modes"] = binning_modes
     print(json.dumps(res), flush=True)

@@ -207,6 +207,30 @@ fgs_status fgs_prepared_release(fgs_context *ctx, fgs_prepared *prepared);
 fgs_status fgs_render_prepared(fgs_context *ctx, const fgs_prepared *prepared, const fgs_camera *cam, int32_t W,
                                int32_t H, const fgs_options *opt, float *out_rgb, float *out_T, uint32_t *out_last,
                                fgs_frame **saved, fgs_stats *stats, void *stream);
+/* Several viewpoints of one prepared scene in one call (Sec. 5.3.1 carried
+ * one step further: the preprocessing of every viewpoint of the batch shares
+ * one pass).  One cull keeps the union of the cameras' candidates and one
+ * preprocess pass walks that list, evaluating each Gaussian for every camera
+ * in turn, so its precompute comes from HBM once per batch, not once per
+ * camera; sorting and blending then run per camera.
+ *   cams      host, ncams cameras, 1 <= ncams <= FGS_MAX_BATCH_CAMERAS; one
+ *             W, H and opt (as for fgs_render_prepared) for all of them.
+ *   out_rgb   host array of ncams device pointers, each [3][H][W] float.
+ *   out_T, out_last  NULL, or host arrays of ncams device pointers (an
+ *             entry may be NULL), [H][W] float / uint32.
+ *   stats     NULL or host array of ncams fgs_stats.
+ * Camera c's image, T_final and last contributor are bit for bit those of
+ * fgs_render_prepared for camera c alone.  No frame is saved (a batch has
+ * no backward) and a batch collects neither stage times nor work counts.
+ * Device memory: one set of frame buffers per camera slot, kept by the
+ * context for later batches.  Enqueued on `stream`; like fgs_render_prepared
+ * it returns once the frame counters are on the host.  Errors as for
+ * fgs_render_prepared, and INVALID_ARGUMENT for ncams out of range. */
+#define FGS_MAX_BATCH_CAMERAS 8
+fgs_status fgs_render_prepared_batch(fgs_context *ctx, const fgs_prepared *prepared, const fgs_camera *cams,
+                                     int32_t ncams, int32_t W, int32_t H, const fgs_options *opt,
+                                     float *const *out_rgb, float *const *out_T, uint32_t *const *out_last,
+                                     fgs_stats *stats, void *stream);
 
 /* ---- backward ----------------------------------------------------------- */
 

@@ -59,6 +59,7 @@ INSTR_STAGE_TIMES = 1
 INSTR_WORK = 2
 BLEND_LDS_BATCHES = 0
 BLEND_PREFETCH = 1
+MAX_BATCH_CAMERAS = 8
 
 
 class FgsServerConfig(C.Structure):
@@ -115,6 +116,10 @@ PROTOTYPES = {
     "fgs_render_prepared": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(FgsCamera), C.c_int32, C.c_int32,
                                       C.POINTER(FgsOptions), C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.POINTER(C.c_void_p), C.POINTER(FgsStats), C.c_void_p]),
+    "fgs_render_prepared_batch": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(FgsCamera), C.c_int32, C.c_int32,
+                                            C.c_int32, C.POINTER(FgsOptions), C.POINTER(C.c_void_p),
+                                            C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(FgsStats),
+                                            C.c_void_p]),
     "fgs_clock_ns": (C.c_int64, []),
     "fgs_server_create": (C.c_int, [C.c_int, C.POINTER(FgsScene), C.POINTER(FgsOptions),
                                     C.POINTER(FgsServerConfig), C.POINTER(C.c_void_p)]),

@@ -115,6 +115,35 @@ void launch_preprocess(const DevScene &sc, const DevPrepared *pp, const DevCamer
                        uint32_t *cand, uint32_t *seg_count, uint32_t *gmap, uint2 *chunks, uint32_t chunk_cap,
                        FrameCounters *fc, uint32_t *gsum_clear, hipStream_t s);
 
+// Multi-camera batch over one prepared scene (Sec. 5.3.1 applied to several
+// viewpoints at once): one cull keeps the union of the cameras' candidates,
+// and one preprocess pass over that list reads each Gaussian's precompute
+// once from HBM and evaluates it for every camera in turn.  Camera c's
+// outputs are those launch_preprocess would write for it alone over the
+// union list (a candidate culled for camera c gets key kInvalidKey and count
+// 0), so every later stage runs per camera unchanged.
+constexpr int kMaxCams = 8;  // FGS_MAX_BATCH_CAMERAS
+struct CamOut {
+    DevCamera cam;
+    GaussState *gs;
+    uint4 *rect;
+    uint32_t *count;
+    uint8_t *count8;
+    uint4 *erec;
+    uint32_t *dkey;
+    uint2 *chunks;
+    FrameCounters *fc;     // this camera's counters (cleared by the cull)
+    uint32_t *gsum_clear;  // this camera's first depth pass group sums
+    uint32_t chunk_cap;
+};
+struct MultiOut {
+    CamOut c[kMaxCams];
+    int n;  // cameras in the batch, 1..kMaxCams
+};
+// cand, seg_count, gmap: as for launch_preprocess (one union list).
+void launch_preprocess_multi(const DevScene &sc, const DevPrepared &pp, const MultiOut &mo, const DevOptions &op,
+                             int W, int H, uint32_t *cand, uint32_t *seg_count, uint32_t *gmap, hipStream_t s);
+
 // View-independent precompute (opacity, 3D covariance, k^2, log2 opacity,
 // Gaussian-major SH) for options op (alpha_min and cap_3sigma).
 void launch_prepare(const DevScene &sc, const DevOptions &op, float4 *pos_o, float4 *cov, float *sh, float2 *bnd,

@@ -303,23 +303,70 @@ __device__ __forceinline__ void cull_range(int64_t P, uint32_t b, int64_t *lo, i
     if (*lo > *hi) *lo = *hi;
 }
 
+// The cull's keep test of Gaussian g (position and opacity p4) for one
+// camera.
+__device__ __forceinline__ bool cull_keep(const DevPrepared &pp, int64_t g, const float4 &p4, const DevCamera &cam,
+                                          const DevOptions &op, int W, int H) {
+    const float *R = cam.R;
+    const float tx = ((R[0] * p4.x + R[1] * p4.y) + R[2] * p4.z) + cam.t[0];
+    const float ty = ((R[3] * p4.x + R[4] * p4.y) + R[5] * p4.z) + cam.t[1];
+    const float tz = ((R[6] * p4.x + R[7] * p4.y) + R[8] * p4.z) + cam.t[2];
+    bool keep = tz > cam.near_z && p4.w > op.alpha_min && isfinite(p4.x) && isfinite(p4.y) && isfinite(p4.z);
+    if (keep) {
+        const float2 b = pp.bnd[g];
+        const float iz = 1.0f / tz;
+        const float xt = tx * iz, yt = ty * iz;
+        const float limx = op.jac_clip * (0.5f * (float)W / cam.fx);
+        const float limy = op.jac_clip * (0.5f * (float)H / cam.fy);
+        const float xc = fminf(fmaxf(xt, -limx), limx), yc = fminf(fmaxf(yt, -limy), limy);
+        const float J00 = cam.fx * iz, J02 = -cam.fx * xc * iz, J11 = cam.fy * iz, J12 = -cam.fy * yc * iz;
+        float n0 = 0.0f, n1 = 0.0f;
+        for (int j = 0; j < 3; ++j) {
+            const float t0 = J00 * R[j] + J02 * R[6 + j], t1 = J11 * R[3 + j] + J12 * R[6 + j];
+            n0 += t0 * t0;
+            n1 += t1 * t1;
+        }
+        float hx, hy;
+        if (op.binning == 2) {
+            // square of radius ceil(3 sqrt(lambda_max(Sigma'))), lambda_max <= trace
+            hx = sqrtf(9.0f * ((n0 + n1) * b.x + op.dilation)) * 1.001f + 3.0f;
+            hy = hx;
+        } else {
+            hx = sqrtf(b.y * (n0 * b.x + op.dilation)) * 1.001f + 3.0f;
+            hy = sqrtf(b.y * (n1 * b.x + op.dilation)) * 1.001f + 3.0f;
+        }
+        const float u = cam.fx * xt + cam.cx, v = cam.fy * yt + cam.cy;
+        // drop only what is certainly off the image (a NaN keeps it)
+        const bool out = (u + hx < 0.0f) || (u - hx > (float)W) || (v + hy < 0.0f) || (v - hy > (float)H);
+        keep = !out;
+    }
+    return keep;
+}
+
 // Cull of a prepared scene: reads 24 bytes per Gaussian and keeps those in
 // front of the near plane, above the opacity threshold and whose extent may
 // reach a pixel sample.  The extent test is conservative: Sigma'_xx =
 // t0^T Sigma t0 <= |t0|^2 trace(Sigma) for the row t0 of T = J R_cam, so
 // sqrt(k^2 (|t0|^2 trace + dilation)) (or the 3 sigma radius plus one for the
 // square box) bounds the half-width of the box, and a 0.1 % + 3 px margin
-// covers rounding.  Everything it drops the exact path would cull too.  Each
+// covers rounding.  Everything it drops the exact path would cull too.
+// kMulti: the union over the cameras of mo, whose counters it clears.  Each
 // workgroup owns a contiguous range of Gaussians and lists its candidates in
 // index order at the start of that range (no global atomics).
+template <bool kMulti>
 __global__ __launch_bounds__(kBlock) void k_cull(DevScene sc, DevPrepared pp, DevCamera cam, DevOptions op, int W,
                                                  int H, uint32_t *__restrict__ cand, uint32_t *__restrict__ seg_count,
-                                                 FrameCounters *fc) {
+                                                 FrameCounters *fc, MultiOut mo) {
     __shared__ uint32_t s_w[kBlock / kWave];
     // the frame's counters start at zero (the preprocess, next on the
     // stream, is their first user)
     static_assert(sizeof(FrameCounters) / 4 <= kBlock, "counters cleared by one workgroup");
-    if (blockIdx.x == 0 && threadIdx.x < sizeof(FrameCounters) / 4) reinterpret_cast<uint32_t *>(fc)[threadIdx.x] = 0;
+    if constexpr (kMulti) {
+        if (blockIdx.x == 0 && threadIdx.x < sizeof(FrameCounters) / 4)
+            for (int c = 0; c < mo.n; ++c) reinterpret_cast<uint32_t *>(mo.c[c].fc)[threadIdx.x] = 0;
+    } else {
+        if (blockIdx.x == 0 && threadIdx.x < sizeof(FrameCounters) / 4) reinterpret_cast<uint32_t *>(fc)[threadIdx.x] = 0;
+    }
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     int64_t lo, hi;
     cull_range(sc.P, blockIdx.x, &lo, &hi);
@@ -329,38 +376,12 @@ __global__ __launch_bounds__(kBlock) void k_cull(DevScene sc, DevPrepared pp, De
         bool keep = false;
         if (g < hi) {
             const float4 p4 = pp.pos_o[g];
-            const float *R = cam.R;
-            const float tx = ((R[0] * p4.x + R[1] * p4.y) + R[2] * p4.z) + cam.t[0];
-            const float ty = ((R[3] * p4.x + R[4] * p4.y) + R[5] * p4.z) + cam.t[1];
-            const float tz = ((R[6] * p4.x + R[7] * p4.y) + R[8] * p4.z) + cam.t[2];
-            keep = tz > cam.near_z && p4.w > op.alpha_min && isfinite(p4.x) && isfinite(p4.y) && isfinite(p4.z);
-            if (keep) {
-                const float2 b = pp.bnd[g];
-                const float iz = 1.0f / tz;
-                const float xt = tx * iz, yt = ty * iz;
-                const float limx = op.jac_clip * (0.5f * (float)W / cam.fx);
-                const float limy = op.jac_clip * (0.5f * (float)H / cam.fy);
-                const float xc = fminf(fmaxf(xt, -limx), limx), yc = fminf(fmaxf(yt, -limy), limy);
-                const float J00 = cam.fx * iz, J02 = -cam.fx * xc * iz, J11 = cam.fy * iz, J12 = -cam.fy * yc * iz;
-                float n0 = 0.0f, n1 = 0.0f;
-                for (int j = 0; j < 3; ++j) {
-                    const float t0 = J00 * R[j] + J02 * R[6 + j], t1 = J11 * R[3 + j] + J12 * R[6 + j];
-                    n0 += t0 * t0;
-                    n1 += t1 * t1;
-                }
-                float hx, hy;
-                if (op.binning == 2) {
-                    // square of radius ceil(3 sqrt(lambda_max(Sigma'))), lambda_max <= trace
-                    hx = sqrtf(9.0f * ((n0 + n1) * b.x + op.dilation)) * 1.001f + 3.0f;
-                    hy = hx;
-                } else {
-                    hx = sqrtf(b.y * (n0 * b.x + op.dilation)) * 1.001f + 3.0f;
-                    hy = sqrtf(b.y * (n1 * b.x + op.dilation)) * 1.001f + 3.0f;
-                }
-                const float u = cam.fx * xt + cam.cx, v = cam.fy * yt + cam.cy;
-                // drop only what is certainly off the image (a NaN keeps it)
-                const bool out = (u + hx < 0.0f) || (u - hx > (float)W) || (v + hy < 0.0f) || (v - hy > (float)H);
-                keep = !out;
+            if constexpr (kMulti) {
+                // union of the cameras' candidates: the exact path of each
+                // camera culls the rest
+                for (int c = 0; c < mo.n && !keep; ++c) keep = cull_keep(pp, g, p4, mo.c[c].cam, op, W, H);
+            } else {
+                keep = cull_keep(pp, g, p4, cam, op, W, H);
             }
         }
         // ordered compaction into this workgroup's own segment
@@ -380,7 +401,12 @@ __global__ __launch_bounds__(kBlock) void k_cull(DevScene sc, DevPrepared pp, De
     if (threadIdx.x == 0) seg_count[blockIdx.x] = n;
 }
 
-template <bool kPrep>
+// kMulti (with kPrep): every camera of mo in turn over the union candidate
+// list, each with its own outputs and counters (the camera and output
+// arguments are then unused); the repeated reads of a Gaussian's precompute
+// for the second and later cameras follow the first within the same
+// wavefront and hit the caches.
+template <bool kPrep, bool kMulti = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_preprocess(DevScene sc, DevPrepared pp, DevCamera cam, DevOptions op,
                                                        int W, int H, GaussState *__restrict__ gs,
                                                        uint4 *__restrict__ rect, uint32_t *__restrict__ count,
@@ -390,10 +416,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                                                        const uint32_t *__restrict__ seg_count,
                                                        uint32_t *__restrict__ gmap, uint2 *__restrict__ chunks,
                                                        uint32_t chunk_cap, FrameCounters *fc,
-                                                       uint32_t *__restrict__ gsum_clear) {
+                                                       uint32_t *__restrict__ gsum_clear, MultiOut mo) {
+    static_assert(!kMulti || kPrep, "a batch walks a union candidate list");
     // the first depth pass's group sums start at zero
-    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < (uint32_t)kGsumWords; i += gridDim.x * kBlock)
-        gsum_clear[i] = 0;
+    if constexpr (kMulti) {
+        for (int c = 0; c < mo.n; ++c)
+            for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < (uint32_t)kGsumWords; i += gridDim.x * kBlock)
+                mo.c[c].gsum_clear[i] = 0;
+    } else {
+        for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < (uint32_t)kGsumWords; i += gridDim.x * kBlock)
+            gsum_clear[i] = 0;
+    }
     // Persistent grid: each workgroup walks batches of 256 Gaussians.  Every
     // wavefront keeps its own visible count and pending chunk reservations
     // (LDS), so the batch loop has no workgroup barrier and global atomics
@@ -405,11 +438,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const int wv = threadIdx.x / kWave;  // this lane's wavefront
     uint32_t w_nbig = 0, w_nch = 0;      // wave-uniform: pending entries and their chunks
     uint32_t w_vis = 0;                  // wave-uniform: visible Gaussians so far
+    __shared__ uint32_t s_vis[kMulti ? kBlock / kWave : 1][kMulti ? kMaxCams : 1];  // per camera (kMulti)
+    if constexpr (kMulti) {
+        if ((threadIdx.x & (kWave - 1)) == 0)
+            for (int c = 0; c < kMaxCams; ++c) s_vis[wv][c] = 0;
+    }
 
     // reserve chunk-list space for the wavefront's pending large Gaussians
     // and write their entries (g, first chunk); on overflow only flag it
     // (the host resizes the list and renders the frame again)
-    auto flush_big = [&](int ln) {
+    auto flush_big = [&](int ln, FrameCounters *fc, uint2 *__restrict__ chunks, uint32_t chunk_cap,
+                         uint4 *__restrict__ erec) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -465,7 +504,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         }
         __syncthreads();
     }
-    if constexpr (kPrep) {
+    if constexpr (kMulti) {
+        if (blockIdx.x == 0 && threadIdx.x == 0)
+            for (int c = 0; c < mo.n; ++c) mo.c[c].fc->ncand = ncand;
+    } else if constexpr (kPrep) {
         if (blockIdx.x == 0 && threadIdx.x == 0) fc->ncand = ncand;
     }
     // outputs of a prepared scene go to the candidate's list position (dense,
@@ -494,6 +536,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         if (ii < sc.P) g = ii;
         batch += gridDim.x;
     }
+    const int ncams = kMulti ? mo.n : 1;
+    for (int ci = 0; ci < ncams; ++ci) {
+    // this camera and its outputs
+    const DevCamera &cm = kMulti ? mo.c[ci].cam : cam;
+    GaussState *__restrict__ const gs_c = kMulti ? mo.c[ci].gs : gs;
+    uint4 *__restrict__ const rect_c = kMulti ? mo.c[ci].rect : rect;
+    uint32_t *__restrict__ const count_c = kMulti ? mo.c[ci].count : count;
+    uint8_t *__restrict__ const count8_c = kMulti ? mo.c[ci].count8 : count8;
+    uint4 *__restrict__ const erec_c = kMulti ? mo.c[ci].erec : erec;
+    uint32_t *__restrict__ const dkey_c = kMulti ? mo.c[ci].dkey : dkey;
     const int64_t st = sc.stride;
     bool valid = false;
     float u = 0, v = 0, A = 0, B = 0, C = 0, k2 = 0, o = 0, tz = 0, l2o = 0;
@@ -513,14 +565,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             my = sc.means[st + g];
             mz = sc.means[2 * st + g];
         }
-        const float *R = cam.R;
+        const float *R = cm.R;
         // view transform (p_view)
-        const float tx = ((R[0] * mx + R[1] * my) + R[2] * mz) + cam.t[0];
-        const float ty = ((R[3] * mx + R[4] * my) + R[5] * mz) + cam.t[1];
-        tz = ((R[6] * mx + R[7] * my) + R[8] * mz) + cam.t[2];
+        const float tx = ((R[0] * mx + R[1] * my) + R[2] * mz) + cm.t[0];
+        const float ty = ((R[3] * mx + R[4] * my) + R[5] * mz) + cm.t[1];
+        tz = ((R[6] * mx + R[7] * my) + R[8] * mz) + cm.t[2];
         // near plane (Alg. 4: p_view.z > 0.2); the remaining attributes are
         // read only for Gaussians in front of the camera
-        if (tz > cam.near_z && isfinite(mx) && isfinite(my) && isfinite(mz)) {
+        if (tz > cm.near_z && isfinite(mx) && isfinite(my) && isfinite(mz)) {
             bool ok = false;
             float S[6] = {0, 0, 0, 0, 0, 0};
             float log2o = 0.0f;
@@ -555,15 +607,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 {
                     // pinhole projection (project + ndc2Pix)
                     const float xt = tx / tz, yt = ty / tz;
-                    u = cam.fx * xt + cam.cx;
-                    v = cam.fy * yt + cam.cy;
+                    u = cm.fx * xt + cm.cx;
+                    v = cm.fy * yt + cm.cy;
                     // EWA Jacobian with the view-direction clamp
-                    const float limx = op.jac_clip * ((0.5f * (float)W) / cam.fx);
-                    const float limy = op.jac_clip * ((0.5f * (float)H) / cam.fy);
+                    const float limx = op.jac_clip * ((0.5f * (float)W) / cm.fx);
+                    const float limy = op.jac_clip * ((0.5f * (float)H) / cm.fy);
                     const float xc = clampf_(xt, -limx, limx);
                     const float yc = clampf_(yt, -limy, limy);
-                    const float J00 = cam.fx / tz, J02 = -((cam.fx * xc) / tz);
-                    const float J11 = cam.fy / tz, J12 = -((cam.fy * yc) / tz);
+                    const float J00 = cm.fx / tz, J02 = -((cm.fx * xc) / tz);
+                    const float J11 = cm.fy / tz, J12 = -((cm.fy * yc) / tz);
                     // 2D covariance Sigma' = T Sigma T^T, T = J R_cam
                     const float T00 = J00 * R[0] + J02 * R[6], T01 = J00 * R[1] + J02 * R[7],
                                 T02 = J00 * R[2] + J02 * R[8];
@@ -614,7 +666,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                             ty0 = j0 / kTile;
                             ty1 = j1 / kTile;
                             // SH colour for surviving Gaussians only (Alg. 4)
-                            const float dxw = mx - cam.eye[0], dyw = my - cam.eye[1], dzw = mz - cam.eye[2];
+                            const float dxw = mx - cm.eye[0], dyw = my - cm.eye[1], dzw = mz - cm.eye[2];
                             const float dn = sqrtf((dxw * dxw + dyw * dyw) + dzw * dzw);
                             float Y[16];
                             sh_basis(dxw / dn, dyw / dn, dzw / dn, sc.D, Y);
@@ -727,34 +779,51 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     if (g < sc.P) {
         const uint32_t key = valid ? __float_as_uint(tz) : kInvalidKey;
         const int64_t oi = kPrep ? (int64_t)ii : g;  // output slot
-        if constexpr (kPrep) gmap[ii] = (uint32_t)g;
-        dkey[oi] = key;
-        count[oi] = valid ? cnt : 0u;
-        count8[oi] = chunked ? kCount8Big : (uint8_t)(valid ? cnt : 0u);  // cnt <= kBigTiles < kCount8Big
+        if constexpr (kPrep) {
+            if (ci == 0) gmap[ii] = (uint32_t)g;
+        }
+        dkey_c[oi] = key;
+        count_c[oi] = valid ? cnt : 0u;
+        count8_c[oi] = chunked ? kCount8Big : (uint8_t)(valid ? cnt : 0u);  // cnt <= kBigTiles < kCount8Big
         if (valid) {
             GaussState s;
             s.f0 = make_float4(u, v, A, B);
             s.f1 = make_float4(C, k2, l2o, col[0]);
             s.f2 = make_float4(col[1], col[2], tz, o);
-            gs[oi] = s;
-            rect[oi] = make_uint4((uint32_t)tx0, (uint32_t)tx1, (uint32_t)ty0, (uint32_t)ty1);
+            gs_c[oi] = s;
+            rect_c[oi] = make_uint4((uint32_t)tx0, (uint32_t)tx1, (uint32_t)ty0, (uint32_t)ty1);
             // emission record: rectangle (4 x 16 bits) and hit mask in one
             // 16-byte gather
             if (!chunked)
-                erec[oi] = make_uint4((uint32_t)tx0 | ((uint32_t)tx1 << 16), (uint32_t)ty0 | ((uint32_t)ty1 << 16),
+                erec_c[oi] = make_uint4((uint32_t)tx0 | ((uint32_t)tx1 << 16), (uint32_t)ty0 | ((uint32_t)ty1 << 16),
                                       (uint32_t)hm, (uint32_t)(hm >> 32));
         } else if (kPrep) {
             // a list slot is reused every frame: clear a culled candidate's
             // state and rectangle
-            gs[oi] = GaussState{};
-            rect[oi] = make_uint4(0u, 0u, 0u, 0u);
+            gs_c[oi] = GaussState{};
+            rect_c[oi] = make_uint4(0u, 0u, 0u, 0u);
         }
     }
-    w_vis += (uint32_t)__popcll(__ballot(valid));
-    if (w_nbig > (uint32_t)(kWaveBig - kWave)) flush_big(lane);  // room for the next batch
+    if constexpr (kMulti) {
+        // pending large rectangles belong to this camera: flush them now
+        const uint32_t nv = (uint32_t)__popcll(__ballot(valid));
+        if (lane == 0) s_vis[wv][ci] += nv;
+        if (w_nbig) flush_big(lane, mo.c[ci].fc, mo.c[ci].chunks, mo.c[ci].chunk_cap, erec_c);
+    } else {
+        w_vis += (uint32_t)__popcll(__ballot(valid));
+        if (w_nbig > (uint32_t)(kWaveBig - kWave))
+            flush_big(lane, fc, chunks, chunk_cap, erec);  // room for the next batch
+    }
+    }  // camera loop
     }  // batch loop
-    if (w_nbig) flush_big(lane);
-    if (lane == 0 && w_vis) atomicAdd(&fc->visible, w_vis);
+    if constexpr (kMulti) {
+        if (lane == 0)
+            for (int c = 0; c < mo.n; ++c)
+                if (s_vis[wv][c]) atomicAdd(&mo.c[c].fc->visible, s_vis[wv][c]);
+    } else {
+        if (w_nbig) flush_big(lane, fc, chunks, chunk_cap, erec);
+        if (lane == 0 && w_vis) atomicAdd(&fc->visible, w_vis);
+    }
 }
 
 // Key emission: one lane per Gaussian in (depth, index) order writes its
@@ -1017,14 +1086,25 @@ void launch_preprocess(const DevScene &sc, const DevPrepared *pp, const DevCamer
                        FrameCounters *fc, uint32_t *gsum_clear, hipStream_t s) {
     if (sc.P <= 0) return;
     if (pp) {
-        hipLaunchKernelGGL(k_cull, dim3(kCullBlocks), dim3(kBlock), 0, s, sc, *pp, cam, op, W, H, cand, seg_count,
-                           fc);
+        hipLaunchKernelGGL(k_cull<false>, dim3(kCullBlocks), dim3(kBlock), 0, s, sc, *pp, cam, op, W, H, cand, seg_count,
+                           fc, MultiOut{});
         hipLaunchKernelGGL(k_preprocess<true>, dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, *pp, cam, op, W,
-                           H, gs, rect, count, count8, erec, dkey, cand, seg_count, gmap, chunks, chunk_cap, fc, gsum_clear);
+                           H, gs, rect, count, count8, erec, dkey, cand, seg_count, gmap, chunks, chunk_cap, fc, gsum_clear, MultiOut{});
     } else {
         hipLaunchKernelGGL(k_preprocess<false>, dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, DevPrepared{},
-                           cam, op, W, H, gs, rect, count, count8, erec, dkey, cand, seg_count, gmap, chunks, chunk_cap, fc, gsum_clear);
+                           cam, op, W, H, gs, rect, count, count8, erec, dkey, cand, seg_count, gmap, chunks, chunk_cap, fc, gsum_clear, MultiOut{});
     }
+}
+
+void launch_preprocess_multi(const DevScene &sc, const DevPrepared &pp, const MultiOut &mo, const DevOptions &op,
+                             int W, int H, uint32_t *cand, uint32_t *seg_count, uint32_t *gmap, hipStream_t s) {
+    if (sc.P <= 0 || mo.n < 1 || mo.n > kMaxCams) return;
+    hipLaunchKernelGGL(k_cull<true>, dim3(kCullBlocks), dim3(kBlock), 0, s, sc, pp, mo.c[0].cam, op, W, H, cand,
+                       seg_count, mo.c[0].fc, mo);
+    const CamOut &c0 = mo.c[0];
+    hipLaunchKernelGGL((k_preprocess<true, true>), dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, pp, c0.cam, op, W,
+                       H, c0.gs, c0.rect, c0.count, c0.count8, c0.erec, c0.dkey, cand, seg_count, gmap, c0.chunks,
+                       c0.chunk_cap, c0.fc, c0.gsum_clear, mo);
 }
 
 void launch_prepare(const DevScene &sc, const DevOptions &op, float4 *pos_o, float4 *cov, float *sh, float2 *bnd,

@@ -278,6 +278,13 @@ void enqueue_front(const DevScene &sc, const DevPrepared *pp, const DevCamera &c
     // previous pass's downsweep)
     launch_preprocess(sc, pp, cam, op, W, H, fb.gs, fb.rect, fb.count, fb.count8, fb.erec, fb.dkey, fb.dv_b, fb.seg_count,
                       fb.gmap, ch.chunks, chunk_cap, fc, ss.slot(0), s);
+    enqueue_front_rest(pp != nullptr, (uint32_t)sc.P, op, W, H, fb, ch, ss, fc, host_fc, s, side, mk, counters_ready);
+}
+
+void enqueue_front_rest(bool dense, uint32_t P32, const DevOptions &op, int W, int H, FrameBuffers &fb, ChunkList &ch,
+                        SortScratch &ss, FrameCounters *fc, FrameCounters *host_fc, hipStream_t s,
+                        const SideStream &side, const StageMarks &mk, hipEvent_t counters_ready) {
+    const uint32_t chunk_cap = (uint32_t)std::min<size_t>(ch.cap, 0xffffffffu);
     // the large rectangles' exact tests touch neither the depth keys nor the
     // sort scratch: they run beside the depth sort
     hipStream_t sb = s;
@@ -291,10 +298,9 @@ void enqueue_front(const DevScene &sc, const DevPrepared *pp, const DevCamera &c
     // digits, hoisted before key duplication (the low half of the (tile |
     // depth) key is the same for every pair of a Gaussian) --------------------
     mk.mark(1, s);
-    const uint32_t P32 = (uint32_t)sc.P;
     // (values: the output slots, i.e. list positions of a prepared scene's
     // candidates or Gaussian indices)
-    launch_radix_pass(fb.dkey, nullptr, fb.dk_b, fb.dv_b, P32, pp ? &fc->ncand : nullptr, 0, 8, true, true, ss.rhist,
+    launch_radix_pass(fb.dkey, nullptr, fb.dk_b, fb.dv_b, P32, dense ? &fc->ncand : nullptr, 0, 8, true, true, ss.rhist,
                       ss.slot(0), ss.slot(1), s);
     launch_radix_pass(fb.dk_b, fb.dv_b, fb.dkey, fb.dv_a, P32, &fc->visible, 8, 8, false, true, ss.rhist, ss.slot(1),
                       ss.slot(2), s);

@@ -113,6 +113,12 @@ void enqueue_front(const DevScene &sc, const DevPrepared *pp, const DevCamera &c
                    int H, FrameBuffers &fb, ChunkList &ch, SortScratch &ss, FrameCounters *fc,
                    FrameCounters *host_fc, hipStream_t s, const SideStream &side, const StageMarks &mk,
                    hipEvent_t counters_ready = nullptr);
+// The part of enqueue_front after the preprocess (for a preprocess run
+// elsewhere, as in a multi-camera batch).  dense: the outputs are over a
+// candidate list of fc->ncand positions (a prepared scene); P32 bounds it.
+void enqueue_front_rest(bool dense, uint32_t P32, const DevOptions &op, int W, int H, FrameBuffers &fb, ChunkList &ch,
+                        SortScratch &ss, FrameCounters *fc, FrameCounters *host_fc, hipStream_t s,
+                        const SideStream &side, const StageMarks &mk, hipEvent_t counters_ready = nullptr);
 
 // Device buffers of a scene's view-independent precompute.
 struct PreparedBuffers {

@@ -67,6 +67,14 @@ struct fgs_context {
     float *gacc = nullptr;
     size_t gacc_stride = 0;
     std::vector<fgs_prepared *> prepared;
+    // multi-camera batches: the buffers of each camera of a batch
+    struct BatchCam {
+        FrameBuffers fb;
+        ChunkList ch;
+        SortScratch ss;
+    };
+    std::vector<BatchCam> batch;
+    FrameCounters *bfc_dev = nullptr, *bfc_host = nullptr;  // kMaxCams each
 };
 
 namespace {
@@ -209,6 +217,13 @@ void fgs_destroy(fgs_context *ctx) {
     }
     for (FrameBuffers &b : ctx->pool) free_frame_buffers(b);
     free_frame_buffers(ctx->fb);
+    for (auto &bc : ctx->batch) {
+        free_frame_buffers(bc.fb);
+        free_chunks(bc.ch);
+        free_sort_scratch(bc.ss);
+    }
+    if (ctx->bfc_dev) (void)hipFree(ctx->bfc_dev);
+    if (ctx->bfc_host) (void)hipHostFree(ctx->bfc_host);
     for (auto &set : ctx->ev)
         for (hipEvent_t &e : set)
             if (e) (void)hipEventDestroy(e);
@@ -509,6 +524,141 @@ fgs_status fgs_render_prepared(fgs_context *ctx, const fgs_prepared *p, const fg
     for (const fgs_prepared *q : ctx->prepared) owned |= (q == p);
     if (!p || !owned) return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "prepared scene is NULL or not of this context");
     return render_impl(ctx, &p->scene, p, cam, W, H, opt, out_rgb, out_T, out_last, saved, stats, stream);
+}
+
+static_assert(kMaxCams == FGS_MAX_BATCH_CAMERAS, "batch size limit of the ABI");
+
+fgs_status fgs_render_prepared_batch(fgs_context *ctx, const fgs_prepared *p, const fgs_camera *cams, int32_t ncams,
+                                     int32_t W, int32_t H, const fgs_options *opt_in, float *const *out_rgb,
+                                     float *const *out_T, uint32_t *const *out_last, fgs_stats *stats, void *stream_v) {
+    if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARGUMENT, "context is NULL");
+    bool owned = false;
+    for (const fgs_prepared *q : ctx->prepared) owned |= (q == p);
+    if (!p || !owned) return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "prepared scene is NULL or not of this context");
+    if (!cams || ncams < 1 || ncams > kMaxCams)
+        return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "ncams must be 1..%d with cams given", kMaxCams);
+    if (!out_rgb) return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "out_rgb is NULL");
+    for (int c = 0; c < ncams; ++c) {
+        fgs_status st = validate(ctx, &p->scene, &cams[c], W, H, opt_in);
+        if (st != FGS_OK) return st;
+        if (!out_rgb[c]) return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "out_rgb[%d] is NULL", c);
+    }
+    fgs_options opt;
+    if (opt_in)
+        opt = *opt_in;
+    else
+        fgs_default_options(&opt);
+    if (opt.alpha_min != p->opt.alpha_min || opt.cap_3sigma != p->opt.cap_3sigma)
+        return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "alpha_min / cap_3sigma differ from the scene's preparation");
+    ctx->err.clear();
+    hipStream_t s = (hipStream_t)stream_v;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const int64_t P = p->scene.num_gaussians;
+    const int tiles_x = (W + kTile - 1) / kTile, tiles_y = (H + kTile - 1) / kTile;
+    const uint32_t ntiles = (uint32_t)tiles_x * (uint32_t)tiles_y;
+    if (!ctx->bfc_dev) HIP_TRY(ctx, hipMalloc((void **)&ctx->bfc_dev, kMaxCams * sizeof(FrameCounters)));
+    if (!ctx->bfc_host)
+        HIP_TRY(ctx, hipHostMalloc((void **)&ctx->bfc_host, kMaxCams * sizeof(FrameCounters), hipHostMallocDefault));
+    if (ctx->batch.size() < (size_t)ncams) ctx->batch.resize(ncams);
+    for (int c = 0; c < ncams; ++c) {
+        auto &bc = ctx->batch[c];
+        HIP_TRY(ctx, ensure_gauss(bc.fb, (size_t)P));
+        HIP_TRY(ctx, ensure_tiles(bc.fb, ntiles));
+        HIP_TRY(ctx, ensure_sort_scratch(bc.ss));
+        HIP_TRY(ctx, ensure_chunks(bc.ch, (size_t)P / 8));
+    }
+    const DevScene dsc = to_dev(p->scene);
+    const DevOptions dop = to_dev(opt);
+    const DevPrepared pdev = p->pb.dev();
+    const StageMarks nomk;
+    size_t spec_cap[kMaxCams] = {};  // pair capacity of a second half already enqueued (0: none)
+    for (int attempt = 0;; ++attempt) {
+        // one cull and one preprocess for every camera; the candidate list
+        // and the Gaussian of each list position live in camera 0's buffers
+        MultiOut mo{};
+        mo.n = ncams;
+        for (int c = 0; c < ncams; ++c) {
+            auto &bc = ctx->batch[c];
+            CamOut &o = mo.c[c];
+            o.cam = to_dev(cams[c]);
+            o.gs = bc.fb.gs;
+            o.rect = bc.fb.rect;
+            o.count = bc.fb.count;
+            o.count8 = bc.fb.count8;
+            o.erec = bc.fb.erec;
+            o.dkey = bc.fb.dkey;
+            o.chunks = bc.ch.chunks;
+            o.chunk_cap = (uint32_t)std::min<size_t>(bc.ch.cap, 0xffffffffu);
+            o.fc = ctx->bfc_dev + c;
+            o.gsum_clear = bc.ss.slot(0);
+        }
+        FrameBuffers &fb0 = ctx->batch[0].fb;
+        if (P <= 0) launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->bfc_dev), 0u, kMaxCams * sizeof(FrameCounters) / 4, s);
+        launch_preprocess_multi(dsc, pdev, mo, dop, W, H, fb0.dv_b, fb0.seg_count, fb0.gmap, s);
+        // each camera's depth order and scan, then (beside the host's wait
+        // for the counters) each camera's second half
+        for (int c = 0; c < ncams; ++c) {
+            auto &bc = ctx->batch[c];
+            enqueue_front_rest(true, (uint32_t)P, dop, W, H, bc.fb, bc.ch, bc.ss, ctx->bfc_dev + c, ctx->bfc_host + c,
+                               s, ctx->side, nomk);
+        }
+        HIP_TRY(ctx, hipEventRecord(ctx->front_done, s));
+        for (int c = 0; c < ncams; ++c) {
+            auto &bc = ctx->batch[c];
+            spec_cap[c] = 0;
+            if (bc.fb.capN > 0) {
+                (void)enqueue_back(W, H, dop, (uint32_t)P, bc.fb, bc.ch, bc.ss, ctx->bfc_dev + c, out_rgb[c],
+                                   out_T ? out_T[c] : nullptr, out_last ? out_last[c] : nullptr, nullptr, s, nomk,
+                                   ctx->blend_variant);
+                spec_cap[c] = bc.fb.capN;
+            }
+        }
+        HIP_TRY(ctx, hipGetLastError());
+        hipError_t q;
+        while ((q = hipEventQuery(ctx->front_done)) == hipErrorNotReady) {
+        }
+        HIP_TRY(ctx, q);
+        bool overflow = false;
+        for (int c = 0; c < ncams; ++c) overflow |= (ctx->bfc_host[c].error & kErrChunkOverflow) != 0;
+        if (!overflow) break;
+        // a chunk list was too small: size it exactly and render the batch again
+        if (attempt > 0) return fail(ctx, FGS_ERR_INTERNAL, "chunk list overflow after resizing");
+        HIP_TRY(ctx, hipStreamSynchronize(s));  // the lists are in use
+        for (int c = 0; c < ncams; ++c) {
+            const size_t need = ctx->bfc_host[c].nchunks;
+            HIP_TRY(ctx, ensure_chunks(ctx->batch[c].ch, need + need / 8));
+        }
+    }
+    bool synced = false;
+    for (int c = 0; c < ncams; ++c) {
+        auto &bc = ctx->batch[c];
+        const uint32_t N = ctx->bfc_host[c].pairs;
+        if (spec_cap[c] == 0 || N > spec_cap[c]) {
+            // no second half yet, or it ran out of pair buffer: grow the
+            // buffers (once every enqueued half has finished) and enqueue it
+            if (!synced) HIP_TRY(ctx, hipStreamSynchronize(s));
+            synced = true;
+            HIP_TRY(ctx, ensure_pairs(bc.fb, N));
+            (void)enqueue_back(W, H, dop, (uint32_t)P, bc.fb, bc.ch, bc.ss, ctx->bfc_dev + c, out_rgb[c],
+                               out_T ? out_T[c] : nullptr, out_last ? out_last[c] : nullptr, nullptr, s, nomk,
+                               ctx->blend_variant);
+        }
+        if (stats) {
+            fgs_stats stt{};
+            stt.visible = ctx->bfc_host[c].visible;
+            stt.pairs = N;
+            stt.tiles_x = tiles_x;
+            stt.tiles_y = tiles_y;
+            stt.big_chunks = (int32_t)ctx->bfc_host[c].nchunks;
+            stt.candidates = (int64_t)ctx->bfc_host[c].ncand;
+            int b = 0;
+            while ((1ull << b) < (uint64_t)ntiles) ++b;
+            stt.sort_passes = 4 + (b + kRadixBits - 1) / kRadixBits;
+            stats[c] = stt;
+        }
+    }
+    HIP_TRY(ctx, hipGetLastError());
+    return FGS_OK;
 }
 
 fgs_status fgs_frame_release(fgs_context *ctx, fgs_frame *frame) {

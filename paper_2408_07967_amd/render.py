@@ -111,6 +111,28 @@ class Renderer:
                                sort_passes=st.sort_passes, big_chunks=st.big_chunks,
                                candidates=st.candidates))
 
+    def render_batch(self, prepared, scene, cams, W, H, opts=None, want_T=False, want_last=False):
+        """Render several cameras of a prepared scene in one call (one cull and
+        one preprocess pass for the whole batch).  Returns one dict per camera
+        like render(), without a frame handle."""
+        dev = scene.means.device
+        n = len(cams)
+        rgb = [torch.empty((3, H, W), dtype=torch.float32, device=dev) for _ in range(n)]
+        T = [torch.empty((H, W), dtype=torch.float32, device=dev) for _ in range(n)] if want_T else None
+        last = [torch.empty((H, W), dtype=torch.int32, device=dev) for _ in range(n)] if want_last else None
+        cm = (B.FgsCamera * max(n, 1))(*[camera_abi(c) for c in cams])
+        ptrs = lambda ts: (C.c_void_p * max(n, 1))(*[t.data_ptr() for t in ts]) if ts is not None else None
+        op = options_abi(opts)
+        st = (B.FgsStats * max(n, 1))()
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        self.ctx.check(B.lib().fgs_render_prepared_batch(self.ctx.handle, prepared, cm, n, int(W), int(H),
+                                                         C.byref(op), ptrs(rgb), ptrs(T), ptrs(last), st, stream))
+        return [dict(rgb=rgb[i], T=T[i] if T else None, last=last[i] if last else None, frame=None,
+                     stats=dict(visible=st[i].visible, pairs=st[i].pairs, tiles_x=st[i].tiles_x,
+                                tiles_y=st[i].tiles_y, sort_passes=st[i].sort_passes,
+                                big_chunks=st[i].big_chunks, candidates=st[i].candidates))
+                for i in range(n)]
+
     def plan(self, scene, cam, W, H, opts=None):
         """Pair count and device bytes of one frame, without rendering it:
         returns dict(pairs, bytes)."""

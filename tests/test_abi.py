@@ -117,6 +117,9 @@ def test_null_arguments_rejected_without_device():
     assert B.lib().fgs_frame_field_bytes(None, 0) == 0
     assert B.lib().fgs_scratch_bytes(None) == 0
     assert B.lib().fgs_set_blend_variant(None, B.BLEND_PREFETCH) == B.FGS_ERR_INVALID_ARGUMENT
+    cams = (B.FgsCamera * 2)(cam, cam)
+    assert B.lib().fgs_render_prepared_batch(None, None, cams, 2, 8, 8, C.byref(op), None, None, None, None,
+                                             None) == B.FGS_ERR_INVALID_ARGUMENT
 
 
 def test_status_strings():
