@@ -439,9 +439,26 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     uint32_t w_nbig = 0, w_nch = 0;      // wave-uniform: pending entries and their chunks
     uint32_t w_vis = 0;                  // wave-uniform: visible Gaussians so far
     __shared__ uint32_t s_vis[kMulti ? kBlock / kWave : 1][kMulti ? kMaxCams : 1];  // per camera (kMulti)
+    // kMulti: the pending list holds entries of every camera, each tagged
+    // with its camera; chunks are counted per camera, and a flush reserves
+    // each camera's share of its own chunk list
+    constexpr int kMB = kMulti ? kWaveBig : 1;
+    constexpr int kMC = kMulti ? kMaxCams : 1;
+    __shared__ uint32_t s_bc[kBlock / kWave][kMB], s_nch[kBlock / kWave][kMC], s_cbase[kBlock / kWave][kMC];
+    __shared__ uint2 *s_chunks[kMC];
+    __shared__ uint4 *s_erec[kMC];
     if constexpr (kMulti) {
         if ((threadIdx.x & (kWave - 1)) == 0)
-            for (int c = 0; c < kMaxCams; ++c) s_vis[wv][c] = 0;
+            for (int c = 0; c < kMaxCams; ++c) {
+                s_vis[wv][c] = 0;
+                s_nch[wv][c] = 0;
+            }
+        if (threadIdx.x == 0)
+            for (int c = 0; c < mo.n; ++c) {
+                s_chunks[c] = mo.c[c].chunks;
+                s_erec[c] = mo.c[c].erec;
+            }
+        __syncthreads();
     }
 
     // reserve chunk-list space for the wavefront's pending large Gaussians
@@ -468,6 +485,39 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         __builtin_amdgcn_wave_barrier();
         w_nbig = 0;
         w_nch = 0;
+    };
+    constexpr uint32_t kNoBase = 0xffffffffu;
+    auto flush_big_multi = [&](int ln) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (ln == 0)
+            for (int c = 0; c < mo.n; ++c) {
+                const uint32_t n = s_nch[wv][c];
+                uint32_t base = kNoBase;
+                if (n) {
+                    base = atomicAdd(&mo.c[c].fc->nchunks, n);
+                    if ((uint64_t)base + n > mo.c[c].chunk_cap) {
+                        atomicOr(&mo.c[c].fc->error, kErrChunkOverflow);
+                        base = kNoBase;
+                    }
+                }
+                s_cbase[wv][c] = base;
+                s_nch[wv][c] = 0;
+            }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (uint32_t e = (uint32_t)ln; e < w_nbig; e += kWave) {
+            const uint32_t c = s_bc[wv][e], base = s_cbase[wv][c];
+            if (base == kNoBase) continue;
+            const uint32_t gg = s_bg[wv][e], first = base + s_boff[wv][e], n = s_bn[wv][e];
+            uint2 *const ck = s_chunks[c];
+            for (uint32_t k = 0; k < n; ++k) ck[first + k] = make_uint2(gg, first);
+            s_erec[c][gg] = make_uint4(s_bx[wv][e], s_by[wv][e], 0u, first);
+        }
+        __builtin_amdgcn_wave_barrier();
+        w_nbig = 0;
     };
 
     const int lane = threadIdx.x & (kWave - 1);
@@ -724,20 +774,29 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     // workgroups across the GPU test them kChunkTiles tiles at a time
     const bool chunked = valid && nt > kBigTiles;
     {
-        const uint64_t cm = __ballot(chunked);
-        if (cm) {  // uniform
+        const uint64_t bm = __ballot(chunked);
+        if (bm) {  // uniform
             const uint32_t nch = chunked ? (uint32_t)((nt + kChunkTiles - 1) / kChunkTiles) : 0u;
             const uint32_t incl = wave_incl_scan(nch, lane);
+            // chunks pending before these (this camera's, kMulti)
+            uint32_t cbase = w_nch;
+            if constexpr (kMulti) cbase = s_nch[wv][ci];
             if (chunked) {
-                const uint32_t slot = w_nbig + (uint32_t)__popcll(cm & ((1ull << lane) - 1ull));
+                const uint32_t slot = w_nbig + (uint32_t)__popcll(bm & ((1ull << lane) - 1ull));
+                if constexpr (kMulti) s_bc[wv][slot] = (uint32_t)ci;
                 s_bg[wv][slot] = kPrep ? ii : (uint32_t)g;
                 s_bn[wv][slot] = nch;
                 s_bx[wv][slot] = (uint32_t)tx0 | ((uint32_t)tx1 << 16);
                 s_by[wv][slot] = (uint32_t)ty0 | ((uint32_t)ty1 << 16);
-                s_boff[wv][slot] = w_nch + incl - nch;
+                s_boff[wv][slot] = cbase + incl - nch;
             }
-            w_nbig += (uint32_t)__popcll(cm);
-            w_nch += (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+            w_nbig += (uint32_t)__popcll(bm);
+            const uint32_t tot = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+            if constexpr (kMulti) {
+                if (lane == 0) s_nch[wv][ci] = cbase + tot;
+            } else {
+                w_nch += tot;
+            }
         }
     }
     const bool small = valid && !chunked;  // rectangle of at most kBigTiles tiles
@@ -805,10 +864,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         }
     }
     if constexpr (kMulti) {
-        // pending large rectangles belong to this camera: flush them now
         const uint32_t nv = (uint32_t)__popcll(__ballot(valid));
         if (lane == 0) s_vis[wv][ci] += nv;
-        if (w_nbig) flush_big(lane, mo.c[ci].fc, mo.c[ci].chunks, mo.c[ci].chunk_cap, erec_c);
+        if (w_nbig > (uint32_t)(kWaveBig - kWave)) flush_big_multi(lane);  // room for the next camera
     } else {
         w_vis += (uint32_t)__popcll(__ballot(valid));
         if (w_nbig > (uint32_t)(kWaveBig - kWave))
@@ -817,6 +875,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     }  // camera loop
     }  // batch loop
     if constexpr (kMulti) {
+        if (w_nbig) flush_big_multi(lane);
         if (lane == 0)
             for (int c = 0; c < mo.n; ++c)
                 if (s_vis[wv][c]) atomicAdd(&mo.c[c].fc->visible, s_vis[wv][c]);
