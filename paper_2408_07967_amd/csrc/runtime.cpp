@@ -603,15 +603,27 @@ fgs_status fgs_render_prepared_batch(fgs_context *ctx, const fgs_prepared *p, co
                                s, ctx->side, nomk);
         }
         HIP_TRY(ctx, hipEventRecord(ctx->front_done, s));
+        // the cameras' second halves share no buffer: odd cameras run on the
+        // side stream beside the even ones (one camera's sort passes, bound by
+        // HBM, overlap another's blend, bound by the VALU), and s joins the
+        // side stream at the end
+        hipStream_t s2 = s;
+        if (ncams > 1 && ctx->side.side && hipEventRecord(ctx->side.fork, s) == hipSuccess &&
+            hipStreamWaitEvent(ctx->side.side, ctx->side.fork, 0) == hipSuccess)
+            s2 = ctx->side.side;
         for (int c = 0; c < ncams; ++c) {
             auto &bc = ctx->batch[c];
             spec_cap[c] = 0;
             if (bc.fb.capN > 0) {
                 (void)enqueue_back(W, H, dop, (uint32_t)P, bc.fb, bc.ch, bc.ss, ctx->bfc_dev + c, out_rgb[c],
-                                   out_T ? out_T[c] : nullptr, out_last ? out_last[c] : nullptr, nullptr, s, nomk,
-                                   ctx->blend_variant);
+                                   out_T ? out_T[c] : nullptr, out_last ? out_last[c] : nullptr, nullptr,
+                                   (c & 1) ? s2 : s, nomk, ctx->blend_variant);
                 spec_cap[c] = bc.fb.capN;
             }
+        }
+        if (s2 != s) {
+            HIP_TRY(ctx, hipEventRecord(ctx->side.join, s2));
+            HIP_TRY(ctx, hipStreamWaitEvent(s, ctx->side.join, 0));
         }
         HIP_TRY(ctx, hipGetLastError());
         hipError_t q;
@@ -623,7 +635,7 @@ fgs_status fgs_render_prepared_batch(fgs_context *ctx, const fgs_prepared *p, co
         if (!overflow) break;
         // a chunk list was too small: size it exactly and render the batch again
         if (attempt > 0) return fail(ctx, FGS_ERR_INTERNAL, "chunk list overflow after resizing");
-        HIP_TRY(ctx, hipStreamSynchronize(s));  // the lists are in use
+        HIP_TRY(ctx, hipStreamSynchronize(s));  // the lists are in use (s has joined the side stream)
         for (int c = 0; c < ncams; ++c) {
             const size_t need = ctx->bfc_host[c].nchunks;
             HIP_TRY(ctx, ensure_chunks(ctx->batch[c].ch, need + need / 8));
@@ -635,7 +647,8 @@ fgs_status fgs_render_prepared_batch(fgs_context *ctx, const fgs_prepared *p, co
         const uint32_t N = ctx->bfc_host[c].pairs;
         if (spec_cap[c] == 0 || N > spec_cap[c]) {
             // no second half yet, or it ran out of pair buffer: grow the
-            // buffers (once every enqueued half has finished) and enqueue it
+            // buffers (once every enqueued half has finished: s has joined
+            // the side stream) and enqueue it on s
             if (!synced) HIP_TRY(ctx, hipStreamSynchronize(s));
             synced = true;
             HIP_TRY(ctx, ensure_pairs(bc.fb, N));
