@@ -6,14 +6,14 @@ path held bit-exact against the FP32 oracle by the other GPU tests), with the
 same visible and pair counts; one camera of each case is also checked against
 the FP64 oracle directly.  Cases cover one camera, the largest batch, a camera
 that sees nothing, ragged image sizes, and pair buffers that grow between and
-inside batches."""
+inside batches, and chunk lists that overflow and are resized within a batch."""
 import math
 
 import numpy as np
 import pytest
 
 from gpu_helpers import check_image
-from oracle_helpers import opts
+from oracle_helpers import identity_camera, opts, scene_from
 
 pytestmark = pytest.mark.gpu
 
@@ -116,6 +116,40 @@ def test_batch_buffers_grow_between_batches(scenes):
     finally:
         R.release_prepared(h)
         R.close()
+
+
+def test_batch_chunk_lists_overflow_and_resize():
+    """600 screen-filling Gaussians at 4K need far more large-rectangle chunk
+    entries than a fresh context's lists hold, for every camera of the batch:
+    the batch resizes each camera's list and renders again, and every camera
+    still matches its single render."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2408_07967_amd.render import GaussianScene, Renderer
+    from paper_2408_07967_amd.scenes import Camera
+    rng = np.random.default_rng(32)
+    P = 600
+    means = np.c_[rng.uniform(-0.3, 0.3, P), rng.uniform(-0.2, 0.2, P), rng.uniform(5, 9, P)]
+    sc = scene_from(means, np.full((P, 3), 1.2), rng.normal(size=(P, 4)), rng.normal(0, 1, P),
+                    dc_rgb=rng.uniform(0, 1, (P, 3)))
+    W, H = 3840, 2160
+    base = identity_camera(W, H, 1500.0)
+    cams = [base]
+    for dx in (0.2, -0.35):
+        t = np.asarray(base.t, np.float32) + np.float32([dx, 0.0, 0.0])
+        cams.append(Camera(base.R, t, np.asarray(base.eye, np.float32) - np.float32([dx, 0.0, 0.0]), base.fx,
+                           base.fy, base.cx, base.cy, base.near, W, H))
+    o = opts()
+    R = Renderer()
+    gsc = GaussianScene.from_numpy(sc)
+    h = R.prepare(gsc, o)
+    try:
+        got = _check_batch(R, gsc, h, cams, W, H, o, "overflow")
+    finally:
+        R.release_prepared(h)
+        R.close()
+    assert all(g["stats"]["big_chunks"] > P for g in got)
 
 
 def test_batch_rejects_bad_camera_counts(scenes):
