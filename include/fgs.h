@@ -223,9 +223,12 @@ fgs_status fgs_render_prepared(fgs_context *ctx, const fgs_prepared *prepared, c
  * fgs_render_prepared for camera c alone.  No frame is saved (a batch has
  * no backward) and a batch collects neither stage times nor work counts.
  * Device memory: one set of frame buffers per camera slot, kept by the
- * context for later batches.  Enqueued on `stream`; like fgs_render_prepared
- * it returns once the frame counters are on the host.  Errors as for
- * fgs_render_prepared, and INVALID_ARGUMENT for ncams out of range. */
+ * context for later batches.  Enqueued on `stream`: the second halves of odd
+ * cameras run on the context's own second stream, which `stream` waits for
+ * on the device, so later work on `stream` sees every output.  Like
+ * fgs_render_prepared it returns once the frame counters are on the host.
+ * Errors as for fgs_render_prepared, and INVALID_ARGUMENT for ncams out of
+ * range. */
 #define FGS_MAX_BATCH_CAMERAS 8
 fgs_status fgs_render_prepared_batch(fgs_context *ctx, const fgs_prepared *prepared, const fgs_camera *cams,
                                      int32_t ncams, int32_t W, int32_t H, const fgs_options *opt,
