@@ -260,6 +260,9 @@ size_t fgs_scratch_bytes(const fgs_context *ctx) {
     for (const fgs_prepared *p : ctx->prepared) b += p->pb.bytes();
     for (const FrameBuffers &p : ctx->pool) b += p.bytes();
     for (const fgs_frame *f : ctx->frames) b += f->fb.bytes();
+    for (const auto &bc : ctx->batch)
+        b += bc.fb.bytes() + bc.ch.bytes() + (bc.ss.rhist ? SortScratch::bytes() : 0);
+    if (ctx->bfc_dev) b += kMaxCams * sizeof(FrameCounters);
     return b;
 }
 

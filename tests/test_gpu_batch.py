@@ -110,8 +110,13 @@ def test_batch_buffers_grow_between_batches(scenes):
     try:
         small = [scenes.camera_for("medium", i, W=160, H=90) for i in (0, 3)]
         big = [scenes.camera_for("medium", i, W=1920, H=1080) for i in (0, 2, 5)]
+        before = R.scratch_bytes()
         _check_batch(R, gsc, h, small, 160, 90, o, "grow-1")
+        mid = R.scratch_bytes()
+        # the batch's per-camera buffers are counted in the context's scratch
+        assert mid > before
         _check_batch(R, gsc, h, big, 1920, 1080, o, "grow-2")
+        assert R.scratch_bytes() > mid
         _check_batch(R, gsc, h, small, 160, 90, o, "grow-3")
     finally:
         R.release_prepared(h)
