@@ -222,8 +222,8 @@ fgs_status fgs_render_prepared(fgs_context *ctx, const fgs_prepared *prepared, c
  * Camera c's image, T_final and last contributor are bit for bit those of
  * fgs_render_prepared for camera c alone.  No frame is saved (a batch has
  * no backward) and a batch collects neither stage times nor work counts.
- * Device memory: one set of frame buffers per camera slot, kept by the
- * context for later batches.  Enqueued on `stream`: the second halves of odd
+ * Device memory: one set of frame buffers per camera slot, grown on demand
+ * (fgs_reserve does not size them) and kept by the context for later batches.  Enqueued on `stream`: the second halves of odd
  * cameras run on the context's own second stream, which `stream` waits for
  * on the device, so later work on `stream` sees every output.  Like
  * fgs_render_prepared it returns once the frame counters are on the host.
