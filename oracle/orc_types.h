@@ -1,10 +1,10 @@
 /*
  * Types shared by the oracle's translation units (test infrastructure only;
  * never included by the product library).  The including file defines REAL
- * (float or double) and TYPE(name) (name_f32 / name_f64) first.
+ * (float or double) and TYPE(name) (name_f32 / name_f64) first.  The struct
+ * typedefs may be included once per (REAL, TYPE) pair in one file; the state
+ * indices once in all.
  */
-#ifndef ORC_TYPES_H
-#define ORC_TYPES_H
 #include <stdint.h>
 
 /* ---- inputs ------------------------------------------------------------ */
@@ -38,6 +38,8 @@ typedef struct {
 } TYPE(orc_options);
 
 /* ---- per-Gaussian state ------------------------------------------------ */
+#ifndef ORC_STATE_INDICES
+#define ORC_STATE_INDICES
 
 enum {
     S_U, S_V, S_A, S_B, S_C, S_K2, S_O, S_DEPTH, S_R, S_G, S_BL,

@@ -138,7 +138,12 @@ void fold_events(fgs_context *ctx) {
 extern "C" {
 
 const char *fgs_status_string(fgs_status s) {
-    switch (s) {
+    // a C caller may pass any int; read it as one (a C++ enum holding a value
+    // outside its enumerators' range is undefined)
+    int v = 0;
+    static_assert(sizeof v == sizeof s, "fgs_status is int-sized");
+    memcpy(&v, &s, sizeof v);
+    switch (v) {
     case FGS_OK: return "ok";
     case FGS_ERR_INVALID_ARGUMENT: return "invalid argument";
     case FGS_ERR_OUT_OF_MEMORY: return "out of device memory";
