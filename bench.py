@@ -1,25 +1,30 @@
 #!/usr/bin/env python3
-"""Benchmark of the plain renderer on one MI355X.
+"""Benchmark of the renderer on one MI355X.
 
 Default workload: the 10,000,000-Gaussian ground-plane scene (SH degree 3)
 rendered at 3840x2160 through the camera at 80 m altitude pitched 30 deg
 down (synthetic stand-in for the paper's large-scale aerial 4K case).
-A step is one full frame through the C ABI: preprocess with the exact
+A step is one full frame through the C ABI: cull, preprocess with the exact
 ellipse/tile test, depth sort, count scan, key emission, tile sort, tile
 ranges and blending, with the scene already resident in HBM together with
-its view-independent precompute (opacity, 3D covariance, extent, and SH
-coefficients Gaussian-major; built once, Sec. 5.3.1).  The frame rate from
-the raw parameters is reported beside it.
+its view-independent precompute (opacity, scales and rotation, extent, and
+SH coefficients Gaussian-major; built once, Sec. 5.3.1).  The frame rate
+from the raw parameters is reported beside it.
 
-Prints one JSON line with frames/s, the blend kernel's roofline figures
-(measured live with HIP events on the render stream) and the CPU oracle
-timed on the same frame.
+Prints one JSON line: frames/s, per-stage times and roofline fractions
+(HIP events on the render stream; the dominant kernel in `roofline`), the
+image against the binary64 oracle with a pass flag, the CPU oracle timed on
+the host, the other workloads (10k at 256x256, 1M at 1080p through eight
+cameras, the 8K stress case), the multi-camera batch, the serving workload
+(batched server against the plain renderer on the same resident scene) and
+the forward + backward timing.
 """
 import argparse
 import hashlib
-import re
 import json
+import math
 import os
+import re
 import sys
 import time
 
@@ -33,24 +38,29 @@ WORKLOADS = {
     "medium": dict(kind="medium", W=1920, H=1080, name="medium-1M-gaussians-1920x1080"),
     "small": dict(kind="small", W=256, H=256, name="small-10k-gaussians-256x256"),
 }
-# FP32 operations of one (pixel, Gaussian) evaluation of the blend, FMA = 2:
-# dx, dy (2); q = A dx^2 + 2B dx dy + C dy^2 (7); exponent FMA (2); exp2 (1);
-# alpha clamp (1); T' = T - alpha T (2); weight alpha T (1); 3 colour FMAs (6).
-FLOP_PER_EVAL = 22
-# 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, non-packed FP32
-PEAK_ALU_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+# VALU issue: 256 CUs, 4 SIMDs each issuing one wave64 instruction every 4
+# cycles, 2.4 GHz: 614.4 G wave instructions/s = 39.3 T lane operations/s
+# (non-packed FP32; an FMA is one operation)
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# slots of one (pixel, Gaussian) evaluation of the blend in the two-pixels-
+# per-lane form: 14 VALU operations and one quarter-rate v_exp_f32 (4 slots)
+BLEND_SLOTS_PER_EVAL = 18
+PROFILE_SOURCES = {
+    "k_blend": ("k_blend.hip", "blend_common.hpp", "fgs_internal.hpp"),
+    "k_preprocess": ("k_project.hip", "fgs_internal.hpp", "sh_basis.hpp"),
+}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
-    """Hash of the blend kernel's code (the kernel file and its shared
-    per-pixel arithmetic) with comments and blank lines left out, so that a
-    change of wording only does not void the counters taken on the kernel."""
+def kernel_source_hash(kernel):
+    """Hash of a kernel's sources with comments and blank lines left out, so
+    that a change of wording alone does not void the counters taken on it."""
     h = hashlib.sha256()
-    for f in ("k_blend.hip", "blend_common.hpp"):
+    for f in PROFILE_SOURCES[kernel]:
         src = open(os.path.join(ROOT, "paper_2408_07967_amd", "csrc", f)).read()
         src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
         lines = (re.sub(r"//.*$", "", ln).rstrip() for ln in src.splitlines())
@@ -58,19 +68,30 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(workload, evals_per_launch):
-    """HBM bytes per blend launch from committed rocprofv3 counter runs, or
-    None if absent or taken on a different blend kernel source."""
-    p = os.path.join(ROOT, "profiles", f"blend_{workload}_traffic.json")
+def profile_record(kernel, workload):
+    """A committed rocprofv3 summary of the kernel on the workload
+    (profiles/<kernel>_<workload>_counters.json), or None if absent or taken
+    on different kernel sources."""
+    p = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.json")
     if not os.path.exists(p):
         return None
     try:
         d = json.load(open(p))
     except Exception:
         return None
-    if d.get("kernel_sha") != kernel_source_hash():
+    if d.get("kernel_sha") != kernel_source_hash(kernel):
         return None
-    return d.get("bytes_per_launch")
+    return d
+
+
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def oracle_frame(scene, cam, W, H, opts, mode="f64"):
@@ -86,35 +107,152 @@ def oracle_frame(scene, cam, W, H, opts, mode="f64"):
 
 
 def cpu_baseline(scene, cam, W, H, opts):
-    """The CPU oracle (binary64, OpenMP over Gaussians and tiles), untuned,
-    timed on one full frame of the same workload; also returns its image."""
+    """The CPU oracle, untuned, timed on the host: one full frame of the
+    timed workload in binary64 (the baseline) and in its binary32 mode, one
+    frame of each smaller workload, and the 10k-Gaussian frame on one thread.
+    Returns the record and the binary64 and binary32 images of the frame."""
     from oracle import oracle as orc
     from paper_2408_07967_amd import scenes
+    threads = int(orc._lib().orc_num_threads())
     dt, npairs, rgb = oracle_frame(scene, cam, W, H, opts)
-    res = dict(value=round(1.0 / dt, 5), unit="frames/s", cores=int(orc._lib().orc_num_threads()),
-               kind="oracle", sample=f"one full {W}x{H} frame of the same scene and camera, binary64 "
-                                     f"(preprocess + pairs + sort + blend; input conversion excluded); "
-                                     f"{dt:.2f} s", pairs_per_s=round(npairs / dt, 1))
-    # the smaller synthetic workloads, one frame each
+    dt32, _, rgb32 = oracle_frame(scene, cam, W, H, opts, "f32")
+    res = dict(value=round(1.0 / dt, 5), unit="frames/s", cores=threads, kind="oracle",
+               sample=f"one full {W}x{H} frame of the same scene and camera, binary64 "
+                      f"(preprocess + pairs + sort + blend; input conversion excluded); {dt:.2f} s",
+               cpu_model=cpu_model(), host_cpus=os.cpu_count(), pairs_per_s=round(npairs / dt, 1),
+               binary32_mode=dict(frames_per_s=round(1.0 / dt32, 5), seconds=round(dt32, 3)))
     other = {}
-    for kind, name in (("small", "small-10k-gaussians-256x256"), ("medium", "medium-1M-gaussians-1920x1080")):
+    for kind, name in (("small", WORKLOADS["small"]["name"]), ("medium", WORKLOADS["medium"]["name"])):
         sc2 = scenes.make_scene(kind)
         cam2 = scenes.camera_for(kind, 0)
         dt2, n2, _ = oracle_frame(sc2, cam2, cam2.W, cam2.H, opts)
-        other[name] = dict(frames_per_s=round(1.0 / dt2, 3), pairs_per_s=round(n2 / dt2, 1), seconds=round(dt2, 3))
+        other[name] = dict(frames_per_s=round(1.0 / dt2, 3), pairs_per_s=round(n2 / dt2, 1), seconds=round(dt2, 3),
+                           cores=threads)
+        if kind == "small":
+            orc._lib().orc_set_num_threads(1)
+            try:
+                reps = 5
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    dt1, n1, _ = oracle_frame(sc2, cam2, cam2.W, cam2.H, opts)
+                dt1 = (time.perf_counter() - t0) / reps
+            finally:
+                orc._lib().orc_set_num_threads(threads)
+            other[name + "-one-thread"] = dict(frames_per_s=round(1.0 / dt1, 3), pairs_per_s=round(n1 / dt1, 1),
+                                               seconds=round(dt1, 4), cores=1)
     res["other_workloads"] = other
-    return res, rgb
+    return res, rgb, rgb32
 
 
-def image_parity(gpu_rgb, ref_rgb, tol=2e-3):
-    """Per-pixel comparison of the rendered image with the binary64 oracle's:
-    a pixel is within tolerance when all three channels are."""
+def image_parity(gpu_rgb, ref_rgb, tol=2e-3, frac_bar=0.999, mean_bar=1e-5):
+    """Per-pixel comparison with the binary64 oracle's image: a pixel is
+    within tolerance when all three channels are; pass = both bars met."""
     import numpy as np
     d = np.abs(gpu_rgb.astype(np.float64) - ref_rgb.astype(np.float64))
     px = d.max(axis=0)
+    frac, mean = float((px <= tol).mean()), float(d.mean())
     return dict(reference="oracle binary64, same scene and camera", tolerance=tol,
-                frac_pixels_within=round(float((px <= tol).mean()), 6), max_abs=float(px.max()),
-                mean_abs=float(d.mean()), bar="frac_pixels_within >= 0.999 and mean_abs <= 1e-5")
+                frac_pixels_within=round(frac, 6), max_abs=float(px.max()), mean_abs=mean,
+                bar=f"frac_pixels_within >= {frac_bar} and mean_abs <= {mean_bar}",
+                passed=bool(frac >= frac_bar and mean <= mean_bar))
+
+
+def visible_bounds(scene, cam):
+    """P_z: Gaussians whose camera-space depth exceeds the near plane (the
+    Gaussians whose remaining attributes the method reads, Alg. 4)."""
+    import numpy as np
+    m = scene.means.astype(np.float64)
+    R = np.asarray(cam.R, np.float64)
+    z = R[2] @ m + float(cam.t[2])
+    return int(np.count_nonzero(z > cam.near))
+
+
+def tile_sort_bytes(N, ntiles):
+    """Bytes the design's tile sort moves: stable LSD passes of at most 8 bits
+    over the tile-id bits; keys are uint16 up to 65,536 tiles, else uint32;
+    per pass the upsweep reads the keys and the downsweep reads and writes
+    keys and values, except the last pass, which writes values only."""
+    bits = max(1, math.ceil(math.log2(max(ntiles, 2))))
+    passes = math.ceil(bits / 8) if ntiles > 1 else 0
+    kb = 2 if ntiles <= 65536 else 4
+    b = 0
+    for p in range(passes):
+        last = p == passes - 1
+        b += N * (kb + (kb + 4) + (4 if last else kb + 4))
+    return b, passes
+
+
+def stage_rooflines(stage_ms, stats, P, P_z, W, H, steps_exec):
+    """Per-stage achieved bandwidth or VALU rate against the MI355X peaks.
+    Algorithmic bytes: the method's (the hot-path scope table's per-unit
+    figures) for the preprocess; the design's own for the sort and the
+    emission (it sorts the depth digits once per Gaussian and the pairs by
+    tile id only)."""
+    V, N, cand = stats["visible"], stats["pairs"], stats["candidates"]
+    ntiles = stats["tiles_x"] * stats["tiles_y"]
+    tsort, tpasses = tile_sort_bytes(N, ntiles)
+    kb = 2 if ntiles <= 65536 else 4
+    rows = {}
+
+    def hbm(name, nbytes, ms, note):
+        if ms <= 0:
+            return
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        rows[name] = dict(bound="hbm", bytes=int(nbytes), ms=round(ms, 4), achieved_gbs=round(gbs, 1),
+                          frac=round(gbs / HBM_PEAK_GBS, 4), bytes_are=note)
+
+    hbm("cull", 24 * P, stage_ms["cull"], "24 B per Gaussian: position, opacity, trace of the covariance, k^2")
+    hbm("preprocess", 32 * P_z + 232 * V, stage_ms["preprocess"],
+        "method: 32 P_z (scales, rotation, opacity of the Gaussians past the near plane) + 192 P_vis (SH) + "
+        "40 P_vis (state written)")
+    hbm("cull_and_preprocess", 12 * P + 32 * P_z + 232 * V, stage_ms["cull"] + stage_ms["preprocess"],
+        "method: 12 P (means) + 32 P_z + 232 P_vis")
+    hbm("depth_sort", 80 * V, stage_ms["depth_sort"],
+        "design: 4 LSD passes over the visible (depth, index) pairs, 20 B per pair and pass")
+    hbm("tile_sort", tsort, stage_ms["tile_sort"],
+        f"design: {tpasses} LSD passes over the pairs by tile id ({kb}-byte ids): the upsweep reads the ids, "
+        "the downsweep reads and writes ids and values (the last pass values only)")
+    hbm("sort", 80 * V + tsort, stage_ms["depth_sort"] + stage_ms["tile_sort"],
+        "design: depth sort + tile sort (the method's full-key sort would move 8 N + 24 N per 8-bit key pass)")
+    hbm("emit", 24 * V + (kb + 4) * N + 8 * ntiles, stage_ms["emit"],
+        "design: order, offset and 16-byte record per visible Gaussian read, tile id and value per pair "
+        "written, empty ranges per tile")
+    hbm("scan", 17 * V, stage_ms["scan"], "design: order (4 B) and count (1 B) gathered, 12 B per visible "
+                                           "Gaussian written and read")
+    if steps_exec and stage_ms["blend"] > 0:
+        slots = steps_exec * 128 * BLEND_SLOTS_PER_EVAL
+        tops = slots / (stage_ms["blend"] * 1e-3) / 1e12
+        rows["blend"] = dict(bound="alu", slots=int(slots), ms=round(stage_ms["blend"], 4),
+                             achieved_tops=round(tops, 3), peak_tops=round(VALU_PEAK_TOPS, 2),
+                             frac=round(tops / VALU_PEAK_TOPS, 4),
+                             slots_are=f"(wavefront, entry) steps executed x 128 pixels x {BLEND_SLOTS_PER_EVAL} "
+                                       "VALU slots (14 operations + v_exp_f32 at quarter rate)")
+    return rows
+
+
+def dominant_roofline(rows, stage_ms, workload):
+    """The `roofline` object: the kernel with the longest launch of the frame
+    (the preprocess or the blend), with the HBM traffic of its committed
+    counter run when that run was taken on the current kernel sources."""
+    cands = [k for k in ("preprocess", "blend") if k in rows]
+    if not cands:
+        return None
+    k = max(cands, key=lambda c: stage_ms[c])
+    r = rows[k]
+    kernel = "k_preprocess" if k == "preprocess" else "k_blend"
+    prof = profile_record(kernel, workload)
+    traffic = prof.get("hbm_bytes_per_launch") if prof else None
+    if r["bound"] == "hbm":
+        out = dict(bound="hbm", achieved=r["achieved_gbs"], peak=HBM_PEAK_GBS, unit="GB/s", frac=r["frac"],
+                   traffic=traffic, kernel=kernel, algorithmic_bytes_per_launch=r["bytes"],
+                   avg_launch_ms=r["ms"], bytes_are=r["bytes_are"])
+    else:
+        out = dict(bound="alu", achieved=r["achieved_tops"], peak=r["peak_tops"], unit="TVALUop/s",
+                   frac=r["frac"], traffic=traffic, kernel=kernel, valu_slots_per_launch=r["slots"],
+                   avg_launch_ms=r["ms"], slots_are=r["slots_are"])
+    if prof:
+        out["counters"] = {k2: v for k2, v in prof.items() if k2 not in ("commands", "kernel_sha")}
+    return out
 
 
 SERVE_BUDGET = 3 << 30   # pair and sort buffers of admitted requests
@@ -127,7 +265,9 @@ def serving_leg(args):
     distributions, Poisson camera requests on the 200 m orbit with mixed
     resolutions, replayed natively through the render server (continuous
     batching, byte-budget admission, graph replay) and through the plain
-    one-request-at-a-time renderer on the same GPU."""
+    one-request-at-a-time renderer on the same GPU, both from the scene's
+    resident precompute (the plain renderer from the raw parameters as a
+    second reference)."""
     import torch
     from paper_2408_07967_amd import scenes
     from paper_2408_07967_amd.render import GaussianScene, Renderer
@@ -140,56 +280,60 @@ def serving_leg(args):
     warm = make_trace(400.0, 0.25, seed=6)
     log(f"[bench] serving: P={gsc.P}, {len(trace)} requests over {args.serve_seconds:.0f} s at "
         f"{args.serve_rate:.0f}/s (setup {time.perf_counter() - t0:.1f}s)")
+    rnd = lambda d: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
     R = Renderer(0)
-    replay_plain(R, gsc, None, warm)
-    plain = replay_plain(R, gsc, None, trace)
-    ps = latency_summary(plain)
-    log(f"[bench] plain renderer: {ps}")
-    R.close()
-    torch.cuda.synchronize()
+    prep = R.prepare(gsc)
+
+    def plain(tr, raw=False):
+        replay_plain(R, gsc, None, warm, prepared=None if raw else prep)
+        return latency_summary(replay_plain(R, gsc, None, tr, prepared=None if raw else prep))
+
     def server():
         return RenderServer(gsc, budget_bytes=SERVE_BUDGET, max_inflight=SERVE_SLOTS, max_bypass=4,
                             share_queue=SERVE_SHARE)
 
-    srv = server()
-    try:
-        srv.replay(warm)
-        res = srv.replay(trace)
-        st = srv.stats()
-    finally:
-        srv.close()
-    ss = latency_summary(res)
-    log(f"[bench] server: {ss} stats {st}")
-    rnd = lambda d: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
-    # load sweep on shorter traces of the same workload: at 4x the plain
-    # renderer can no longer keep up and its queue grows for the whole trace
-    sweep = []
-    for mult, secs in ((2.5, 8.0), (4.0, 4.0)):
-        rate = mult * args.serve_rate
-        tr = make_trace(rate, min(args.serve_seconds, secs), seed=7)
-        R = Renderer(0)
-        hp = latency_summary(replay_plain(R, gsc, None, tr))
-        R.close()
+    def served(tr):
         srv = server()
         try:
             srv.replay(warm)
-            hs = latency_summary(srv.replay(tr))
+            res = srv.replay(tr)
+            st = srv.stats()
         finally:
             srv.close()
+        return latency_summary(res), st
+
+    ps = plain(trace)
+    log(f"[bench] plain renderer (prepared scene): {ps}")
+    ss, st = served(trace)
+    log(f"[bench] server: {ss} stats {st}")
+    # the raw-parameter plain renderer on a shorter stretch of the same trace
+    tr_raw = [q for q in trace if q["t_ns"] < min(args.serve_seconds, 10.0) * 1e9]
+    pr = plain(tr_raw, raw=True)
+    log(f"[bench] plain renderer (raw parameters, first {len(tr_raw)} requests): {pr}")
+    sweep = []
+    for rate, secs in ((500.0, 8.0), (800.0, 5.0)):
+        tr = make_trace(rate, min(args.serve_seconds, secs), seed=7)
+        hp = plain(tr)
+        hs, _ = served(tr)
         log(f"[bench] at {rate:.0f}/s: plain {hp} server {hs}")
         sweep.append(dict(rate_per_s=rate, requests=len(tr), server=rnd(hs), plain=rnd(hp),
                           p50_ratio_plain_over_server=round(hp["p50_ms"] / hs["p50_ms"], 3),
                           p99_ratio_plain_over_server=round(hp["p99_ms"] / hs["p99_ms"], 3)))
+    R.release_prepared(prep)
+    R.close()
+    del gsc
+    torch.cuda.empty_cache()
     return dict(workload=f"serve-6M-gaussians-poisson{args.serve_rate:.0f}-{args.serve_seconds:.0f}s-"
                          f"720p-1080p-1440p-2160p",
                 requests=len(trace), server=rnd(ss), plain=rnd(ps),
+                plain_is="fgs_render_prepared one request at a time on the same resident precompute",
+                plain_raw_parameters=dict(rnd(pr), requests=len(tr_raw)),
                 p50_ratio_plain_over_server=round(ps["p50_ms"] / ss["p50_ms"], 3),
                 p99_ratio_plain_over_server=round(ps["p99_ms"] / ss["p99_ms"], 3),
                 load_sweep=sweep,
                 budget_bytes=SERVE_BUDGET, slots=SERVE_SLOTS, share_queue=SERVE_SHARE,
-                peak_bytes_in_use=st["peak_bytes_in_use"], graphs_captured=st["graphs_captured"],
-                graph_launches=st["graph_launches"], bypasses=st["bypasses"],
-                region_evictions=st["region_evictions"])
+                server_stats={k: st[k] for k in ("peak_bytes_in_use", "graphs_captured", "graph_launches",
+                                                 "bypasses", "region_evictions")})
 
 
 def differentiation_leg(steps):
@@ -237,7 +381,6 @@ def batch_leg(R, gsc, prep, W, H, opts, ncams, steps):
     same orientation) rendered by one batch call, against the same cameras
     rendered one call each.  Both sides have every input resident in HBM;
     frames/s counts camera images."""
-    import math
     import numpy as np
     import torch
     from paper_2408_07967_amd import scenes
@@ -269,6 +412,68 @@ def batch_leg(R, gsc, prep, W, H, opts, ncams, steps):
     return dict(cameras=ncams, rig="eye moved sideways in 2 m steps", batched_frames_per_s=round(batched, 2),
                 one_call_per_camera_frames_per_s=round(single, 2), speedup=round(batched / single, 4),
                 union_candidates=int(got[0]["stats"]["candidates"]), bit_identical=bool(same))
+
+
+def time_frames(R, gsc, cams, W, H, opts, steps, prepared):
+    """Frames/s of `steps` passes over `cams`, one request at a time (each
+    render call enqueues its frame; the stream orders them), and the stats
+    of the last frame of each camera."""
+    import torch
+    out = torch.empty((3, H, W), dtype=torch.float32, device="cuda:0")
+    stats = [R.render(gsc, c, W, H, opts, out=out, prepared=prepared)["stats"] for c in cams]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for c in cams:
+            R.render(gsc, c, W, H, opts, out=out, prepared=prepared)
+    torch.cuda.synchronize()
+    return steps * len(cams) / (time.perf_counter() - t0), stats, out
+
+
+def workloads_leg(R, city_sc, city_gsc, city_prep, opts, steps, with_parity):
+    """Frames/s and pairs/s of the other benchmark workloads, each from the
+    prepared scene and from the raw parameters: 10k Gaussians at 256x256;
+    1M Gaussians at 1920x1080 through the eight orbit cameras, one request
+    at a time; the 10M city scene at 7680x4320.  With parity: camera 0 of
+    the 1M workload and the 8K frame against the binary64 oracle."""
+    import numpy as np
+    import torch
+    from paper_2408_07967_amd import scenes
+    from paper_2408_07967_amd.render import GaussianScene
+    out = {}
+    for key in ("small", "medium", "city8k"):
+        wl = WORKLOADS[key]
+        W, H = wl["W"], wl["H"]
+        if key == "city8k":
+            sc, gsc, prep, owns = city_sc, city_gsc, city_prep, False
+        else:
+            sc = scenes.make_scene(wl["kind"])
+            gsc = GaussianScene.from_numpy(sc, "cuda:0")
+            prep, owns = R.prepare(gsc, opts), True
+        cams = [scenes.camera_for(wl["kind"], k, W=W, H=H) for k in range(8 if key == "medium" else 1)]
+        n = max(3, steps // (8 if key == "medium" else 1) // (4 if key == "city8k" else 1))
+        fps_p, st_p, img = time_frames(R, gsc, cams, W, H, opts, n, prep)
+        fps_r, _, _ = time_frames(R, gsc, cams, W, H, opts, max(2, n // 2), None)
+        pairs = [int(s["pairs"]) for s in st_p]
+        row = dict(workload=wl["name"], cameras=len(cams), frames_per_s=round(fps_p, 2),
+                   raw_params_frames_per_s=round(fps_r, 2),
+                   pairs_per_frame=pairs if len(pairs) > 1 else pairs[0],
+                   pairs_per_s=round(float(np.mean(pairs)) * fps_p, 1),
+                   visible=[int(s["visible"]) for s in st_p] if len(st_p) > 1 else int(st_p[0]["visible"]))
+        if with_parity and key in ("medium", "city8k"):
+            cam0 = cams[0]
+            o = R.render(gsc, cam0, W, H, opts, prepared=prep)["rgb"]
+            torch.cuda.synchronize()
+            _, _, ref = oracle_frame(sc, cam0, W, H, opts)
+            row["parity_camera0"] = image_parity(o.cpu().numpy(), ref)
+            del ref
+        log(f"[bench] workload {wl['name']}: {row}")
+        out[key] = row
+        if owns:
+            R.release_prepared(prep)
+            del gsc
+        torch.cuda.empty_cache()
+    return out
 
 
 def compare_binning(steps):
@@ -332,18 +537,18 @@ def main():
     ap.add_argument("--no-work-count", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-backward", action="store_true", help="skip the forward + backward timing")
+    ap.add_argument("--no-workloads", action="store_true", help="skip the 10k, 1M x 8 cameras and 8K legs")
     ap.add_argument("--blend-variant", type=int, default=0, choices=(0, 1),
                     help="0: LDS-batched blend (default); 1: prefetch-pipeline blend (same image)")
     ap.add_argument("--compare-binning", action="store_true",
                     help="also report pairs and stage times of the three binning modes")
-    ap.add_argument("--serve-seconds", type=float, default=20.0,
-                    help="length of the Poisson request trace (the full serving workload is 60 s)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="length of the Poisson request trace")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--batch-cameras", type=int, default=4,
                     help="cameras of the multi-camera batch leg (0 skips it)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed region, run one device copy of 256 MiB (read 256 MiB, write 256 MiB) "
-                         "whose FETCH_SIZE / WRITE_SIZE counters scale the blend kernel's counters")
+                         "whose FETCH_SIZE / WRITE_SIZE counters scale the kernels' counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this renderer runs on a single MI355X; "
@@ -361,7 +566,8 @@ def main():
     t0 = time.perf_counter()
     sc = scenes.make_scene(wl["kind"])
     cam = scenes.camera_for(wl["kind"], W=W, H=H)
-    log(f"[bench] scene {wl['kind']} P={sc.P} drawn in {time.perf_counter() - t0:.1f}s")
+    P_z = visible_bounds(sc, cam)
+    log(f"[bench] scene {wl['kind']} P={sc.P} drawn in {time.perf_counter() - t0:.1f}s; {P_z} past the near plane")
     torch.cuda.set_device(0)
     gsc = GaussianScene.from_numpy(sc, "cuda:0")
     R = Renderer(0)
@@ -390,13 +596,15 @@ def main():
     torch.cuda.synchronize()
     log(f"[bench] prepared in {prep_ms:.1f} ms; warmup done")
 
-    evals = None
+    evals = steps_exec = None
     if not args.no_work_count:
         R.set_instrumentation(B.INSTR_WORK)
         R.render(gsc, cam, W, H, opts, out=out, prepared=prep)
-        evals = int(R.instrumentation()["blend_evaluations"])
+        inst = R.instrumentation()
+        evals, steps_exec = int(inst["blend_evaluations"]), int(inst["blend_wave_steps"])
         R.set_instrumentation(0)
-        log(f"[bench] blend evaluations per frame: {evals}")
+        log(f"[bench] blend: {evals} evaluations per frame (method), {steps_exec} wavefront steps executed "
+            f"({steps_exec * 128} pixel evaluations)")
 
     # the timed frames run without instrumentation
     R.set_instrumentation(0)
@@ -438,27 +646,20 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    roof = None
-    if evals is not None and stage_ms["blend"] > 0:
-        achieved = evals * FLOP_PER_EVAL / (stage_ms["blend"] * 1e-3) / 1e12
-        roof = dict(bound="alu", achieved=round(achieved, 3), peak=round(PEAK_ALU_TFLOPS, 1), unit="TFLOP/s",
-                    frac=round(achieved / PEAK_ALU_TFLOPS, 4),
-                    traffic=traffic_from_profiles(args.workload, evals),
-                    kernel="k_blend", evaluations_per_launch=evals, flop_per_evaluation=FLOP_PER_EVAL,
-                    avg_launch_ms=stage_ms["blend"])
+    rows = stage_rooflines(stage_ms, stats, sc.P, P_z, W, H, steps_exec)
+    roof = dominant_roofline(rows, stage_ms, args.workload)
+    log(f"[bench] rooflines {rows}")
 
     cpu = None
     parity = None
     if not args.no_cpu_baseline:
-        log("[bench] timing the CPU oracle on one frame ...")
-        cpu, ref_rgb = cpu_baseline(sc, cam, W, H, opts)
+        log("[bench] timing the CPU oracle ...")
+        cpu, ref_rgb, f32_rgb = cpu_baseline(sc, cam, W, H, opts)
         log(f"[bench] cpu baseline {cpu}")
         parity = image_parity(out.cpu().numpy(), ref_rgb)
-        # the same comparison for the oracle's own binary32 mode: what binary32
-        # arithmetic reaches on this frame
-        _, _, f32_rgb = oracle_frame(sc, cam, W, H, opts, "f32")
+        # the same comparison for the oracle's own binary32 mode
         parity["oracle_binary32_vs_binary64"] = {k: v for k, v in image_parity(f32_rgb, ref_rgb).items()
-                                                 if k in ("frac_pixels_within", "max_abs", "mean_abs")}
+                                                 if k in ("frac_pixels_within", "max_abs", "mean_abs", "passed")}
         del ref_rgb, f32_rgb
         log(f"[bench] image parity {parity}")
 
@@ -466,9 +667,13 @@ def main():
     if args.batch_cameras > 0:
         batch = batch_leg(R, gsc, prep, W, H, opts, args.batch_cameras, max(3, args.steps // 10))
         log(f"[bench] multi-camera batch: {batch}")
+    others = None
+    if not args.no_workloads and args.workload == "city4k":
+        others = workloads_leg(R, sc, gsc, prep, opts, max(20, args.steps // 2), with_parity=not args.no_cpu_baseline)
     R.release_prepared(prep)
     R.close()
     del gsc, out
+    torch.cuda.empty_cache()
     serving = None
     if not args.no_serve:
         serving = serving_leg(args)
@@ -485,12 +690,13 @@ def main():
                            blend_variant="prefetch pipeline" if args.blend_variant else "LDS batches",
                            raw_params_frames_per_s=round(raw_fps, 3), prepare_ms=round(prep_ms, 2),
                            visible=int(stats["visible"]), pairs=int(stats["pairs"]),
+                           candidates=int(stats["candidates"]), past_near_plane=P_z,
                            big_rect_chunks=int(stats["big_chunks"]),
-                           candidates=int(stats["candidates"]),
                            pairs_per_s=round(stats["pairs"] * fps, 1), stage_ms=stage_ms,
-                           single_frame_ms=frame_ms),
-               roofline=roof, cpu_baseline=cpu, parity=parity, serving=serving, differentiation=differentiation,
-               multi_camera=batch)
+                           single_frame_ms=frame_ms,
+                           blend_evaluations=evals, blend_wave_steps=steps_exec),
+               roofline=roof, stage_roofline=rows, cpu_baseline=cpu, parity=parity, workloads=others,
+               serving=serving, differentiation=differentiation, multi_camera=batch)
     if binning_modes is not None:
         res["binning_modes"] = binning_modes
     print(json.dumps(res), flush=True)

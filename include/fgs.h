@@ -188,11 +188,12 @@ fgs_status fgs_plan(fgs_context *ctx, const fgs_scene *scene, const fgs_camera *
 /* The paper moves preprocessing shared by the viewpoints of one scene to an
  * initial stage (Sec. 5.3.1).  fgs_prepare_scene computes, once, the
  * view-independent part of every Gaussian: opacity (0 for a Gaussian that can
- * never be visible), 3D covariance, extent k^2 and log2 opacity, and the SH
- * coefficients Gaussian-major, so a frame reads 16 bytes for every Gaussian,
- * 32 more for those in front of the camera and one contiguous run of SH for
- * the visible ones.  Device memory owned by the context: 48 B + 4 ceil4(3 (D+1)^2)
- * B per Gaussian (240 B at degree 3).  It depends on the scene's values
+ * never be visible), scales and unit quaternion, extent k^2, a bound of the
+ * screen extent (trace of the 3D covariance), and the SH coefficients
+ * Gaussian-major, so a frame reads 24 bytes for every Gaussian, 48 more for
+ * the candidates of its cull and one contiguous run of SH for the visible
+ * ones.  Device memory owned by the context: 56 B + 4 ceil4(3 (D+1)^2) B per
+ * Gaussian (248 B at degree 3).  It depends on the scene's values
  * (copy of the fgs_scene struct kept; the planes must stay valid and
  * unchanged for backward passes) and on opt->alpha_min and opt->cap_3sigma.
  * Frames rendered from it are bit-identical to fgs_render of the scene.
@@ -266,9 +267,13 @@ fgs_status fgs_frame_release(fgs_context *ctx, fgs_frame *frame);
 
 /* Introspection of a saved frame for tests and tools: copies one field to
  * host memory (synchronising the frame's stream).  Fields and layouts:
- *   FGS_FIELD_GAUSS   [P][12] float: u, v, conic A, B, C, k^2, log2(o),
- *                     r, g, b, depth, o (valid Gaussians only; others are 0
- *                     for a prepared scene's frame and unspecified otherwise)
+ *   FGS_FIELD_GAUSS   [P][16] float: u, v, conic A, B, C, k^2, log2(o),
+ *                     r, g, b, depth, o, blend conic Ab, Bb, Cb, 0 (valid
+ *                     Gaussians only; others are 0 for a prepared scene's
+ *                     frame and unspecified otherwise).  A, B, C is the
+ *                     canonical binary32 conic that decides the pairs; the
+ *                     blend evaluates pixels with Ab, Bb, Cb, the same conic
+ *                     computed in binary64 and rounded once
  *   FGS_FIELD_RECT    [P][4] int32: tx0, tx1, ty0, ty1 (valid only)
  *   FGS_FIELD_COUNT   [P] uint32 exact tile count (0 for culled Gaussians)
  *   FGS_FIELD_ORDER   [visible] uint32 Gaussian indices in (depth, index) order
@@ -294,7 +299,9 @@ typedef enum {
 
 typedef struct {
     int64_t frames;            /* instrumented frames folded into the sums below     */
-    double ms_preprocess;      /* summed stage times over those frames (ms)          */
+    double ms_preprocess;      /* summed stage times over those frames (ms); the
+                                  preprocess kernel alone (a prepared scene's cull
+                                  is ms_cull)                                        */
     double ms_depth_sort;
     double ms_scan;
     double ms_emit;
@@ -305,6 +312,11 @@ typedef struct {
                                   list entries the pixel examines (up to and including
                                   the entry at which it stops, else the whole list),
                                   summed over the instrumented frames                */
+    double ms_cull;            /* the cull of a prepared scene (0 for raw parameters) */
+    int64_t blend_wave_steps;  /* with FGS_INSTR_WORK: (wavefront, list entry) steps the
+                                  blend executes; each evaluates one entry at the
+                                  wavefront's 128 pixels (entries that miss the
+                                  wavefront's half tile are skipped)                 */
 } fgs_timings;
 
 /* Select instrumentation flags for later fgs_render calls and clear the sums. */
@@ -430,6 +442,14 @@ fgs_status fgs_server_replay(fgs_server *srv, const fgs_trace_request *trace, in
 fgs_status fgs_replay_plain(fgs_context *ctx, const fgs_scene *scene, const fgs_options *opt,
                             const fgs_trace_request *trace, int64_t n, float *rgb_scratch,
                             fgs_server_result *results, void *stream);
+
+/* The same replay from a prepared scene of ctx (fgs_render_prepared per
+ * request): the plain renderer with the resident precompute the server
+ * keeps, so that a comparison with the server measures the serving machinery
+ * alone.  INVALID_ARGUMENT also for a NULL prepared scene. */
+fgs_status fgs_replay_plain_prepared(fgs_context *ctx, const fgs_prepared *prepared, const fgs_options *opt,
+                                     const fgs_trace_request *trace, int64_t n, float *rgb_scratch,
+                                     fgs_server_result *results, void *stream);
 
 #ifdef __cplusplus
 }

@@ -43,6 +43,16 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Threads of later parallel regions (the benchmark's single-thread baseline). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 #define ORC_LN2_HI 0x1.62e42fee00000p-1
 #define ORC_LN2_LO 0x1.a39ef35793c76p-33
 #define ORC_INV_LN2 0x1.71547652b82fep+0

@@ -52,7 +52,8 @@ class FgsStats(C.Structure):
 class FgsTimings(C.Structure):
     _fields_ = [("frames", C.c_int64), ("ms_preprocess", C.c_double), ("ms_depth_sort", C.c_double),
                 ("ms_scan", C.c_double), ("ms_emit", C.c_double), ("ms_tile_sort", C.c_double),
-                ("ms_ranges", C.c_double), ("ms_blend", C.c_double), ("blend_evaluations", C.c_int64)]
+                ("ms_ranges", C.c_double), ("ms_blend", C.c_double), ("blend_evaluations", C.c_int64),
+                ("ms_cull", C.c_double), ("blend_wave_steps", C.c_int64)]
 
 
 INSTR_STAGE_TIMES = 1
@@ -135,6 +136,9 @@ PROTOTYPES = {
     "fgs_replay_plain": (C.c_int, [C.c_void_p, C.POINTER(FgsScene), C.POINTER(FgsOptions),
                                    C.POINTER(FgsTraceRequest), C.c_int64, C.c_void_p, C.POINTER(FgsServerResult),
                                    C.c_void_p]),
+    "fgs_replay_plain_prepared": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(FgsOptions),
+                                            C.POINTER(FgsTraceRequest), C.c_int64, C.c_void_p,
+                                            C.POINTER(FgsServerResult), C.c_void_p]),
 }
 
 _lib = None

@@ -23,6 +23,15 @@ struct DevCamera {
     float fx, fy, cx, cy, near_z;
 };
 
+// The camera in binary64 for the blend's conic (see GaussState): rotation,
+// translation and focal lengths promoted from the binary32 camera, and the
+// Jacobian clamp limits jac_clip (W / 2) / fx, jac_clip (H / 2) / fy.
+// Computed on the host, so that the kernels read them as uniform arguments.
+struct DevCam64 {
+    double R[9], t[3];
+    double fx, fy, limx, limy;
+};
+
 struct DevOptions {
     float alpha_min, T_stop, alpha_max, dilation, jac_clip;
     float bg[3];
@@ -38,16 +47,25 @@ struct DevScene {
 // View-independent precompute of a resident scene (see launch_prepare).
 struct DevPrepared {
     const float4 *pos_o;  // (x, y, z, opacity); opacity 0: never visible
-    const float4 *cov;    // 2 per Gaussian: (S00, S01, S02, S11), (S12, S22, k^2, log2 o)
+    const float4 *cov;    // 2 per Gaussian: (s0, s1, s2, k^2), (w, x, y, z): scales exp(log-scale)
+                          // and the unit quaternion, both binary32 as the canonical evaluation rounds them
     const float *sh;      // Gaussian-major SH, sh_stride floats per Gaussian
     const float2 *bnd;    // (trace of the 3D covariance, k^2): bounds the screen extent
     int sh_stride;
 };
 
-// Per-Gaussian state for the blend, 48 bytes = 3 x float4.
-//   f0 = (u, v, A, B)   f1 = (C, k2, log2 o, r)   f2 = (g, b, depth, o)
+// Per-Gaussian state, 64 bytes = 4 x float4.
+//   f0 = (u, v, Ab, Bb)   f1 = (Cb, k2, log2 o, r)   f2 = (g, b, depth, o)
+//   f3 = (A, B, C, 0)
+// (A, B, C) is the conic of the canonical binary32 evaluation: it decides the
+// Gaussian-tile pairs (exact tile test) bit for bit.  (Ab, Bb, Cb) is the
+// same conic evaluated in binary64 from the binary32 scales and unit
+// quaternion and rounded once: the blend and its adjoint evaluate pixels with
+// it.  For long thin footprints the binary32 inverse of the dilated 2D
+// covariance loses most of its bits to cancellation in the determinant; the
+// binary64 one keeps the narrow axis.  The blend reads f0..f2 only.
 struct alignas(16) GaussState {
-    float4 f0, f1, f2;
+    float4 f0, f1, f2, f3;
 };
 
 // Frame-scoped device counters, cleared at the start of a frame.
@@ -109,8 +127,11 @@ constexpr int kCullBlocks = 2048;
 // 1-byte array, which the L2 caches hold whole.
 constexpr uint8_t kCount8Big = 255;
 // gsum_clear: kGsumWords counters cleared (the first depth pass's group sums).
-void launch_preprocess(const DevScene &sc, const DevPrepared *pp, const DevCamera &cam, const DevOptions &op,
-                       int W, int H, GaussState *gs, uint4 *rect, uint32_t *count, uint8_t *count8, uint4 *erec,
+// With a precompute, launch_cull runs first (the preprocess reads its lists).
+void launch_cull(const DevScene &sc, const DevPrepared &pp, const DevCamera &cam, const DevOptions &op, int W, int H,
+                 uint32_t *cand, uint32_t *seg_count, FrameCounters *fc, hipStream_t s);
+void launch_preprocess(const DevScene &sc, const DevPrepared *pp, const DevCamera &cam, const DevCam64 &cam64,
+                       const DevOptions &op, int W, int H, GaussState *gs, uint4 *rect, uint32_t *count, uint8_t *count8, uint4 *erec,
                        uint32_t *dkey,
                        uint32_t *cand, uint32_t *seg_count, uint32_t *gmap, uint2 *chunks, uint32_t chunk_cap,
                        FrameCounters *fc, uint32_t *gsum_clear, hipStream_t s);
@@ -125,6 +146,7 @@ void launch_preprocess(const DevScene &sc, const DevPrepared *pp, const DevCamer
 constexpr int kMaxCams = 8;  // FGS_MAX_BATCH_CAMERAS
 struct CamOut {
     DevCamera cam;
+    DevCam64 cam64;
     GaussState *gs;
     uint4 *rect;
     uint32_t *count;
@@ -204,8 +226,9 @@ void launch_count_scan(const uint32_t *order, const uint8_t *count8, const uint3
 // A one-tile image: ranges[0] = [0, min(*n_dev, n)).
 void launch_single_range(uint2 *ranges, uint32_t n, const uint32_t *n_dev, hipStream_t s);
 
-// work: if non-null, the blend adds the number of list entries every pixel
-// examines (a separate, slower kernel instantiation)
+// work: if non-null, work[0] += the number of list entries every pixel
+// examines, work[1] += the (wavefront, entry) steps the blend executes (a
+// separate, slower kernel instantiation)
 // variant: 0 the LDS-batched blend; 1 the prefetch-pipeline blend (same
 // image bit for bit; not with work).  nvalues, ngs: entries held by the
 // values and gs buffers (the bounds of the variant's buffer loads).

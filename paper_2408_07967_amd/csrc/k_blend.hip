@@ -106,6 +106,7 @@ __global__ __launch_bounds__(kThreads) void k_blend(const GaussState *__restrict
     // value, so the minimum needs no per-iteration canonicalisation)
     const float amax = op.alpha_max + 0.0f;
     const float tstop = op.T_stop;
+    uint32_t wsteps = 0;  // kCountWork: entries this wavefront evaluates (uniform)
 
     for (uint32_t b0 = start; b0 < end; b0 += kBatch) {
         const uint32_t nb = (end - b0) < (uint32_t)kBatch ? (end - b0) : (uint32_t)kBatch;
@@ -151,6 +152,7 @@ __global__ __launch_bounds__(kThreads) void k_blend(const GaussState *__restrict
                 // one staged Gaussian for both pixels of the lane; true once
                 // every pixel of the wavefront has stopped
                 auto blend_one = [&](int j) {
+                    if (kCountWork) ++wsteps;
                     const float4 f0 = s_f0[j], f1 = s_f1[j];
                     const float2 f2 = *reinterpret_cast<const float2 *>(&s_f2[j]);
                     const RowTerms rt = row_terms(f0, f1, py);
@@ -191,7 +193,10 @@ __global__ __launch_bounds__(kThreads) void k_blend(const GaussState *__restrict
         unsigned long long v = (unsigned long long)p0.examined + p1.examined;
 #pragma unroll
         for (int d = 1; d < kWave; d <<= 1) v += __shfl_xor(v, d, kWave);
-        if (lane == 0) atomicAdd(work, v);
+        if (lane == 0) {
+            atomicAdd(work, v);
+            atomicAdd(work + 1, (unsigned long long)wsteps);
+        }
     }
     const size_t hw = (size_t)W * H;
     const size_t q = (size_t)pj * W + pi0;

@@ -202,18 +202,30 @@ __device__ __forceinline__ int small_div(uint32_t k, int n) {
     return (int)(((float)k + 0.5f) * __builtin_amdgcn_rcpf((float)n));
 }
 
-// 3D covariance Sigma = M M^T with M = R(q / |q|) diag(exp(log-scale))
-// (computeCov3D), upper triangle S00, S01, S02, S11, S12, S22.  False for a
+// Scales exp(log-scale) and the unit quaternion q / |q| (computeCov3D's
+// inputs), as the binary32 values of the canonical evaluation.  False for a
 // non-finite scale or a quaternion of zero or non-finite norm.
-__device__ __forceinline__ bool cov3d(float ls0, float ls1, float ls2, const float *q4, float *S) {
+__device__ __forceinline__ bool scale_rot(float ls0, float ls1, float ls2, const float *q4, float *s3, float *qu) {
     const float qw = q4[0], qx = q4[1], qy = q4[2], qz = q4[3];
-    const float s0 = (float)canon_exp((double)ls0), s1 = (float)canon_exp((double)ls1),
-                s2 = (float)canon_exp((double)ls2);
+    s3[0] = (float)canon_exp((double)ls0);
+    s3[1] = (float)canon_exp((double)ls1);
+    s3[2] = (float)canon_exp((double)ls2);
     const float n2 = ((qw * qw + qx * qx) + qy * qy) + qz * qz;
     const bool fin = isfinite(ls0) && isfinite(ls1) && isfinite(ls2) && isfinite(n2);
     if (!(fin && n2 > 0.0f)) return false;
     const float qn = sqrtf(n2);
-    const float w = qw / qn, x = qx / qn, y = qy / qn, z = qz / qn;
+    qu[0] = qw / qn;
+    qu[1] = qx / qn;
+    qu[2] = qy / qn;
+    qu[3] = qz / qn;
+    return true;
+}
+
+// 3D covariance Sigma = M M^T with M = R(q) diag(s) (computeCov3D), upper
+// triangle S00, S01, S02, S11, S12, S22, in binary32.
+__device__ __forceinline__ void sigma3(const float *s3, const float *qu, float *S) {
+    const float s0 = s3[0], s1 = s3[1], s2 = s3[2];
+    const float w = qu[0], x = qu[1], y = qu[2], z = qu[3];
     const float r00 = 1.0f - 2.0f * (y * y + z * z);
     const float r01 = 2.0f * (x * y - w * z);
     const float r02 = 2.0f * (x * z + w * y);
@@ -232,6 +244,55 @@ __device__ __forceinline__ bool cov3d(float ls0, float ls1, float ls2, const flo
     S[3] = (M10 * M10 + M11 * M11) + M12 * M12;
     S[4] = (M10 * M20 + M11 * M21) + M12 * M22;
     S[5] = (M20 * M20 + M21 * M21) + M22 * M22;
+}
+
+// Conic of the dilated EWA covariance in binary64, rounded once to binary32
+// (the blend's conic, see GaussState).  The inputs are the binary32 scales,
+// unit quaternion, mean and camera, promoted to binary64 (c: the camera and
+// its Jacobian clamp limits in binary64); the Jacobian clamp is the same.
+// With M = R(q) diag(s) and T = J R_cam, Sigma' = T M M^T T^T + dilation I =
+// N N^T + dilation I for N = T M, accumulated one column of M at a time (the
+// product the canonical evaluation forms as T Sigma T^T).  The binary32
+// determinant of Sigma' cancels badly for long thin footprints; in binary64
+// the narrow axis keeps its accuracy.  False if the binary64 determinant is
+// not positive.
+__device__ bool conic_b64(const float *s3, const float *qu, float mx, float my, float mz, const DevCam64 &c,
+                          double dil, float *Ab, float *Bb, float *Cb) {
+    const double px = mx, py = my, pz = mz;
+    const double tx = c.R[0] * px + c.R[1] * py + c.R[2] * pz + c.t[0];
+    const double ty = c.R[3] * px + c.R[4] * py + c.R[5] * pz + c.t[1];
+    const double tz = c.R[6] * px + c.R[7] * py + c.R[8] * pz + c.t[2];
+    const double iz = 1.0 / tz;
+    double xc = tx * iz, yc = ty * iz;
+    xc = xc < -c.limx ? -c.limx : (xc > c.limx ? c.limx : xc);
+    yc = yc < -c.limy ? -c.limy : (yc > c.limy ? c.limy : yc);
+    const double J00 = c.fx * iz, J02 = -(c.fx * xc) * iz, J11 = c.fy * iz, J12 = -(c.fy * yc) * iz;
+    double T0[3], T1[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        T0[j] = J00 * c.R[j] + J02 * c.R[6 + j];
+        T1[j] = J11 * c.R[3 + j] + J12 * c.R[6 + j];
+    }
+    const double w = qu[0], x = qu[1], y = qu[2], z = qu[3];
+    double a = 0.0, b = 0.0, cc = 0.0;
+    auto column = [&](double r0, double r1, double r2, double sj) {
+        const double n0 = (T0[0] * r0 + T0[1] * r1 + T0[2] * r2) * sj;
+        const double n1 = (T1[0] * r0 + T1[1] * r1 + T1[2] * r2) * sj;
+        a += n0 * n0;
+        b += n0 * n1;
+        cc += n1 * n1;
+    };
+    column(1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y + w * z), 2.0 * (x * z - w * y), (double)s3[0]);
+    column(2.0 * (x * y - w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z + w * x), (double)s3[1]);
+    column(2.0 * (x * z + w * y), 2.0 * (y * z - w * x), 1.0 - 2.0 * (x * x + y * y), (double)s3[2]);
+    a += dil;
+    cc += dil;
+    const double det = a * cc - b * b;
+    if (!(det > 0.0)) return false;
+    const double inv = 1.0 / det;
+    *Ab = (float)(cc * inv);
+    *Bb = (float)(-b * inv);
+    *Cb = (float)(a * inv);
     return true;
 }
 
@@ -244,9 +305,10 @@ __device__ __forceinline__ float extent_k2(float o, const DevOptions &op) {
 
 // View-independent precompute of a resident scene (Sec. 5.3.1: preprocessing
 // shared by the viewpoints of one scene): per Gaussian (x, y, z, opacity) with
-// opacity 0 for a Gaussian that can never be visible, the 3D covariance with
-// k^2 and log2(opacity), and the SH coefficients Gaussian-major.  The same
-// operations as the per-frame path, so frames render bit for bit the same.
+// opacity 0 for a Gaussian that can never be visible, the scales, the unit
+// quaternion and k^2, the trace of the 3D covariance with k^2 (the cull's
+// extent bound), and the SH coefficients Gaussian-major.  The same operations
+// as the per-frame path, so frames render bit for bit the same.
 __global__ __launch_bounds__(kBlock) void k_prepare(DevScene sc, DevOptions op, float4 *__restrict__ pos_o,
                                                     float4 *__restrict__ cov, float *__restrict__ sh_out,
                                                     float2 *__restrict__ bnd, int sh_stride) {
@@ -257,20 +319,20 @@ __global__ __launch_bounds__(kBlock) void k_prepare(DevScene sc, DevOptions op, 
         const float mx = sc.means[g], my = sc.means[st + g], mz = sc.means[2 * st + g];
         const float logit = sc.logits[g];
         const float o = (float)(1.0 / (1.0 + canon_exp(-(double)logit)));
-        float S[6] = {0, 0, 0, 0, 0, 0};
-        float k2 = 0.0f, l2o = 0.0f;
+        float S[6] = {0, 0, 0, 0, 0, 0}, s3[3] = {0, 0, 0}, qu[4] = {0, 0, 0, 0};
+        float k2 = 0.0f;
         bool ok = isfinite(logit) && o > op.alpha_min;
         if (ok) {
             const float q4[4] = {sc.quats[g], sc.quats[st + g], sc.quats[2 * st + g], sc.quats[3 * st + g]};
-            ok = cov3d(sc.log_scales[g], sc.log_scales[st + g], sc.log_scales[2 * st + g], q4, S);
+            ok = scale_rot(sc.log_scales[g], sc.log_scales[st + g], sc.log_scales[2 * st + g], q4, s3, qu);
         }
         if (ok) {
+            sigma3(s3, qu, S);
             k2 = extent_k2(o, op);
-            l2o = log2f(o);
         }
         pos_o[g] = make_float4(mx, my, mz, ok ? o : 0.0f);
-        cov[2 * g] = make_float4(S[0], S[1], S[2], S[3]);
-        cov[2 * g + 1] = make_float4(S[4], S[5], k2, l2o);
+        cov[2 * g] = make_float4(s3[0], s3[1], s3[2], k2);
+        cov[2 * g + 1] = make_float4(qu[0], qu[1], qu[2], qu[3]);
         // trace(Sigma) >= its largest eigenvalue: bounds the screen extent
         bnd[g] = make_float2(S[0] + S[3] + S[5], k2);
     }
@@ -407,7 +469,7 @@ __global__ __launch_bounds__(kBlock) void k_cull(DevScene sc, DevPrepared pp, De
 // for the second and later cameras follow the first within the same
 // wavefront and hit the caches.
 template <bool kPrep, bool kMulti = false>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_preprocess(DevScene sc, DevPrepared pp, DevCamera cam, DevOptions op,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_preprocess(DevScene sc, DevPrepared pp, DevCamera cam, DevCam64 cam64, DevOptions op,
                                                        int W, int H, GaussState *__restrict__ gs,
                                                        uint4 *__restrict__ rect, uint32_t *__restrict__ count,
                                                        uint8_t *__restrict__ count8, uint4 *__restrict__ erec,
@@ -474,12 +536,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         base = (uint32_t)__shfl((int)base, 0, kWave);
         const bool ok = (uint64_t)base + w_nch <= chunk_cap;
         if (!ok && ln == 0) atomicOr(&fc->error, kErrChunkOverflow);
-        if (ok) {
-            for (uint32_t e = (uint32_t)ln; e < w_nbig; e += kWave) {
-                const uint32_t gg = s_bg[wv][e], first = base + s_boff[wv][e], n = s_bn[wv][e];
+        for (uint32_t e = (uint32_t)ln; e < w_nbig; e += kWave) {
+            const uint32_t gg = s_bg[wv][e], first = base + s_boff[wv][e], n = s_bn[wv][e];
+            if (ok)
                 for (uint32_t c = 0; c < n; ++c) chunks[first + c] = make_uint2(gg, first);
-                erec[gg] = make_uint4(s_bx[wv][e], s_by[wv][e], 0u, first);
-            }
+            // (on overflow the record still marks the rectangle as chunked, so
+            // that the emission of this frame reads no record of an earlier one)
+            erec[gg] = make_uint4(s_bx[wv][e], s_by[wv][e], 0u, ok ? first : 0u);
         }
         // every lane has read the list before it is refilled
         __builtin_amdgcn_wave_barrier();
@@ -510,8 +573,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         for (uint32_t e = (uint32_t)ln; e < w_nbig; e += kWave) {
             const uint32_t c = s_bc[wv][e], base = s_cbase[wv][c];
-            if (base == kNoBase) continue;
-            const uint32_t gg = s_bg[wv][e], first = base + s_boff[wv][e], n = s_bn[wv][e];
+            const uint32_t gg = s_bg[wv][e];
+            if (base == kNoBase) {
+                // overflow: still mark the rectangle as chunked (no stale record)
+                s_erec[c][gg] = make_uint4(s_bx[wv][e], s_by[wv][e], 0u, 0u);
+                continue;
+            }
+            const uint32_t first = base + s_boff[wv][e], n = s_bn[wv][e];
             uint2 *const ck = s_chunks[c];
             for (uint32_t k = 0; k < n; ++k) ck[first + k] = make_uint2(gg, first);
             s_erec[c][gg] = make_uint4(s_bx[wv][e], s_by[wv][e], 0u, first);
@@ -590,6 +658,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     for (int ci = 0; ci < ncams; ++ci) {
     // this camera and its outputs
     const DevCamera &cm = kMulti ? mo.c[ci].cam : cam;
+    const DevCam64 &cm64 = kMulti ? mo.c[ci].cam64 : cam64;
     GaussState *__restrict__ const gs_c = kMulti ? mo.c[ci].gs : gs;
     uint4 *__restrict__ const rect_c = kMulti ? mo.c[ci].rect : rect;
     uint32_t *__restrict__ const count_c = kMulti ? mo.c[ci].count : count;
@@ -599,6 +668,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const int64_t st = sc.stride;
     bool valid = false;
     float u = 0, v = 0, A = 0, B = 0, C = 0, k2 = 0, o = 0, tz = 0, l2o = 0;
+    float Ab = 0, Bb = 0, Cb = 0;  // the blend's conic (see GaussState)
     int tx0 = 0, tx1 = -1, ty0 = 0, ty1 = -1;
     float col[3] = {0, 0, 0};
 
@@ -624,7 +694,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         // read only for Gaussians in front of the camera
         if (tz > cm.near_z && isfinite(mx) && isfinite(my) && isfinite(mz)) {
             bool ok = false;
-            float S[6] = {0, 0, 0, 0, 0, 0};
+            float S[6] = {0, 0, 0, 0, 0, 0}, s3[3] = {0, 0, 0}, qu[4] = {0, 0, 0, 0};
             float log2o = 0.0f;
             if constexpr (kPrep) {
                 // view-independent part precomputed once (Sec. 5.3.1); an
@@ -633,9 +703,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 ok = o > op.alpha_min;
                 if (ok) {
                     const float4 c0 = pp.cov[2 * g], c1 = pp.cov[2 * g + 1];
-                    S[0] = c0.x; S[1] = c0.y; S[2] = c0.z; S[3] = c0.w; S[4] = c1.x; S[5] = c1.y;
-                    k2 = c1.z;
-                    log2o = c1.w;
+                    s3[0] = c0.x; s3[1] = c0.y; s3[2] = c0.z;
+                    k2 = c0.w;
+                    qu[0] = c1.x; qu[1] = c1.y; qu[2] = c1.z; qu[3] = c1.w;
                 }
             } else {
                 const float logit = sc.logits[g];
@@ -645,14 +715,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                     const float ls0 = sc.log_scales[g], ls1 = sc.log_scales[st + g],
                                 ls2 = sc.log_scales[2 * st + g];
                     const float q4[4] = {sc.quats[g], sc.quats[st + g], sc.quats[2 * st + g], sc.quats[3 * st + g]};
-                    ok = cov3d(ls0, ls1, ls2, q4, S);
-                    if (ok) {
-                        k2 = extent_k2(o, op);
-                        log2o = log2f(o);
-                    }
+                    ok = scale_rot(ls0, ls1, ls2, q4, s3, qu);
+                    if (ok) k2 = extent_k2(o, op);
                 }
             }
             if (ok) {
+                sigma3(s3, qu, S);
+                log2o = log2f(o);
+                // the blend's conic (binary64, rounded once)
+                const bool have_b64 = conic_b64(s3, qu, mx, my, mz, cm64, (double)op.dilation, &Ab, &Bb, &Cb);
                 const float S00 = S[0], S01 = S[1], S02 = S[2], S11 = S[3], S12 = S[4], S22 = S[5];
                 {
                     // pinhole projection (project + ndc2Pix)
@@ -685,6 +756,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                         A = cc / det;
                         B = (-cb) / det;
                         C = ca / det;
+                        // the blend's conic: the binary32 one if the binary64
+                        // determinant was not positive
+                        if (!have_b64) {
+                            Ab = A;
+                            Bb = B;
+                            Cb = C;
+                        }
                         // rectangle tangent to the ellipse (Sec. 4.1), in pixel samples;
                         // binning 2: the square of the 3 sigma circle of 3DGS
                         // (Alg. 1: radius ceil(3 sqrt(lambda_max)) of Sigma')
@@ -846,9 +924,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         count8_c[oi] = chunked ? kCount8Big : (uint8_t)(valid ? cnt : 0u);  // cnt <= kBigTiles < kCount8Big
         if (valid) {
             GaussState s;
-            s.f0 = make_float4(u, v, A, B);
-            s.f1 = make_float4(C, k2, l2o, col[0]);
+            s.f0 = make_float4(u, v, Ab, Bb);
+            s.f1 = make_float4(Cb, k2, l2o, col[0]);
             s.f2 = make_float4(col[1], col[2], tz, o);
+            s.f3 = make_float4(A, B, C, 0.0f);
             gs_c[oi] = s;
             rect_c[oi] = make_uint4((uint32_t)tx0, (uint32_t)tx1, (uint32_t)ty0, (uint32_t)ty1);
             // emission record: rectangle (4 x 16 bits) and hit mask in one
@@ -927,7 +1006,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(int W, int H, const uint32_t *_
     const int ntx = (int)rc.y - (int)rc.x + 1;
     const int nt = act ? ntx * ((int)rc.w - (int)rc.z + 1) : 0;
     // chunked Gaussians only publish their output base; their pairs come later
-    const bool chunked = act && nt > kBigTiles && (uint32_t)(m >> 32) != kNoChunk;
+    const bool chunked = act && nt > kBigTiles;
     if (chunked) erec[g].z = base;
 
 
@@ -1003,7 +1082,7 @@ __global__ __launch_bounds__(kBlock) void k_big_count(int W, int H, int binning,
                 int ry, rx;
                 row_col(idx, ntx, rcpn, ry, rx);
                 h = binning != 0 ||
-                    tile_hit(s.f0.x, s.f0.y, s.f0.z, s.f0.w, s.f1.x, s.f1.y, (int)rc.x + rx, (int)rc.z + ry, W, H);
+                    tile_hit(s.f0.x, s.f0.y, s.f3.x, s.f3.y, s.f3.z, s.f1.y, (int)rc.x + rx, (int)rc.z + ry, W, H);
             }
             const uint64_t b = __ballot(h);
             tot += (uint32_t)__popcll(b);
@@ -1039,6 +1118,9 @@ __global__ __launch_bounds__(kBlock) void k_big_emit(int W, const uint4 *__restr
     // lanes of the look-ahead load
     constexpr int kLaneHits = kMaskWords, kLaneRect = kLaneHits + 1, kLaneBase = kLaneRect + 4,
                   kLanePre = kLaneBase + 1;
+    // an overflowed list has entries this frame never wrote (the frame is
+    // rendered again, or reported, by the host)
+    if (fc->error & kErrChunkOverflow) return;
     const int lane = threadIdx.x & (kWave - 1);
     const int tiles_x = (W + kTile - 1) / kTile;
     const uint64_t lt = (1ull << lane) - 1ull;
@@ -1138,21 +1220,26 @@ unsigned emit_grid(uint32_t visible) {
     return b < cap ? (b > 0 ? b : 1u) : cap;
 }
 
-void launch_preprocess(const DevScene &sc, const DevPrepared *pp, const DevCamera &cam, const DevOptions &op,
-                       int W, int H, GaussState *gs, uint4 *rect, uint32_t *count, uint8_t *count8, uint4 *erec,
+void launch_preprocess(const DevScene &sc, const DevPrepared *pp, const DevCamera &cam, const DevCam64 &cam64,
+                       const DevOptions &op, int W, int H, GaussState *gs, uint4 *rect, uint32_t *count, uint8_t *count8, uint4 *erec,
                        uint32_t *dkey,
                        uint32_t *cand, uint32_t *seg_count, uint32_t *gmap, uint2 *chunks, uint32_t chunk_cap,
                        FrameCounters *fc, uint32_t *gsum_clear, hipStream_t s) {
     if (sc.P <= 0) return;
     if (pp) {
-        hipLaunchKernelGGL(k_cull<false>, dim3(kCullBlocks), dim3(kBlock), 0, s, sc, *pp, cam, op, W, H, cand, seg_count,
-                           fc, MultiOut{});
-        hipLaunchKernelGGL(k_preprocess<true>, dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, *pp, cam, op, W,
+        hipLaunchKernelGGL(k_preprocess<true>, dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, *pp, cam, cam64, op, W,
                            H, gs, rect, count, count8, erec, dkey, cand, seg_count, gmap, chunks, chunk_cap, fc, gsum_clear, MultiOut{});
     } else {
         hipLaunchKernelGGL(k_preprocess<false>, dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, DevPrepared{},
-                           cam, op, W, H, gs, rect, count, count8, erec, dkey, cand, seg_count, gmap, chunks, chunk_cap, fc, gsum_clear, MultiOut{});
+                           cam, cam64, op, W, H, gs, rect, count, count8, erec, dkey, cand, seg_count, gmap, chunks, chunk_cap, fc, gsum_clear, MultiOut{});
     }
+}
+
+void launch_cull(const DevScene &sc, const DevPrepared &pp, const DevCamera &cam, const DevOptions &op, int W, int H,
+                 uint32_t *cand, uint32_t *seg_count, FrameCounters *fc, hipStream_t s) {
+    if (sc.P <= 0) return;
+    hipLaunchKernelGGL(k_cull<false>, dim3(kCullBlocks), dim3(kBlock), 0, s, sc, pp, cam, op, W, H, cand, seg_count,
+                       fc, MultiOut{});
 }
 
 void launch_preprocess_multi(const DevScene &sc, const DevPrepared &pp, const MultiOut &mo, const DevOptions &op,
@@ -1161,7 +1248,7 @@ void launch_preprocess_multi(const DevScene &sc, const DevPrepared &pp, const Mu
     hipLaunchKernelGGL(k_cull<true>, dim3(kCullBlocks), dim3(kBlock), 0, s, sc, pp, mo.c[0].cam, op, W, H, cand,
                        seg_count, mo.c[0].fc, mo);
     const CamOut &c0 = mo.c[0];
-    hipLaunchKernelGGL((k_preprocess<true, true>), dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, pp, c0.cam, op, W,
+    hipLaunchKernelGGL((k_preprocess<true, true>), dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, pp, c0.cam, c0.cam64, op, W,
                        H, c0.gs, c0.rect, c0.count, c0.count8, c0.erec, c0.dkey, cand, seg_count, gmap, c0.chunks,
                        c0.chunk_cap, c0.fc, c0.gsum_clear, mo);
 }

@@ -210,6 +210,21 @@ DevCamera to_dev(const fgs_camera &c) {
     return d;
 }
 
+DevCam64 to_dev64(const DevCamera &c, const DevOptions &o, int W, int H) {
+    DevCam64 d{};
+    for (int i = 0; i < 9; ++i) d.R[i] = c.R[i];
+    for (int i = 0; i < 3; ++i) d.t[i] = c.t[i];
+    d.fx = c.fx;
+    d.fy = c.fy;
+    d.limx = (double)o.jac_clip * ((0.5 * (double)W) / d.fx);
+    d.limy = (double)o.jac_clip * ((0.5 * (double)H) / d.fy);
+    return d;
+}
+
+DevCam64 to_dev64(const fgs_camera &c, const fgs_options &o, int W, int H) {
+    return to_dev64(to_dev(c), to_dev(o), W, H);
+}
+
 DevScene to_dev(const fgs_scene &s) {
     DevScene d{};
     d.means = s.means;
@@ -276,7 +291,9 @@ void enqueue_front(const DevScene &sc, const DevPrepared *pp, const DevCamera &c
     // group-sum slots: depth passes 0-3, tile passes 4-7; each slot is cleared
     // by the kernel before its pass (the preprocess, the emission, or the
     // previous pass's downsweep)
-    launch_preprocess(sc, pp, cam, op, W, H, fb.gs, fb.rect, fb.count, fb.count8, fb.erec, fb.dkey, fb.dv_b, fb.seg_count,
+    if (pp) launch_cull(sc, *pp, cam, op, W, H, fb.dv_b, fb.seg_count, fc, s);
+    mk.mark(kMarkCulled, s);
+    launch_preprocess(sc, pp, cam, to_dev64(cam, op, W, H), op, W, H, fb.gs, fb.rect, fb.count, fb.count8, fb.erec, fb.dkey, fb.dv_b, fb.seg_count,
                       fb.gmap, ch.chunks, chunk_cap, fc, ss.slot(0), s);
     enqueue_front_rest(pp != nullptr, (uint32_t)sc.P, op, W, H, fb, ch, ss, fc, host_fc, s, side, mk, counters_ready);
 }
@@ -320,7 +337,7 @@ void enqueue_front_rest(bool dense, uint32_t P32, const DevOptions &op, int W, i
     if (counters_ready && side.side && hipEventRecord(side.fork, s) == hipSuccess &&
         hipStreamWaitEvent(side.side, side.fork, 0) == hipSuccess)
         sc2 = side.side;
-    (void)hipMemcpyAsync(host_fc, fc, sizeof(FrameCounters), hipMemcpyDeviceToHost, sc2);
+    if (host_fc) (void)hipMemcpyAsync(host_fc, fc, sizeof(FrameCounters), hipMemcpyDeviceToHost, sc2);
     if (counters_ready) (void)hipEventRecord(counters_ready, sc2);
 }
 

@@ -74,15 +74,27 @@ void free_frame_buffers(FrameBuffers &b);
 void free_sort_scratch(SortScratch &s);
 void free_chunks(ChunkList &c);
 
+// Text that fgs_last_error(NULL) returns on this thread (calls without a
+// context).
+void set_error_without_context(const char *msg);
+
 // Argument checks shared by every entry point; writes a message to err.
 fgs_status check_args(const fgs_scene *sc, const fgs_camera *cam, int32_t W, int32_t H, const fgs_options *opt,
                       std::string &err);
 
 DevOptions to_dev(const fgs_options &o);
 DevCamera to_dev(const fgs_camera &c);
+DevCam64 to_dev64(const fgs_camera &c, const fgs_options &o, int W, int H);
+DevCam64 to_dev64(const DevCamera &c, const DevOptions &o, int W, int H);
 DevScene to_dev(const fgs_scene &s);
 
-// Optional per-stage HIP events (index 0..7 around the stages).
+// Optional per-stage HIP events: 0..7 around the stages (0 before the
+// preprocess, 1 before the depth sort, 2 before the scan, 3 before the
+// emission, 4 before the tile sort, 5 before the ranges, 6 before the blend,
+// 7 after it), and kMarkCulled between a prepared scene's cull and the
+// preprocess (recorded right after 0 for raw parameters).
+constexpr int kMarkCulled = 8;
+constexpr int kStageMarks = 9;
 struct StageMarks {
     hipEvent_t *ev = nullptr;
     void mark(int i, hipStream_t s) const {
@@ -105,9 +117,9 @@ struct SideStream {
 // visible Gaussians, scan of the tile counts in depth order.  The exact tests
 // of the large rectangles run on the side stream while the depth order is
 // sorted on s; the scan waits for both.  Ends with an asynchronous copy of
-// the frame counters to host_fc (pinned): on s when counters_ready is NULL;
-// otherwise on the side stream, followed there by counters_ready, so that s
-// goes straight on to the second half.
+// the frame counters to host_fc (pinned; NULL: no copy): on s when
+// counters_ready is NULL; otherwise on the side stream, followed there by
+// counters_ready, so that s goes straight on to the second half.
 // pp: NULL (raw parameters) or the scene's view-independent precompute.
 void enqueue_front(const DevScene &sc, const DevPrepared *pp, const DevCamera &cam, const DevOptions &op, int W,
                    int H, FrameBuffers &fb, ChunkList &ch, SortScratch &ss, FrameCounters *fc,

@@ -20,6 +20,8 @@ namespace {
 thread_local std::string g_null_ctx_error;
 }  // namespace
 
+void fgs::set_error_without_context(const char *msg) { g_null_ctx_error = msg; }
+
 struct fgs_frame {
     FrameBuffers fb;
     int W = 0, H = 0;
@@ -58,7 +60,7 @@ struct fgs_context {
     // instrumentation
     int instr = 0;
     int blend_variant = 0;  // FGS_BLEND_*
-    hipEvent_t ev[2][8] = {};
+    hipEvent_t ev[2][kStageMarks] = {};
     int ev_pending = -1;  // event set of the last instrumented frame not yet folded in
     int ev_next = 0;
     fgs_timings acc{};
@@ -111,14 +113,31 @@ fgs_status validate(fgs_context *ctx, const fgs_scene *sc, const fgs_camera *cam
     return FGS_OK;
 }
 
+// Per-Gaussian records as fgs_frame_download documents them: the device
+// keeps the blend's conic where the blend loads it (GaussState), the host
+// field lists the canonical conic first.
+void gauss_to_host_order(void *dst, size_t bytes) {
+    static_assert(sizeof(GaussState) == 16 * sizeof(float), "16 floats per record");
+    // host column j takes device column from[j]
+    static const int from[16] = {0, 1, 12, 13, 14, 5, 6, 7, 8, 9, 10, 11, 2, 3, 4, 15};
+    float *r = static_cast<float *>(dst);
+    for (size_t i = 0; i < bytes / sizeof(GaussState); ++i, r += 16) {
+        float t[16];
+        memcpy(t, r, sizeof t);
+        for (int j = 0; j < 16; ++j) r[j] = t[from[j]];
+    }
+}
+
 // Add the stage times of a completed instrumented frame to the sums.
 void fold_events(fgs_context *ctx) {
     if (ctx->ev_pending < 0) return;
     hipEvent_t *e = ctx->ev[ctx->ev_pending];
-    float ms[7] = {0, 0, 0, 0, 0, 0, 0};
+    float ms[7] = {0, 0, 0, 0, 0, 0, 0}, cull = 0.0f;
     for (int i = 0; i < 7; ++i)
-        if (hipEventElapsedTime(&ms[i], e[i], e[i + 1]) != hipSuccess) ms[i] = 0.0f;
+        if (hipEventElapsedTime(&ms[i], e[i == 0 ? kMarkCulled : i], e[i + 1]) != hipSuccess) ms[i] = 0.0f;
+    if (hipEventElapsedTime(&cull, e[0], e[kMarkCulled]) != hipSuccess) cull = 0.0f;
     ctx->acc.frames += 1;
+    ctx->acc.ms_cull += cull;
     ctx->acc.ms_preprocess += ms[0];
     ctx->acc.ms_depth_sort += ms[1];
     ctx->acc.ms_scan += ms[2];
@@ -589,6 +608,7 @@ fgs_status fgs_render_prepared_batch(fgs_context *ctx, const fgs_prepared *p, co
             auto &bc = ctx->batch[c];
             CamOut &o = mo.c[c];
             o.cam = to_dev(cams[c]);
+            o.cam64 = to_dev64(cams[c], opt, W, H);
             o.gs = bc.fb.gs;
             o.rect = bc.fb.rect;
             o.count = bc.fb.count;
@@ -778,9 +798,11 @@ fgs_status fgs_frame_download(fgs_context *ctx, const fgs_frame *f, fgs_field fi
         memset(d, 0, bytes);
         for (size_t c = 0; c < f->ncand; ++c)
             if ((size_t)gm[c] * esz + esz <= bytes) memcpy(d + (size_t)gm[c] * esz, tmp.data() + c * esz, esz);
+        if (field == FGS_FIELD_GAUSS) gauss_to_host_order(host_dst, bytes);
         return FGS_OK;
     }
     HIP_TRY(ctx, hipMemcpy(host_dst, src, bytes, hipMemcpyDeviceToHost));
+    if (field == FGS_FIELD_GAUSS) gauss_to_host_order(host_dst, bytes);
     if (field == FGS_FIELD_RANGES) {
         // an empty tile may hold start > end on the device; report (0, 0)
         uint2 *r = static_cast<uint2 *>(host_dst);
@@ -801,8 +823,8 @@ fgs_status fgs_set_instrumentation(fgs_context *ctx, int flags) {
             for (hipEvent_t &e : set)
                 if (!e) HIP_TRY(ctx, hipEventCreate(&e));
     if ((flags & FGS_INSTR_WORK) && !ctx->work_dev)
-        HIP_TRY(ctx, hipMalloc((void **)&ctx->work_dev, sizeof(unsigned long long)));
-    if (ctx->work_dev) HIP_TRY(ctx, hipMemset(ctx->work_dev, 0, sizeof(unsigned long long)));
+        HIP_TRY(ctx, hipMalloc((void **)&ctx->work_dev, 2 * sizeof(unsigned long long)));
+    if (ctx->work_dev) HIP_TRY(ctx, hipMemset(ctx->work_dev, 0, 2 * sizeof(unsigned long long)));
     ctx->instr = flags;
     ctx->ev_pending = -1;
     ctx->acc = fgs_timings{};
@@ -821,14 +843,15 @@ fgs_status fgs_get_instrumentation(fgs_context *ctx, fgs_timings *out) {
     if (!ctx || !out) return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "NULL argument");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     if (ctx->ev_pending >= 0) {
-        HIP_TRY(ctx, hipEventSynchronize(ctx->ev[ctx->ev_pending][7]));
+        HIP_TRY(ctx, hipEventSynchronize(ctx->ev[ctx->ev_pending][7]));  // the frame's last mark
         fold_events(ctx);
     }
     if (ctx->work_dev) {
         HIP_TRY(ctx, hipDeviceSynchronize());
-        unsigned long long w = 0;
-        HIP_TRY(ctx, hipMemcpy(&w, ctx->work_dev, sizeof w, hipMemcpyDeviceToHost));
-        ctx->acc.blend_evaluations = (int64_t)w;
+        unsigned long long w[2] = {0, 0};
+        HIP_TRY(ctx, hipMemcpy(w, ctx->work_dev, sizeof w, hipMemcpyDeviceToHost));
+        ctx->acc.blend_evaluations = (int64_t)w[0];
+        ctx->acc.blend_wave_steps = (int64_t)w[1];
     }
     *out = ctx->acc;
     return FGS_OK;

@@ -645,13 +645,19 @@ fgs_status fgs_server_replay(fgs_server *srv, const fgs_trace_request *trace, in
     return FGS_OK;
 }
 
-fgs_status fgs_replay_plain(fgs_context *ctx, const fgs_scene *scene, const fgs_options *opt,
-                            const fgs_trace_request *trace, int64_t n, float *rgb_scratch,
-                            fgs_server_result *results, void *stream) {
-    if (!ctx || (n > 0 && (!trace || !results || !rgb_scratch)) || n < 0) return FGS_ERR_INVALID_ARGUMENT;
+}  // extern "C"
+
+namespace {
+
+// The plain renderer's replay: each request at its arrival time, one at a
+// time in arrival order, waiting for each frame before the next (completion
+// observed by polling an event, as the server's worker does).  render(q, st)
+// renders request q into the caller's scratch image.
+template <class Render>
+fgs_status replay_plain_impl(const fgs_trace_request *trace, int64_t n, fgs_server_result *results, void *stream,
+                             Render render) {
     for (int64_t i = 1; i < n; ++i)
         if (trace[i].arrival_offset_ns < trace[i - 1].arrival_offset_ns) return FGS_ERR_INVALID_ARGUMENT;
-    // completion is observed by polling an event, as the server's worker does
     hipEvent_t done = nullptr;
     if (hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) return FGS_ERR_DEVICE;
     struct EventGuard {
@@ -672,8 +678,7 @@ fgs_status fgs_replay_plain(fgs_context *ctx, const fgs_scene *scene, const fgs_
         r.arrival_ns = arrive;
         r.start_ns = now_ns();
         fgs_stats stt{};
-        fgs_status s = fgs_render(ctx, scene, &q.cam, q.width, q.height, opt, rgb_scratch, nullptr, nullptr, nullptr,
-                                  &stt, stream);
+        fgs_status s = render(q, &stt);
         r.admit_ns = now_ns();  // the render call returns once the second half is enqueued
         if (s == FGS_OK) {
             hipError_t q2 = hipEventRecord(done, (hipStream_t)stream);
@@ -689,6 +694,31 @@ fgs_status fgs_replay_plain(fgs_context *ctx, const fgs_scene *scene, const fgs_
         if (s != FGS_OK) return s;
     }
     return FGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fgs_status fgs_replay_plain(fgs_context *ctx, const fgs_scene *scene, const fgs_options *opt,
+                            const fgs_trace_request *trace, int64_t n, float *rgb_scratch,
+                            fgs_server_result *results, void *stream) {
+    if (!ctx || (n > 0 && (!trace || !results || !rgb_scratch)) || n < 0) return FGS_ERR_INVALID_ARGUMENT;
+    return replay_plain_impl(trace, n, results, stream, [&](const fgs_trace_request &q, fgs_stats *st) {
+        return fgs_render(ctx, scene, &q.cam, q.width, q.height, opt, rgb_scratch, nullptr, nullptr, nullptr, st,
+                          stream);
+    });
+}
+
+fgs_status fgs_replay_plain_prepared(fgs_context *ctx, const fgs_prepared *prepared, const fgs_options *opt,
+                                     const fgs_trace_request *trace, int64_t n, float *rgb_scratch,
+                                     fgs_server_result *results, void *stream) {
+    if (!ctx || !prepared || (n > 0 && (!trace || !results || !rgb_scratch)) || n < 0)
+        return FGS_ERR_INVALID_ARGUMENT;
+    return replay_plain_impl(trace, n, results, stream, [&](const fgs_trace_request &q, fgs_stats *st) {
+        return fgs_render_prepared(ctx, prepared, &q.cam, q.width, q.height, opt, rgb_scratch, nullptr, nullptr,
+                                   nullptr, st, stream);
+    });
 }
 
 }  // extern "C"

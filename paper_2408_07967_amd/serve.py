@@ -115,8 +115,10 @@ def make_trace(rate_hz, seconds, seed=5):
     return out
 
 
-def replay_plain(renderer, scene, opts, trace, stream=None):
-    """The trace through the plain renderer (one request at a time, FIFO)."""
+def replay_plain(renderer, scene, opts, trace, stream=None, prepared=None):
+    """The trace through the plain renderer (one request at a time, FIFO),
+    from the raw parameters or, with prepared (a handle of
+    renderer.prepare(scene)), from the resident precompute."""
     import torch
     W = max(q["W"] for q in trace)
     H = max(q["H"] for q in trace)
@@ -126,8 +128,12 @@ def replay_plain(renderer, scene, opts, trace, stream=None):
     arr = _trace_array(trace)
     res = (B.FgsServerResult * len(trace))()
     s = torch.cuda.current_stream(scene.means.device).cuda_stream if stream is None else stream
-    renderer.ctx.check(B.lib().fgs_replay_plain(renderer.ctx.handle, C.byref(sc), C.byref(op), arr, len(trace),
-                                                scratch.data_ptr(), res, s))
+    if prepared is not None:
+        renderer.ctx.check(B.lib().fgs_replay_plain_prepared(renderer.ctx.handle, prepared, C.byref(op), arr,
+                                                             len(trace), scratch.data_ptr(), res, s))
+    else:
+        renderer.ctx.check(B.lib().fgs_replay_plain(renderer.ctx.handle, C.byref(sc), C.byref(op), arr, len(trace),
+                                                    scratch.data_ptr(), res, s))
     return [_result_dict(r) for r in res]
 
 

@@ -21,7 +21,7 @@ def gpu_frame(R, gscene, cam, W, H, opts, prepared=None):
     P = gscene.P
     res = dict(rgb=out["rgb"].cpu().numpy(), T=out["T"].cpu().numpy(),
                last=out["last"].cpu().numpy().view(np.uint32), stats=out["stats"])
-    res["gauss"] = R.frame_field(fr, B.FIELD_GAUSS).view(np.float32).reshape(P, 12) if P else np.zeros((0, 12))
+    res["gauss"] = R.frame_field(fr, B.FIELD_GAUSS).view(np.float32).reshape(P, 16) if P else np.zeros((0, 16))
     res["rect"] = R.frame_field(fr, B.FIELD_RECT).reshape(P, 4) if P else np.zeros((0, 4), np.uint32)
     res["count"] = R.frame_field(fr, B.FIELD_COUNT)
     res["order"] = R.frame_field(fr, B.FIELD_ORDER)
@@ -76,7 +76,33 @@ def image_error(a, b):
     return d.max(), (d <= IMG_MAX).mean(), d.mean()
 
 
+# columns of the downloaded per-Gaussian record (fgs.h, FGS_FIELD_GAUSS)
+COL_A, COL_B, COL_C, COL_AB, COL_BB, COL_CB = 2, 3, 4, 12, 13, 14
+# the blend's conic is the binary64 conic rounded once: against the binary64
+# oracle's conic, relative to the larger diagonal entry
+BLEND_CONIC_REL = 1e-4
+
+
+def check_blend_conic(g, o64, tag=""):
+    """The conic the blend evaluates pixels with against the binary64 oracle's
+    (the binary32 canonical conic, which decides the pairs, may be several
+    per cent off for long thin footprints)."""
+    st = o64["state"]
+    vis = np.zeros(st.shape[0], bool)
+    vis[g["order"]] = True  # the GPU's visible set
+    vidx = np.nonzero((o64["ints"][:, 0] == 1) & vis)[0]
+    if vidx.size == 0:
+        return
+    gg = g["gauss"][vidx].astype(np.float64)
+    ref = st[vidx][:, [2, 3, 4]]
+    got = gg[:, [COL_AB, COL_BB, COL_CB]]
+    scale = np.maximum(np.abs(ref[:, 0]), np.abs(ref[:, 2]))
+    rel = np.abs(got - ref).max(axis=1) / scale
+    assert rel.max() <= BLEND_CONIC_REL, f"{tag} blend conic: max relative error {rel.max():.3g}"
+
+
 def check_image(g, o64, tag=""):
+    check_blend_conic(g, o64, tag)
     mx, frac, mean = image_error(g["rgb"], o64["rgb"])
     assert frac >= IMG_FRAC and mean <= IMG_MEAN, f"{tag} image: max {mx:.3g} frac {frac:.6f} mean {mean:.3g}"
     mx, frac, mean = image_error(g["T"], o64["T"])

@@ -22,10 +22,14 @@ namespace fgs {
 void launch_fill_u32(uint32_t *, uint32_t, size_t, hipStream_t) { reached("fill_u32"); }
 unsigned preprocess_grid(int64_t) { reached("preprocess_grid"); }
 unsigned emit_grid(uint32_t) { reached("emit_grid"); }
-void launch_preprocess(const DevScene &, const DevPrepared *, const DevCamera &, const DevOptions &, int, int,
+void launch_preprocess(const DevScene &, const DevPrepared *, const DevCamera &, const DevCam64 &, const DevOptions &, int, int,
                        GaussState *, uint4 *, uint32_t *, uint8_t *, uint4 *, uint32_t *, uint32_t *, uint32_t *,
                        uint32_t *, uint2 *, uint32_t, FrameCounters *, uint32_t *, hipStream_t) {
     reached("preprocess");
+}
+void launch_cull(const DevScene &, const DevPrepared &, const DevCamera &, const DevOptions &, int, int, uint32_t *,
+                 uint32_t *, FrameCounters *, hipStream_t) {
+    reached("cull");
 }
 void launch_preprocess_multi(const DevScene &, const DevPrepared &, const MultiOut &, const DevOptions &, int, int,
                              uint32_t *, uint32_t *, uint32_t *, hipStream_t) {

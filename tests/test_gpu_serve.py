@@ -21,7 +21,7 @@ def setup():
     sc = scenes.make_scene("serve", P=400_000)
     gsc = GaussianScene.from_numpy(sc)
     R = Renderer()
-    yield scenes, gsc, R
+    yield scenes, gsc, R, sc
     R.close()
 
 
@@ -52,7 +52,7 @@ def test_served_images_equal_alone_under_a_tight_budget(setup, share_queue):
     through both the shared and the one-at-a-time regime."""
     import torch
     from paper_2408_07967_amd.serve import RenderServer
-    scenes, gsc, R = setup
+    scenes, gsc, R, _ = setup
     rng = np.random.default_rng(11)
     reqs = []
     for i in range(14):
@@ -89,7 +89,7 @@ def test_graph_replays_on_one_slot_match_eager(setup):
     between."""
     import torch
     from paper_2408_07967_amd.serve import RenderServer
-    scenes, gsc, R = setup
+    scenes, gsc, R, _ = setup
     rng = np.random.default_rng(12)
     cams = [scenes.serve_pose(rng) for _ in range(3)]
     srv = RenderServer(gsc, budget_bytes=2 << 30, max_inflight=1)
@@ -113,7 +113,7 @@ def test_direct_launch_mode_and_capacity_rejection(setup):
     import torch
     from paper_2408_07967_amd import binding as B
     from paper_2408_07967_amd.serve import RenderServer
-    scenes, gsc, R = setup
+    scenes, gsc, R, _ = setup
     rng = np.random.default_rng(13)
     cam = scenes.serve_pose(rng)
     ref, pairs = _alone(R, gsc, cam, cam.W, cam.H, None)
@@ -137,7 +137,7 @@ def test_direct_launch_mode_and_capacity_rejection(setup):
 
 def test_trace_replay_server_and_plain(setup):
     from paper_2408_07967_amd.serve import RenderServer, make_trace, replay_plain, latency_summary
-    scenes, gsc, R = setup
+    scenes, gsc, R, _ = setup
     trace = make_trace(rate_hz=150.0, seconds=0.5, seed=9)
     print(f"[serve] trace of {len(trace)} requests", flush=True)
     srv = RenderServer(gsc, budget_bytes=4 << 30, max_inflight=4)
@@ -153,3 +153,33 @@ def test_trace_replay_server_and_plain(setup):
         assert a["done_ns"] >= a["arrival_ns"] and b["done_ns"] >= b["arrival_ns"]
     print("[serve] server", latency_summary(res), flush=True)
     print("[serve] plain ", latency_summary(plain), flush=True)
+
+
+def test_served_images_match_the_binary64_oracle(setup, orc):
+    """One request of each serving resolution, submitted together so that
+    they overlap on the device, against the binary64 oracle at the image bar
+    (|diff| <= 2e-3 on >= 99.9 % of pixels, mean |diff| <= 1e-5)."""
+    import torch
+    from gpu_helpers import IMG_FRAC, IMG_MAX, IMG_MEAN, image_error
+    from oracle_helpers import opts
+    from paper_2408_07967_amd.serve import RenderServer
+    scenes, gsc, R, sc = setup
+    rng = np.random.default_rng(14)
+    want = [(1280, 720), (1920, 1080), (2560, 1440), (3840, 2160)]
+    reqs = []
+    while len(reqs) < len(want):
+        cam = scenes.serve_pose(rng)
+        if (cam.W, cam.H) == want[len(reqs)]:
+            reqs.append((len(reqs), cam, cam.W, cam.H))
+    srv = RenderServer(gsc, budget_bytes=4 << 30, max_inflight=4, share_queue=0)
+    try:
+        got, outs = _serve_all(srv, reqs, gsc)
+    finally:
+        srv.close()
+    for rid, cam, W, H in reqs:
+        assert got[rid]["status"] == 0, got[rid]
+        o64 = orc.render(sc, cam, W, H, opts(), mode="f64")
+        mx, frac, mean = image_error(outs[rid].view(3, H, W).cpu().numpy(), o64["rgb"])
+        print(f"[serve] request {rid} {W}x{H}: pairs {got[rid]['pairs']} max {mx:.3g} within {IMG_MAX}: "
+              f"{frac:.6f} mean {mean:.3g}", flush=True)
+        assert frac >= IMG_FRAC and mean <= IMG_MEAN, (W, H, mx, frac, mean)
