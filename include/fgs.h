@@ -351,7 +351,9 @@ fgs_status fgs_frame_stats(const fgs_frame *frame, fgs_stats *stats);
  * requests of mixed resolutions concurrently.  A request takes a slot (its
  * own stream and per-Gaussian buffers) and runs the first half of the frame
  * (preprocess, exact tile counts, depth order, count scan), which yields its
- * exact pair count N.  It is then admitted when its pair and sort buffers
+ * exact pair count N; requests that start together share the cull and
+ * preprocess of that half (batch_fronts).  It is then admitted when its pair
+ * and sort buffers
  * (16 bytes per pair) fit in the free part of a device byte budget: FIFO, a
  * request that does not fit may be overtaken by at most max_bypass later
  * ones.  The second half (emission, tile sort, ranges, blend) then runs as
@@ -373,6 +375,11 @@ typedef struct {
                                k >= 1: a request starts beside others still in flight
                                only while at least k requests are waiting, so at light
                                load requests run one at a time on the whole GPU      */
+    int32_t batch_fronts;   /* 0 or 1.  1: requests that start together (up to
+                               FGS_MAX_BATCH_CAMERAS, any mix of resolutions) share one
+                               cull and one preprocess pass, which reads each
+                               candidate's precompute once for all of them; 0: every
+                               request runs its own                                  */
 } fgs_server_config;
 
 typedef struct {
@@ -397,6 +404,8 @@ typedef struct {
     int64_t budget_bytes;
     int64_t slot_bytes;         /* buffers outside the budget: all slots and the
                                    scene's view-independent precompute             */
+    int64_t batched_fronts;     /* first halves run as one batch (batch_fronts)     */
+    int64_t batched_requests;   /* requests whose first half ran in such a batch    */
 } fgs_server_stats;
 
 /* Monotonic clock (ns) of the server's timestamps. */

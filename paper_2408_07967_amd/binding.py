@@ -66,7 +66,7 @@ MAX_BATCH_CAMERAS = 8
 class FgsServerConfig(C.Structure):
     _fields_ = [("budget_bytes", C.c_int64), ("max_inflight", C.c_int32), ("max_width", C.c_int32),
                 ("max_height", C.c_int32), ("max_bypass", C.c_int32), ("use_graphs", C.c_int32),
-                ("share_queue", C.c_int32)]
+                ("share_queue", C.c_int32), ("batch_fronts", C.c_int32)]
 
 
 class FgsServerResult(C.Structure):
@@ -79,7 +79,8 @@ class FgsServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("rejected", C.c_int64),
                 ("graphs_captured", C.c_int64), ("graph_launches", C.c_int64), ("region_allocs", C.c_int64),
                 ("region_evictions", C.c_int64), ("bypasses", C.c_int64), ("peak_bytes_in_use", C.c_int64),
-                ("budget_bytes", C.c_int64), ("slot_bytes", C.c_int64)]
+                ("budget_bytes", C.c_int64), ("slot_bytes", C.c_int64), ("batched_fronts", C.c_int64),
+                ("batched_requests", C.c_int64)]
 
 
 class FgsTraceRequest(C.Structure):

@@ -147,6 +147,7 @@ constexpr int kMaxCams = 8;  // FGS_MAX_BATCH_CAMERAS
 struct CamOut {
     DevCamera cam;
     DevCam64 cam64;
+    int W, H;  // this camera's image
     GaussState *gs;
     uint4 *rect;
     uint32_t *count;
@@ -162,9 +163,10 @@ struct MultiOut {
     CamOut c[kMaxCams];
     int n;  // cameras in the batch, 1..kMaxCams
 };
-// cand, seg_count, gmap: as for launch_preprocess (one union list).
+// Each camera has its own image size.  cand, seg_count, gmap: as for
+// launch_preprocess (one union list).
 void launch_preprocess_multi(const DevScene &sc, const DevPrepared &pp, const MultiOut &mo, const DevOptions &op,
-                             int W, int H, uint32_t *cand, uint32_t *seg_count, uint32_t *gmap, hipStream_t s);
+                             uint32_t *cand, uint32_t *seg_count, uint32_t *gmap, hipStream_t s);
 
 // View-independent precompute (opacity, 3D covariance, k^2, log2 opacity,
 // Gaussian-major SH) for options op (alpha_min and cap_3sigma).

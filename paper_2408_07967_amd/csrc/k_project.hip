@@ -441,7 +441,7 @@ __global__ __launch_bounds__(kBlock) void k_cull(DevScene sc, DevPrepared pp, De
             if constexpr (kMulti) {
                 // union of the cameras' candidates: the exact path of each
                 // camera culls the rest
-                for (int c = 0; c < mo.n && !keep; ++c) keep = cull_keep(pp, g, p4, mo.c[c].cam, op, W, H);
+                for (int c = 0; c < mo.n && !keep; ++c) keep = cull_keep(pp, g, p4, mo.c[c].cam, op, mo.c[c].W, mo.c[c].H);
             } else {
                 keep = cull_keep(pp, g, p4, cam, op, W, H);
             }
@@ -470,7 +470,7 @@ __global__ __launch_bounds__(kBlock) void k_cull(DevScene sc, DevPrepared pp, De
 // wavefront and hit the caches.
 template <bool kPrep, bool kMulti = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_preprocess(DevScene sc, DevPrepared pp, DevCamera cam, DevCam64 cam64, DevOptions op,
-                                                       int W, int H, GaussState *__restrict__ gs,
+                                                       int W_arg, int H_arg, GaussState *__restrict__ gs,
                                                        uint4 *__restrict__ rect, uint32_t *__restrict__ count,
                                                        uint8_t *__restrict__ count8, uint4 *__restrict__ erec,
                                                        uint32_t *__restrict__ dkey,
@@ -656,8 +656,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     }
     const int ncams = kMulti ? mo.n : 1;
     for (int ci = 0; ci < ncams; ++ci) {
-    // this camera and its outputs
+    // this camera, its image size and its outputs
     const DevCamera &cm = kMulti ? mo.c[ci].cam : cam;
+    const int W = kMulti ? mo.c[ci].W : W_arg, H = kMulti ? mo.c[ci].H : H_arg;
     const DevCam64 &cm64 = kMulti ? mo.c[ci].cam64 : cam64;
     GaussState *__restrict__ const gs_c = kMulti ? mo.c[ci].gs : gs;
     uint4 *__restrict__ const rect_c = kMulti ? mo.c[ci].rect : rect;
@@ -1243,13 +1244,13 @@ void launch_cull(const DevScene &sc, const DevPrepared &pp, const DevCamera &cam
 }
 
 void launch_preprocess_multi(const DevScene &sc, const DevPrepared &pp, const MultiOut &mo, const DevOptions &op,
-                             int W, int H, uint32_t *cand, uint32_t *seg_count, uint32_t *gmap, hipStream_t s) {
+                             uint32_t *cand, uint32_t *seg_count, uint32_t *gmap, hipStream_t s) {
     if (sc.P <= 0 || mo.n < 1 || mo.n > kMaxCams) return;
-    hipLaunchKernelGGL(k_cull<true>, dim3(kCullBlocks), dim3(kBlock), 0, s, sc, pp, mo.c[0].cam, op, W, H, cand,
-                       seg_count, mo.c[0].fc, mo);
     const CamOut &c0 = mo.c[0];
-    hipLaunchKernelGGL((k_preprocess<true, true>), dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, pp, c0.cam, c0.cam64, op, W,
-                       H, c0.gs, c0.rect, c0.count, c0.count8, c0.erec, c0.dkey, cand, seg_count, gmap, c0.chunks,
+    hipLaunchKernelGGL(k_cull<true>, dim3(kCullBlocks), dim3(kBlock), 0, s, sc, pp, c0.cam, op, c0.W, c0.H, cand,
+                       seg_count, c0.fc, mo);
+    hipLaunchKernelGGL((k_preprocess<true, true>), dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, pp, c0.cam, c0.cam64, op, c0.W,
+                       c0.H, c0.gs, c0.rect, c0.count, c0.count8, c0.erec, c0.dkey, cand, seg_count, gmap, c0.chunks,
                        c0.chunk_cap, c0.fc, c0.gsum_clear, mo);
 }
 

@@ -609,6 +609,8 @@ fgs_status fgs_render_prepared_batch(fgs_context *ctx, const fgs_prepared *p, co
             CamOut &o = mo.c[c];
             o.cam = to_dev(cams[c]);
             o.cam64 = to_dev64(cams[c], opt, W, H);
+            o.W = W;
+            o.H = H;
             o.gs = bc.fb.gs;
             o.rect = bc.fb.rect;
             o.count = bc.fb.count;
@@ -622,7 +624,7 @@ fgs_status fgs_render_prepared_batch(fgs_context *ctx, const fgs_prepared *p, co
         }
         FrameBuffers &fb0 = ctx->batch[0].fb;
         if (P <= 0) launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->bfc_dev), 0u, kMaxCams * sizeof(FrameCounters) / 4, s);
-        launch_preprocess_multi(dsc, pdev, mo, dop, W, H, fb0.dv_b, fb0.seg_count, fb0.gmap, s);
+        launch_preprocess_multi(dsc, pdev, mo, dop, fb0.dv_b, fb0.seg_count, fb0.gmap, s);
         // each camera's depth order and scan, then (beside the host's wait
         // for the counters) each camera's second half
         for (int c = 0; c < ncams; ++c) {

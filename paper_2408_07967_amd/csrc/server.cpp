@@ -4,7 +4,9 @@
 // Request life cycle, driven by one worker thread that issues all GPU work:
 //   QUEUED  -> FRONT  a free slot runs the first half of the frame on its
 //                     own stream (preprocess, exact tile counts, depth order,
-//                     count scan) and copies the frame counters to the host
+//                     count scan) and copies the frame counters to the host;
+//                     requests that start together share one cull and one
+//                     preprocess pass (then sort and scan on their own slots)
 //   FRONT   -> WAIT   the counters arrived: N pairs are known
 //   WAIT    -> BACK   admitted: 16 N bytes (+ headroom) of the byte budget
 //                     back the slot's pair and sort buffers; the second half
@@ -70,6 +72,7 @@ struct Slot {
     SlotState state = SlotState::IDLE;
     hipStream_t stream = nullptr;
     hipEvent_t evA = nullptr, evB = nullptr;
+    hipEvent_t evP = nullptr;  // a batched front half's shared preprocess is complete
     SideStream side;
     FrameBuffers fb;
     ChunkList ch;
@@ -183,6 +186,51 @@ void start_front(fgs_server *srv, Slot &s) {
                   s.stream, s.side, StageMarks{});
     (void)hipEventRecord(s.evA, s.stream);
     s.state = SlotState::FRONT;
+}
+
+// First halves of several requests that start together (each on its own
+// slot, any mix of resolutions): one cull keeps the union of their
+// candidates and one preprocess pass evaluates every candidate for each
+// camera, reading its precompute once (Sec. 5.3.1's unified preprocessing
+// across viewpoints); each slot then sorts by depth and scans on its own
+// stream.  The union list lives in the first slot's buffers.
+void start_front_batch(fgs_server *srv, const std::vector<Slot *> &b) {
+    MultiOut mo{};
+    mo.n = (int)b.size();
+    for (size_t c = 0; c < b.size(); ++c) {
+        Slot &s = *b[c];
+        CamOut &o = mo.c[c];
+        o.cam = to_dev(s.req.cam);
+        o.cam64 = to_dev64(s.req.cam, srv->opt, s.req.W, s.req.H);
+        o.W = s.req.W;
+        o.H = s.req.H;
+        o.gs = s.fb.gs;
+        o.rect = s.fb.rect;
+        o.count = s.fb.count;
+        o.count8 = s.fb.count8;
+        o.erec = s.fb.erec;
+        o.dkey = s.fb.dkey;
+        o.chunks = s.ch.chunks;
+        o.chunk_cap = (uint32_t)std::min<size_t>(s.ch.cap, 0xffffffffu);
+        o.fc = s.fc_dev;
+        o.gsum_clear = s.ss.slot(0);
+    }
+    Slot &s0 = *b[0];
+    const uint32_t P = (uint32_t)srv->scene.num_gaussians;
+    if (P == 0)
+        for (Slot *s : b) launch_fill_u32(reinterpret_cast<uint32_t *>(s->fc_dev), 0u, sizeof(FrameCounters) / 4, s0.stream);
+    launch_preprocess_multi(srv->dsc, srv->pdev, mo, srv->dop, s0.fb.dv_b, s0.fb.seg_count, s0.fb.gmap, s0.stream);
+    (void)hipEventRecord(s0.evP, s0.stream);
+    for (size_t c = 0; c < b.size(); ++c) {
+        Slot &s = *b[c];
+        if (c > 0) (void)hipStreamWaitEvent(s.stream, s0.evP, 0);
+        enqueue_front_rest(true, P, srv->dop, s.req.W, s.req.H, s.fb, s.ch, s.ss, s.fc_dev, s.fc_host, s.stream,
+                           s.side, StageMarks{});
+        (void)hipEventRecord(s.evA, s.stream);
+        s.state = SlotState::FRONT;
+    }
+    srv->wst.batched_fronts += 1;
+    srv->wst.batched_requests += (int64_t)b.size();
 }
 
 hipError_t start_back(fgs_server *srv, Slot &s) {
@@ -308,8 +356,9 @@ void worker_main(fgs_server *srv) {
         int active = 0;
         for (const Slot &s : srv->slots)
             active += (s.state == SlotState::FRONT || s.state == SlotState::WAIT || s.state == SlotState::BACK);
+        std::vector<Slot *> starting;
         for (Slot &s : srv->slots) {
-            if (pending.empty()) break;
+            if (pending.empty() || (int)starting.size() == kMaxCams) break;
             if (s.state != SlotState::IDLE) continue;
             const int k = srv->cfg.share_queue;
             if (active > 0 && k > 0 && (int64_t)pending.size() < (int64_t)k) break;
@@ -319,9 +368,15 @@ void worker_main(fgs_server *srv) {
             s.attempts = 0;
             s.bypassed = 0;
             s.start_ns = now_ns();
-            start_front(srv, s);
-            progress = true;
+            starting.push_back(&s);
         }
+        // requests that start together share one cull and preprocess pass
+        if (starting.size() == 1 || (starting.size() > 1 && !srv->cfg.batch_fronts)) {
+            for (Slot *s : starting) start_front(srv, *s);
+        } else if (starting.size() > 1) {
+            start_front_batch(srv, starting);
+        }
+        progress |= !starting.empty();
         // 2. first halves that finished: their pair counts are known
         for (Slot &s : srv->slots) {
             if (s.state != SlotState::FRONT) continue;
@@ -394,6 +449,8 @@ void worker_main(fgs_server *srv) {
             srv->st.region_evictions = srv->wst.region_evictions;
             srv->st.bypasses = srv->wst.bypasses;
             srv->st.peak_bytes_in_use = srv->wst.peak_bytes_in_use;
+            srv->st.batched_fronts = srv->wst.batched_fronts;
+            srv->st.batched_requests = srv->wst.batched_requests;
         } else if (in_flight) {
             std::this_thread::yield();  // completions are polled: stay on the core
         } else {
@@ -430,6 +487,7 @@ void free_server(fgs_server *srv) {
         if (s.img) (void)hipFree(s.img);
         if (s.evA) (void)hipEventDestroy(s.evA);
         if (s.evB) (void)hipEventDestroy(s.evB);
+        if (s.evP) (void)hipEventDestroy(s.evP);
         if (s.stream) (void)hipStreamDestroy(s.stream);
         s.side.destroy();
     }
@@ -451,7 +509,7 @@ fgs_status fgs_server_create(int device, const fgs_scene *scene, const fgs_optio
     if (!cfg) return FGS_ERR_INVALID_ARGUMENT;
     if (cfg->budget_bytes < (1 << 20) || cfg->max_inflight < 1 || cfg->max_inflight > 32 || cfg->max_width < 1 ||
         cfg->max_width > 16384 || cfg->max_height < 1 || cfg->max_height > 16384 || cfg->max_bypass < 0 ||
-        cfg->share_queue < 0)
+        cfg->share_queue < 0 || (cfg->batch_fronts != 0 && cfg->batch_fronts != 1))
         return FGS_ERR_INVALID_ARGUMENT;
     fgs_camera probe{};
     for (int i = 0; i < 3; ++i) probe.R[4 * i] = 1.0f;
@@ -496,6 +554,7 @@ fgs_status fgs_server_create(int device, const fgs_scene *scene, const fgs_optio
         if ((e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking)) != hipSuccess) break;
         if ((e = hipEventCreateWithFlags(&s.evA, hipEventDisableTiming)) != hipSuccess) break;
         if ((e = hipEventCreateWithFlags(&s.evB, hipEventDisableTiming)) != hipSuccess) break;
+        if ((e = hipEventCreateWithFlags(&s.evP, hipEventDisableTiming)) != hipSuccess) break;
         if ((e = s.side.create()) != hipSuccess) break;
         if ((e = ensure_gauss(s.fb, P)) != hipSuccess) break;
         if ((e = ensure_tiles(s.fb, tiles)) != hipSuccess) break;

@@ -20,14 +20,15 @@ def clock_ns():
 
 class RenderServer:
     def __init__(self, scene, opts=None, budget_bytes=8 << 30, max_inflight=6, max_width=3840, max_height=2160,
-                 max_bypass=4, use_graphs=True, share_queue=0, device=0):
+                 max_bypass=4, use_graphs=True, share_queue=0, batch_fronts=True, device=0):
         if not isinstance(scene, GaussianScene):
             raise TypeError("scene must be a GaussianScene")
         self.scene = scene  # keeps the device planes alive
         self._sc = scene.abi()
         self._op = options_abi(opts)
         cfg = B.FgsServerConfig(int(budget_bytes), int(max_inflight), int(max_width), int(max_height),
-                                int(max_bypass), 1 if use_graphs else 0, int(share_queue))
+                                int(max_bypass), 1 if use_graphs else 0, int(share_queue),
+                                1 if batch_fronts else 0)
         h = C.c_void_p()
         st = B.lib().fgs_server_create(int(device), C.byref(self._sc), C.byref(self._op), C.byref(cfg), C.byref(h))
         if st != B.FGS_OK:

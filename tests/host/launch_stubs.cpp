@@ -31,8 +31,8 @@ void launch_cull(const DevScene &, const DevPrepared &, const DevCamera &, const
                  uint32_t *, FrameCounters *, hipStream_t) {
     reached("cull");
 }
-void launch_preprocess_multi(const DevScene &, const DevPrepared &, const MultiOut &, const DevOptions &, int, int,
-                             uint32_t *, uint32_t *, uint32_t *, hipStream_t) {
+void launch_preprocess_multi(const DevScene &, const DevPrepared &, const MultiOut &, const DevOptions &, uint32_t *,
+                             uint32_t *, uint32_t *, hipStream_t) {
     reached("preprocess_multi");
 }
 void launch_prepare(const DevScene &, const DevOptions &, float4 *, float4 *, float *, float2 *, int, hipStream_t) {

@@ -184,6 +184,7 @@ void error_paths() {
     bad_cfg([](fgs_server_config &k) { k.max_width = 16385; }, "server width");
     bad_cfg([](fgs_server_config &k) { k.max_bypass = -1; }, "server bypass");
     bad_cfg([](fgs_server_config &k) { k.share_queue = -1; }, "server share threshold");
+    bad_cfg([](fgs_server_config &k) { k.batch_fronts = 2; }, "server batching flag");
     Planes bad;
     fgs_scene bs = valid_scene(bad);
     bs.sh_degree = 9;

@@ -45,11 +45,13 @@ def _serve_all(srv, reqs, gsc):
     return got, outs
 
 
-@pytest.mark.parametrize("share_queue", [0, 2])
-def test_served_images_equal_alone_under_a_tight_budget(setup, share_queue):
+@pytest.mark.parametrize("share_queue,batch_fronts", [(0, True), (2, True), (0, False)])
+def test_served_images_equal_alone_under_a_tight_budget(setup, share_queue, batch_fronts):
     """All requests queued at once: with share_queue = 2 the server starts a
     request beside others only while two or more wait, so the queue drains
-    through both the shared and the one-at-a-time regime."""
+    through both the shared and the one-at-a-time regime.  With batch_fronts
+    the requests that start together (mixed resolutions) share one cull and
+    preprocess pass; their images are still those rendered alone."""
     import torch
     from paper_2408_07967_amd.serve import RenderServer
     scenes, gsc, R, _ = setup
@@ -64,7 +66,8 @@ def test_served_images_equal_alone_under_a_tight_budget(setup, share_queue):
     biggest = max(p for _, p in alone.values())
     # room for about two of the largest requests at once
     budget = int(2.2 * 16 * (biggest * 9 // 8 + 4096))
-    srv = RenderServer(gsc, budget_bytes=budget, max_inflight=5, max_bypass=2, share_queue=share_queue)
+    srv = RenderServer(gsc, budget_bytes=budget, max_inflight=5, max_bypass=2, share_queue=share_queue,
+                       batch_fronts=batch_fronts)
     try:
         got, outs = _serve_all(srv, reqs, gsc)
         st = srv.stats()
@@ -81,6 +84,10 @@ def test_served_images_equal_alone_under_a_tight_budget(setup, share_queue):
     assert st["completed"] == len(reqs)
     assert st["peak_bytes_in_use"] <= budget
     assert st["graphs_captured"] >= 1 and st["graph_launches"] == len(reqs)
+    if batch_fronts and share_queue == 0:
+        assert st["batched_fronts"] >= 1 and st["batched_requests"] >= 2
+    if not batch_fronts:
+        assert st["batched_fronts"] == 0
 
 
 def test_graph_replays_on_one_slot_match_eager(setup):
