@@ -183,6 +183,34 @@ fgs_status fgs_render(fgs_context *ctx, const fgs_scene *scene, const fgs_camera
 fgs_status fgs_plan(fgs_context *ctx, const fgs_scene *scene, const fgs_camera *cam, int32_t W, int32_t H,
                     const fgs_options *opt, int64_t *pairs_out, size_t *bytes_out, void *stream);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): fgs_render without a saved frame, whose
+ * kernels take every scratch buffer (per-Gaussian state, depth order, count
+ * scan, pairs and their sort ping-pong, tile ranges, large-rectangle chunk
+ * list, frame counters) from one fixed device array of
+ * FGS_NOALLOC_SCRATCH_BYTES per GPU, part of the library's code object: each
+ * GPU the library runs on holds it until the process ends.  The call makes no
+ * hipMalloc, hipFree or other allocating call (the context's events, second
+ * stream and pinned counter copy come from fgs_create, which also takes the
+ * array's device address).  Arguments, outputs and the single wait for the
+ * pair count are those of fgs_render; the image is bit-identical to it.
+ * Limits: the per-Gaussian part (about 130 B per Gaussian), the tile ranges
+ * (8 B per tile), the sort scratch and a chunk list of max(P / 8, 8192)
+ * entries are carved first and must fit, else FGS_ERR_CAPACITY before any
+ * device work; the rest holds the pairs (16 B each).  A frame with more pairs
+ * than that, or with more large-rectangle chunks than the list holds, returns
+ * FGS_ERR_CAPACITY after its device work (the image is then incomplete).
+ * Every call on one GPU, from any context, uses that GPU's one array, which
+ * keeps the previous call's contents (each frame clears what must start at
+ * zero): calls that overlap on one GPU race (different streams, threads or
+ * contexts without ordering between them), and a call returns with its
+ * second half still in flight on `stream`, so a later call on another stream
+ * must wait for that one first. */
+#define FGS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+fgs_status fgs_render_noalloc(fgs_context *ctx, const fgs_scene *scene, const fgs_camera *cam, int32_t W,
+                              int32_t H, const fgs_options *opt, float *out_rgb, float *out_T, uint32_t *out_last,
+                              fgs_stats *stats, void *stream);
+
 /* ---- prepared (resident) scenes ------------------------------------------ */
 
 /* The paper moves preprocessing shared by the viewpoints of one scene to an

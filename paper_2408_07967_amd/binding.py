@@ -61,6 +61,7 @@ INSTR_WORK = 2
 BLEND_LDS_BATCHES = 0
 BLEND_PREFETCH = 1
 MAX_BATCH_CAMERAS = 8
+NOALLOC_SCRATCH_BYTES = 64 << 20   # FGS_NOALLOC_SCRATCH_BYTES
 
 
 class FgsServerConfig(C.Structure):
@@ -101,6 +102,9 @@ PROTOTYPES = {
     "fgs_render": (C.c_int, [C.c_void_p, C.POINTER(FgsScene), C.POINTER(FgsCamera), C.c_int32, C.c_int32,
                              C.POINTER(FgsOptions), C.c_void_p, C.c_void_p, C.c_void_p,
                              C.POINTER(C.c_void_p), C.POINTER(FgsStats), C.c_void_p]),
+    "fgs_render_noalloc": (C.c_int, [C.c_void_p, C.POINTER(FgsScene), C.POINTER(FgsCamera), C.c_int32, C.c_int32,
+                                     C.POINTER(FgsOptions), C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.POINTER(FgsStats), C.c_void_p]),
     "fgs_render_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(FgsScene), C.POINTER(FgsCamera),
                                       C.POINTER(FgsOptions), C.c_void_p, C.POINTER(FgsSceneGrad), C.c_void_p]),
     "fgs_frame_release": (C.c_int, [C.c_void_p, C.c_void_p]),

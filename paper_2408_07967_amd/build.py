@@ -23,7 +23,7 @@ COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
 PER_FILE = {
     "k_project.hip": ["-ffp-contract=off"],
 }
-SOURCES = ["runtime.cpp", "pipeline.cpp", "server.cpp", "k_project.hip", "k_radix.hip", "k_sort.hip",
+SOURCES = ["runtime.cpp", "pipeline.cpp", "server.cpp", "noalloc.hip", "k_project.hip", "k_radix.hip", "k_sort.hip",
            "k_blend.hip", "k_backward.hip"]
 
 

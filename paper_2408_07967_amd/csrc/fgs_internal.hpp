@@ -79,6 +79,10 @@ struct FrameCounters {
 
 // ---- launchers (implemented in the .hip files) ----------------------------
 
+// Device address of the fixed scratch of fgs_render_noalloc
+// (FGS_NOALLOC_SCRATCH_BYTES) on `device`, which must be the current device.
+hipError_t noalloc_scratch(int device, unsigned char **base);
+
 void launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t s);
 
 // Rectangles of more than kBigTiles tiles are tested and emitted in chunks of

@@ -20,6 +20,7 @@ namespace {
 thread_local std::string g_null_ctx_error;
 }  // namespace
 
+
 void fgs::set_error_without_context(const char *msg) { g_null_ctx_error = msg; }
 
 struct fgs_frame {
@@ -77,6 +78,7 @@ struct fgs_context {
     };
     std::vector<BatchCam> batch;
     FrameCounters *bfc_dev = nullptr, *bfc_host = nullptr;  // kMaxCams each
+    unsigned char *noalloc_base = nullptr;  // this device's fixed scratch (fgs_render_noalloc)
 };
 
 namespace {
@@ -220,6 +222,12 @@ fgs_status fgs_create(int device, fgs_context **out) {
         ctx->side.create() != hipSuccess) {
         fgs_destroy(ctx);
         return fail(nullptr, FGS_ERR_DEVICE, "cannot create an event");
+    }
+    const hipError_t ne = noalloc_scratch(device, &ctx->noalloc_base);
+    if (ne != hipSuccess) {
+        fgs_destroy(ctx);
+        return fail(nullptr, FGS_ERR_DEVICE, "cannot take the fixed scratch's device address: %s",
+                    hipGetErrorString(ne));
     }
     *out = ctx;
     return FGS_OK;
@@ -493,6 +501,146 @@ fgs_status fgs_plan(fgs_context *ctx, const fgs_scene *scene, const fgs_camera *
     const PlanOut plan{pairs_out, bytes_out};
     return render_impl(ctx, scene, nullptr, cam, W, H, opt, nullptr, nullptr, nullptr, nullptr, nullptr, stream,
                        &plan);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Bump carving of the fixed scratch: 256-byte aligned pieces, in order.
+struct Carve {
+    unsigned char *base;
+    size_t size, used = 0;
+    bool overflow = false;
+    template <class T>
+    T *take(size_t n) {
+        const size_t off = (used + 255) & ~size_t(255);
+        const size_t b = n * sizeof(T);
+        if (off > size || b > size - off) {
+            overflow = true;
+            return nullptr;
+        }
+        used = off + b;
+        return reinterpret_cast<T *>(base + off);
+    }
+};
+
+// One frame's buffers in the fixed scratch: counters, sort scratch, tile
+// ranges, the per-Gaussian arrays for P, the chunk list, then four pair
+// arrays sharing what is left.  False if the fixed part does not fit.
+bool carve_noalloc(unsigned char *base, size_t P, size_t ntiles, FrameBuffers &fb, SortScratch &ss, ChunkList &ch,
+                   FrameCounters *&fc, size_t &fixed_bytes) {
+    Carve c{base, FGS_NOALLOC_SCRATCH_BYTES};
+    fb = FrameBuffers{};
+    fc = c.take<FrameCounters>(1);
+    ss.rhist = c.take<uint32_t>((size_t)kSortBlocks * kRadix);
+    ss.gsum = c.take<uint32_t>((size_t)kGsumSlots * kGsumWords);
+    ss.sums = c.take<uint32_t>((size_t)kSortBlocks);
+    fb.ranges = c.take<uint2>(ntiles);
+    fb.capTiles = ntiles;
+    const size_t capP = std::max<size_t>(P, 1);
+    fb.gs = c.take<GaussState>(capP);
+    fb.rect = c.take<uint4>(capP);
+    fb.count = c.take<uint32_t>(capP);
+    fb.count8 = c.take<uint8_t>(capP);
+    fb.erec = c.take<uint4>(capP);
+    fb.dkey = c.take<uint32_t>(capP);
+    fb.dk_b = c.take<uint32_t>(capP);
+    fb.dv_a = c.take<uint32_t>(capP);
+    fb.dv_b = c.take<uint32_t>(capP);
+    fb.offsets = c.take<uint32_t>(capP + 1);
+    fb.seg_count = c.take<uint32_t>(kCullBlocks);
+    fb.gmap = c.take<uint32_t>(capP);
+    fb.capP = capP;
+    ch.cap = std::max<size_t>(P / 8, 8192);
+    ch.chunks = c.take<uint2>(ch.cap);
+    ch.hits = c.take<uint32_t>(ch.cap);
+    ch.mask = c.take<uint32_t>(ch.cap * (kChunkTiles / 32));
+    fixed_bytes = c.used;
+    if (c.overflow) return false;
+    // the rest: four pair arrays of equal capacity, each 256-byte aligned
+    const size_t rest = FGS_NOALLOC_SCRATCH_BYTES - ((c.used + 255) & ~size_t(255));
+    const size_t capN = rest >= 4 * 256 ? (rest - 4 * 256) / (4 * sizeof(uint32_t)) : 0;
+    if (capN == 0) return false;
+    fb.tk_a = c.take<uint32_t>(capN);
+    fb.tk_b = c.take<uint32_t>(capN);
+    fb.tv_a = c.take<uint32_t>(capN);
+    fb.tv_b = c.take<uint32_t>(capN);
+    fb.capN = capN;
+    fb.pairs_owned = false;
+    return !c.overflow;
+}
+
+}  // namespace
+
+extern "C" {
+
+fgs_status fgs_render_noalloc(fgs_context *ctx, const fgs_scene *scene, const fgs_camera *cam, int32_t W,
+                              int32_t H, const fgs_options *opt_in, float *out_rgb, float *out_T, uint32_t *out_last,
+                              fgs_stats *stats, void *stream_v) {
+    if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARGUMENT, "context is NULL");
+    fgs_status st = validate(ctx, scene, cam, W, H, opt_in);
+    if (st != FGS_OK) return st;
+    if (!out_rgb) return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "out_rgb is NULL");
+    if (!ctx->noalloc_base) return fail(ctx, FGS_ERR_DEVICE, "the fixed scratch has no device address");
+    fgs_options opt;
+    if (opt_in)
+        opt = *opt_in;
+    else
+        fgs_default_options(&opt);
+    const int64_t P = scene->num_gaussians;
+    const int tiles_x = (W + kTile - 1) / kTile, tiles_y = (H + kTile - 1) / kTile;
+    const size_t ntiles = (size_t)tiles_x * (size_t)tiles_y;
+    FrameBuffers fb;
+    SortScratch ss;
+    ChunkList ch;
+    FrameCounters *fc = nullptr;
+    size_t fixed = 0;
+    if (!carve_noalloc(ctx->noalloc_base, (size_t)P, ntiles, fb, ss, ch, fc, fixed))
+        return fail(ctx, FGS_ERR_CAPACITY,
+                    "%lld Gaussians at %dx%d need %zu bytes of per-Gaussian, tile, sort and chunk buffers "
+                    "plus pair space; the fixed scratch holds %zu",
+                    (long long)P, W, H, fixed, (size_t)FGS_NOALLOC_SCRATCH_BYTES);
+    ctx->err.clear();
+    hipStream_t s = (hipStream_t)stream_v;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const DevScene dsc = to_dev(*scene);
+    const DevCamera dcam = to_dev(*cam);
+    const DevOptions dop = to_dev(opt);
+    const StageMarks mk;  // no stage events
+    enqueue_front(dsc, nullptr, dcam, dop, W, H, fb, ch, ss, fc, ctx->fc_host, s, ctx->side, mk, ctx->front_done);
+    HIP_TRY(ctx, hipGetLastError());
+    // the second half reads the pair count on the device and stays within the
+    // pair arrays, so it goes right behind the first
+    enqueue_back(W, H, dop, (uint32_t)P, fb, ch, ss, fc, out_rgb, out_T, out_last, nullptr, s, mk,
+                 ctx->blend_variant);
+    HIP_TRY(ctx, hipGetLastError());
+    hipError_t q;
+    while ((q = hipEventQuery(ctx->front_done)) == hipErrorNotReady) {
+    }
+    HIP_TRY(ctx, q);
+    const FrameCounters h = *ctx->fc_host;
+    if (stats) {
+        fgs_stats stt{};
+        stt.visible = h.visible;
+        stt.pairs = h.pairs;
+        stt.tiles_x = tiles_x;
+        stt.tiles_y = tiles_y;
+        stt.big_chunks = (int32_t)h.nchunks;
+        stt.candidates = P;
+        int b = 0;
+        while ((1ull << b) < (uint64_t)ntiles) ++b;
+        stt.sort_passes = 4 + (b + kRadixBits - 1) / kRadixBits;
+        *stats = stt;
+    }
+    if (h.error & kErrChunkOverflow)
+        return fail(ctx, FGS_ERR_CAPACITY, "the frame needs %u large-rectangle chunks; the fixed scratch holds %zu",
+                    h.nchunks, ch.cap);
+    if ((size_t)h.pairs > fb.capN)
+        return fail(ctx, FGS_ERR_CAPACITY, "the frame has %u pairs; the fixed scratch holds %zu beside its %zu "
+                    "bytes of per-Gaussian, tile, sort and chunk buffers",
+                    h.pairs, fb.capN, fixed);
+    return FGS_OK;
 }
 
 fgs_status fgs_prepare_scene(fgs_context *ctx, const fgs_scene *scene, const fgs_options *opt_in,

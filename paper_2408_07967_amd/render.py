@@ -111,6 +111,30 @@ class Renderer:
                                sort_passes=st.sort_passes, big_chunks=st.big_chunks,
                                candidates=st.candidates))
 
+    def render_noalloc(self, scene, cam, W, H, opts=None, out=None, want_T=False, want_last=False):
+        """render() through fgs_render_noalloc: every scratch buffer comes from
+        the library's fixed per-GPU array (B.NOALLOC_SCRATCH_BYTES); no frame
+        is saved.  Raises FgsError (FGS_ERR_CAPACITY) for a frame that does not
+        fit."""
+        dev = scene.means.device
+        rgb = out if out is not None else torch.empty((3, H, W), dtype=torch.float32, device=dev)
+        T = torch.empty((H, W), dtype=torch.float32, device=dev) if want_T else None
+        last = torch.empty((H, W), dtype=torch.int32, device=dev) if want_last else None
+        sc = scene.abi()
+        cm = camera_abi(cam)
+        op = options_abi(opts)
+        st = B.FgsStats()
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        self.ctx.check(B.lib().fgs_render_noalloc(self.ctx.handle, C.byref(sc), C.byref(cm), int(W), int(H),
+                                                  C.byref(op), rgb.data_ptr(),
+                                                  T.data_ptr() if T is not None else None,
+                                                  last.data_ptr() if last is not None else None, C.byref(st),
+                                                  stream))
+        return dict(rgb=rgb, T=T, last=last, frame=None,
+                    stats=dict(visible=st.visible, pairs=st.pairs, tiles_x=st.tiles_x, tiles_y=st.tiles_y,
+                               sort_passes=st.sort_passes, big_chunks=st.big_chunks,
+                               candidates=st.candidates))
+
     def render_batch(self, prepared, scene, cams, W, H, opts=None, want_T=False, want_last=False):
         """Render several cameras of a prepared scene in one call (one cull and
         one preprocess pass for the whole batch).  Returns one dict per camera

@@ -20,6 +20,7 @@ namespace {
 namespace fgs {
 
 void launch_fill_u32(uint32_t *, uint32_t, size_t, hipStream_t) { reached("fill_u32"); }
+hipError_t noalloc_scratch(int, unsigned char **) { reached("noalloc_scratch"); }
 unsigned preprocess_grid(int64_t) { reached("preprocess_grid"); }
 unsigned emit_grid(uint32_t) { reached("emit_grid"); }
 void launch_preprocess(const DevScene &, const DevPrepared *, const DevCamera &, const DevCam64 &, const DevOptions &, int, int,
