@@ -220,12 +220,17 @@ fgs_status fgs_render_noalloc(fgs_context *ctx, const fgs_scene *scene, const fg
  * screen extent (trace of the 3D covariance), and the SH coefficients
  * Gaussian-major, so a frame reads 24 bytes for every Gaussian, 48 more for
  * the candidates of its cull and one contiguous run of SH for the visible
- * ones.  Device memory owned by the context: 56 B + 4 ceil4(3 (D+1)^2) B per
- * Gaussian (248 B at degree 3).  It depends on the scene's values
- * (copy of the fgs_scene struct kept; the planes must stay valid and
- * unchanged for backward passes) and on opt->alpha_min and opt->cap_3sigma.
- * Frames rendered from it are bit-identical to fgs_render of the scene.
- * Enqueued on `stream`. */
+ * ones.  The precompute stores the Gaussians in a spatial order (Morton order
+ * of the means, computed and sorted here), so that the candidates of a
+ * frame's cull, which see one region of the scene, are read as few
+ * contiguous runs; frames re-order equal depths by Gaussian index, so the
+ * pair order is still the method's.  Device memory owned by the context:
+ * 60 B + 4 ceil4(3 (D+1)^2) B per Gaussian (252 B at degree 3), plus 16 B
+ * per Gaussian and the sort scratch during the call.  It depends on the
+ * scene's values (copy of the fgs_scene struct kept; the planes must stay
+ * valid and unchanged for backward passes) and on opt->alpha_min and
+ * opt->cap_3sigma.  Frames rendered from it are bit-identical to fgs_render
+ * of the scene.  Runs on `stream` and waits for it before returning. */
 typedef struct fgs_prepared fgs_prepared;
 fgs_status fgs_prepare_scene(fgs_context *ctx, const fgs_scene *scene, const fgs_options *opt, fgs_prepared **out,
                              void *stream);

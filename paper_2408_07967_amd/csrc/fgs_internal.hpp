@@ -51,6 +51,8 @@ struct DevPrepared {
                           // and the unit quaternion, both binary32 as the canonical evaluation rounds them
     const float *sh;      // Gaussian-major SH, sh_stride floats per Gaussian
     const float2 *bnd;    // (trace of the 3D covariance, k^2): bounds the screen extent
+    const uint32_t *orig; // Gaussian (index in the caller's scene) of each precompute slot: the slots
+                          // follow a spatial order of the means (see launch_prepare)
     int sh_stride;
 };
 
@@ -75,6 +77,7 @@ struct FrameCounters {
     uint32_t error;    // error bits (kErrChunkOverflow)
     uint32_t nchunks;  // entries requested in the large-Gaussian chunk list
     uint32_t ncand;    // candidates of a prepared scene's cull (dense depth keys)
+    uint32_t nlong;    // runs of more than kShortTieRun equal depths (prepared scene)
 };
 
 // ---- launchers (implemented in the .hip files) ----------------------------
@@ -158,6 +161,7 @@ struct CamOut {
     uint8_t *count8;
     uint4 *erec;
     uint32_t *dkey;
+    uint32_t *gmap;        // this camera's copy of the list's Gaussian indices
     uint2 *chunks;
     FrameCounters *fc;     // this camera's counters (cleared by the cull)
     uint32_t *gsum_clear;  // this camera's first depth pass group sums
@@ -167,15 +171,38 @@ struct MultiOut {
     CamOut c[kMaxCams];
     int n;  // cameras in the batch, 1..kMaxCams
 };
-// Each camera has its own image size.  cand, seg_count, gmap: as for
-// launch_preprocess (one union list).
+// Each camera has its own image size.  cand, seg_count: as for
+// launch_preprocess (one union list); each camera gets the list's Gaussian
+// indices in its own CamOut::gmap (gmap is unused).
 void launch_preprocess_multi(const DevScene &sc, const DevPrepared &pp, const MultiOut &mo, const DevOptions &op,
                              uint32_t *cand, uint32_t *seg_count, uint32_t *gmap, hipStream_t s);
 
 // View-independent precompute (opacity, 3D covariance, k^2, log2 opacity,
-// Gaussian-major SH) for options op (alpha_min and cap_3sigma).
-void launch_prepare(const DevScene &sc, const DevOptions &op, float4 *pos_o, float4 *cov, float *sh, float2 *bnd,
-                    int sh_stride, hipStream_t s);
+// Gaussian-major SH) for options op (alpha_min and cap_3sigma), stored in
+// slot order: slot i holds Gaussian perm[i] (orig[i] = perm[i]).
+void launch_prepare(const DevScene &sc, const DevOptions &op, const uint32_t *perm, float4 *pos_o, float4 *cov,
+                    float *sh, float2 *bnd, uint32_t *orig, int sh_stride, hipStream_t s);
+// Spatial order of a scene's Gaussians: bounds[0..5] = (min x, y, z, max x,
+// y, z) of the finite means (bounds: 6 words, initialised by the launcher),
+// then keys[g] = 30-bit Morton code of the mean quantised to 1024 cells per
+// axis of that box (0xffffffff for a non-finite mean).  Sorting (key, g) by
+// key gives the precompute's slot order: a cull's candidates then lie in
+// few contiguous runs of slots.
+void launch_spatial_keys(const DevScene &sc, uint32_t *bounds, uint32_t *keys, hipStream_t s);
+
+// Depth ties of a prepared scene's frame: the depth sort orders equal depths
+// by list position, which follows the precompute's spatial order; the
+// method's order (depth, then Gaussian index) needs every run of equal keys
+// re-ordered by gmap (the list position's Gaussian index).  keys: the sorted
+// depth keys, vals: the sorted list positions (n = *n_dev, bounded by
+// n_host).  A run of at most kShortTieRun is sorted by the thread that
+// starts it; longer runs (rare: that many Gaussians at one binary32 depth)
+// are listed in long_list (fc->nlong of them, which the frame's cull
+// cleared) and sorted by one workgroup each, with the run's region of tmp_v
+// ([n_host]) as scratch.
+constexpr int kShortTieRun = 32;
+void launch_depth_ties(const uint32_t *keys, uint32_t *vals, const uint32_t *gmap, uint32_t n_host,
+                       const uint32_t *n_dev, uint32_t *long_list, FrameCounters *fc, uint32_t *tmp_v, hipStream_t s);
 
 // Exact tile counts of the chunked Gaussians: per-chunk hit masks and counts,
 // atomic per-Gaussian sums.

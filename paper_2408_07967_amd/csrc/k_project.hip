@@ -308,14 +308,19 @@ __device__ __forceinline__ float extent_k2(float o, const DevOptions &op) {
 // opacity 0 for a Gaussian that can never be visible, the scales, the unit
 // quaternion and k^2, the trace of the 3D covariance with k^2 (the cull's
 // extent bound), and the SH coefficients Gaussian-major.  The same operations
-// as the per-frame path, so frames render bit for bit the same.
-__global__ __launch_bounds__(kBlock) void k_prepare(DevScene sc, DevOptions op, float4 *__restrict__ pos_o,
-                                                    float4 *__restrict__ cov, float *__restrict__ sh_out,
-                                                    float2 *__restrict__ bnd, int sh_stride) {
+// as the per-frame path, so frames render bit for bit the same.  Slot i holds
+// Gaussian perm[i] (a spatial order, so that the candidates of a frame's cull
+// are read as few contiguous runs), and orig[i] = perm[i].
+__global__ __launch_bounds__(kBlock) void k_prepare(DevScene sc, DevOptions op, const uint32_t *__restrict__ perm,
+                                                    float4 *__restrict__ pos_o, float4 *__restrict__ cov,
+                                                    float *__restrict__ sh_out, float2 *__restrict__ bnd,
+                                                    uint32_t *__restrict__ orig, int sh_stride) {
     const int64_t st = sc.stride;
     const int ncoef = 3 * (sc.D + 1) * (sc.D + 1);
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < sc.P;
-         g += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < sc.P;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t g = perm[i];
+        orig[i] = (uint32_t)g;
         const float mx = sc.means[g], my = sc.means[st + g], mz = sc.means[2 * st + g];
         const float logit = sc.logits[g];
         const float o = (float)(1.0 / (1.0 + canon_exp(-(double)logit)));
@@ -330,28 +335,119 @@ __global__ __launch_bounds__(kBlock) void k_prepare(DevScene sc, DevOptions op, 
             sigma3(s3, qu, S);
             k2 = extent_k2(o, op);
         }
-        pos_o[g] = make_float4(mx, my, mz, ok ? o : 0.0f);
-        cov[2 * g] = make_float4(s3[0], s3[1], s3[2], k2);
-        cov[2 * g + 1] = make_float4(qu[0], qu[1], qu[2], qu[3]);
+        pos_o[i] = make_float4(mx, my, mz, ok ? o : 0.0f);
+        cov[2 * i] = make_float4(s3[0], s3[1], s3[2], k2);
+        cov[2 * i + 1] = make_float4(qu[0], qu[1], qu[2], qu[3]);
         // trace(Sigma) >= its largest eigenvalue: bounds the screen extent
-        bnd[g] = make_float2(S[0] + S[3] + S[5], k2);
+        bnd[i] = make_float2(S[0] + S[3] + S[5], k2);
     }
-    // SH: planar in, Gaussian-major out, transposed through LDS so that both
-    // the reads (one plane, consecutive Gaussians) and the writes (the
-    // workgroup's records, one contiguous range) are coalesced
+    // SH: planar in, Gaussian-major out, transposed through LDS so that the
+    // writes (the workgroup's slots, one contiguous range) are coalesced
     __shared__ float s_t[kBlock * (48 + 1)];
-    for (int64_t g0 = (int64_t)blockIdx.x * kBlock; g0 < sc.P; g0 += (int64_t)gridDim.x * kBlock) {
-        const int64_t g = g0 + threadIdx.x;
-        const int n = sc.P - g0 < kBlock ? (int)(sc.P - g0) : kBlock;
+    for (int64_t i0 = (int64_t)blockIdx.x * kBlock; i0 < sc.P; i0 += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = i0 + threadIdx.x;
+        const int n = sc.P - i0 < kBlock ? (int)(sc.P - i0) : kBlock;
+        const int64_t g = i < sc.P ? (int64_t)perm[i] : 0;
         __syncthreads();
         for (int j = 0; j < sh_stride; ++j)
-            s_t[threadIdx.x * (48 + 1) + j] = (j < ncoef && g < sc.P) ? sc.sh[(int64_t)j * st + g] : 0.0f;
+            s_t[threadIdx.x * (48 + 1) + j] = (j < ncoef && i < sc.P) ? sc.sh[(int64_t)j * st + g] : 0.0f;
         __syncthreads();
-        float *dst = sh_out + g0 * sh_stride;
+        float *dst = sh_out + i0 * sh_stride;
         for (int e = threadIdx.x; e < n * sh_stride; e += kBlock) {
             const int r = e / sh_stride, j = e - r * sh_stride;
             dst[e] = s_t[r * (48 + 1) + j];
         }
+    }
+}
+
+// A binary32 value as an unsigned integer of the same order (for atomic
+// min / max), and back.
+__device__ __forceinline__ uint32_t float_order(float f) {
+    const uint32_t b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float order_float(uint32_t u) {
+    return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+// Box of the finite means: per workgroup a reduction over its Gaussians,
+// then one atomic min / max per axis into bounds (order-mapped, see
+// float_order).
+__global__ __launch_bounds__(kBlock) void k_spatial_bounds(DevScene sc, uint32_t *__restrict__ bounds) {
+    const int64_t st = sc.stride;
+    uint32_t lo[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu}, hi[3] = {0u, 0u, 0u};
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < sc.P; g += (int64_t)gridDim.x * blockDim.x) {
+        const float m[3] = {sc.means[g], sc.means[st + g], sc.means[2 * st + g]};
+        if (!(isfinite(m[0]) && isfinite(m[1]) && isfinite(m[2]))) continue;
+        for (int a = 0; a < 3; ++a) {
+            const uint32_t u = float_order(m[a]);
+            lo[a] = u < lo[a] ? u : lo[a];
+            hi[a] = u > hi[a] ? u : hi[a];
+        }
+    }
+    __shared__ uint32_t s_lo[3][kBlock / kWave], s_hi[3][kBlock / kWave];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    for (int a = 0; a < 3; ++a) {
+        uint32_t l = lo[a], h = hi[a];
+        for (int d = kWave / 2; d > 0; d >>= 1) {
+            const uint32_t l2 = (uint32_t)__shfl_xor((int)l, d, kWave), h2 = (uint32_t)__shfl_xor((int)h, d, kWave);
+            l = l2 < l ? l2 : l;
+            h = h2 > h ? h2 : h;
+        }
+        if (lane == 0) {
+            s_lo[a][wave] = l;
+            s_hi[a][wave] = h;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int a = threadIdx.x;
+        uint32_t l = 0xffffffffu, h = 0u;
+        for (int w = 0; w < kBlock / kWave; ++w) {
+            l = s_lo[a][w] < l ? s_lo[a][w] : l;
+            h = s_hi[a][w] > h ? s_hi[a][w] : h;
+        }
+        if (l != 0xffffffffu) atomicMin(&bounds[a], l);
+        if (h != 0u) atomicMax(&bounds[3 + a], h);
+    }
+}
+
+__global__ void k_spatial_bounds_init(uint32_t *bounds) {
+    if (threadIdx.x < 6) bounds[threadIdx.x] = threadIdx.x < 3 ? 0xffffffffu : 0u;
+}
+
+// Ten bits of x spread to every third bit (bit b to bit 3b).
+__device__ __forceinline__ uint32_t spread3(uint32_t x) {
+    x &= 0x3ffu;
+    x = (x | (x << 16)) & 0x030000ffu;
+    x = (x | (x << 8)) & 0x0300f00fu;
+    x = (x | (x << 4)) & 0x030c30c3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+
+// Morton code of each mean quantised to 1024 cells per axis of the box.
+__global__ __launch_bounds__(kBlock) void k_spatial_keys(DevScene sc, const uint32_t *__restrict__ bounds,
+                                                         uint32_t *__restrict__ keys) {
+    const int64_t st = sc.stride;
+    float lo[3], sc3[3];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = order_float(bounds[a]);
+        const float ext = order_float(bounds[3 + a]) - lo[a];
+        sc3[a] = ext > 0.0f ? 1024.0f / ext : 0.0f;
+    }
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < sc.P; g += (int64_t)gridDim.x * blockDim.x) {
+        const float m[3] = {sc.means[g], sc.means[st + g], sc.means[2 * st + g]};
+        uint32_t key = 0xffffffffu;
+        if (isfinite(m[0]) && isfinite(m[1]) && isfinite(m[2]) && bounds[0] != 0xffffffffu) {
+            uint32_t q[3];
+            for (int a = 0; a < 3; ++a) {
+                const float c = (m[a] - lo[a]) * sc3[a];
+                q[a] = c <= 0.0f ? 0u : (c >= 1023.0f ? 1023u : (uint32_t)c);
+            }
+            key = spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2);
+        }
+        keys[g] = key;
     }
 }
 
@@ -918,7 +1014,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         const uint32_t key = valid ? __float_as_uint(tz) : kInvalidKey;
         const int64_t oi = kPrep ? (int64_t)ii : g;  // output slot
         if constexpr (kPrep) {
-            if (ci == 0) gmap[ii] = (uint32_t)g;
+            // the Gaussian of this list position, in the caller's indexing
+            uint32_t *const gmap_c = kMulti ? mo.c[ci].gmap : gmap;
+            gmap_c[ii] = pp.orig[g];
         }
         dkey_c[oi] = key;
         count_c[oi] = valid ? cnt : 0u;
@@ -1254,12 +1352,21 @@ void launch_preprocess_multi(const DevScene &sc, const DevPrepared &pp, const Mu
                        c0.chunk_cap, c0.fc, c0.gsum_clear, mo);
 }
 
-void launch_prepare(const DevScene &sc, const DevOptions &op, float4 *pos_o, float4 *cov, float *sh, float2 *bnd,
-                    int sh_stride, hipStream_t s) {
+void launch_prepare(const DevScene &sc, const DevOptions &op, const uint32_t *perm, float4 *pos_o, float4 *cov,
+                    float *sh, float2 *bnd, uint32_t *orig, int sh_stride, hipStream_t s) {
     if (sc.P <= 0) return;
     const int64_t blocks = (sc.P + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_prepare, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(kBlock), 0, s, sc, op,
-                       pos_o, cov, sh, bnd, sh_stride);
+    hipLaunchKernelGGL(k_prepare, dim3((unsigned)(blocks < 8192 ? blocks : 8192)), dim3(kBlock), 0, s, sc, op, perm,
+                       pos_o, cov, sh, bnd, orig, sh_stride);
+}
+
+void launch_spatial_keys(const DevScene &sc, uint32_t *bounds, uint32_t *keys, hipStream_t s) {
+    hipLaunchKernelGGL(k_spatial_bounds_init, dim3(1), dim3(64), 0, s, bounds);
+    if (sc.P <= 0) return;
+    const int64_t blocks = (sc.P + kBlock - 1) / kBlock;
+    const unsigned grid = (unsigned)(blocks < 4096 ? blocks : 4096);
+    hipLaunchKernelGGL(k_spatial_bounds, dim3(grid), dim3(kBlock), 0, s, sc, bounds);
+    hipLaunchKernelGGL(k_spatial_keys, dim3(grid), dim3(kBlock), 0, s, sc, bounds, keys);
 }
 
 void launch_big_count(int W, int H, int binning, const GaussState *gs, const uint4 *rect, const uint2 *chunks,

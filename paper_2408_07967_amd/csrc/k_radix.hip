@@ -398,6 +398,192 @@ __global__ __launch_bounds__(kBlock) void k_scan_downsweep(const uint32_t *__res
     if (hi == n && lo < hi && threadIdx.x == 0) offsets[n] = run;
 }
 
+// ---- depth ties of a prepared scene's frame -------------------------------
+// The depth sort is stable over list positions, whose order follows the
+// precompute's spatial order; the method orders equal depths by Gaussian
+// index.  Each wavefront owns kTieOwn consecutive sorted positions and also
+// reads the kTieLook after them.  A run of equal keys that begins among its
+// own positions and ends within that span is re-ordered in place: every
+// member reads its list position's Gaussian index, counts the members with
+// a smaller index (through LDS) and stores its list position at that rank.
+// The wavefront whose positions hold a run's start is the only one that
+// touches the run.  A run that reaches the end of the span (at least
+// kTieLook + 1 long) is listed for k_depth_long_ties.  Keys and list
+// positions are read once, coalesced; only tied positions gather.
+constexpr int kTieOwn = 256, kTieLook = 32, kTieSpan = kTieOwn + kTieLook;
+static_assert(kTieLook <= kWave && kTieOwn % kWave == 0, "span of whole wavefront loads");
+static_assert(kTieLook <= kShortTieRun, "runs listed as long are longer than kShortTieRun");
+__global__ __launch_bounds__(kBlock) void k_depth_ties(const uint32_t *__restrict__ keys, uint32_t *vals,
+                                                       const uint32_t *__restrict__ gmap, uint32_t n_host,
+                                                       const uint32_t *n_dev, uint32_t *__restrict__ long_list,
+                                                       FrameCounters *fc) {
+    constexpr int kSub = (kTieSpan + kWave - 1) / kWave;
+    __shared__ uint32_t s_key[kWaves][kTieSpan], s_idx[kWaves][kTieSpan];
+    const uint32_t n = count_of(n_host, n_dev);
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const uint32_t base = (blockIdx.x * kWaves + (uint32_t)wv) * (uint32_t)kTieOwn;
+    if (base >= n) return;  // uniform over the wavefront
+    uint32_t *const sk = s_key[wv], *const si = s_idx[wv];
+    // sorted keys are valid depth bits, never kInvalidKey
+    uint32_t k[kSub], v[kSub];
+#pragma unroll
+    for (int w = 0; w < kSub; ++w) {
+        const int q = w * kWave + lane;
+        const bool in = q < kTieSpan && base + (uint32_t)q < n;
+        k[w] = in ? keys[base + q] : kInvalidKey;
+        v[w] = in ? vals[base + q] : 0u;
+        if (q < kTieSpan) sk[q] = k[w];
+    }
+    const uint32_t kbefore = base > 0 ? keys[base - 1] : kInvalidKey;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    int S[kSub], E[kSub];
+    bool here[kSub];
+#pragma unroll
+    for (int w = 0; w < kSub; ++w) {
+        const int q = w * kWave + lane;
+        here[w] = false;
+        S[w] = E[w] = q;
+        if (q >= kTieSpan || k[w] == kInvalidKey) continue;
+        const uint32_t kq = k[w];
+        const bool prev_eq = q > 0 ? sk[q - 1] == kq : kbefore == kq;
+        const bool next_eq = q + 1 < kTieSpan ? sk[q + 1] == kq : true;  // unknown past the span
+        if (!prev_eq && !next_eq) continue;
+        int s0 = q;
+        while (s0 > 0 && sk[s0 - 1] == kq) --s0;
+        if (s0 == 0 && kbefore == kq) continue;  // begun before these positions
+        if (s0 >= kTieOwn) continue;              // the next wavefront's run
+        int e0 = q + 1;
+        while (e0 < kTieSpan && sk[e0] == kq) ++e0;
+        if (e0 == kTieSpan) {
+            // reaches the end of the span: a long run, ordered elsewhere
+            if (q == s0) long_list[atomicAdd(&fc->nlong, 1u)] = base + (uint32_t)s0;
+            continue;
+        }
+        S[w] = s0;
+        E[w] = e0;
+        here[w] = true;
+        si[q] = gmap[v[w]];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int w = 0; w < kSub; ++w) {
+        if (!here[w]) continue;
+        const int q = w * kWave + lane;
+        const uint32_t o = si[q];
+        uint32_t rank = 0;
+        for (int j = S[w]; j < E[w]; ++j) rank += si[j] < o ? 1u : 0u;
+        vals[base + (uint32_t)S[w] + rank] = v[w];
+    }
+}
+
+// Position of the first of the n ascending Gaussian indices gmap[v[.]] that
+// is not below key.
+__device__ __forceinline__ uint32_t tie_lower_bound(const uint32_t *v, uint32_t n, const uint32_t *gmap,
+                                                    uint32_t key) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t m = (lo + hi) >> 1;
+        if (gmap[v[m]] < key)
+            lo = m + 1;
+        else
+            hi = m;
+    }
+    return lo;
+}
+
+// One workgroup per listed run of more than kShortTieRun equal keys: its
+// length, then a sort of its list positions by Gaussian index (distinct
+// keys): chunks of kTieChunk by a bitonic sort in LDS, then merge passes in
+// which every element finds its place in the merged pair of sorted pieces by
+// a binary search in the other piece.  The values ping-pong between vals and
+// tmp_v (the run's own region of each), so runs never touch each other's data.
+constexpr uint32_t kTieChunk = 1024;
+__global__ __launch_bounds__(kBlock) void k_depth_long_ties(const uint32_t *__restrict__ keys, uint32_t *vals,
+                                                            const uint32_t *__restrict__ gmap, uint32_t n_host,
+                                                            const uint32_t *n_dev,
+                                                            const uint32_t *__restrict__ long_list,
+                                                            const FrameCounters *fc, uint32_t *tmp_v) {
+    __shared__ uint32_t s_k[kTieChunk], s_v[kTieChunk];
+    __shared__ uint32_t s_len;
+    const uint32_t n = count_of(n_host, n_dev);
+    const uint32_t nl = fc->nlong;
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t r = blockIdx.x; r < nl; r += gridDim.x) {
+        const uint32_t s0 = long_list[r];
+        const uint32_t k = keys[s0];
+        if (tid == 0) s_len = n - s0;
+        __syncthreads();
+        // run length: the first later position with another key
+        for (uint32_t base = s0; base < n; base += kBlock) {
+            const uint32_t p = base + tid;
+            if (p < n && keys[p] != k) atomicMin(&s_len, p - s0);
+            __syncthreads();
+            const bool found = s_len < base + kBlock - s0;
+            __syncthreads();
+            if (found) break;
+        }
+        const uint32_t L = s_len;
+        uint32_t *run = vals + s0, *tmp = tmp_v + s0;
+        // sorted chunks, written to tmp
+        for (uint32_t c0 = 0; c0 < L; c0 += kTieChunk) {
+            for (uint32_t j = tid; j < kTieChunk; j += kBlock) {
+                const uint32_t p = c0 + j;
+                const uint32_t v = p < L ? run[p] : 0u;
+                s_v[j] = v;
+                s_k[j] = p < L ? gmap[v] : 0xffffffffu;
+            }
+            __syncthreads();
+            for (uint32_t size = 2; size <= kTieChunk; size <<= 1) {
+                for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+                    for (uint32_t j = tid; j < kTieChunk; j += kBlock) {
+                        const uint32_t q = j ^ stride;
+                        if (q > j) {
+                            const bool up = (j & size) == 0;
+                            const uint32_t kj = s_k[j], kq = s_k[q];
+                            if ((kj > kq) == up) {
+                                s_k[j] = kq;
+                                s_k[q] = kj;
+                                const uint32_t t = s_v[j];
+                                s_v[j] = s_v[q];
+                                s_v[q] = t;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            for (uint32_t j = tid; j < kTieChunk; j += kBlock)
+                if (c0 + j < L) tmp[c0 + j] = s_v[j];
+            __syncthreads();
+        }
+        // merge passes: pieces of w sorted values, pairs merged into the
+        // other buffer
+        const uint32_t *src = tmp;
+        uint32_t *dst = run;
+        for (uint32_t w = kTieChunk; w < L; w <<= 1) {
+            for (uint32_t p = tid; p < L; p += kBlock) {
+                const uint32_t p0 = p / (2 * w) * (2 * w);
+                const uint32_t mid = p0 + w < L ? p0 + w : L, end = p0 + 2 * w < L ? p0 + 2 * w : L;
+                const uint32_t v = src[p], key = gmap[v];
+                const uint32_t pos = p < mid ? (p - p0) + tie_lower_bound(src + mid, end - mid, gmap, key)
+                                             : (p - mid) + tie_lower_bound(src + p0, mid - p0, gmap, key);
+                dst[p0 + pos] = v;
+            }
+            __syncthreads();
+            const uint32_t *t = src;
+            src = dst;
+            dst = const_cast<uint32_t *>(t);
+        }
+        if (src != run)
+            for (uint32_t p = tid; p < L; p += kBlock) run[p] = src[p];
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 void launch_radix_pass(const void *keys_in, const uint32_t *vals_in, void *keys_out, uint32_t *vals_out,
@@ -443,6 +629,17 @@ void launch_count_scan(const uint32_t *order, const uint8_t *count8, const uint3
                        sums);
     hipLaunchKernelGGL(k_scan_downsweep, dim3(kSortBlocks), dim3(kBlock), 0, s, cs, n_host, n_dev, sums, offsets,
                        pairs);
+}
+
+void launch_depth_ties(const uint32_t *keys, uint32_t *vals, const uint32_t *gmap, uint32_t n_host,
+                       const uint32_t *n_dev, uint32_t *long_list, FrameCounters *fc, uint32_t *tmp_v, hipStream_t s) {
+    if (n_host == 0) return;
+    const uint32_t per_block = (uint32_t)kWaves * kTieOwn;
+    const uint32_t blocks = (n_host + per_block - 1) / per_block;
+    hipLaunchKernelGGL(k_depth_ties, dim3(blocks), dim3(kBlock), 0, s, keys, vals, gmap, n_host, n_dev, long_list,
+                       fc);
+    hipLaunchKernelGGL(k_depth_long_ties, dim3(64), dim3(kBlock), 0, s, keys, vals, gmap, n_host, n_dev, long_list,
+                       static_cast<const FrameCounters *>(fc), tmp_v);
 }
 
 }  // namespace fgs

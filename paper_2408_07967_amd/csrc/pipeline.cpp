@@ -250,11 +250,38 @@ hipError_t build_prepared(const fgs_scene &sc, const fgs_options &op, PreparedBu
     if ((e = hipMalloc((void **)&pb.cov, 2 * n * sizeof(float4))) != hipSuccess) return e;
     if ((e = hipMalloc((void **)&pb.sh, n * (size_t)pb.sh_stride * sizeof(float))) != hipSuccess) return e;
     if ((e = hipMalloc((void **)&pb.bnd, n * sizeof(float2))) != hipSuccess) return e;
-    launch_prepare(to_dev(sc), to_dev(op), pb.pos_o, pb.cov, pb.sh, pb.bnd, pb.sh_stride, s);
-    return hipGetLastError();
+    if ((e = hipMalloc((void **)&pb.orig, n * sizeof(uint32_t))) != hipSuccess) return e;
+    // Slot order: the Gaussians sorted by the Morton code of their means
+    // (stable, so equal codes keep index order), so that the candidates of a
+    // frame's cull, which see one region of the scene, occupy few contiguous
+    // runs of slots and their precompute is read line by line.
+    const DevScene dsc = to_dev(sc);
+    uint32_t *tmp = nullptr;  // keys a, keys b, values a, values b (n each), bounds (8)
+    SortScratch ss;
+    if ((e = hipMalloc((void **)&tmp, (4 * n + 8) * sizeof(uint32_t))) != hipSuccess) return e;
+    if ((e = ensure_sort_scratch(ss)) != hipSuccess) {
+        (void)hipFree(tmp);
+        return e;
+    }
+    uint32_t *ka = tmp, *kb = tmp + n, *va = tmp + 2 * n, *vb = tmp + 3 * n, *bounds = tmp + 4 * n;
+    const uint32_t P32 = (uint32_t)(P > 0 ? P : 0);
+    launch_spatial_keys(dsc, bounds, ka, s);
+    launch_fill_u32(ss.slot(0), 0u, (size_t)kGsumWords, s);
+    launch_radix_pass(ka, nullptr, kb, vb, P32, nullptr, 0, 8, false, true, ss.rhist, ss.slot(0), ss.slot(1), s);
+    launch_radix_pass(kb, vb, ka, va, P32, nullptr, 8, 8, false, true, ss.rhist, ss.slot(1), ss.slot(2), s);
+    launch_radix_pass(ka, va, kb, vb, P32, nullptr, 16, 8, false, true, ss.rhist, ss.slot(2), ss.slot(3), s);
+    launch_radix_pass(kb, vb, nullptr, va, P32, nullptr, 24, 8, false, false, ss.rhist, ss.slot(3), nullptr, s);
+    launch_prepare(dsc, to_dev(op), va, pb.pos_o, pb.cov, pb.sh, pb.bnd, pb.orig, pb.sh_stride, s);
+    e = hipGetLastError();
+    // the temporary buffers are read by the work just enqueued
+    const hipError_t e2 = hipStreamSynchronize(s);
+    (void)hipFree(tmp);
+    free_sort_scratch(ss);
+    return e != hipSuccess ? e : e2;
 }
 
 void free_prepared(PreparedBuffers &pb) {
+    free_p(*(void **)&pb.orig);
     free_p(*(void **)&pb.pos_o);
     free_p(*(void **)&pb.cov);
     free_p(*(void **)&pb.sh);
@@ -323,8 +350,14 @@ void enqueue_front_rest(bool dense, uint32_t P32, const DevOptions &op, int W, i
                       ss.slot(2), s);
     launch_radix_pass(fb.dkey, fb.dv_a, fb.dk_b, fb.dv_b, P32, &fc->visible, 16, 8, false, true, ss.rhist, ss.slot(2),
                       ss.slot(3), s);
-    launch_radix_pass(fb.dk_b, fb.dv_b, fb.dkey, fb.dv_a, P32, &fc->visible, 24, 8, false, false, ss.rhist,
+    // (a prepared scene's frame keeps the sorted keys: its ties need them)
+    launch_radix_pass(fb.dk_b, fb.dv_b, fb.dkey, fb.dv_a, P32, &fc->visible, 24, 8, false, dense, ss.rhist,
                       ss.slot(3), nullptr, s);
+    // A prepared scene's list positions follow the precompute's spatial
+    // order, so the stable sort left equal depths in that order: re-order each
+    // run of equal depths by Gaussian index (the long-run list borrows the
+    // offsets, which the scan writes next; dv_b is free after the last pass)
+    if (dense) launch_depth_ties(fb.dkey, fb.dv_a, fb.gmap, P32, &fc->visible, fb.offsets, fc, fb.dv_b, s);
     // the scan reads the counts of the large rectangles
     if (sb != s && joined && hipStreamWaitEvent(s, side.join, 0) != hipSuccess) (void)hipStreamSynchronize(sb);
     mk.mark(2, s);

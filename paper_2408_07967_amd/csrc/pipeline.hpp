@@ -138,15 +138,17 @@ struct PreparedBuffers {
     float4 *cov = nullptr;
     float *sh = nullptr;
     float2 *bnd = nullptr;
+    uint32_t *orig = nullptr;  // Gaussian of each slot (the slots follow a spatial order)
     int sh_stride = 0;
     int64_t P = 0;
     size_t bytes() const {
-        return (size_t)P * (3 * sizeof(float4) + sizeof(float2) + (size_t)sh_stride * sizeof(float));
+        return (size_t)P * (3 * sizeof(float4) + sizeof(float2) + sizeof(uint32_t) + (size_t)sh_stride * sizeof(float));
     }
-    DevPrepared dev() const { return DevPrepared{pos_o, cov, sh, bnd, sh_stride}; }
+    DevPrepared dev() const { return DevPrepared{pos_o, cov, sh, bnd, orig, sh_stride}; }
 };
 
-// Allocate and fill the precompute of sc for options op on stream s.
+// Allocate and fill the precompute of sc for options op on stream s, in a
+// spatial slot order (Morton order of the means); waits for the stream.
 hipError_t build_prepared(const fgs_scene &sc, const fgs_options &op, PreparedBuffers &pb, hipStream_t s);
 void free_prepared(PreparedBuffers &pb);
 

@@ -765,6 +765,7 @@ fgs_status fgs_render_prepared_batch(fgs_context *ctx, const fgs_prepared *p, co
             o.count8 = bc.fb.count8;
             o.erec = bc.fb.erec;
             o.dkey = bc.fb.dkey;
+            o.gmap = bc.fb.gmap;
             o.chunks = bc.ch.chunks;
             o.chunk_cap = (uint32_t)std::min<size_t>(bc.ch.cap, 0xffffffffu);
             o.fc = ctx->bfc_dev + c;

@@ -210,6 +210,7 @@ void start_front_batch(fgs_server *srv, const std::vector<Slot *> &b) {
         o.count8 = s.fb.count8;
         o.erec = s.fb.erec;
         o.dkey = s.fb.dkey;
+        o.gmap = s.fb.gmap;
         o.chunks = s.ch.chunks;
         o.chunk_cap = (uint32_t)std::min<size_t>(s.ch.cap, 0xffffffffu);
         o.fc = s.fc_dev;

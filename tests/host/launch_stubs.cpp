@@ -36,8 +36,14 @@ void launch_preprocess_multi(const DevScene &, const DevPrepared &, const MultiO
                              uint32_t *, uint32_t *, hipStream_t) {
     reached("preprocess_multi");
 }
-void launch_prepare(const DevScene &, const DevOptions &, float4 *, float4 *, float *, float2 *, int, hipStream_t) {
+void launch_prepare(const DevScene &, const DevOptions &, const uint32_t *, float4 *, float4 *, float *, float2 *,
+                    uint32_t *, int, hipStream_t) {
     reached("prepare");
+}
+void launch_spatial_keys(const DevScene &, uint32_t *, uint32_t *, hipStream_t) { reached("spatial_keys"); }
+void launch_depth_ties(const uint32_t *, uint32_t *, const uint32_t *, uint32_t, const uint32_t *, uint32_t *,
+                       FrameCounters *, uint32_t *, hipStream_t) {
+    reached("depth_ties");
 }
 void launch_big_count(int, int, int, const GaussState *, const uint4 *, const uint2 *, uint32_t, uint32_t *,
                       uint32_t *, uint32_t *, const FrameCounters *, hipStream_t) {

@@ -146,12 +146,31 @@ def test_3sigma_square_binning_parity(orc, R, scenes, kind, P, W, H):
 
 
 @pytest.mark.parametrize("case", ["small", "random_sh3", "degenerate", "medium_binning2", "uncapped",
-                                  "offscreen_big", "offscreen_big_binning2"])
+                                  "offscreen_big", "offscreen_big_binning2", "ties_short", "ties_long",
+                                  "ties_one_run", "city1M-540p"])
 def test_prepared_scene_is_bit_identical(orc, R, scenes, case):
     """A frame from the view-independent precompute equals the frame from the
-    raw parameters bit for bit (state, pairs, order, image, T, last)."""
+    raw parameters bit for bit (state, pairs, order, image, T, last).  The
+    precompute holds the Gaussians in a spatial order, so equal depths leave
+    its depth sort in that order and are re-ordered by Gaussian index; the
+    ties cases put many Gaussians at exactly equal depths: runs of 2 to 30
+    (sorted by one thread each), runs of about 60 (sorted by a workgroup in
+    LDS), and one run of 6000 (sorted in 1024-chunks and merged)."""
     o = opts()
-    if case == "small":
+    if case.startswith("ties"):
+        rng = np.random.default_rng({"ties_short": 41, "ties_long": 42, "ties_one_run": 43}[case])
+        n = 6000
+        sc = random_scene(rng, n, ls_mu=-3.4, ls_sigma=0.3, sh_degree=1)
+        levels = {"ties_short": 600, "ties_long": 100, "ties_one_run": 1}[case]
+        # identity camera: the depth is the mean's z, exactly
+        sc.means[2] = (np.float32(4.0) + np.float32(0.01) * rng.integers(0, levels, n).astype(np.float32))
+        W, H = 320, 240
+        cam = identity_camera(W, H, 0.9 * W)
+    elif case == "city1M-540p":
+        sc = scenes.make_scene("city", P=1_000_000)
+        W, H = 960, 540
+        cam = scenes.camera_for("city", W=W, H=H)
+    elif case == "small":
         sc, cam, W, H = scenes.make_scene("small"), scenes.camera_for("small"), 256, 256
     elif case == "random_sh3":
         sc = random_scene(np.random.default_rng(31), 4000, ls_mu=-2.4, sh_degree=3)
@@ -184,6 +203,7 @@ def test_prepared_scene_is_bit_identical(orc, R, scenes, case):
     else:
         sc, cam, W, H = scenes.make_scene("small"), scenes.camera_for("small"), 256, 256
         o = opts(cap_3sigma=0, alpha_min=0.01)
+    print(f"[parity] prepared scene: {case} P={sc.P} {W}x{H}", flush=True)
     gsc = _gs(sc)
     h = R.prepare(gsc, o)
     try:
@@ -191,6 +211,12 @@ def test_prepared_scene_is_bit_identical(orc, R, scenes, case):
         b = gpu_frame(R, gsc, cam, W, H, o, prepared=h)
     finally:
         R.release_prepared(h)
+    if case.startswith("ties"):
+        d = a["gauss"][a["order"].astype(np.int64), 10].view(np.uint32)
+        runs = np.diff(np.flatnonzero(np.r_[True, d[1:] != d[:-1], True]))
+        print(f"[parity] {case}: {a['stats']['visible']} visible, longest run of equal depths {runs.max()}, "
+              f"runs over 32: {(runs > 32).sum()}", flush=True)
+        assert runs.max() >= {"ties_short": 2, "ties_long": 33, "ties_one_run": 4000}[case]
     # the prepared scene preprocesses only the cull's candidates: never fewer
     # than the visible Gaussians, never more than the scene holds
     ca, cb = a["stats"].pop("candidates"), b["stats"].pop("candidates")
