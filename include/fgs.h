@@ -373,6 +373,22 @@ fgs_status fgs_set_blend_variant(fgs_context *ctx, int32_t variant);
 /* Wait for the last instrumented frame and return the sums. */
 fgs_status fgs_get_instrumentation(fgs_context *ctx, fgs_timings *out);
 
+/* Measured peak rates of the context's device (measurement only): kernels
+ * that do nothing but one operation over enough wavefronts to fill every
+ * SIMD, timed with HIP events (best of several runs).  They give the
+ * measured denominators of the rooflines beside the published peaks.
+ * Allocates and frees 2 GiB of device memory for the copy; synchronises the
+ * device.  Takes a few tens of milliseconds. */
+typedef struct {
+    double fma_lane_ops_per_s;    /* binary32 FMAs (non-packed), lane operations per second */
+    double valu_wave_instr_per_s; /* the same as wave64 VALU instructions per second        */
+    double exp_lane_ops_per_s;    /* v_exp_f32, lane operations per second                   */
+    double copy_bytes_per_s;      /* device-to-device copy, bytes read plus written per second */
+    int32_t compute_units;
+    int32_t clock_mhz;            /* the device's reported peak engine clock                 */
+} fgs_peaks;
+fgs_status fgs_measure_peaks(fgs_context *ctx, fgs_peaks *out);
+
 size_t fgs_frame_field_bytes(const fgs_frame *frame, fgs_field field);
 fgs_status fgs_frame_download(fgs_context *ctx, const fgs_frame *frame, fgs_field field, void *host_dst,
                               size_t bytes);

@@ -56,6 +56,12 @@ class FgsTimings(C.Structure):
                 ("ms_cull", C.c_double), ("blend_wave_steps", C.c_int64)]
 
 
+class FgsPeaks(C.Structure):
+    _fields_ = [("fma_lane_ops_per_s", C.c_double), ("valu_wave_instr_per_s", C.c_double),
+                ("exp_lane_ops_per_s", C.c_double), ("copy_bytes_per_s", C.c_double),
+                ("compute_units", C.c_int32), ("clock_mhz", C.c_int32)]
+
+
 INSTR_STAGE_TIMES = 1
 INSTR_WORK = 2
 BLEND_LDS_BATCHES = 0
@@ -114,6 +120,7 @@ PROTOTYPES = {
     "fgs_set_instrumentation": (C.c_int, [C.c_void_p, C.c_int]),
     "fgs_set_blend_variant": (C.c_int, [C.c_void_p, C.c_int32]),
     "fgs_get_instrumentation": (C.c_int, [C.c_void_p, C.POINTER(FgsTimings)]),
+    "fgs_measure_peaks": (C.c_int, [C.c_void_p, C.POINTER(FgsPeaks)]),
     "fgs_plan": (C.c_int, [C.c_void_p, C.POINTER(FgsScene), C.POINTER(FgsCamera), C.c_int32, C.c_int32,
                            C.POINTER(FgsOptions), C.POINTER(C.c_int64), C.POINTER(C.c_size_t), C.c_void_p]),
     "fgs_prepare_scene": (C.c_int, [C.c_void_p, C.POINTER(FgsScene), C.POINTER(FgsOptions),

@@ -24,7 +24,7 @@ PER_FILE = {
     "k_project.hip": ["-ffp-contract=off"],
 }
 SOURCES = ["runtime.cpp", "pipeline.cpp", "server.cpp", "noalloc.hip", "k_project.hip", "k_radix.hip", "k_sort.hip",
-           "k_blend.hip", "k_backward.hip"]
+           "k_blend.hip", "k_backward.hip", "k_peaks.hip"]
 
 
 def hipcc():

@@ -56,18 +56,19 @@ struct DevPrepared {
     int sh_stride;
 };
 
-// Per-Gaussian state, 64 bytes = 4 x float4.
+// Per-Gaussian state of the blend, 48 bytes = 3 x float4.
 //   f0 = (u, v, Ab, Bb)   f1 = (Cb, k2, log2 o, r)   f2 = (g, b, depth, o)
-//   f3 = (A, B, C, 0)
-// (A, B, C) is the conic of the canonical binary32 evaluation: it decides the
-// Gaussian-tile pairs (exact tile test) bit for bit.  (Ab, Bb, Cb) is the
-// same conic evaluated in binary64 from the binary32 scales and unit
-// quaternion and rounded once: the blend and its adjoint evaluate pixels with
+// (Ab, Bb, Cb) is the conic evaluated in binary64 from the binary32 scales
+// and unit quaternion and rounded once: the blend and its adjoint evaluate
+// pixels with it.  The canonical binary32 conic (A, B, C), which decides the
+// Gaussian-tile pairs (exact tile test) bit for bit, travels in a separate
+// float4 array (A, B, C, 0): the preprocess tests the small rectangles
+// itself, so only the large ones' tests (and the frame introspection) read
 // it.  For long thin footprints the binary32 inverse of the dilated 2D
 // covariance loses most of its bits to cancellation in the determinant; the
-// binary64 one keeps the narrow axis.  The blend reads f0..f2 only.
+// binary64 one keeps the narrow axis.
 struct alignas(16) GaussState {
-    float4 f0, f1, f2, f3;
+    float4 f0, f1, f2;
 };
 
 // Frame-scoped device counters, cleared at the start of a frame.
@@ -87,6 +88,14 @@ struct FrameCounters {
 hipError_t noalloc_scratch(int device, unsigned char **base);
 
 void launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t s);
+
+// Peak-rate kernels (fgs_measure_peaks): `blocks` workgroups of kBlock lanes,
+// each lane running `iters` x 8 independent binary32 FMAs / v_exp_f32; a
+// 16-byte-element device copy of `bytes`.
+constexpr int kPeakChains = 8;
+void launch_peak_fma(int blocks, int iters, float *sink, hipStream_t s);
+void launch_peak_exp(int blocks, int iters, float *sink, hipStream_t s);
+void launch_peak_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 
 // Rectangles of more than kBigTiles tiles are tested and emitted in chunks of
 // kChunkTiles tiles by workgroups spread over the whole GPU.
@@ -114,6 +123,12 @@ unsigned emit_grid(uint32_t visible);
 
 // Preprocess: per-Gaussian state, tile rectangle, exact tile count, emission
 // record, depth key (kInvalidKey for culled Gaussians) and the visible count.
+// What later kernels need is always written: state, emission record, one-byte
+// count, depth key, Gaussian map, and for rectangles of more than kBigTiles
+// tiles the canonical conic and count 0.  With `full` (a frame kept for
+// introspection or the backward) the rectangle, the count and the canonical
+// conic of every valid Gaussian are written too, and a prepared scene's
+// culled candidates get zero state, rectangle and conic.
 // The emission record is (tx0 | tx1 << 16, ty0 | ty1 << 16, hit mask low,
 // hit mask high).  Large rectangles append chunk entries (g, first chunk) to
 // `chunks` (capacity chunk_cap; on overflow the error bit kErrChunkOverflow
@@ -138,10 +153,10 @@ constexpr uint8_t kCount8Big = 255;
 void launch_cull(const DevScene &sc, const DevPrepared &pp, const DevCamera &cam, const DevOptions &op, int W, int H,
                  uint32_t *cand, uint32_t *seg_count, FrameCounters *fc, hipStream_t s);
 void launch_preprocess(const DevScene &sc, const DevPrepared *pp, const DevCamera &cam, const DevCam64 &cam64,
-                       const DevOptions &op, int W, int H, GaussState *gs, uint4 *rect, uint32_t *count, uint8_t *count8, uint4 *erec,
-                       uint32_t *dkey,
-                       uint32_t *cand, uint32_t *seg_count, uint32_t *gmap, uint2 *chunks, uint32_t chunk_cap,
-                       FrameCounters *fc, uint32_t *gsum_clear, hipStream_t s);
+                       const DevOptions &op, int W, int H, GaussState *gs, float4 *conic, uint4 *rect, uint32_t *count,
+                       uint8_t *count8, uint4 *erec, uint32_t *dkey, uint32_t *cand, uint32_t *seg_count,
+                       uint32_t *gmap, uint2 *chunks, uint32_t chunk_cap, FrameCounters *fc, uint32_t *gsum_clear,
+                       bool full, hipStream_t s);
 
 // Multi-camera batch over one prepared scene (Sec. 5.3.1 applied to several
 // viewpoints at once): one cull keeps the union of the cameras' candidates,
@@ -156,6 +171,7 @@ struct CamOut {
     DevCam64 cam64;
     int W, H;  // this camera's image
     GaussState *gs;
+    float4 *conic;
     uint4 *rect;
     uint32_t *count;
     uint8_t *count8;
@@ -206,7 +222,8 @@ void launch_depth_ties(const uint32_t *keys, uint32_t *vals, const uint32_t *gma
 
 // Exact tile counts of the chunked Gaussians: per-chunk hit masks and counts,
 // atomic per-Gaussian sums.
-void launch_big_count(int W, int H, int binning, const GaussState *gs, const uint4 *rect, const uint2 *chunks,
+void launch_big_count(int W, int H, int binning, const GaussState *gs, const float4 *conic, const uint4 *erec,
+                      const uint2 *chunks,
                       uint32_t chunk_cap, uint32_t *chunk_hits, uint32_t *chunk_mask, uint32_t *count,
                       const FrameCounters *fc, hipStream_t s);
 
@@ -222,7 +239,7 @@ void launch_emit(int W, int H, const uint32_t *order, uint32_t visible, const ui
                  uint2 *ranges, uint32_t ntiles, uint32_t *gsum_clear, hipStream_t s);
 
 // Emit the pairs of the chunked Gaussians (after launch_emit).
-void launch_big_emit(int W, const uint4 *rect, const uint4 *erec, const uint2 *chunks, uint32_t chunk_cap,
+void launch_big_emit(int W, const uint4 *erec, const uint2 *chunks, uint32_t chunk_cap,
                      const uint32_t *chunk_hits, const uint32_t *chunk_mask, void *tile_keys, int key_bytes,
                      uint32_t *values, uint32_t cap, const FrameCounters *fc, hipStream_t s);
 

@@ -176,6 +176,11 @@ __device__ __forceinline__ void row_col(int idx, int ntx, float rcpn, int &ry, i
     rx += (below - above) * ntx;
 }
 
+// (tx0, tx1, ty0, ty1) of an emission record's packed rectangle
+__device__ __forceinline__ uint4 unpack_rect(const uint4 &r) {
+    return make_uint4(r.x & 0xffffu, r.x >> 16, r.y & 0xffffu, r.y >> 16);
+}
+
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, int lane) {
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) {
@@ -567,6 +572,7 @@ __global__ __launch_bounds__(kBlock) void k_cull(DevScene sc, DevPrepared pp, De
 template <bool kPrep, bool kMulti = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_preprocess(DevScene sc, DevPrepared pp, DevCamera cam, DevCam64 cam64, DevOptions op,
                                                        int W_arg, int H_arg, GaussState *__restrict__ gs,
+                                                       float4 *__restrict__ conic,
                                                        uint4 *__restrict__ rect, uint32_t *__restrict__ count,
                                                        uint8_t *__restrict__ count8, uint4 *__restrict__ erec,
                                                        uint32_t *__restrict__ dkey,
@@ -574,7 +580,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                                                        const uint32_t *__restrict__ seg_count,
                                                        uint32_t *__restrict__ gmap, uint2 *__restrict__ chunks,
                                                        uint32_t chunk_cap, FrameCounters *fc,
-                                                       uint32_t *__restrict__ gsum_clear, MultiOut mo) {
+                                                       uint32_t *__restrict__ gsum_clear, int full, MultiOut mo) {
     static_assert(!kMulti || kPrep, "a batch walks a union candidate list");
     // the first depth pass's group sums start at zero
     if constexpr (kMulti) {
@@ -757,6 +763,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const int W = kMulti ? mo.c[ci].W : W_arg, H = kMulti ? mo.c[ci].H : H_arg;
     const DevCam64 &cm64 = kMulti ? mo.c[ci].cam64 : cam64;
     GaussState *__restrict__ const gs_c = kMulti ? mo.c[ci].gs : gs;
+    float4 *__restrict__ const conic_c = kMulti ? mo.c[ci].conic : conic;
     uint4 *__restrict__ const rect_c = kMulti ? mo.c[ci].rect : rect;
     uint32_t *__restrict__ const count_c = kMulti ? mo.c[ci].count : count;
     uint8_t *__restrict__ const count8_c = kMulti ? mo.c[ci].count8 : count8;
@@ -1019,25 +1026,29 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             gmap_c[ii] = pp.orig[g];
         }
         dkey_c[oi] = key;
-        count_c[oi] = valid ? cnt : 0u;
         count8_c[oi] = chunked ? kCount8Big : (uint8_t)(valid ? cnt : 0u);  // cnt <= kBigTiles < kCount8Big
+        // the 4-byte count: a chunked rectangle's starts at 0 (k_big_count
+        // adds its hits); the others are read from count8
+        if (full || chunked) count_c[oi] = valid ? cnt : 0u;
         if (valid) {
             GaussState s;
             s.f0 = make_float4(u, v, Ab, Bb);
             s.f1 = make_float4(Cb, k2, l2o, col[0]);
             s.f2 = make_float4(col[1], col[2], tz, o);
-            s.f3 = make_float4(A, B, C, 0.0f);
             gs_c[oi] = s;
-            rect_c[oi] = make_uint4((uint32_t)tx0, (uint32_t)tx1, (uint32_t)ty0, (uint32_t)ty1);
+            // the canonical conic: the large rectangles' tile tests read it
+            if (full || chunked) conic_c[oi] = make_float4(A, B, C, 0.0f);
+            if (full) rect_c[oi] = make_uint4((uint32_t)tx0, (uint32_t)tx1, (uint32_t)ty0, (uint32_t)ty1);
             // emission record: rectangle (4 x 16 bits) and hit mask in one
-            // 16-byte gather
+            // 16-byte gather (a chunked one's is written at its flush)
             if (!chunked)
                 erec_c[oi] = make_uint4((uint32_t)tx0 | ((uint32_t)tx1 << 16), (uint32_t)ty0 | ((uint32_t)ty1 << 16),
                                       (uint32_t)hm, (uint32_t)(hm >> 32));
-        } else if (kPrep) {
+        } else if (kPrep && full) {
             // a list slot is reused every frame: clear a culled candidate's
-            // state and rectangle
+            // introspected state
             gs_c[oi] = GaussState{};
+            conic_c[oi] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             rect_c[oi] = make_uint4(0u, 0u, 0u, 0u);
         }
     }
@@ -1145,7 +1156,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(int W, int H, const uint32_t *_
 // workgroup keeps four chunks in flight without barriers; the next chunk's
 // descriptor is loaded before the current chunk is tested.
 __global__ __launch_bounds__(kBlock) void k_big_count(int W, int H, int binning, const GaussState *__restrict__ gs,
-                                                      const uint4 *__restrict__ rect,
+                                                      const float4 *__restrict__ conic,
+                                                      const uint4 *__restrict__ erec,
                                                       const uint2 *__restrict__ chunks, uint32_t chunk_cap,
                                                       uint32_t *__restrict__ chunk_hits,
                                                       uint32_t *__restrict__ chunk_mask, uint32_t *count,
@@ -1166,11 +1178,15 @@ __global__ __launch_bounds__(kBlock) void k_big_count(int W, int H, int binning,
             continue;
         }
         const uint32_t g = e.x, c = ch - e.y;
-        const uint4 rc = rect[g];
+        const uint4 rc = unpack_rect(erec[g]);
         const int ntx = (int)rc.y - (int)rc.x + 1;
         const int nt = ntx * ((int)rc.w - (int)rc.z + 1);
         GaussState s{};
-        if (binning == 0) s = gs[g];
+        float4 cn = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (binning == 0) {
+            s = gs[g];
+            cn = conic[g];
+        }
         const float rcpn = __builtin_amdgcn_rcpf((float)ntx);
         uint32_t tot = 0;
 #pragma unroll
@@ -1181,7 +1197,7 @@ __global__ __launch_bounds__(kBlock) void k_big_count(int W, int H, int binning,
                 int ry, rx;
                 row_col(idx, ntx, rcpn, ry, rx);
                 h = binning != 0 ||
-                    tile_hit(s.f0.x, s.f0.y, s.f3.x, s.f3.y, s.f3.z, s.f1.y, (int)rc.x + rx, (int)rc.z + ry, W, H);
+                    tile_hit(s.f0.x, s.f0.y, cn.x, cn.y, cn.z, s.f1.y, (int)rc.x + rx, (int)rc.z + ry, W, H);
             }
             const uint64_t b = __ballot(h);
             tot += (uint32_t)__popcll(b);
@@ -1203,19 +1219,19 @@ __global__ __launch_bounds__(kBlock) void k_big_count(int W, int H, int binning,
 // A wavefront walks its chunks one ahead: while it writes a chunk's pairs, the
 // next chunk's data is already in flight in a single vector load (one dword
 // per lane: the hit mask, the chunk's hit count, the rectangle, the output
-// base and the hit counts of up to 50 earlier chunks of the Gaussian), and
+// base and the hit counts of up to 52 earlier chunks of the Gaussian), and
 // the chunk entry after that in a scalar load.
 template <class KeyT>
-__global__ __launch_bounds__(kBlock) void k_big_emit(int W, const uint4 *__restrict__ rect,
-                                                     const uint4 *__restrict__ erec, const uint2 *__restrict__ chunks,
+__global__ __launch_bounds__(kBlock) void k_big_emit(int W, const uint4 *__restrict__ erec,
+                                                     const uint2 *__restrict__ chunks,
                                                      uint32_t chunk_cap, const uint32_t *__restrict__ chunk_hits,
                                                      const uint32_t *__restrict__ chunk_mask,
                                                      KeyT *__restrict__ tile_keys, uint32_t *__restrict__ values,
                                                      uint32_t cap, const FrameCounters *fc) {
     constexpr int kPer = kChunkTiles / kWave;
     constexpr int kMaskWords = kChunkTiles / 32;
-    // lanes of the look-ahead load
-    constexpr int kLaneHits = kMaskWords, kLaneRect = kLaneHits + 1, kLaneBase = kLaneRect + 4,
+    // lanes of the look-ahead load (the rectangle: the record's two packed words)
+    constexpr int kLaneHits = kMaskWords, kLaneRect = kLaneHits + 1, kLaneBase = kLaneRect + 2,
                   kLanePre = kLaneBase + 1;
     // an overflowed list has entries this frame never wrote (the frame is
     // rendered again, or reported, by the host)
@@ -1233,7 +1249,7 @@ __global__ __launch_bounds__(kBlock) void k_big_emit(int W, const uint4 *__restr
         const uint32_t *src = chunk_hits + k;
         const bool use = lane < kLanePre || k < c;
         src = lane == kLaneBase ? reinterpret_cast<const uint32_t *>(erec + g) + 2 : src;
-        src = lane < kLaneBase ? reinterpret_cast<const uint32_t *>(rect + g) + (lane - kLaneRect) : src;
+        src = lane < kLaneBase ? reinterpret_cast<const uint32_t *>(erec + g) + (lane - kLaneRect) : src;
         src = lane == kLaneHits ? chunk_hits + c : src;
         src = lane < kMaskWords ? chunk_mask + (size_t)c * kMaskWords + lane : src;
         return use ? *src : 0u;
@@ -1243,8 +1259,7 @@ __global__ __launch_bounds__(kBlock) void k_big_emit(int W, const uint4 *__restr
         const uint32_t hits = bcast(v, kLaneHits);
         if (hits == 0) return;
         const uint32_t g = ec.x, first = ec.y;
-        const uint4 rc = make_uint4(bcast(v, kLaneRect), bcast(v, kLaneRect + 1), bcast(v, kLaneRect + 2),
-                                    bcast(v, kLaneRect + 3));
+        const uint4 rc = unpack_rect(make_uint4(bcast(v, kLaneRect), bcast(v, kLaneRect + 1), 0u, 0u));
         const uint32_t base = bcast(v, kLaneBase);
         // hits of this Gaussian's earlier chunks (past the first 50: loaded here)
         uint32_t p = lane >= kLanePre ? v : 0u;
@@ -1320,17 +1335,19 @@ unsigned emit_grid(uint32_t visible) {
 }
 
 void launch_preprocess(const DevScene &sc, const DevPrepared *pp, const DevCamera &cam, const DevCam64 &cam64,
-                       const DevOptions &op, int W, int H, GaussState *gs, uint4 *rect, uint32_t *count, uint8_t *count8, uint4 *erec,
-                       uint32_t *dkey,
-                       uint32_t *cand, uint32_t *seg_count, uint32_t *gmap, uint2 *chunks, uint32_t chunk_cap,
-                       FrameCounters *fc, uint32_t *gsum_clear, hipStream_t s) {
+                       const DevOptions &op, int W, int H, GaussState *gs, float4 *conic, uint4 *rect, uint32_t *count,
+                       uint8_t *count8, uint4 *erec, uint32_t *dkey, uint32_t *cand, uint32_t *seg_count,
+                       uint32_t *gmap, uint2 *chunks, uint32_t chunk_cap, FrameCounters *fc, uint32_t *gsum_clear,
+                       bool full, hipStream_t s) {
     if (sc.P <= 0) return;
     if (pp) {
-        hipLaunchKernelGGL(k_preprocess<true>, dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, *pp, cam, cam64, op, W,
-                           H, gs, rect, count, count8, erec, dkey, cand, seg_count, gmap, chunks, chunk_cap, fc, gsum_clear, MultiOut{});
+        hipLaunchKernelGGL(k_preprocess<true>, dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, *pp, cam, cam64, op,
+                           W, H, gs, conic, rect, count, count8, erec, dkey, cand, seg_count, gmap, chunks, chunk_cap,
+                           fc, gsum_clear, (int)full, MultiOut{});
     } else {
         hipLaunchKernelGGL(k_preprocess<false>, dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, DevPrepared{},
-                           cam, cam64, op, W, H, gs, rect, count, count8, erec, dkey, cand, seg_count, gmap, chunks, chunk_cap, fc, gsum_clear, MultiOut{});
+                           cam, cam64, op, W, H, gs, conic, rect, count, count8, erec, dkey, cand, seg_count, gmap,
+                           chunks, chunk_cap, fc, gsum_clear, (int)full, MultiOut{});
     }
 }
 
@@ -1347,9 +1364,9 @@ void launch_preprocess_multi(const DevScene &sc, const DevPrepared &pp, const Mu
     const CamOut &c0 = mo.c[0];
     hipLaunchKernelGGL(k_cull<true>, dim3(kCullBlocks), dim3(kBlock), 0, s, sc, pp, c0.cam, op, c0.W, c0.H, cand,
                        seg_count, c0.fc, mo);
-    hipLaunchKernelGGL((k_preprocess<true, true>), dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, pp, c0.cam, c0.cam64, op, c0.W,
-                       c0.H, c0.gs, c0.rect, c0.count, c0.count8, c0.erec, c0.dkey, cand, seg_count, gmap, c0.chunks,
-                       c0.chunk_cap, c0.fc, c0.gsum_clear, mo);
+    hipLaunchKernelGGL((k_preprocess<true, true>), dim3(preprocess_grid(sc.P)), dim3(kBlock), 0, s, sc, pp, c0.cam,
+                       c0.cam64, op, c0.W, c0.H, c0.gs, c0.conic, c0.rect, c0.count, c0.count8, c0.erec, c0.dkey, cand,
+                       seg_count, gmap, c0.chunks, c0.chunk_cap, c0.fc, c0.gsum_clear, 0, mo);
 }
 
 void launch_prepare(const DevScene &sc, const DevOptions &op, const uint32_t *perm, float4 *pos_o, float4 *cov,
@@ -1369,22 +1386,22 @@ void launch_spatial_keys(const DevScene &sc, uint32_t *bounds, uint32_t *keys, h
     hipLaunchKernelGGL(k_spatial_keys, dim3(grid), dim3(kBlock), 0, s, sc, bounds, keys);
 }
 
-void launch_big_count(int W, int H, int binning, const GaussState *gs, const uint4 *rect, const uint2 *chunks,
-                      uint32_t chunk_cap, uint32_t *chunk_hits, uint32_t *chunk_mask, uint32_t *count,
-                      const FrameCounters *fc, hipStream_t s) {
+void launch_big_count(int W, int H, int binning, const GaussState *gs, const float4 *conic, const uint4 *erec,
+                      const uint2 *chunks, uint32_t chunk_cap, uint32_t *chunk_hits, uint32_t *chunk_mask,
+                      uint32_t *count, const FrameCounters *fc, hipStream_t s) {
     if (chunk_cap == 0) return;
-    hipLaunchKernelGGL(k_big_count, dim3(kPersistentBlocks), dim3(kBlock), 0, s, W, H, binning, gs, rect, chunks,
-                       chunk_cap, chunk_hits, chunk_mask, count, fc);
+    hipLaunchKernelGGL(k_big_count, dim3(kPersistentBlocks), dim3(kBlock), 0, s, W, H, binning, gs, conic, erec,
+                       chunks, chunk_cap, chunk_hits, chunk_mask, count, fc);
 }
 
-void launch_big_emit(int W, const uint4 *rect, const uint4 *erec, const uint2 *chunks, uint32_t chunk_cap,
-                     const uint32_t *chunk_hits, const uint32_t *chunk_mask, void *tile_keys, int key_bytes,
-                     uint32_t *values, uint32_t cap, const FrameCounters *fc, hipStream_t s) {
+void launch_big_emit(int W, const uint4 *erec, const uint2 *chunks, uint32_t chunk_cap, const uint32_t *chunk_hits,
+                     const uint32_t *chunk_mask, void *tile_keys, int key_bytes, uint32_t *values, uint32_t cap,
+                     const FrameCounters *fc, hipStream_t s) {
     if (key_bytes == 2)
-        hipLaunchKernelGGL(k_big_emit<uint16_t>, dim3(kPersistentBlocks), dim3(kBlock), 0, s, W, rect, erec, chunks,
+        hipLaunchKernelGGL(k_big_emit<uint16_t>, dim3(kPersistentBlocks), dim3(kBlock), 0, s, W, erec, chunks,
                            chunk_cap, chunk_hits, chunk_mask, static_cast<uint16_t *>(tile_keys), values, cap, fc);
     else
-        hipLaunchKernelGGL(k_big_emit<uint32_t>, dim3(kPersistentBlocks), dim3(kBlock), 0, s, W, rect, erec, chunks,
+        hipLaunchKernelGGL(k_big_emit<uint32_t>, dim3(kPersistentBlocks), dim3(kBlock), 0, s, W, erec, chunks,
                            chunk_cap, chunk_hits, chunk_mask, static_cast<uint32_t *>(tile_keys), values, cap, fc);
 }
 

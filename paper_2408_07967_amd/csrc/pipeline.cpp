@@ -66,6 +66,7 @@ hipError_t ensure_gauss(FrameBuffers &b, size_t P) {
     if (P <= b.capP && b.gs) return hipSuccess;
     const size_t cap = P + P / 8 + 1024;
     FGS_GROW(b.gs, cap);
+    FGS_GROW(b.conic, cap);
     FGS_GROW(b.rect, cap);
     FGS_GROW(b.count, cap);
     FGS_GROW(b.count8, cap);
@@ -127,7 +128,7 @@ hipError_t ensure_chunks(ChunkList &c, size_t need) {
 }
 
 void free_frame_buffers(FrameBuffers &b) {
-    void **ps[] = {(void **)&b.gs, (void **)&b.rect, (void **)&b.count, (void **)&b.count8, (void **)&b.erec, (void **)&b.dkey,
+    void **ps[] = {(void **)&b.gs, (void **)&b.conic, (void **)&b.rect, (void **)&b.count, (void **)&b.count8, (void **)&b.erec, (void **)&b.dkey,
                    (void **)&b.dk_b, (void **)&b.dv_a, (void **)&b.dv_b, (void **)&b.offsets, (void **)&b.seg_count, (void **)&b.gmap,
                    (void **)&b.ranges,
                    (void **)&b.T, (void **)&b.last};
@@ -306,7 +307,7 @@ void SideStream::destroy() {
 void enqueue_front(const DevScene &sc, const DevPrepared *pp, const DevCamera &cam, const DevOptions &op, int W,
                    int H, FrameBuffers &fb, ChunkList &ch, SortScratch &ss, FrameCounters *fc,
                    FrameCounters *host_fc, hipStream_t s, const SideStream &side, const StageMarks &mk,
-                   hipEvent_t counters_ready) {
+                   hipEvent_t counters_ready, bool full) {
     const uint32_t chunk_cap = (uint32_t)std::min<size_t>(ch.cap, 0xffffffffu);
     // ---- stage 1: preprocess + exact tile count -------------------------------
     // (a prepared scene's cull clears the counters itself)
@@ -320,8 +321,8 @@ void enqueue_front(const DevScene &sc, const DevPrepared *pp, const DevCamera &c
     // previous pass's downsweep)
     if (pp) launch_cull(sc, *pp, cam, op, W, H, fb.dv_b, fb.seg_count, fc, s);
     mk.mark(kMarkCulled, s);
-    launch_preprocess(sc, pp, cam, to_dev64(cam, op, W, H), op, W, H, fb.gs, fb.rect, fb.count, fb.count8, fb.erec, fb.dkey, fb.dv_b, fb.seg_count,
-                      fb.gmap, ch.chunks, chunk_cap, fc, ss.slot(0), s);
+    launch_preprocess(sc, pp, cam, to_dev64(cam, op, W, H), op, W, H, fb.gs, fb.conic, fb.rect, fb.count, fb.count8,
+                      fb.erec, fb.dkey, fb.dv_b, fb.seg_count, fb.gmap, ch.chunks, chunk_cap, fc, ss.slot(0), full, s);
     enqueue_front_rest(pp != nullptr, (uint32_t)sc.P, op, W, H, fb, ch, ss, fc, host_fc, s, side, mk, counters_ready);
 }
 
@@ -335,7 +336,8 @@ void enqueue_front_rest(bool dense, uint32_t P32, const DevOptions &op, int W, i
     if (side.side && hipEventRecord(side.fork, s) == hipSuccess &&
         hipStreamWaitEvent(side.side, side.fork, 0) == hipSuccess)
         sb = side.side;
-    launch_big_count(W, H, op.binning, fb.gs, fb.rect, ch.chunks, chunk_cap, ch.hits, ch.mask, fb.count, fc, sb);
+    launch_big_count(W, H, op.binning, fb.gs, fb.conic, fb.erec, ch.chunks, chunk_cap, ch.hits, ch.mask, fb.count, fc,
+                     sb);
     const bool joined = sb == s || hipEventRecord(side.join, sb) == hipSuccess;
     if (!joined) (void)hipStreamSynchronize(sb);  // cannot order the streams by an event: wait here instead
     // ---- depth order of the visible Gaussians: 4 LSD passes over the depth
@@ -392,8 +394,7 @@ bool enqueue_back(int W, int H, const DevOptions &op, uint32_t P, FrameBuffers &
     static_assert(kGsumSlots >= 4 + 4, "four depth and up to four tile passes");
     launch_emit(W, H, fb.dv_a, P, &fc->visible, fb.offsets, fb.erec, fb.tk_a, kb, fb.tv_a, pair_cap,
                 npass > 0 ? fb.ranges : nullptr, ntiles, npass > 0 ? ss.slot(4) : nullptr, s);
-    launch_big_emit(W, fb.rect, fb.erec, ch.chunks, chunk_cap, ch.hits, ch.mask, fb.tk_a, kb, fb.tv_a, pair_cap, fc,
-                    s);
+    launch_big_emit(W, fb.erec, ch.chunks, chunk_cap, ch.hits, ch.mask, fb.tk_a, kb, fb.tv_a, pair_cap, fc, s);
     mk.mark(4, s);
     // ---- stage 3: stable LSD sort of the pairs by tile id ---------------------------
     uint32_t *ki = fb.tk_a, *vi = fb.tv_a, *ko = fb.tk_b, *vo = fb.tv_b;

@@ -19,7 +19,8 @@ struct FrameBuffers {
     size_t capP = 0, capN = 0, capTiles = 0, capPix = 0;
     // per Gaussian
     GaussState *gs = nullptr;
-    uint4 *rect = nullptr;
+    float4 *conic = nullptr;  // canonical binary32 conic (A, B, C, 0): large rectangles always, all with `full`
+    uint4 *rect = nullptr;    // written with `full` only (introspection)
     uint32_t *count = nullptr;
     uint8_t *count8 = nullptr;  // tile count of a small rectangle, kCount8Big for a chunked one (the scan's gather)
     uint4 *erec = nullptr;  // emission record: rectangle (16-bit) and hit mask
@@ -36,7 +37,8 @@ struct FrameBuffers {
     uint32_t *last = nullptr;
 
     size_t gauss_bytes() const {
-        return capP * (sizeof(GaussState) + sizeof(uint4) + sizeof(uint32_t) + sizeof(uint4) + 5 * sizeof(uint32_t) +
+        return capP * (sizeof(GaussState) + sizeof(float4) + sizeof(uint4) + sizeof(uint32_t) + sizeof(uint4) +
+                       5 * sizeof(uint32_t) +
                        sizeof(uint8_t)) +
                (capP + 1) * sizeof(uint32_t) + kCullBlocks * sizeof(uint32_t);
     }
@@ -121,10 +123,12 @@ struct SideStream {
 // counters_ready is NULL; otherwise on the side stream, followed there by
 // counters_ready, so that s goes straight on to the second half.
 // pp: NULL (raw parameters) or the scene's view-independent precompute.
+// full: also write what only a kept frame's introspection reads (see
+// launch_preprocess).
 void enqueue_front(const DevScene &sc, const DevPrepared *pp, const DevCamera &cam, const DevOptions &op, int W,
                    int H, FrameBuffers &fb, ChunkList &ch, SortScratch &ss, FrameCounters *fc,
                    FrameCounters *host_fc, hipStream_t s, const SideStream &side, const StageMarks &mk,
-                   hipEvent_t counters_ready = nullptr);
+                   hipEvent_t counters_ready = nullptr, bool full = false);
 // The part of enqueue_front after the preprocess (for a preprocess run
 // elsewhere, as in a multi-camera batch).  dense: the outputs are over a
 // candidate list of fc->ncand positions (a prepared scene); P32 bounds it.

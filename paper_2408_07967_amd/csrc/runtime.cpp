@@ -115,18 +115,20 @@ fgs_status validate(fgs_context *ctx, const fgs_scene *sc, const fgs_camera *cam
     return FGS_OK;
 }
 
-// Per-Gaussian records as fgs_frame_download documents them: the device
-// keeps the blend's conic where the blend loads it (GaussState), the host
-// field lists the canonical conic first.
-void gauss_to_host_order(void *dst, size_t bytes) {
-    static_assert(sizeof(GaussState) == 16 * sizeof(float), "16 floats per record");
-    // host column j takes device column from[j]
+// Per-Gaussian records as fgs_frame_download documents them (16 floats): the
+// device keeps the blend's state (GaussState, 12 floats) and the canonical
+// conic (4 floats) in two arrays; the host field lists the canonical conic
+// first.  Builds n host records from n device entries of each array.
+constexpr size_t kHostGaussFloats = 16;
+void gauss_to_host(const float *gs, const float *conic, size_t n, float *dst) {
+    static_assert(sizeof(GaussState) == 12 * sizeof(float), "12 floats of blend state");
+    // host column j takes column from[j] of (state | conic)
     static const int from[16] = {0, 1, 12, 13, 14, 5, 6, 7, 8, 9, 10, 11, 2, 3, 4, 15};
-    float *r = static_cast<float *>(dst);
-    for (size_t i = 0; i < bytes / sizeof(GaussState); ++i, r += 16) {
+    for (size_t i = 0; i < n; ++i, dst += kHostGaussFloats) {
         float t[16];
-        memcpy(t, r, sizeof t);
-        for (int j = 0; j < 16; ++j) r[j] = t[from[j]];
+        memcpy(t, gs + 12 * i, 12 * sizeof(float));
+        memcpy(t + 12, conic + 4 * i, 4 * sizeof(float));
+        for (int j = 0; j < 16; ++j) dst[j] = t[from[j]];
     }
 }
 
@@ -357,7 +359,7 @@ fgs_status render_impl(fgs_context *ctx, const fgs_scene *scene, const fgs_prepa
     for (int attempt = 0;; ++attempt) {
         const DevPrepared pdev = prep ? prep->pb.dev() : DevPrepared{};
         enqueue_front(dsc, prep ? &pdev : nullptr, dcam, dop, W, H, fb, ctx->ch, ctx->ss, ctx->fc_dev, ctx->fc_host,
-                      s, ctx->side, mk, ctx->front_done);
+                      s, ctx->side, mk, ctx->front_done, saved != nullptr);
         HIP_TRY(ctx, hipGetLastError());
         // The second half reads every count on the device and never writes
         // beyond the pair buffers, so it is enqueued at once with the buffers
@@ -540,6 +542,7 @@ bool carve_noalloc(unsigned char *base, size_t P, size_t ntiles, FrameBuffers &f
     fb.capTiles = ntiles;
     const size_t capP = std::max<size_t>(P, 1);
     fb.gs = c.take<GaussState>(capP);
+    fb.conic = c.take<float4>(capP);
     fb.rect = c.take<uint4>(capP);
     fb.count = c.take<uint32_t>(capP);
     fb.count8 = c.take<uint8_t>(capP);
@@ -760,6 +763,7 @@ fgs_status fgs_render_prepared_batch(fgs_context *ctx, const fgs_prepared *p, co
             o.W = W;
             o.H = H;
             o.gs = bc.fb.gs;
+            o.conic = bc.fb.conic;
             o.rect = bc.fb.rect;
             o.count = bc.fb.count;
             o.count8 = bc.fb.count8;
@@ -887,7 +891,7 @@ size_t fgs_frame_field_bytes(const fgs_frame *f, fgs_field field) {
     if (!f) return 0;
     const size_t tiles = (size_t)f->stats.tiles_x * f->stats.tiles_y;
     switch (field) {
-    case FGS_FIELD_GAUSS: return (size_t)f->P * sizeof(GaussState);
+    case FGS_FIELD_GAUSS: return (size_t)f->P * kHostGaussFloats * sizeof(float);
     case FGS_FIELD_RECT: return (size_t)f->P * sizeof(uint4);
     case FGS_FIELD_COUNT: return (size_t)f->P * sizeof(uint32_t);
     case FGS_FIELD_ORDER: return (size_t)f->visible * sizeof(uint32_t);
@@ -906,7 +910,7 @@ fgs_status fgs_frame_download(fgs_context *ctx, const fgs_frame *f, fgs_field fi
     const void *src = nullptr;
     const FrameBuffers &b = f->fb;
     switch (field) {
-    case FGS_FIELD_GAUSS: src = b.gs; break;
+    case FGS_FIELD_GAUSS: break;  // assembled from the state and conic arrays below
     case FGS_FIELD_RECT: src = b.rect; break;
     case FGS_FIELD_COUNT: src = b.count; break;
     case FGS_FIELD_ORDER: src = b.dv_a; break;
@@ -929,7 +933,30 @@ fgs_status fgs_frame_download(fgs_context *ctx, const fgs_frame *f, fgs_field fi
             for (uint32_t i = rg[t].x; i < rg[t].y && i < f->pairs; ++i) dst[i] = (uint32_t)t;
         return FGS_OK;
     }
-    if (f->dense && (field == FGS_FIELD_GAUSS || field == FGS_FIELD_RECT || field == FGS_FIELD_COUNT ||
+    if (field == FGS_FIELD_GAUSS) {
+        // state and canonical conic of every output slot (Gaussian, or list
+        // position of a prepared scene's frame), assembled into host records
+        const size_t n = f->dense ? (size_t)f->ncand : (size_t)f->P;
+        std::vector<float> gsh(n * 12), cnh(n * 4), rec(n * kHostGaussFloats);
+        if (n) {
+            HIP_TRY(ctx, hipMemcpy(gsh.data(), b.gs, n * sizeof(GaussState), hipMemcpyDeviceToHost));
+            HIP_TRY(ctx, hipMemcpy(cnh.data(), b.conic, n * sizeof(float4), hipMemcpyDeviceToHost));
+        }
+        gauss_to_host(gsh.data(), cnh.data(), n, rec.data());
+        if (!f->dense) {
+            memcpy(host_dst, rec.data(), bytes);
+            return FGS_OK;
+        }
+        std::vector<uint32_t> gm(n);
+        if (n) HIP_TRY(ctx, hipMemcpy(gm.data(), b.gmap, n * sizeof(uint32_t), hipMemcpyDeviceToHost));
+        const size_t esz = kHostGaussFloats * sizeof(float);
+        uint8_t *d = static_cast<uint8_t *>(host_dst);
+        memset(d, 0, bytes);
+        for (size_t c = 0; c < n; ++c)
+            if ((size_t)gm[c] * esz + esz <= bytes) memcpy(d + (size_t)gm[c] * esz, rec.data() + c * kHostGaussFloats, esz);
+        return FGS_OK;
+    }
+    if (f->dense && (field == FGS_FIELD_RECT || field == FGS_FIELD_COUNT ||
                      field == FGS_FIELD_ORDER || field == FGS_FIELD_VALUES)) {
         // a prepared scene's frame holds per-Gaussian data by candidate list
         // position: map positions to Gaussian indices
@@ -941,19 +968,16 @@ fgs_status fgs_frame_download(fgs_context *ctx, const fgs_frame *f, fgs_field fi
             for (size_t i = 0; i < bytes / sizeof(uint32_t); ++i) d[i] = d[i] < f->ncand ? gm[d[i]] : 0xffffffffu;
             return FGS_OK;
         }
-        const size_t esz = field == FGS_FIELD_GAUSS ? sizeof(GaussState)
-                                                    : (field == FGS_FIELD_RECT ? sizeof(uint4) : sizeof(uint32_t));
+        const size_t esz = field == FGS_FIELD_RECT ? sizeof(uint4) : sizeof(uint32_t);
         std::vector<uint8_t> tmp((size_t)f->ncand * esz);
         if (f->ncand) HIP_TRY(ctx, hipMemcpy(tmp.data(), src, tmp.size(), hipMemcpyDeviceToHost));
         uint8_t *d = static_cast<uint8_t *>(host_dst);
         memset(d, 0, bytes);
         for (size_t c = 0; c < f->ncand; ++c)
             if ((size_t)gm[c] * esz + esz <= bytes) memcpy(d + (size_t)gm[c] * esz, tmp.data() + c * esz, esz);
-        if (field == FGS_FIELD_GAUSS) gauss_to_host_order(host_dst, bytes);
         return FGS_OK;
     }
     HIP_TRY(ctx, hipMemcpy(host_dst, src, bytes, hipMemcpyDeviceToHost));
-    if (field == FGS_FIELD_GAUSS) gauss_to_host_order(host_dst, bytes);
     if (field == FGS_FIELD_RANGES) {
         // an empty tile may hold start > end on the device; report (0, 0)
         uint2 *r = static_cast<uint2 *>(host_dst);
@@ -1006,6 +1030,70 @@ fgs_status fgs_get_instrumentation(fgs_context *ctx, fgs_timings *out) {
     }
     *out = ctx->acc;
     return FGS_OK;
+}
+
+fgs_status fgs_measure_peaks(fgs_context *ctx, fgs_peaks *out) {
+    if (!ctx) return fail(nullptr, FGS_ERR_INVALID_ARGUMENT, "context is NULL");
+    if (!out) return fail(ctx, FGS_ERR_INVALID_ARGUMENT, "out is NULL");
+    *out = fgs_peaks{};
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipDeviceProp_t prop;
+    HIP_TRY(ctx, hipGetDeviceProperties(&prop, ctx->device));
+    out->compute_units = prop.multiProcessorCount;
+    out->clock_mhz = prop.clockRate / 1000;
+    const size_t copy_bytes = (size_t)1 << 30;
+    float *sink = nullptr;
+    void *a = nullptr, *b = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipStream_t s = ctx->side.side;
+    fgs_status st = FGS_OK;
+    auto cleanup = [&]() {
+        (void)hipDeviceSynchronize();
+        if (sink) (void)hipFree(sink);
+        if (a) (void)hipFree(a);
+        if (b) (void)hipFree(b);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    // best of `reps` timed launches (after one untimed) of `launch`, in ms
+    auto best_ms = [&](int reps, auto launch, float *ms) -> hipError_t {
+        hipError_t e;
+        launch();
+        *ms = 1e30f;
+        for (int r = 0; r < reps; ++r) {
+            if ((e = hipEventRecord(e0, s)) != hipSuccess) return e;
+            launch();
+            if ((e = hipEventRecord(e1, s)) != hipSuccess) return e;
+            if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
+            float t = 0.0f;
+            if ((e = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) return e;
+            *ms = t < *ms ? t : *ms;
+        }
+        return hipGetLastError();
+    };
+    hipError_t e = hipMalloc((void **)&sink, sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&a, copy_bytes);
+    if (e == hipSuccess) e = hipMalloc(&b, copy_bytes);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipMemsetAsync(a, 0, copy_bytes, s);
+    const int blocks = 32 * (prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256);
+    const int fma_iters = 4096, exp_iters = 1024;
+    float ms = 0.0f;
+    if (e == hipSuccess) e = best_ms(3, [&] { launch_peak_fma(blocks, fma_iters, sink, s); }, &ms);
+    if (e == hipSuccess) {
+        out->fma_lane_ops_per_s = (double)blocks * kBlock * fma_iters * kPeakChains / (ms * 1e-3);
+        out->valu_wave_instr_per_s = out->fma_lane_ops_per_s / 64.0;
+        e = best_ms(3, [&] { launch_peak_exp(blocks, exp_iters, sink, s); }, &ms);
+    }
+    if (e == hipSuccess) {
+        out->exp_lane_ops_per_s = (double)blocks * kBlock * exp_iters * kPeakChains / (ms * 1e-3);
+        e = best_ms(5, [&] { launch_peak_copy(a, b, copy_bytes, s); }, &ms);
+    }
+    if (e == hipSuccess) out->copy_bytes_per_s = 2.0 * (double)copy_bytes / (ms * 1e-3);
+    if (e != hipSuccess) st = hip_fail(ctx, e, "peak-rate measurement");
+    cleanup();
+    return st;
 }
 
 fgs_status fgs_render_backward(fgs_context *ctx, const fgs_frame *frame, const fgs_scene *scene,

@@ -205,6 +205,7 @@ void start_front_batch(fgs_server *srv, const std::vector<Slot *> &b) {
         o.W = s.req.W;
         o.H = s.req.H;
         o.gs = s.fb.gs;
+        o.conic = s.fb.conic;
         o.rect = s.fb.rect;
         o.count = s.fb.count;
         o.count8 = s.fb.count8;

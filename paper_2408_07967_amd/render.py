@@ -196,6 +196,13 @@ class Renderer:
         that render the same image bit for bit."""
         self.ctx.check(B.lib().fgs_set_blend_variant(self.ctx.handle, int(variant)))
 
+    def measure_peaks(self):
+        """Measured peak rates of the device (FMA and v_exp_f32 issue, copy
+        bandwidth): dict of the fgs_peaks fields."""
+        p = B.FgsPeaks()
+        self.ctx.check(B.lib().fgs_measure_peaks(self.ctx.handle, C.byref(p)))
+        return {k: getattr(p, k) for k, _ in B.FgsPeaks._fields_}
+
     def instrumentation(self):
         t = B.FgsTimings()
         self.ctx.check(B.lib().fgs_get_instrumentation(self.ctx.handle, C.byref(t)))

@@ -21,11 +21,14 @@ namespace fgs {
 
 void launch_fill_u32(uint32_t *, uint32_t, size_t, hipStream_t) { reached("fill_u32"); }
 hipError_t noalloc_scratch(int, unsigned char **) { reached("noalloc_scratch"); }
+void launch_peak_fma(int, int, float *, hipStream_t) { reached("peak_fma"); }
+void launch_peak_exp(int, int, float *, hipStream_t) { reached("peak_exp"); }
+void launch_peak_copy(const void *, void *, size_t, hipStream_t) { reached("peak_copy"); }
 unsigned preprocess_grid(int64_t) { reached("preprocess_grid"); }
 unsigned emit_grid(uint32_t) { reached("emit_grid"); }
 void launch_preprocess(const DevScene &, const DevPrepared *, const DevCamera &, const DevCam64 &, const DevOptions &, int, int,
-                       GaussState *, uint4 *, uint32_t *, uint8_t *, uint4 *, uint32_t *, uint32_t *, uint32_t *,
-                       uint32_t *, uint2 *, uint32_t, FrameCounters *, uint32_t *, hipStream_t) {
+                       GaussState *, float4 *, uint4 *, uint32_t *, uint8_t *, uint4 *, uint32_t *, uint32_t *,
+                       uint32_t *, uint32_t *, uint2 *, uint32_t, FrameCounters *, uint32_t *, bool, hipStream_t) {
     reached("preprocess");
 }
 void launch_cull(const DevScene &, const DevPrepared &, const DevCamera &, const DevOptions &, int, int, uint32_t *,
@@ -45,16 +48,16 @@ void launch_depth_ties(const uint32_t *, uint32_t *, const uint32_t *, uint32_t,
                        FrameCounters *, uint32_t *, hipStream_t) {
     reached("depth_ties");
 }
-void launch_big_count(int, int, int, const GaussState *, const uint4 *, const uint2 *, uint32_t, uint32_t *,
-                      uint32_t *, uint32_t *, const FrameCounters *, hipStream_t) {
+void launch_big_count(int, int, int, const GaussState *, const float4 *, const uint4 *, const uint2 *, uint32_t,
+                      uint32_t *, uint32_t *, uint32_t *, const FrameCounters *, hipStream_t) {
     reached("big_count");
 }
 void launch_emit(int, int, const uint32_t *, uint32_t, const uint32_t *, const uint32_t *, uint4 *, void *, int,
                  uint32_t *, uint32_t, uint2 *, uint32_t, uint32_t *, hipStream_t) {
     reached("emit");
 }
-void launch_big_emit(int, const uint4 *, const uint4 *, const uint2 *, uint32_t, const uint32_t *, const uint32_t *,
-                     void *, int, uint32_t *, uint32_t, const FrameCounters *, hipStream_t) {
+void launch_big_emit(int, const uint4 *, const uint2 *, uint32_t, const uint32_t *, const uint32_t *, void *, int,
+                     uint32_t *, uint32_t, const FrameCounters *, hipStream_t) {
     reached("big_emit");
 }
 void launch_radix_pass(const void *, const uint32_t *, void *, uint32_t *, uint32_t, const uint32_t *, int, int, bool,
