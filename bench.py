@@ -39,13 +39,19 @@ WORKLOADS = {
     "small": dict(kind="small", W=256, H=256, name="small-10k-gaussians-256x256"),
 }
 HBM_PEAK_GBS = 8000.0
-# VALU issue: 256 CUs, 4 SIMDs each issuing one wave64 instruction every 4
-# cycles, 2.4 GHz: 614.4 G wave instructions/s = 39.3 T lane operations/s
-# (non-packed FP32; an FMA is one operation)
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# slots of one (pixel, Gaussian) evaluation of the blend in the two-pixels-
-# per-lane form: 14 VALU operations and one quarter-rate v_exp_f32 (4 slots)
-BLEND_SLOTS_PER_EVAL = 18
+# FP32 vector issue of MI355X: the published 157.3 TFLOP/s counts packed FMAs
+# (two lanes' worth and two FLOP per instruction slot of a lane); one
+# non-packed FP32 instruction slot per lane is a quarter of it, 39.3 T
+# lane-slots/s (256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz).  An add, multiply or
+# FMA takes one slot; v_exp_f32 issues at half rate (two slots, measured by
+# fgs_measure_peaks).
+VALU_PEAK_TSLOTS = 157.3 / 4
+# FP32 slots the blend spends per (pixel, Gaussian) evaluation in its
+# two-pixels-per-lane form: 10.6 add / multiply / FMA instructions (the
+# kernel's instruction mix, SQ_INSTS_VALU_{ADD,MUL,FMA}_F32 per executed
+# step of 128 pixel evaluations, committed under profiles/) and one
+# v_exp_f32 at two slots
+BLEND_SLOTS_PER_EVAL = 12.6
 PROFILE_SOURCES = {
     "k_blend": ("k_blend.hip", "blend_common.hpp", "fgs_internal.hpp"),
     "k_preprocess": ("k_project.hip", "fgs_internal.hpp", "sh_basis.hpp"),
@@ -182,7 +188,7 @@ def tile_sort_bytes(N, ntiles):
     return b, passes
 
 
-def stage_rooflines(stage_ms, stats, P, P_z, W, H, steps_exec):
+def stage_rooflines(stage_ms, stats, P, P_z, W, H, evals, steps_exec, peaks=None):
     """Per-stage achieved bandwidth or VALU rate against the MI355X peaks.
     Algorithmic bytes: the method's (the hot-path scope table's per-unit
     figures) for the preprocess; the design's own for the sort and the
@@ -219,14 +225,23 @@ def stage_rooflines(stage_ms, stats, P, P_z, W, H, steps_exec):
         "written, empty ranges per tile")
     hbm("scan", 17 * V, stage_ms["scan"], "design: order (4 B) and count (1 B) gathered, 12 B per visible "
                                            "Gaussian written and read")
-    if steps_exec and stage_ms["blend"] > 0:
-        slots = steps_exec * 128 * BLEND_SLOTS_PER_EVAL
+    if evals and stage_ms["blend"] > 0:
+        slots = evals * BLEND_SLOTS_PER_EVAL
         tops = slots / (stage_ms["blend"] * 1e-3) / 1e12
         rows["blend"] = dict(bound="alu", slots=int(slots), ms=round(stage_ms["blend"], 4),
-                             achieved_tops=round(tops, 3), peak_tops=round(VALU_PEAK_TOPS, 2),
-                             frac=round(tops / VALU_PEAK_TOPS, 4),
-                             slots_are=f"(wavefront, entry) steps executed x 128 pixels x {BLEND_SLOTS_PER_EVAL} "
-                                       "VALU slots (14 operations + v_exp_f32 at quarter rate)")
+                             achieved_tops=round(tops, 3), peak_tops=round(VALU_PEAK_TSLOTS, 2),
+                             frac=round(tops / VALU_PEAK_TSLOTS, 4),
+                             slots_are=f"method evaluations (every pixel's examined list entries) x "
+                                       f"{BLEND_SLOTS_PER_EVAL} FP32 lane-slots (10.6 add/mul/fma + v_exp_f32 at 2)",
+                             executed_steps=steps_exec)
+        if peaks:
+            m = peaks["fma_lane_ops_per_s"] / 1e12
+            rows["blend"].update(measured_peak_tops=round(m, 2), frac_of_measured=round(tops / m, 4))
+    if peaks:
+        cb = peaks["copy_bytes_per_s"] / 1e9
+        for r in rows.values():
+            if r["bound"] == "hbm":
+                r["frac_of_measured_copy"] = round(r["achieved_gbs"] / cb, 4)
     return rows
 
 
@@ -246,10 +261,16 @@ def dominant_roofline(rows, stage_ms, workload):
         out = dict(bound="hbm", achieved=r["achieved_gbs"], peak=HBM_PEAK_GBS, unit="GB/s", frac=r["frac"],
                    traffic=traffic, kernel=kernel, algorithmic_bytes_per_launch=r["bytes"],
                    avg_launch_ms=r["ms"], bytes_are=r["bytes_are"])
+        if "frac_of_measured_copy" in r:
+            out["frac_of_measured_copy"] = r["frac_of_measured_copy"]
     else:
-        out = dict(bound="alu", achieved=r["achieved_tops"], peak=r["peak_tops"], unit="TVALUop/s",
+        out = dict(bound="alu", achieved=r["achieved_tops"], peak=r["peak_tops"], unit="T FP32 lane-slots/s",
                    frac=r["frac"], traffic=traffic, kernel=kernel, valu_slots_per_launch=r["slots"],
-                   avg_launch_ms=r["ms"], slots_are=r["slots_are"])
+                   avg_launch_ms=r["ms"], slots_are=r["slots_are"],
+                   peak_is="published 157.3 TFLOP/s FP32 vector / 4 (packed FMA counted as 2 lanes x 2 FLOP)")
+        for k2 in ("measured_peak_tops", "frac_of_measured"):
+            if k2 in r:
+                out[k2] = r[k2]
     if prof:
         out["counters"] = {k2: v for k2, v in prof.items() if k2 not in ("commands", "kernel_sha")}
     return out
@@ -571,6 +592,9 @@ def main():
     torch.cuda.set_device(0)
     gsc = GaussianScene.from_numpy(sc, "cuda:0")
     R = Renderer(0)
+    peaks = R.measure_peaks()
+    log(f"[bench] measured peaks: FP32 FMA {peaks['fma_lane_ops_per_s'] / 1e12:.2f} T lane-ops/s, v_exp_f32 "
+        f"{peaks['exp_lane_ops_per_s'] / 1e12:.2f} T, copy {peaks['copy_bytes_per_s'] / 1e12:.2f} TB/s")
     R.set_blend_variant(args.blend_variant)
     opts = scenes.DEFAULT_OPTIONS
     out = torch.empty((3, H, W), dtype=torch.float32, device="cuda:0")
@@ -646,7 +670,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    rows = stage_rooflines(stage_ms, stats, sc.P, P_z, W, H, steps_exec)
+    rows = stage_rooflines(stage_ms, stats, sc.P, P_z, W, H, evals, steps_exec, peaks)
     roof = dominant_roofline(rows, stage_ms, args.workload)
     log(f"[bench] rooflines {rows}")
 
@@ -695,7 +719,13 @@ def main():
                            pairs_per_s=round(stats["pairs"] * fps, 1), stage_ms=stage_ms,
                            single_frame_ms=frame_ms,
                            blend_evaluations=evals, blend_wave_steps=steps_exec),
-               roofline=roof, stage_roofline=rows, cpu_baseline=cpu, parity=parity, workloads=others,
+               roofline=roof, stage_roofline=rows,
+               measured_peaks=dict(fp32_fma_tlane_ops=round(peaks["fma_lane_ops_per_s"] / 1e12, 3),
+                                   v_exp_f32_tlane_ops=round(peaks["exp_lane_ops_per_s"] / 1e12, 3),
+                                   copy_gbs=round(peaks["copy_bytes_per_s"] / 1e9, 1),
+                                   how="fgs_measure_peaks: FMA chains, v_exp_f32 chains, 1 GiB device copy; "
+                                       "best of several runs"),
+               cpu_baseline=cpu, parity=parity, workloads=others,
                serving=serving, differentiation=differentiation, multi_camera=batch)
     if binning_modes is not None:
         res["binning_modes"] = binning_modes

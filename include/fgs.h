@@ -406,7 +406,12 @@ fgs_status fgs_frame_stats(const fgs_frame *frame, fgs_stats *stats);
  * (16 bytes per pair) fit in the free part of a device byte budget: FIFO, a
  * request that does not fit may be overtaken by at most max_bypass later
  * ones.  The second half (emission, tile sort, ranges, blend) then runs as
- * a hipGraph captured once per (slot, resolution) and replayed.  Requests
+ * a hipGraph captured once per (slot, resolution) and replayed.  A slot that
+ * still holds the pair region of an earlier request enqueues that graph right
+ * behind the first half, before the pair count is known (its kernels read
+ * the count on the device and stay within the region), so that the host's
+ * wait for the count is off the request's path; a frame with more pairs than
+ * the region is admitted and run again.  Requests
  * in different slots overlap on the device.  One worker thread owned by the
  * server issues all of its GPU work.  The server keeps the scene's
  * view-independent precompute (see fgs_prepare_scene).  Images are
@@ -455,6 +460,10 @@ typedef struct {
                                    scene's view-independent precompute             */
     int64_t batched_fronts;     /* first halves run as one batch (batch_fronts)     */
     int64_t batched_requests;   /* requests whose first half ran in such a batch    */
+    int64_t spec_launches;      /* second halves enqueued right behind the first on
+                                   a slot's cached pair region                     */
+    int64_t spec_misses;        /* of those, frames with more pairs than the region:
+                                   the request was admitted and run again          */
 } fgs_server_stats;
 
 /* Monotonic clock (ns) of the server's timestamps. */

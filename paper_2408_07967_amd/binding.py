@@ -87,7 +87,7 @@ class FgsServerStats(C.Structure):
                 ("graphs_captured", C.c_int64), ("graph_launches", C.c_int64), ("region_allocs", C.c_int64),
                 ("region_evictions", C.c_int64), ("bypasses", C.c_int64), ("peak_bytes_in_use", C.c_int64),
                 ("budget_bytes", C.c_int64), ("slot_bytes", C.c_int64), ("batched_fronts", C.c_int64),
-                ("batched_requests", C.c_int64)]
+                ("batched_requests", C.c_int64), ("spec_launches", C.c_int64), ("spec_misses", C.c_int64)]
 
 
 class FgsTraceRequest(C.Structure):

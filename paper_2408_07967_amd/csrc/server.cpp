@@ -83,6 +83,10 @@ struct Slot {
     bool has_region = false;
     size_t reg_off = 0, reg_bytes = 0;
     std::vector<GraphEntry> graphs;
+    // a second half enqueued right behind the first, on the slot's cached
+    // pair region, before the pair count is known; its region stays in use
+    // until evB has passed
+    bool spec = false;
     // current request
     Request req;
     int attempts = 0;
@@ -166,7 +170,7 @@ bool ensure_region(fgs_server *srv, Slot &s) {
     bool ok = srv->arena.alloc(need, &off);
     for (size_t i = 0; !ok && i < srv->slots.size(); ++i) {
         Slot &o = srv->slots[i];
-        if (&o == &s || !o.has_region || o.state == SlotState::BACK) continue;
+        if (&o == &s || !o.has_region || o.state == SlotState::BACK || o.spec) continue;
         drop_region(srv, o);
         ok = srv->arena.alloc(need, &off);
     }
@@ -180,12 +184,15 @@ bool ensure_region(fgs_server *srv, Slot &s) {
     return true;
 }
 
+void speculate_back(fgs_server *srv, Slot &s);
+
 void start_front(fgs_server *srv, Slot &s) {
     const DevCamera dcam = to_dev(s.req.cam);
     enqueue_front(srv->dsc, &srv->pdev, dcam, srv->dop, s.req.W, s.req.H, s.fb, s.ch, s.ss, s.fc_dev, s.fc_host,
                   s.stream, s.side, StageMarks{});
     (void)hipEventRecord(s.evA, s.stream);
     s.state = SlotState::FRONT;
+    speculate_back(srv, s);
 }
 
 // First halves of several requests that start together (each on its own
@@ -230,12 +237,15 @@ void start_front_batch(fgs_server *srv, const std::vector<Slot *> &b) {
                            s.side, StageMarks{});
         (void)hipEventRecord(s.evA, s.stream);
         s.state = SlotState::FRONT;
+        speculate_back(srv, s);
     }
     srv->wst.batched_fronts += 1;
     srv->wst.batched_requests += (int64_t)b.size();
 }
 
-hipError_t start_back(fgs_server *srv, Slot &s) {
+// Enqueue the second half (and the caller's image copy) on the slot's stream
+// and record evB behind it.
+hipError_t launch_back(fgs_server *srv, Slot &s) {
     const int W = s.req.W, H = s.req.H;
     const uint32_t P = (uint32_t)srv->scene.num_gaussians;
     if (srv->cfg.use_graphs) {
@@ -268,10 +278,35 @@ hipError_t start_back(fgs_server *srv, Slot &s) {
                                             hipMemcpyDeviceToDevice, s.stream);
         if (c != hipSuccess) return c;
     }
-    hipError_t e = hipEventRecord(s.evB, s.stream);
+    return hipEventRecord(s.evB, s.stream);
+}
+
+hipError_t start_back(fgs_server *srv, Slot &s) {
+    const hipError_t e = launch_back(srv, s);
     if (e != hipSuccess) return e;
     s.state = SlotState::BACK;
     return hipSuccess;
+}
+
+// Pairs a slot's region holds (the admission criterion of ensure_region).
+bool region_fits(const Slot &s) { return s.has_region && s.reg_bytes / 16 >= (size_t)s.N + 64; }
+
+// A slot that kept its pair region from an earlier request enqueues the
+// second half right behind the first (as fgs_render does): its kernels read
+// the pair count on the device and stay within the region, so no host round
+// trip sits between the halves.  If the frame turns out to have more pairs
+// than the region holds, the request waits for that half to finish and is
+// admitted as usual.
+void speculate_back(fgs_server *srv, Slot &s) {
+    s.spec = false;
+    if (!s.has_region) return;
+    if (launch_back(srv, s) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    s.spec = true;
+    s.admit_ns = now_ns();
+    srv->wst.spec_launches += 1;
 }
 
 fgs_server_result make_result(const Slot &s, int32_t status) {
@@ -387,6 +422,7 @@ void worker_main(fgs_server *srv) {
             progress = true;
             if (q != hipSuccess) {
                 set_error(srv, hipGetErrorString(q));
+                s.spec = false;
                 finish(srv, s, FGS_ERR_DEVICE);
                 continue;
             }
@@ -394,6 +430,8 @@ void worker_main(fgs_server *srv) {
                 // large-Gaussian chunk list too small: grow it (its graphs
                 // reference it) and run the first half again
                 s.attempts += 1;
+                if (s.spec) (void)hipEventSynchronize(s.evB);  // that half reads the chunk list
+                s.spec = false;
                 drop_graphs(s);
                 if (ensure_chunks(s.ch, (size_t)s.fc_host->nchunks + (size_t)s.fc_host->nchunks / 8) != hipSuccess) {
                     finish(srv, s, FGS_ERR_OUT_OF_MEMORY);
@@ -403,15 +441,26 @@ void worker_main(fgs_server *srv) {
                 continue;
             }
             if (s.fc_host->error & kErrChunkOverflow) {
+                if (s.spec) (void)hipEventSynchronize(s.evB);
+                s.spec = false;
                 finish(srv, s, FGS_ERR_INTERNAL);
                 continue;
             }
             s.V = s.fc_host->visible;
             s.N = s.fc_host->pairs;
+            if (s.spec && region_fits(s)) {
+                // the second half enqueued with the first holds every pair
+                s.spec = false;
+                s.state = SlotState::BACK;
+                continue;
+            }
             if (bytes_for_pairs(s.N) > srv->arena.size()) {
+                if (s.spec) (void)hipEventSynchronize(s.evB);  // the region is in use until then
+                s.spec = false;
                 finish(srv, s, FGS_ERR_CAPACITY);  // can never fit the budget
                 continue;
             }
+            if (s.spec) srv->wst.spec_misses += 1;
             s.state = SlotState::WAIT;
         }
         // 3. admission: FIFO over waiting requests, bounded bypass
@@ -421,6 +470,13 @@ void worker_main(fgs_server *srv) {
                 if (s.state == SlotState::WAIT) waiting.push_back(&s);
             std::sort(waiting.begin(), waiting.end(), [](Slot *a, Slot *b) { return a->req.seq < b->req.seq; });
             auto try_admit = [&](Slot *s) {
+                if (s->spec) {
+                    // its speculative second half ran out of pairs: the
+                    // region is free to grow once that half has finished
+                    const hipError_t q = hipEventQuery(s->evB);
+                    if (q == hipErrorNotReady) return false;
+                    s->spec = false;
+                }
                 if (!ensure_region(srv, *s)) return false;
                 s->admit_ns = now_ns();
                 const hipError_t e = start_back(srv, *s);
@@ -453,6 +509,8 @@ void worker_main(fgs_server *srv) {
             srv->st.peak_bytes_in_use = srv->wst.peak_bytes_in_use;
             srv->st.batched_fronts = srv->wst.batched_fronts;
             srv->st.batched_requests = srv->wst.batched_requests;
+            srv->st.spec_launches = srv->wst.spec_launches;
+            srv->st.spec_misses = srv->wst.spec_misses;
         } else if (in_flight) {
             std::this_thread::yield();  // completions are polled: stay on the core
         } else {

@@ -83,7 +83,9 @@ def test_served_images_equal_alone_under_a_tight_budget(setup, share_queue, batc
         assert torch.equal(img, alone[rid][0]), f"request {rid} ({W}x{H}) differs from the image rendered alone"
     assert st["completed"] == len(reqs)
     assert st["peak_bytes_in_use"] <= budget
-    assert st["graphs_captured"] >= 1 and st["graph_launches"] == len(reqs)
+    # a speculative second half that ran out of pairs is launched once more
+    assert st["graphs_captured"] >= 1 and st["graph_launches"] == len(reqs) + st["spec_misses"]
+    assert st["spec_launches"] >= 1
     if batch_fronts and share_queue == 0:
         assert st["batched_fronts"] >= 1 and st["batched_requests"] >= 2
     if not batch_fronts:
@@ -112,8 +114,8 @@ def test_graph_replays_on_one_slot_match_eager(setup):
         st = srv.stats()
     finally:
         srv.close()
-    assert st["graph_launches"] == 9
-    assert st["graphs_captured"] <= 9
+    assert st["graph_launches"] == 9 + st["spec_misses"]
+    assert st["graphs_captured"] <= 9 + st["spec_misses"]
 
 
 def test_direct_launch_mode_and_capacity_rejection(setup):
