@@ -106,9 +106,10 @@ typedef struct {
     int64_t visible;   /* Gaussians that survived preprocessing          */
     int64_t pairs;     /* Gaussian-tile key/value pairs emitted          */
     int32_t tiles_x, tiles_y;
-    int32_t sort_passes;
+    int32_t sort_passes; /* radix passes: 4 over the depth keys, then those
+                           over the super-tile ids of the entries            */
     int32_t big_chunks; /* 256-tile chunks of the rectangles of more than 64
-                           tiles, tested by workgroups across the GPU        */
+                           tiles, tested by wavefronts across the GPU        */
     int64_t candidates; /* Gaussians preprocessed: the cull's candidates of a
                            prepared scene, every Gaussian otherwise          */
 } fgs_stats;
@@ -186,7 +187,7 @@ fgs_status fgs_plan(fgs_context *ctx, const fgs_scene *scene, const fgs_camera *
 /* For callers that cannot allocate device memory (tight serving loops,
  * harnesses that forbid hipMalloc): fgs_render without a saved frame, whose
  * kernels take every scratch buffer (per-Gaussian state, depth order, count
- * scan, pairs and their sort ping-pong, tile ranges, large-rectangle chunk
+ * scan, super-tile entries and their sort ping-pong, pairs, tile ranges, large-rectangle chunk
  * list, frame counters) from one fixed device array of
  * FGS_NOALLOC_SCRATCH_BYTES per GPU, part of the library's code object: each
  * GPU the library runs on holds it until the process ends.  The call makes no
@@ -195,10 +196,11 @@ fgs_status fgs_plan(fgs_context *ctx, const fgs_scene *scene, const fgs_camera *
  * array's device address).  Arguments, outputs and the single wait for the
  * pair count are those of fgs_render; the image is bit-identical to it.
  * Limits: the per-Gaussian part (about 130 B per Gaussian), the tile ranges
- * (8 B per tile), the sort scratch and a chunk list of max(P / 8, 8192)
+ * (16 B per tile), the sort scratch and a chunk list of max(P / 8, 8192)
  * entries are carved first and must fit, else FGS_ERR_CAPACITY before any
- * device work; the rest holds the pairs (16 B each).  A frame with more pairs
- * than that, or with more large-rectangle chunks than the list holds, returns
+ * device work; the rest holds the pairs (16 B each, which also hold the
+ * super-tile entries: 28 B each).  A frame with more pairs or entries than
+ * that, or with more large-rectangle chunks than the list holds, returns
  * FGS_ERR_CAPACITY after its device work (the image is then incomplete).
  * Every call on one GPU, from any context, uses that GPU's one array, which
  * keeps the previous call's contents (each frame clears what must start at

@@ -74,12 +74,44 @@ struct alignas(16) GaussState {
 // Frame-scoped device counters, cleared at the start of a frame.
 struct FrameCounters {
     uint32_t visible;  // Gaussians that passed preprocessing
-    uint32_t pairs;    // total pairs (written by the count scan)
+    uint32_t pairs;    // total (Gaussian, tile) pairs: the preprocess adds the small rectangles' hits, the
+                       // large-rectangle tests theirs
     uint32_t error;    // error bits (kErrChunkOverflow)
     uint32_t nchunks;  // entries requested in the large-Gaussian chunk list
     uint32_t ncand;    // candidates of a prepared scene's cull (dense depth keys)
     uint32_t nlong;    // runs of more than kShortTieRun equal depths (prepared scene)
+    uint32_t entries;  // (Gaussian, super-tile) entries (written by the count scan)
 };
+
+// Super-tiles: blocks of kSuper x kSuper tiles (the last row and column may be
+// cut by the image).  Key emission writes one entry per (Gaussian, super-tile
+// its tile rectangle overlaps): the super-tile's id and the 64-bit mask of
+// the Gaussian's tiles in it (bit lx + kSuper ly, after the exact test; an
+// overlapped super-tile none of whose tiles is hit keeps a zero mask).  The
+// entries are sorted by super-tile, and each super-tile's depth-ordered
+// entries are expanded into its 64 tiles' lists (see launch_tile_lists).
+constexpr int kSuperShift = 3;
+constexpr int kSuper = 1 << kSuperShift;
+constexpr int kMaxSupers = 65536;  // super-tile ids travel as uint16
+// The four per-pair arrays of capacity capN are one block: the last holds
+// the sorted values, the first three (12 capN bytes) the entries of both
+// sort buffers (kEntryBytes each: mask, Gaussian index, super-tile id) and
+// the tile-list scratch (list_scratch_words).
+constexpr size_t kEntryBytes = 2 * (sizeof(uint64_t) + sizeof(uint32_t) + sizeof(uint16_t));
+// The tile lists are built from chunks of kListChunk consecutive entries of
+// one super-tile (a super-tile's last chunk may be shorter), one wavefront
+// each; at most list_chunks_max of them.
+constexpr uint32_t kListChunk = 256;
+__host__ __device__ inline size_t list_chunks_max(size_t ecap, size_t nsuper) {
+    return (ecap + kListChunk - 1) / kListChunk + nsuper;
+}
+// Tile-list scratch (words): chunk base of each super-tile (nsuper + 1) and
+// pair count of each row of super-tiles (at most nsuper), the super-tile of
+// each chunk, 64 per-tile counts of each chunk; each part padded to 64 words.
+__host__ __device__ inline size_t list_scratch_words(size_t ecap, size_t nsuper) {
+    const size_t g = list_chunks_max(ecap, nsuper);
+    return (2 * nsuper + 1 + 63) / 64 * 64 + (g + 63) / 64 * 64 + g * 64;
+}
 
 // ---- launchers (implemented in the .hip files) ----------------------------
 
@@ -97,11 +129,13 @@ void launch_peak_fma(int blocks, int iters, float *sink, hipStream_t s);
 void launch_peak_exp(int blocks, int iters, float *sink, hipStream_t s);
 void launch_peak_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 
-// Rectangles of more than kBigTiles tiles are tested and emitted in chunks of
-// kChunkTiles tiles by workgroups spread over the whole GPU.
+// Rectangles of more than kBigTiles tiles are tested in chunks of
+// kChunkTiles tiles (row-major over the rectangle) by wavefronts spread over
+// the whole GPU.
 constexpr int kBigTiles = 64;
 constexpr int kChunkTiles = kBlock;
 constexpr uint32_t kNoChunk = 0xffffffffu;
+constexpr size_t kChunkCapAlign = 64;  // chunk-list capacities are multiples of this
 constexpr int kPersistentBlocks = 2048;
 constexpr int kBigList = 512;                    // pending chunk reservations per workgroup
 // FrameCounters::error bits
@@ -130,10 +164,11 @@ unsigned emit_grid(uint32_t visible);
 // conic of every valid Gaussian are written too, and a prepared scene's
 // culled candidates get zero state, rectangle and conic.
 // The emission record is (tx0 | tx1 << 16, ty0 | ty1 << 16, hit mask low,
-// hit mask high).  Large rectangles append chunk entries (g, first chunk) to
-// `chunks` (capacity chunk_cap; on overflow the error bit kErrChunkOverflow
-// is set and the host renders the frame again with a larger list) and get
-// count 0 and record (rectangle, 0, first chunk).
+// hit mask high).  Large rectangles append one chunk entry (g, first chunk)
+// per kChunkTiles tiles to `chunks` (capacity chunk_cap; on overflow the
+// error bit kErrChunkOverflow is set and the host renders the frame again
+// with a larger list) and get count 0 and record (rectangle, 0, first
+// chunk).  The small rectangles' hits are added to fc->pairs.
 // pp: NULL (raw parameters) or the scene's precompute.  With a precompute a
 // cull pass of kCullBlocks workgroups (which also clears *fc) first lists, for each workgroup's
 // contiguous range, the Gaussians that may be visible (in index order, at the
@@ -144,9 +179,10 @@ unsigned emit_grid(uint32_t visible);
 // Gaussian of position i to gmap[i].  Without a precompute the outputs are
 // indexed by Gaussian and gmap is unused.
 constexpr int kCullBlocks = 2048;
-// count8: the count again in one byte (kCount8Big for a chunked rectangle,
-// whose count k_big_count adds to count later): the scan gathers this
-// 1-byte array, which the L2 caches hold whole.
+// count8: the number of super-tiles the rectangle overlaps, i.e. its
+// entries (kCount8Big for a chunked rectangle, whose entries the scan takes
+// from its record): the scan gathers this 1-byte array, which the L2 caches
+// hold whole.
 constexpr uint8_t kCount8Big = 255;
 // gsum_clear: kGsumWords counters cleared (the first depth pass's group sums).
 // With a precompute, launch_cull runs first (the preprocess reads its lists).
@@ -220,28 +256,52 @@ constexpr int kShortTieRun = 32;
 void launch_depth_ties(const uint32_t *keys, uint32_t *vals, const uint32_t *gmap, uint32_t n_host,
                        const uint32_t *n_dev, uint32_t *long_list, FrameCounters *fc, uint32_t *tmp_v, hipStream_t s);
 
-// Exact tile counts of the chunked Gaussians: per-chunk hit masks and counts,
-// atomic per-Gaussian sums.
+// Exact tile tests of the chunked Gaussians: chunk c of a Gaussian holds
+// tiles [c kChunkTiles, (c + 1) kChunkTiles) of its rectangle in row-major
+// order.  Writes each chunk's hit mask (kChunkTiles / 32 words, bit i = tile
+// c kChunkTiles + i), adds the hits to count[g] and to fc->pairs.
 void launch_big_count(int W, int H, int binning, const GaussState *gs, const float4 *conic, const uint4 *erec,
-                      const uint2 *chunks,
-                      uint32_t chunk_cap, uint32_t *chunk_hits, uint32_t *chunk_mask, uint32_t *count,
-                      const FrameCounters *fc, hipStream_t s);
+                      const uint2 *chunks, uint32_t chunk_cap, uint32_t *chunk_mask, uint32_t *count,
+                      FrameCounters *fc, hipStream_t s);
 
-// Emit (tile, gaussian) pairs for Gaussians in depth order.  Chunked
-// Gaussians only record their output base in erec[g].z.
-// visible: the count, or a bound on it when visible_dev (device) holds it.
-// tile_keys: uint32 or, with key_bytes == 2, uint16 tile ids
-// ranges: if non-null, ranges[t] = (0xffffffff, 0) for t < ntiles first
-// (the empty ranges that the last tile-sort pass narrows); gsum_clear, if
-// non-null: kGsumWords counters cleared (the first tile pass's group sums)
-void launch_emit(int W, int H, const uint32_t *order, uint32_t visible, const uint32_t *visible_dev,
-                 const uint32_t *offsets, uint4 *erec, void *tile_keys, int key_bytes, uint32_t *values, uint32_t cap,
-                 uint2 *ranges, uint32_t ntiles, uint32_t *gsum_clear, hipStream_t s);
+// Number of super-tiles a tile rectangle [tx0, tx1] x [ty0, ty1] overlaps:
+// the rectangle's entries.
+__host__ __device__ inline uint32_t super_span(int tx0, int tx1, int ty0, int ty1) {
+    return (uint32_t)(((tx1 >> kSuperShift) - (tx0 >> kSuperShift) + 1) *
+                      ((ty1 >> kSuperShift) - (ty0 >> kSuperShift) + 1));
+}
 
-// Emit the pairs of the chunked Gaussians (after launch_emit).
-void launch_big_emit(int W, const uint4 *erec, const uint2 *chunks, uint32_t chunk_cap,
-                     const uint32_t *chunk_hits, const uint32_t *chunk_mask, void *tile_keys, int key_bytes,
-                     uint32_t *values, uint32_t cap, const FrameCounters *fc, hipStream_t s);
+// Key emission at super-tile granularity: for the visible Gaussians in depth
+// order (order, `visible` or the bound-checked *visible_dev), the entries of
+// Gaussian order[r] go to [offsets[r], offsets[r] + its count) in row-major
+// order of the overlapped super-tiles: key = super-tile id (sy * stx + sx),
+// gidx = the Gaussian's output slot, mask = its hit tiles in the super-tile.
+// Small rectangles take the hit mask of their emission record.  A chunked
+// Gaussian leaves (output slot, offset) at big[first chunk], and a second
+// kernel gathers its super-tiles' bits from the chunk masks of
+// launch_big_count (chunks, big: capacity chunk_cap; ng bounds the output
+// slots).  Entries at or beyond ecap are dropped (the host sees the count
+// and renders again).  Also sets the super-tile ranges empty, (0xffffffff,
+// 0) for s < nsuper, and clears the first sort pass's group sums
+// (gsum_clear, kGsumWords words).
+void launch_super_emit(int W, int H, const uint32_t *order, uint32_t visible, const uint32_t *visible_dev,
+                       const uint32_t *offsets, const uint4 *erec, uint32_t ng, const uint2 *chunks, uint2 *big,
+                       const uint32_t *chunk_mask, uint32_t chunk_cap, const FrameCounters *fc, uint16_t *skey,
+                       uint32_t *gidx, uint64_t *smask, uint32_t ecap, uint2 *sranges, uint32_t nsuper,
+                       uint32_t *gsum_clear, hipStream_t s);
+
+// Per-tile lists from the entries sorted by super-tile (stable, so each
+// super-tile's entries are in depth order): sranges[s] = [start, end) of
+// super-tile s in the sorted arrays (start > end: none; at most ecap).  Every
+// pair (entry, set mask bit) is written to values at its tile's start plus
+// the number of earlier entries of the super-tile that hit the same tile,
+// which is the order of the method's stable sort by (tile, depth).  ranges[t]
+// = [start, end) of tile t for every tile of the W x H image (an empty tile
+// gets start == end), clamped to ncap; writes beyond ncap are dropped.
+// scratch: list_scratch_words(ecap, super-tiles) words.
+void launch_tile_lists(int W, int H, const uint2 *sranges, const uint32_t *gidx, const uint64_t *smask,
+                       uint32_t ecap, uint32_t *scratch, uint2 *ranges, uint32_t *values, uint32_t ncap,
+                       hipStream_t s);
 
 // One stable LSD radix pass of (key, value) pairs by the digit
 // (key >> shift) & ((1 << bits) - 1), bits <= 8.
@@ -259,18 +319,23 @@ void launch_big_emit(int W, const uint4 *erec, const uint2 *chunks, uint32_t chu
 //           by atomic min / max on entries that launch_emit set empty; a key
 //           with no element keeps start > end
 //   key_bytes 4 (uint32 keys) or 2 (uint16 keys: unfiltered passes with
-//           explicit values only)
+//           explicit values, or with a payload)
+//   mask_in if non-null (16-bit keys only): the payload (vals_in[i],
+//           mask_in[i]) travels with key i to (vals_out, mask_out); it is
+//           read at its destination's store, from the workgroup's tile
 void launch_radix_pass(const void *keys_in, const uint32_t *vals_in, void *keys_out, uint32_t *vals_out,
                        uint32_t n_host, const uint32_t *n_dev, int shift, int bits, bool filter, bool write_keys,
                        uint32_t *hist, uint32_t *gsum, uint32_t *gsum_next, hipStream_t s,
-                       uint2 *run_ends = nullptr, uint32_t nruns = 0, int key_bytes = 4);
+                       uint2 *run_ends = nullptr, uint32_t nruns = 0, int key_bytes = 4,
+                       const uint64_t *mask_in = nullptr, uint64_t *mask_out = nullptr);
 
 // offsets[r] = sum of count[order[r']] for r' < r over the n visible
-// Gaussians (n_dev, bounded by n_host); offsets[n] and *pairs get the total.
-// The count is read from count8, and from count where count8 holds
-// kCount8Big.  cs: scratch [n_host]; sums: scratch [kSortBlocks].
-void launch_count_scan(const uint32_t *order, const uint8_t *count8, const uint32_t *count, uint32_t n_host,
-                       const uint32_t *n_dev, uint32_t *cs, uint32_t *sums, uint32_t *offsets, uint32_t *pairs,
+// Gaussians (n_dev, bounded by n_host); offsets[n] and *total get the total.
+// The count (super-tile entries) is read from count8, and computed from the
+// emission record's rectangle where count8 holds kCount8Big.  cs: scratch
+// [n_host]; sums: scratch [kSortBlocks].
+void launch_count_scan(const uint32_t *order, const uint8_t *count8, const uint4 *erec, uint32_t n_host,
+                       const uint32_t *n_dev, uint32_t *cs, uint32_t *sums, uint32_t *offsets, uint32_t *total,
                        hipStream_t s);
 
 // A one-tile image: ranges[0] = [0, min(*n_dev, n)).

@@ -15,8 +15,6 @@ namespace fgs {
 namespace {
 
 constexpr int kWave = 64;
-constexpr int kSmallCount = 4;   // rectangles of up to this many tiles: one lane
-constexpr int kSmallEmit = 4;    // Gaussians with up to this many pairs: one lane
 
 // ---- canonical binary64 exp / ln (Cody-Waite reduction + Taylor; atanh series)
 
@@ -602,7 +600,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const int wv = threadIdx.x / kWave;  // this lane's wavefront
     uint32_t w_nbig = 0, w_nch = 0;      // wave-uniform: pending entries and their chunks
     uint32_t w_vis = 0;                  // wave-uniform: visible Gaussians so far
+    uint32_t l_pairs = 0;                // this lane's small-rectangle hits so far
     __shared__ uint32_t s_vis[kMulti ? kBlock / kWave : 1][kMulti ? kMaxCams : 1];  // per camera (kMulti)
+    __shared__ uint32_t s_pairs[kMulti ? kBlock / kWave : 1][kMulti ? kMaxCams : 1];
     // kMulti: the pending list holds entries of every camera, each tagged
     // with its camera; chunks are counted per camera, and a flush reserves
     // each camera's share of its own chunk list
@@ -615,6 +615,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         if ((threadIdx.x & (kWave - 1)) == 0)
             for (int c = 0; c < kMaxCams; ++c) {
                 s_vis[wv][c] = 0;
+                s_pairs[wv][c] = 0;
                 s_nch[wv][c] = 0;
             }
         if (threadIdx.x == 0)
@@ -953,7 +954,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     uint32_t cnt = 0;
     uint64_t hm = 0;
     // rectangles of more than kBigTiles tiles go to the chunk list, where
-    // workgroups across the GPU test them kChunkTiles tiles at a time
+    // wavefronts across the GPU test them kChunkTiles tiles at a time
     const bool chunked = valid && nt > kBigTiles;
     {
         const uint64_t bm = __ballot(chunked);
@@ -1026,7 +1027,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             gmap_c[ii] = pp.orig[g];
         }
         dkey_c[oi] = key;
-        count8_c[oi] = chunked ? kCount8Big : (uint8_t)(valid ? cnt : 0u);  // cnt <= kBigTiles < kCount8Big
+        // entries: the overlapped super-tiles (at most 10 for a rectangle of
+        // at most kBigTiles tiles)
+        count8_c[oi] = chunked ? kCount8Big : (uint8_t)(valid ? super_span(tx0, tx1, ty0, ty1) : 0u);
         // the 4-byte count: a chunked rectangle's starts at 0 (k_big_count
         // adds its hits); the others are read from count8
         if (full || chunked) count_c[oi] = valid ? cnt : 0u;
@@ -1054,9 +1057,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     }
     if constexpr (kMulti) {
         const uint32_t nv = (uint32_t)__popcll(__ballot(valid));
-        if (lane == 0) s_vis[wv][ci] += nv;
+        uint32_t np = small ? cnt : 0u;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) np += (uint32_t)__shfl_xor((int)np, d, kWave);
+        if (lane == 0) {
+            s_vis[wv][ci] += nv;
+            s_pairs[wv][ci] += np;
+        }
         if (w_nbig > (uint32_t)(kWaveBig - kWave)) flush_big_multi(lane);  // room for the next camera
     } else {
+        l_pairs += small ? cnt : 0u;
         w_vis += (uint32_t)__popcll(__ballot(valid));
         if (w_nbig > (uint32_t)(kWaveBig - kWave))
             flush_big(lane, fc, chunks, chunk_cap, erec);  // room for the next batch
@@ -1066,32 +1076,59 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     if constexpr (kMulti) {
         if (w_nbig) flush_big_multi(lane);
         if (lane == 0)
-            for (int c = 0; c < mo.n; ++c)
+            for (int c = 0; c < mo.n; ++c) {
                 if (s_vis[wv][c]) atomicAdd(&mo.c[c].fc->visible, s_vis[wv][c]);
+                if (s_pairs[wv][c]) atomicAdd(&mo.c[c].fc->pairs, s_pairs[wv][c]);
+            }
     } else {
         if (w_nbig) flush_big(lane, fc, chunks, chunk_cap, erec);
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) l_pairs += (uint32_t)__shfl_xor((int)l_pairs, d, kWave);
         if (lane == 0 && w_vis) atomicAdd(&fc->visible, w_vis);
+        if (lane == 0 && l_pairs) atomicAdd(&fc->pairs, l_pairs);
     }
 }
 
-// Key emission: one lane per Gaussian in (depth, index) order writes its
-// (tile, index) pairs at its scanned offset (Alg. 2 with the offsets of a
-// prefix scan; the tile test is reused from the preprocess through the hit
-// mask).  Chunked Gaussians only record their output base here.
-template <class KeyT>
-__global__ __launch_bounds__(kBlock) void k_emit(int W, int H, const uint32_t *__restrict__ order,
-                                                 uint32_t visible, const uint32_t *__restrict__ visible_dev,
-                                                 const uint32_t *__restrict__ offsets, uint4 *__restrict__ erec,
-                                                 KeyT *__restrict__ tile_keys, uint32_t *__restrict__ values,
-                                                 uint32_t cap, uint2 *__restrict__ ranges, uint32_t ntiles,
-                                                 uint32_t *__restrict__ gsum_clear) {
+// Hit mask of a small rectangle (bit rx + ntx ry of its emission record)
+// restricted to super-tile (sx, sy), in the super-tile's own layout (bit
+// lx + kSuper ly): the rectangle's rows in the super-tile, each cut to the
+// super-tile's columns and moved to its place.
+__device__ __forceinline__ uint64_t super_mask(uint64_t hm, int tx0, int ty0, int ntx, int nty, int sx, int sy) {
+    const int xs = sx * kSuper, ys = sy * kSuper;
+    const int a = xs - tx0 > 0 ? xs - tx0 : 0, b = xs + kSuper - tx0 < ntx ? xs + kSuper - tx0 : ntx;
+    const int c = ys - ty0 > 0 ? ys - ty0 : 0, d = ys + kSuper - ty0 < nty ? ys + kSuper - ty0 : nty;
+    const uint64_t wm = (1ull << (b - a)) - 1ull;  // b - a <= kSuper
+    const int lx0 = tx0 + a - xs;
+    uint64_t m = 0;
+    for (int ry = c; ry < d; ++ry)
+        m |= ((hm >> (ry * ntx + a)) & wm) << ((ty0 + ry - ys) * kSuper + lx0);
+    return m;
+}
+
+// Key emission at super-tile granularity (Alg. 2 with the offsets of a
+// prefix scan, the pair (tile, Gaussian) replaced by (super-tile, Gaussian,
+// hit mask); the tile test is reused from the preprocess through the hit
+// mask).  The visible Gaussians are taken 64 at a time in (depth, index)
+// order; the wavefront flattens the small rectangles' entries so that every
+// lane builds one entry per step, written at its Gaussian's scanned offset
+// plus its index among the Gaussian's entries (row-major over the
+// overlapped super-tiles).  A chunked Gaussian only leaves (its output slot,
+// its offset) at its first chunk's slot of `big` for k_big_entries.
+__global__ __launch_bounds__(kBlock) void k_super_emit(int W, const uint32_t *__restrict__ order, uint32_t visible,
+                                                       const uint32_t *__restrict__ visible_dev,
+                                                       const uint32_t *__restrict__ offsets,
+                                                       const uint4 *__restrict__ erec, uint2 *__restrict__ big,
+                                                       uint32_t chunk_cap, uint16_t *__restrict__ skey,
+                                                       uint32_t *__restrict__ gidx, uint64_t *__restrict__ smask,
+                                                       uint32_t ecap, uint2 *__restrict__ sranges, uint32_t nsuper,
+                                                       uint32_t *__restrict__ gsum_clear) {
     __shared__ uint32_t s_excl[kBlock / kWave][kWave];
-    // every tile's range starts empty, (0xffffffff, 0), for the last sort
-    // pass to narrow (ranges NULL: no pass records them)
-    if (ranges)
-        for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < ntiles; t += gridDim.x * kBlock)
-            ranges[t] = make_uint2(0xffffffffu, 0u);
-    // and the first tile pass's group sums start at zero
+    // every super-tile's range starts empty, (0xffffffff, 0), for the last
+    // sort pass to narrow (sranges NULL: no pass records them)
+    if (sranges)
+        for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < nsuper; t += gridDim.x * kBlock)
+            sranges[t] = make_uint2(0xffffffffu, 0u);
+    // and the first sort pass's group sums start at zero
     if (gsum_clear)
         for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < (uint32_t)kGsumWords; i += gridDim.x * kBlock)
             gsum_clear[i] = 0;
@@ -1099,209 +1136,226 @@ __global__ __launch_bounds__(kBlock) void k_emit(int W, int H, const uint32_t *_
     // bound (graph-captured frames); it never exceeds the bound
     if (visible_dev) visible = min(visible, *visible_dev);
     const int tiles_x = (W + kTile - 1) / kTile;
+    const uint32_t stx = (uint32_t)((tiles_x + kSuper - 1) >> kSuperShift);
     const int lane = threadIdx.x & (kWave - 1);
-    for (uint32_t r0 = blockIdx.x * kBlock; r0 < visible; r0 += gridDim.x * kBlock) {
-    const uint32_t r = r0 + threadIdx.x;
-    const bool act = r < visible;
-    uint32_t g = 0, base = 0;
-    uint4 rc = make_uint4(0, 0, 0, 0);
-    uint64_t m = 0;
-    if (act) {
-        g = order[r];
-        base = offsets[r];
-        const uint4 er = erec[g];
-        rc = make_uint4(er.x & 0xffffu, er.x >> 16, er.y & 0xffffu, er.y >> 16);
-        m = (uint64_t)er.z | ((uint64_t)er.w << 32);
-    }
-    const int ntx = (int)rc.y - (int)rc.x + 1;
-    const int nt = act ? ntx * ((int)rc.w - (int)rc.z + 1) : 0;
-    // chunked Gaussians only publish their output base; their pairs come later
-    const bool chunked = act && nt > kBigTiles;
-    if (chunked) erec[g].z = base;
-
-
-    // flattened (Gaussian, rectangle tile) items: every lane handles one tile
-    // of some Gaussian per step and writes it if the hit mask of the
-    // preprocess has its bit, at the Gaussian's offset plus the hits before it
-    const uint32_t items = (act && !chunked && m != 0) ? (uint32_t)nt : 0u;
-    const uint32_t incl = wave_incl_scan(items, lane);
-    const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
     uint32_t *sx = s_excl[threadIdx.x / kWave];
-    sx[lane] = incl - items;
-    for (uint32_t b0 = 0; b0 < total; b0 += kWave) {
-        const uint32_t item = b0 + (uint32_t)lane;
-        const int L = owner_lane(sx, item < total ? item : total - 1u);
-        const uint32_t k = item - sx[L];
-        const uint64_t mL = (uint64_t)(uint32_t)__shfl((int)(uint32_t)m, L, kWave) |
-                            ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(m >> 32), L, kWave) << 32);
-        const uint32_t gL = (uint32_t)__shfl((int)g, L, kWave), baseL = (uint32_t)__shfl((int)base, L, kWave);
-        const int tx0L = __shfl((int)rc.x, L, kWave), ty0L = __shfl((int)rc.z, L, kWave),
-                  ntxL = __shfl(ntx, L, kWave);
-        if (item < total && ((mL >> k) & 1ull)) {
-            const int ry = small_div(k, ntxL), rx = (int)k - ry * ntxL;
-            const uint32_t tile = (uint32_t)((ty0L + ry) * tiles_x + (tx0L + rx));
-            const uint32_t at = baseL + (uint32_t)__popcll(mL & ((1ull << k) - 1ull));
-            if (at < cap) {  // never leave the pair buffers
-                tile_keys[at] = (KeyT)tile;
-                values[at] = gL;
+    for (uint32_t r0 = blockIdx.x * kBlock; r0 < visible; r0 += gridDim.x * kBlock) {
+        const uint32_t r = r0 + threadIdx.x;
+        const bool act = r < visible;
+        uint32_t g = 0, base = 0;
+        uint4 er = make_uint4(0u, 0u, 0u, 0u);
+        if (act) {
+            g = order[r];
+            base = offsets[r];
+            er = erec[g];
+        }
+        const uint4 rc = unpack_rect(er);
+        const int tx0 = (int)rc.x, ty0 = (int)rc.z;
+        const int ntx = (int)rc.y - tx0 + 1, nty = (int)rc.w - ty0 + 1;
+        const bool chunked = act && ntx * nty > kBigTiles;
+        if (chunked && er.w < chunk_cap) big[er.w] = make_uint2(g, base);
+        // flattened (Gaussian, super-tile) items of the small rectangles
+        const uint32_t items = act && !chunked ? super_span(tx0, (int)rc.y, ty0, (int)rc.w) : 0u;
+        const uint32_t incl = wave_incl_scan(items, lane);
+        const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+        sx[lane] = incl - items;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint32_t prect = (uint32_t)tx0 | ((uint32_t)ty0 << 16), psize = (uint32_t)ntx | ((uint32_t)nty << 8);
+        for (uint32_t i0 = 0; i0 < total; i0 += kWave) {
+            const uint32_t item = i0 + (uint32_t)lane;
+            const int L = owner_lane(sx, item < total ? item : total - 1u);
+            const uint32_t k = item < total ? item - sx[L] : 0u;  // (a spare lane redoes entry 0)
+            const uint32_t gL = (uint32_t)__shfl((int)g, L, kWave), bL = (uint32_t)__shfl((int)base, L, kWave);
+            const uint32_t pr = (uint32_t)__shfl((int)prect, L, kWave), ps = (uint32_t)__shfl((int)psize, L, kWave);
+            const uint32_t hlo = (uint32_t)__shfl((int)er.z, L, kWave), hhi = (uint32_t)__shfl((int)er.w, L, kWave);
+            const int ltx0 = (int)(pr & 0xffffu), lty0 = (int)(pr >> 16);
+            const int lntx = (int)(ps & 0xffu), lnty = (int)(ps >> 8);
+            const int sx0 = ltx0 >> kSuperShift, sy0 = lty0 >> kSuperShift;
+            const int nsx = ((ltx0 + lntx - 1) >> kSuperShift) - sx0 + 1;  // at most 9 (k < 16)
+            const int ey = small_div(k, nsx), ex = (int)k - ey * nsx;
+            const uint64_t m = super_mask((uint64_t)hlo | ((uint64_t)hhi << 32), ltx0, lty0, lntx, lnty, sx0 + ex,
+                                          sy0 + ey);
+            const uint32_t at = bL + k;
+            if (item < total && at < ecap) {  // never leave the entry buffers
+                skey[at] = (uint16_t)((uint32_t)(sy0 + ey) * stx + (uint32_t)(sx0 + ex));
+                gidx[at] = gL;
+                smask[at] = m;
             }
         }
-    }
-    }  // batch loop
-}
-
-
-// Exact tile tests of the chunked Gaussians: one wavefront per chunk of
-// kChunkTiles rectangle tiles (4 per lane, independent), so that every
-// workgroup keeps four chunks in flight without barriers; the next chunk's
-// descriptor is loaded before the current chunk is tested.
-__global__ __launch_bounds__(kBlock) void k_big_count(int W, int H, int binning, const GaussState *__restrict__ gs,
-                                                      const float4 *__restrict__ conic,
-                                                      const uint4 *__restrict__ erec,
-                                                      const uint2 *__restrict__ chunks, uint32_t chunk_cap,
-                                                      uint32_t *__restrict__ chunk_hits,
-                                                      uint32_t *__restrict__ chunk_mask, uint32_t *count,
-                                                      const FrameCounters *fc) {
-    constexpr int kPer = kChunkTiles / kWave;
-    const int lane = threadIdx.x & (kWave - 1);
-    if (fc->error & kErrChunkOverflow) return;  // the frame is rendered again with a larger list
-    const uint32_t n = fc->nchunks < chunk_cap ? fc->nchunks : chunk_cap;
-    const uint32_t nwaves = gridDim.x * (kBlock / kWave);
-    uint32_t ch = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-    uint2 e = ch < n ? chunks[ch] : make_uint2(kNoChunk, 0u);
-    for (; ch < n; ch += nwaves) {
-        const uint32_t nxt = ch + nwaves;
-        const uint2 e_next = nxt < n ? chunks[nxt] : make_uint2(kNoChunk, 0u);
-        if (e.x == kNoChunk) {
-            if (lane == 0) chunk_hits[ch] = 0;
-            e = e_next;
-            continue;
-        }
-        const uint32_t g = e.x, c = ch - e.y;
-        const uint4 rc = unpack_rect(erec[g]);
-        const int ntx = (int)rc.y - (int)rc.x + 1;
-        const int nt = ntx * ((int)rc.w - (int)rc.z + 1);
-        GaussState s{};
-        float4 cn = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (binning == 0) {
-            s = gs[g];
-            cn = conic[g];
-        }
-        const float rcpn = __builtin_amdgcn_rcpf((float)ntx);
-        uint32_t tot = 0;
-#pragma unroll
-        for (int j = 0; j < kPer; ++j) {
-            const int idx = (int)c * kChunkTiles + j * kWave + lane;
-            bool h = false;
-            if (idx < nt) {
-                int ry, rx;
-                row_col(idx, ntx, rcpn, ry, rx);
-                h = binning != 0 ||
-                    tile_hit(s.f0.x, s.f0.y, cn.x, cn.y, cn.z, s.f1.y, (int)rc.x + rx, (int)rc.z + ry, W, H);
-            }
-            const uint64_t b = __ballot(h);
-            tot += (uint32_t)__popcll(b);
-            if (lane == 0) {
-                chunk_mask[(size_t)ch * (kChunkTiles / 32) + 2 * j] = (uint32_t)b;
-                chunk_mask[(size_t)ch * (kChunkTiles / 32) + 2 * j + 1] = (uint32_t)(b >> 32);
-            }
-        }
-        if (lane == 0) {
-            chunk_hits[ch] = tot;
-            if (tot) atomicAdd(&count[g], tot);
-        }
-        e = e_next;
+        // every lane has read the item starts before they are replaced
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
-// Pairs of the chunked Gaussians: each chunk (one wavefront) writes the hits
-// recorded by k_big_count after those of the Gaussian's earlier chunks.
-// A wavefront walks its chunks one ahead: while it writes a chunk's pairs, the
-// next chunk's data is already in flight in a single vector load (one dword
-// per lane: the hit mask, the chunk's hit count, the rectangle, the output
-// base and the hit counts of up to 52 earlier chunks of the Gaussian), and
-// the chunk entry after that in a scalar load.
-template <class KeyT>
-__global__ __launch_bounds__(kBlock) void k_big_emit(int W, const uint4 *__restrict__ erec,
-                                                     const uint2 *__restrict__ chunks,
-                                                     uint32_t chunk_cap, const uint32_t *__restrict__ chunk_hits,
-                                                     const uint32_t *__restrict__ chunk_mask,
-                                                     KeyT *__restrict__ tile_keys, uint32_t *__restrict__ values,
-                                                     uint32_t cap, const FrameCounters *fc) {
-    constexpr int kPer = kChunkTiles / kWave;
-    constexpr int kMaskWords = kChunkTiles / 32;
-    // lanes of the look-ahead load (the rectangle: the record's two packed words)
-    constexpr int kLaneHits = kMaskWords, kLaneRect = kLaneHits + 1, kLaneBase = kLaneRect + 2,
-                  kLanePre = kLaneBase + 1;
+// Entries of the chunked Gaussians.  Each wavefront takes 64 chunk slots,
+// one per lane; a Gaussian's first chunk holds, in `big`, its output slot
+// and entry offset.  The wavefront flattens the entries of its Gaussians so
+// that every lane builds one entry per step: entry k of a Gaussian is
+// super-tile k of its rectangle's overlap in row-major order.  The chunk
+// masks of a Gaussian are one bit stream over its rectangle in row-major
+// order, so each of the super-tile's (at most kSuper) rows is a run of at
+// most kSuper consecutive bits, read from two words.
+__global__ __launch_bounds__(kBlock) void k_big_entries(int W, const uint4 *__restrict__ erec, uint32_t ng,
+                                                        const uint2 *__restrict__ chunks,
+                                                        const uint2 *__restrict__ big, uint32_t chunk_cap,
+                                                        const uint32_t *__restrict__ chunk_mask,
+                                                        const FrameCounters *__restrict__ fc,
+                                                        uint16_t *__restrict__ skey, uint32_t *__restrict__ gidx,
+                                                        uint64_t *__restrict__ smask, uint32_t ecap) {
+    __shared__ uint32_t s_excl[kBlock / kWave][kWave];
     // an overflowed list has entries this frame never wrote (the frame is
     // rendered again, or reported, by the host)
     if (fc->error & kErrChunkOverflow) return;
     const int lane = threadIdx.x & (kWave - 1);
+    uint32_t *sx = s_excl[threadIdx.x / kWave];
     const int tiles_x = (W + kTile - 1) / kTile;
-    const uint64_t lt = (1ull << lane) - 1ull;
+    const uint32_t stx = (uint32_t)((tiles_x + kSuper - 1) >> kSuperShift);
     const uint32_t n = fc->nchunks < chunk_cap ? fc->nchunks : chunk_cap;
     const uint32_t nwaves = gridDim.x * (kBlock / kWave);
-    auto entry = [&](uint32_t c) { return c < n ? chunks[c] : make_uint2(kNoChunk, 0u); };
-    auto load_data = [&](uint32_t c, uint2 ec) -> uint32_t {
-        if (ec.x == kNoChunk) return 0u;  // uniform
-        const uint32_t g = ec.x, first = ec.y;
-        const uint32_t k = first + (uint32_t)(lane - kLanePre);  // an earlier chunk (lanes from kLanePre on)
-        const uint32_t *src = chunk_hits + k;
-        const bool use = lane < kLanePre || k < c;
-        src = lane == kLaneBase ? reinterpret_cast<const uint32_t *>(erec + g) + 2 : src;
-        src = lane < kLaneBase ? reinterpret_cast<const uint32_t *>(erec + g) + (lane - kLaneRect) : src;
-        src = lane == kLaneHits ? chunk_hits + c : src;
-        src = lane < kMaskWords ? chunk_mask + (size_t)c * kMaskWords + lane : src;
-        return use ? *src : 0u;
-    };
-    auto emit = [&](uint32_t c, uint2 ec, uint32_t v) {
-        if (ec.x == kNoChunk) return;
-        const uint32_t hits = bcast(v, kLaneHits);
-        if (hits == 0) return;
-        const uint32_t g = ec.x, first = ec.y;
-        const uint4 rc = unpack_rect(make_uint4(bcast(v, kLaneRect), bcast(v, kLaneRect + 1), 0u, 0u));
-        const uint32_t base = bcast(v, kLaneBase);
-        // hits of this Gaussian's earlier chunks (past the first 50: loaded here)
-        uint32_t p = lane >= kLanePre ? v : 0u;
-        for (uint32_t k = first + (uint32_t)(kWave - kLanePre) + (uint32_t)lane; k < c; k += kWave)
-            p += chunk_hits[k];
+    constexpr uint32_t kWordsPerChunk = kChunkTiles / 32;
+    const size_t wlast = (size_t)chunk_cap * kWordsPerChunk - 1;
+    for (uint32_t c0 = (blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave) * kWave; c0 < n;
+         c0 += nwaves * kWave) {
+        const uint32_t c = c0 + (uint32_t)lane;
+        bool first = false;
+        uint2 gb = make_uint2(0u, 0u);
+        if (c < n) {
+            first = chunks[c].y == c;
+            gb = big[c];
+        }
+        first = first && gb.x < ng;
+        uint4 rc = make_uint4(0u, 0u, 0u, 0u);
+        if (first) rc = unpack_rect(erec[gb.x]);
+        const uint32_t items = first ? super_span((int)rc.x, (int)rc.y, (int)rc.z, (int)rc.w) : 0u;
+        const uint32_t incl = wave_incl_scan(items, lane);
+        const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+        sx[lane] = incl - items;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const uint32_t px = rc.x | (rc.y << 16), py = rc.z | (rc.w << 16);
+        for (uint32_t i0 = 0; i0 < total; i0 += kWave) {
+            const uint32_t item = i0 + (uint32_t)lane;
+            const int L = owner_lane(sx, item < total ? item : total - 1u);
+            const uint32_t k = item < total ? item - sx[L] : 0u;  // (a spare lane redoes entry 0)
+            const uint32_t g = (uint32_t)__shfl((int)gb.x, L, kWave), base = (uint32_t)__shfl((int)gb.y, L, kWave);
+            const uint32_t lx = (uint32_t)__shfl((int)px, L, kWave), ly = (uint32_t)__shfl((int)py, L, kWave);
+            const int bx0 = (int)(lx & 0xffffu), bx1 = (int)(lx >> 16), by0 = (int)(ly & 0xffffu), by1 = (int)(ly >> 16);
+            const int bntx = bx1 - bx0 + 1;
+            const int sx0 = bx0 >> kSuperShift, sy0 = by0 >> kSuperShift;
+            const int nsx = (bx1 >> kSuperShift) - sx0 + 1;
+            int ey, ex;
+            row_col((int)k, nsx, __builtin_amdgcn_rcpf((float)nsx), ey, ex);
+            const int xs = (sx0 + ex) << kSuperShift, ys = (sy0 + ey) << kSuperShift;
+            const int xa = xs > bx0 ? xs : bx0, xb = xs + kSuper - 1 < bx1 ? xs + kSuper - 1 : bx1;
+            const int ya = ys > by0 ? ys : by0, yb = ys + kSuper - 1 < by1 ? ys + kSuper - 1 : by1;
+            const uint64_t lmask = (1ull << (xb - xa + 1)) - 1ull;  // xb - xa + 1 <= kSuper
+            const size_t wbase = (size_t)(c0 + (uint32_t)L) * kWordsPerChunk;
+            // every row's two words are loaded (rows past yb repeat row yb)
+            // before any is used: one memory round trip
+            uint32_t lo[kSuper], hi[kSuper], sh[kSuper];
 #pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) p += __shfl_xor(p, d, kWave);
-        uint64_t b[kPer];
+            for (int rr = 0; rr < kSuper; ++rr) {
+                const int ty = ya + rr < yb ? ya + rr : yb;
+                const uint32_t idx = (uint32_t)((ty - by0) * bntx + (xa - bx0));
+                const size_t w0 = wbase + idx / 32 < wlast ? wbase + idx / 32 : wlast;
+                const size_t w1 = w0 + 1 < wlast ? w0 + 1 : wlast;
+                lo[rr] = chunk_mask[w0];
+                hi[rr] = chunk_mask[w1];
+                sh[rr] = idx % 32;
+            }
+            uint64_t m = 0;
 #pragma unroll
-        for (int j = 0; j < kPer; ++j)
-            b[j] = (uint64_t)bcast(v, 2 * j) | ((uint64_t)bcast(v, 2 * j + 1) << 32);
-        const int ntx = (int)rc.y - (int)rc.x + 1;
-        const float rcpn = __builtin_amdgcn_rcpf((float)ntx);
-        const uint32_t cc = c - first;
-        uint32_t before = base + p;
+            for (int rr = 0; rr < kSuper; ++rr) {
+                const uint64_t bits = (((uint64_t)lo[rr] | ((uint64_t)hi[rr] << 32)) >> sh[rr]) & lmask;
+                const int place = (ya + rr - ys) * kSuper + (xa - xs);
+                m |= ya + rr <= yb ? bits << place : 0ull;
+            }
+            const uint32_t at = base + k;
+            if (item < total && at < ecap) {
+                skey[at] = (uint16_t)((uint32_t)(ys >> kSuperShift) * stx + (uint32_t)(xs >> kSuperShift));
+                gidx[at] = g;
+                smask[at] = m;
+            }
+        }
+        // every lane has read the item starts before they are replaced
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Exact tile tests of the chunked Gaussians: one wavefront per chunk of
+// kChunkTiles rectangle tiles (4 per lane, independent), so that every
+// workgroup keeps four chunks in flight without barriers; the next chunk's
+// descriptor is loaded before the current chunk is tested.  A workgroup adds
+// its hits to the frame's pair count once.
+__global__ __launch_bounds__(kBlock) void k_big_count(int W, int H, int binning, const GaussState *__restrict__ gs,
+                                                      const float4 *__restrict__ conic,
+                                                      const uint4 *__restrict__ erec,
+                                                      const uint2 *__restrict__ chunks, uint32_t chunk_cap,
+                                                      uint32_t *__restrict__ chunk_mask, uint32_t *count,
+                                                      FrameCounters *fc) {
+    constexpr int kPer = kChunkTiles / kWave;
+    __shared__ uint32_t s_hits[kBlock / kWave];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    uint32_t whits = 0;  // wave-uniform
+    // an overflowed list has entries this frame never wrote (the frame is
+    // rendered again, or reported, by the host)
+    if (!(fc->error & kErrChunkOverflow)) {
+        const uint32_t n = fc->nchunks < chunk_cap ? fc->nchunks : chunk_cap;
+        const uint32_t nwaves = gridDim.x * (kBlock / kWave);
+        uint32_t ch = blockIdx.x * (kBlock / kWave) + (uint32_t)wv;
+        uint2 e = ch < n ? chunks[ch] : make_uint2(kNoChunk, 0u);
+        for (; ch < n; ch += nwaves) {
+            const uint32_t nxt = ch + nwaves;
+            const uint2 e_next = nxt < n ? chunks[nxt] : make_uint2(kNoChunk, 0u);
+            if (e.x == kNoChunk) {
+                e = e_next;
+                continue;
+            }
+            const uint32_t g = e.x, c = ch - e.y;
+            const uint4 rc = unpack_rect(erec[g]);
+            const int ntx = (int)rc.y - (int)rc.x + 1;
+            const int nt = ntx * ((int)rc.w - (int)rc.z + 1);
+            GaussState s{};
+            float4 cn = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (binning == 0) {
+                s = gs[g];
+                cn = conic[g];
+            }
+            const float rcpn = __builtin_amdgcn_rcpf((float)ntx);
+            uint32_t tot = 0;
 #pragma unroll
-        for (int j = 0; j < kPer; ++j) {
-            if ((b[j] >> lane) & 1ull) {
-                const int idx = (int)cc * kChunkTiles + j * kWave + lane;
-                int ry, rx;
-                row_col(idx, ntx, rcpn, ry, rx);
-                const uint32_t tile = (uint32_t)(((int)rc.z + ry) * tiles_x + ((int)rc.x + rx));
-                const uint32_t at = before + (uint32_t)__popcll(b[j] & lt);
-                if (at < cap) {  // never leave the pair buffers
-                    tile_keys[at] = (KeyT)tile;
-                    values[at] = g;
+            for (int j = 0; j < kPer; ++j) {
+                const int idx = (int)c * kChunkTiles + j * kWave + lane;
+                bool h = false;
+                if (idx < nt) {
+                    int ry, rx;
+                    row_col(idx, ntx, rcpn, ry, rx);
+                    h = binning != 0 ||
+                        tile_hit(s.f0.x, s.f0.y, cn.x, cn.y, cn.z, s.f1.y, (int)rc.x + rx, (int)rc.z + ry, W, H);
+                }
+                const uint64_t b = __ballot(h);
+                tot += (uint32_t)__popcll(b);
+                if (lane == 0) {
+                    chunk_mask[(size_t)ch * (kChunkTiles / 32) + 2 * j] = (uint32_t)b;
+                    chunk_mask[(size_t)ch * (kChunkTiles / 32) + 2 * j + 1] = (uint32_t)(b >> 32);
                 }
             }
-            before += (uint32_t)__popcll(b[j]);
+            if (lane == 0 && tot) atomicAdd(&count[g], tot);
+            whits += tot;
+            e = e_next;
         }
-    };
-    uint32_t ch = (uint32_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave));
-    uint2 e0 = entry(ch), e1 = entry(ch + nwaves);
-    uint32_t d0 = load_data(ch, e0);
-    for (; ch < n; ch += nwaves) {
-        const uint32_t c1 = ch + nwaves;
-        const uint32_t d1 = load_data(c1, e1);
-        const uint2 e2 = entry(c1 + nwaves);
-        emit(ch, e0, d0);
-        e0 = e1;
-        e1 = e2;
-        d0 = d1;
+    }
+    if (lane == 0) s_hits[wv] = whits;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / kWave; ++w) t += s_hits[w];
+        if (t) atomicAdd(&fc->pairs, t);
     }
 }
 
@@ -1329,7 +1383,7 @@ unsigned preprocess_grid(int64_t P) {
 }
 
 unsigned emit_grid(uint32_t visible) {
-    static const unsigned cap = resident_blocks(k_emit<uint32_t>);
+    static const unsigned cap = resident_blocks(k_super_emit);
     const uint32_t b = (visible + kBlock - 1) / kBlock;
     return b < cap ? (b > 0 ? b : 1u) : cap;
 }
@@ -1387,36 +1441,27 @@ void launch_spatial_keys(const DevScene &sc, uint32_t *bounds, uint32_t *keys, h
 }
 
 void launch_big_count(int W, int H, int binning, const GaussState *gs, const float4 *conic, const uint4 *erec,
-                      const uint2 *chunks, uint32_t chunk_cap, uint32_t *chunk_hits, uint32_t *chunk_mask,
-                      uint32_t *count, const FrameCounters *fc, hipStream_t s) {
+                      const uint2 *chunks, uint32_t chunk_cap, uint32_t *chunk_mask, uint32_t *count,
+                      FrameCounters *fc, hipStream_t s) {
     if (chunk_cap == 0) return;
     hipLaunchKernelGGL(k_big_count, dim3(kPersistentBlocks), dim3(kBlock), 0, s, W, H, binning, gs, conic, erec,
-                       chunks, chunk_cap, chunk_hits, chunk_mask, count, fc);
+                       chunks, chunk_cap, chunk_mask, count, fc);
 }
 
-void launch_big_emit(int W, const uint4 *erec, const uint2 *chunks, uint32_t chunk_cap, const uint32_t *chunk_hits,
-                     const uint32_t *chunk_mask, void *tile_keys, int key_bytes, uint32_t *values, uint32_t cap,
-                     const FrameCounters *fc, hipStream_t s) {
-    if (key_bytes == 2)
-        hipLaunchKernelGGL(k_big_emit<uint16_t>, dim3(kPersistentBlocks), dim3(kBlock), 0, s, W, erec, chunks,
-                           chunk_cap, chunk_hits, chunk_mask, static_cast<uint16_t *>(tile_keys), values, cap, fc);
-    else
-        hipLaunchKernelGGL(k_big_emit<uint32_t>, dim3(kPersistentBlocks), dim3(kBlock), 0, s, W, erec, chunks,
-                           chunk_cap, chunk_hits, chunk_mask, static_cast<uint32_t *>(tile_keys), values, cap, fc);
-}
-
-void launch_emit(int W, int H, const uint32_t *order, uint32_t visible, const uint32_t *visible_dev,
-                 const uint32_t *offsets, uint4 *erec, void *tile_keys, int key_bytes, uint32_t *values, uint32_t cap,
-                 uint2 *ranges, uint32_t ntiles, uint32_t *gsum_clear, hipStream_t s) {
-    if (visible == 0 && (!ranges || ntiles == 0) && !gsum_clear) return;
+void launch_super_emit(int W, int H, const uint32_t *order, uint32_t visible, const uint32_t *visible_dev,
+                       const uint32_t *offsets, const uint4 *erec, uint32_t ng, const uint2 *chunks, uint2 *big,
+                       const uint32_t *chunk_mask, uint32_t chunk_cap, const FrameCounters *fc, uint16_t *skey,
+                       uint32_t *gidx, uint64_t *smask, uint32_t ecap, uint2 *sranges, uint32_t nsuper,
+                       uint32_t *gsum_clear, hipStream_t s) {
+    (void)H;
+    if (visible == 0 && (!sranges || nsuper == 0) && !gsum_clear) return;
     unsigned grid = emit_grid(visible);
-    if (ranges) grid = std::max(grid, std::min<unsigned>((ntiles + kBlock - 1) / kBlock, kPersistentBlocks));
-    if (key_bytes == 2)
-        hipLaunchKernelGGL(k_emit<uint16_t>, dim3(grid), dim3(kBlock), 0, s, W, H, order, visible, visible_dev,
-                           offsets, erec, static_cast<uint16_t *>(tile_keys), values, cap, ranges, ntiles, gsum_clear);
-    else
-        hipLaunchKernelGGL(k_emit<uint32_t>, dim3(grid), dim3(kBlock), 0, s, W, H, order, visible, visible_dev,
-                           offsets, erec, static_cast<uint32_t *>(tile_keys), values, cap, ranges, ntiles, gsum_clear);
+    if (sranges) grid = std::max(grid, std::min<unsigned>((nsuper + kBlock - 1) / kBlock, kPersistentBlocks));
+    hipLaunchKernelGGL(k_super_emit, dim3(grid), dim3(kBlock), 0, s, W, order, visible, visible_dev, offsets, erec,
+                       big, chunk_cap, skey, gidx, smask, ecap, sranges, nsuper, gsum_clear);
+    if (chunk_cap == 0 || visible == 0) return;
+    hipLaunchKernelGGL(k_big_entries, dim3(kPersistentBlocks), dim3(kBlock), 0, s, W, erec, ng, chunks, big,
+                       chunk_cap, chunk_mask, fc, skey, gidx, smask, ecap);
 }
 
 }  // namespace fgs

@@ -117,7 +117,10 @@ static_assert(kSortBlocks % kSortGroup == 0, "whole groups of workgroups");
 
 // (LDS holds four workgroups per CU, so registers are capped at what four
 // waves per SIMD allow.)
-template <bool kIdentityVals, bool kFilter, bool kWriteKeys, class KeyT>
+// kPayload: the values are the input positions while ranking (as with
+// kIdentityVals), and each element's payload (vals_in, mask_in at that
+// position, inside the workgroup's tile) is read when it is stored.
+template <bool kIdentityVals, bool kFilter, bool kWriteKeys, class KeyT, bool kPayload = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_radix_downsweep(const KeyT *__restrict__ keys_in,
                                                             const uint32_t *__restrict__ vals_in,
                                                             KeyT *__restrict__ keys_out,
@@ -126,7 +129,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                                                             const uint32_t *__restrict__ hist,
                                                             const uint32_t *__restrict__ gsum,
                                                             uint32_t *__restrict__ gsum_next,
-                                                            uint32_t *__restrict__ run_end, uint32_t nruns) {
+                                                            uint32_t *__restrict__ run_end, uint32_t nruns,
+                                                            const uint64_t *__restrict__ mask_in,
+                                                            uint64_t *__restrict__ mask_out) {
+    static_assert(!kPayload || kIdentityVals, "a payload is ranked by position");
     // (per-wave and per-tile digit counts are at most kSortTile: 16 bits)
     __shared__ KeyT s_keys[kSortTile];
     __shared__ uint32_t s_vals[kSortTile];
@@ -204,13 +210,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             // lanes of this step with the same digit (stable rank = lower
             // lanes): a lane differs from this one where some digit bit
             // disagrees, i.e. where ballot(bit) xor (own bit, widened) is
-            // set.  All kRadixBits bits are matched (a narrower digit has zero
-            // high bits in every lane).  Per bit: one bitfield extract, one
+            // set.  The pass's `bits` digit bits are matched (a uniform
+            // branch skips the rest).  Per bit: one bitfield extract, one
             // compare and one three-input logic op per half mask
             // (bitop3 table 0xf6 = src0 | (src1 ^ src2)).
             uint32_t diff_lo = 0, diff_hi = 0;
 #pragma unroll
             for (int bb = 0; bb < kRadixBits; ++bb) {
+                if (bb >= bits) break;
                 // bit bb of d widened to 0 or ~0 by one signed bitfield extract
                 // (written out: the compiler otherwise splits it into two shifts)
                 uint32_t t;
@@ -264,7 +271,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             const uint32_t gpos = s_gbase[d] + j;
             if (gpos < n) {  // never leave the output (n bounds the scattered count)
                 if (kWriteKeys) keys_out[gpos] = (KeyT)k;
-                vals_out[gpos] = s_vals[j];
+                if constexpr (kPayload) {
+                    const uint32_t src = s_vals[j];  // < hi: an element of this tile
+                    vals_out[gpos] = vals_in[src];
+                    mask_out[gpos] = mask_in[src];
+                } else {
+                    vals_out[gpos] = s_vals[j];
+                }
                 // last pass of a sort by the whole key: the keys of one
                 // digit run of this tile are in key order, so the first and
                 // last element of each key's stretch may start and end its run
@@ -285,11 +298,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 // visible Gaussians keep every one of the kSortBlocks workgroups busy.
 constexpr uint32_t kScanGranule = 1024;
 
-// cs[r] = count of order[r] (from the one-byte copy, or count[] for a
-// chunked rectangle); sums[b] = sum over the workgroup's range
+// cs[r] = count of order[r] (from the one-byte copy, or the super-tile span
+// of a chunked rectangle's record); sums[b] = sum over the workgroup's range
 __global__ __launch_bounds__(kBlock) void k_scan_upsweep(const uint32_t *__restrict__ order,
                                                          const uint8_t *__restrict__ count8,
-                                                         const uint32_t *__restrict__ count, uint32_t n_host,
+                                                         const uint4 *__restrict__ erec, uint32_t n_host,
                                                          const uint32_t *n_dev, uint32_t *__restrict__ cs,
                                                          uint32_t *__restrict__ sums) {
     __shared__ uint32_t s_tmp[kWaves];
@@ -311,7 +324,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_upsweep(const uint32_t *__restr
         }
 #pragma unroll
         for (int k = 0; k < 8; ++k)
-            if (c[k] == kCount8Big) c[k] = count[g[k]];  // a chunked rectangle (rare)
+            if (c[k] == kCount8Big) {  // a chunked rectangle (rare)
+                const uint4 r = erec[g[k]];
+                c[k] = super_span((int)(r.x & 0xffffu), (int)(r.x >> 16), (int)(r.y & 0xffffu), (int)(r.y >> 16));
+            }
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const uint32_t i = c0 + (uint32_t)(k * kBlock) + threadIdx.x;
@@ -324,12 +340,12 @@ __global__ __launch_bounds__(kBlock) void k_scan_upsweep(const uint32_t *__restr
     if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
-// offsets[r] = exclusive prefix of cs; offsets[n] and *pairs = total.  Each
+// offsets[r] = exclusive prefix of cs; offsets[n] and *total = total.  Each
 // workgroup sums the kSortBlocks workgroup sums itself (4 KB from L2) for its
 // base and the total.
 __global__ __launch_bounds__(kBlock) void k_scan_downsweep(const uint32_t *__restrict__ cs, uint32_t n_host,
                                                            const uint32_t *n_dev, const uint32_t *__restrict__ sums,
-                                                           uint32_t *__restrict__ offsets, uint32_t *pairs) {
+                                                           uint32_t *__restrict__ offsets, uint32_t *total) {
     __shared__ uint32_t s_tmp[kWaves];
     const uint32_t n = count_of(n_host, n_dev);
     uint32_t lo, hi;
@@ -350,7 +366,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_downsweep(const uint32_t *__res
         (void)block_exclusive_scan(pre, s_tmp, &tot_pre);
         (void)block_exclusive_scan(all, s_tmp, &tot_all);
         run = tot_pre;
-        if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *pairs = tot_all;
+        if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = tot_all;
     }
     // one 4096-entry tile per step: every thread scans its own 16
     // consecutive entries (four 16-byte loads and stores where the tile is
@@ -589,7 +605,7 @@ __global__ __launch_bounds__(kBlock) void k_depth_long_ties(const uint32_t *__re
 void launch_radix_pass(const void *keys_in, const uint32_t *vals_in, void *keys_out, uint32_t *vals_out,
                        uint32_t n_host, const uint32_t *n_dev, int shift, int bits, bool filter, bool write_keys,
                        uint32_t *hist, uint32_t *gsum, uint32_t *gsum_next, hipStream_t s, uint2 *run_ends,
-                       uint32_t nruns, int key_bytes) {
+                       uint32_t nruns, int key_bytes, const uint64_t *mask_in, uint64_t *mask_out) {
     if (n_host == 0) return;
     const unsigned nb = kSortBlocks;
     const bool k16 = key_bytes == 2;
@@ -609,9 +625,16 @@ void launch_radix_pass(const void *keys_in, const uint32_t *vals_in, void *keys_
 #define FGS_DS(I, F, K, T)                                                                                          \
     hipLaunchKernelGGL((k_radix_downsweep<I, F, K, T>), dim3(nb), dim3(kBlock), 0, s, static_cast<const T *>(keys_in), \
                        vals_in, static_cast<T *>(keys_out), vals_out, n_host, n_dev, shift, bits, hist, gsum,         \
-                       gsum_next, ends, nruns)
-    // 16-bit keys: the tile passes (never filtered, explicit values)
-    if (k16 && write_keys) FGS_DS(false, false, true, uint16_t);
+                       gsum_next, ends, nruns, nullptr, nullptr)
+#define FGS_DSP(K)                                                                                                  \
+    hipLaunchKernelGGL((k_radix_downsweep<true, false, K, uint16_t, true>), dim3(nb), dim3(kBlock), 0, s,         \
+                       static_cast<const uint16_t *>(keys_in), vals_in, static_cast<uint16_t *>(keys_out), vals_out,   \
+                       n_host, n_dev, shift, bits, hist, gsum, gsum_next, ends, nruns, mask_in, mask_out)
+    // 16-bit keys with a payload: the super-tile passes
+    if (k16 && mask_in && write_keys) FGS_DSP(true);
+    else if (k16 && mask_in) FGS_DSP(false);
+    // 16-bit keys: unfiltered, explicit values
+    else if (k16 && write_keys) FGS_DS(false, false, true, uint16_t);
     else if (k16) FGS_DS(false, false, false, uint16_t);
     else if (ident && filter && write_keys) FGS_DS(true, true, true, uint32_t);
     else if (!ident && !filter && write_keys) FGS_DS(false, false, true, uint32_t);
@@ -619,16 +642,17 @@ void launch_radix_pass(const void *keys_in, const uint32_t *vals_in, void *keys_
     else if (ident && !filter && write_keys) FGS_DS(true, false, true, uint32_t);
     else FGS_DS(false, true, true, uint32_t);
 #undef FGS_DS
+#undef FGS_DSP
 }
 
-void launch_count_scan(const uint32_t *order, const uint8_t *count8, const uint32_t *count, uint32_t n_host,
-                       const uint32_t *n_dev, uint32_t *cs, uint32_t *sums, uint32_t *offsets, uint32_t *pairs,
+void launch_count_scan(const uint32_t *order, const uint8_t *count8, const uint4 *erec, uint32_t n_host,
+                       const uint32_t *n_dev, uint32_t *cs, uint32_t *sums, uint32_t *offsets, uint32_t *total,
                        hipStream_t s) {
     if (n_host == 0) return;
-    hipLaunchKernelGGL(k_scan_upsweep, dim3(kSortBlocks), dim3(kBlock), 0, s, order, count8, count, n_host, n_dev, cs,
+    hipLaunchKernelGGL(k_scan_upsweep, dim3(kSortBlocks), dim3(kBlock), 0, s, order, count8, erec, n_host, n_dev, cs,
                        sums);
     hipLaunchKernelGGL(k_scan_downsweep, dim3(kSortBlocks), dim3(kBlock), 0, s, cs, n_host, n_dev, sums, offsets,
-                       pairs);
+                       total);
 }
 
 void launch_depth_ties(const uint32_t *keys, uint32_t *vals, const uint32_t *gmap, uint32_t n_host,

@@ -84,11 +84,12 @@ hipError_t ensure_gauss(FrameBuffers &b, size_t P) {
 
 hipError_t ensure_pairs(FrameBuffers &b, size_t N) {
     if (N <= b.capN && b.tk_a) return hipSuccess;
-    const size_t cap = N + N / 4 + 4096;
-    FGS_GROW(b.tk_a, cap);
-    FGS_GROW(b.tk_b, cap);
-    FGS_GROW(b.tv_a, cap);
-    FGS_GROW(b.tv_b, cap);
+    const size_t cap = (N + N / 4 + 4096 + 63) / 64 * 64;
+    // one block for the four arrays
+    FGS_GROW(b.tk_a, 4 * cap);
+    b.tk_b = b.tk_a + cap;
+    b.tv_a = b.tk_a + 2 * cap;
+    b.tv_b = b.tk_a + 3 * cap;
     b.capN = cap;
     b.pairs_owned = true;
     return hipSuccess;
@@ -97,6 +98,7 @@ hipError_t ensure_pairs(FrameBuffers &b, size_t N) {
 hipError_t ensure_tiles(FrameBuffers &b, size_t tiles) {
     if (tiles <= b.capTiles && b.ranges) return hipSuccess;
     FGS_GROW(b.ranges, tiles);
+    FGS_GROW(b.sranges, tiles);
     b.capTiles = tiles;
     return hipSuccess;
 }
@@ -118,11 +120,11 @@ hipError_t ensure_sort_scratch(SortScratch &s) {
 }
 
 hipError_t ensure_chunks(ChunkList &c, size_t need) {
-    need = std::max<size_t>(need, 65536);
+    need = (std::max<size_t>(need, 65536) + kChunkCapAlign - 1) / kChunkCapAlign * kChunkCapAlign;
     if (need <= c.cap && c.chunks) return hipSuccess;
     FGS_GROW(c.chunks, need);
-    FGS_GROW(c.hits, need);
     FGS_GROW(c.mask, need * (kChunkTiles / 32));
+    FGS_GROW(c.big, need);
     c.cap = need;
     return hipSuccess;
 }
@@ -130,12 +132,11 @@ hipError_t ensure_chunks(ChunkList &c, size_t need) {
 void free_frame_buffers(FrameBuffers &b) {
     void **ps[] = {(void **)&b.gs, (void **)&b.conic, (void **)&b.rect, (void **)&b.count, (void **)&b.count8, (void **)&b.erec, (void **)&b.dkey,
                    (void **)&b.dk_b, (void **)&b.dv_a, (void **)&b.dv_b, (void **)&b.offsets, (void **)&b.seg_count, (void **)&b.gmap,
-                   (void **)&b.ranges,
+                   (void **)&b.ranges, (void **)&b.sranges,
                    (void **)&b.T, (void **)&b.last};
     for (void **p : ps) free_p(*p);
     if (b.pairs_owned) {
-        void **pp[] = {(void **)&b.tk_a, (void **)&b.tk_b, (void **)&b.tv_a, (void **)&b.tv_b};
-        for (void **p : pp) free_p(*p);
+        free_p(*(void **)&b.tk_a);  // the block of all four
     }
     b = FrameBuffers{};
 }
@@ -148,8 +149,8 @@ void free_sort_scratch(SortScratch &s) {
 
 void free_chunks(ChunkList &c) {
     free_p(*(void **)&c.chunks);
-    free_p(*(void **)&c.hits);
     free_p(*(void **)&c.mask);
+    free_p(*(void **)&c.big);
     c.cap = 0;
 }
 
@@ -336,8 +337,7 @@ void enqueue_front_rest(bool dense, uint32_t P32, const DevOptions &op, int W, i
     if (side.side && hipEventRecord(side.fork, s) == hipSuccess &&
         hipStreamWaitEvent(side.side, side.fork, 0) == hipSuccess)
         sb = side.side;
-    launch_big_count(W, H, op.binning, fb.gs, fb.conic, fb.erec, ch.chunks, chunk_cap, ch.hits, ch.mask, fb.count, fc,
-                     sb);
+    launch_big_count(W, H, op.binning, fb.gs, fb.conic, fb.erec, ch.chunks, chunk_cap, ch.mask, fb.count, fc, sb);
     const bool joined = sb == s || hipEventRecord(side.join, sb) == hipSuccess;
     if (!joined) (void)hipStreamSynchronize(sb);  // cannot order the streams by an event: wait here instead
     // ---- depth order of the visible Gaussians: 4 LSD passes over the depth
@@ -360,11 +360,13 @@ void enqueue_front_rest(bool dense, uint32_t P32, const DevOptions &op, int W, i
     // run of equal depths by Gaussian index (the long-run list borrows the
     // offsets, which the scan writes next; dv_b is free after the last pass)
     if (dense) launch_depth_ties(fb.dkey, fb.dv_a, fb.gmap, P32, &fc->visible, fb.offsets, fc, fb.dv_b, s);
-    // the scan reads the counts of the large rectangles
-    if (sb != s && joined && hipStreamWaitEvent(s, side.join, 0) != hipSuccess) (void)hipStreamSynchronize(sb);
     mk.mark(2, s);
-    // ---- stage 2a: scan of the tile counts in depth order -------------------------
-    launch_count_scan(fb.dv_a, fb.count8, fb.count, P32, &fc->visible, fb.dk_b, ss.sums, fb.offsets, &fc->pairs, s);
+    // ---- stage 2a: scan of the super-tile entry counts in depth order --------------
+    // (a large rectangle's entries follow from its rectangle: the scan does
+    // not wait for its tests)
+    launch_count_scan(fb.dv_a, fb.count8, fb.erec, P32, &fc->visible, fb.dk_b, ss.sums, fb.offsets, &fc->entries, s);
+    // the pair count and the emission read what the large-rectangle tests wrote
+    if (sb != s && joined && hipStreamWaitEvent(s, side.join, 0) != hipSuccess) (void)hipStreamSynchronize(sb);
     mk.mark(3, s);
     // the second half reads the counters on the device; only the host waits
     // for their copy, which therefore runs beside it when it can
@@ -379,45 +381,61 @@ void enqueue_front_rest(bool dense, uint32_t P32, const DevOptions &op, int W, i
 bool enqueue_back(int W, int H, const DevOptions &op, uint32_t P, FrameBuffers &fb, ChunkList &ch, SortScratch &ss,
                   FrameCounters *fc, float *rgb, float *T, uint32_t *last, unsigned long long *work, hipStream_t s,
                   const StageMarks &mk, int blend_variant) {
-    const int tiles_x = (W + kTile - 1) / kTile, tiles_y = (H + kTile - 1) / kTile;
-    const uint32_t ntiles = (uint32_t)tiles_x * (uint32_t)tiles_y;
+    const uint32_t nsuper = super_count(W, H);
     const uint32_t chunk_cap = (uint32_t)std::min<size_t>(ch.cap, 0xffffffffu);
     const uint32_t pair_cap = (uint32_t)std::min<size_t>(fb.capN, 0xffffffffu);
-    // ---- stage 2b: key emission -------------------------------------------------
-    // tile ids travel as uint16 through emission and sort when they fit
-    const int kb = ntiles <= 65536u ? 2 : 4;
+    // The values go to tv_b; the entries of both sort buffers and the
+    // tile-list scratch fill the 12 capN bytes before it (tk_a, tk_b, tv_a:
+    // one block), each array 128-byte aligned (ecap is a multiple of 64).
+    const size_t ecap_z = std::min<size_t>(entry_capacity(fb.capN, W, H), 0xffffffc0u);
+    const uint32_t ecap = (uint32_t)ecap_z;
+    uint8_t *blk = reinterpret_cast<uint8_t *>(fb.tk_a);
+    uint64_t *mask_a = reinterpret_cast<uint64_t *>(blk), *mask_b = mask_a + ecap;
+    uint32_t *gidx_a = reinterpret_cast<uint32_t *>(mask_b + ecap), *gidx_b = gidx_a + ecap;
+    uint16_t *skey_a = reinterpret_cast<uint16_t *>(gidx_b + ecap), *skey_b = skey_a + ecap;
+    uint32_t *lscratch = reinterpret_cast<uint32_t *>(skey_b + ecap);
+    const bool fits = ecap_z > 0;
+    // ---- stage 2b: key emission ----------------------------------------------------
     int shifts[4] = {0, 0, 0, 0}, widths[4] = {0, 0, 0, 0};
-    const int npass = plan_tile_passes(ceil_log2(ntiles), shifts, widths);
-    // the emission also sets every tile's range empty when a sort pass
-    // records the ranges (a one-tile image has no pass: its single range
-    // holds every pair)
-    static_assert(kGsumSlots >= 4 + 4, "four depth and up to four tile passes");
-    launch_emit(W, H, fb.dv_a, P, &fc->visible, fb.offsets, fb.erec, fb.tk_a, kb, fb.tv_a, pair_cap,
-                npass > 0 ? fb.ranges : nullptr, ntiles, npass > 0 ? ss.slot(4) : nullptr, s);
-    launch_big_emit(W, fb.erec, ch.chunks, chunk_cap, ch.hits, ch.mask, fb.tk_a, kb, fb.tv_a, pair_cap, fc, s);
+    const int npass = plan_tile_passes(ceil_log2(nsuper), shifts, widths);
+    // the emission also sets every super-tile's range empty when a sort pass
+    // records the ranges (one super-tile: no pass, its range holds every entry)
+    static_assert(kGsumSlots >= 4 + 2, "four depth and up to two super-tile passes");
+    launch_super_emit(W, H, fb.dv_a, P, &fc->visible, fb.offsets, fb.erec, (uint32_t)std::min<size_t>(fb.capP, 0xffffffffu),
+                      ch.chunks, ch.big, ch.mask, chunk_cap, fc, skey_a, gidx_a, mask_a, ecap,
+                      npass > 0 ? fb.sranges : nullptr, nsuper, npass > 0 ? ss.slot(4) : nullptr, s);
     mk.mark(4, s);
-    // ---- stage 3: stable LSD sort of the pairs by tile id ---------------------------
-    uint32_t *ki = fb.tk_a, *vi = fb.tv_a, *ko = fb.tk_b, *vo = fb.tv_b;
-    // The last pass records where each tile's run starts and ends instead of
-    // writing the sorted tile ids (an empty tile keeps start > end).
+    // ---- stage 3: stable LSD sort of the entries by super-tile ----------------------
+    uint16_t *ki = skey_a, *ko = skey_b;
+    uint32_t *vi = gidx_a, *vo = gidx_b;
+    uint64_t *mi = mask_a, *mo = mask_b;
+    // The last pass records where each super-tile's run starts and ends
+    // instead of writing the sorted keys (an empty super-tile keeps start > end).
     for (int p = 0; p < npass; ++p) {
         const bool last_pass = p + 1 == npass;
-        launch_radix_pass(ki, vi, ko, vo, pair_cap, &fc->pairs, shifts[p], widths[p], false, !last_pass, ss.rhist,
-                          ss.slot(4 + p), last_pass ? nullptr : ss.slot(5 + p), s, last_pass ? fb.ranges : nullptr,
-                          ntiles, kb);
+        launch_radix_pass(ki, vi, ko, vo, ecap, &fc->entries, shifts[p], widths[p], false, !last_pass, ss.rhist,
+                          ss.slot(4 + p), last_pass ? nullptr : ss.slot(5 + p), s, last_pass ? fb.sranges : nullptr,
+                          nsuper, 2, mi, mo);
         std::swap(ki, ko);
         std::swap(vi, vo);
+        std::swap(mi, mo);
     }
+    if (npass == 0) launch_single_range(fb.sranges, ecap, &fc->entries, s);
     mk.mark(5, s);
-    if (npass == 0) launch_single_range(fb.ranges, pair_cap, &fc->pairs, s);
+    // ---- per-tile lists and ranges (the sorted pairs) -----------------------------
+    if (fits)
+        launch_tile_lists(W, H, fb.sranges, vi, mi, ecap, lscratch, fb.ranges, fb.tv_b, pair_cap, s);
+    else  // too small for the list scratch: empty ranges (the host renders the frame again)
+        launch_fill_u32(reinterpret_cast<uint32_t *>(fb.ranges), 0u,
+                        (size_t)2 * (size_t)((W + kTile - 1) / kTile) * (size_t)((H + kTile - 1) / kTile), s);
     mk.mark(6, s);
     // ---- stage 4: blend -------------------------------------------------------------
     // (the variant's buffer loads take 32-bit byte offsets)
-    const bool fits = fb.capN <= 0x7fffffffu / 4u && fb.capP <= 0x7fffffffu / sizeof(GaussState);
-    launch_blend(fb.gs, vi, fb.ranges, W, H, op, rgb, T, last, work, fits ? blend_variant : 0, (uint32_t)fb.capN,
-                 (uint32_t)fb.capP, s);
+    const bool fits32 = fb.capN <= 0x7fffffffu / 4u && fb.capP <= 0x7fffffffu / sizeof(GaussState);
+    launch_blend(fb.gs, fb.tv_b, fb.ranges, W, H, op, rgb, T, last, work, fits32 ? blend_variant : 0,
+                 (uint32_t)fb.capN, (uint32_t)fb.capP, s);
     mk.mark(7, s);
-    return ki == fb.tk_a;
+    return false;
 }
 
 }  // namespace fgs

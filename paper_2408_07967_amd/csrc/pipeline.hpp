@@ -28,11 +28,12 @@ struct FrameBuffers {
     uint32_t *offsets = nullptr;
     uint32_t *seg_count = nullptr;  // kCullBlocks candidate counts of a prepared scene's cull
     uint32_t *gmap = nullptr;       // prepared scene: Gaussian of each candidate list position
-    // per pair (ping-pong for the LSD passes)
+    // per pair: four arrays of capN words, consecutive parts of one block
+    // that starts at tk_a (the entries and the values, see entry_capacity)
     uint32_t *tk_a = nullptr, *tk_b = nullptr, *tv_a = nullptr, *tv_b = nullptr;
     bool pairs_owned = true;  // false: the pair arrays live in a caller's arena
-    // per tile / pixel
-    uint2 *ranges = nullptr;
+    // per tile / pixel (sranges: per super-tile, sized like ranges)
+    uint2 *ranges = nullptr, *sranges = nullptr;
     float *T = nullptr;
     uint32_t *last = nullptr;
 
@@ -43,7 +44,7 @@ struct FrameBuffers {
                (capP + 1) * sizeof(uint32_t) + kCullBlocks * sizeof(uint32_t);
     }
     size_t bytes() const {
-        return gauss_bytes() + (pairs_owned ? capN * 4 * sizeof(uint32_t) : 0) + capTiles * sizeof(uint2) +
+        return gauss_bytes() + (pairs_owned ? capN * 4 * sizeof(uint32_t) : 0) + capTiles * 2 * sizeof(uint2) +
                capPix * (sizeof(float) + sizeof(uint32_t));
     }
 };
@@ -57,14 +58,56 @@ struct SortScratch {
     }
 };
 
-// List of Gaussians whose rectangles exceed kBigTiles tiles.
+// List of Gaussians whose rectangles exceed kBigTiles tiles, in chunks of
+// kChunkTiles tiles.
 struct ChunkList {
     uint2 *chunks = nullptr;
-    uint32_t *hits = nullptr;
-    uint32_t *mask = nullptr;  // 256-bit hit mask per chunk
+    uint32_t *mask = nullptr;  // kChunkTiles-bit hit mask per chunk
+    uint2 *big = nullptr;      // at a Gaussian's first chunk: its output slot and entry offset
     size_t cap = 0;
-    size_t bytes() const { return cap * (sizeof(uint2) + 9 * sizeof(uint32_t)); }
+    size_t bytes() const { return cap * (2 * sizeof(uint2) + (kChunkTiles / 32) * sizeof(uint32_t)); }
 };
+
+// Super-tiles of a W x H image.
+inline uint32_t super_tiles_x(int W) { return (uint32_t)((((W + kTile - 1) / kTile) + kSuper - 1) >> kSuperShift); }
+inline uint32_t super_count(int W, int H) { return super_tiles_x(W) * super_tiles_x(H); }
+
+// Passes of the entries' sort by super-tile id (kRadixBits per pass).
+inline int super_sort_passes(int W, int H) {
+    int b = 0;
+    while ((1ull << b) < (uint64_t)super_count(W, H)) ++b;
+    return (b + kRadixBits - 1) / kRadixBits;
+}
+
+// Bytes of the first three per-pair arrays that ecap entries and their
+// tile-list scratch take for nsuper super-tiles.
+inline size_t entry_bytes(size_t ecap, size_t nsuper) {
+    return ecap * kEntryBytes + list_scratch_words(ecap, nsuper) * sizeof(uint32_t);
+}
+
+// Entries that the first three per-pair arrays (12 capN bytes) hold beside
+// their tile-list scratch for a W x H image (a multiple of 64; 0 if the
+// scratch alone does not fit).
+inline size_t entry_capacity(size_t capN, int W, int H) {
+    const size_t ns = super_count(W, H), room = 12 * capN;
+    const size_t fixed = entry_bytes(0, ns);
+    if (room < fixed) return 0;
+    // per entry kEntryBytes plus a chunk's 65 scratch words per kListChunk
+    size_t e = (room - fixed) * kListChunk / (kEntryBytes * kListChunk + 65 * sizeof(uint32_t)) / 64 * 64;
+    while (e > 0 && entry_bytes(e, ns) > room) e -= 64;
+    return e;
+}
+
+// Capacity (in pairs) of the per-pair arrays that a frame with `pairs`
+// pairs and `entries` super-tile entries needs: the values in the last
+// array, the entries and the tile-list scratch in the other three.
+inline size_t pair_capacity_needed(size_t pairs, size_t entries, int W, int H) {
+    const size_t e = (entries + 63) / 64 * 64;
+    const size_t rest = (entry_bytes(e, super_count(W, H)) + 11) / 12;
+    size_t need = pairs > rest ? pairs : rest;
+    while (entry_capacity(need, W, H) < e) need += 64;  // rounding of entry_capacity
+    return need;
+}
 
 hipError_t ensure_gauss(FrameBuffers &b, size_t P);
 hipError_t ensure_pairs(FrameBuffers &b, size_t N);
@@ -92,9 +135,9 @@ DevScene to_dev(const fgs_scene &s);
 
 // Optional per-stage HIP events: 0..7 around the stages (0 before the
 // preprocess, 1 before the depth sort, 2 before the scan, 3 before the
-// emission, 4 before the tile sort, 5 before the ranges, 6 before the blend,
-// 7 after it), and kMarkCulled between a prepared scene's cull and the
-// preprocess (recorded right after 0 for raw parameters).
+// emission, 4 before the super-tile sort, 5 before the tile lists, 6 before
+// the blend, 7 after it), and kMarkCulled between a prepared scene's cull and
+// the preprocess (recorded right after 0 for raw parameters).
 constexpr int kMarkCulled = 8;
 constexpr int kStageMarks = 9;
 struct StageMarks {
@@ -156,12 +199,13 @@ struct PreparedBuffers {
 hipError_t build_prepared(const fgs_scene &sc, const fgs_options &op, PreparedBuffers &pb, hipStream_t s);
 void free_prepared(PreparedBuffers &pb);
 
-// Stages 2b to 4: key emission, stable tile sort, tile ranges and blending.
-// Every count is read on the device from fc, and every grid is sized by a
-// capacity, so the sequence holds no host dependency and can be captured in
-// a graph.  P bounds the visible count; fb.capN bounds the pair count.
-// Returns true if the sorted tile ids end in tk_a (else tk_b).
-// blend_variant: see launch_blend.
+// Stages 2b to 4: key emission (super-tile entries), their stable sort by
+// super-tile, the per-tile lists and ranges, and blending.  Every count is
+// read on the device from fc, and every grid is sized by a capacity, so the
+// sequence holds no host dependency and can be captured in a graph.  P
+// bounds the visible count; fb.capN bounds the pair count (and, through
+// entry_capacity, the entries).  The sorted values end in tv_b (returns
+// false: not in tv_a).  blend_variant: see launch_blend.
 bool enqueue_back(int W, int H, const DevOptions &op, uint32_t P, FrameBuffers &fb, ChunkList &ch, SortScratch &ss,
                   FrameCounters *fc, float *rgb, float *T, uint32_t *last, unsigned long long *work, hipStream_t s,
                   const StageMarks &mk, int blend_variant = 0);

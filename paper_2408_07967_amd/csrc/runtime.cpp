@@ -354,6 +354,7 @@ fgs_status render_impl(fgs_context *ctx, const fgs_scene *scene, const fgs_prepa
     uint32_t *Ldst = saved ? fb.last : out_last;
     unsigned long long *work = (ctx->instr & FGS_INSTR_WORK) ? ctx->work_dev : nullptr;
     uint32_t V = 0, N = 0, big = 0, ncand = 0;
+    size_t Ncap = 0;  // pair-array capacity the frame needs
     bool tiles_in_a = true;
     size_t spec_cap = 0;  // pair capacity of a second half already enqueued (0: none)
     for (int attempt = 0;; ++attempt) {
@@ -391,6 +392,7 @@ fgs_status render_impl(fgs_context *ctx, const fgs_scene *scene, const fgs_prepa
         }
         V = ctx->fc_host->visible;
         N = ctx->fc_host->pairs;
+        Ncap = pair_capacity_needed(N, ctx->fc_host->entries, W, H);
         big = ctx->fc_host->nchunks;
         ncand = prep ? ctx->fc_host->ncand : 0;
         break;
@@ -398,7 +400,7 @@ fgs_status render_impl(fgs_context *ctx, const fgs_scene *scene, const fgs_prepa
     if (plan) {
         FrameBuffers need;
         need.capP = (size_t)P;
-        need.capN = N;
+        need.capN = Ncap;
         need.capTiles = ntiles;
         ChunkList chunks_need;
         chunks_need.cap = std::max<size_t>((size_t)big + big / 8, 65536);
@@ -417,11 +419,11 @@ fgs_status render_impl(fgs_context *ctx, const fgs_scene *scene, const fgs_prepa
         }
         return FGS_OK;
     }
-    if (spec_cap == 0 || N > spec_cap) {
+    if (spec_cap == 0 || Ncap > spec_cap) {
         // no second half yet, or it ran out of pair buffer: grow the buffers
         // (after it has finished with them) and enqueue it again
         if (spec_cap) HIP_TRY(ctx, hipStreamSynchronize(s));
-        HIP_TRY(ctx, ensure_pairs(fb, N));
+        HIP_TRY(ctx, ensure_pairs(fb, Ncap));
         tiles_in_a = enqueue_back(W, H, dop, (uint32_t)P, fb, ctx->ch, ctx->ss, ctx->fc_dev, out_rgb, Tdst, Ldst,
                                   work, s, mk, ctx->blend_variant);
     }
@@ -443,11 +445,7 @@ fgs_status render_impl(fgs_context *ctx, const fgs_scene *scene, const fgs_prepa
     stt.tiles_y = tiles_y;
     stt.big_chunks = (int32_t)big;
     stt.candidates = prep ? (int64_t)ncand : (int64_t)P;
-    {
-        int b = 0;
-        while ((1ull << b) < (uint64_t)ntiles) ++b;
-        stt.sort_passes = 4 + (b + kRadixBits - 1) / kRadixBits;
-    }
+    stt.sort_passes = 4 + super_sort_passes(W, H);
     if (stats) *stats = stt;
 
     if (saved) {
@@ -539,6 +537,7 @@ bool carve_noalloc(unsigned char *base, size_t P, size_t ntiles, FrameBuffers &f
     ss.gsum = c.take<uint32_t>((size_t)kGsumSlots * kGsumWords);
     ss.sums = c.take<uint32_t>((size_t)kSortBlocks);
     fb.ranges = c.take<uint2>(ntiles);
+    fb.sranges = c.take<uint2>(ntiles);
     fb.capTiles = ntiles;
     const size_t capP = std::max<size_t>(P, 1);
     fb.gs = c.take<GaussState>(capP);
@@ -555,20 +554,20 @@ bool carve_noalloc(unsigned char *base, size_t P, size_t ntiles, FrameBuffers &f
     fb.seg_count = c.take<uint32_t>(kCullBlocks);
     fb.gmap = c.take<uint32_t>(capP);
     fb.capP = capP;
-    ch.cap = std::max<size_t>(P / 8, 8192);
+    ch.cap = (std::max<size_t>(P / 8, 8192) + kChunkCapAlign - 1) / kChunkCapAlign * kChunkCapAlign;
     ch.chunks = c.take<uint2>(ch.cap);
-    ch.hits = c.take<uint32_t>(ch.cap);
     ch.mask = c.take<uint32_t>(ch.cap * (kChunkTiles / 32));
+    ch.big = c.take<uint2>(ch.cap);
     fixed_bytes = c.used;
     if (c.overflow) return false;
-    // the rest: four pair arrays of equal capacity, each 256-byte aligned
+    // the rest: the four pair arrays of equal capacity, one block
     const size_t rest = FGS_NOALLOC_SCRATCH_BYTES - ((c.used + 255) & ~size_t(255));
-    const size_t capN = rest >= 4 * 256 ? (rest - 4 * 256) / (4 * sizeof(uint32_t)) : 0;
+    const size_t capN = rest / (4 * sizeof(uint32_t)) / 64 * 64;
     if (capN == 0) return false;
-    fb.tk_a = c.take<uint32_t>(capN);
-    fb.tk_b = c.take<uint32_t>(capN);
-    fb.tv_a = c.take<uint32_t>(capN);
-    fb.tv_b = c.take<uint32_t>(capN);
+    fb.tk_a = c.take<uint32_t>(4 * capN);
+    fb.tk_b = fb.tk_a + capN;
+    fb.tv_a = fb.tk_a + 2 * capN;
+    fb.tv_b = fb.tk_a + 3 * capN;
     fb.capN = capN;
     fb.pairs_owned = false;
     return !c.overflow;
@@ -631,18 +630,18 @@ fgs_status fgs_render_noalloc(fgs_context *ctx, const fgs_scene *scene, const fg
         stt.tiles_y = tiles_y;
         stt.big_chunks = (int32_t)h.nchunks;
         stt.candidates = P;
-        int b = 0;
-        while ((1ull << b) < (uint64_t)ntiles) ++b;
-        stt.sort_passes = 4 + (b + kRadixBits - 1) / kRadixBits;
+        stt.sort_passes = 4 + super_sort_passes(W, H);
         *stats = stt;
     }
     if (h.error & kErrChunkOverflow)
         return fail(ctx, FGS_ERR_CAPACITY, "the frame needs %u large-rectangle chunks; the fixed scratch holds %zu",
                     h.nchunks, ch.cap);
-    if ((size_t)h.pairs > fb.capN)
-        return fail(ctx, FGS_ERR_CAPACITY, "the frame has %u pairs; the fixed scratch holds %zu beside its %zu "
-                    "bytes of per-Gaussian, tile, sort and chunk buffers",
-                    h.pairs, fb.capN, fixed);
+    const size_t need = pair_capacity_needed(h.pairs, h.entries, W, H);
+    if (need > fb.capN)
+        return fail(ctx, FGS_ERR_CAPACITY, "the frame has %u pairs and %u super-tile entries, which need pair "
+                    "arrays of %zu; the fixed scratch holds %zu beside its %zu bytes of per-Gaussian, tile, sort and "
+                    "chunk buffers",
+                    h.pairs, h.entries, need, fb.capN, fixed);
     return FGS_OK;
 }
 
@@ -828,13 +827,14 @@ fgs_status fgs_render_prepared_batch(fgs_context *ctx, const fgs_prepared *p, co
     for (int c = 0; c < ncams; ++c) {
         auto &bc = ctx->batch[c];
         const uint32_t N = ctx->bfc_host[c].pairs;
-        if (spec_cap[c] == 0 || N > spec_cap[c]) {
+        const size_t Ncap = pair_capacity_needed(N, ctx->bfc_host[c].entries, W, H);
+        if (spec_cap[c] == 0 || Ncap > spec_cap[c]) {
             // no second half yet, or it ran out of pair buffer: grow the
             // buffers (once every enqueued half has finished: s has joined
             // the side stream) and enqueue it on s
             if (!synced) HIP_TRY(ctx, hipStreamSynchronize(s));
             synced = true;
-            HIP_TRY(ctx, ensure_pairs(bc.fb, N));
+            HIP_TRY(ctx, ensure_pairs(bc.fb, Ncap));
             (void)enqueue_back(W, H, dop, (uint32_t)P, bc.fb, bc.ch, bc.ss, ctx->bfc_dev + c, out_rgb[c],
                                out_T ? out_T[c] : nullptr, out_last ? out_last[c] : nullptr, nullptr, s, nomk,
                                ctx->blend_variant);
@@ -847,9 +847,7 @@ fgs_status fgs_render_prepared_batch(fgs_context *ctx, const fgs_prepared *p, co
             stt.tiles_y = tiles_y;
             stt.big_chunks = (int32_t)ctx->bfc_host[c].nchunks;
             stt.candidates = (int64_t)ctx->bfc_host[c].ncand;
-            int b = 0;
-            while ((1ull << b) < (uint64_t)ntiles) ++b;
-            stt.sort_passes = 4 + (b + kRadixBits - 1) / kRadixBits;
+            stt.sort_passes = 4 + super_sort_passes(W, H);
             stats[c] = stt;
         }
     }
@@ -922,8 +920,8 @@ fgs_status fgs_frame_download(fgs_context *ctx, const fgs_frame *f, fgs_field fi
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     HIP_TRY(ctx, hipStreamSynchronize(f->stream));
     if (field == FGS_FIELD_TILES) {
-        // the sort's last pass records the tile ranges, not the sorted tile
-        // ids: the id of pair i is the tile whose range holds i
+        // the tile lists keep only their ranges, not the tile id of each
+        // pair: the id of pair i is the tile whose range holds i
         const size_t tiles = (size_t)f->stats.tiles_x * f->stats.tiles_y;
         std::vector<uint2> rg(tiles);
         HIP_TRY(ctx, hipMemcpy(rg.data(), b.ranges, tiles * sizeof(uint2), hipMemcpyDeviceToHost));
@@ -979,7 +977,7 @@ fgs_status fgs_frame_download(fgs_context *ctx, const fgs_frame *f, fgs_field fi
     }
     HIP_TRY(ctx, hipMemcpy(host_dst, src, bytes, hipMemcpyDeviceToHost));
     if (field == FGS_FIELD_RANGES) {
-        // an empty tile may hold start > end on the device; report (0, 0)
+        // an empty tile holds start == end on the device; report (0, 0)
         uint2 *r = static_cast<uint2 *>(host_dst);
         for (size_t t = 0; t < bytes / sizeof(uint2); ++t)
             if (r[t].x >= r[t].y) r[t] = make_uint2(0u, 0u);

@@ -93,6 +93,7 @@ struct Slot {
     int bypassed = 0;
     int64_t start_ns = 0, admit_ns = 0, done_ns = 0;
     uint32_t V = 0, N = 0;
+    size_t Ncap = 0;  // pair-array capacity the request needs (pairs and super-tile entries)
 };
 
 }  // namespace
@@ -158,13 +159,13 @@ void point_pairs(fgs_server *srv, Slot &s) {
     s.fb.pairs_owned = false;
 }
 
-size_t bytes_for_pairs(uint32_t N) { return align_up(16 * ((size_t)N + (size_t)N / 8 + 4096)); }
+size_t bytes_for_pairs(size_t N) { return align_up(16 * (N + N / 8 + 4096)); }
 
-// Try to give slot s a region for its N pairs; evicts cached regions of
+// Try to give slot s a region for its pairs and entries (Ncap); evicts cached regions of
 // slots that are not blending.  Returns false if the budget cannot hold it now.
 bool ensure_region(fgs_server *srv, Slot &s) {
-    if (s.has_region && s.reg_bytes / 16 >= (size_t)s.N + 64) return true;
-    const size_t need = bytes_for_pairs(s.N);
+    if (s.has_region && s.reg_bytes / 16 >= s.Ncap + 64) return true;
+    const size_t need = bytes_for_pairs(s.Ncap);
     drop_region(srv, s);
     size_t off = 0;
     bool ok = srv->arena.alloc(need, &off);
@@ -288,8 +289,9 @@ hipError_t start_back(fgs_server *srv, Slot &s) {
     return hipSuccess;
 }
 
-// Pairs a slot's region holds (the admission criterion of ensure_region).
-bool region_fits(const Slot &s) { return s.has_region && s.reg_bytes / 16 >= (size_t)s.N + 64; }
+// Whether a slot's region holds its pairs and entries (the admission criterion
+// of ensure_region).
+bool region_fits(const Slot &s) { return s.has_region && s.reg_bytes / 16 >= s.Ncap + 64; }
 
 // A slot that kept its pair region from an earlier request enqueues the
 // second half right behind the first (as fgs_render does): its kernels read
@@ -448,13 +450,14 @@ void worker_main(fgs_server *srv) {
             }
             s.V = s.fc_host->visible;
             s.N = s.fc_host->pairs;
+            s.Ncap = pair_capacity_needed(s.N, s.fc_host->entries, s.req.W, s.req.H);
             if (s.spec && region_fits(s)) {
                 // the second half enqueued with the first holds every pair
                 s.spec = false;
                 s.state = SlotState::BACK;
                 continue;
             }
-            if (bytes_for_pairs(s.N) > srv->arena.size()) {
+            if (bytes_for_pairs(s.Ncap) > srv->arena.size()) {
                 if (s.spec) (void)hipEventSynchronize(s.evB);  // the region is in use until then
                 s.spec = false;
                 finish(srv, s, FGS_ERR_CAPACITY);  // can never fit the budget

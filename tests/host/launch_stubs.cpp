@@ -49,22 +49,24 @@ void launch_depth_ties(const uint32_t *, uint32_t *, const uint32_t *, uint32_t,
     reached("depth_ties");
 }
 void launch_big_count(int, int, int, const GaussState *, const float4 *, const uint4 *, const uint2 *, uint32_t,
-                      uint32_t *, uint32_t *, uint32_t *, const FrameCounters *, hipStream_t) {
+                      uint32_t *, uint32_t *, FrameCounters *, hipStream_t) {
     reached("big_count");
 }
-void launch_emit(int, int, const uint32_t *, uint32_t, const uint32_t *, const uint32_t *, uint4 *, void *, int,
-                 uint32_t *, uint32_t, uint2 *, uint32_t, uint32_t *, hipStream_t) {
-    reached("emit");
+void launch_super_emit(int, int, const uint32_t *, uint32_t, const uint32_t *, const uint32_t *, const uint4 *,
+                       uint32_t, const uint2 *, uint2 *, const uint32_t *, uint32_t, const FrameCounters *, uint16_t *,
+                       uint32_t *, uint64_t *, uint32_t, uint2 *, uint32_t, uint32_t *, hipStream_t) {
+    reached("super_emit");
 }
-void launch_big_emit(int, const uint4 *, const uint2 *, uint32_t, const uint32_t *, const uint32_t *, void *, int,
-                     uint32_t *, uint32_t, const FrameCounters *, hipStream_t) {
-    reached("big_emit");
+void launch_tile_lists(int, int, const uint2 *, const uint32_t *, const uint64_t *, uint32_t, uint32_t *, uint2 *,
+                       uint32_t *, uint32_t, hipStream_t) {
+    reached("tile_lists");
 }
 void launch_radix_pass(const void *, const uint32_t *, void *, uint32_t *, uint32_t, const uint32_t *, int, int, bool,
-                       bool, uint32_t *, uint32_t *, uint32_t *, hipStream_t, uint2 *, uint32_t, int) {
+                       bool, uint32_t *, uint32_t *, uint32_t *, hipStream_t, uint2 *, uint32_t, int, const uint64_t *,
+                       uint64_t *) {
     reached("radix_pass");
 }
-void launch_count_scan(const uint32_t *, const uint8_t *, const uint32_t *, uint32_t, const uint32_t *, uint32_t *,
+void launch_count_scan(const uint32_t *, const uint8_t *, const uint4 *, uint32_t, const uint32_t *, uint32_t *,
                        uint32_t *, uint32_t *, uint32_t *, hipStream_t) {
     reached("count_scan");
 }

@@ -6,8 +6,8 @@ the stated bar (|diff| <= 2e-3 on >= 99.9 % of pixels, mean |diff| <= 1e-5).
 
 * 10M-Gaussian city scene at 3840x2160 (the timed workload), from the
   prepared scene and from the raw parameters (which must agree bit for bit);
-* the same scene at 7680x4320 (the stress case: 129,600 tiles, so tile ids
-  travel as uint32 through three sort passes);
+* the same scene at 7680x4320 (the stress case: 129,600 tiles in 2040
+  super-tiles, whose ids are sorted in two passes);
 * the 1M-Gaussian orbit scene at 1920x1080 through all eight orbit cameras,
   one request at a time.
 
@@ -106,11 +106,11 @@ def test_city_10M_4k_prepared_full_size(orc, scenes):
 
 @pytest.mark.timeout(900)
 def test_city_10M_8k_full_size(orc, scenes):
-    """The 7680x4320 stress case: 129,600 tiles (> 65,536), so the tile ids
-    are sorted as uint32 in three passes."""
+    """The 7680x4320 stress case: 129,600 tiles (> 65,536) in 2040
+    super-tiles, whose ids are sorted in two passes."""
     _gpu()
     g = _city(orc, scenes, 7680, 4320, both_paths=False)
-    assert g["stats"]["sort_passes"] == 4 + 3
+    assert g["stats"]["sort_passes"] == 4 + 2
 
 
 @pytest.mark.timeout(600)

@@ -84,7 +84,7 @@ def test_noalloc_refuses_what_does_not_fit(R):
     assert status == B.FGS_ERR_CAPACITY and "fixed scratch" in msg
     # more pairs than the pair arrays hold: refused after the frame's counters
     # (150k Gaussians of about 30 tiles each: 4.4M pairs against room for
-    # about 2.9M; 7.4k large-rectangle chunks, within the chunk list)
+    # about 2.7M; 7.4k large-rectangle chunks, within the chunk list)
     many = random_scene(rng, 150_000, ls_mu=-2.9, ls_sigma=0.3, sh_degree=0)
     cam = identity_camera(1024, 1024, 900.0)
     status, *_ = _noalloc(R, GaussianScene.from_numpy(many), cam, 1024, 1024, opts())
