@@ -13,6 +13,8 @@ constexpr int kSortItems = 16;     // keys per thread in a sort pass
 constexpr int kSortTile = kBlock * kSortItems;  // keys per sort workgroup
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
+constexpr int kRadixBitsMax = 9;  // a single pass may take a 9-bit digit
+constexpr int kRadixMax = 1 << kRadixBitsMax;
 constexpr uint32_t kInvalidKey = 0xffffffffu;
 
 // Camera and options passed by value: they land in the kernel-argument
@@ -146,10 +148,10 @@ constexpr uint32_t kErrChunkOverflow = 2u;       // chunk list too small: render
 constexpr int kSortBlocks = 1024;
 constexpr int kSortGroup = 32;
 constexpr int kSortGroups = (kSortBlocks + kSortGroup - 1) / kSortGroup;
-// Group sums of one pass: kSortGroups x kRadix counters.  Every pass of a
-// frame has its own (4 depth passes, up to 4 tile passes), cleared by the
-// kernel that runs before the pass.
-constexpr int kGsumWords = kSortGroups * kRadix;
+// Group sums of one pass: kSortGroups x (up to kRadixMax) counters.  Every
+// pass of a frame has its own (4 depth passes, up to 4 tile passes), cleared
+// by the kernel that runs before the pass.
+constexpr int kGsumWords = kSortGroups * kRadixMax;
 constexpr int kGsumSlots = 8;
 
 unsigned preprocess_grid(int64_t P);
@@ -304,13 +306,14 @@ void launch_tile_lists(int W, int H, const uint2 *sranges, const uint32_t *gidx,
                        hipStream_t s);
 
 // One stable LSD radix pass of (key, value) pairs by the digit
-// (key >> shift) & ((1 << bits) - 1), bits <= 8.
+// (key >> shift) & ((1 << bits) - 1), bits <= kRadixBitsMax (9 only for
+// 16-bit keys with a payload).
 //   n_host  upper bound on the number of keys; n_dev: if non-null, the
 //           actual count is read there on the device
 //   vals_in null: values are the input positions
 //   filter  drop keys equal to kInvalidKey
-//   hist    scratch [kSortBlocks][kRadix]
-//   gsum    [kSortGroups][kRadix], zero on entry: the upsweep adds each
+//   hist    scratch [kSortBlocks][kRadixMax]
+//   gsum    [kSortGroups][kRadixMax], zero on entry: the upsweep adds each
 //           workgroup's histogram into its group's row (so no separate group
 //           kernel runs); gsum_next, if non-null, is cleared by the downsweep
 //           for the next pass
@@ -323,11 +326,15 @@ void launch_tile_lists(int W, int H, const uint2 *sranges, const uint32_t *gidx,
 //   mask_in if non-null (16-bit keys only): the payload (vals_in[i],
 //           mask_in[i]) travels with key i to (vals_out, mask_out); it is
 //           read at its destination's store, from the workgroup's tile
+//   whole_key (with a payload and run_ends): the digit is the whole key
+//           (shift 0, keys < 2^bits), so each key's run is its digit's
+//           range, written by the first workgroup from the digit offsets
+//           (every key < nruns gets it, an absent key start == end)
 void launch_radix_pass(const void *keys_in, const uint32_t *vals_in, void *keys_out, uint32_t *vals_out,
                        uint32_t n_host, const uint32_t *n_dev, int shift, int bits, bool filter, bool write_keys,
                        uint32_t *hist, uint32_t *gsum, uint32_t *gsum_next, hipStream_t s,
                        uint2 *run_ends = nullptr, uint32_t nruns = 0, int key_bytes = 4,
-                       const uint64_t *mask_in = nullptr, uint64_t *mask_out = nullptr);
+                       const uint64_t *mask_in = nullptr, uint64_t *mask_out = nullptr, bool whole_key = false);
 
 // offsets[r] = sum of count[order[r']] for r' < r over the n visible
 // Gaussians (n_dev, bounded by n_host); offsets[n] and *total get the total.

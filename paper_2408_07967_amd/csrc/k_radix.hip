@@ -67,13 +67,22 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *s
     return wpre + x - v;
 }
 
-template <bool kFilter, class KeyT>
+// kDB: digit bits the pass may take (8, or 9 for a one-pass sort of up to
+// 512 keys); each thread owns kDigitsPerThread consecutive digits.
+template <int kDB>
+constexpr int digits_per_thread() {
+    return (1 << kDB) / kBlock;
+}
+
+template <bool kFilter, class KeyT, int kDB = kRadixBits>
 __global__ __launch_bounds__(kBlock) void k_radix_upsweep(const KeyT *__restrict__ keys, uint32_t n_host,
                                                           const uint32_t *n_dev, int shift, int bits,
                                                           uint32_t *__restrict__ hist, uint32_t *gsum) {
-    __shared__ uint32_t s_h[kWaves][kRadix];
+    constexpr int kR = 1 << kDB, kP = digits_per_thread<kDB>();
+    static_assert(kP >= 1 && kR <= kRadixMax, "digit width");
+    __shared__ uint32_t s_h[kWaves][kR];
     const int tid = threadIdx.x, wave = tid / kWave;
-    for (int i = tid; i < kWaves * kRadix; i += kBlock) (&s_h[0][0])[i] = 0;
+    for (int i = tid; i < kWaves * kR; i += kBlock) (&s_h[0][0])[i] = 0;
     __syncthreads();
     const uint32_t n = count_of(n_host, n_dev);
     uint32_t lo, hi;
@@ -108,20 +117,25 @@ __global__ __launch_bounds__(kBlock) void k_radix_upsweep(const KeyT *__restrict
         }
     }
     __syncthreads();
-    const uint32_t h = s_h[0][tid] + s_h[1][tid] + s_h[2][tid] + s_h[3][tid];
-    hist[(size_t)blockIdx.x * kRadix + tid] = h;
-    if (h) atomicAdd(&gsum[(size_t)(blockIdx.x / kSortGroup) * kRadix + tid], h);
+#pragma unroll
+    for (int q = 0; q < kP; ++q) {
+        const int d = tid * kP + q;
+        const uint32_t h = s_h[0][d] + s_h[1][d] + s_h[2][d] + s_h[3][d];
+        hist[(size_t)blockIdx.x * kR + d] = h;
+        if (h) atomicAdd(&gsum[(size_t)(blockIdx.x / kSortGroup) * kR + d], h);
+    }
 }
 
 static_assert(kSortBlocks % kSortGroup == 0, "whole groups of workgroups");
 
 // (LDS holds four workgroups per CU, so registers are capped at what four
-// waves per SIMD allow.)
+// waves per SIMD allow; a 9-bit pass, whose digit bookkeeping needs more,
+// at what three allow.)
 // kPayload: the values are the input positions while ranking (as with
 // kIdentityVals), and each element's payload (vals_in, mask_in at that
 // position, inside the workgroup's tile) is read when it is stored.
-template <bool kIdentityVals, bool kFilter, bool kWriteKeys, class KeyT, bool kPayload = false>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_radix_downsweep(const KeyT *__restrict__ keys_in,
+template <bool kIdentityVals, bool kFilter, bool kWriteKeys, class KeyT, bool kPayload = false, int kDB = kRadixBits>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kDB > kRadixBits ? 3 : 4))) void k_radix_downsweep(const KeyT *__restrict__ keys_in,
                                                             const uint32_t *__restrict__ vals_in,
                                                             KeyT *__restrict__ keys_out,
                                                             uint32_t *__restrict__ vals_out, uint32_t n_host,
@@ -131,15 +145,18 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                                                             uint32_t *__restrict__ gsum_next,
                                                             uint32_t *__restrict__ run_end, uint32_t nruns,
                                                             const uint64_t *__restrict__ mask_in,
-                                                            uint64_t *__restrict__ mask_out) {
+                                                            uint64_t *__restrict__ mask_out,
+                                                            uint32_t *__restrict__ digit_run) {
     static_assert(!kPayload || kIdentityVals, "a payload is ranked by position");
+    constexpr int kR = 1 << kDB, kP = digits_per_thread<kDB>();
+    static_assert(kP >= 1 && kR <= kRadixMax, "digit width");
     // (per-wave and per-tile digit counts are at most kSortTile: 16 bits)
     __shared__ KeyT s_keys[kSortTile];
     __shared__ uint32_t s_vals[kSortTile];
-    __shared__ uint16_t s_wave[kWaves][kRadix];
-    __shared__ uint32_t s_off[kRadix];
-    __shared__ uint16_t s_excl[kRadix + 1];
-    __shared__ uint32_t s_gbase[kRadix];  // output position of tile element j of digit d: s_gbase[d] + j
+    __shared__ uint16_t s_wave[kWaves][kR];
+    __shared__ uint32_t s_off[kR];
+    __shared__ uint16_t s_excl[kR + 1];
+    __shared__ uint32_t s_gbase[kR];  // output position of tile element j of digit d: s_gbase[d] + j
     __shared__ uint32_t s_tmp[kWaves];
     __shared__ uint32_t s_nv;
 
@@ -152,31 +169,60 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     uint32_t lo, hi;
     block_range(n, b, nb, &lo, &hi);
 
-    // global offset of this workgroup's first key of digit tid: every group
-    // sum and every earlier histogram row of the group is loaded at once (a
-    // fixed, unrolled trip count keeps all the loads in flight together)
+    // global offset of this workgroup's first key of each of the thread's
+    // digits: every group sum and every earlier histogram row of the group is
+    // loaded at once per digit (a fixed, unrolled trip count keeps all the
+    // loads in flight together)
     {
         constexpr uint32_t kGroups = kSortGroups;
         const uint32_t mygroup = b / kSortGroup;
-        uint32_t gv[kGroups], hv[kSortGroup];
+        uint32_t dtot[kP], dbefore[kP], own = 0;
 #pragma unroll
-        for (uint32_t w = 0; w < kGroups; ++w) gv[w] = gsum[(size_t)w * kRadix + tid];
+        for (int q = 0; q < kP; ++q) dtot[q] = dbefore[q] = 0;
+        // the group sums of the thread's digits, then the earlier rows of its
+        // group (each phase's loads issued together)
+        {
+            uint32_t gv[kGroups][kP];
 #pragma unroll
-        for (uint32_t r = 0; r < (uint32_t)kSortGroup; ++r) {
-            const uint32_t row = mygroup * kSortGroup + r;
-            hv[r] = row < b ? hist[(size_t)row * kRadix + tid] : 0u;
+            for (uint32_t w = 0; w < kGroups; ++w)
+#pragma unroll
+                for (int q = 0; q < kP; ++q) gv[w][q] = gsum[(size_t)w * kR + tid * kP + q];
+#pragma unroll
+            for (uint32_t w = 0; w < kGroups; ++w)
+#pragma unroll
+                for (int q = 0; q < kP; ++q) {
+                    dtot[q] += gv[w][q];
+                    dbefore[q] += (w < mygroup) ? gv[w][q] : 0u;
+                }
         }
-        uint32_t total = 0, before = 0;
+        {
+            uint32_t hv[kSortGroup][kP];
 #pragma unroll
-        for (uint32_t w = 0; w < kGroups; ++w) {
-            total += gv[w];
-            before += (w < mygroup) ? gv[w] : 0u;
+            for (uint32_t r = 0; r < (uint32_t)kSortGroup; ++r) {
+                const uint32_t row = mygroup * kSortGroup + r;
+#pragma unroll
+                for (int q = 0; q < kP; ++q) hv[r][q] = row < b ? hist[(size_t)row * kR + tid * kP + q] : 0u;
+            }
+#pragma unroll
+            for (uint32_t r = 0; r < (uint32_t)kSortGroup; ++r)
+#pragma unroll
+                for (int q = 0; q < kP; ++q) dbefore[q] += hv[r][q];
         }
 #pragma unroll
-        for (uint32_t r = 0; r < (uint32_t)kSortGroup; ++r) before += hv[r];
+        for (int q = 0; q < kP; ++q) own += dtot[q];
         uint32_t all = 0;
-        const uint32_t dbase = block_exclusive_scan(total, s_tmp, &all);
-        s_off[tid] = dbase + before;
+        uint32_t dbase = block_exclusive_scan(own, s_tmp, &all);
+#pragma unroll
+        for (int q = 0; q < kP; ++q) {
+            const uint32_t d = (uint32_t)(tid * kP + q);
+            s_off[d] = dbase + dbefore[q];
+            // a pass by the whole key: digit d's run is [its offset, + its total)
+            if (digit_run && b == 0 && d < nruns) {
+                digit_run[2 * (size_t)d] = dbase;
+                digit_run[2 * (size_t)d + 1] = dbase + dtot[q];
+            }
+            dbase += dtot[q];
+        }
     }
     if (lo >= hi) return;  // uniform: no tile for this workgroup
 
@@ -184,7 +230,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     // A tile's loads are all issued before any use, and the next tile's are
     // issued as soon as the current one sits in LDS, so that they are in
     // flight while the current tile is written out.
-    uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+    // (identity values are the input positions, computed where they are
+    // staged rather than held in registers)
+    uint32_t key[kSortItems], val[kIdentityVals ? 1 : kSortItems], rank[kSortItems];
     auto load_tile = [&](uint32_t t) {
         const uint32_t base = t + (uint32_t)wave * (kSortItems * kWave);
 #pragma unroll
@@ -192,12 +240,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             const uint32_t idx = base + (uint32_t)(i * kWave + lane);
             const bool in = idx < hi;
             key[i] = in ? (uint32_t)keys_in[idx] : kInvalidKey;
-            val[i] = kIdentityVals ? idx : (in ? vals_in[idx] : 0u);
+            if constexpr (!kIdentityVals) val[i] = in ? vals_in[idx] : 0u;
         }
     };
     load_tile(lo);
     for (uint32_t t0 = lo; t0 < hi; t0 += kSortTile) {
-        for (int i = tid; i < kWaves * kRadix; i += kBlock) (&s_wave[0][0])[i] = 0;
+        for (int i = tid; i < kWaves * kR; i += kBlock) (&s_wave[0][0])[i] = 0;
         __syncthreads();
         const uint32_t base = t0 + (uint32_t)wave * (kSortItems * kWave);
 #pragma unroll
@@ -210,14 +258,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             // lanes of this step with the same digit (stable rank = lower
             // lanes): a lane differs from this one where some digit bit
             // disagrees, i.e. where ballot(bit) xor (own bit, widened) is
-            // set.  The pass's `bits` digit bits are matched (a uniform
-            // branch skips the rest).  Per bit: one bitfield extract, one
+            // set.  All kDB bits are matched (a narrower digit has zero high
+            // bits in every lane).  Per bit: one bitfield extract, one
             // compare and one three-input logic op per half mask
             // (bitop3 table 0xf6 = src0 | (src1 ^ src2)).
             uint32_t diff_lo = 0, diff_hi = 0;
 #pragma unroll
-            for (int bb = 0; bb < kRadixBits; ++bb) {
-                if (bb >= bits) break;
+            for (int bb = 0; bb < kDB; ++bb) {
                 // bit bb of d widened to 0 or ~0 by one signed bitfield extract
                 // (written out: the compiler otherwise splits it into two shifts)
                 uint32_t t;
@@ -237,20 +284,32 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             rank[i] = ok ? prev + before : 0xffffffffu;
         }
         __syncthreads();
-        // thread tid owns digit tid: per-wave counts -> exclusive over waves
-        const uint32_t c0 = s_wave[0][tid], c1 = s_wave[1][tid], c2 = s_wave[2][tid], c3 = s_wave[3][tid];
-        s_wave[0][tid] = 0;
-        s_wave[1][tid] = c0;
-        s_wave[2][tid] = c0 + c1;
-        s_wave[3][tid] = c0 + c1 + c2;
-        const uint32_t dsum = c0 + c1 + c2 + c3;
+        // thread tid owns digits tid kP ... tid kP + kP - 1: per-wave counts
+        // -> exclusive over waves
+        uint32_t dsum[kP], own = 0;
+#pragma unroll
+        for (int q = 0; q < kP; ++q) {
+            const int d = tid * kP + q;
+            const uint32_t c0 = s_wave[0][d], c1 = s_wave[1][d], c2 = s_wave[2][d], c3 = s_wave[3][d];
+            s_wave[0][d] = 0;
+            s_wave[1][d] = c0;
+            s_wave[2][d] = c0 + c1;
+            s_wave[3][d] = c0 + c1 + c2;
+            dsum[q] = c0 + c1 + c2 + c3;
+            own += dsum[q];
+        }
         uint32_t nvalid = 0;
-        const uint32_t excl = block_exclusive_scan(dsum, s_tmp, &nvalid);
-        s_excl[tid] = (uint16_t)excl;
-        s_gbase[tid] = s_off[tid] - excl;
+        uint32_t excl = block_exclusive_scan(own, s_tmp, &nvalid);
+#pragma unroll
+        for (int q = 0; q < kP; ++q) {
+            const int d = tid * kP + q;
+            s_excl[d] = (uint16_t)excl;
+            s_gbase[d] = s_off[d] - excl;
+            excl += dsum[q];
+        }
         if (tid == 0) {
             s_nv = nvalid;
-            s_excl[kRadix] = (uint16_t)nvalid;
+            s_excl[kR] = (uint16_t)nvalid;
         }
         __syncthreads();
 #pragma unroll
@@ -259,7 +318,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 const uint32_t d = (key[i] >> shift) & dmask;
                 const uint32_t lp = s_excl[d] + s_wave[wave][d] + rank[i];
                 s_keys[lp] = (KeyT)key[i];
-                s_vals[lp] = val[i];
+                if constexpr (kIdentityVals)
+                    s_vals[lp] = t0 + (uint32_t)wave * (kSortItems * kWave) + (uint32_t)(i * kWave + lane);
+                else
+                    s_vals[lp] = val[i];
             }
         }
         if (t0 + kSortTile < hi) load_tile(t0 + kSortTile);
@@ -288,7 +350,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             }
         }
         __syncthreads();
-        s_off[tid] += dsum;
+#pragma unroll
+        for (int q = 0; q < kP; ++q) s_off[tid * kP + q] += dsum[q];
     }
 }
 
@@ -605,13 +668,17 @@ __global__ __launch_bounds__(kBlock) void k_depth_long_ties(const uint32_t *__re
 void launch_radix_pass(const void *keys_in, const uint32_t *vals_in, void *keys_out, uint32_t *vals_out,
                        uint32_t n_host, const uint32_t *n_dev, int shift, int bits, bool filter, bool write_keys,
                        uint32_t *hist, uint32_t *gsum, uint32_t *gsum_next, hipStream_t s, uint2 *run_ends,
-                       uint32_t nruns, int key_bytes, const uint64_t *mask_in, uint64_t *mask_out) {
+                       uint32_t nruns, int key_bytes, const uint64_t *mask_in, uint64_t *mask_out, bool whole_key) {
     if (n_host == 0) return;
     const unsigned nb = kSortBlocks;
     const bool k16 = key_bytes == 2;
     const uint32_t *k32i = static_cast<const uint32_t *>(keys_in);
     const uint16_t *k16i = static_cast<const uint16_t *>(keys_in);
-    if (k16)
+    const bool wide = bits > kRadixBits;  // a 9-bit digit: 16-bit keys with a payload only
+    if (k16 && wide)
+        hipLaunchKernelGGL((k_radix_upsweep<false, uint16_t, kRadixBitsMax>), dim3(nb), dim3(kBlock), 0, s, k16i,
+                           n_host, n_dev, shift, bits, hist, gsum);
+    else if (k16)
         hipLaunchKernelGGL((k_radix_upsweep<false, uint16_t>), dim3(nb), dim3(kBlock), 0, s, k16i, n_host, n_dev,
                            shift, bits, hist, gsum);
     else if (filter)
@@ -625,14 +692,18 @@ void launch_radix_pass(const void *keys_in, const uint32_t *vals_in, void *keys_
 #define FGS_DS(I, F, K, T)                                                                                          \
     hipLaunchKernelGGL((k_radix_downsweep<I, F, K, T>), dim3(nb), dim3(kBlock), 0, s, static_cast<const T *>(keys_in), \
                        vals_in, static_cast<T *>(keys_out), vals_out, n_host, n_dev, shift, bits, hist, gsum,         \
-                       gsum_next, ends, nruns, nullptr, nullptr)
-#define FGS_DSP(K)                                                                                                  \
-    hipLaunchKernelGGL((k_radix_downsweep<true, false, K, uint16_t, true>), dim3(nb), dim3(kBlock), 0, s,         \
+                       gsum_next, ends, nruns, nullptr, nullptr, nullptr)
+#define FGS_DSP(K, DB)                                                                                              \
+    hipLaunchKernelGGL((k_radix_downsweep<true, false, K, uint16_t, true, DB>), dim3(nb), dim3(kBlock), 0, s,     \
                        static_cast<const uint16_t *>(keys_in), vals_in, static_cast<uint16_t *>(keys_out), vals_out,   \
-                       n_host, n_dev, shift, bits, hist, gsum, gsum_next, ends, nruns, mask_in, mask_out)
-    // 16-bit keys with a payload: the super-tile passes
-    if (k16 && mask_in && write_keys) FGS_DSP(true);
-    else if (k16 && mask_in) FGS_DSP(false);
+                       n_host, n_dev, shift, bits, hist, gsum, gsum_next, whole_key ? nullptr : ends, nruns, mask_in,  \
+                       mask_out, whole_key ? ends : nullptr)
+    // 16-bit keys with a payload: the super-tile passes (one 9-bit pass
+    // sorts up to 512 super-tiles)
+    if (k16 && mask_in && wide && write_keys) FGS_DSP(true, kRadixBitsMax);
+    else if (k16 && mask_in && wide) FGS_DSP(false, kRadixBitsMax);
+    else if (k16 && mask_in && write_keys) FGS_DSP(true, kRadixBits);
+    else if (k16 && mask_in) FGS_DSP(false, kRadixBits);
     // 16-bit keys: unfiltered, explicit values
     else if (k16 && write_keys) FGS_DS(false, false, true, uint16_t);
     else if (k16) FGS_DS(false, false, false, uint16_t);

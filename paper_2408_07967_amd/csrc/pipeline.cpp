@@ -46,9 +46,15 @@ int ceil_log2(uint64_t x) {
     return b;
 }
 
-// Split `bits` tile-id bits into passes of at most kRadixBits each.
+// Split `bits` key bits into passes: one pass of up to kRadixBitsMax bits,
+// else passes of at most kRadixBits each.
 int plan_tile_passes(int bits, int *shift, int *width) {
     if (bits <= 0) return 0;
+    if (bits <= kRadixBitsMax) {
+        shift[0] = 0;
+        width[0] = bits;
+        return 1;
+    }
     const int np = (bits + kRadixBits - 1) / kRadixBits;
     int s = 0;
     for (int p = 0; p < np; ++p) {
@@ -113,7 +119,7 @@ hipError_t ensure_pixels(FrameBuffers &b, size_t pix) {
 
 hipError_t ensure_sort_scratch(SortScratch &s) {
     if (s.rhist) return hipSuccess;
-    FGS_GROW(s.rhist, (size_t)kSortBlocks * kRadix);
+    FGS_GROW(s.rhist, (size_t)kSortBlocks * kRadixMax);
     FGS_GROW(s.gsum, (size_t)kGsumSlots * kGsumWords);
     FGS_GROW(s.sums, (size_t)kSortBlocks);
     return hipSuccess;
@@ -400,7 +406,7 @@ bool enqueue_back(int W, int H, const DevOptions &op, uint32_t P, FrameBuffers &
     const int npass = plan_tile_passes(ceil_log2(nsuper), shifts, widths);
     // the emission also sets every super-tile's range empty when a sort pass
     // records the ranges (one super-tile: no pass, its range holds every entry)
-    static_assert(kGsumSlots >= 4 + 2, "four depth and up to two super-tile passes");
+    static_assert(kGsumSlots >= 4 + 2, "four depth and up to two super-tile passes (ids < 65536)");
     launch_super_emit(W, H, fb.dv_a, P, &fc->visible, fb.offsets, fb.erec, (uint32_t)std::min<size_t>(fb.capP, 0xffffffffu),
                       ch.chunks, ch.big, ch.mask, chunk_cap, fc, skey_a, gidx_a, mask_a, ecap,
                       npass > 0 ? fb.sranges : nullptr, nsuper, npass > 0 ? ss.slot(4) : nullptr, s);
@@ -415,7 +421,7 @@ bool enqueue_back(int W, int H, const DevOptions &op, uint32_t P, FrameBuffers &
         const bool last_pass = p + 1 == npass;
         launch_radix_pass(ki, vi, ko, vo, ecap, &fc->entries, shifts[p], widths[p], false, !last_pass, ss.rhist,
                           ss.slot(4 + p), last_pass ? nullptr : ss.slot(5 + p), s, last_pass ? fb.sranges : nullptr,
-                          nsuper, 2, mi, mo);
+                          nsuper, 2, mi, mo, npass == 1);
         std::swap(ki, ko);
         std::swap(vi, vo);
         std::swap(mi, mo);

@@ -54,7 +54,7 @@ struct SortScratch {
     uint32_t *rhist = nullptr, *gsum = nullptr, *sums = nullptr;  // gsum: kGsumSlots slots of kGsumWords
     uint32_t *slot(int i) const { return gsum + (size_t)i * kGsumWords; }
     static size_t bytes() {
-        return ((size_t)kSortBlocks * kRadix + (size_t)kGsumSlots * kGsumWords + kSortBlocks) * sizeof(uint32_t);
+        return ((size_t)kSortBlocks * kRadixMax + (size_t)kGsumSlots * kGsumWords + kSortBlocks) * sizeof(uint32_t);
     }
 };
 
@@ -72,11 +72,12 @@ struct ChunkList {
 inline uint32_t super_tiles_x(int W) { return (uint32_t)((((W + kTile - 1) / kTile) + kSuper - 1) >> kSuperShift); }
 inline uint32_t super_count(int W, int H) { return super_tiles_x(W) * super_tiles_x(H); }
 
-// Passes of the entries' sort by super-tile id (kRadixBits per pass).
+// Passes of the entries' sort by super-tile id: one for up to
+// kRadixBitsMax bits, else kRadixBits per pass.
 inline int super_sort_passes(int W, int H) {
     int b = 0;
     while ((1ull << b) < (uint64_t)super_count(W, H)) ++b;
-    return (b + kRadixBits - 1) / kRadixBits;
+    return b == 0 ? 0 : (b <= kRadixBitsMax ? 1 : (b + kRadixBits - 1) / kRadixBits);
 }
 
 // Bytes of the first three per-pair arrays that ecap entries and their

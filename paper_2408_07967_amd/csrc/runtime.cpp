@@ -533,7 +533,7 @@ bool carve_noalloc(unsigned char *base, size_t P, size_t ntiles, FrameBuffers &f
     Carve c{base, FGS_NOALLOC_SCRATCH_BYTES};
     fb = FrameBuffers{};
     fc = c.take<FrameCounters>(1);
-    ss.rhist = c.take<uint32_t>((size_t)kSortBlocks * kRadix);
+    ss.rhist = c.take<uint32_t>((size_t)kSortBlocks * kRadixMax);
     ss.gsum = c.take<uint32_t>((size_t)kGsumSlots * kGsumWords);
     ss.sums = c.take<uint32_t>((size_t)kSortBlocks);
     fb.ranges = c.take<uint2>(ntiles);

@@ -63,7 +63,7 @@ void launch_tile_lists(int, int, const uint2 *, const uint32_t *, const uint64_t
 }
 void launch_radix_pass(const void *, const uint32_t *, void *, uint32_t *, uint32_t, const uint32_t *, int, int, bool,
                        bool, uint32_t *, uint32_t *, uint32_t *, hipStream_t, uint2 *, uint32_t, int, const uint64_t *,
-                       uint64_t *) {
+                       uint64_t *, bool) {
     reached("radix_pass");
 }
 void launch_count_scan(const uint32_t *, const uint8_t *, const uint4 *, uint32_t, const uint32_t *, uint32_t *,

@@ -101,7 +101,7 @@ def _city(orc, scenes, W, H, both_paths):
 def test_city_10M_4k_prepared_full_size(orc, scenes):
     _gpu()
     g = _city(orc, scenes, 3840, 2160, both_paths=True)
-    assert g["stats"]["sort_passes"] == 4 + 2
+    assert g["stats"]["sort_passes"] == 4 + 1  # 510 super-tiles: one 9-bit pass
 
 
 @pytest.mark.timeout(900)

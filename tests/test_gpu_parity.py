@@ -105,8 +105,8 @@ def test_one_pixel_and_one_tile_images(orc, R, scenes):
 
 def test_wide_image_with_32bit_tile_ids(orc, R):
     """More than 65536 tiles (16384 x 1040 = 66560): tile ids need more than
-    16 bits; the entries' 1152 super-tile ids (128 x 9) are sorted in two
-    8-bit passes."""
+    16 bits; the entries' 1152 super-tile ids (128 x 9, 11 bits) are sorted in
+    two passes."""
     from oracle_helpers import scene_from
     rng = np.random.default_rng(23)
     P = 4000
