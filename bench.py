@@ -5,8 +5,9 @@ Default workload: the 10,000,000-Gaussian ground-plane scene (SH degree 3)
 rendered at 3840x2160 through the camera at 80 m altitude pitched 30 deg
 down (synthetic stand-in for the paper's large-scale aerial 4K case).
 A step is one full frame through the C ABI: cull, preprocess with the exact
-ellipse/tile test, depth sort, count scan, key emission, tile sort, tile
-ranges and blending, with the scene already resident in HBM together with
+ellipse/tile test, depth sort, count scan, key emission (super-tile
+entries), their sort by super-tile, the per-tile lists and ranges, and
+blending, with the scene already resident in HBM together with
 its view-independent precompute (opacity, scales and rotation, extent, and
 SH coefficients Gaussian-major; built once, Sec. 5.3.1).  The frame rate
 from the raw parameters is reported beside it.
@@ -173,31 +174,33 @@ def visible_bounds(scene, cam):
     return int(np.count_nonzero(z > cam.near))
 
 
-def tile_sort_bytes(N, ntiles):
-    """Bytes the design's tile sort moves: stable LSD passes of at most 8 bits
-    over the tile-id bits; keys are uint16 up to 65,536 tiles, else uint32;
-    per pass the upsweep reads the keys and the downsweep reads and writes
-    keys and values, except the last pass, which writes values only."""
-    bits = max(1, math.ceil(math.log2(max(ntiles, 2))))
-    passes = math.ceil(bits / 8) if ntiles > 1 else 0
-    kb = 2 if ntiles <= 65536 else 4
+def super_sort_bytes(E, nsuper):
+    """Bytes the design's sort of the super-tile entries moves: one LSD pass
+    of up to 9 bits (else passes of 8 bits) over the uint16 super-tile ids;
+    per pass the upsweep reads the ids and the downsweep reads the ids and
+    the 12-byte payload (Gaussian index, 64-bit tile mask) and writes the
+    payload, and the ids too except in the last pass."""
+    bits = max(1, math.ceil(math.log2(max(nsuper, 2))))
+    passes = 0 if nsuper <= 1 else (1 if bits <= 9 else math.ceil(bits / 8))
     b = 0
     for p in range(passes):
         last = p == passes - 1
-        b += N * (kb + (kb + 4) + (4 if last else kb + 4))
+        b += E * (2 + 2 + 12 + 12 + (0 if last else 2))
     return b, passes
 
 
 def stage_rooflines(stage_ms, stats, P, P_z, W, H, evals, steps_exec, peaks=None):
     """Per-stage achieved bandwidth or VALU rate against the MI355X peaks.
-    Algorithmic bytes: the method's (the hot-path scope table's per-unit
-    figures) for the preprocess; the design's own for the sort and the
-    emission (it sorts the depth digits once per Gaussian and the pairs by
-    tile id only)."""
+    Algorithmic bytes: the method's (what it reads and writes per Gaussian)
+    for the preprocess; the design's own for the sorts, the
+    emission and the tile lists (it sorts the depth digits once per Gaussian
+    and the super-tile entries by super-tile, then expands the entries'
+    masks into the per-tile lists)."""
     V, N, cand = stats["visible"], stats["pairs"], stats["candidates"]
+    E, C = stats["entries"], stats["big_chunks"]
     ntiles = stats["tiles_x"] * stats["tiles_y"]
-    tsort, tpasses = tile_sort_bytes(N, ntiles)
-    kb = 2 if ntiles <= 65536 else 4
+    nsuper = math.ceil(stats["tiles_x"] / 8) * math.ceil(stats["tiles_y"] / 8)
+    ssort, spasses = super_sort_bytes(E, nsuper)
     rows = {}
 
     def hbm(name, nbytes, ms, note):
@@ -215,14 +218,18 @@ def stage_rooflines(stage_ms, stats, P, P_z, W, H, evals, steps_exec, peaks=None
         "method: 12 P (means) + 32 P_z + 232 P_vis")
     hbm("depth_sort", 80 * V, stage_ms["depth_sort"],
         "design: 4 LSD passes over the visible (depth, index) pairs, 20 B per pair and pass")
-    hbm("tile_sort", tsort, stage_ms["tile_sort"],
-        f"design: {tpasses} LSD passes over the pairs by tile id ({kb}-byte ids): the upsweep reads the ids, "
-        "the downsweep reads and writes ids and values (the last pass values only)")
-    hbm("sort", 80 * V + tsort, stage_ms["depth_sort"] + stage_ms["tile_sort"],
-        "design: depth sort + tile sort (the method's full-key sort would move 8 N + 24 N per 8-bit key pass)")
-    hbm("emit", 24 * V + (kb + 4) * N + 8 * ntiles, stage_ms["emit"],
-        "design: order, offset and 16-byte record per visible Gaussian read, tile id and value per pair "
-        "written, empty ranges per tile")
+    hbm("super_sort", ssort, stage_ms["super_sort"],
+        f"design: {spasses} LSD pass(es) over the super-tile entries: ids read twice, 12-byte payload read "
+        "and written (ids written too before the last pass)")
+    hbm("sort", 80 * V + ssort, stage_ms["depth_sort"] + stage_ms["super_sort"],
+        "design: depth sort + super-tile sort (the method's full-key sort would move 8 N + 24 N per 8-bit "
+        "key pass over the pairs)")
+    hbm("emit", 24 * V + 32 * C + 14 * E + 8 * nsuper, stage_ms["emit"],
+        "design: order, offset and 16-byte record per visible Gaussian, a 256-tile chunk mask per large "
+        "rectangle chunk read; a 14-byte entry per overlapped super-tile written")
+    hbm("tile_lists", 20 * E + 4 * N + 8 * ntiles, stage_ms["tile_lists"],
+        "design: masks read twice and Gaussian indices once per entry, a 4-byte value per pair and the "
+        "ranges per tile written")
     hbm("scan", 17 * V, stage_ms["scan"], "design: order (4 B) and count (1 B) gathered, 12 B per visible "
                                            "Gaussian written and read")
     if evals and stage_ms["blend"] > 0:

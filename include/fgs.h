@@ -10,7 +10,9 @@
  *      (Sec. 4.1, Alg. 3, Eq. 1-3 and Eq. 7, Alg. 4),
  *   2. key emission after a prefix scan of per-Gaussian tile counts
  *      (Alg. 2 offsets; Sec. 4.2 fusion of intersection and key generation),
- *   3. radix sort of (tile | depth) keys and per-tile ranges (Sec. 2.2),
+ *   3. radix sort of (tile | depth) keys and per-tile ranges (Sec. 2.2):
+ *      depth first, once per Gaussian, then the (super-tile, Gaussian, hit
+ *      mask) entries by super-tile, expanded into the per-tile lists,
  *   4. per-tile front-to-back alpha blending with early termination
  *      (Sec. 2.2, Sec. 5.2).
  *
@@ -107,11 +109,14 @@ typedef struct {
     int64_t pairs;     /* Gaussian-tile key/value pairs emitted          */
     int32_t tiles_x, tiles_y;
     int32_t sort_passes; /* radix passes: 4 over the depth keys, then those
-                           over the super-tile ids of the entries            */
+                           over the super-tile ids of the entries (one of up
+                           to 9 bits, else 8 bits each)                      */
     int32_t big_chunks; /* 256-tile chunks of the rectangles of more than 64
                            tiles, tested by wavefronts across the GPU        */
     int64_t candidates; /* Gaussians preprocessed: the cull's candidates of a
                            prepared scene, every Gaussian otherwise          */
+    int64_t entries;    /* (Gaussian, 8 x 8-tile super-tile) entries emitted:
+                           one per super-tile a Gaussian's rectangle overlaps */
 } fgs_stats;
 
 /* ---- context --------------------------------------------------------- */
@@ -339,9 +344,9 @@ typedef struct {
                                   is ms_cull)                                        */
     double ms_depth_sort;
     double ms_scan;
-    double ms_emit;
-    double ms_tile_sort;
-    double ms_ranges;
+    double ms_emit;            /* super-tile entries (key emission)                  */
+    double ms_super_sort;      /* radix sort of the entries by super-tile            */
+    double ms_tile_lists;      /* per-tile lists and ranges from the sorted entries  */
     double ms_blend;
     int64_t blend_evaluations; /* with FGS_INSTR_WORK: sum over pixels of the number of
                                   list entries the pixel examines (up to and including

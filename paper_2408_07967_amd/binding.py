@@ -46,13 +46,13 @@ class FgsOptions(C.Structure):
 class FgsStats(C.Structure):
     _fields_ = [("visible", C.c_int64), ("pairs", C.c_int64), ("tiles_x", C.c_int32), ("tiles_y", C.c_int32),
                 ("sort_passes", C.c_int32), ("big_chunks", C.c_int32),
-                ("candidates", C.c_int64)]
+                ("candidates", C.c_int64), ("entries", C.c_int64)]
 
 
 class FgsTimings(C.Structure):
     _fields_ = [("frames", C.c_int64), ("ms_preprocess", C.c_double), ("ms_depth_sort", C.c_double),
-                ("ms_scan", C.c_double), ("ms_emit", C.c_double), ("ms_tile_sort", C.c_double),
-                ("ms_ranges", C.c_double), ("ms_blend", C.c_double), ("blend_evaluations", C.c_int64),
+                ("ms_scan", C.c_double), ("ms_emit", C.c_double), ("ms_super_sort", C.c_double),
+                ("ms_tile_lists", C.c_double), ("ms_blend", C.c_double), ("blend_evaluations", C.c_int64),
                 ("ms_cull", C.c_double), ("blend_wave_steps", C.c_int64)]
 
 

@@ -146,8 +146,8 @@ void fold_events(fgs_context *ctx) {
     ctx->acc.ms_depth_sort += ms[1];
     ctx->acc.ms_scan += ms[2];
     ctx->acc.ms_emit += ms[3];
-    ctx->acc.ms_tile_sort += ms[4];
-    ctx->acc.ms_ranges += ms[5];
+    ctx->acc.ms_super_sort += ms[4];
+    ctx->acc.ms_tile_lists += ms[5];
     ctx->acc.ms_blend += ms[6];
     ctx->ev_pending = -1;
 }
@@ -355,6 +355,7 @@ fgs_status render_impl(fgs_context *ctx, const fgs_scene *scene, const fgs_prepa
     unsigned long long *work = (ctx->instr & FGS_INSTR_WORK) ? ctx->work_dev : nullptr;
     uint32_t V = 0, N = 0, big = 0, ncand = 0;
     size_t Ncap = 0;  // pair-array capacity the frame needs
+    uint32_t E = 0;   // super-tile entries
     bool tiles_in_a = true;
     size_t spec_cap = 0;  // pair capacity of a second half already enqueued (0: none)
     for (int attempt = 0;; ++attempt) {
@@ -392,7 +393,8 @@ fgs_status render_impl(fgs_context *ctx, const fgs_scene *scene, const fgs_prepa
         }
         V = ctx->fc_host->visible;
         N = ctx->fc_host->pairs;
-        Ncap = pair_capacity_needed(N, ctx->fc_host->entries, W, H);
+        E = ctx->fc_host->entries;
+        Ncap = pair_capacity_needed(N, E, W, H);
         big = ctx->fc_host->nchunks;
         ncand = prep ? ctx->fc_host->ncand : 0;
         break;
@@ -415,6 +417,7 @@ fgs_status render_impl(fgs_context *ctx, const fgs_scene *scene, const fgs_prepa
             stt.tiles_y = tiles_y;
             stt.big_chunks = (int32_t)big;
             stt.candidates = prep ? (int64_t)ncand : (int64_t)P;
+            stt.entries = E;
             *stats = stt;
         }
         return FGS_OK;
@@ -445,6 +448,7 @@ fgs_status render_impl(fgs_context *ctx, const fgs_scene *scene, const fgs_prepa
     stt.tiles_y = tiles_y;
     stt.big_chunks = (int32_t)big;
     stt.candidates = prep ? (int64_t)ncand : (int64_t)P;
+    stt.entries = E;
     stt.sort_passes = 4 + super_sort_passes(W, H);
     if (stats) *stats = stt;
 
@@ -630,6 +634,7 @@ fgs_status fgs_render_noalloc(fgs_context *ctx, const fgs_scene *scene, const fg
         stt.tiles_y = tiles_y;
         stt.big_chunks = (int32_t)h.nchunks;
         stt.candidates = P;
+        stt.entries = h.entries;
         stt.sort_passes = 4 + super_sort_passes(W, H);
         *stats = stt;
     }
@@ -847,6 +852,7 @@ fgs_status fgs_render_prepared_batch(fgs_context *ctx, const fgs_prepared *p, co
             stt.tiles_y = tiles_y;
             stt.big_chunks = (int32_t)ctx->bfc_host[c].nchunks;
             stt.candidates = (int64_t)ctx->bfc_host[c].ncand;
+            stt.entries = ctx->bfc_host[c].entries;
             stt.sort_passes = 4 + super_sort_passes(W, H);
             stats[c] = stt;
         }

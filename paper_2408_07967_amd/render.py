@@ -109,7 +109,7 @@ class Renderer:
         return dict(rgb=rgb, T=T, last=last, frame=fr if save else None,
                     stats=dict(visible=st.visible, pairs=st.pairs, tiles_x=st.tiles_x, tiles_y=st.tiles_y,
                                sort_passes=st.sort_passes, big_chunks=st.big_chunks,
-                               candidates=st.candidates))
+                               candidates=st.candidates, entries=st.entries))
 
     def render_noalloc(self, scene, cam, W, H, opts=None, out=None, want_T=False, want_last=False):
         """render() through fgs_render_noalloc: every scratch buffer comes from
@@ -133,7 +133,7 @@ class Renderer:
         return dict(rgb=rgb, T=T, last=last, frame=None,
                     stats=dict(visible=st.visible, pairs=st.pairs, tiles_x=st.tiles_x, tiles_y=st.tiles_y,
                                sort_passes=st.sort_passes, big_chunks=st.big_chunks,
-                               candidates=st.candidates))
+                               candidates=st.candidates, entries=st.entries))
 
     def render_batch(self, prepared, scene, cams, W, H, opts=None, want_T=False, want_last=False):
         """Render several cameras of a prepared scene in one call (one cull and
@@ -154,7 +154,8 @@ class Renderer:
         return [dict(rgb=rgb[i], T=T[i] if T else None, last=last[i] if last else None, frame=None,
                      stats=dict(visible=st[i].visible, pairs=st[i].pairs, tiles_x=st[i].tiles_x,
                                 tiles_y=st[i].tiles_y, sort_passes=st[i].sort_passes,
-                                big_chunks=st[i].big_chunks, candidates=st[i].candidates))
+                                big_chunks=st[i].big_chunks, candidates=st[i].candidates,
+                                entries=st[i].entries))
                 for i in range(n)]
 
     def plan(self, scene, cam, W, H, opts=None):
