@@ -22,10 +22,11 @@
 //                  of tile ids): the earlier rows' sums, then an exclusive
 //                  scan of the band's tile totals in tile id order ->
 //                  ranges[t] = [start, start + count);
-//   k_list_write   per chunk again, 64 entries (one per lane) at a time: for
-//                  each tile, the lanes whose mask has its bit write their
-//                  Gaussian at the tile's running position plus their rank
-//                  among those lanes (a ballot), one contiguous store.
+//   k_list_write   per chunk again, tile by tile over its four 64-entry
+//                  blocks (one entry per lane): the lanes whose mask has the
+//                  tile's bit write their Gaussian at the tile's running
+//                  position plus their rank among those lanes (a ballot),
+//                  one contiguous store per block.
 // Chunks are dealt to the XCDs in eight contiguous ranges, so that a
 // super-tile's consecutive chunks, which write the same tiles' lists, share
 // an L2.
@@ -291,17 +292,20 @@ __global__ __launch_bounds__(kListBlock) void k_list_write(const uint2 *__restri
             m[k] = i < e ? smask[i] : 0ull;
             g[k] = i < e ? gidx[i] : 0u;
         }
-        // lane j: the next output position of tile j (bit j) of this super-tile
+        // lane j: the first output position of tile j (bit j) of this super-tile
         const int64_t t = lane_tile(s, stx, tiles_x, tiles_y, lane);
-        uint32_t next = t >= 0 ? ranges[t].x + pre[(size_t)q * kWave + lane] : 0u;
-        for (int k = 0; k < (int)(kListChunk / kWave); ++k) {
-            const uint32_t mlo = (uint32_t)m[k], mhi = (uint32_t)(m[k] >> 32);
+        const uint32_t first = t >= 0 ? ranges[t].x + pre[(size_t)q * kWave + lane] : 0u;
+        // tile by tile: the chunk's four 64-entry blocks in order, the
+        // running position kept as a wavefront-uniform value
 #pragma unroll
-            for (int j = 0; j < kWave; ++j) {
-                const bool hit = (((j < 32 ? mlo : mhi) >> (j & 31)) & 1u) != 0u;
+        for (int j = 0; j < kWave; ++j) {
+            uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)first, j);
+#pragma unroll
+            for (int k = 0; k < (int)(kListChunk / kWave); ++k) {
+                const uint32_t w = j < 32 ? (uint32_t)m[k] : (uint32_t)(m[k] >> 32);
+                const bool hit = ((w >> (j & 31)) & 1u) != 0u;
                 const uint64_t bal = __ballot(hit);
                 if (bal) {  // uniform
-                    const uint32_t base = (uint32_t)__builtin_amdgcn_readlane((int)next, j);
                     const uint32_t pos =
                         base + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
                     if (hit) {
@@ -310,11 +314,9 @@ __global__ __launch_bounds__(kListBlock) void k_list_write(const uint2 *__restri
                         else if (pos < ncap)  // never leave the values
                             values[pos] = g[k];
                     }
+                    base += (uint32_t)__popcll(bal);
                 }
             }
-            // every tile moves on by its hits in this block: the popcount of
-            // its column of the block's masks
-            next += (uint32_t)__popcll(transpose64(m[k], lane));
         }
     }
 }
