@@ -722,7 +722,7 @@ def main():
                            raw_params_frames_per_s=round(raw_fps, 3), prepare_ms=round(prep_ms, 2),
                            visible=int(stats["visible"]), pairs=int(stats["pairs"]),
                            candidates=int(stats["candidates"]), past_near_plane=P_z,
-                           big_rect_chunks=int(stats["big_chunks"]),
+                           big_rect_chunks=int(stats["big_chunks"]), super_tile_entries=int(stats["entries"]),
                            pairs_per_s=round(stats["pairs"] * fps, 1), stage_ms=stage_ms,
                            single_frame_ms=frame_ms,
                            blend_evaluations=evals, blend_wave_steps=steps_exec),
