@@ -1285,11 +1285,17 @@ __global__ __launch_bounds__(kBlock) void k_big_entries(int W, const uint4 *__re
     }
 }
 
-// Exact tile tests of the chunked Gaussians: one wavefront per chunk of
-// kChunkTiles rectangle tiles (4 per lane, independent), so that every
-// workgroup keeps four chunks in flight without barriers; the next chunk's
-// descriptor is loaded before the current chunk is tested.  A workgroup adds
-// its hits to the frame's pair count once.
+// Exact tile tests of the chunked Gaussians.  A wavefront takes 64
+// consecutive chunk slots: every lane loads one slot's descriptor and then
+// its Gaussian's rectangle, centre, conic and k^2, so that the 64 chunks cost
+// two memory round trips together; the chunks are then tested one after the
+// other with their values read from the owning lane (kChunkTiles tiles, 4
+// per lane, independent).  The 8 mask words of a chunk are written by four
+// lanes, and the hits of a Gaussian's consecutive chunks are summed across
+// the lanes before one atomic per Gaussian and wavefront.  A workgroup adds
+// its hits to the frame's pair count once.  (With 64 slots per wavefront the
+// kernel runs as fewer, longer wavefronts, which leaves the depth sort
+// beside it more of each CU than one chunk per wavefront did.)
 __global__ __launch_bounds__(kBlock) void k_big_count(int W, int H, int binning, const GaussState *__restrict__ gs,
                                                       const float4 *__restrict__ conic,
                                                       const uint4 *__restrict__ erec,
@@ -1297,6 +1303,7 @@ __global__ __launch_bounds__(kBlock) void k_big_count(int W, int H, int binning,
                                                       uint32_t *__restrict__ chunk_mask, uint32_t *count,
                                                       FrameCounters *fc) {
     constexpr int kPer = kChunkTiles / kWave;
+    static_assert(kPer == 4, "a chunk's mask is written as four 64-bit words");
     __shared__ uint32_t s_hits[kBlock / kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
@@ -1306,47 +1313,69 @@ __global__ __launch_bounds__(kBlock) void k_big_count(int W, int H, int binning,
     if (!(fc->error & kErrChunkOverflow)) {
         const uint32_t n = fc->nchunks < chunk_cap ? fc->nchunks : chunk_cap;
         const uint32_t nwaves = gridDim.x * (kBlock / kWave);
-        uint32_t ch = blockIdx.x * (kBlock / kWave) + (uint32_t)wv;
-        uint2 e = ch < n ? chunks[ch] : make_uint2(kNoChunk, 0u);
-        for (; ch < n; ch += nwaves) {
-            const uint32_t nxt = ch + nwaves;
-            const uint2 e_next = nxt < n ? chunks[nxt] : make_uint2(kNoChunk, 0u);
-            if (e.x == kNoChunk) {
-                e = e_next;
-                continue;
+        uint64_t *const mask64 = reinterpret_cast<uint64_t *>(chunk_mask);
+        for (uint32_t c0 = (blockIdx.x * (kBlock / kWave) + (uint32_t)wv) * kWave; c0 < n; c0 += nwaves * kWave) {
+            const uint32_t c = c0 + (uint32_t)lane;
+            uint2 e = make_uint2(kNoChunk, 0u);
+            if (c < n) e = chunks[c];
+            const bool have = e.x != kNoChunk;
+            // this lane's chunk: its Gaussian's record, centre, k^2 and conic
+            uint4 rr = make_uint4(0u, 0u, 0u, 0u);
+            float4 f0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), f1 = f0, cn = f0;
+            if (have) {
+                rr = erec[e.x];
+                if (binning == 0) {
+                    const float4 *sp = reinterpret_cast<const float4 *>(gs + e.x);
+                    f0 = sp[0];
+                    f1 = sp[1];
+                    cn = conic[e.x];
+                }
             }
-            const uint32_t g = e.x, c = ch - e.y;
-            const uint4 rc = unpack_rect(erec[g]);
-            const int ntx = (int)rc.y - (int)rc.x + 1;
-            const int nt = ntx * ((int)rc.w - (int)rc.z + 1);
-            GaussState s{};
-            float4 cn = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if (binning == 0) {
-                s = gs[g];
-                cn = conic[g];
-            }
-            const float rcpn = __builtin_amdgcn_rcpf((float)ntx);
-            uint32_t tot = 0;
+            const uint32_t cidx = have ? c - e.y : 0u;  // chunk within its Gaussian
+            uint32_t my_hits = 0;
+            uint64_t todo = __ballot(have);
+            while (todo) {
+                const int j = __builtin_ctzll(todo);
+                todo &= todo - 1ull;
+                const uint32_t px = bcast(rr.x, j), py = bcast(rr.y, j), cc = bcast(cidx, j);
+                const float u = bcast(f0.x, j), v = bcast(f0.y, j), k2 = bcast(f1.y, j);
+                const float A = bcast(cn.x, j), B = bcast(cn.y, j), C = bcast(cn.z, j);
+                const int tx0 = (int)(px & 0xffffu), ntx = (int)(px >> 16) - tx0 + 1;
+                const int ty0 = (int)(py & 0xffffu), nt = ntx * ((int)(py >> 16) - ty0 + 1);
+                const float rcpn = __builtin_amdgcn_rcpf((float)ntx);
+                uint64_t bw[kPer];
 #pragma unroll
-            for (int j = 0; j < kPer; ++j) {
-                const int idx = (int)c * kChunkTiles + j * kWave + lane;
-                bool h = false;
-                if (idx < nt) {
-                    int ry, rx;
-                    row_col(idx, ntx, rcpn, ry, rx);
-                    h = binning != 0 ||
-                        tile_hit(s.f0.x, s.f0.y, cn.x, cn.y, cn.z, s.f1.y, (int)rc.x + rx, (int)rc.z + ry, W, H);
+                for (int q = 0; q < kPer; ++q) {
+                    const int idx = (int)cc * kChunkTiles + q * kWave + lane;
+                    bool h = false;
+                    if (idx < nt) {
+                        int ry, rx;
+                        row_col(idx, ntx, rcpn, ry, rx);
+                        h = binning != 0 || tile_hit(u, v, A, B, C, k2, tx0 + rx, ty0 + ry, W, H);
+                    }
+                    bw[q] = __ballot(h);
                 }
-                const uint64_t b = __ballot(h);
-                tot += (uint32_t)__popcll(b);
-                if (lane == 0) {
-                    chunk_mask[(size_t)ch * (kChunkTiles / 32) + 2 * j] = (uint32_t)b;
-                    chunk_mask[(size_t)ch * (kChunkTiles / 32) + 2 * j + 1] = (uint32_t)(b >> 32);
+                const uint32_t tot = (uint32_t)(__popcll(bw[0]) + __popcll(bw[1]) + __popcll(bw[2]) + __popcll(bw[3]));
+                if (lane < kPer) {
+                    const uint64_t w = lane == 0 ? bw[0] : lane == 1 ? bw[1] : lane == 2 ? bw[2] : bw[3];
+                    mask64[(size_t)(c0 + (uint32_t)j) * kPer + (uint32_t)lane] = w;
                 }
+                my_hits = lane == j ? tot : my_hits;
+                whits += tot;
             }
-            if (lane == 0 && tot) atomicAdd(&count[g], tot);
-            whits += tot;
-            e = e_next;
+            // one atomic per run of lanes holding chunks of the same Gaussian
+            // (a Gaussian's chunks are consecutive slots)
+            const uint32_t incl = wave_incl_scan(my_hits, lane);
+            const uint32_t gprev = (uint32_t)__shfl_up((int)e.x, 1, kWave);
+            const uint32_t gnext = (uint32_t)__shfl_down((int)e.x, 1, kWave);
+            const bool head = lane == 0 || gprev != e.x;
+            const bool tail = lane == kWave - 1 || gnext != e.x;
+            const uint64_t heads = __ballot(head);
+            // the run's first lane: the highest head at or below this lane
+            const int first = 63 - __builtin_clzll(heads & (lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1ull)));
+            const uint32_t before = (uint32_t)__shfl((int)incl, first > 0 ? first - 1 : 0, kWave);
+            const uint32_t run = incl - (first > 0 ? before : 0u);
+            if (have && tail && run) atomicAdd(&count[e.x], run);
         }
     }
     if (lane == 0) s_hits[wv] = whits;
