@@ -148,7 +148,7 @@ def test_3sigma_square_binning_parity(orc, R, scenes, kind, P, W, H):
 
 @pytest.mark.parametrize("case", ["small", "random_sh3", "degenerate", "medium_binning2", "uncapped",
                                   "offscreen_big", "offscreen_big_binning2", "ties_short", "ties_long",
-                                  "ties_one_run", "city1M-540p"])
+                                  "ties_one_run", "city1M-540p", "sh_huge", "eye_at_mean"])
 def test_prepared_scene_is_bit_identical(orc, R, scenes, case):
     """A frame from the view-independent precompute equals the frame from the
     raw parameters bit for bit (state, pairs, order, image, T, last).  The
@@ -156,7 +156,14 @@ def test_prepared_scene_is_bit_identical(orc, R, scenes, case):
     its depth sort in that order and are re-ordered by Gaussian index; the
     ties cases put many Gaussians at exactly equal depths: runs of 2 to 30
     (sorted by one thread each), runs of about 60 (sorted by a workgroup in
-    LDS), and one run of 6000 (sorted in 1024-chunks and merged)."""
+    LDS), and one run of 6000 (sorted in 1024-chunks and merged).
+
+    The colour decides visibility too (a non-finite colour culls): a
+    non-finite coefficient ("degenerate"), a zero view direction
+    ("eye_at_mean": the camera centre given on a visible Gaussian's mean,
+    0 / 0 in the basis) and coefficients near the binary32 maximum, which
+    overflow the colour from some directions only ("sh_huge"), must cull the
+    same Gaussians on both paths and in the binary32 oracle."""
     o = opts()
     if case.startswith("ties"):
         rng = np.random.default_rng({"ties_short": 41, "ties_long": 42, "ties_one_run": 43}[case])
@@ -188,6 +195,27 @@ def test_prepared_scene_is_bit_identical(orc, R, scenes, case):
         sc.means[2, 10] = -1.0      # behind the camera
         W, H = 96, 80
         cam = identity_camera(W, H, 70.0)
+    elif case == "sh_huge":
+        rng = np.random.default_rng(34)
+        sc = random_scene(rng, 3000, ls_mu=-2.6, sh_degree=2)
+        # band-1 and band-2 coefficients of one colour channel near the
+        # binary32 maximum, of mixed signs: the sum overflows for some view
+        # directions and not for others
+        idx = rng.choice(sc.P, 400, replace=False)
+        for k in (1, 2, 3, 4, 6):
+            sc.sh[3 * k, idx] = np.float32(3.0e38) * rng.choice([-1.0, 1.0], idx.size).astype(np.float32)
+        W, H = 240, 160
+        cam = identity_camera(W, H, 0.9 * W)
+    elif case == "eye_at_mean":
+        rng = np.random.default_rng(35)
+        sc = random_scene(rng, 2000, ls_mu=-2.4, sh_degree=1)
+        W, H = 160, 120
+        cam = identity_camera(W, H, 0.9 * W)
+        # the camera centre on the mean of a Gaussian the camera sees (its
+        # view-space depth stays positive: eye and R, t are separate inputs)
+        j = int(np.argmin(np.abs(sc.means[0]) + np.abs(sc.means[1])))
+        cam.eye = sc.means[:, j].astype(np.float32).copy()
+        sc.logits[0, j] = np.float32(4.0)
     elif case == "medium_binning2":
         sc = scenes.make_scene("medium", P=120_000)
         W, H = 960, 540
@@ -212,6 +240,15 @@ def test_prepared_scene_is_bit_identical(orc, R, scenes, case):
         b = gpu_frame(R, gsc, cam, W, H, o, prepared=h)
     finally:
         R.release_prepared(h)
+    if case == "eye_at_mean":
+        # the raw path culls that Gaussian through its NaN colour
+        assert j not in set(a["order"].tolist())
+    if case in ("sh_huge", "eye_at_mean"):
+        # the raw frame against the binary32 oracle (the prepared frame
+        # equals it bit for bit, below)
+        o32 = orc.render(sc, cam, W, H, o, mode="f32")
+        check_gauss_state(orc, a, o32)
+        check_pairs(a, o32)
     if case.startswith("ties"):
         d = a["gauss"][a["order"].astype(np.int64), 10].view(np.uint32)
         runs = np.diff(np.flatnonzero(np.r_[True, d[1:] != d[:-1], True]))
