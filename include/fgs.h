@@ -407,13 +407,13 @@ fgs_status fgs_frame_stats(const fgs_frame *frame, fgs_stats *stats);
  * requests of mixed resolutions concurrently.  A request takes a slot (its
  * own stream and per-Gaussian buffers) and runs the first half of the frame
  * (preprocess, exact tile counts, depth order, count scan), which yields its
- * exact pair count N; requests that start together share the cull and
- * preprocess of that half (batch_fronts).  It is then admitted when its pair
- * and sort buffers
- * (16 bytes per pair) fit in the free part of a device byte budget: FIFO, a
+ * exact pair count N and its super-tile entries; requests that start
+ * together share the cull and preprocess of that half (batch_fronts).  It is
+ * then admitted when its pair and sort buffers (16 bytes per unit of the pair
+ * capacity those need) fit in the free part of a device byte budget: FIFO, a
  * request that does not fit may be overtaken by at most max_bypass later
- * ones.  The second half (emission, tile sort, ranges, blend) then runs as
- * a hipGraph captured once per (slot, resolution) and replayed.  A slot that
+ * ones.  The second half (emission, super-tile sort, tile lists, blend) then
+ * runs as a hipGraph captured once per (slot, resolution) and replayed.  A slot that
  * still holds the pair region of an earlier request enqueues that graph right
  * behind the first half, before the pair count is known (its kernels read
  * the count on the device and stay within the region), so that the host's

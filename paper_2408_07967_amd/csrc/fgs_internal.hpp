@@ -319,8 +319,9 @@ void launch_tile_lists(int W, int H, const uint2 *sranges, const uint32_t *gidx,
 //           for the next pass
 //   run_ends if non-null (the last pass of a sort by the whole key, keys <
 //           nruns): run_ends[k] = [start, end) of key k's run in the output,
-//           by atomic min / max on entries that launch_emit set empty; a key
-//           with no element keeps start > end
+//           by atomic min / max on entries that the caller set empty (the
+//           emission does for the super-tiles); a key with no element keeps
+//           start > end
 //   key_bytes 4 (uint32 keys) or 2 (uint16 keys: unfiltered passes with
 //           explicit values, or with a payload)
 //   mask_in if non-null (16-bit keys only): the payload (vals_in[i],

@@ -1,6 +1,7 @@
 // Host-side frame pipeline: buffer management, argument checks and the
 // kernel sequence of one frame (preprocess -> depth order -> count scan ->
-// emission -> tile sort -> ranges -> blend).
+// super-tile entries -> their sort by super-tile -> per-tile lists and
+// ranges -> blend).
 #include "pipeline.hpp"
 
 #include <algorithm>

@@ -8,9 +8,11 @@
 //                     requests that start together share one cull and one
 //                     preprocess pass (then sort and scan on their own slots)
 //   FRONT   -> WAIT   the counters arrived: N pairs are known
-//   WAIT    -> BACK   admitted: 16 N bytes (+ headroom) of the byte budget
-//                     back the slot's pair and sort buffers; the second half
-//                     (emission, tile sort, ranges, blend) is a graph captured
+//   WAIT    -> BACK   admitted: 16 C bytes (+ headroom) of the byte budget
+//                     back the slot's pair and sort buffers (C: the pair
+//                     capacity the frame's pairs and super-tile entries
+//                     need); the second half (emission, super-tile sort,
+//                     tile lists, blend) is a graph captured
 //                     once per (slot, W, H) while the slot's buffers stay put
 //   BACK    -> DONE   the image is complete; the client polls the result
 //   DONE    -> IDLE   the client released the image
