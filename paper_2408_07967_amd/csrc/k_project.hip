@@ -1285,12 +1285,22 @@ __global__ __launch_bounds__(kBlock) void k_big_entries(int W, const uint4 *__re
     }
 }
 
+// LDS visibility of this wavefront's own writes to its own later reads
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Exact tile tests of the chunked Gaussians.  A wavefront takes 64
 // consecutive chunk slots: every lane loads one slot's descriptor and then
 // its Gaussian's rectangle, centre, conic and k^2, so that the 64 chunks cost
 // two memory round trips together; the chunks are then tested one after the
 // other with their values read from the owning lane (kChunkTiles tiles, 4
-// per lane, independent).  The 8 mask words of a chunk are written by four
+// per lane, independent).  A chunk covers few tile rows, whose terms of the
+// test (tile_row_terms) are computed once per row into LDS; each tile adds
+// its column's terms and combines them (tile_hit_terms: the operations of
+// tile_hit).  The 8 mask words of a chunk are written by four
 // lanes, and the hits of a Gaussian's consecutive chunks are summed across
 // the lanes before one atomic per Gaussian and wavefront.  A workgroup adds
 // its hits to the frame's pair count once.  (With 64 slots per wavefront the
@@ -1305,6 +1315,8 @@ __global__ __launch_bounds__(kBlock) void k_big_count(int W, int H, int binning,
     constexpr int kPer = kChunkTiles / kWave;
     static_assert(kPer == 4, "a chunk's mask is written as four 64-bit words");
     __shared__ uint32_t s_hits[kBlock / kWave];
+    // the row terms of the chunk being tested (one lane per row)
+    __shared__ float4 s_ra[kBlock / kWave][kWave], s_rb[kBlock / kWave][kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
     uint32_t whits = 0;  // wave-uniform
@@ -1343,15 +1355,39 @@ __global__ __launch_bounds__(kBlock) void k_big_count(int W, int H, int binning,
                 const int tx0 = (int)(px & 0xffffu), ntx = (int)(px >> 16) - tx0 + 1;
                 const int ty0 = (int)(py & 0xffffu), nt = ntx * ((int)(py >> 16) - ty0 + 1);
                 const float rcpn = __builtin_amdgcn_rcpf((float)ntx);
+                // the chunk's rows: their terms once each (a chunk over more
+                // rows than a wavefront has lanes tests tile by tile)
+                const int i0 = (int)cc * kChunkTiles;
+                const int i1 = (i0 + kChunkTiles < nt ? i0 + kChunkTiles : nt) - 1;
+                int ry_a, rx_a, ry_b, rx_b;
+                row_col(i0, ntx, rcpn, ry_a, rx_a);
+                row_col(i1, ntx, rcpn, ry_b, rx_b);
+                const bool rows = binning == 0 && ry_b - ry_a < kWave;
+                if (rows) {
+                    wave_sync();  // every lane has read the previous chunk's terms
+                    if (lane <= ry_b - ry_a) {
+                        float4 ra, rb;
+                        tile_row_terms(v, A, B, C, k2, ty0 + ry_a + lane, H, ra, rb);
+                        s_ra[wv][lane] = ra;
+                        s_rb[wv][lane] = rb;
+                    }
+                    wave_sync();
+                }
                 uint64_t bw[kPer];
 #pragma unroll
                 for (int q = 0; q < kPer; ++q) {
-                    const int idx = (int)cc * kChunkTiles + q * kWave + lane;
+                    const int idx = i0 + q * kWave + lane;
                     bool h = false;
                     if (idx < nt) {
                         int ry, rx;
                         row_col(idx, ntx, rcpn, ry, rx);
-                        h = binning != 0 || tile_hit(u, v, A, B, C, k2, tx0 + rx, ty0 + ry, W, H);
+                        if (rows) {
+                            float4 ca, cb;
+                            tile_col_terms(u, A, B, C, k2, tx0 + rx, W, ca, cb);
+                            h = tile_hit_terms(ca, cb, s_ra[wv][ry - ry_a], s_rb[wv][ry - ry_a]);
+                        } else {
+                            h = binning != 0 || tile_hit(u, v, A, B, C, k2, tx0 + rx, ty0 + ry, W, H);
+                        }
                     }
                     bw[q] = __ballot(h);
                 }
