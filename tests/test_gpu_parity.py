@@ -59,6 +59,31 @@ def test_random_scenes(orc, R, seed, P, W, H, deg, ls_mu):
     _full_check(orc, R, sc, cam, W, H, opts(), f"random{seed}")
 
 
+@pytest.mark.parametrize("seed,P,W,H,ls_mu", [
+    (501, 60000, 2049, 1201, -1.6),   # ~10^5 chunks: Gaussians over many 64-slot windows, ragged super-tiles
+    (502, 20000, 1023, 511, -1.1),    # rectangles up to the whole image, more tile rows per chunk
+])
+def test_dense_large_rectangles(orc, R, seed, P, W, H, ls_mu):
+    """Frames whose pairs mostly come from chunked rectangles (hundreds of
+    thousands of 256-tile chunks), on images that are not a whole number of
+    super-tiles: state, order, pairs and ranges bit-exact against the
+    binary32 oracle, the image against binary64, and the prepared scene's
+    frame equal to the raw one."""
+    rng = np.random.default_rng(seed)
+    sc = random_scene(rng, P, box=2.0, ls_mu=ls_mu, ls_sigma=0.6, sh_degree=2)
+    cam = identity_camera(W, H, 0.8 * W)
+    g, _, _ = _full_check(orc, R, sc, cam, W, H, opts(), f"dense-large-{seed}")
+    assert g["stats"]["big_chunks"] > 10000, g["stats"]["big_chunks"]
+    gsc = _gs(sc)
+    h = R.prepare(gsc, opts())
+    try:
+        p = gpu_frame(R, gsc, cam, W, H, opts(), prepared=h)
+    finally:
+        R.release_prepared(h)
+    for k in ("rgb", "T", "last", "order", "tiles", "values", "ranges"):
+        assert np.array_equal(np.asarray(g[k]).view(np.uint32), np.asarray(p[k]).view(np.uint32)), k
+
+
 def test_medium_scene_reduced(orc, R, scenes):
     sc = scenes.make_scene("medium", P=200_000)
     _full_check(orc, R, sc, scenes.camera_for("medium", 0), 1920, 1080, opts(), "medium200k")
