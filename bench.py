@@ -210,7 +210,14 @@ def stage_rooflines(stage_ms, stats, P, P_z, W, H, evals, steps_exec, peaks=None
         rows[name] = dict(bound="hbm", bytes=int(nbytes), ms=round(ms, 4), achieved_gbs=round(gbs, 1),
                           frac=round(gbs / HBM_PEAK_GBS, 4), bytes_are=note)
 
-    hbm("cull", 24 * P, stage_ms["cull"], "24 B per Gaussian: position, opacity, trace of the covariance, k^2")
+    nb = (P + 255) // 256
+    read = stats.get("cull_batches", 0)
+    if read:
+        hbm("cull", 48 * nb + 24 * min(P, 256 * read), stage_ms["cull"],
+            f"design: 48 B of bounds per 256-slot batch ({nb}), and 24 B per Gaussian (position, opacity, trace of "
+            f"the covariance, k^2) of the {read} batches the bounds keep")
+    else:
+        hbm("cull", 24 * P, stage_ms["cull"], "24 B per Gaussian: position, opacity, trace of the covariance, k^2")
     hbm("preprocess", 32 * P_z + 232 * V, stage_ms["preprocess"],
         "method: 32 P_z (scales, rotation, opacity of the Gaussians past the near plane) + 192 P_vis (SH) + "
         "40 P_vis (state written)")
@@ -721,7 +728,8 @@ def main():
                            blend_variant="prefetch pipeline" if args.blend_variant else "LDS batches",
                            raw_params_frames_per_s=round(raw_fps, 3), prepare_ms=round(prep_ms, 2),
                            visible=int(stats["visible"]), pairs=int(stats["pairs"]),
-                           candidates=int(stats["candidates"]), past_near_plane=P_z,
+                           candidates=int(stats["candidates"]), cull_batches_read=int(stats["cull_batches"]),
+                           past_near_plane=P_z,
                            big_rect_chunks=int(stats["big_chunks"]), super_tile_entries=int(stats["entries"]),
                            pairs_per_s=round(stats["pairs"] * fps, 1), stage_ms=stage_ms,
                            single_frame_ms=frame_ms,

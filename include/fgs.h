@@ -117,6 +117,9 @@ typedef struct {
                            prepared scene, every Gaussian otherwise          */
     int64_t entries;    /* (Gaussian, 8 x 8-tile super-tile) entries emitted:
                            one per super-tile a Gaussian's rectangle overlaps */
+    int64_t cull_batches; /* prepared scene: batches of 256 precompute slots its
+                           cull read (the others' bounds showed that every
+                           member would be culled); 0 for raw parameters    */
 } fgs_stats;
 
 /* ---- context --------------------------------------------------------- */
@@ -225,15 +228,18 @@ fgs_status fgs_render_noalloc(fgs_context *ctx, const fgs_scene *scene, const fg
  * view-independent part of every Gaussian: opacity (0 for a Gaussian that can
  * never be visible), scales and unit quaternion, extent k^2, a bound of the
  * screen extent (trace of the 3D covariance), and the SH coefficients
- * Gaussian-major, so a frame reads 24 bytes for every Gaussian, 48 more for
- * the candidates of its cull and one contiguous run of SH for the visible
- * ones.  The precompute stores the Gaussians in a spatial order (Morton order
- * of the means, computed and sorted here), so that the candidates of a
- * frame's cull, which see one region of the scene, are read as few
- * contiguous runs; frames re-order equal depths by Gaussian index, so the
- * pair order is still the method's.  Device memory owned by the context:
- * 60 B + 4 ceil4(3 (D+1)^2) B per Gaussian (252 B at degree 3), plus 16 B
- * per Gaussian and the sort scratch during the call.  It depends on the
+ * Gaussian-major, so a frame reads 24 bytes for every Gaussian of the
+ * 256-slot batches its cull reads, 48 more for the candidates of its cull and
+ * one contiguous run of SH for the visible ones.  The precompute stores the
+ * Gaussians in a spatial order (Morton order of the means, computed and
+ * sorted here), so that the candidates of a frame's cull, which see one
+ * region of the scene, are read as few contiguous runs; per batch it keeps
+ * bounds (box of the means, greatest opacity, trace and k^2) from which the
+ * cull skips the batches whose every member it would cull.  Frames re-order
+ * equal depths by Gaussian index, so the pair order is still the method's.
+ * Device memory owned by the context: 60 B + 4 ceil4(3 (D+1)^2) B per
+ * Gaussian (252 B at degree 3) and 48 B per batch, plus 16 B per Gaussian and
+ * the sort scratch during the call.  It depends on the
  * scene's values (copy of the fgs_scene struct kept; the planes must stay
  * valid and unchanged for backward passes) and on opt->alpha_min and
  * opt->cap_3sigma.  Frames rendered from it are bit-identical to fgs_render

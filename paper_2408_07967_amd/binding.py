@@ -46,7 +46,7 @@ class FgsOptions(C.Structure):
 class FgsStats(C.Structure):
     _fields_ = [("visible", C.c_int64), ("pairs", C.c_int64), ("tiles_x", C.c_int32), ("tiles_y", C.c_int32),
                 ("sort_passes", C.c_int32), ("big_chunks", C.c_int32),
-                ("candidates", C.c_int64), ("entries", C.c_int64)]
+                ("candidates", C.c_int64), ("entries", C.c_int64), ("cull_batches", C.c_int64)]
 
 
 class FgsTimings(C.Structure):

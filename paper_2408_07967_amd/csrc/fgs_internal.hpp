@@ -56,6 +56,11 @@ struct DevPrepared {
     const uint32_t *orig; // Gaussian (index in the caller's scene) of each precompute slot: the slots
                           // follow a spatial order of the means (see launch_prepare)
     int sh_stride;
+    // per batch of kBlock consecutive slots, over its members that can be
+    // visible (opacity > 0, finite mean): (min x, min y, min z, max opacity),
+    // (max x, max y, max z, max trace), (max k^2, 0, 0, 0); a NaN trace or k^2
+    // is taken as +inf (see launch_block_bounds)
+    const float4 *blk;
 };
 
 // Per-Gaussian state of the blend, 48 bytes = 3 x float4.
@@ -83,6 +88,8 @@ struct FrameCounters {
     uint32_t ncand;    // candidates of a prepared scene's cull (dense depth keys)
     uint32_t nlong;    // runs of more than kShortTieRun equal depths (prepared scene)
     uint32_t entries;  // (Gaussian, super-tile) entries (written by the count scan)
+    uint32_t cull_read;  // batches of kBlock slots a prepared scene's cull read (the others its
+                         // batch bounds skipped; written by the preprocess)
 };
 
 // Super-tiles: blocks of kSuper x kSuper tiles (the last row and column may be
@@ -180,6 +187,8 @@ unsigned emit_grid(uint32_t visible);
 // count, erec, dkey, chunk entries) of position i goes to index i, and the
 // Gaussian of position i to gmap[i].  Without a precompute the outputs are
 // indexed by Gaussian and gmap is unused.
+// seg_count holds 2 kCullBlocks words: the candidate counts, then the
+// batches each cull workgroup read.
 constexpr int kCullBlocks = 2048;
 // count8: the number of super-tiles the rectangle overlaps, i.e. its
 // entries (kCount8Big for a chunked rectangle, whose entries the scan takes
@@ -236,6 +245,12 @@ void launch_preprocess_multi(const DevScene &sc, const DevPrepared &pp, const Mu
 // slot order: slot i holds Gaussian perm[i] (orig[i] = perm[i]).
 void launch_prepare(const DevScene &sc, const DevOptions &op, const uint32_t *perm, float4 *pos_o, float4 *cov,
                     float *sh, float2 *bnd, uint32_t *orig, int sh_stride, hipStream_t s);
+// Batch bounds of a prepared scene (DevPrepared::blk, 3 float4 per batch of
+// kBlock slots), from the precompute's positions, opacities and extent
+// bounds.  The cull skips a batch whose bounds show that it would drop every
+// member (Sec. 5.3.1: the view-independent part precomputed once): behind
+// the near plane, below the opacity threshold, or off the image.
+void launch_block_bounds(const float4 *pos_o, const float2 *bnd, int64_t P, float4 *blk, hipStream_t s);
 // Spatial order of a scene's Gaussians: bounds[0..5] = (min x, y, z, max x,
 // y, z) of the finite means (bounds: 6 words, initialised by the launcher),
 // then keys[g] = 30-bit Morton code of the mean quantised to 1024 cells per

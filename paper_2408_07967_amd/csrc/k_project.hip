@@ -464,44 +464,150 @@ __device__ __forceinline__ void cull_range(int64_t P, uint32_t b, int64_t *lo, i
     if (*lo > *hi) *lo = *hi;
 }
 
-// The cull's keep test of Gaussian g (position and opacity p4) for one
-// camera.
-__device__ __forceinline__ bool cull_keep(const DevPrepared &pp, int64_t g, const float4 &p4, const DevCamera &cam,
+// The cull's keep test of one Gaussian (position and opacity p4, extent
+// terms b) for one camera.  Evaluated without branches, so that a caller's
+// loads of p4 and b are all issued together.
+__device__ __forceinline__ bool cull_keep(const float4 &p4, const float2 &b, const DevCamera &cam,
                                           const DevOptions &op, int W, int H) {
     const float *R = cam.R;
     const float tx = ((R[0] * p4.x + R[1] * p4.y) + R[2] * p4.z) + cam.t[0];
     const float ty = ((R[3] * p4.x + R[4] * p4.y) + R[5] * p4.z) + cam.t[1];
     const float tz = ((R[6] * p4.x + R[7] * p4.y) + R[8] * p4.z) + cam.t[2];
-    bool keep = tz > cam.near_z && p4.w > op.alpha_min && isfinite(p4.x) && isfinite(p4.y) && isfinite(p4.z);
-    if (keep) {
-        const float2 b = pp.bnd[g];
-        const float iz = 1.0f / tz;
-        const float xt = tx * iz, yt = ty * iz;
-        const float limx = op.jac_clip * (0.5f * (float)W / cam.fx);
-        const float limy = op.jac_clip * (0.5f * (float)H / cam.fy);
-        const float xc = fminf(fmaxf(xt, -limx), limx), yc = fminf(fmaxf(yt, -limy), limy);
-        const float J00 = cam.fx * iz, J02 = -cam.fx * xc * iz, J11 = cam.fy * iz, J12 = -cam.fy * yc * iz;
-        float n0 = 0.0f, n1 = 0.0f;
-        for (int j = 0; j < 3; ++j) {
-            const float t0 = J00 * R[j] + J02 * R[6 + j], t1 = J11 * R[3 + j] + J12 * R[6 + j];
-            n0 += t0 * t0;
-            n1 += t1 * t1;
-        }
-        float hx, hy;
-        if (op.binning == 2) {
-            // square of radius ceil(3 sqrt(lambda_max(Sigma'))), lambda_max <= trace
-            hx = sqrtf(9.0f * ((n0 + n1) * b.x + op.dilation)) * 1.001f + 3.0f;
-            hy = hx;
-        } else {
-            hx = sqrtf(b.y * (n0 * b.x + op.dilation)) * 1.001f + 3.0f;
-            hy = sqrtf(b.y * (n1 * b.x + op.dilation)) * 1.001f + 3.0f;
-        }
-        const float u = cam.fx * xt + cam.cx, v = cam.fy * yt + cam.cy;
-        // drop only what is certainly off the image (a NaN keeps it)
-        const bool out = (u + hx < 0.0f) || (u - hx > (float)W) || (v + hy < 0.0f) || (v - hy > (float)H);
-        keep = !out;
+    const bool front = (tz > cam.near_z) & (p4.w > op.alpha_min) & isfinite(p4.x) & isfinite(p4.y) & isfinite(p4.z);
+    const float iz = 1.0f / tz;
+    const float xt = tx * iz, yt = ty * iz;
+    const float limx = op.jac_clip * (0.5f * (float)W / cam.fx);
+    const float limy = op.jac_clip * (0.5f * (float)H / cam.fy);
+    const float xc = fminf(fmaxf(xt, -limx), limx), yc = fminf(fmaxf(yt, -limy), limy);
+    const float J00 = cam.fx * iz, J02 = -cam.fx * xc * iz, J11 = cam.fy * iz, J12 = -cam.fy * yc * iz;
+    float n0 = 0.0f, n1 = 0.0f;
+    for (int j = 0; j < 3; ++j) {
+        const float t0 = J00 * R[j] + J02 * R[6 + j], t1 = J11 * R[3 + j] + J12 * R[6 + j];
+        n0 += t0 * t0;
+        n1 += t1 * t1;
     }
-    return keep;
+    float hx, hy;
+    if (op.binning == 2) {
+        // square of radius ceil(3 sqrt(lambda_max(Sigma'))), lambda_max <= trace
+        hx = sqrtf(9.0f * ((n0 + n1) * b.x + op.dilation)) * 1.001f + 3.0f;
+        hy = hx;
+    } else {
+        hx = sqrtf(b.y * (n0 * b.x + op.dilation)) * 1.001f + 3.0f;
+        hy = sqrtf(b.y * (n1 * b.x + op.dilation)) * 1.001f + 3.0f;
+    }
+    const float u = cam.fx * xt + cam.cx, v = cam.fy * yt + cam.cy;
+    // drop only what is certainly off the image (a NaN keeps it)
+    const bool out = (u + hx < 0.0f) | (u - hx > (float)W) | (v + hy < 0.0f) | (v - hy > (float)H);
+    return front & !out;
+}
+
+// Whether the cull would drop every member of a batch whose bounds are
+// (lo, hi, kx) (DevPrepared::blk), for one camera.  A member is dropped if
+// its opacity is at most alpha_min, its view depth is not past the near
+// plane, or its screen extent bound is off the image (cull_keep).  Over the
+// batch: the opacity is at most lo.w; the view depth is affine in the mean,
+// so over the box of means it lies between the corners' depths; in front of
+// the camera the projection is linear-fractional with a positive
+// denominator, so the means' screen coordinates also lie between the
+// corners'; and each member's extent bound sqrt(k^2 (|t0|^2 trace +
+// dilation)) grows with k^2, trace and |t0|^2 = (fx / z)^2 |R_0 - xc R_2|^2
+// <= (fx / z_min)^2 (|R_0| + limx |R_2|)^2 (|xc| <= limx; the 3 sigma square
+// likewise).  Margins (a relative 1e-5 on the depths, 1 % and 8 pixels on
+// the extent) cover the rounding of either evaluation.
+__device__ bool batch_culled(const float4 &lo, const float4 &hi, const float4 &kx, const DevCamera &cam,
+                             const DevOptions &op, int W, int H) {
+    if (!(lo.w > op.alpha_min)) return true;  // every opacity too low (or no member)
+    const float *R = cam.R;
+    bool behind = true, front = true;
+    float umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY, zmin = INFINITY;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const float x = (c & 1) ? hi.x : lo.x, y = (c & 2) ? hi.y : lo.y, z = (c & 4) ? hi.z : lo.z;
+        const float tx = ((R[0] * x + R[1] * y) + R[2] * z) + cam.t[0];
+        const float ty = ((R[3] * x + R[4] * y) + R[5] * z) + cam.t[1];
+        const float tz = ((R[6] * x + R[7] * y) + R[8] * z) + cam.t[2];
+        const float mag = ((fabsf(R[6] * x) + fabsf(R[7] * y)) + fabsf(R[8] * z)) + fabsf(cam.t[2]);
+        behind = behind && tz < cam.near_z - 1e-5f * mag;
+        front = front && tz > 1e-5f * mag && tz > 1e-20f;
+        const float iz = 1.0f / tz;
+        umin = fminf(umin, cam.fx * (tx * iz) + cam.cx);
+        umax = fmaxf(umax, cam.fx * (tx * iz) + cam.cx);
+        vmin = fminf(vmin, cam.fy * (ty * iz) + cam.cy);
+        vmax = fmaxf(vmax, cam.fy * (ty * iz) + cam.cy);
+        zmin = fminf(zmin, tz);
+    }
+    if (behind) return true;   // every member's depth is at most the near plane
+    if (!front) return false;  // the box reaches behind the camera: test each member
+    const float r0 = sqrtf((R[0] * R[0] + R[1] * R[1]) + R[2] * R[2]);
+    const float r1 = sqrtf((R[3] * R[3] + R[4] * R[4]) + R[5] * R[5]);
+    const float r2 = sqrtf((R[6] * R[6] + R[7] * R[7]) + R[8] * R[8]);
+    const float limx = op.jac_clip * (0.5f * (float)W / cam.fx);
+    const float limy = op.jac_clip * (0.5f * (float)H / cam.fy);
+    const float ax = (cam.fx / zmin) * (r0 + limx * r2), ay = (cam.fy / zmin) * (r1 + limy * r2);
+    const float n0 = ax * ax, n1 = ay * ay;
+    float hx, hy;
+    if (op.binning == 2) {
+        hx = sqrtf(9.0f * ((n0 + n1) * hi.w + op.dilation));
+        hy = hx;
+    } else {
+        hx = sqrtf(kx.x * (n0 * hi.w + op.dilation));
+        hy = sqrtf(kx.x * (n1 * hi.w + op.dilation));
+    }
+    hx = hx * 1.01f + 8.0f;
+    hy = hy * 1.01f + 8.0f;
+    // (a NaN anywhere keeps the batch)
+    return (umax + hx < 0.0f) || (umin - hx > (float)W) || (vmax + hy < 0.0f) || (vmin - hy > (float)H);
+}
+
+// Bounds of each batch of kBlock slots (one workgroup per batch) over its
+// members that can be visible (see DevPrepared::blk).
+__global__ __launch_bounds__(kBlock) void k_block_bounds(const float4 *__restrict__ pos_o,
+                                                         const float2 *__restrict__ bnd, int64_t P,
+                                                         float4 *__restrict__ blk) {
+    __shared__ float s_r[kBlock / kWave][8];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    float4 p = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    float2 b = make_float2(0.0f, 0.0f);
+    if (i < P) {
+        p = pos_o[i];
+        b = bnd[i];
+    }
+    const bool use = i < P && p.w > 0.0f && isfinite(p.x) && isfinite(p.y) && isfinite(p.z);
+    float r[8] = {use ? p.x : INFINITY, use ? p.y : INFINITY, use ? p.z : INFINITY,
+                  use ? -p.x : -INFINITY, use ? -p.y : -INFINITY, use ? -p.z : -INFINITY,
+                  use ? -p.w : 0.0f, 0.0f};
+    // maxima as minima of negatives; a NaN trace or k^2 counts as +inf
+    const float tr = isnan(b.x) ? INFINITY : b.x, k2 = isnan(b.y) ? INFINITY : b.y;
+    float mtr = use ? tr : 0.0f, mk2 = use ? k2 : 0.0f;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+#pragma unroll
+        for (int q = 0; q < 7; ++q) r[q] = fminf(r[q], __shfl_xor(r[q], d, kWave));
+        mtr = fmaxf(mtr, __shfl_xor(mtr, d, kWave));
+        mk2 = fmaxf(mk2, __shfl_xor(mk2, d, kWave));
+    }
+    r[7] = mtr;
+    if (lane == 0) {
+        for (int q = 0; q < 7; ++q) s_r[wv][q] = r[q];
+        s_r[wv][7] = mtr;
+    }
+    __shared__ float s_k2[kBlock / kWave];
+    if (lane == 0) s_k2[wv] = mk2;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float o[8];
+        float k2m = s_k2[0];
+        for (int q = 0; q < 8; ++q) o[q] = s_r[0][q];
+        for (int w = 1; w < kBlock / kWave; ++w) {
+            for (int q = 0; q < 7; ++q) o[q] = fminf(o[q], s_r[w][q]);
+            o[7] = fmaxf(o[7], s_r[w][7]);
+            k2m = fmaxf(k2m, s_k2[w]);
+        }
+        blk[3 * blockIdx.x] = make_float4(o[0], o[1], o[2], -o[6]);
+        blk[3 * blockIdx.x + 1] = make_float4(-o[3], -o[4], -o[5], o[7]);
+        blk[3 * blockIdx.x + 2] = make_float4(k2m, 0.0f, 0.0f, 0.0f);
+    }
 }
 
 // Cull of a prepared scene: reads 24 bytes per Gaussian and keeps those in
@@ -531,35 +637,106 @@ __global__ __launch_bounds__(kBlock) void k_cull(DevScene sc, DevPrepared pp, De
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     int64_t lo, hi;
     cull_range(sc.P, blockIdx.x, &lo, &hi);
-    uint32_t n = 0;  // candidates of this workgroup so far (uniform)
-    for (int64_t g0 = lo; g0 < hi; g0 += kBlock) {
-        const int64_t g = g0 + threadIdx.x;
-        bool keep = false;
-        if (g < hi) {
-            const float4 p4 = pp.pos_o[g];
+    uint32_t n = 0;     // candidates of this workgroup so far (uniform)
+    uint32_t read = 0;  // batches read (uniform)
+    // The batch bounds of the workgroup's range are tested first, one batch
+    // per thread, into a mask (a batch that the test below would drop
+    // entirely is not read); then the kept batches are read in turn.
+    __shared__ uint32_t s_skip[kBlock / 32];
+    const int64_t b_lo = lo / kBlock, b_hi = (hi + kBlock - 1) / kBlock;
+    for (int64_t cb = b_lo; cb < b_hi; cb += kBlock) {
+        {
+            const int64_t bt = cb + threadIdx.x;
+            bool skip = false;
+            if (bt < b_hi) {
+                const float4 *const bb = pp.blk + 3 * bt;
+                const float4 blo = bb[0], bhi = bb[1], bkx = bb[2];
+                skip = true;
+                if constexpr (kMulti) {
+                    for (int c = 0; c < mo.n && skip; ++c)
+                        skip = batch_culled(blo, bhi, bkx, mo.c[c].cam, op, mo.c[c].W, mo.c[c].H);
+                } else {
+                    skip = batch_culled(blo, bhi, bkx, cam, op, W, H);
+                }
+            }
+            const uint64_t bal = __ballot(skip);
+            if (lane == 0) {
+                s_skip[2 * wave] = (uint32_t)bal;
+                s_skip[2 * wave + 1] = (uint32_t)(bal >> 32);
+            }
+            __syncthreads();
+        }
+        const int nq = (int)((cb + kBlock < b_hi ? cb + kBlock : b_hi) - cb);
+        // the first kept batch of the chunk at or after q (nq if none)
+        auto next_kept = [&](int q) {
+            while (q < nq) {
+                const uint32_t w = ~s_skip[q >> 5] >> (q & 31);
+                if (w) return min(q + (int)__builtin_ctz(w), nq);
+                q = (q | 31) + 1;
+            }
+            return nq;
+        };
+        // member threadIdx.x of kept batch q: its position, opacity and
+        // extent terms.  The index is clamped into the range (some member's
+        // data past its end or for q = nq, unused): the loads are issued
+        // unconditionally, so that nothing waits on a pending one.
+        auto load = [&](int q, float4 &p4, float2 &bd) {
+            int64_t g = (cb + (q < nq ? q : 0)) * kBlock + threadIdx.x;
+            g = g < hi ? g : hi - 1;
+            p4 = pp.pos_o[g];
+            bd = pp.bnd[g];
+        };
+        // test and compact kept batch q, members' data p4 and bd
+        auto batch = [&](int q, const float4 &p4, const float2 &bd) {
+            ++read;
+            const int64_t g = (cb + q) * kBlock + threadIdx.x;
+            bool keep;
             if constexpr (kMulti) {
                 // union of the cameras' candidates: the exact path of each
                 // camera culls the rest
-                for (int c = 0; c < mo.n && !keep; ++c) keep = cull_keep(pp, g, p4, mo.c[c].cam, op, mo.c[c].W, mo.c[c].H);
+                keep = cull_keep(p4, bd, mo.c[0].cam, op, mo.c[0].W, mo.c[0].H);
+                for (int c = 1; c < mo.n && !keep; ++c) keep = cull_keep(p4, bd, mo.c[c].cam, op, mo.c[c].W, mo.c[c].H);
             } else {
-                keep = cull_keep(pp, g, p4, cam, op, W, H);
+                keep = cull_keep(p4, bd, cam, op, W, H);
             }
-        }
-        // ordered compaction into this workgroup's own segment
-        const uint64_t bal = __ballot(keep);
-        if (lane == 0) s_w[wave] = (uint32_t)__popcll(bal);
-        __syncthreads();
-        uint32_t before = 0, tot = 0;
+            keep = keep && g < hi;
+            // ordered compaction into this workgroup's own segment
+            const uint64_t bal = __ballot(keep);
+            if (lane == 0) s_w[wave] = (uint32_t)__popcll(bal);
+            __syncthreads();
+            uint32_t before = 0, tot = 0;
 #pragma unroll
-        for (int w = 0; w < kBlock / kWave; ++w) {
-            before += w < wave ? s_w[w] : 0u;
-            tot += s_w[w];
+            for (int w = 0; w < kBlock / kWave; ++w) {
+                before += w < wave ? s_w[w] : 0u;
+                tot += s_w[w];
+            }
+            if (keep) cand[lo + n + before + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull))] = (uint32_t)g;
+            n += tot;
+            __syncthreads();
+        };
+        // two buffers in turn: the next kept batch's loads are in flight
+        // during this one's test, with no copy between them
+        float4 pa, pb;
+        float2 ba, bb;
+        int q = next_kept(0);
+        load(q, pa, ba);
+        while (q < nq) {
+            int qn = next_kept(q + 1);
+            load(qn, pb, bb);
+            batch(q, pa, ba);
+            q = qn;
+            if (q >= nq) break;
+            qn = next_kept(q + 1);
+            load(qn, pa, ba);
+            batch(q, pb, bb);
+            q = qn;
         }
-        if (keep) cand[lo + n + before + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull))] = (uint32_t)g;
-        n += tot;
-        __syncthreads();
+        __syncthreads();  // every thread has read the mask before it is replaced
     }
-    if (threadIdx.x == 0) seg_count[blockIdx.x] = n;
+    if (threadIdx.x == 0) {
+        seg_count[blockIdx.x] = n;
+        seg_count[kCullBlocks + blockIdx.x] = read;
+    }
 }
 
 // kMulti (with kPrep): every camera of mo in turn over the union candidate
@@ -725,11 +902,31 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         }
         __syncthreads();
     }
-    if constexpr (kMulti) {
-        if (blockIdx.x == 0 && threadIdx.x == 0)
-            for (int c = 0; c < mo.n; ++c) mo.c[c].fc->ncand = ncand;
-    } else if constexpr (kPrep) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) fc->ncand = ncand;
+    if constexpr (kPrep) {
+        // the batches the cull read (its workgroups' counts), for the stats
+        if (blockIdx.x == 0) {
+            constexpr int kPer = kCullBlocks / kBlock;
+            uint32_t r = 0;
+#pragma unroll
+            for (int j = 0; j < kPer; ++j) r += seg_count[kCullBlocks + threadIdx.x * kPer + j];
+            const uint32_t incl = wave_incl_scan(r, lane);
+            __syncthreads();  // s_wtot is free again
+            if (lane == kWave - 1) s_wtot[threadIdx.x / kWave] = incl;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                uint32_t tot = 0;
+                for (int w = 0; w < kBlock / kWave; ++w) tot += s_wtot[w];
+                if constexpr (kMulti) {
+                    for (int c = 0; c < mo.n; ++c) {
+                        mo.c[c].fc->ncand = ncand;
+                        mo.c[c].fc->cull_read = tot;
+                    }
+                } else {
+                    fc->ncand = ncand;
+                    fc->cull_read = tot;
+                }
+            }
+        }
     }
     // outputs of a prepared scene go to the candidate's list position (dense,
     // contiguous per wavefront), of raw parameters to the Gaussian's index
@@ -1121,8 +1318,15 @@ __global__ __launch_bounds__(kBlock) void k_super_emit(int W, const uint32_t *__
                                                        uint32_t chunk_cap, uint16_t *__restrict__ skey,
                                                        uint32_t *__restrict__ gidx, uint64_t *__restrict__ smask,
                                                        uint32_t ecap, uint2 *__restrict__ sranges, uint32_t nsuper,
-                                                       uint32_t *__restrict__ gsum_clear) {
+                                                       uint32_t *__restrict__ gsum_clear,
+                                                       const FrameCounters *__restrict__ fc) {
     __shared__ uint32_t s_excl[kBlock / kWave][kWave];
+    // an overflowed chunk list left the large rectangles untested: their
+    // entries (k_big_entries writes them otherwise) are filled here with
+    // super-tile 0, the Gaussian and an empty mask, so that the second half
+    // of this frame, which the host discards and renders again, reads only
+    // entries it wrote (every list value a valid Gaussian)
+    const bool overflow = (fc->error & kErrChunkOverflow) != 0;
     // every super-tile's range starts empty, (0xffffffff, 0), for the last
     // sort pass to narrow (sranges NULL: no pass records them)
     if (sranges)
@@ -1154,6 +1358,14 @@ __global__ __launch_bounds__(kBlock) void k_super_emit(int W, const uint32_t *__
         const int ntx = (int)rc.y - tx0 + 1, nty = (int)rc.w - ty0 + 1;
         const bool chunked = act && ntx * nty > kBigTiles;
         if (chunked && er.w < chunk_cap) big[er.w] = make_uint2(g, base);
+        if (chunked && overflow) {  // (rare: one lane per Gaussian is enough)
+            const uint32_t n = super_span(tx0, (int)rc.y, ty0, (int)rc.w);
+            for (uint32_t k = 0; k < n && base + k < ecap; ++k) {
+                skey[base + k] = 0;
+                gidx[base + k] = g;
+                smask[base + k] = 0ull;
+            }
+        }
         // flattened (Gaussian, super-tile) items of the small rectangles
         const uint32_t items = act && !chunked ? super_span(tx0, (int)rc.y, ty0, (int)rc.w) : 0u;
         const uint32_t incl = wave_incl_scan(items, lane);
@@ -1496,6 +1708,12 @@ void launch_prepare(const DevScene &sc, const DevOptions &op, const uint32_t *pe
                        pos_o, cov, sh, bnd, orig, sh_stride);
 }
 
+void launch_block_bounds(const float4 *pos_o, const float2 *bnd, int64_t P, float4 *blk, hipStream_t s) {
+    if (P <= 0) return;
+    hipLaunchKernelGGL(k_block_bounds, dim3((unsigned)((P + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, pos_o, bnd, P,
+                       blk);
+}
+
 void launch_spatial_keys(const DevScene &sc, uint32_t *bounds, uint32_t *keys, hipStream_t s) {
     hipLaunchKernelGGL(k_spatial_bounds_init, dim3(1), dim3(64), 0, s, bounds);
     if (sc.P <= 0) return;
@@ -1523,7 +1741,7 @@ void launch_super_emit(int W, int H, const uint32_t *order, uint32_t visible, co
     unsigned grid = emit_grid(visible);
     if (sranges) grid = std::max(grid, std::min<unsigned>((nsuper + kBlock - 1) / kBlock, kPersistentBlocks));
     hipLaunchKernelGGL(k_super_emit, dim3(grid), dim3(kBlock), 0, s, W, order, visible, visible_dev, offsets, erec,
-                       big, chunk_cap, skey, gidx, smask, ecap, sranges, nsuper, gsum_clear);
+                       big, chunk_cap, skey, gidx, smask, ecap, sranges, nsuper, gsum_clear, fc);
     if (chunk_cap == 0 || visible == 0) return;
     hipLaunchKernelGGL(k_big_entries, dim3(kPersistentBlocks), dim3(kBlock), 0, s, W, erec, ng, chunks, big,
                        chunk_cap, chunk_mask, fc, skey, gidx, smask, ecap);

@@ -83,7 +83,7 @@ hipError_t ensure_gauss(FrameBuffers &b, size_t P) {
     FGS_GROW(b.dv_a, cap);
     FGS_GROW(b.dv_b, cap);
     FGS_GROW(b.offsets, cap + 1);
-    FGS_GROW(b.seg_count, kCullBlocks);
+    FGS_GROW(b.seg_count, 2 * kCullBlocks);
     FGS_GROW(b.gmap, cap);
     b.capP = cap;
     return hipSuccess;
@@ -260,6 +260,8 @@ hipError_t build_prepared(const fgs_scene &sc, const fgs_options &op, PreparedBu
     if ((e = hipMalloc((void **)&pb.sh, n * (size_t)pb.sh_stride * sizeof(float))) != hipSuccess) return e;
     if ((e = hipMalloc((void **)&pb.bnd, n * sizeof(float2))) != hipSuccess) return e;
     if ((e = hipMalloc((void **)&pb.orig, n * sizeof(uint32_t))) != hipSuccess) return e;
+    if ((e = hipMalloc((void **)&pb.blk, 3 * (pb.batches() > 0 ? pb.batches() : 1) * sizeof(float4))) != hipSuccess)
+        return e;
     // Slot order: the Gaussians sorted by the Morton code of their means
     // (stable, so equal codes keep index order), so that the candidates of a
     // frame's cull, which see one region of the scene, occupy few contiguous
@@ -281,6 +283,7 @@ hipError_t build_prepared(const fgs_scene &sc, const fgs_options &op, PreparedBu
     launch_radix_pass(ka, va, kb, vb, P32, nullptr, 16, 8, false, true, ss.rhist, ss.slot(2), ss.slot(3), s);
     launch_radix_pass(kb, vb, nullptr, va, P32, nullptr, 24, 8, false, false, ss.rhist, ss.slot(3), nullptr, s);
     launch_prepare(dsc, to_dev(op), va, pb.pos_o, pb.cov, pb.sh, pb.bnd, pb.orig, pb.sh_stride, s);
+    launch_block_bounds(pb.pos_o, pb.bnd, P, pb.blk, s);
     e = hipGetLastError();
     // the temporary buffers are read by the work just enqueued
     const hipError_t e2 = hipStreamSynchronize(s);
@@ -295,6 +298,7 @@ void free_prepared(PreparedBuffers &pb) {
     free_p(*(void **)&pb.cov);
     free_p(*(void **)&pb.sh);
     free_p(*(void **)&pb.bnd);
+    free_p(*(void **)&pb.blk);
     pb = PreparedBuffers{};
 }
 

@@ -26,7 +26,7 @@ struct FrameBuffers {
     uint4 *erec = nullptr;  // emission record: rectangle (16-bit) and hit mask
     uint32_t *dkey = nullptr, *dk_b = nullptr, *dv_a = nullptr, *dv_b = nullptr;
     uint32_t *offsets = nullptr;
-    uint32_t *seg_count = nullptr;  // kCullBlocks candidate counts of a prepared scene's cull
+    uint32_t *seg_count = nullptr;  // a prepared scene's cull: kCullBlocks candidate counts, then batches read
     uint32_t *gmap = nullptr;       // prepared scene: Gaussian of each candidate list position
     // per pair: four arrays of capN words, consecutive parts of one block
     // that starts at tk_a (the entries and the values, see entry_capacity)
@@ -41,7 +41,7 @@ struct FrameBuffers {
         return capP * (sizeof(GaussState) + sizeof(float4) + sizeof(uint4) + sizeof(uint32_t) + sizeof(uint4) +
                        5 * sizeof(uint32_t) +
                        sizeof(uint8_t)) +
-               (capP + 1) * sizeof(uint32_t) + kCullBlocks * sizeof(uint32_t);
+               (capP + 1) * sizeof(uint32_t) + 2 * kCullBlocks * sizeof(uint32_t);
     }
     size_t bytes() const {
         return gauss_bytes() + (pairs_owned ? capN * 4 * sizeof(uint32_t) : 0) + capTiles * 2 * sizeof(uint2) +
@@ -187,12 +187,15 @@ struct PreparedBuffers {
     float *sh = nullptr;
     float2 *bnd = nullptr;
     uint32_t *orig = nullptr;  // Gaussian of each slot (the slots follow a spatial order)
+    float4 *blk = nullptr;     // batch bounds, 3 per kBlock slots (see DevPrepared)
     int sh_stride = 0;
     int64_t P = 0;
+    size_t batches() const { return (size_t)((P + kBlock - 1) / kBlock); }
     size_t bytes() const {
-        return (size_t)P * (3 * sizeof(float4) + sizeof(float2) + sizeof(uint32_t) + (size_t)sh_stride * sizeof(float));
+        return (size_t)P * (3 * sizeof(float4) + sizeof(float2) + sizeof(uint32_t) + (size_t)sh_stride * sizeof(float)) +
+               3 * batches() * sizeof(float4);
     }
-    DevPrepared dev() const { return DevPrepared{pos_o, cov, sh, bnd, orig, sh_stride}; }
+    DevPrepared dev() const { return DevPrepared{pos_o, cov, sh, bnd, orig, sh_stride, blk}; }
 };
 
 // Allocate and fill the precompute of sc for options op on stream s, in a

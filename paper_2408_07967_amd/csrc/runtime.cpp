@@ -418,6 +418,7 @@ fgs_status render_impl(fgs_context *ctx, const fgs_scene *scene, const fgs_prepa
             stt.big_chunks = (int32_t)big;
             stt.candidates = prep ? (int64_t)ncand : (int64_t)P;
             stt.entries = E;
+            stt.cull_batches = prep ? (int64_t)ctx->fc_host->cull_read : 0;
             *stats = stt;
         }
         return FGS_OK;
@@ -449,6 +450,7 @@ fgs_status render_impl(fgs_context *ctx, const fgs_scene *scene, const fgs_prepa
     stt.big_chunks = (int32_t)big;
     stt.candidates = prep ? (int64_t)ncand : (int64_t)P;
     stt.entries = E;
+    stt.cull_batches = prep ? (int64_t)ctx->fc_host->cull_read : 0;
     stt.sort_passes = 4 + super_sort_passes(W, H);
     if (stats) *stats = stt;
 
@@ -555,7 +557,7 @@ bool carve_noalloc(unsigned char *base, size_t P, size_t ntiles, FrameBuffers &f
     fb.dv_a = c.take<uint32_t>(capP);
     fb.dv_b = c.take<uint32_t>(capP);
     fb.offsets = c.take<uint32_t>(capP + 1);
-    fb.seg_count = c.take<uint32_t>(kCullBlocks);
+    fb.seg_count = c.take<uint32_t>(2 * kCullBlocks);
     fb.gmap = c.take<uint32_t>(capP);
     fb.capP = capP;
     ch.cap = (std::max<size_t>(P / 8, 8192) + kChunkCapAlign - 1) / kChunkCapAlign * kChunkCapAlign;
@@ -853,6 +855,7 @@ fgs_status fgs_render_prepared_batch(fgs_context *ctx, const fgs_prepared *p, co
             stt.big_chunks = (int32_t)ctx->bfc_host[c].nchunks;
             stt.candidates = (int64_t)ctx->bfc_host[c].ncand;
             stt.entries = ctx->bfc_host[c].entries;
+            stt.cull_batches = ctx->bfc_host[c].cull_read;
             stt.sort_passes = 4 + super_sort_passes(W, H);
             stats[c] = stt;
         }

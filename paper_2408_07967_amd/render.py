@@ -109,7 +109,7 @@ class Renderer:
         return dict(rgb=rgb, T=T, last=last, frame=fr if save else None,
                     stats=dict(visible=st.visible, pairs=st.pairs, tiles_x=st.tiles_x, tiles_y=st.tiles_y,
                                sort_passes=st.sort_passes, big_chunks=st.big_chunks,
-                               candidates=st.candidates, entries=st.entries))
+                               candidates=st.candidates, entries=st.entries, cull_batches=st.cull_batches))
 
     def render_noalloc(self, scene, cam, W, H, opts=None, out=None, want_T=False, want_last=False):
         """render() through fgs_render_noalloc: every scratch buffer comes from
@@ -133,7 +133,7 @@ class Renderer:
         return dict(rgb=rgb, T=T, last=last, frame=None,
                     stats=dict(visible=st.visible, pairs=st.pairs, tiles_x=st.tiles_x, tiles_y=st.tiles_y,
                                sort_passes=st.sort_passes, big_chunks=st.big_chunks,
-                               candidates=st.candidates, entries=st.entries))
+                               candidates=st.candidates, entries=st.entries, cull_batches=st.cull_batches))
 
     def render_batch(self, prepared, scene, cams, W, H, opts=None, want_T=False, want_last=False):
         """Render several cameras of a prepared scene in one call (one cull and
@@ -155,7 +155,7 @@ class Renderer:
                      stats=dict(visible=st[i].visible, pairs=st[i].pairs, tiles_x=st[i].tiles_x,
                                 tiles_y=st[i].tiles_y, sort_passes=st[i].sort_passes,
                                 big_chunks=st[i].big_chunks, candidates=st[i].candidates,
-                                entries=st[i].entries))
+                                entries=st[i].entries, cull_batches=st[i].cull_batches))
                 for i in range(n)]
 
     def plan(self, scene, cam, W, H, opts=None):

@@ -44,6 +44,7 @@ void launch_prepare(const DevScene &, const DevOptions &, const uint32_t *, floa
     reached("prepare");
 }
 void launch_spatial_keys(const DevScene &, uint32_t *, uint32_t *, hipStream_t) { reached("spatial_keys"); }
+void launch_block_bounds(const float4 *, const float2 *, int64_t, float4 *, hipStream_t) { reached("block_bounds"); }
 void launch_depth_ties(const uint32_t *, uint32_t *, const uint32_t *, uint32_t, const uint32_t *, uint32_t *,
                        FrameCounters *, uint32_t *, hipStream_t) {
     reached("depth_ties");

@@ -173,7 +173,7 @@ def test_3sigma_square_binning_parity(orc, R, scenes, kind, P, W, H):
 
 @pytest.mark.parametrize("case", ["small", "random_sh3", "degenerate", "medium_binning2", "uncapped",
                                   "offscreen_big", "offscreen_big_binning2", "ties_short", "ties_long",
-                                  "ties_one_run", "city1M-540p", "sh_huge", "eye_at_mean"])
+                                  "ties_one_run", "city1M-540p", "sh_huge", "eye_at_mean", "wide_batches"])
 def test_prepared_scene_is_bit_identical(orc, R, scenes, case):
     """A frame from the view-independent precompute equals the frame from the
     raw parameters bit for bit (state, pairs, order, image, T, last).  The
@@ -254,6 +254,15 @@ def test_prepared_scene_is_bit_identical(orc, R, scenes, case):
         W, H = 200, 120
         cam = identity_camera(W, H, 60.0)
         o = opts(binning=2) if case.endswith("binning2") else opts()
+    elif case == "wide_batches":
+        # about 200 spatial batches over a box that reaches behind the
+        # camera: batches wholly behind it, across its near plane, off the
+        # image, and off the image with footprints that reach into it; the
+        # batch bounds may skip only batches with no candidate
+        rng = np.random.default_rng(36)
+        sc = random_scene(rng, 50_000, box=8.0, ls_mu=-1.3, ls_sigma=0.8, sh_degree=1)
+        W, H = 200, 120
+        cam = identity_camera(W, H, 60.0)
     else:
         sc, cam, W, H = scenes.make_scene("small"), scenes.camera_for("small"), 256, 256
         o = opts(cap_3sigma=0, alpha_min=0.01)
@@ -284,6 +293,12 @@ def test_prepared_scene_is_bit_identical(orc, R, scenes, case):
     # than the visible Gaussians, never more than the scene holds
     ca, cb = a["stats"].pop("candidates"), b["stats"].pop("candidates")
     assert ca == sc.P and a["stats"]["visible"] <= cb <= sc.P
+    # the prepared scene's cull reads the batches its bounds keep
+    nb = b["stats"].pop("cull_batches")
+    assert a["stats"].pop("cull_batches") == 0 and 0 < nb <= (sc.P + 255) // 256
+    if case == "wide_batches":
+        print(f"[parity] wide_batches: {nb} of {(sc.P + 255) // 256} batches read, {cb} candidates", flush=True)
+        assert nb < (sc.P + 255) // 256
     assert a["stats"] == b["stats"]
     for k in ("rgb", "T", "last", "gauss", "rect", "count", "order", "tiles", "values", "ranges"):
         if k in ("gauss", "rect"):
