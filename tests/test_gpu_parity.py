@@ -94,6 +94,36 @@ def test_city_scene_reduced(orc, R, scenes):
     _full_check(orc, R, sc, scenes.camera_for("city", W=960, H=540), 960, 540, opts(), "city1M-540p")
 
 
+def test_wide_depth_span(orc, R):
+    """Depths from 0.3 to 2e6 (the visible depth keys span more than 2^27
+    binary32 values, about 16 binades, with different high key bits): raw
+    frame against the binary32 oracle, state, order and pairs bit-exact; the
+    prepared frame equal to it."""
+    rng = np.random.default_rng(37)
+    n = 4000
+    z = np.exp(rng.uniform(np.log(0.3), np.log(2.0e6), n))
+    means = np.stack([rng.uniform(-0.6, 0.6, n) * z, rng.uniform(-0.4, 0.4, n) * z, z], 1)
+    ls = np.log(0.02 * z)[:, None] + rng.normal(0, 0.3, (n, 3))
+    q = rng.normal(size=(n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    sc = scene_from(means, ls, q, rng.normal(1.0, 1.0, n), sh=rng.normal(0, 0.4, (3, n)), sh_degree=0)
+    W, H = 320, 200
+    cam = identity_camera(W, H, 0.8 * W)
+    g, o32, _ = _full_check(orc, R, sc, cam, W, H, opts(), "wide_depth_span")
+    d = g["gauss"][g["order"].astype(np.int64), 10].view(np.uint32).astype(np.int64)
+    span = int(d.max()) - (int(d.min()) & ~511)
+    print(f"[parity] wide_depth_span: {d.size} visible, key span 2^{np.log2(span):.2f}", flush=True)
+    assert span >> 27 != 0
+    gsc = _gs(sc)
+    h = R.prepare(gsc, opts())
+    try:
+        b = gpu_frame(R, gsc, cam, W, H, opts(), prepared=h)
+    finally:
+        R.release_prepared(h)
+    for k in ("order", "tiles", "values", "ranges", "rgb"):
+        assert np.array_equal(np.asarray(g[k]).view(np.uint32), np.asarray(b[k]).view(np.uint32)), k
+
+
 def test_empty_scene_is_background(orc, R):
     import torch
     from paper_2408_07967_amd.render import GaussianScene
