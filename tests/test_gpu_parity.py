@@ -338,6 +338,45 @@ def test_prepared_scene_is_bit_identical(orc, R, scenes, case):
             assert np.array_equal(np.asarray(a[k]).view(np.uint32), np.asarray(b[k]).view(np.uint32)), k
 
 
+def test_prepared_random_camera_poses(orc, R, scenes):
+    """Sixteen seeded random camera poses, eyes inside and outside scene
+    boxes of 2 to 10 units, fields of view of 30-100 degrees: the raw frame
+    against the binary32 oracle (state, order, pairs bit-exact) and the
+    prepared frame, whose cull skips 256-slot batches by their bounds, equal
+    to it.  Some batches must be skipped over the set."""
+    skipped = 0
+    for seed in range(500, 516):
+        rng = np.random.default_rng(seed)
+        W = int(rng.choice([97, 256, 320, 640, 1000]))
+        H = int(rng.choice([64, 180, 240, 480]))
+        P = int(rng.choice([3000, 20000, 60000]))
+        deg = int(rng.integers(0, 4))
+        box = float(rng.uniform(2.0, 10.0))
+        sc = random_scene(rng, P, box=box, ls_mu=float(rng.uniform(-3.0, -0.8)),
+                          ls_sigma=float(rng.uniform(0.2, 0.9)), sh_degree=deg)
+        eye = rng.uniform(-1.5 * box, 1.5 * box, 3) + np.array([0.0, 0.0, 4.0])
+        target = rng.uniform(-box, box, 3) + np.array([0.0, 0.0, 4.0])
+        cam = scenes.look_at(eye, target, W, H, float(rng.uniform(30.0, 100.0)))
+        o = opts(binning=int(rng.choice([0, 0, 0, 2])))
+        tag = f"pose{seed}"
+        print(f"[parity] {tag}: P={P} {W}x{H} deg {deg} box {box:.1f}", flush=True)
+        gsc = _gs(sc)
+        g = gpu_frame(R, gsc, cam, W, H, o)
+        o32 = orc.render(sc, cam, W, H, o, mode="f32")
+        check_gauss_state(orc, g, o32)
+        check_pairs(g, o32)
+        h = R.prepare(gsc, o)
+        try:
+            p = gpu_frame(R, gsc, cam, W, H, o, prepared=h)
+        finally:
+            R.release_prepared(h)
+        for k in ("rgb", "T", "last", "order", "tiles", "values", "ranges"):
+            assert np.array_equal(np.asarray(g[k]).view(np.uint32), np.asarray(p[k]).view(np.uint32)), (tag, k)
+        skipped += (P + 255) // 256 - p["stats"]["cull_batches"]
+    print(f"[parity] random poses: {skipped} batches skipped", flush=True)
+    assert skipped > 0
+
+
 def test_backward_of_prepared_frame_not_supported(R, scenes):
     """A prepared scene's frame holds its state by candidate position: the
     adjoint is for frames rendered from the parameters, and says so."""
