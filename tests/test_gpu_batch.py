@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 from gpu_helpers import check_image
-from oracle_helpers import identity_camera, opts, scene_from
+from oracle_helpers import identity_camera, opts, random_scene, scene_from
 
 pytestmark = pytest.mark.gpu
 
@@ -92,6 +92,37 @@ def test_batch_is_bit_identical_to_single_renders(orc, scenes, case):
     if case == "small-4":
         assert got[3]["stats"]["visible"] == 0 and got[3]["stats"]["pairs"] == 0
         assert np.all(got[3]["rgb"] == 0.0) and np.all(got[3]["T"] == 1.0)
+
+
+@pytest.mark.parametrize("seed", [600, 601, 602])
+def test_batch_random_camera_poses(scenes, seed):
+    """Up to eight cameras at seeded random poses around and inside one scene
+    (so that each camera's cull would skip other batches): the batch's union
+    cull skips only batches that every camera culls, and every camera's images
+    equal its single render bit for bit."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2408_07967_amd.render import GaussianScene, Renderer
+    rng = np.random.default_rng(seed)
+    box = float(rng.uniform(3.0, 8.0))
+    sc = random_scene(rng, 40000, box=box, ls_mu=-2.2, ls_sigma=0.5, sh_degree=int(rng.integers(0, 4)))
+    W, H = 320, 200
+    cams = []
+    for _ in range(int(rng.integers(2, 9))):
+        eye = rng.uniform(-1.5 * box, 1.5 * box, 3) + np.array([0.0, 0.0, 4.0])
+        target = rng.uniform(-box, box, 3) + np.array([0.0, 0.0, 4.0])
+        cams.append(scenes.look_at(eye, target, W, H, float(rng.uniform(40.0, 90.0))))
+    print(f"[batch] random poses {seed}: P={sc.P} box {box:.1f} cameras={len(cams)}", flush=True)
+    R = Renderer()
+    gsc = GaussianScene.from_numpy(sc)
+    o = opts()
+    h = R.prepare(gsc, o)
+    try:
+        _check_batch(R, gsc, h, cams, W, H, o, f"poses{seed}")
+    finally:
+        R.release_prepared(h)
+        R.close()
 
 
 def test_batch_buffers_grow_between_batches(scenes):
