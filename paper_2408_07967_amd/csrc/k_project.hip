@@ -574,10 +574,11 @@ __global__ __launch_bounds__(kBlock) void k_block_bounds(const float4 *__restric
         b = bnd[i];
     }
     const bool use = i < P && p.w > 0.0f && isfinite(p.x) && isfinite(p.y) && isfinite(p.z);
+    // maxima as minima of negatives (a slot without a member adds +inf to
+    // every minimum); a NaN trace or k^2 counts as +inf
     float r[8] = {use ? p.x : INFINITY, use ? p.y : INFINITY, use ? p.z : INFINITY,
-                  use ? -p.x : -INFINITY, use ? -p.y : -INFINITY, use ? -p.z : -INFINITY,
-                  use ? -p.w : 0.0f, 0.0f};
-    // maxima as minima of negatives; a NaN trace or k^2 counts as +inf
+                  use ? -p.x : INFINITY, use ? -p.y : INFINITY, use ? -p.z : INFINITY,
+                  use ? -p.w : INFINITY, 0.0f};
     const float tr = isnan(b.x) ? INFINITY : b.x, k2 = isnan(b.y) ? INFINITY : b.y;
     float mtr = use ? tr : 0.0f, mk2 = use ? k2 : 0.0f;
 #pragma unroll

@@ -203,7 +203,8 @@ def test_3sigma_square_binning_parity(orc, R, scenes, kind, P, W, H):
 
 @pytest.mark.parametrize("case", ["small", "random_sh3", "degenerate", "medium_binning2", "uncapped",
                                   "offscreen_big", "offscreen_big_binning2", "ties_short", "ties_long",
-                                  "ties_one_run", "city1M-540p", "sh_huge", "eye_at_mean", "wide_batches"])
+                                  "ties_one_run", "city1M-540p", "sh_huge", "eye_at_mean", "wide_batches", "one_gaussian",
+                                  "one_behind"])
 def test_prepared_scene_is_bit_identical(orc, R, scenes, case):
     """A frame from the view-independent precompute equals the frame from the
     raw parameters bit for bit (state, pairs, order, image, T, last).  The
@@ -284,6 +285,12 @@ def test_prepared_scene_is_bit_identical(orc, R, scenes, case):
         W, H = 200, 120
         cam = identity_camera(W, H, 60.0)
         o = opts(binning=2) if case.endswith("binning2") else opts()
+    elif case in ("one_gaussian", "one_behind"):
+        # one partial batch of one slot, in view or wholly behind the camera
+        z = 3.0 if case == "one_gaussian" else -3.0
+        sc = scene_from([(0.1, -0.05, z)], [(-1.5,) * 3], [(1, 0, 0, 0)], [2.0], dc_rgb=(0.8, 0.4, 0.2))
+        W, H = 64, 48
+        cam = identity_camera(W, H, 50.0)
     elif case == "wide_batches":
         # about 200 spatial batches over a box that reaches behind the
         # camera: batches wholly behind it, across its near plane, off the
@@ -325,7 +332,11 @@ def test_prepared_scene_is_bit_identical(orc, R, scenes, case):
     assert ca == sc.P and a["stats"]["visible"] <= cb <= sc.P
     # the prepared scene's cull reads the batches its bounds keep
     nb = b["stats"].pop("cull_batches")
-    assert a["stats"].pop("cull_batches") == 0 and 0 < nb <= (sc.P + 255) // 256
+    assert a["stats"].pop("cull_batches") == 0 and nb <= (sc.P + 255) // 256
+    # a batch holding a visible Gaussian is always read
+    assert nb > 0 or a["stats"]["visible"] == 0
+    if case == "one_behind":
+        assert nb == 0 and a["stats"]["visible"] == 0
     if case == "wide_batches":
         print(f"[parity] wide_batches: {nb} of {(sc.P + 255) // 256} batches read, {cb} candidates", flush=True)
         assert nb < (sc.P + 255) // 256
