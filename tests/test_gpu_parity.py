@@ -204,7 +204,7 @@ def test_3sigma_square_binning_parity(orc, R, scenes, kind, P, W, H):
 @pytest.mark.parametrize("case", ["small", "random_sh3", "degenerate", "medium_binning2", "uncapped",
                                   "offscreen_big", "offscreen_big_binning2", "ties_short", "ties_long",
                                   "ties_one_run", "city1M-540p", "sh_huge", "eye_at_mean", "wide_batches", "one_gaussian",
-                                  "one_behind"])
+                                  "one_behind", "all_transparent"])
 def test_prepared_scene_is_bit_identical(orc, R, scenes, case):
     """A frame from the view-independent precompute equals the frame from the
     raw parameters bit for bit (state, pairs, order, image, T, last).  The
@@ -291,6 +291,14 @@ def test_prepared_scene_is_bit_identical(orc, R, scenes, case):
         sc = scene_from([(0.1, -0.05, z)], [(-1.5,) * 3], [(1, 0, 0, 0)], [2.0], dc_rgb=(0.8, 0.4, 0.2))
         W, H = 64, 48
         cam = identity_camera(W, H, 50.0)
+    elif case == "all_transparent":
+        # every opacity below the threshold: each batch is skipped by its
+        # greatest opacity alone
+        rng = np.random.default_rng(38)
+        sc = random_scene(rng, 3000, ls_mu=-2.0, sh_degree=1)
+        sc.logits[:] = np.float32(-7.0)
+        W, H = 160, 120
+        cam = identity_camera(W, H, 0.9 * W)
     elif case == "wide_batches":
         # about 200 spatial batches over a box that reaches behind the
         # camera: batches wholly behind it, across its near plane, off the
@@ -335,7 +343,7 @@ def test_prepared_scene_is_bit_identical(orc, R, scenes, case):
     assert a["stats"].pop("cull_batches") == 0 and nb <= (sc.P + 255) // 256
     # a batch holding a visible Gaussian is always read
     assert nb > 0 or a["stats"]["visible"] == 0
-    if case == "one_behind":
+    if case in ("one_behind", "all_transparent"):
         assert nb == 0 and a["stats"]["visible"] == 0
     if case == "wide_batches":
         print(f"[parity] wide_batches: {nb} of {(sc.P + 255) // 256} batches read, {cb} candidates", flush=True)
